@@ -1,0 +1,418 @@
+"""Pins of the FP64 oracle against things other than itself: textbook values,
+closed forms, invariants, library routines (PyTorch CPU float64 modules) and
+brute force on tiny inputs.  CPU only."""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import vit64 as O
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+torch.set_default_dtype(torch.float64)
+
+
+def _rng(seed=0):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# --------------------------------------------------------------------- GELU
+def test_gelu_textbook_table():
+    rows = [l.split() for l in open(os.path.join(GOLD, "normal_cdf.txt"))
+            if l.strip() and not l.startswith("#")]
+    for xs, phis in rows:
+        x, phi = float(xs), float(phis)
+        assert abs(O.gelu(np.array([x]))[0] - x * phi) <= 1e-14
+        # GELU(x) - GELU(-x) = x * (Phi(x) + Phi(-x) - 1 + 1) = x
+        assert abs(O.gelu(np.array([x]))[0] - O.gelu(np.array([-x]))[0] - x) <= 1e-14
+    assert O.gelu(np.array([0.0]))[0] == 0.0
+    assert abs(O.gelu(np.array([-1.0]))[0] + 0.15865525393145707) <= 1e-15
+
+
+def test_gelu_matches_torch_erf_form():
+    x = _rng(1).standard_normal(10000) * 4
+    ref = torch.nn.functional.gelu(torch.from_numpy(x), approximate="none").numpy()
+    assert np.max(np.abs(O.gelu(x) - ref)) <= 1e-14
+    # and differs from the tanh form by far more than the FP32 tolerance
+    tanh = torch.nn.functional.gelu(torch.from_numpy(x), approximate="tanh").numpy()
+    assert np.max(np.abs(O.gelu(x) - tanh)) > 1e-4
+
+
+# ---------------------------------------------------------------- LayerNorm
+def test_layernorm_moments_closed_form():
+    rng = _rng(2)
+    x = rng.standard_normal((64, 96)) * 3 + 1.5
+    eps = 1e-5
+    y = O.layernorm(x, np.ones(96), np.zeros(96), eps)
+    var_in = x.var(axis=1)
+    assert np.max(np.abs(y.mean(axis=1))) <= 1e-14 * 10
+    # biased variance of the output is sigma^2 / (sigma^2 + eps) exactly
+    np.testing.assert_allclose(y.var(axis=1), var_in / (var_in + eps), rtol=1e-13)
+
+
+def test_layernorm_affine_invariance_and_torch():
+    rng = _rng(3)
+    x = rng.standard_normal((32, 128))
+    g = rng.standard_normal(128)
+    b = rng.standard_normal(128)
+    a = O.layernorm(x, g, b, 0.0)
+    assert np.max(np.abs(O.layernorm(7.0 * x + 3.0, g, b, 0.0) - a)) <= 1e-12
+    ref = torch.nn.functional.layer_norm(torch.from_numpy(x), (128,), torch.from_numpy(g),
+                                         torch.from_numpy(b), 1e-5).numpy()
+    assert np.max(np.abs(O.layernorm(x, g, b, 1e-5) - ref)) <= 1e-13
+
+
+# ------------------------------------------------------------------ softmax
+def test_softmax_rows_and_shift():
+    rng = _rng(4)
+    x = rng.standard_normal((50, 300)) * 30
+    p = O.softmax(x)
+    assert np.max(np.abs(p.sum(axis=1) - 1)) <= 1e-14
+    assert np.max(np.abs(O.softmax(x + 123.0) - p)) <= 1e-13  # x + 123 itself rounds
+    ref = torch.softmax(torch.from_numpy(x), dim=1).numpy()
+    assert np.max(np.abs(p - ref)) <= 1e-15
+    # scale 100 logits would overflow exp() without the max subtraction
+    big = np.array([[100.0, 99.0, -100.0]])
+    assert np.isfinite(O.softmax(big * 10)).all()
+
+
+# ---------------------------------------------------------------- attention
+def test_attention_two_tokens_one_head_by_hand():
+    rng = _rng(5)
+    d = 8
+    q, k, v = rng.standard_normal((3, 2, d))
+    s11 = q[0] @ k[0] / math.sqrt(d)
+    s12 = q[0] @ k[1] / math.sqrt(d)
+    p11 = 1.0 / (1.0 + math.exp(-(s11 - s12)))
+    o1 = p11 * v[0] + (1 - p11) * v[1]
+    out = O.attention_head(q, k, v)
+    assert np.max(np.abs(out[0] - o1)) <= 1e-15
+
+
+def test_attention_identical_tokens_uniform():
+    rng = _rng(6)
+    n, dm, heads = 9, 32, 4
+    tok = rng.standard_normal(dm)
+    y = np.tile(tok, (n, 1))
+    qkv_w = rng.standard_normal((3 * dm, dm))
+    qkv_b = rng.standard_normal(3 * dm)
+    o_w = rng.standard_normal((dm, dm))
+    o_b = rng.standard_normal(dm)
+    out = O.mhsa(y, qkv_w, qkv_b, o_w, o_b, heads)
+    v = tok @ qkv_w[2 * dm:].T + qkv_b[2 * dm:]
+    np.testing.assert_allclose(out, np.tile(v @ o_w.T + o_b, (n, 1)), rtol=1e-12, atol=1e-12)
+    # W_q = W_k = 0, b_q = b_k = 0: uniform weights 1/N for distinct tokens
+    y2 = rng.standard_normal((n, dm))
+    w0 = qkv_w.copy()
+    w0[:2 * dm] = 0
+    b0 = qkv_b.copy()
+    b0[:2 * dm] = 0
+    out2 = O.mhsa(y2, w0, b0, o_w, o_b, heads)
+    vv = y2 @ qkv_w[2 * dm:].T + qkv_b[2 * dm:]
+    np.testing.assert_allclose(out2, np.tile(vv.mean(axis=0) @ o_w.T + o_b, (n, 1)),
+                               rtol=1e-12, atol=1e-12)
+
+
+def test_mhsa_matches_torch_multihead_attention():
+    rng = _rng(7)
+    n, dm, heads = 13, 48, 6
+    y = rng.standard_normal((n, dm))
+    qkv_w = rng.standard_normal((3 * dm, dm)) * 0.2
+    qkv_b = rng.standard_normal(3 * dm) * 0.2
+    o_w = rng.standard_normal((dm, dm)) * 0.2
+    o_b = rng.standard_normal(dm) * 0.2
+    m = torch.nn.MultiheadAttention(dm, heads, batch_first=True)
+    with torch.no_grad():
+        m.in_proj_weight.copy_(torch.from_numpy(qkv_w))
+        m.in_proj_bias.copy_(torch.from_numpy(qkv_b))
+        m.out_proj.weight.copy_(torch.from_numpy(o_w))
+        m.out_proj.bias.copy_(torch.from_numpy(o_b))
+        t = torch.from_numpy(y)[None]
+        ref = m(t, t, t, need_weights=False)[0][0].numpy()
+    assert np.max(np.abs(O.mhsa(y, qkv_w, qkv_b, o_w, o_b, heads) - ref)) <= 1e-12
+
+
+def test_block_matches_torch_pre_ln_encoder_layer():
+    c = synth.MODELS["tiny"]
+    p = synth.make_params(c, 11, std=0.2)
+    lp = p["layers"][0]
+    x = _rng(8).standard_normal((17, c.width))
+    layer = torch.nn.TransformerEncoderLayer(
+        c.width, c.heads, c.mlp, dropout=0.0, activation="gelu",
+        layer_norm_eps=c.ln_eps, batch_first=True, norm_first=True)
+    layer.eval()
+    f = lambda a: torch.from_numpy(np.asarray(a, np.float64))  # noqa: E731
+    with torch.no_grad():
+        layer.self_attn.in_proj_weight.copy_(f(lp["qkv_w"]))
+        layer.self_attn.in_proj_bias.copy_(f(lp["qkv_b"]))
+        layer.self_attn.out_proj.weight.copy_(f(lp["o_w"]))
+        layer.self_attn.out_proj.bias.copy_(f(lp["o_b"]))
+        layer.linear1.weight.copy_(f(lp["fc1_w"]))
+        layer.linear1.bias.copy_(f(lp["fc1_b"]))
+        layer.linear2.weight.copy_(f(lp["fc2_w"]))
+        layer.linear2.bias.copy_(f(lp["fc2_b"]))
+        layer.norm1.weight.copy_(f(lp["ln1_g"]))
+        layer.norm1.bias.copy_(f(lp["ln1_b"]))
+        layer.norm2.weight.copy_(f(lp["ln2_g"]))
+        layer.norm2.bias.copy_(f(lp["ln2_b"]))
+        ref = layer(torch.from_numpy(x)[None])[0].numpy()
+    out = O.block(x, lp, c.heads, c.ln_eps)
+    assert np.max(np.abs(out - ref)) <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+# ----------------------------------------------------------------- patchify
+def test_patchify_conv_loops_equal_unfold_gemm_and_torch_conv():
+    rng = _rng(9)
+    P, D = 4, 5
+    img = rng.standard_normal((3, 13, 10))          # ragged: 3x2 grid, extra pixels
+    w = rng.standard_normal((D, 3, P, P))
+    b = rng.standard_normal(D)
+    gemm = O.patch_embed(img, w, b, P)
+    loops = O.patch_embed_conv(img, w, b, P)
+    assert gemm.shape == (6, D)
+    assert np.max(np.abs(gemm - loops)) <= 1e-13 * np.abs(loops).max()
+    ref = torch.nn.functional.conv2d(torch.from_numpy(img)[None], torch.from_numpy(w),
+                                     torch.from_numpy(b), stride=P)[0]
+    ref = ref.permute(1, 2, 0).reshape(-1, D).numpy()
+    assert np.max(np.abs(gemm - ref)) <= 1e-13 * np.abs(ref).max()
+
+
+def test_patch_vector_order_is_channel_major():
+    P = 2
+    img = np.arange(3 * 4 * 4, dtype=np.float64).reshape(3, 4, 4)
+    u = O.patchify(img, P)
+    # patch (r=0, q=1): channel 0 rows 0..1, cols 2..3, then channel 1, ...
+    assert list(u[1][:4]) == [2.0, 3.0, 6.0, 7.0]
+    assert u[1][4] == 16 + 2.0
+
+
+def test_normalisation_fold_closed_form():
+    """Folding (x - mu)/sigma into the patch weights is exact in real
+    arithmetic: W' = W / sigma_c, b' = b - sum W * mu_c / sigma_c."""
+    rng = _rng(10)
+    P, D = 4, 6
+    img = rng.random((3, 8, 8))
+    w = rng.standard_normal((D, 3, P, P))
+    b = rng.standard_normal(D)
+    mu = np.array([0.5, 0.4, 0.3])
+    sd = np.array([0.29, 0.25, 0.2])
+    ref = O.patch_embed(O.normalise_pixels(img, mu, sd), w, b, P)
+    w2 = w / sd[None, :, None, None]
+    b2 = b - (w * (mu / sd)[None, :, None, None]).sum(axis=(1, 2, 3))
+    assert np.max(np.abs(O.patch_embed(img, w2, b2, P) - ref)) <= 1e-13 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------ position interp
+def test_pos_interp_identity_constant_and_torch_bilinear():
+    rng = _rng(11)
+    g0, D = 5, 7
+    pos = rng.standard_normal((1 + g0 * g0, D))
+    assert np.array_equal(O.interp_pos(pos, g0, g0, g0), pos)
+    const = np.ones((1 + g0 * g0, D)) * 2.5
+    np.testing.assert_allclose(O.interp_pos(const, g0, 9, 3), 2.5, rtol=0, atol=1e-15)
+    for gh, gw in [(9, 9), (3, 7), (8, 5), (2, 2)]:
+        out = O.interp_pos(pos, g0, gh, gw)
+        grid = torch.from_numpy(pos[1:].reshape(g0, g0, D)).permute(2, 0, 1)[None]
+        ref = torch.nn.functional.interpolate(grid, size=(gh, gw), mode="bilinear",
+                                              align_corners=False, antialias=False)
+        ref = ref[0].permute(1, 2, 0).reshape(gh * gw, D).numpy()
+        assert np.max(np.abs(out[1:] - ref)) <= 1e-14
+        assert np.array_equal(out[0], pos[0])
+
+
+def test_pos_interp_reproduces_linear_ramp_in_interior():
+    g0, g = 6, 11
+    r = np.arange(g0, dtype=np.float64)
+    ramp = (2.0 * r[:, None] - 3.0 * r[None, :]).reshape(-1, 1)
+    pos = np.concatenate([[[0.0]], ramp])
+    out = O.interp_pos(pos, g0, g, g)[1:].reshape(g, g)
+    for o in range(g):
+        s = (o + 0.5) * g0 / g - 0.5
+        if 0 <= s <= g0 - 1:
+            for q in range(g):
+                t = (q + 0.5) * g0 / g - 0.5
+                if 0 <= t <= g0 - 1:
+                    assert abs(out[o, q] - (2 * s - 3 * t)) <= 1e-13
+
+
+# ------------------------------------------------------------- whole encoder
+def _tiny_setup(seed=12):
+    c = synth.MODELS["tiny"]
+    p = synth.make_params(c, seed)
+    imgs = synth.make_images([(64, 64)] * 3, seed + 1)
+    return c, p, imgs
+
+
+def test_zero_block_model_closed_form():
+    c, p, imgs = _tiny_setup()
+    for lp in p["layers"]:
+        for k in list(lp):
+            lp[k] = np.zeros_like(lp[k])
+    z = O.layernorm(np.asarray(p["cls"], np.float64) + p["pos"][0], p["lnf_g"], p["lnf_b"])
+    e = p["proj_w"].astype(np.float64) @ z
+    e /= np.linalg.norm(e)
+    for im in imgs:
+        assert np.max(np.abs(O.encode_image(im, p, c) - e)) <= 1e-14
+
+
+def test_permutation_equivariance_with_zero_pos():
+    c, p, imgs = _tiny_setup(13)
+    p["pos"] = np.zeros_like(p["pos"])
+    img = imgs[0]
+    P = c.patch
+    # swap two patches of the image: the class-token output must not change
+    img2 = img.copy()
+    img2[:, 0:P, 0:P], img2[:, 2 * P:3 * P, P:2 * P] = \
+        img[:, 2 * P:3 * P, P:2 * P].copy(), img[:, 0:P, 0:P].copy()
+    a = O.encode_image(img, p, c)
+    b = O.encode_image(img2, p, c)
+    assert np.max(np.abs(a - b)) <= 1e-12
+    assert np.max(np.abs(a - O.encode_image(imgs[1], p, c))) > 1e-3
+
+
+def test_embeddings_unit_norm_and_not_degenerate():
+    c, p, imgs = _tiny_setup(14)
+    e = O.encode(imgs, p, c)
+    np.testing.assert_allclose(np.linalg.norm(e, axis=1), 1.0, rtol=0, atol=1e-15)
+    cos = e @ e.T
+    off = cos[~np.eye(len(e), dtype=bool)]
+    assert off.max() < 0.99, "different images must not collapse to one embedding"
+
+
+def test_encoder_matches_torch_modules():
+    """Whole forward against PyTorch library modules (conv patchify,
+    pre-LN TransformerEncoderLayer, layer_norm, linear), all float64."""
+    c, p, imgs = _tiny_setup(15)
+    f = lambda a: torch.from_numpy(np.asarray(a, np.float64))  # noqa: E731
+    layers = []
+    for lp in p["layers"]:
+        L = torch.nn.TransformerEncoderLayer(c.width, c.heads, c.mlp, dropout=0.0,
+                                             activation="gelu", layer_norm_eps=c.ln_eps,
+                                             batch_first=True, norm_first=True).eval()
+        with torch.no_grad():
+            L.self_attn.in_proj_weight.copy_(f(lp["qkv_w"]))
+            L.self_attn.in_proj_bias.copy_(f(lp["qkv_b"]))
+            L.self_attn.out_proj.weight.copy_(f(lp["o_w"]))
+            L.self_attn.out_proj.bias.copy_(f(lp["o_b"]))
+            L.linear1.weight.copy_(f(lp["fc1_w"]))
+            L.linear1.bias.copy_(f(lp["fc1_b"]))
+            L.linear2.weight.copy_(f(lp["fc2_w"]))
+            L.linear2.bias.copy_(f(lp["fc2_b"]))
+            L.norm1.weight.copy_(f(lp["ln1_g"]))
+            L.norm1.bias.copy_(f(lp["ln1_b"]))
+            L.norm2.weight.copy_(f(lp["ln2_g"]))
+            L.norm2.bias.copy_(f(lp["ln2_b"]))
+        layers.append(L)
+    mean = torch.tensor(c.chan_mean)[:, None, None]
+    std = torch.tensor(c.chan_std)[:, None, None]
+    with torch.no_grad():
+        for im in imgs:
+            x = (f(im) - mean) / std
+            t = torch.nn.functional.conv2d(x[None], f(p["patch_w"]), f(p["patch_b"]),
+                                           stride=c.patch)[0]
+            t = t.flatten(1).T
+            t = torch.cat([f(p["cls"])[None], t]) + f(p["pos"])
+            t = t[None]
+            for L in layers:
+                t = L(t)
+            z = torch.nn.functional.layer_norm(t[0, 0], (c.width,), f(p["lnf_g"]),
+                                               f(p["lnf_b"]), c.ln_eps)
+            e = torch.nn.functional.normalize(z @ f(p["proj_w"]).T, dim=0).numpy()
+            assert np.max(np.abs(O.encode_image(im, p, c) - e)) <= 1e-12
+
+
+# ------------------------------------------------------------------- scoring
+def test_score_heads_bounds_special_cases_and_ties():
+    rng = _rng(16)
+    e = rng.standard_normal((5, 32))
+    e /= np.linalg.norm(e, axis=1, keepdims=True)
+    t = rng.standard_normal((40, 32))
+    t /= np.linalg.norm(t, axis=1, keepdims=True)
+    t[7] = e[2]                                   # a text equal to image 2
+    p, top1 = O.score(e, t, "softmax", 100.0)
+    assert np.max(np.abs(p.sum(axis=1) - 1)) <= 1e-14
+    assert abs(O.logits(e, t, 100.0)[2, 7] - 100.0) <= 1e-12
+    assert top1[2] == 7
+    ps, top1s = O.score(e, t, "sigmoid", 10.0, -10.0)
+    lo, hi = 1 / (1 + math.exp(20.0)), 0.5
+    assert ps.min() >= lo - 1e-18 and ps.max() <= hi + 1e-15
+    assert np.array_equal(top1, top1s)            # same ranking, monotone heads
+    t2 = np.concatenate([t[:3], t[:3]])           # exact ties -> lowest index
+    assert (O.score(e, t2, "softmax", 100.0)[1] < 3).all()
+
+
+# ------------------------------------------------------------ number formats
+def test_bf16_round_matches_torch():
+    rng = _rng(17)
+    x = np.concatenate([rng.standard_normal(200000).astype(np.float32) * 10,
+                        np.array([0.0, -0.0, 1.0, 65504.0, 3.0e38, 1e-40, -1e-38],
+                                 np.float32)])
+    bits = rng.integers(0, 2 ** 32, size=200000, dtype=np.uint64).astype(np.uint32)
+    y = bits.view(np.float32)
+    y = y[np.isfinite(y)]
+    for arr in (x, y):
+        ref = torch.from_numpy(arr).to(torch.bfloat16).to(torch.float64).numpy()
+        got = O.bf16_round(arr)
+        finite = np.isfinite(ref)
+        assert np.array_equal(got[finite], ref[finite])
+    # exact tie cases: 1 + 2^-8 rounds to even (1.0), 1 + 3*2^-8 rounds up
+    assert O.bf16_round(np.array([1 + 2 ** -8], np.float32))[0] == 1.0
+    assert O.bf16_round(np.array([1 + 3 * 2 ** -8], np.float32))[0] == 1 + 2 ** -6
+
+
+def test_e4m3_landmarks_and_grid_vs_torch():
+    rows = [l.split() for l in open(os.path.join(GOLD, "e4m3fn_points.txt"))
+            if l.strip() and not l.startswith("#")]
+    codes = torch.arange(256, dtype=torch.uint8).view(torch.float8_e4m3fn).to(torch.float64)
+    for hx, val, _ in rows:
+        v = float(val)
+        assert codes[int(hx, 16)].item() == v
+        assert O.e4m3_round(np.array([v]))[0] == v
+    grid = codes.numpy()
+    grid = np.unique(grid[np.isfinite(grid)])
+    assert grid.max() == 448.0 and len(grid) == 253   # 126 pos, 126 neg, one zero
+    # every representable value is a fixed point
+    assert np.array_equal(O.e4m3_round(grid), grid)
+    # random values: nearest grid point, ties to even code, vs torch's cast
+    rng = _rng(18)
+    y = np.concatenate([rng.standard_normal(100000) * 50, rng.standard_normal(20000) * 0.01,
+                        (grid[:-1] + grid[1:]) / 2])
+    y = y[np.abs(y) <= 448]
+    ref = torch.from_numpy(y.astype(np.float32)).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(O.e4m3_round(y.astype(np.float32)), ref)
+    assert O.e4m3_round(np.array([1000.0, -500.0]))[0] == 448.0
+    assert O.e4m3_round(np.array([-500.0]))[0] == -448.0
+
+
+def test_fp8_row_quantiser_properties():
+    rng = _rng(19)
+    w = (rng.standard_normal((64, 200)) * 0.02).astype(np.float32)
+    q, s = O.quantise_fp8_rows(w)
+    amax_idx = np.abs(w).argmax(axis=1)
+    assert np.all(np.abs(q[np.arange(64), amax_idx]) == 448.0)
+    assert np.abs(q).max() <= 448.0
+    deq = q * s[:, None]
+    y = np.abs(w / s[:, None])
+    normal = y >= 2.0 ** -6
+    err = np.abs(deq - w)
+    assert np.all(err[normal] <= 2.0 ** -4 * np.abs(w)[normal] * (1 + 1e-6))
+    assert np.all(err[~normal] <= (s[:, None] * 2.0 ** -10 * (1 + 1e-6)).repeat(200, 1)[~normal])
+    # round trip of values already on the grid is exact
+    q2, s2 = O.quantise_fp8_rows((q * s[:, None]).astype(np.float32))
+    assert np.allclose(q2 * s2[:, None], q * s[:, None], rtol=1e-6, atol=0)
+
+
+def test_weights_for_only_touches_block_linears():
+    c = synth.MODELS["tiny"]
+    p = synth.make_params(c, 20)
+    for prec in ("bf16", "fp8w"):
+        w = O.weights_for(p, prec)
+        assert np.array_equal(w["patch_w"], p["patch_w"])
+        assert np.array_equal(w["layers"][0]["qkv_b"], p["layers"][0]["qkv_b"])
+        assert not np.array_equal(w["layers"][0]["qkv_w"], p["layers"][0]["qkv_w"])
+        rel = np.abs(w["layers"][1]["fc1_w"] - p["layers"][1]["fc1_w"]) / \
+            np.abs(p["layers"][1]["fc1_w"]).max()
+        assert rel.max() < (2 ** -8 if prec == "bf16" else 2 ** -4)
