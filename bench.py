@@ -1,0 +1,244 @@
+"""Throughput benchmark of the image-encoder hot path on one MI355X.
+
+A step is one pass of the whole path over one batch: patch embedding, all
+transformer blocks, pooling / projection / L2 norm (vl_encode_images), then
+the logit GEMM and scoring head against the resident text embeddings
+(vl_score).  Inputs are seeded synthetic tensors already resident in HBM.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload l14_336]
+
+Prints one JSON line (rank 0).  Only one GPU is used: --gpus above 1 exits
+with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+BF16_PEAK = 2.5e15       # MI355X dense BF16 MFMA, FLOP/s
+FP32_PEAK = 157.3e12     # MI355X FP32 vector, FLOP/s
+HBM_PEAK = 8.0e12        # B/s
+
+
+def flops_per_image(c: synth.ModelConfig, res: int) -> float:
+    """Algorithmic FLOPs (2 per multiply-add, no padding credited)."""
+    g = res // c.patch
+    npch = g * g
+    n = npch + 1
+    D, F = c.width, c.mlp
+    f = 2.0 * npch * 3 * c.patch ** 2 * D
+    per_layer = 2.0 * n * D * 3 * D + 4.0 * n * n * D + 2.0 * n * D * D + 4.0 * n * D * F
+    f += c.layers * per_layer
+    f += 2.0 * D * c.proj_dim
+    return f
+
+
+def op_flops(c: synth.ModelConfig, sizes, op: str) -> float:
+    """Algorithmic FLOPs of one launch of an encoder operation."""
+    D, F = c.width, c.mlp
+    toks = [1 + (h // c.patch) * (w // c.patch) for h, w in sizes]
+    T = sum(toks)
+    return {
+        "qkv_gemm": 2.0 * T * D * 3 * D,
+        "oproj_gemm": 2.0 * T * D * D,
+        "fc1_gemm": 2.0 * T * D * F,
+        "fc2_gemm": 2.0 * T * F * D,
+        "attention": sum(4.0 * n * n * D for n in toks),
+        "patch_embed": sum(2.0 * (n - 1) * 3 * c.patch ** 2 * D for n in toks),
+    }.get(op, 0.0)
+
+
+def traffic_from_profile(op: str, workload: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or
+    None when there is none or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{op}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("{") and '"fetch_kib"' in line:
+            rec = json.loads(line)
+    if rec is None:
+        return None
+    src = os.path.join(ROOT, "paper_2505_00690_amd", "csrc", rec["source"])
+    if not os.path.exists(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        return None
+    return (rec["fetch_kib"] + rec["write_kib"]) * 1024.0 * rec["copy_factor"]
+
+
+def cpu_baseline(wl: synth.Workload, blob: np.ndarray, images, texts, n_sample: int):
+    """The FP64 oracle as it stands, on the host cores, over a bounded
+    sample of the same workload: encode + score of n_sample images."""
+    from oracle import vit64 as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()
+                       if i.get("user_api") == "blas"] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    c = synth.MODELS[wl.model]
+    params = O.weights_for(synth.blob_to_params(c, blob), wl.precision)
+    sample = images[:n_sample]
+    t0 = time.perf_counter()
+    emb = O.encode(sample, params, c)
+    O.score(emb, texts, wl.head, wl.scale, wl.bias)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample / dt, "unit": "images/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n_sample} of {len(images)} images of the workload "
+                      f"({wl.model}, {images[0].shape[1]}x{images[0].shape[2]}), FP64 encode + "
+                      f"{wl.head} scoring vs {len(texts)} texts; {dt:.1f} s"}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="l14_336", choices=["tiny_fp32", "b16_224", "l14_336",
+                                                             "b16_mixed"])
+    ap.add_argument("--precision", default=None, help="fp32 | bf16 | fp8w (default: workload's)")
+    ap.add_argument("--no-graphs", action="store_true")
+    ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the plain FP32 path")
+    ap.add_argument("--cpu-sample", type=int, default=None, help="images for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--timing-steps", type=int, default=3)
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(images are independent; see DESIGN.md for how the path would shard).",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2505_00690_amd import vl
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    wl = synth.WORKLOADS[args.workload]
+    prec = args.precision or wl.precision
+    c = synth.MODELS[wl.model]
+    seeds = synth.seeds_for(wl)
+    if len(wl.resolutions) == 1:
+        sizes = [(wl.resolutions[0],) * 2] * wl.n_images
+    else:
+        sizes = [(r, r) for r in synth.draw_resolutions(wl.n_images, wl.resolutions,
+                                                        seeds["resolutions"])]
+    t0 = time.time()
+    blob = synth.make_blob(c, seeds["weights"])
+    images = synth.make_images(sizes, seeds["images"])
+    texts = synth.make_texts(wl.n_texts, c.proj_dim, seeds["texts"])
+    print(f"# inputs generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    w = torch.from_numpy(blob).to(dev)
+    pix = torch.from_numpy(np.concatenate([im.reshape(-1) for im in images])).to(dev)
+    tx = torch.from_numpy(texts).to(dev)
+    n = len(sizes)
+    emb = torch.empty((n, c.proj_dim), dtype=torch.float32, device=dev)
+    scores = torch.empty((n, wl.n_texts), dtype=torch.float32, device=dev)
+    top1 = torch.empty(n, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    enc = vl.Encoder(c, w, prec, graphs=not args.no_graphs)
+
+    def step(e):
+        e.encode(pix, sizes, out=emb)
+        vl.vl_score(emb, tx, wl.head, wl.scale, wl.bias, scores, top1)
+
+    for _ in range(args.warmup):
+        step(enc)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step(enc)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    value = n / (ms / 1e3)
+    print(f"# {prec}: {ms:.3f} ms/step, {value:.1f} images/s", file=sys.stderr, flush=True)
+
+    # Per-operation device time: events around every launch, same stream.
+    vl.vl_model_set_option(enc.handle, vl.VL_OPT_TIMING, 1)
+    vl.vl_model_op_times(enc.handle, reset=True)
+    for _ in range(args.timing_steps):
+        step(enc)
+    torch.cuda.synchronize()
+    ops = vl.vl_model_op_times(enc.handle, reset=True)
+    vl.vl_model_set_option(enc.handle, vl.VL_OPT_TIMING, 0)
+    breakdown = {k: round(v[0] / args.timing_steps, 4) for k, v in ops.items() if v[1]}
+    gemm_like = ["qkv_gemm", "oproj_gemm", "fc1_gemm", "fc2_gemm", "attention"]
+    dom = max(gemm_like, key=lambda k: ops[k][0])
+    avg_s = ops[dom][0] / ops[dom][1] / 1e3
+    achieved = op_flops(c, sizes, dom) / avg_s
+    fp8_note = prec == "fp8w"
+    roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved / 1e12,
+                "peak": BF16_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / BF16_PEAK,
+                "avg_launch_ms": avg_s * 1e3,
+                "flops_per_launch": op_flops(c, sizes, dom),
+                "traffic": traffic_from_profile(dom, args.workload)}
+    if prec == "fp32":
+        roofline.update({"peak": FP32_PEAK / 1e12, "frac": achieved / FP32_PEAK, "bound": "alu"})
+
+    total_flops = sum(flops_per_image(c, h) for h, _ in sizes)
+    result = {
+        "metric": "images/sec ViT-L/14@336 bf16 vs fp32 plain, same GPU; p50/p99 latency @ QPS",
+        "value": value, "unit": "images/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"fp32": "f32", "bf16": "bf16", "fp8w": "fp8w-bf16a"}[prec],
+        "data": "synthetic (seeded U[0,1] pixels, N(0,0.02^2) weights, unit random texts)",
+        "config": {"workload": args.workload, "model": wl.model, "batch": n,
+                   "resolutions": sorted(set(h for h, _ in sizes)), "precision": prec,
+                   "head": wl.head, "n_texts": wl.n_texts, "graphs": not args.no_graphs},
+        "encoder_tflops": total_flops / (ms / 1e3) / 1e12,
+        "mfu_bf16": total_flops / (ms / 1e3) / BF16_PEAK,
+        "op_ms_per_step": breakdown,
+        "roofline": roofline,
+    }
+    if fp8_note:
+        result["roofline"]["note"] = "weight-only e4m3: MFMA runs in BF16"
+
+    if args.fp32_steps > 0 and prec != "fp32":
+        del enc
+        torch.cuda.synchronize()
+        enc32 = vl.Encoder(c, w, "fp32", graphs=not args.no_graphs)
+        step(enc32)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.fp32_steps):
+            step(enc32)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms32 = ev0.elapsed_time(ev1) / args.fp32_steps
+        result["fp32_path"] = {"value": n / (ms32 / 1e3), "unit": "images/s",
+                               "ms_per_step": ms32, "steps": args.fp32_steps,
+                               "speedup_of_value": ms32 / ms}
+        del enc32
+
+    if not args.no_cpu_baseline:
+        k = args.cpu_sample or {"tiny_fp32": 8, "b16_224": 8, "l14_336": 4, "b16_mixed": 6}[
+            args.workload]
+        result["cpu_baseline"] = cpu_baseline(wl, blob, images, texts, k)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

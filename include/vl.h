@@ -1,0 +1,196 @@
+/*
+ * vl.h -- C ABI of the MI355X (gfx950) contrastive image-encoder library.
+ *
+ * The library computes, entirely in hand-written HIP kernels:
+ *   vl_encode_images : pixels -> unit image embeddings.  A ViT image tower
+ *       (Dosovitskiy et al., ICLR 2021, Sec. 3.1, Eq. 1-4): per-channel
+ *       normalisation, P x P patch embedding, class token, (bilinearly
+ *       resampled, Sec. 3.2) position embedding, L pre-LN blocks of
+ *       multi-head self-attention (Vaswani et al. 2017, Sec. 3.2, Eq. 1) and
+ *       a GELU MLP (Hendrycks & Gimpel 2016), final LayerNorm on the class
+ *       token, bias-free projection and L2 normalisation (CLIP, Radford et
+ *       al. 2021, Sec. 2.3).
+ *   vl_score : logits l_ij = scale * <e_i, t_j> + bias against resident text
+ *       embeddings, then a softmax over texts per image (CLIP, Sec. 3.1.2) or
+ *       a sigmoid per pair (SigLIP, Zhai et al. 2023, Eq. 1), plus top-1.
+ * The URBAN-SIM paper (arXiv 2505.00690) consumes per-environment RGB-D
+ * frames at 128x128 in its navigation policy (Appendix, navigation
+ * benchmark, observation spaces); it does not itself specify an encoder.
+ *
+ * Conventions
+ *  - Every pointer named *_dev is device memory on the current HIP device and
+ *    is owned by the caller; the library never frees it.  Host arrays are
+ *    read during the call only.
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream) and never synchronises the device.  Outputs are valid once the
+ *    stream reaches the call.
+ *  - Arguments are validated before anything is enqueued.  On any error
+ *    nothing is enqueued, outputs are untouched, and vl_last_error_message()
+ *    returns a description (thread-local).  A HIP failure after enqueue
+ *    returns VL_ERR_DEVICE.
+ *  - A model may be used from several host threads on different streams,
+ *    provided each concurrent call has its own workspace.
+ */
+#ifndef VL_H_
+#define VL_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VL_ABI_VERSION 1
+
+typedef enum vl_status {
+  VL_OK = 0,
+  VL_ERR_INVALID_ARG = 1,
+  VL_ERR_UNSUPPORTED = 2,
+  VL_ERR_WORKSPACE_TOO_SMALL = 3,
+  VL_ERR_DEVICE = 4,
+  VL_ERR_INTERNAL = 5
+} vl_status;
+
+/* Arithmetic of the encoder.
+ *  VL_FP32       : every operand and accumulator FP32.
+ *  VL_BF16       : block linear weights rounded to BF16 (round to nearest
+ *                  even); GEMM and attention operands BF16 with FP32
+ *                  accumulation; residual stream, LayerNorm statistics,
+ *                  softmax max/sum, final LayerNorm, projection and L2 norm
+ *                  FP32.
+ *  VL_FP8W_BF16A : as VL_BF16, but the four per-block linear weights (QKV,
+ *                  output projection, FC1, FC2) are OCP e4m3fn codes with one
+ *                  FP32 scale per output row, s_o = max_k |W_ok| / 448,
+ *                  q = sat(RNE(W / s_o)) (OFP8 rev 1.0, Sec. 5.1).  Codes are
+ *                  widened to BF16 exactly inside the GEMM and the scale is
+ *                  applied to the FP32 accumulator.                          */
+typedef enum vl_precision {
+  VL_FP32 = 0,
+  VL_BF16 = 1,
+  VL_FP8W_BF16A = 2
+} vl_precision;
+
+typedef enum vl_head {
+  VL_HEAD_SOFTMAX = 0, /* p_ij = softmax_j(l_ij)          */
+  VL_HEAD_SIGMOID = 1  /* p_ij = 1 / (1 + exp(-l_ij))     */
+} vl_head;
+
+/* Model dimensions.  width % heads == 0 and head_dim = width/heads must be
+ * 32 or 64; width % 128 == 0; mlp % 128 == 0; proj_dim % 4 == 0;
+ * width <= 1024.  ln_eps is the LayerNorm epsilon (biased variance).
+ * Pixels are normalised as (x - chan_mean[c]) / chan_std[c].               */
+typedef struct vl_config {
+  int32_t patch;
+  int32_t width;
+  int32_t layers;
+  int32_t heads;
+  int32_t mlp;
+  int32_t proj_dim;
+  int32_t base_grid; /* the position table covers base_grid x base_grid  */
+  float ln_eps;
+  float chan_mean[3];
+  float chan_std[3];
+} vl_config;
+
+typedef struct vl_model vl_model; /* opaque; immutable after creation */
+
+/* Number of FP32 values in the weight blob for `cfg`, 0 if cfg is invalid.
+ * Blob layout: tensors back to back, each C-contiguous, in this order
+ *   patch_w [D,3,P,P]  patch_b [D]  cls [D]  pos [1+g0*g0, D]
+ *   for each of the L blocks:
+ *     ln1_g [D] ln1_b [D] qkv_w [3D,D] qkv_b [3D] o_w [D,D] o_b [D]
+ *     ln2_g [D] ln2_b [D] fc1_w [F,D] fc1_b [F] fc2_w [D,F] fc2_b [D]
+ *   lnf_g [D]  lnf_b [D]  proj_w [P_dim, D]
+ * Linear weights are [out, in] (y = x W^T + b).  qkv_w's rows are
+ * [Q | K | V]; head k uses rows/columns k*d .. k*d+d-1 of each part.  The
+ * position table's row 0 belongs to the class token; rows 1.. are the
+ * g0 x g0 grid, row-major.                                                  */
+size_t vl_weights_count(const vl_config* cfg);
+
+/* Build a model from an FP32 weight blob (device, caller-owned, may be freed
+ * once the stream has passed this call).  The library allocates its own
+ * device copy of the weights in the requested precision (hipMalloc), folds
+ * the pixel normalisation into the patch embedding, and enqueues the
+ * conversion kernels on `stream`.  *out receives the handle.
+ * Errors: VL_ERR_INVALID_ARG (null pointers, bad dims, n_floats mismatch),
+ * VL_ERR_UNSUPPORTED (head_dim not 32/64, width > 1024), VL_ERR_DEVICE.    */
+vl_status vl_model_create(const vl_config* cfg, vl_precision prec,
+                          const float* weights_dev, size_t n_floats,
+                          void* stream, vl_model** out);
+
+/* Frees the model's device memory and cached graphs.  Synchronises the
+ * device first, so in-flight work that reads the model finishes. NULL ok. */
+void vl_model_destroy(vl_model* m);
+
+/* Options (all off by default).
+ *   VL_OPT_GRAPHS : 1 = capture each distinct call (shapes, pointers,
+ *                   stream) into a HIP graph on first use and replay it.
+ *   VL_OPT_TIMING : 1 = bracket every kernel launch of vl_encode_images
+ *                   with HIP events on the call's stream and accumulate
+ *                   per-operation device time (read with
+ *                   vl_model_op_times).  Calls made while timing is on are
+ *                   launched eagerly even if VL_OPT_GRAPHS is set.        */
+typedef enum vl_option { VL_OPT_GRAPHS = 0, VL_OPT_TIMING = 1 } vl_option;
+vl_status vl_model_set_option(vl_model* m, vl_option opt, int64_t value);
+
+/* Operations of the encoder, as reported by vl_model_op_times:
+ *   0 patch embedding (patch gather + GEMM with bias/class/position add)
+ *   1 LayerNorm (both per block)      2 QKV GEMM          3 attention
+ *   4 output projection GEMM (+ residual)                 5 FC1 GEMM (+ GELU)
+ *   6 FC2 GEMM (+ residual)           7 pooling, final LayerNorm, projection,
+ *                                       L2 normalisation                   */
+#define VL_N_OPS 8
+
+/* Waits for all timed launches recorded so far, then writes the summed
+ * device milliseconds and the launch count of each operation into
+ * ms_out[VL_N_OPS] and launches_out[VL_N_OPS] (host arrays; either may be
+ * NULL).  reset != 0 clears the totals afterwards.                         */
+vl_status vl_model_op_times(vl_model* m, double* ms_out, int64_t* launches_out,
+                            int32_t reset);
+
+/* Bytes of device workspace vl_encode_images needs for this batch.
+ * heights/widths: host arrays of n_images entries.  0 on invalid input.   */
+size_t vl_encode_workspace_bytes(const vl_model* m, int32_t n_images,
+                                 const int32_t* heights, const int32_t* widths);
+
+/* Encode n_images images.
+ *  pixels_dev : FP32 images back to back, image i is [3, H_i, W_i]
+ *               (channel, row, column), values as given (normalisation is
+ *               applied inside).  The patch grid is floor(H/P) x floor(W/P);
+ *               pixels past the last whole patch are ignored.
+ *  heights, widths : host arrays; each side >= patch and the grid must have
+ *               at most 1024 patches (1025 tokens).
+ *  emb_out_dev : [n_images, proj_dim] FP32, each row unit-L2 (norm clamped
+ *               at 1e-12).
+ *  workspace_dev : >= vl_encode_workspace_bytes(...) bytes, 256-B aligned.
+ * All images are packed into one variable-length token stream; attention
+ * never crosses images, so each image's result does not depend on what else
+ * is in the batch.                                                          */
+vl_status vl_encode_images(vl_model* m, const float* pixels_dev,
+                           const int32_t* heights, const int32_t* widths,
+                           int32_t n_images, float* emb_out_dev,
+                           void* workspace_dev, size_t workspace_bytes,
+                           void* stream);
+
+/* Score unit image embeddings against text embeddings, FP32 throughout.
+ *  emb_dev   : [n_images, dim]   texts_dev : [n_texts, dim]  (row-major)
+ *  scores_out_dev : [n_images, n_texts] probabilities (softmax over texts)
+ *                   or sigmoids of the logits.
+ *  top1_out_dev   : [n_images] lowest index attaining the maximum logit, or
+ *                   NULL.
+ * dim % 4 == 0.  No workspace.                                             */
+vl_status vl_score(const float* emb_dev, int32_t n_images,
+                   const float* texts_dev, int32_t n_texts, int32_t dim,
+                   vl_head head, float scale, float bias,
+                   float* scores_out_dev, int32_t* top1_out_dev,
+                   void* stream);
+
+const char* vl_status_string(vl_status s);
+const char* vl_last_error_message(void);
+int32_t vl_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VL_H_ */

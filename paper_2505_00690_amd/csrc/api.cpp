@@ -1,0 +1,654 @@
+// C ABI of the encoder library: model construction (weight conversion on the
+// device), batch planning (variable-length packing of mixed-resolution
+// images), workspace layout, kernel sequencing, optional HIP-graph replay,
+// and the scoring entry point.  Declarations and contracts: include/vl.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <list>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/vl.h"
+#include "kernels.hpp"
+
+using namespace vl;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+vl_status fail(vl_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+vl_status hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return VL_ERR_DEVICE;
+}
+
+#define VL_HIP(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);  \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+constexpr int kMaxTokens = 1025;   // 32 x 32 patches + class token
+constexpr int kAttnQ = 128;        // queries per attention work item
+
+struct Layer {
+  const float *ln1_g, *ln1_b, *ln2_g, *ln2_b;
+  const float *qkv_b, *o_b, *fc1_b, *fc2_b;
+  const void *qkv_w, *o_w, *fc1_w, *fc2_w;          // f32, bf16 or e4m3 [out, in]
+  const float *qkv_s, *o_s, *fc1_s, *fc2_s;         // per-row scales (e4m3 only)
+};
+
+// Pinned host buffer holding a call's descriptors while its copy is pending.
+struct Staging {
+  void* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+};
+
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  void* host = nullptr;  // pinned descriptors captured by the graph's copy node
+};
+
+struct TimedLaunch {
+  int op;
+  hipEvent_t start, stop;
+};
+
+}  // namespace
+
+struct vl_model {
+  vl_config cfg;
+  vl_precision prec;
+  int device = 0;
+  int D, F, heads, hd, L, P, Pd, g0, Kpe, Kpad;
+  char* wmem = nullptr;
+  size_t wbytes = 0;
+  const void* patch_w = nullptr;  // folded [D, Kpad], f32 or bf16
+  const float *patch_b, *cls, *pos, *lnf_g, *lnf_b, *proj;
+  std::vector<Layer> layers;
+  bool use_graphs = false;
+  std::mutex mu;
+  std::vector<Staging> ring;
+  size_t ring_pos = 0;
+  std::unordered_map<std::string, GraphEntry> graphs;
+  bool timing = false;
+  std::vector<TimedLaunch> timed;      // recorded, not yet harvested
+  std::vector<hipEvent_t> free_events;
+  double op_ms[VL_N_OPS] = {};
+  int64_t op_launches[VL_N_OPS] = {};
+};
+
+namespace {
+
+bool config_ok(const vl_config* c, std::string* why) {
+  if (!c) { *why = "cfg is NULL"; return false; }
+  if (c->patch < 1 || c->width <= 0 || c->layers < 0 || c->heads <= 0 || c->mlp <= 0 ||
+      c->proj_dim <= 0 || c->base_grid < 1) {
+    *why = "non-positive dimension in cfg";
+    return false;
+  }
+  if (c->width % c->heads) { *why = "width % heads != 0"; return false; }
+  if (c->width % 128 || c->mlp % 128) { *why = "width and mlp must be multiples of 128"; return false; }
+  if (c->proj_dim % 4) { *why = "proj_dim must be a multiple of 4"; return false; }
+  if (c->proj_dim > 1024) { *why = "proj_dim must be <= 1024"; return false; }
+  if (!(c->ln_eps >= 0.f)) { *why = "ln_eps must be >= 0"; return false; }
+  for (int i = 0; i < 3; ++i)
+    if (!(c->chan_std[i] > 0.f)) { *why = "chan_std must be > 0"; return false; }
+  return true;
+}
+
+size_t weights_count(const vl_config& c) {
+  const size_t D = c.width, F = c.mlp, P = c.patch, g = c.base_grid;
+  size_t n = D * 3 * P * P + D + D + (1 + g * g) * D;
+  n += (size_t)c.layers * (2 * D + 3 * D * D + 3 * D + D * D + D + 2 * D + F * D + F + D * F + D);
+  n += 2 * D + (size_t)c.proj_dim * D;
+  return n;
+}
+
+// ----------------------------------------------------------------- planning
+struct Plan {
+  int n = 0, T = 0, max_ntok = 0, n_items = 0;
+  std::vector<ImgDesc> imgs;
+  std::vector<AttnItem> items;
+  size_t desc_bytes = 0;   // imgs + items
+  size_t off_tok = 0, off_X = 0, off_Y = 0, off_QH = 0, total = 0;
+};
+
+bool make_plan(const vl_model* m, int32_t n, const int32_t* hs, const int32_t* ws, Plan* p,
+               std::string* why) {
+  if (n <= 0) { *why = "n_images must be > 0"; return false; }
+  if (!hs || !ws) { *why = "heights/widths are NULL"; return false; }
+  p->n = n;
+  p->imgs.resize(n);
+  p->items.clear();
+  int64_t pix = 0;
+  int64_t T = 0;
+  int max_ntok = 0;
+  for (int i = 0; i < n; ++i) {
+    const int H = hs[i], W = ws[i];
+    if (H < m->P || W < m->P) { *why = "image " + std::to_string(i) + " smaller than one patch"; return false; }
+    const int gh = H / m->P, gw = W / m->P;
+    const int64_t ntok = 1 + (int64_t)gh * gw;
+    if (ntok > kMaxTokens) { *why = "image " + std::to_string(i) + " has more than 1024 patches"; return false; }
+    ImgDesc& d = p->imgs[i];
+    d.pix_off = pix;
+    d.H = H; d.W = W; d.gh = gh; d.gw = gw;
+    d.tok_start = (int32_t)T;
+    d.ntok = (int32_t)ntok;
+    pix += 3LL * H * W;
+    T += ntok;
+    max_ntok = std::max<int>(max_ntok, (int)ntok);
+    for (int q0 = 0; q0 < ntok; q0 += kAttnQ) p->items.push_back(AttnItem{i, q0});
+  }
+  if (T > (1LL << 24)) { *why = "batch exceeds 2^24 tokens"; return false; }
+  p->T = (int)T;
+  p->max_ntok = max_ntok;
+  p->n_items = (int)p->items.size();
+  p->desc_bytes = sizeof(ImgDesc) * n + sizeof(AttnItem) * p->items.size();
+  const size_t es = m->prec == VL_FP32 ? 4 : 2;
+  size_t off = align_up(p->desc_bytes);
+  p->off_tok = off;
+  off += align_up(sizeof(int2) * T);
+  p->off_X = off;
+  off += align_up(4ull * T * m->D);
+  p->off_Y = off;
+  off += align_up(es * T * m->D);
+  p->off_QH = off;
+  const size_t qh_cols = std::max<size_t>({(size_t)3 * m->D, (size_t)m->F, (size_t)m->Kpad});
+  off += align_up(es * T * qh_cols);
+  p->total = off;
+  return true;
+}
+
+// Upload the plan's descriptors with an async copy from pinned memory.
+vl_status stage_descriptors(vl_model* m, const Plan& p, void* dst, hipStream_t s) {
+  Staging& st = m->ring[m->ring_pos];
+  m->ring_pos = (m->ring_pos + 1) % m->ring.size();
+  if (st.pending) {
+    VL_HIP(hipEventSynchronize(st.ev));
+    st.pending = false;
+  }
+  if (st.cap < p.desc_bytes) {
+    if (st.host) VL_HIP(hipHostFree(st.host));
+    st.host = nullptr;
+    st.cap = std::max<size_t>(p.desc_bytes, 16384);
+    VL_HIP(hipHostMalloc(&st.host, st.cap, hipHostMallocDefault));
+  }
+  std::memcpy(st.host, p.imgs.data(), sizeof(ImgDesc) * p.n);
+  std::memcpy(static_cast<char*>(st.host) + sizeof(ImgDesc) * p.n, p.items.data(),
+              sizeof(AttnItem) * p.items.size());
+  VL_HIP(hipMemcpyAsync(dst, st.host, p.desc_bytes, hipMemcpyHostToDevice, s));
+  VL_HIP(hipEventRecord(st.ev, s));
+  st.pending = true;
+  return VL_OK;
+}
+
+enum { T_PATCH = 0, T_LN, T_QKV, T_ATTN, T_OPROJ, T_FC1, T_FC2, T_POOL };
+
+hipError_t take_event(vl_model* m, hipEvent_t* ev) {
+  if (!m->free_events.empty()) {
+    *ev = m->free_events.back();
+    m->free_events.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(ev);
+}
+
+// Brackets the launches of one operation with events when timing is on.
+struct OpScope {
+  vl_model* m;
+  hipStream_t s;
+  TimedLaunch t{};
+  bool on;
+  hipError_t err = hipSuccess;
+  OpScope(vl_model* m_, int op, hipStream_t s_) : m(m_), s(s_), on(m_->timing) {
+    if (!on) return;
+    t.op = op;
+    if ((err = take_event(m, &t.start)) != hipSuccess) return;
+    if ((err = take_event(m, &t.stop)) != hipSuccess) return;
+    err = hipEventRecord(t.start, s);
+  }
+  hipError_t close() {
+    if (!on || err != hipSuccess) return err;
+    err = hipEventRecord(t.stop, s);
+    if (err == hipSuccess) m->timed.push_back(t);
+    return err;
+  }
+};
+
+#define VL_TIMED(op, ...)                                 \
+  do {                                                    \
+    OpScope sc_(m, op, s);                                \
+    if (sc_.err != hipSuccess) return hip_fail(sc_.err, "timing event"); \
+    __VA_ARGS__;                                          \
+    VL_HIP(sc_.close());                                  \
+  } while (0)
+
+// The kernel sequence of one encode call.
+vl_status run_encoder(vl_model* m, const Plan& p, const float* pix, float* emb, char* ws,
+                      hipStream_t s) {
+  const bool f32 = m->prec == VL_FP32;
+  const bool fp8 = m->prec == VL_FP8W_BF16A;
+  const ImgDesc* d_imgs = reinterpret_cast<const ImgDesc*>(ws);
+  const AttnItem* d_items = reinterpret_cast<const AttnItem*>(ws + sizeof(ImgDesc) * p.n);
+  int2* tok = reinterpret_cast<int2*>(ws + p.off_tok);
+  float* X = reinterpret_cast<float*>(ws + p.off_X);
+  void* Y = ws + p.off_Y;
+  void* QH = ws + p.off_QH;
+  const int T = p.T, D = m->D, F = m->F;
+  const float eps = m->cfg.ln_eps;
+
+  EpiArgs pe;
+  pe.bias = m->patch_b;
+  pe.out = X;
+  pe.ldo = D;
+  pe.tok_info = tok;
+  pe.imgs = d_imgs;
+  pe.cls = m->cls;
+  pe.pos = m->pos;
+  pe.base_grid = m->g0;
+  VL_TIMED(T_PATCH, {
+    VL_HIP(im2col(pix, d_imgs, p.n, p.max_ntok, m->P, m->Kpad, QH, !f32, tok, s));
+    if (f32)
+      VL_HIP(gemm_f32(static_cast<const float*>(QH), m->Kpad,
+                      static_cast<const float*>(m->patch_w), m->Kpad, T, D, m->Kpad, OP_PATCH,
+                      pe, s));
+    else
+      VL_HIP(gemm_bf16(static_cast<const bf16_t*>(QH), m->Kpad, m->patch_w, m->Kpad, false, T,
+                       D, m->Kpad, OP_PATCH, pe, s));
+  });
+
+  for (const Layer& ly : m->layers) {
+    VL_TIMED(T_LN, VL_HIP(layernorm_rows(X, ly.ln1_g, ly.ln1_b, eps, Y, !f32, T, D, s)));
+    EpiArgs e1;
+    e1.bias = ly.qkv_b; e1.wscale = ly.qkv_s; e1.out = QH; e1.ldo = 3 * D;
+    EpiArgs e2;
+    e2.bias = ly.o_b; e2.wscale = ly.o_s; e2.out = X; e2.ldo = D;
+    EpiArgs e3;
+    e3.bias = ly.fc1_b; e3.wscale = ly.fc1_s; e3.out = QH; e3.ldo = F;
+    EpiArgs e4;
+    e4.bias = ly.fc2_b; e4.wscale = ly.fc2_s; e4.out = X; e4.ldo = D;
+    if (f32) {
+      const float* y = static_cast<const float*>(Y);
+      const float* qh = static_cast<const float*>(QH);
+      VL_TIMED(T_QKV, VL_HIP(gemm_f32(y, D, static_cast<const float*>(ly.qkv_w), D, T, 3 * D, D,
+                                      OP_QKV, e1, s)));
+      VL_TIMED(T_ATTN, VL_HIP(attention_f32(qh, static_cast<float*>(Y), d_imgs, d_items,
+                                            p.n_items, m->heads, m->hd, s)));
+      VL_TIMED(T_OPROJ, VL_HIP(gemm_f32(y, D, static_cast<const float*>(ly.o_w), D, T, D, D,
+                                        OP_OPROJ, e2, s)));
+      VL_TIMED(T_LN, VL_HIP(layernorm_rows(X, ly.ln2_g, ly.ln2_b, eps, Y, false, T, D, s)));
+      VL_TIMED(T_FC1, VL_HIP(gemm_f32(y, D, static_cast<const float*>(ly.fc1_w), D, T, F, D,
+                                      OP_FC1, e3, s)));
+      VL_TIMED(T_FC2, VL_HIP(gemm_f32(qh, F, static_cast<const float*>(ly.fc2_w), F, T, D, F,
+                                      OP_FC2, e4, s)));
+    } else {
+      const bf16_t* y = static_cast<const bf16_t*>(Y);
+      const bf16_t* qh = static_cast<const bf16_t*>(QH);
+      VL_TIMED(T_QKV, VL_HIP(gemm_bf16(y, D, ly.qkv_w, D, fp8, T, 3 * D, D, OP_QKV, e1, s)));
+      VL_TIMED(T_ATTN, VL_HIP(attention_bf16(qh, static_cast<bf16_t*>(Y), d_imgs, d_items,
+                                             p.n_items, m->heads, m->hd, s)));
+      VL_TIMED(T_OPROJ, VL_HIP(gemm_bf16(y, D, ly.o_w, D, fp8, T, D, D, OP_OPROJ, e2, s)));
+      VL_TIMED(T_LN, VL_HIP(layernorm_rows(X, ly.ln2_g, ly.ln2_b, eps, Y, true, T, D, s)));
+      VL_TIMED(T_FC1, VL_HIP(gemm_bf16(y, D, ly.fc1_w, D, fp8, T, F, D, OP_FC1, e3, s)));
+      VL_TIMED(T_FC2, VL_HIP(gemm_bf16(qh, F, ly.fc2_w, F, fp8, T, D, F, OP_FC2, e4, s)));
+    }
+  }
+  VL_TIMED(T_POOL, VL_HIP(pool_project(X, d_imgs, p.n, m->lnf_g, m->lnf_b, eps, m->proj, D,
+                                        m->Pd, emb, s)));
+  return VL_OK;
+}
+
+std::string graph_key(const Plan& p, const void* pix, const void* emb, const void* ws,
+                      size_t ws_bytes, hipStream_t s) {
+  std::string k;
+  k.reserve(64 + 8 * p.n);
+  auto put = [&](const void* v, size_t n) { k.append(static_cast<const char*>(v), n); };
+  put(&pix, sizeof pix); put(&emb, sizeof emb); put(&ws, sizeof ws); put(&ws_bytes, sizeof ws_bytes);
+  put(&s, sizeof s); put(&p.n, sizeof p.n);
+  for (const ImgDesc& d : p.imgs) { put(&d.H, 4); put(&d.W, 4); }
+  return k;
+}
+
+void destroy_graphs(vl_model* m) {
+  for (auto& kv : m->graphs) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.host) (void)hipHostFree(kv.second.host);
+  }
+  m->graphs.clear();
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+int32_t vl_abi_version(void) { return VL_ABI_VERSION; }
+
+const char* vl_status_string(vl_status s) {
+  switch (s) {
+    case VL_OK: return "ok";
+    case VL_ERR_INVALID_ARG: return "invalid argument";
+    case VL_ERR_UNSUPPORTED: return "unsupported";
+    case VL_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case VL_ERR_DEVICE: return "device error";
+    case VL_ERR_INTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+const char* vl_last_error_message(void) { return g_last_error.c_str(); }
+
+size_t vl_weights_count(const vl_config* cfg) {
+  std::string why;
+  if (!config_ok(cfg, &why)) return 0;
+  return weights_count(*cfg);
+}
+
+vl_status vl_model_create(const vl_config* cfg, vl_precision prec, const float* wdev,
+                          size_t n_floats, void* stream, vl_model** out) {
+  std::string why;
+  if (!out) return fail(VL_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!config_ok(cfg, &why)) return fail(VL_ERR_INVALID_ARG, why);
+  if (!wdev) return fail(VL_ERR_INVALID_ARG, "weights_dev is NULL");
+  if (prec != VL_FP32 && prec != VL_BF16 && prec != VL_FP8W_BF16A)
+    return fail(VL_ERR_INVALID_ARG, "unknown precision");
+  if (n_floats != weights_count(*cfg))
+    return fail(VL_ERR_INVALID_ARG, "weight blob has " + std::to_string(n_floats) +
+                                        " floats, expected " + std::to_string(weights_count(*cfg)));
+  const int hd = cfg->width / cfg->heads;
+  if (hd != 32 && hd != 64) return fail(VL_ERR_UNSUPPORTED, "head_dim must be 32 or 64");
+  if (cfg->width > 1024) return fail(VL_ERR_UNSUPPORTED, "width must be <= 1024");
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  vl_model* m = new vl_model();
+  m->cfg = *cfg;
+  m->prec = prec;
+  if (hipGetDevice(&m->device) != hipSuccess) { delete m; return fail(VL_ERR_DEVICE, "hipGetDevice failed"); }
+  m->D = cfg->width; m->F = cfg->mlp; m->heads = cfg->heads; m->hd = hd; m->L = cfg->layers;
+  m->P = cfg->patch; m->Pd = cfg->proj_dim; m->g0 = cfg->base_grid;
+  m->Kpe = 3 * m->P * m->P;
+  m->Kpad = (m->Kpe + 63) / 64 * 64;
+  const size_t D = m->D, F = m->F, G = 1 + (size_t)m->g0 * m->g0;
+
+  // Source offsets in the FP32 blob (layout in include/vl.h).
+  size_t o = 0;
+  auto take = [&](size_t n) { size_t r = o; o += n; return wdev + r; };
+  const float* s_patch_w = take(D * m->Kpe);
+  const float* s_patch_b = take(D);
+  const float* s_cls = take(D);
+  const float* s_pos = take(G * D);
+  struct SrcLayer { const float *ln1_g, *ln1_b, *qkv_w, *qkv_b, *o_w, *o_b, *ln2_g, *ln2_b, *fc1_w, *fc1_b, *fc2_w, *fc2_b; };
+  std::vector<SrcLayer> src(m->L);
+  for (int l = 0; l < m->L; ++l) {
+    SrcLayer& x = src[l];
+    x.ln1_g = take(D); x.ln1_b = take(D); x.qkv_w = take(3 * D * D); x.qkv_b = take(3 * D);
+    x.o_w = take(D * D); x.o_b = take(D); x.ln2_g = take(D); x.ln2_b = take(D);
+    x.fc1_w = take(F * D); x.fc1_b = take(F); x.fc2_w = take(D * F); x.fc2_b = take(D);
+  }
+  const float* s_lnf_g = take(D);
+  const float* s_lnf_b = take(D);
+  const float* s_proj = take((size_t)m->Pd * D);
+
+  // Destination layout.
+  const size_t wes = prec == VL_FP32 ? 4 : (prec == VL_BF16 ? 2 : 1);
+  const size_t pes = prec == VL_FP32 ? 4 : 2;
+  size_t sz = 0;
+  auto alloc = [&](size_t bytes) { size_t r = sz; sz += align_up(bytes); return r; };
+  const size_t d_patch_w = alloc(pes * D * m->Kpad);
+  const size_t d_patch_b = alloc(4 * D);
+  const size_t d_cls = alloc(4 * D);
+  const size_t d_pos = alloc(4 * G * D);
+  struct DstLayer { size_t ln1_g, ln1_b, ln2_g, ln2_b, qkv_b, o_b, fc1_b, fc2_b, qkv_w, o_w, fc1_w, fc2_w, qkv_s, o_s, fc1_s, fc2_s; };
+  std::vector<DstLayer> dl(m->L);
+  for (int l = 0; l < m->L; ++l) {
+    DstLayer& x = dl[l];
+    x.ln1_g = alloc(4 * D); x.ln1_b = alloc(4 * D); x.ln2_g = alloc(4 * D); x.ln2_b = alloc(4 * D);
+    x.qkv_b = alloc(4 * 3 * D); x.o_b = alloc(4 * D); x.fc1_b = alloc(4 * F); x.fc2_b = alloc(4 * D);
+    x.qkv_w = alloc(wes * 3 * D * D); x.o_w = alloc(wes * D * D);
+    x.fc1_w = alloc(wes * F * D); x.fc2_w = alloc(wes * D * F);
+    if (prec == VL_FP8W_BF16A) {
+      x.qkv_s = alloc(4 * 3 * D); x.o_s = alloc(4 * D); x.fc1_s = alloc(4 * F); x.fc2_s = alloc(4 * D);
+    }
+  }
+  const size_t d_lnf_g = alloc(4 * D);
+  const size_t d_lnf_b = alloc(4 * D);
+  const size_t d_proj = alloc(4 * (size_t)m->Pd * D);
+  m->wbytes = sz;
+  {
+    hipError_t e = hipMalloc(&m->wmem, sz);
+    if (e != hipSuccess) { delete m; return hip_fail(e, "hipMalloc(model weights)"); }
+  }
+  char* b = m->wmem;
+  auto f = [&](size_t off) { return reinterpret_cast<float*>(b + off); };
+
+  vl_status st = VL_OK;
+  auto chk = [&](hipError_t e, const char* what) {
+    if (st == VL_OK && e != hipSuccess) st = hip_fail(e, what);
+  };
+  chk(fold_patch_weights(s_patch_w, s_patch_b, cfg->chan_mean, cfg->chan_std, m->D, m->P, m->Kpad,
+                         prec == VL_FP32 ? f(d_patch_w) : nullptr,
+                         prec == VL_FP32 ? nullptr : reinterpret_cast<bf16_t*>(b + d_patch_w),
+                         f(d_patch_b), s),
+      "fold_patch_weights");
+  chk(copy_f32(s_cls, f(d_cls), D, s), "copy cls");
+  chk(copy_f32(s_pos, f(d_pos), G * D, s), "copy pos");
+  auto conv_w = [&](const float* src_w, size_t dst_off, size_t scale_off, int rows, int cols) {
+    if (prec == VL_FP32)
+      chk(copy_f32(src_w, f(dst_off), (size_t)rows * cols, s), "copy weight");
+    else if (prec == VL_BF16)
+      chk(convert_bf16(src_w, reinterpret_cast<bf16_t*>(b + dst_off), (size_t)rows * cols, s),
+          "convert_bf16");
+    else
+      chk(quantise_e4m3_rows(src_w, reinterpret_cast<uint8_t*>(b + dst_off), f(scale_off), rows,
+                             cols, s),
+          "quantise_e4m3_rows");
+  };
+  m->layers.resize(m->L);
+  for (int l = 0; l < m->L; ++l) {
+    const SrcLayer& x = src[l];
+    const DstLayer& y = dl[l];
+    chk(copy_f32(x.ln1_g, f(y.ln1_g), D, s), "copy");
+    chk(copy_f32(x.ln1_b, f(y.ln1_b), D, s), "copy");
+    chk(copy_f32(x.ln2_g, f(y.ln2_g), D, s), "copy");
+    chk(copy_f32(x.ln2_b, f(y.ln2_b), D, s), "copy");
+    chk(copy_f32(x.qkv_b, f(y.qkv_b), 3 * D, s), "copy");
+    chk(copy_f32(x.o_b, f(y.o_b), D, s), "copy");
+    chk(copy_f32(x.fc1_b, f(y.fc1_b), F, s), "copy");
+    chk(copy_f32(x.fc2_b, f(y.fc2_b), D, s), "copy");
+    conv_w(x.qkv_w, y.qkv_w, y.qkv_s, 3 * m->D, m->D);
+    conv_w(x.o_w, y.o_w, y.o_s, m->D, m->D);
+    conv_w(x.fc1_w, y.fc1_w, y.fc1_s, m->F, m->D);
+    conv_w(x.fc2_w, y.fc2_w, y.fc2_s, m->D, m->F);
+    Layer& ly = m->layers[l];
+    ly.ln1_g = f(y.ln1_g); ly.ln1_b = f(y.ln1_b); ly.ln2_g = f(y.ln2_g); ly.ln2_b = f(y.ln2_b);
+    ly.qkv_b = f(y.qkv_b); ly.o_b = f(y.o_b); ly.fc1_b = f(y.fc1_b); ly.fc2_b = f(y.fc2_b);
+    ly.qkv_w = b + y.qkv_w; ly.o_w = b + y.o_w; ly.fc1_w = b + y.fc1_w; ly.fc2_w = b + y.fc2_w;
+    const bool q8 = prec == VL_FP8W_BF16A;
+    ly.qkv_s = q8 ? f(y.qkv_s) : nullptr; ly.o_s = q8 ? f(y.o_s) : nullptr;
+    ly.fc1_s = q8 ? f(y.fc1_s) : nullptr; ly.fc2_s = q8 ? f(y.fc2_s) : nullptr;
+  }
+  chk(copy_f32(s_lnf_g, f(d_lnf_g), D, s), "copy");
+  chk(copy_f32(s_lnf_b, f(d_lnf_b), D, s), "copy");
+  chk(copy_f32(s_proj, f(d_proj), (size_t)m->Pd * D, s), "copy");
+  m->patch_w = b + d_patch_w;
+  m->patch_b = f(d_patch_b);
+  m->cls = f(d_cls);
+  m->pos = f(d_pos);
+  m->lnf_g = f(d_lnf_g);
+  m->lnf_b = f(d_lnf_b);
+  m->proj = f(d_proj);
+  m->ring.resize(8);
+  for (Staging& r : m->ring) chk(hipEventCreateWithFlags(&r.ev, hipEventDisableTiming), "hipEventCreate");
+  if (st != VL_OK) {
+    vl_model_destroy(m);
+    return st;
+  }
+  *out = m;
+  return VL_OK;
+}
+
+void vl_model_destroy(vl_model* m) {
+  if (!m) return;
+  (void)hipDeviceSynchronize();
+  destroy_graphs(m);
+  for (TimedLaunch& t : m->timed) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  for (hipEvent_t e : m->free_events) (void)hipEventDestroy(e);
+  for (Staging& r : m->ring) {
+    if (r.host) (void)hipHostFree(r.host);
+    if (r.ev) (void)hipEventDestroy(r.ev);
+  }
+  if (m->wmem) (void)hipFree(m->wmem);
+  delete m;
+}
+
+vl_status vl_model_set_option(vl_model* m, vl_option opt, int64_t value) {
+  if (!m) return fail(VL_ERR_INVALID_ARG, "model is NULL");
+  std::lock_guard<std::mutex> lk(m->mu);
+  switch (opt) {
+    case VL_OPT_GRAPHS:
+      m->use_graphs = value != 0;
+      if (!m->use_graphs) {
+        (void)hipDeviceSynchronize();
+        destroy_graphs(m);
+      }
+      return VL_OK;
+    case VL_OPT_TIMING:
+      m->timing = value != 0;
+      return VL_OK;
+  }
+  return fail(VL_ERR_INVALID_ARG, "unknown option");
+}
+
+vl_status vl_model_op_times(vl_model* m, double* ms_out, int64_t* launches_out, int32_t reset) {
+  if (!m) return fail(VL_ERR_INVALID_ARG, "model is NULL");
+  std::lock_guard<std::mutex> lk(m->mu);
+  for (TimedLaunch& t : m->timed) {
+    VL_HIP(hipEventSynchronize(t.stop));
+    float ms = 0.f;
+    VL_HIP(hipEventElapsedTime(&ms, t.start, t.stop));
+    m->op_ms[t.op] += ms;
+    m->op_launches[t.op] += 1;
+    m->free_events.push_back(t.start);
+    m->free_events.push_back(t.stop);
+  }
+  m->timed.clear();
+  for (int i = 0; i < VL_N_OPS; ++i) {
+    if (ms_out) ms_out[i] = m->op_ms[i];
+    if (launches_out) launches_out[i] = m->op_launches[i];
+    if (reset) {
+      m->op_ms[i] = 0.0;
+      m->op_launches[i] = 0;
+    }
+  }
+  return VL_OK;
+}
+
+size_t vl_encode_workspace_bytes(const vl_model* m, int32_t n, const int32_t* hs,
+                                 const int32_t* ws) {
+  if (!m) return 0;
+  Plan p;
+  std::string why;
+  if (!make_plan(m, n, hs, ws, &p, &why)) return 0;
+  return p.total;
+}
+
+vl_status vl_encode_images(vl_model* m, const float* pix, const int32_t* hs, const int32_t* wsz,
+                           int32_t n, float* emb, void* ws, size_t ws_bytes, void* stream) {
+  if (!m) return fail(VL_ERR_INVALID_ARG, "model is NULL");
+  if (!pix || !emb || !ws) return fail(VL_ERR_INVALID_ARG, "pixels, emb_out or workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(VL_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (reinterpret_cast<uintptr_t>(pix) % 16 || reinterpret_cast<uintptr_t>(emb) % 16)
+    return fail(VL_ERR_INVALID_ARG, "pixels and emb_out must be 16-byte aligned");
+  Plan p;
+  std::string why;
+  if (!make_plan(m, n, hs, wsz, &p, &why)) return fail(VL_ERR_INVALID_ARG, why);
+  if (ws_bytes < p.total)
+    return fail(VL_ERR_WORKSPACE_TOO_SMALL, "workspace has " + std::to_string(ws_bytes) +
+                                                " bytes, needs " + std::to_string(p.total));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  std::lock_guard<std::mutex> lk(m->mu);
+  if (!m->use_graphs || m->timing) {
+    vl_status st = stage_descriptors(m, p, w, s);
+    if (st != VL_OK) return st;
+    return run_encoder(m, p, pix, emb, w, s);
+  }
+  const std::string key = graph_key(p, pix, emb, ws, ws_bytes, s);
+  auto it = m->graphs.find(key);
+  if (it == m->graphs.end()) {
+    if (m->graphs.size() >= 64) {
+      VL_HIP(hipStreamSynchronize(s));
+      (void)hipDeviceSynchronize();
+      destroy_graphs(m);
+    }
+    GraphEntry ge;
+    VL_HIP(hipHostMalloc(&ge.host, std::max<size_t>(p.desc_bytes, 256), hipHostMallocDefault));
+    std::memcpy(ge.host, p.imgs.data(), sizeof(ImgDesc) * p.n);
+    std::memcpy(static_cast<char*>(ge.host) + sizeof(ImgDesc) * p.n, p.items.data(),
+                sizeof(AttnItem) * p.items.size());
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { (void)hipHostFree(ge.host); return hip_fail(e, "hipStreamBeginCapture"); }
+    vl_status st = VL_OK;
+    e = hipMemcpyAsync(w, ge.host, p.desc_bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) st = hip_fail(e, "hipMemcpyAsync(descriptors)");
+    if (st == VL_OK) st = run_encoder(m, p, pix, emb, w, s);
+    e = hipStreamEndCapture(s, &g);
+    if (st == VL_OK && e != hipSuccess) st = hip_fail(e, "hipStreamEndCapture");
+    if (st == VL_OK) {
+      e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) st = hip_fail(e, "hipGraphInstantiate");
+    }
+    if (g) (void)hipGraphDestroy(g);
+    if (st != VL_OK) { (void)hipHostFree(ge.host); return st; }
+    it = m->graphs.emplace(key, ge).first;
+  }
+  VL_HIP(hipGraphLaunch(it->second.exec, s));
+  return VL_OK;
+}
+
+vl_status vl_score(const float* emb, int32_t n_images, const float* texts, int32_t n_texts,
+                   int32_t dim, vl_head head, float scale, float bias, float* scores,
+                   int32_t* top1, void* stream) {
+  if (!emb || !texts || !scores) return fail(VL_ERR_INVALID_ARG, "NULL pointer argument");
+  if (n_images <= 0 || n_texts <= 0 || dim <= 0) return fail(VL_ERR_INVALID_ARG, "sizes must be > 0");
+  if (dim % 16) return fail(VL_ERR_INVALID_ARG, "dim must be a multiple of 16");
+  if (n_texts % 4) return fail(VL_ERR_INVALID_ARG, "n_texts must be a multiple of 4");
+  if (head != VL_HEAD_SOFTMAX && head != VL_HEAD_SIGMOID) return fail(VL_ERR_INVALID_ARG, "unknown head");
+  if (!std::isfinite(scale) || !std::isfinite(bias)) return fail(VL_ERR_INVALID_ARG, "scale/bias not finite");
+  if (reinterpret_cast<uintptr_t>(emb) % 16 || reinterpret_cast<uintptr_t>(texts) % 16 ||
+      reinterpret_cast<uintptr_t>(scores) % 16)
+    return fail(VL_ERR_INVALID_ARG, "emb, texts and scores must be 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  EpiArgs e;
+  e.out = scores;
+  e.ldo = n_texts;
+  e.alpha = scale;
+  e.beta = bias;
+  VL_HIP(gemm_f32(emb, dim, texts, dim, n_images, n_texts, dim, OP_LOGITS, e, s));
+  VL_HIP(score_rows(scores, top1, n_images, n_texts, head == VL_HEAD_SOFTMAX ? 0 : 1, s));
+  return VL_OK;
+}
+
+}  // extern "C"

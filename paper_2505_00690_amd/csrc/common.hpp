@@ -1,0 +1,61 @@
+// Shared device-side types and helpers for the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vl {
+
+typedef uint16_t bf16_t;  // BF16 bit pattern
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// FP32 -> BF16, round to nearest even (inputs are finite).
+__device__ __forceinline__ uint32_t f32_to_bf16_bits(float x) {
+  uint32_t b = __float_as_uint(x);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return b >> 16;
+}
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  return f32_to_bf16_bits(lo) | (f32_to_bf16_bits(hi) << 16);
+}
+__device__ __forceinline__ float bf16_bits_to_f32(uint32_t h) {
+  return __uint_as_float(h << 16);
+}
+
+// OCP e4m3fn code (byte) -> BF16 bits.  Exact: every e4m3 value has a BF16
+// representation.  Normal codes (exponent field e >= 1) map to BF16 exponent
+// e + 120 with the 3 significand bits shifted up by 4; subnormal codes
+// (e == 0) are m * 2^-9.
+__device__ __forceinline__ uint32_t e4m3_to_bf16_bits(uint32_t b) {
+  uint32_t s = (b & 0x80u) << 8;
+  uint32_t mag = b & 0x7Fu;
+  uint32_t r;
+  if (mag >= 8u) {
+    r = (mag << 4) + 0x3C00u;
+  } else {
+    r = __float_as_uint((float)mag * 0.001953125f) >> 16;
+  }
+  return s | r;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// GELU(x) = x * Phi(x) = x/2 * (1 + erf(x / sqrt 2)), exact-erf form.
+__device__ __forceinline__ float gelu_erf(float x) {
+  return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
+}
+
+}  // namespace vl

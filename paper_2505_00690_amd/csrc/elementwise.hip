@@ -1,0 +1,335 @@
+// Row and elementwise kernels: LayerNorm, patch gathering, class-token
+// pooling with projection and L2 normalisation, scoring heads, and the
+// weight preparation done once per model.
+#include "kernels.hpp"
+
+namespace vl {
+
+// ---------------------------------------------------------------- LayerNorm
+// LayerNorm (Ba et al. 2016, Sec. 3): mean and biased variance of each row,
+// computed in FP32 with two passes over registers.  One wave per row.
+template <int NPER, bool OUT_BF16>
+__global__ __launch_bounds__(256) void k_layernorm(const float* __restrict__ x,
+                                                   const float* __restrict__ gm,
+                                                   const float* __restrict__ bt, float eps,
+                                                   void* __restrict__ y, int M) {
+  constexpr int D = NPER * 64;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= M) return;
+  const float* xr = x + (size_t)row * D;
+  float v[NPER];
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < NPER; ++i) {
+    v[i] = xr[lane + 64 * i];
+    s += v[i];
+  }
+  const float mean = wave_sum(s) * (1.f / D);
+  float q = 0.f;
+#pragma unroll
+  for (int i = 0; i < NPER; ++i) {
+    v[i] -= mean;
+    q += v[i] * v[i];
+  }
+  const float rstd = rsqrtf(wave_sum(q) * (1.f / D) + eps);
+#pragma unroll
+  for (int i = 0; i < NPER; ++i) {
+    const int c = lane + 64 * i;
+    const float o = v[i] * rstd * gm[c] + bt[c];
+    if (OUT_BF16)
+      static_cast<bf16_t*>(y)[(size_t)row * D + c] = (bf16_t)f32_to_bf16_bits(o);
+    else
+      static_cast<float*>(y)[(size_t)row * D + c] = o;
+  }
+}
+
+template <int NPER>
+static void launch_ln(const float* x, const float* g, const float* b, float eps, void* y,
+                      bool y_bf16, int M, hipStream_t s) {
+  dim3 grid((M + 3) / 4), block(256);
+  if (y_bf16)
+    hipLaunchKernelGGL((k_layernorm<NPER, true>), grid, block, 0, s, x, g, b, eps, y, M);
+  else
+    hipLaunchKernelGGL((k_layernorm<NPER, false>), grid, block, 0, s, x, g, b, eps, y, M);
+}
+
+hipError_t layernorm_rows(const float* x, const float* g, const float* b, float eps, void* y,
+                          bool y_bf16, int M, int D, hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  switch (D / 64) {
+    case 2: launch_ln<2>(x, g, b, eps, y, y_bf16, M, s); break;
+    case 4: launch_ln<4>(x, g, b, eps, y, y_bf16, M, s); break;
+    case 6: launch_ln<6>(x, g, b, eps, y, y_bf16, M, s); break;
+    case 8: launch_ln<8>(x, g, b, eps, y, y_bf16, M, s); break;
+    case 10: launch_ln<10>(x, g, b, eps, y, y_bf16, M, s); break;
+    case 12: launch_ln<12>(x, g, b, eps, y, y_bf16, M, s); break;
+    case 14: launch_ln<14>(x, g, b, eps, y, y_bf16, M, s); break;
+    case 16: launch_ln<16>(x, g, b, eps, y, y_bf16, M, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ im2col
+// Token row t of image i: zeros for the class token, otherwise the patch's
+// raw pixels in (channel, row-in-patch, column-in-patch) order followed by
+// zero padding to kpad.  One wave per token; blockIdx.y is the image.
+template <bool OUT_BF16>
+__global__ __launch_bounds__(256) void k_im2col(const float* __restrict__ pix,
+                                                const ImgDesc* __restrict__ imgs, int patch,
+                                                int kpad, void* __restrict__ out,
+                                                int2* __restrict__ tok_info) {
+  const ImgDesc d = imgs[blockIdx.y];
+  const int tok = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (tok >= d.ntok) return;
+  const int t = d.tok_start + tok;
+  if (lane == 0) tok_info[t] = make_int2(blockIdx.y, tok);
+  const int pp = patch * patch, kreal = 3 * pp;
+  int r = 0, q = 0;
+  if (tok > 0) {
+    r = (tok - 1) / d.gw;
+    q = (tok - 1) - r * d.gw;
+  }
+  const float* src = pix + d.pix_off;
+  for (int k = lane; k < kpad; k += 64) {
+    float v = 0.f;
+    if (tok > 0 && k < kreal) {
+      const int c = k / pp, rem = k - c * pp;
+      const int a = rem / patch, b = rem - a * patch;
+      v = src[(size_t)c * d.H * d.W + (size_t)(r * patch + a) * d.W + q * patch + b];
+    }
+    if (OUT_BF16)
+      static_cast<bf16_t*>(out)[(size_t)t * kpad + k] = (bf16_t)f32_to_bf16_bits(v);
+    else
+      static_cast<float*>(out)[(size_t)t * kpad + k] = v;
+  }
+}
+
+hipError_t im2col(const float* pix, const ImgDesc* imgs, int n_imgs, int max_ntok, int patch,
+                  int kpad, void* out, bool out_bf16, int2* tok_info, hipStream_t s) {
+  if (n_imgs <= 0) return hipSuccess;
+  dim3 grid((max_ntok + 3) / 4, n_imgs), block(256);
+  if (out_bf16)
+    hipLaunchKernelGGL(k_im2col<true>, grid, block, 0, s, pix, imgs, patch, kpad, out, tok_info);
+  else
+    hipLaunchKernelGGL(k_im2col<false>, grid, block, 0, s, pix, imgs, patch, kpad, out, tok_info);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ block reduce
+template <typename Op>
+__device__ __forceinline__ float block_reduce(float v, float* red, Op op) {
+  // 256 threads = 4 waves
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  v = op(op(red[0], red[1]), op(red[2], red[3]));
+  return v;
+}
+
+// ----------------------------------------------------- pool + LN + proj + L2
+// Class-token pooling, final LayerNorm (ViT Eq. 4), bias-free projection and
+// division by the L2 norm (clamped at 1e-12), all FP32.  One workgroup per
+// image.
+__global__ __launch_bounds__(256) void k_pool_project(const float* __restrict__ x,
+                                                      const ImgDesc* __restrict__ imgs,
+                                                      const float* __restrict__ gm,
+                                                      const float* __restrict__ bt, float eps,
+                                                      const float* __restrict__ proj, int D,
+                                                      int P, float* __restrict__ emb) {
+  __shared__ float z[1024];
+  __shared__ float e[1024];
+  __shared__ float red[4];
+  const int tid = threadIdx.x;
+  const ImgDesc d = imgs[blockIdx.x];
+  const float* xr = x + (size_t)d.tok_start * D;
+  float s = 0.f;
+  for (int c = tid; c < D; c += 256) {
+    z[c] = xr[c];
+    s += z[c];
+  }
+  const float mean = block_reduce(s, red, [](float a, float b) { return a + b; }) / D;
+  float q = 0.f;
+  for (int c = tid; c < D; c += 256) {
+    const float v = z[c] - mean;
+    q += v * v;
+  }
+  const float rstd = rsqrtf(block_reduce(q, red, [](float a, float b) { return a + b; }) / D + eps);
+  for (int c = tid; c < D; c += 256) z[c] = (z[c] - mean) * rstd * gm[c] + bt[c];
+  __syncthreads();
+  const int lane = tid & 63, w = tid >> 6;
+  for (int p = w; p < P; p += 4) {
+    const float* wr = proj + (size_t)p * D;
+    float a = 0.f;
+    for (int c = lane; c < D; c += 64) a = fmaf(wr[c], z[c], a);
+    a = wave_sum(a);
+    if (lane == 0) e[p] = a;
+  }
+  __syncthreads();
+  float n2 = 0.f;
+  for (int p = tid; p < P; p += 256) n2 += e[p] * e[p];
+  const float nrm = sqrtf(block_reduce(n2, red, [](float a, float b) { return a + b; }));
+  const float inv = 1.f / fmaxf(nrm, 1e-12f);
+  for (int p = tid; p < P; p += 256) emb[(size_t)blockIdx.x * P + p] = e[p] * inv;
+}
+
+hipError_t pool_project(const float* x, const ImgDesc* imgs, int n_imgs, const float* g,
+                        const float* b, float eps, const float* proj, int D, int P, float* emb,
+                        hipStream_t s) {
+  if (n_imgs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pool_project, dim3(n_imgs), dim3(256), 0, s, x, imgs, g, b, eps, proj, D,
+                     P, emb);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- score heads
+// In place over logit rows: CLIP head = softmax over the row (texts), SigLIP
+// head = sigmoid of each logit.  top1 = lowest column index of the maximum.
+__global__ __launch_bounds__(256) void k_score_rows(float* __restrict__ sc,
+                                                    int32_t* __restrict__ top1, int cols,
+                                                    int head) {
+  __shared__ float rv[4];
+  __shared__ int ri[4];
+  __shared__ float red[4];
+  float* row = sc + (size_t)blockIdx.x * cols;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  float best = -INFINITY;
+  int bi = 0x7fffffff;
+  for (int c = tid; c < cols; c += 256) {
+    const float v = row[c];
+    if (v > best) { best = v; bi = c; }   // c increases: first max kept
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const float ov = __shfl_xor(best, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+  }
+  if (lane == 0) { rv[w] = best; ri[w] = bi; }
+  __syncthreads();
+  best = rv[0]; bi = ri[0];
+  for (int k = 1; k < 4; ++k)
+    if (rv[k] > best || (rv[k] == best && ri[k] < bi)) { best = rv[k]; bi = ri[k]; }
+  if (top1 && tid == 0) top1[blockIdx.x] = bi;
+  if (head == 0) {
+    float s = 0.f;
+    for (int c = tid; c < cols; c += 256) s += expf(row[c] - best);
+    s = block_reduce(s, red, [](float a, float b) { return a + b; });
+    const float inv = 1.f / s;
+    for (int c = tid; c < cols; c += 256) row[c] = expf(row[c] - best) * inv;
+  } else {
+    for (int c = tid; c < cols; c += 256) row[c] = 1.f / (1.f + expf(-row[c]));
+  }
+}
+
+hipError_t score_rows(float* scores, int32_t* top1, int rows, int cols, int head,
+                      hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_score_rows, dim3(rows), dim3(256), 0, s, scores, top1, cols, head);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------- weight preparation
+__global__ void k_convert_bf16(const float* __restrict__ src, bf16_t* __restrict__ dst,
+                               size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (bf16_t)f32_to_bf16_bits(src[i]);
+}
+
+hipError_t convert_bf16(const float* src, bf16_t* dst, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_convert_bf16, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256),
+                     0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+// OCP e4m3fn encoding (OFP8 rev 1.0, Sec. 5.1) of an FP32 value, round to
+// nearest even, saturating at +-448.  Below 2^-6 the step is 2^-9
+// (subnormal codes 0..7; 8 lands on the smallest normal code 0x08).
+__device__ __forceinline__ uint32_t f32_to_e4m3(float y) {
+  const uint32_t sign = (__float_as_uint(y) >> 24) & 0x80u;
+  const float a = fminf(fabsf(y), 448.f);
+  if (a < 0.015625f) return sign | (uint32_t)rintf(a * 512.f);
+  int ex;
+  const float f = frexpf(a, &ex);      // a = f * 2^ex, f in [0.5, 1)
+  int E = ex - 1;                      // a in [2^E, 2^(E+1))
+  uint32_t mq = (uint32_t)rintf((2.f * f - 1.f) * 8.f);
+  if (mq == 8u) { E += 1; mq = 0u; }
+  return sign | ((uint32_t)(E + 7) << 3) | mq;
+}
+
+// Per-output-row quantiser: s = max|row| / 448 (1 for an all-zero row),
+// code = e4m3(w / s).  One workgroup per row.
+__global__ __launch_bounds__(256) void k_quant_e4m3(const float* __restrict__ src,
+                                                    uint8_t* __restrict__ dst,
+                                                    float* __restrict__ scales, int cols) {
+  __shared__ float red[4];
+  const float* r = src + (size_t)blockIdx.x * cols;
+  float m = 0.f;
+  for (int c = threadIdx.x; c < cols; c += 256) m = fmaxf(m, fabsf(r[c]));
+  m = block_reduce(m, red, [](float a, float b) { return fmaxf(a, b); });
+  float s = m / 448.f;
+  if (!(s > 0.f)) s = 1.f;
+  if (threadIdx.x == 0) scales[blockIdx.x] = s;
+  for (int c = threadIdx.x; c < cols; c += 256)
+    dst[(size_t)blockIdx.x * cols + c] = (uint8_t)f32_to_e4m3(r[c] / s);
+}
+
+hipError_t quantise_e4m3_rows(const float* src, uint8_t* dst, float* scales, int rows, int cols,
+                              hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_quant_e4m3, dim3(rows), dim3(256), 0, s, src, dst, scales, cols);
+  return hipGetLastError();
+}
+
+// Normalisation folded into the patch embedding: W'[d,c,a,b] = W / std_c,
+// b'[d] = b[d] - sum_{c,a,b} W[d,c,a,b] * mean_c / std_c.  Output rows are
+// padded with zeros to kpad columns.  One workgroup per output channel d.
+__global__ __launch_bounds__(256) void k_fold_patch(const float* __restrict__ w,
+                                                    const float* __restrict__ b, float3 mean,
+                                                    float3 stdv, int pp, int kpad,
+                                                    float* __restrict__ w32,
+                                                    bf16_t* __restrict__ w16,
+                                                    float* __restrict__ bout) {
+  __shared__ float red[4];
+  const int d = blockIdx.x;
+  const int kreal = 3 * pp;
+  const float* wr = w + (size_t)d * kreal;
+  float acc = 0.f;
+  for (int k = threadIdx.x; k < kpad; k += 256) {
+    float v = 0.f;
+    if (k < kreal) {
+      const int c = k / pp;
+      const float sd = c == 0 ? stdv.x : (c == 1 ? stdv.y : stdv.z);
+      const float mu = c == 0 ? mean.x : (c == 1 ? mean.y : mean.z);
+      v = wr[k] / sd;
+      acc = fmaf(v, mu, acc);
+    }
+    if (w32) w32[(size_t)d * kpad + k] = v;
+    if (w16) w16[(size_t)d * kpad + k] = (bf16_t)f32_to_bf16_bits(v);
+  }
+  acc = block_reduce(acc, red, [](float a, float c) { return a + c; });
+  if (threadIdx.x == 0) bout[d] = b[d] - acc;
+}
+
+hipError_t fold_patch_weights(const float* w, const float* b, const float* mean,
+                              const float* stdv, int D, int patch, int kpad, float* w_f32,
+                              bf16_t* w_bf16, float* b_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_fold_patch, dim3(D), dim3(256), 0, s, w, b,
+                     make_float3(mean[0], mean[1], mean[2]), make_float3(stdv[0], stdv[1], stdv[2]),
+                     patch * patch, kpad, w_f32, w_bf16, b_out);
+  return hipGetLastError();
+}
+
+hipError_t copy_f32(const float* src, float* dst, size_t n, hipStream_t s) {
+  return hipMemcpyAsync(dst, src, n * sizeof(float), hipMemcpyDeviceToDevice, s);
+}
+
+}  // namespace vl

@@ -1,0 +1,97 @@
+// Launchers of the gfx950 kernels (host-callable).  All launchers enqueue on
+// `s` and return the launch status; shapes are validated by the caller.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace vl {
+
+// Per-image descriptor of a packed batch (uploaded once per call).
+struct ImgDesc {
+  int64_t pix_off;  // offset (floats) of the image in the pixel buffer
+  int32_t H, W;     // pixel size
+  int32_t gh, gw;   // patch grid
+  int32_t tok_start, ntok;  // first token row in the packed stream, 1+gh*gw
+};
+static_assert(sizeof(ImgDesc) == 32, "ImgDesc layout");
+
+// One attention work item: a block of up to 128 queries of one image.
+struct AttnItem {
+  int32_t img;
+  int32_t q0;
+};
+
+// The contractions of the path.  Each has its own kernel instantiation (so
+// profiles name them apart) and a fixed epilogue:
+//   OP_PATCH  : X[m,n] = acc + (class token ? cls[n] : bias[n]) + pos(m,n)
+//   OP_QKV    : out = acc * ws[n] + bias[n]              (BF16 / FP32 out)
+//   OP_OPROJ  : resid[m,n] += acc * ws[n] + bias[n]      (FP32)
+//   OP_FC1    : out = GELU(acc * ws[n] + bias[n])        (BF16 / FP32 out)
+//   OP_FC2    : resid[m,n] += acc * ws[n] + bias[n]      (FP32)
+//   OP_LOGITS : out = alpha * acc + beta                 (FP32)
+enum GemmOp { OP_PATCH = 0, OP_QKV = 1, OP_OPROJ = 2, OP_FC1 = 3, OP_FC2 = 4, OP_LOGITS = 5 };
+
+struct EpiArgs {
+  const float* bias = nullptr;    // [N]
+  const float* wscale = nullptr;  // [N] per-output-row weight scale (FP8)
+  void* out = nullptr;            // [M, ldo], BF16 or FP32
+  int ldo = 0;
+  // patch embedding
+  const int2* tok_info = nullptr;  // [M]: (image, token index in image)
+  const ImgDesc* imgs = nullptr;
+  const float* cls = nullptr;      // [D]
+  const float* pos = nullptr;      // [1 + g0*g0, D]
+  int base_grid = 0;
+  float alpha = 1.f, beta = 0.f;
+};
+
+// C[M,N] = A[M,K] . B[N,K]^T with BF16 A and BF16 (or e4m3 when b_fp8) B,
+// FP32 accumulation, BF16 output for OP_QKV / OP_FC1.  K % 64 == 0,
+// N % 8 == 0.
+hipError_t gemm_bf16(const bf16_t* A, int lda, const void* B, int ldb, bool b_fp8,
+                     int M, int N, int K, int op, const EpiArgs& e, hipStream_t s);
+
+// The same contraction in FP32 (FMA), output FP32.  K % 16 == 0, N % 4 == 0.
+hipError_t gemm_f32(const float* A, int lda, const float* B, int ldb, int M, int N,
+                    int K, int op, const EpiArgs& e, hipStream_t s);
+
+// LayerNorm of FP32 rows [M, D] -> BF16 or FP32 rows.
+hipError_t layernorm_rows(const float* x, const float* g, const float* b, float eps,
+                          void* y, bool y_bf16, int M, int D, hipStream_t s);
+
+// Patch gathering: token rows [T, Kpad] of raw pixels in (c, a, b) order
+// (class-token rows and the K padding are zero) plus tok_info [T].
+hipError_t im2col(const float* pix, const ImgDesc* imgs, int n_imgs, int max_ntok,
+                  int patch, int kpad, void* out, bool out_bf16, int2* tok_info,
+                  hipStream_t s);
+
+// Multi-head self-attention over a packed QKV buffer [T, 3D] -> O [T, D].
+hipError_t attention_bf16(const bf16_t* qkv, bf16_t* o, const ImgDesc* imgs,
+                          const AttnItem* items, int n_items, int heads, int head_dim,
+                          hipStream_t s);
+hipError_t attention_f32(const float* qkv, float* o, const ImgDesc* imgs,
+                         const AttnItem* items, int n_items, int heads, int head_dim,
+                         hipStream_t s);
+
+// Class-token pooling, final LayerNorm, projection [P, D], L2 normalisation.
+hipError_t pool_project(const float* x, const ImgDesc* imgs, int n_imgs, const float* g,
+                        const float* b, float eps, const float* proj, int D, int P,
+                        float* emb, hipStream_t s);
+
+// Per-row softmax / sigmoid of logits in place, and the row argmax.
+hipError_t score_rows(float* scores, int32_t* top1, int rows, int cols, int head,
+                      hipStream_t s);
+
+// Weight preparation.
+hipError_t convert_bf16(const float* src, bf16_t* dst, size_t n, hipStream_t s);
+hipError_t quantise_e4m3_rows(const float* src, uint8_t* dst, float* scales, int rows,
+                              int cols, hipStream_t s);
+hipError_t fold_patch_weights(const float* w, const float* b, const float* mean,
+                              const float* stdv, int D, int patch, int kpad,
+                              float* w_f32, bf16_t* w_bf16, float* b_out, hipStream_t s);
+hipError_t copy_f32(const float* src, float* dst, size_t n, hipStream_t s);
+
+}  // namespace vl

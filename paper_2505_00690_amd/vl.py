@@ -1,0 +1,256 @@
+"""Python binding of libvl.so (ctypes).  Argument marshalling only: every
+step of the encoder and of the scoring head runs in the library's HIP
+kernels.  PyTorch supplies device memory and streams.
+
+The functions mirror the C ABI in include/vl.h one to one (same names, same
+argument order, tensors in place of device pointers); `Encoder` is a thin
+convenience wrapper that owns a model handle and a workspace tensor.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+__all__ = [
+    "VlError", "VlConfig", "lib", "library_path", "VL_FP32", "VL_BF16", "VL_FP8W_BF16A",
+    "VL_HEAD_SOFTMAX", "VL_HEAD_SIGMOID", "VL_OPT_GRAPHS", "VL_OPT_TIMING",
+    "VL_N_OPS", "OP_NAMES", "vl_model_op_times", "PRECISIONS", "HEADS",
+    "vl_abi_version", "vl_weights_count", "vl_model_create", "vl_model_destroy",
+    "vl_model_set_option", "vl_encode_workspace_bytes", "vl_encode_images", "vl_score",
+    "vl_status_string", "vl_last_error_message", "Encoder", "EXPORTED_SYMBOLS",
+]
+
+VL_FP32, VL_BF16, VL_FP8W_BF16A = 0, 1, 2
+VL_HEAD_SOFTMAX, VL_HEAD_SIGMOID = 0, 1
+VL_OPT_GRAPHS, VL_OPT_TIMING = 0, 1
+VL_N_OPS = 8
+OP_NAMES = ("patch_embed", "layernorm", "qkv_gemm", "attention", "oproj_gemm", "fc1_gemm",
+            "fc2_gemm", "pool_proj_l2")
+PRECISIONS = {"fp32": VL_FP32, "bf16": VL_BF16, "fp8w": VL_FP8W_BF16A}
+HEADS = {"softmax": VL_HEAD_SOFTMAX, "sigmoid": VL_HEAD_SIGMOID}
+
+EXPORTED_SYMBOLS = (
+    "vl_abi_version", "vl_status_string", "vl_last_error_message", "vl_weights_count",
+    "vl_model_create", "vl_model_destroy", "vl_model_set_option",
+    "vl_encode_workspace_bytes", "vl_encode_images", "vl_score", "vl_model_op_times",
+)
+
+
+def library_path() -> str:
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvl.so")
+
+
+class VlError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"vl status {status}: {message}")
+        self.status = status
+
+
+class VlConfig(ctypes.Structure):
+    _fields_ = [
+        ("patch", ctypes.c_int32), ("width", ctypes.c_int32), ("layers", ctypes.c_int32),
+        ("heads", ctypes.c_int32), ("mlp", ctypes.c_int32), ("proj_dim", ctypes.c_int32),
+        ("base_grid", ctypes.c_int32), ("ln_eps", ctypes.c_float),
+        ("chan_mean", ctypes.c_float * 3), ("chan_std", ctypes.c_float * 3),
+    ]
+
+    @classmethod
+    def from_model(cls, c) -> "VlConfig":
+        return cls(int(c.patch), int(c.width), int(c.layers), int(c.heads), int(c.mlp),
+                   int(c.proj_dim), int(c.base_grid), float(c.ln_eps),
+                   (ctypes.c_float * 3)(*c.chan_mean), (ctypes.c_float * 3)(*c.chan_std))
+
+
+_LIB: Optional[ctypes.CDLL] = None
+_vp, _i32, _sz, _f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t, ctypes.c_float
+_pi32 = ctypes.POINTER(ctypes.c_int32)
+
+
+def lib() -> ctypes.CDLL:
+    """Load libvl.so from the package directory; raise if it is not built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it first "
+                           "(python -m paper_2505_00690_amd.build)")
+    L = ctypes.CDLL(path)
+    L.vl_abi_version.restype = _i32
+    L.vl_abi_version.argtypes = []
+    L.vl_status_string.restype = ctypes.c_char_p
+    L.vl_status_string.argtypes = [ctypes.c_int]
+    L.vl_last_error_message.restype = ctypes.c_char_p
+    L.vl_last_error_message.argtypes = []
+    L.vl_weights_count.restype = _sz
+    L.vl_weights_count.argtypes = [ctypes.POINTER(VlConfig)]
+    L.vl_model_create.restype = ctypes.c_int
+    L.vl_model_create.argtypes = [ctypes.POINTER(VlConfig), ctypes.c_int, _vp, _sz, _vp,
+                                  ctypes.POINTER(_vp)]
+    L.vl_model_destroy.restype = None
+    L.vl_model_destroy.argtypes = [_vp]
+    L.vl_model_set_option.restype = ctypes.c_int
+    L.vl_model_set_option.argtypes = [_vp, ctypes.c_int, ctypes.c_int64]
+    L.vl_encode_workspace_bytes.restype = _sz
+    L.vl_encode_workspace_bytes.argtypes = [_vp, _i32, _pi32, _pi32]
+    L.vl_encode_images.restype = ctypes.c_int
+    L.vl_encode_images.argtypes = [_vp, _vp, _pi32, _pi32, _i32, _vp, _vp, _sz, _vp]
+    L.vl_model_op_times.restype = ctypes.c_int
+    L.vl_model_op_times.argtypes = [_vp, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+    L.vl_score.restype = ctypes.c_int
+    L.vl_score.argtypes = [_vp, _i32, _vp, _i32, _i32, ctypes.c_int, _f32, _f32, _vp, _vp, _vp]
+    _LIB = L
+    return L
+
+
+def _check(st: int) -> None:
+    if st != 0:
+        raise VlError(st, lib().vl_last_error_message().decode())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=None, name="tensor") -> ctypes.c_void_p:
+    if t is None:
+        return ctypes.c_void_p(0)
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _i32_array(xs: Sequence[int]):
+    return (ctypes.c_int32 * len(xs))(*[int(x) for x in xs])
+
+
+def vl_abi_version() -> int:
+    return int(lib().vl_abi_version())
+
+
+def vl_status_string(status: int) -> str:
+    return lib().vl_status_string(int(status)).decode()
+
+
+def vl_last_error_message() -> str:
+    return lib().vl_last_error_message().decode()
+
+
+def vl_weights_count(cfg) -> int:
+    c = cfg if isinstance(cfg, VlConfig) else VlConfig.from_model(cfg)
+    return int(lib().vl_weights_count(ctypes.byref(c)))
+
+
+def vl_model_create(cfg, precision, weights: torch.Tensor, stream=None) -> ctypes.c_void_p:
+    c = cfg if isinstance(cfg, VlConfig) else VlConfig.from_model(cfg)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    handle = ctypes.c_void_p()
+    _check(lib().vl_model_create(ctypes.byref(c), prec, _ptr(weights, torch.float32, "weights"),
+                                 weights.numel(), _stream(stream), ctypes.byref(handle)))
+    return handle
+
+
+def vl_model_destroy(handle) -> None:
+    lib().vl_model_destroy(handle)
+
+
+def vl_model_set_option(handle, option: int, value: int) -> None:
+    _check(lib().vl_model_set_option(handle, int(option), int(value)))
+
+
+def vl_model_op_times(handle, reset: bool = False):
+    """{op name: (total ms, launches)} of the timed launches so far."""
+    ms = (ctypes.c_double * VL_N_OPS)()
+    n = (ctypes.c_int64 * VL_N_OPS)()
+    _check(lib().vl_model_op_times(handle, ms, n, 1 if reset else 0))
+    return {OP_NAMES[i]: (float(ms[i]), int(n[i])) for i in range(VL_N_OPS)}
+
+
+def vl_encode_workspace_bytes(handle, heights: Sequence[int], widths: Sequence[int]) -> int:
+    return int(lib().vl_encode_workspace_bytes(handle, len(heights), _i32_array(heights),
+                                               _i32_array(widths)))
+
+
+def vl_encode_images(handle, pixels: torch.Tensor, heights: Sequence[int],
+                     widths: Sequence[int], emb_out: torch.Tensor, workspace: torch.Tensor,
+                     stream=None) -> None:
+    if len(heights) != len(widths):
+        raise ValueError("heights and widths differ in length")
+    _check(lib().vl_encode_images(handle, _ptr(pixels, torch.float32, "pixels"),
+                                  _i32_array(heights), _i32_array(widths), len(heights),
+                                  _ptr(emb_out, torch.float32, "emb_out"),
+                                  _ptr(workspace, None, "workspace"),
+                                  workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def vl_score(emb: torch.Tensor, texts: torch.Tensor, head, scale: float, bias: float,
+             scores_out: torch.Tensor, top1_out: Optional[torch.Tensor] = None,
+             stream=None) -> None:
+    h = HEADS[head] if isinstance(head, str) else int(head)
+    n, dim = emb.shape
+    m = texts.shape[0]
+    if texts.shape[1] != dim:
+        raise ValueError("emb and texts differ in width")
+    _check(lib().vl_score(_ptr(emb, torch.float32, "emb"), n, _ptr(texts, torch.float32, "texts"),
+                          m, dim, h, float(scale), float(bias),
+                          _ptr(scores_out, torch.float32, "scores_out"),
+                          _ptr(top1_out, torch.int32, "top1_out"), _stream(stream)))
+
+
+class Encoder:
+    """Owns a model handle built from an FP32 weight blob on the device, plus
+    a reusable workspace tensor."""
+
+    def __init__(self, cfg, weights: torch.Tensor, precision: str = "bf16",
+                 graphs: bool = False, stream=None):
+        self.cfg = cfg
+        self.precision = precision
+        self.handle = vl_model_create(cfg, precision, weights, stream)
+        if graphs:
+            vl_model_set_option(self.handle, VL_OPT_GRAPHS, 1)
+        self._ws: Optional[torch.Tensor] = None
+        self.device = weights.device
+
+    def close(self) -> None:
+        if self.handle is not None and self.handle.value:
+            vl_model_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, sizes: Sequence[Tuple[int, int]]) -> int:
+        return vl_encode_workspace_bytes(self.handle, [h for h, _ in sizes], [w for _, w in sizes])
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def encode(self, pixels: torch.Tensor, sizes: Sequence[Tuple[int, int]],
+               out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """pixels: flat FP32 device tensor holding the [3,H,W] images back to
+        back; sizes: their (H, W).  Returns [n, proj_dim] unit embeddings."""
+        n = len(sizes)
+        if out is None:
+            out = torch.empty((n, self.cfg.proj_dim), dtype=torch.float32, device=self.device)
+        need = self.workspace_bytes(sizes)
+        if need == 0:
+            raise VlError(1, "invalid batch shapes")
+        ws = self.workspace(need)
+        vl_encode_images(self.handle, pixels, [h for h, _ in sizes], [w for _, w in sizes], out,
+                         ws, stream)
+        return out

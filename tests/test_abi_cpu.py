@@ -1,0 +1,73 @@
+"""The C-ABI library loads without a GPU, exports every symbol declared in
+include/vl.h, and rejects invalid arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "vl.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(vl_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def V():
+    from paper_2505_00690_amd import vl
+    vl.lib()
+    return vl
+
+
+def test_every_declared_symbol_is_exported(V):
+    declared = _declared_functions()
+    assert len(declared) >= 10
+    lib = V.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(V.EXPORTED_SYMBOLS)
+
+
+def test_abi_version_and_status_strings(V):
+    assert V.vl_abi_version() == 1
+    assert V.vl_status_string(0) == "ok"
+    assert V.vl_status_string(3) == "workspace too small"
+
+
+def test_weights_count_matches_blob_layout(V):
+    for c in synth.MODELS.values():
+        assert V.vl_weights_count(c) == synth.weight_count(c)
+    bad = synth.ModelConfig("bad", 16, 100, 1, 3, 512, 128, 4)   # width % heads != 0
+    assert V.vl_weights_count(bad) == 0
+
+
+def test_invalid_arguments_rejected_on_host(V):
+    lib = V.lib()
+    cfg = V.VlConfig.from_model(synth.MODELS["tiny"])
+    h = ctypes.c_void_p()
+    st = lib.vl_model_create(ctypes.byref(cfg), 1, None, 0, None, ctypes.byref(h))
+    assert st == 1 and "NULL" in V.vl_last_error_message()
+    st = lib.vl_model_create(ctypes.byref(cfg), 7, ctypes.c_void_p(256), 0, None, ctypes.byref(h))
+    assert st == 1
+    st = lib.vl_model_create(ctypes.byref(cfg), 1, ctypes.c_void_p(256), 5, None, ctypes.byref(h))
+    assert st == 1 and "expected" in V.vl_last_error_message()
+    # head_dim 128 is not supported
+    c2 = V.VlConfig.from_model(synth.ModelConfig("x", 16, 256, 1, 2, 512, 128, 4))
+    n = lib.vl_weights_count(ctypes.byref(c2))
+    st = lib.vl_model_create(ctypes.byref(c2), 1, ctypes.c_void_p(256), n, None, ctypes.byref(h))
+    assert st == 2
+    # scoring argument checks happen before any launch
+    p = ctypes.c_void_p(256)
+    assert lib.vl_score(p, 4, p, 10, 128, 0, 1.0, 0.0, p, None, None) == 1   # n_texts % 4
+    assert lib.vl_score(p, 4, p, 16, 100, 0, 1.0, 0.0, p, None, None) == 1   # dim % 16
+    assert lib.vl_score(p, 0, p, 16, 128, 0, 1.0, 0.0, p, None, None) == 1
+    assert lib.vl_score(p, 4, p, 16, 128, 5, 1.0, 0.0, p, None, None) == 1   # head
+    assert lib.vl_score(None, 4, p, 16, 128, 0, 1.0, 0.0, p, None, None) == 1
+    assert lib.vl_encode_images(None, p, None, None, 1, p, p, 0, None) == 1
+    assert lib.vl_encode_workspace_bytes(None, 1, None, None) == 0

@@ -1,0 +1,222 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.
+
+Bars: FP32 relative embedding error <= 1e-4 (max over images); BF16 and
+FP8-weight cosine >= 0.999 against the oracle run on the exact weights the
+GPU uses; scoring within the bound implied by the embedding error; top-1
+equal wherever the reference margin certifies it; batch invariance bitwise.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import vit64 as O
+
+from helpers import blob, certified_top1, cosine, pack, params, rel_err, sizes_of
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-4
+COS_TOL = 0.999
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def V():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_00690_amd import vl
+    vl.lib()
+    return vl
+
+
+_ENC = {}
+
+
+def encoder(V, model, seed, precision, graphs=False):
+    key = (model, seed, precision, graphs)
+    if key not in _ENC:
+        w = torch.from_numpy(blob(model, seed)).cuda()
+        _ENC[key] = V.Encoder(synth.MODELS[model], w, precision, graphs=graphs)
+        torch.cuda.synchronize()
+        del w
+    return _ENC[key]
+
+
+def run(enc, images):
+    pix = torch.from_numpy(pack(images)).cuda()
+    out = enc.encode(pix, sizes_of(images))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def oracle_emb(model, seed, precision, images):
+    p = O.weights_for(params(model, seed), precision)
+    return O.encode(images, p, synth.MODELS[model])
+
+
+# ------------------------------------------------------------------ tiny
+@pytest.mark.parametrize("layers", [0, 1, 4])
+def test_tiny_fp32_layers(V, layers):
+    """FP32 path of the tiny model with 0, 1 and 4 blocks (isolates the
+    patch embedding, one block, the full stack)."""
+    base = synth.MODELS["tiny"]
+    cfg = synth.ModelConfig("tiny_l%d" % layers, base.patch, base.width, layers, base.heads,
+                            base.mlp, base.proj_dim, base.base_grid)
+    b = synth.make_blob(cfg, 1000)
+    imgs = synth.make_images([(64, 64)] * 8, 2000)
+    _say(f"tiny fp32 layers={layers}")
+    enc = V.Encoder(cfg, torch.from_numpy(b).cuda(), "fp32")
+    got = run(enc, imgs)
+    ref = O.encode(imgs, synth.blob_to_params(cfg, b), cfg)
+    err = rel_err(got, ref)
+    _say(f"  max rel err {err.max():.3e}")
+    assert err.max() <= FP32_TOL
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp8w"])
+def test_tiny_reduced_precision(V, precision):
+    imgs = synth.make_images([(64, 64)] * 8, 2000)
+    _say(f"tiny {precision}")
+    got = run(encoder(V, "tiny", 1000, precision), imgs)
+    ref = oracle_emb("tiny", 1000, precision, imgs)
+    cos = cosine(got, ref)
+    _say(f"  min cos {cos.min():.6f}")
+    assert cos.min() >= COS_TOL
+    # non-vacuity: different images are far apart at this tolerance
+    r = ref @ ref.T
+    assert r[~np.eye(len(r), dtype=bool)].max() < 0.99
+
+
+def test_tiny_ragged_sizes_and_single_patch(V):
+    """Sides that are not patch multiples (extra pixels dropped), a one-patch
+    image (2 tokens), and a mixed batch of them, FP32."""
+    sizes = [(70, 50), (16, 16), (64, 64), (33, 95), (16, 200)]
+    imgs = synth.make_images(sizes, 2100)
+    got = run(encoder(V, "tiny", 1000, "fp32"), imgs)
+    ref = oracle_emb("tiny", 1000, "fp32", imgs)
+    assert rel_err(got, ref).max() <= FP32_TOL
+
+
+def test_tiny_max_tokens(V):
+    """1024 patches + class token (the maximum) through the BF16 attention."""
+    imgs = synth.make_images([(512, 512), (64, 64)], 2200)
+    got = run(encoder(V, "tiny", 1000, "bf16"), imgs)
+    ref = oracle_emb("tiny", 1000, "bf16", imgs)
+    assert cosine(got, ref).min() >= COS_TOL
+    got32 = run(encoder(V, "tiny", 1000, "fp32"), imgs)
+    assert rel_err(got32, oracle_emb("tiny", 1000, "fp32", imgs)).max() <= FP32_TOL
+
+
+def test_batch_invariance_bitwise(V):
+    """Each image's embedding is the same alone and inside a packed batch."""
+    sizes = [(64, 64), (48, 80), (128, 96), (64, 64), (16, 32)]
+    imgs = synth.make_images(sizes, 2300)
+    for prec in ("fp32", "bf16"):
+        enc = encoder(V, "tiny", 1000, prec)
+        full = run(enc, imgs)
+        for i in (0, 2, 4):
+            alone = run(enc, [imgs[i]])
+            assert np.array_equal(alone[0], full[i]), (prec, i)
+
+
+def test_graph_replay_matches_eager(V):
+    imgs = synth.make_images([(64, 64)] * 8, 2000)
+    eager = run(encoder(V, "tiny", 1000, "bf16"), imgs)
+    genc = encoder(V, "tiny", 1000, "bf16", graphs=True)
+    pix = torch.from_numpy(pack(imgs)).cuda()
+    out = torch.empty((8, 128), device="cuda")
+    for _ in range(3):
+        out.zero_()
+        genc.encode(pix, sizes_of(imgs), out=out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager)
+
+
+# --------------------------------------------------------------- scoring
+@pytest.mark.parametrize("head,scale,bias,m", [("softmax", 100.0, 0.0, 16),
+                                               ("softmax", 100.0, 0.0, 1000),
+                                               ("sigmoid", 10.0, -10.0, 4096)])
+def test_score_heads(V, head, scale, bias, m):
+    rng = np.random.Generator(np.random.PCG64(7))
+    e = rng.standard_normal((37, 128))
+    e = (e / np.linalg.norm(e, axis=1, keepdims=True)).astype(np.float32)
+    t = synth.make_texts(m, 128, 3000)
+    t[5] = e[3]                       # an exact match: logit = scale
+    ed, td = torch.from_numpy(e).cuda(), torch.from_numpy(t).cuda()
+    sc = torch.empty((37, m), device="cuda")
+    top = torch.empty(37, dtype=torch.int32, device="cuda")
+    V.vl_score(ed, td, head, scale, bias, sc, top)
+    torch.cuda.synchronize()
+    p_ref, top_ref = O.score(e, t, head, scale, bias)
+    got = sc.cpu().numpy()
+    if head == "softmax":
+        # |d log p| <= 2 * |d logit|; FP32 logits of unit vectors: ~1e-6 * scale
+        assert np.max(np.abs(np.log(got) - np.log(p_ref))) <= 2e-5 * scale
+        assert np.max(np.abs(got.sum(1) - 1)) <= 1e-5
+    else:
+        assert np.max(np.abs(got - p_ref)) <= 1e-6 * scale
+    l = O.logits(e, t, scale, bias)
+    srt = np.sort(l, axis=1)
+    sure = (srt[:, -1] - srt[:, -2]) > 1e-5 * scale
+    gtop = top.cpu().numpy()
+    assert np.array_equal(gtop[sure], top_ref[sure])
+    # where the top two are within rounding, the GPU's pick is one of them
+    for i in np.where(~sure)[0]:
+        assert l[i, gtop[i]] >= srt[i, -1] - 1e-5 * scale
+    assert gtop[3] == 5
+
+
+# ------------------------------------------------- full-size configurations
+def _full(V, model, prec, res, n, img_seed, sample, w_seed):
+    sizes = [(r, r) for r in res] if isinstance(res, list) else [(res, res)] * n
+    imgs = synth.make_images(sizes, img_seed)
+    _say(f"{model} {prec} n={len(imgs)} sample={sample}")
+    got = run(encoder(V, model, w_seed, prec), imgs)
+    ref = oracle_emb(model, w_seed, prec, [imgs[i] for i in sample])
+    return got, ref, imgs
+
+
+def test_b16_224_fp32_sampled(V):
+    got, ref, _ = _full(V, "b16", "fp32", 224, 64, 2001, [0, 37, 63], 1001)
+    err = rel_err(got[[0, 37, 63]], ref)
+    _say(f"  b16 fp32 rel err {err.max():.3e}")
+    assert err.max() <= FP32_TOL
+
+
+def test_b16_224_bf16_sampled(V):
+    got, ref, _ = _full(V, "b16", "bf16", 224, 64, 2001, [0, 37, 63], 1001)
+    cos = cosine(got[[0, 37, 63]], ref)
+    _say(f"  b16 bf16 min cos {cos.min():.6f}")
+    assert cos.min() >= COS_TOL
+    assert np.allclose(np.linalg.norm(got, axis=1), 1.0, atol=1e-5)
+
+
+def test_l14_336_bf16_sampled(V):
+    got, ref, _ = _full(V, "l14", "bf16", 336, 32, 2002, [0, 31], 1002)
+    cos = cosine(got[[0, 31]], ref)
+    _say(f"  l14 bf16 min cos {cos.min():.6f}")
+    assert cos.min() >= COS_TOL
+
+
+def test_b16_mixed_resolution_bf16_sampled(V):
+    res = synth.draw_resolutions(96, (224, 336, 448), 4003)
+    sample = [res.index(224), res.index(336), res.index(448)]
+    got, ref, _ = _full(V, "b16", "bf16", res, 96, 2003, sample, 1003)
+    cos = cosine(got[sample], ref)
+    _say(f"  b16 mixed bf16 min cos {cos.min():.6f}")
+    assert cos.min() >= COS_TOL
+
+
+def test_l14_fp8w_sampled(V):
+    got, ref, _ = _full(V, "l14", "fp8w", [224, 384], 2, 2004, [0, 1], 1004)
+    cos = cosine(got, ref)
+    _say(f"  l14 fp8w min cos {cos.min():.6f}")
+    assert cos.min() >= COS_TOL
