@@ -92,6 +92,7 @@ struct vl_model {
   std::vector<hipEvent_t> free_events;
   double op_ms[VL_N_OPS] = {};
   int64_t op_launches[VL_N_OPS] = {};
+  hipStream_t capture = nullptr;  // private stream graphs are captured on
 };
 
 namespace {
@@ -518,6 +519,7 @@ void vl_model_destroy(vl_model* m) {
     if (r.host) (void)hipHostFree(r.host);
     if (r.ev) (void)hipEventDestroy(r.ev);
   }
+  if (m->capture) (void)hipStreamDestroy(m->capture);
   if (m->wmem) (void)hipFree(m->wmem);
   delete m;
 }
@@ -602,19 +604,24 @@ vl_status vl_encode_images(vl_model* m, const float* pix, const int32_t* hs, con
       (void)hipDeviceSynchronize();
       destroy_graphs(m);
     }
+    // Capture on the model's private stream (the caller's stream may be the
+    // null stream, which cannot be captured); the graph is replayed on the
+    // caller's stream.  Capture records work without running it.
+    if (!m->capture) VL_HIP(hipStreamCreateWithFlags(&m->capture, hipStreamNonBlocking));
+    hipStream_t cs = m->capture;
     GraphEntry ge;
     VL_HIP(hipHostMalloc(&ge.host, std::max<size_t>(p.desc_bytes, 256), hipHostMallocDefault));
     std::memcpy(ge.host, p.imgs.data(), sizeof(ImgDesc) * p.n);
     std::memcpy(static_cast<char*>(ge.host) + sizeof(ImgDesc) * p.n, p.items.data(),
                 sizeof(AttnItem) * p.items.size());
     hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) { (void)hipHostFree(ge.host); return hip_fail(e, "hipStreamBeginCapture"); }
     vl_status st = VL_OK;
-    e = hipMemcpyAsync(w, ge.host, p.desc_bytes, hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(w, ge.host, p.desc_bytes, hipMemcpyHostToDevice, cs);
     if (e != hipSuccess) st = hip_fail(e, "hipMemcpyAsync(descriptors)");
-    if (st == VL_OK) st = run_encoder(m, p, pix, emb, w, s);
-    e = hipStreamEndCapture(s, &g);
+    if (st == VL_OK) st = run_encoder(m, p, pix, emb, w, cs);
+    e = hipStreamEndCapture(cs, &g);
     if (st == VL_OK && e != hipSuccess) st = hip_fail(e, "hipStreamEndCapture");
     if (st == VL_OK) {
       e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
