@@ -103,6 +103,64 @@ def cpu_baseline(wl: synth.Workload, blob: np.ndarray, images, texts, n_sample: 
                       f"{wl.head} scoring vs {len(texts)} texts; {dt:.1f} s"}
 
 
+def serving_leg(torch, vl, n_requests: int, warmup_requests: int, slots: int,
+                budget_gib: float, max_batch_images: int):
+    """The serving workload: ViT-L/14 with e4m3 per-row weights and BF16
+    activations, 8192 resident texts, Poisson requests of 1-16 images at one
+    of {224, 336, 384, 448} each.  Closed-loop capacity first (every request
+    queued at t=0), then open-loop Poisson arrivals at 0.5x and 0.8x of that
+    capacity; nearest-rank p50/p99 of arrival-to-completion latency."""
+    from paper_2505_00690_amd.serve import GpuExecutor, RealClock, Request, Scheduler
+    wl = synth.WORKLOADS["l14_serve"]
+    c = synth.MODELS[wl.model]
+    seeds = synth.seeds_for(wl)
+    w = torch.from_numpy(synth.make_blob(c, seeds["weights"])).cuda()
+    enc = vl.Encoder(c, w, wl.precision)
+    del w
+    texts = torch.from_numpy(synth.make_texts(wl.n_texts, c.proj_dim, seeds["texts"])).cuda()
+    # A pool of 32 distinct images per resolution; requests draw from it.
+    pool = {r: [torch.from_numpy(im.reshape(-1)).cuda()
+                for im in synth.make_images([(r, r)] * 32, seeds["images"] + r)]
+            for r in wl.resolutions}
+    ex = GpuExecutor(enc, texts, wl.head, wl.scale, wl.bias, slots)
+    budget = int(budget_gib * 2 ** 30)
+    sched = Scheduler(ex, budget, slots=slots, max_batch_images=max_batch_images)
+
+    def make(n, qps, seed):
+        out = []
+        for i, r in enumerate(synth.draw_requests(n, qps, wl.resolutions, seed)):
+            res = r.sizes[0][0]
+            out.append(Request(i, r.arrival_s, r.sizes,
+                               [pool[res][(i * 7 + k) % 32] for k in range(len(r.sizes))]))
+        return out
+
+    def run(reqs):
+        st = sched.run(reqs, RealClock())
+        torch.cuda.synchronize()
+        keep = [x for x in st.results if x.rid >= warmup_requests]
+        lat = sorted(x.latency for x in keep)
+        imgs = sum(x.n_images for x in st.results)
+        from paper_2505_00690_amd.serve import percentile
+        return {"images_per_s": imgs / st.wall, "requests_per_s": len(st.results) / st.wall,
+                "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
+                "batches": st.batches, "max_inflight": st.max_inflight,
+                "peak_workspace_gib": st.peak_budget / 2 ** 30, "requests": len(st.results)}
+
+    run(make(64, 1e9, seeds["arrivals"] + 99))   # warm-up (plans, allocator)
+    cap = run(make(max(200, n_requests // 3), 1e9, seeds["arrivals"]))
+    out = {"workload": "l14_serve", "precision": wl.precision, "slots": slots,
+           "budget_gib": budget_gib, "max_batch_images": max_batch_images,
+           "capacity": cap, "open_loop": []}
+    for frac in (0.5, 0.8):
+        qps = frac * cap["requests_per_s"]
+        r = run(make(n_requests, qps, seeds["arrivals"] + int(frac * 10)))
+        r["qps"] = qps
+        r["load"] = frac
+        out["open_loop"].append(r)
+    enc.close()
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +174,11 @@ def main(argv=None) -> int:
     ap.add_argument("--cpu-sample", type=int, default=None, help="images for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-steps", type=int, default=3)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving (p50/p99) leg")
+    ap.add_argument("--serve-requests", type=int, default=1200)
+    ap.add_argument("--serve-slots", type=int, default=2)
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0)
+    ap.add_argument("--serve-max-batch", type=int, default=64)
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -231,6 +294,11 @@ def main(argv=None) -> int:
                                "ms_per_step": ms32, "steps": args.fp32_steps,
                                "speedup_of_value": ms32 / ms}
         del enc32
+
+    if not args.no_serve:
+        result["serving"] = serving_leg(torch, vl, args.serve_requests, 100, args.serve_slots,
+                                        args.serve_budget_gib, args.serve_max_batch)
+        print(f"# serving: {json.dumps(result['serving'])}", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         k = args.cpu_sample or {"tiny_fp32": 8, "b16_224": 8, "l14_336": 4, "b16_mixed": 6}[

@@ -128,7 +128,7 @@ struct Plan {
   std::vector<ImgDesc> imgs;
   std::vector<AttnItem> items;
   size_t desc_bytes = 0;   // imgs + items
-  size_t off_tok = 0, off_X = 0, off_Y = 0, off_QH = 0, total = 0;
+  size_t off_tok = 0, off_X = 0, off_Y = 0, off_QH = 0, off_E = 0, total = 0;
 };
 
 bool make_plan(const vl_model* m, int32_t n, const int32_t* hs, const int32_t* ws, Plan* p,
@@ -173,6 +173,8 @@ bool make_plan(const vl_model* m, int32_t n, const int32_t* hs, const int32_t* w
   p->off_QH = off;
   const size_t qh_cols = std::max<size_t>({(size_t)3 * m->D, (size_t)m->F, (size_t)m->Kpad});
   off += align_up(es * T * qh_cols);
+  p->off_E = off;
+  off += align_up(4ull * n * m->Pd);
   p->total = off;
   return true;
 }
@@ -312,7 +314,8 @@ vl_status run_encoder(vl_model* m, const Plan& p, const float* pix, float* emb, 
     }
   }
   VL_TIMED(T_POOL, VL_HIP(pool_project(X, d_imgs, p.n, m->lnf_g, m->lnf_b, eps, m->proj, D,
-                                        m->Pd, emb, s)));
+                                        m->Pd, reinterpret_cast<float*>(ws + p.off_E), emb,
+                                        s)));
   return VL_OK;
 }
 

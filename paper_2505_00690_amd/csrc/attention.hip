@@ -29,8 +29,11 @@ __device__ __forceinline__ int k_off(int key, int chunk) {  // sK[key][HD], 16-B
   constexpr int NC = HD / 8;
   return key * HD + ((chunk ^ (key & (NC - 1))) << 3);
 }
-__device__ __forceinline__ int vt_off(int d, int key) {  // sVt[d][64 keys]
-  return d * ATT_KV + ((((key >> 3) ^ (d & 7))) << 3) + (key & 7);
+// sVt[d][64 keys]: 16-B chunks of a row swizzled by (d ^ (d >> 3)) & 7, so
+// both the transposing stores (8 rows d = 8c + e at one key) and the
+// fragment reads (32 consecutive rows d at one key chunk) spread over banks.
+__device__ __forceinline__ int vt_off(int d, int key) {
+  return d * ATT_KV + ((((key >> 3) ^ ((d ^ (d >> 3)) & 7))) << 3) + (key & 7);
 }
 
 template <int HD>
@@ -39,9 +42,10 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
                                                    const ImgDesc* __restrict__ imgs,
                                                    const AttnItem* __restrict__ items,
                                                    int heads) {
-  constexpr int NCH = HD / 8;           // 16-B chunks per row of one head
-  constexpr int LOADS = ATT_KV * NCH / 256;  // chunks per thread per tensor
-  static_assert(LOADS >= 1, "tile / threads");
+  constexpr int NCH = HD / 8;                  // 16-B chunks per row of one head
+  constexpr int KLOADS = ATT_KV * NCH / 256;   // K chunks per thread
+  constexpr int VTHREADS = 32 * NCH;           // threads staging V: key pair x chunk
+  static_assert(KLOADS >= 1 && VTHREADS <= 256, "tile / threads");
   __shared__ __attribute__((aligned(16))) bf16_t sK[2][ATT_KV * HD];
   __shared__ __attribute__((aligned(16))) bf16_t sVt[2][HD * ATT_KV];
 
@@ -69,35 +73,46 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
   for (int c = 0; c < HD / 16; ++c)
     qf[c] = *reinterpret_cast<const bf16x8*>(Qp + (size_t)qc * ld + 16 * c + 8 * g);
 
-  // Loader: per tensor, chunk id = tid + i*256 -> key = id / NCH, ch = id % NCH.
-  u32x4 rk[LOADS], rv[LOADS];
+  // Staging: K chunk id = tid + i*256 -> key id / NCH, chunk id % NCH.
+  // V: thread (key pair vp = tid / NCH, chunk vc = tid % NCH) loads rows
+  // 2vp and 2vp+1 (coalesced: NCH consecutive lanes cover a row) and stores
+  // them transposed as 32-bit key pairs.
+  const int vp = tid / NCH, vc = tid % NCH;
+  u32x4 rk[KLOADS], rv0, rv1;
   auto load_kv = [&](int kbase) {
 #pragma unroll
-    for (int i = 0; i < LOADS; ++i) {
+    for (int i = 0; i < KLOADS; ++i) {
       const int id = tid + i * 256;
       const int key = min(kbase + id / NCH, N - 1);
-      const int ch = id % NCH;
-      rk[i] = *reinterpret_cast<const u32x4*>(Kp + (size_t)key * ld + ch * 8);
-      rv[i] = *reinterpret_cast<const u32x4*>(Vp + (size_t)key * ld + ch * 8);
+      rk[i] = *reinterpret_cast<const u32x4*>(Kp + (size_t)key * ld + (id % NCH) * 8);
+    }
+    if (tid < VTHREADS) {
+      const int k0 = min(kbase + 2 * vp, N - 1), k1 = min(kbase + 2 * vp + 1, N - 1);
+      rv0 = *reinterpret_cast<const u32x4*>(Vp + (size_t)k0 * ld + vc * 8);
+      rv1 = *reinterpret_cast<const u32x4*>(Vp + (size_t)k1 * ld + vc * 8);
     }
   };
   auto store_kv = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < LOADS; ++i) {
+    for (int i = 0; i < KLOADS; ++i) {
       const int id = tid + i * 256;
-      const int key = id / NCH, ch = id % NCH;
-      *reinterpret_cast<u32x4*>(&sK[buf][k_off<HD>(key, ch)]) = rk[i];
+      *reinterpret_cast<u32x4*>(&sK[buf][k_off<HD>(id / NCH, id % NCH)]) = rk[i];
+    }
+    if (tid < VTHREADS) {
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
-        const uint32_t x = rv[i][w];
-        sVt[buf][vt_off(ch * 8 + 2 * w, key)] = (bf16_t)(x & 0xFFFF);
-        sVt[buf][vt_off(ch * 8 + 2 * w + 1, key)] = (bf16_t)(x >> 16);
+        const uint32_t a = rv0[w], b = rv1[w];
+        // element 2w (low halves) and 2w+1 (high halves) of the chunk
+        *reinterpret_cast<uint32_t*>(&sVt[buf][vt_off(vc * 8 + 2 * w, 2 * vp)]) =
+            (a & 0xFFFFu) | (b << 16);
+        *reinterpret_cast<uint32_t*>(&sVt[buf][vt_off(vc * 8 + 2 * w + 1, 2 * vp)]) =
+            (a >> 16) | (b & 0xFFFF0000u);
       }
     }
   };
 
   const float sl2 = 1.4426950408889634f / sqrtf((float)HD);  // log2(e)/sqrt(d)
-  float m_run = -INFINITY, l_run = 0.f;
+  float m_run = -INFINITY, l_run = 0.f;   // running max (log2 units) and sum
   f32x16 o[HD / 32];
 #pragma unroll
   for (int a = 0; a < HD / 32; ++a)
@@ -126,58 +141,60 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
           s[kb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kf, qf[c], s[kb], 0, 0, 0);
         }
       }
-      // Scale, mask keys past the image, tile max.
       const int kbase = kt * ATT_KV;
-      float mt = -INFINITY;
+      if (kbase + ATT_KV > N) {            // keys past the image: excluded
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            if (kbase + kb * 32 + 8 * (r >> 2) + 4 * g + (r & 3) >= N) s[kb][r] = -INFINITY;
+      }
+      float mt = s[0][0];
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int key = kbase + kb * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
-          const float v = key < N ? s[kb][r] * sl2 : -INFINITY;
-          s[kb][r] = v;
-          mt = fmaxf(mt, v);
-        }
+        for (int r = 0; r < 16; ++r) mt = fmaxf(mt, s[kb][r]);
       mt = fmaxf(mt, __shfl_xor(mt, 32, 64));
-      const float m_new = fmaxf(m_run, mt);
-      const float alpha = exp2f(m_run - m_new);
+      const float m_new = fmaxf(m_run, mt * sl2);
+      const float nm = -m_new;
+      if (__any(m_new != m_run)) {         // rescale only when some max moved
+        const float alpha = __builtin_amdgcn_exp2f(m_run - m_new);
+        l_run *= alpha;
+#pragma unroll
+        for (int a = 0; a < HD / 32; ++a)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) o[a][r] *= alpha;
+      }
       m_run = m_new;
       float ls = 0.f;
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const float p = exp2f(s[kb][r] - m_new);
+          const float p = __builtin_amdgcn_exp2f(fmaf(s[kb][r], sl2, nm));
           s[kb][r] = p;
           ls += p;
         }
-      l_run = l_run * alpha + ls;
-#pragma unroll
-      for (int a = 0; a < HD / 32; ++a)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) o[a][r] *= alpha;
+      l_run += ls;
       // O^T += V^T P^T over four 16-key chunks j; chunk j = 2kb + hh uses
       // s[kb][8hh .. 8hh+7]: keys 16j + 8(e/4) + 4g + e%4 for element e.
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int kb = j >> 1, hh = j & 1;
-        bf16x8 pf;
-        {
-          u32x4 pk;
+        u32x4 pk;
 #pragma unroll
-          for (int w = 0; w < 4; ++w)
-            pk[w] = pack_bf16x2(s[kb][8 * hh + 2 * w], s[kb][8 * hh + 2 * w + 1]);
-          pf = *reinterpret_cast<bf16x8*>(&pk);
-        }
+        for (int w = 0; w < 4; ++w)
+          pk[w] = pack_bf16x2(s[kb][8 * hh + 2 * w], s[kb][8 * hh + 2 * w + 1]);
+        const bf16x8 pf = __builtin_bit_cast(bf16x8, pk);
 #pragma unroll
         for (int a = 0; a < HD / 32; ++a) {
           const int d = a * 32 + l32;
-          u32x4 vk;
           const u32x2 v0 = *reinterpret_cast<const u32x2*>(&tV[vt_off(d, 16 * j + 4 * g)]);
           const u32x2 v1 = *reinterpret_cast<const u32x2*>(&tV[vt_off(d, 16 * j + 8 + 4 * g)]);
+          u32x4 vk;
           vk[0] = v0.x; vk[1] = v0.y; vk[2] = v1.x; vk[3] = v1.y;
-          const bf16x8 vf = *reinterpret_cast<bf16x8*>(&vk);
-          o[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vf, pf, o[a], 0, 0, 0);
+          o[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, vk), pf, o[a],
+                                                         0, 0, 0);
         }
       }
     }

@@ -133,20 +133,21 @@ __device__ __forceinline__ float block_reduce(float v, float* red, Op op) {
 }
 
 // ----------------------------------------------------- pool + LN + proj + L2
-// Class-token pooling, final LayerNorm (ViT Eq. 4), bias-free projection and
-// division by the L2 norm (clamped at 1e-12), all FP32.  One workgroup per
-// image.
+// Class-token pooling, final LayerNorm (ViT Eq. 4) and bias-free projection,
+// FP32.  Grid (image, chunk of 64 projection outputs): each workgroup
+// normalises its image's class-token row in LDS (cheap, D <= 1024) and
+// produces 64 outputs, one dot product of length D per output, 16 per wave.
 __global__ __launch_bounds__(256) void k_pool_project(const float* __restrict__ x,
                                                       const ImgDesc* __restrict__ imgs,
                                                       const float* __restrict__ gm,
                                                       const float* __restrict__ bt, float eps,
                                                       const float* __restrict__ proj, int D,
-                                                      int P, float* __restrict__ emb) {
+                                                      int P, float* __restrict__ e_out) {
   __shared__ float z[1024];
-  __shared__ float e[1024];
   __shared__ float red[4];
   const int tid = threadIdx.x;
-  const ImgDesc d = imgs[blockIdx.x];
+  const int img = blockIdx.x;
+  const ImgDesc d = imgs[img];
   const float* xr = x + (size_t)d.tok_start * D;
   float s = 0.f;
   for (int c = tid; c < D; c += 256) {
@@ -163,27 +164,41 @@ __global__ __launch_bounds__(256) void k_pool_project(const float* __restrict__ 
   for (int c = tid; c < D; c += 256) z[c] = (z[c] - mean) * rstd * gm[c] + bt[c];
   __syncthreads();
   const int lane = tid & 63, w = tid >> 6;
-  for (int p = w; p < P; p += 4) {
+  const int p0 = blockIdx.y * 64 + w * 16;
+  for (int i = 0; i < 16; ++i) {
+    const int p = p0 + i;
+    if (p >= P) break;
     const float* wr = proj + (size_t)p * D;
     float a = 0.f;
     for (int c = lane; c < D; c += 64) a = fmaf(wr[c], z[c], a);
     a = wave_sum(a);
-    if (lane == 0) e[p] = a;
+    if (lane == 0) e_out[(size_t)img * P + p] = a;
   }
-  __syncthreads();
+}
+
+// Row-wise division by the L2 norm (clamped at 1e-12).  One wave per row.
+__global__ __launch_bounds__(256) void k_l2_normalise(const float* __restrict__ e,
+                                                      float* __restrict__ out, int rows, int P) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= rows) return;
+  const float* er = e + (size_t)row * P;
   float n2 = 0.f;
-  for (int p = tid; p < P; p += 256) n2 += e[p] * e[p];
-  const float nrm = sqrtf(block_reduce(n2, red, [](float a, float b) { return a + b; }));
-  const float inv = 1.f / fmaxf(nrm, 1e-12f);
-  for (int p = tid; p < P; p += 256) emb[(size_t)blockIdx.x * P + p] = e[p] * inv;
+  for (int c = lane; c < P; c += 64) n2 += er[c] * er[c];
+  const float inv = 1.f / fmaxf(sqrtf(wave_sum(n2)), 1e-12f);
+  for (int c = lane; c < P; c += 64) out[(size_t)row * P + c] = er[c] * inv;
 }
 
 hipError_t pool_project(const float* x, const ImgDesc* imgs, int n_imgs, const float* g,
-                        const float* b, float eps, const float* proj, int D, int P, float* emb,
-                        hipStream_t s) {
+                        const float* b, float eps, const float* proj, int D, int P,
+                        float* e_tmp, float* emb, hipStream_t s) {
   if (n_imgs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pool_project, dim3(n_imgs), dim3(256), 0, s, x, imgs, g, b, eps, proj, D,
-                     P, emb);
+  hipLaunchKernelGGL(k_pool_project, dim3(n_imgs, (P + 63) / 64), dim3(256), 0, s, x, imgs, g,
+                     b, eps, proj, D, P, e_tmp);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_l2_normalise, dim3((n_imgs + 3) / 4), dim3(256), 0, s, e_tmp, emb, n_imgs,
+                     P);
   return hipGetLastError();
 }
 

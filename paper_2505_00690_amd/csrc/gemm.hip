@@ -244,6 +244,196 @@ __global__ __launch_bounds__(WGM* WGN * 64) void k_gemm_bf16(
   }
 }
 
+// ------------------------------------------- BF16 MFMA GEMM, direct-to-LDS
+// Same contraction and epilogues, for BF16 weights.  Tiles are fetched with
+// buffer_load ... lds (16 bytes per lane straight into LDS, no staging
+// registers): one wave instruction fills 8 tile rows (1 KB), lane l taking
+// row l/8 and physical chunk l%8, i.e. logical chunk (l%8) ^ (l/8) under the
+// row-XOR swizzle.  Buffer resources are bounded by the matrix end, so rows
+// past M / N read as zero.  Output tiles are assigned XCD by XCD: workgroup
+// ids are dealt round-robin to the 8 XCDs, so a contiguous range of tiles is
+// given to each XCD and walked in groups of GROUP_M row tiles, letting the
+// tiles resident on one XCD share A rows and B rows in its L2.
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+extern "C" __device__ void llvm_amdgcn_raw_buffer_load_lds(
+    i32x4 rsrc, __attribute__((address_space(3))) uint32_t* lds, int size, int voffset,
+    int soffset, int offset, int aux) __asm("llvm.amdgcn.raw.buffer.load.lds");
+
+__device__ __forceinline__ i32x4 buffer_rsrc(const void* base, uint64_t bytes) {
+  const uint64_t p = reinterpret_cast<uint64_t>(base);
+  i32x4 r;
+  r[0] = (int32_t)(uint32_t)(p & 0xffffffffu);
+  r[1] = (int32_t)(uint32_t)(p >> 32);        // stride 0
+  r[2] = (int32_t)(uint32_t)(bytes > 0xffffffffull ? 0xffffffffull : bytes);
+  r[3] = 0x00020000;
+  r[0] = __builtin_amdgcn_readfirstlane(r[0]);
+  r[1] = __builtin_amdgcn_readfirstlane(r[1]);
+  r[2] = __builtin_amdgcn_readfirstlane(r[2]);
+  return r;
+}
+
+__device__ __forceinline__ void xcd_tile(int gm, int gn, int group_m, int* tm, int* tn) {
+  const int total = gm * gn;
+  const int bid = blockIdx.x;
+  const int xcd = bid & 7, local = bid >> 3;
+  const int q = total >> 3, r = total & 7;
+  const int id = xcd * q + min(xcd, r) + local;
+  const int per_group = group_m * gn;
+  const int g = id / per_group;
+  const int first = g * group_m;
+  const int gsz = min(gm - first, group_m);
+  const int w = id - g * per_group;
+  *tm = first + w % gsz;
+  *tn = w / gsz;
+}
+
+template <int BM, int BN, int WGM, int WGN, int OP>
+__global__ __launch_bounds__(WGM* WGN * 64)
+__attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_bf16_dl(
+    const bf16_t* __restrict__ A, int lda, const bf16_t* __restrict__ B, int ldb, int M, int N,
+    int K, int gm, int gn, EpiArgs e) {
+  constexpr int EPI = OpEpi<OP>::kind;
+  constexpr bool OUT_BF16 = OP == OP_QKV || OP == OP_FC1;
+  constexpr int NW = WGM * WGN;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int TM = WM / 32, TN = WN / 32;
+  constexpr int IA = BM / 8 / NW, IB = BN / 8 / NW;  // load instructions per wave per tile
+  static_assert(IA * NW * 8 == BM && IB * NW * 8 == BN, "tile rows / waves");
+
+  __shared__ __attribute__((aligned(1024))) bf16_t sA[2][BM * BK];
+  __shared__ __attribute__((aligned(1024))) bf16_t sB[2][BN * BK];
+
+  int tm_, tn_;
+  xcd_tile(gm, gn, 8, &tm_, &tn_);
+  const int m0 = tm_ * BM, n0 = tn_ * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+
+  const i32x4 ra = buffer_rsrc(A + (size_t)m0 * lda, (uint64_t)(M - m0) * lda * 2);
+  const i32x4 rb = buffer_rsrc(B + (size_t)n0 * ldb, (uint64_t)(N - n0) * ldb * 2);
+  // Lane's byte offset inside an 8-row group: row l/8, logical chunk (l%8)^(l/8).
+  const int lrow = lane >> 3, lchunk = (lane & 7) ^ (lane >> 3);
+  const int a_off = lrow * lda * 2 + lchunk * 16;
+  const int b_off = lrow * ldb * 2 + lchunk * 16;
+
+  auto issue = [&](int buf, int k0) {
+#pragma unroll
+    for (int i = 0; i < IA; ++i) {
+      const int grp = wave + i * NW;  // 8-row group index
+      llvm_amdgcn_raw_buffer_load_lds(
+          ra, (__attribute__((address_space(3))) uint32_t*)(&sA[buf][grp * 8 * BK]), 16,
+          a_off + grp * 8 * lda * 2 + k0 * 2, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < IB; ++i) {
+      const int grp = wave + i * NW;
+      llvm_amdgcn_raw_buffer_load_lds(
+          rb, (__attribute__((address_space(3))) uint32_t*)(&sB[buf][grp * 8 * BK]), 16,
+          b_off + grp * 8 * ldb * 2 + k0 * 2, 0, 0, 0);
+    }
+  };
+
+  f32x16 acc[TN][TM];
+#pragma unroll
+  for (int a = 0; a < TN; ++a)
+#pragma unroll
+    for (int b = 0; b < TM; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+  const int l32 = lane & 31, g = lane >> 5;
+  const int KT = K / BK;
+  issue(0, 0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  for (int kt = 0; kt < KT; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < KT) issue(cur ^ 1, (kt + 1) * BK);
+    const bf16_t* tA = sA[cur];
+    const bf16_t* tB = sB[cur];
+    // Fragments of K sub-step kk are read while the MFMAs of kk-1 run; the
+    // scheduling groups interleave one LDS read per MFMA.
+    bf16x8 fw0[TN], fx0[TM], fw1[TN], fx1[TM];
+    auto ldfrag = [&](bf16x8* fw, bf16x8* fx, int kk) {
+#pragma unroll
+      for (int a = 0; a < TN; ++a)
+        fw[a] = *reinterpret_cast<const bf16x8*>(&tB[swz(wn * WN + a * 32 + l32, 2 * kk + g)]);
+#pragma unroll
+      for (int b = 0; b < TM; ++b)
+        fx[b] = *reinterpret_cast<const bf16x8*>(&tA[swz(wm * WM + b * 32 + l32, 2 * kk + g)]);
+    };
+    auto mma = [&](const bf16x8* fw, const bf16x8* fx) {
+#pragma unroll
+      for (int a = 0; a < TN; ++a)
+#pragma unroll
+        for (int b = 0; b < TM; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fw[a], fx[b], acc[a][b], 0, 0, 0);
+    };
+    ldfrag(fw0, fx0, 0);
+    ldfrag(fw1, fx1, 1);
+    mma(fw0, fx0);
+    ldfrag(fw0, fx0, 2);
+    mma(fw1, fx1);
+    ldfrag(fw1, fx1, 3);
+    mma(fw0, fx0);
+    mma(fw1, fx1);
+    // Pipeline: the next tile's loads, the reads of sub-step 0, then each
+    // sub-step's MFMAs with the next sub-step's reads threaded one per MFMA.
+    constexpr int NF = TN + TM, NM = TN * TM;
+    __builtin_amdgcn_sched_group_barrier(0x100, NF, 0);
+#pragma unroll
+    for (int st = 0; st < 3; ++st) {
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      if (NM > NF) __builtin_amdgcn_sched_group_barrier(0x008, NM - NF, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, NM, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int b = 0; b < TM; ++b) {
+    const int m = m0 + wm * WM + b * 32 + l32;
+    if (m >= M) continue;
+#pragma unroll
+    for (int a = 0; a < TN; ++a) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int n = n0 + wn * WN + a * 32 + 8 * q + 4 * g;
+        if (n < N)
+          epi_store4<EPI, OUT_BF16>(e, m, n, acc[a][b][4 * q + 0], acc[a][b][4 * q + 1],
+                                    acc[a][b][4 * q + 2], acc[a][b][4 * q + 3]);
+      }
+    }
+  }
+}
+
+template <int BM, int BN, int WGM, int WGN>
+static hipError_t launch_bf16_dl(const bf16_t* A, int lda, const bf16_t* B, int ldb, int M,
+                                 int N, int K, int op, const EpiArgs& e, hipStream_t s) {
+  const int gm = (M + BM - 1) / BM, gn = (N + BN - 1) / BN;
+  dim3 grid(gm * gn), block(WGM * WGN * 64);
+#define VL_GEMM_CASE(OP)                                                                      \
+  case OP:                                                                                    \
+    hipLaunchKernelGGL((k_gemm_bf16_dl<BM, BN, WGM, WGN, OP>), grid, block, 0, s, A, lda, B,  \
+                       ldb, M, N, K, gm, gn, e);                                              \
+    break;
+  switch (op) {
+    VL_GEMM_CASE(OP_PATCH)
+    VL_GEMM_CASE(OP_QKV)
+    VL_GEMM_CASE(OP_OPROJ)
+    VL_GEMM_CASE(OP_FC1)
+    VL_GEMM_CASE(OP_FC2)
+    default: return hipErrorInvalidValue;
+  }
+#undef VL_GEMM_CASE
+  return hipGetLastError();
+}
+
 template <int BM, int BN, int WGM, int WGN, bool B_FP8>
 static hipError_t launch_bf16(const bf16_t* A, int lda, const void* B, int ldb, int M, int N,
                               int K, int op, const EpiArgs& e, hipStream_t s) {

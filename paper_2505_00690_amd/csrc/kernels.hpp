@@ -76,10 +76,11 @@ hipError_t attention_f32(const float* qkv, float* o, const ImgDesc* imgs,
                          const AttnItem* items, int n_items, int heads, int head_dim,
                          hipStream_t s);
 
-// Class-token pooling, final LayerNorm, projection [P, D], L2 normalisation.
+// Class-token pooling, final LayerNorm, projection [P, D] into e_tmp
+// [n, P], then L2 normalisation into emb [n, P].
 hipError_t pool_project(const float* x, const ImgDesc* imgs, int n_imgs, const float* g,
                         const float* b, float eps, const float* proj, int D, int P,
-                        float* emb, hipStream_t s);
+                        float* e_tmp, float* emb, hipStream_t s);
 
 // Per-row softmax / sigmoid of logits in place, and the row argmax.
 hipError_t score_rows(float* scores, int32_t* top1, int rows, int cols, int head,

@@ -226,3 +226,33 @@ def test_l14_fp8w_sampled(V):
     cos = cosine(got, ref)
     _say(f"  l14 fp8w min cos {cos.min():.6f}")
     assert cos.min() >= COS_TOL
+
+
+# ---------------------------------------------------------------- serving
+def test_serving_mix_equals_alone(V):
+    """Requests served by the continuous-batching loop (two streams, HBM
+    budget) give the same embeddings and top-1 as each request run alone."""
+    from paper_2505_00690_amd.serve import GpuExecutor, RealClock, Request, Scheduler
+    enc = encoder(V, "tiny", 1000, "fp8w")
+    texts = torch.from_numpy(synth.make_texts(64, 128, 3004)).cuda()
+    reqs = []
+    for i, r in enumerate(synth.draw_requests(24, 2000.0, (64, 96, 128), 5004, 1, 6)):
+        imgs = synth.make_images(r.sizes, 7000 + i)
+        reqs.append(Request(i, r.arrival_s, r.sizes, torch.from_numpy(pack(imgs)).cuda()))
+    torch.cuda.synchronize()
+    ex = GpuExecutor(enc, texts, "sigmoid", 10.0, -10.0, slots=2)
+    budget = 3 * enc.workspace_bytes([(128, 128)] * 6)
+    st = Scheduler(ex, budget, slots=2, max_batch_images=16).run(reqs, RealClock())
+    torch.cuda.synchronize()
+    assert len(st.results) == 24 and st.peak_budget <= budget
+    _say(f"  serving: {st.batches} batches, max in flight {st.max_inflight}")
+    for res in st.results:
+        r = reqs[res.rid]
+        alone = enc.encode(r.payload, r.sizes)
+        sc = torch.empty((len(r.sizes), 64), device="cuda")
+        top = torch.empty(len(r.sizes), dtype=torch.int32, device="cuda")
+        V.vl_score(alone, texts, "sigmoid", 10.0, -10.0, sc, top)
+        torch.cuda.synchronize()
+        emb_mix, top_mix = res.output
+        assert torch.equal(emb_mix, alone), res.rid
+        assert torch.equal(top_mix, top), res.rid
