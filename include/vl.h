@@ -149,6 +149,38 @@ vl_status vl_model_set_option(vl_model* m, vl_option opt, int64_t value);
 vl_status vl_model_op_times(vl_model* m, double* ms_out, int64_t* launches_out,
                             int32_t reset);
 
+/* ---- GEMM tile configurations and the autotuner ------------------------
+ * The BF16 / e4m3-weight GEMMs (patch embedding, QKV, output projection,
+ * FC1, FC2) can run in several tile configurations.  All of them accumulate
+ * K in the same order, so they give bitwise identical results: the choice
+ * only affects speed, and may differ with the batch size.  The choice is a
+ * table indexed by (GEMM operation, M bucket), where M is the packed token
+ * count of the call and the bucket is floor(log2(M)); -1 entries use the
+ * built-in heuristic.  Not used by VL_FP32 models.                        */
+#define VL_N_GEMM_OPS 5       /* 0 patch, 1 qkv, 2 oproj, 3 fc1, 4 fc2      */
+#define VL_N_M_BUCKETS 25
+
+int32_t vl_gemm_config_count(void);
+/* Name of configuration `cfg` (static string), NULL if out of range.      */
+const char* vl_gemm_config_name(int32_t cfg);
+
+/* Copy the model's table (VL_N_GEMM_OPS * VL_N_M_BUCKETS int32, row-major
+ * by operation) to / from host memory.  set validates every entry (-1 or a
+ * valid id) and drops cached graphs.                                       */
+vl_status vl_model_get_tuning(const vl_model* m, int32_t* table);
+vl_status vl_model_set_tuning(vl_model* m, const int32_t* table);
+
+/* Autotune for one batch shape: runs one full vl_encode_images of the given
+ * batch (so the workspace holds live operands), then times every
+ * configuration of each GEMM operation over `reps` launches with HIP events
+ * on `stream`, and stores the fastest for this batch's M bucket.  Arguments
+ * as for vl_encode_images; emb_out_dev receives that encode's result.
+ * Blocks until the timing is done.  VL_ERR_UNSUPPORTED for VL_FP32.       */
+vl_status vl_model_autotune(vl_model* m, const float* pixels_dev, const int32_t* heights,
+                            const int32_t* widths, int32_t n_images, float* emb_out_dev,
+                            void* workspace_dev, size_t workspace_bytes, int32_t reps,
+                            void* stream);
+
 /* Bytes of device workspace vl_encode_images needs for this batch.
  * heights/widths: host arrays of n_images entries.  0 on invalid input.   */
 size_t vl_encode_workspace_bytes(const vl_model* m, int32_t n_images,

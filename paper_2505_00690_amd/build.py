@@ -19,7 +19,8 @@ ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libvl.so")
 OBJDIR = os.path.join(PKG, "_build")
 
-SOURCES = ["api.cpp", "gemm.hip", "attention.hip", "elementwise.hip"]
+SOURCES = ["api.cpp", "gemm.hip", "attention.hip", "elementwise.hip"] + [
+    f"gemm_cfg{i}.hip" for i in range(7)]
 
 ARCH = "gfx950"
 HIPCC_FLAGS = [
@@ -51,7 +52,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(os.cpu_count() or 4, 16, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

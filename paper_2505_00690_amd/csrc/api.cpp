@@ -93,6 +93,7 @@ struct vl_model {
   double op_ms[VL_N_OPS] = {};
   int64_t op_launches[VL_N_OPS] = {};
   hipStream_t capture = nullptr;  // private stream graphs are captured on
+  int32_t tuning[VL_N_GEMM_OPS][VL_N_M_BUCKETS];
 };
 
 namespace {
@@ -204,6 +205,17 @@ vl_status stage_descriptors(vl_model* m, const Plan& p, void* dst, hipStream_t s
 
 enum { T_PATCH = 0, T_LN, T_QKV, T_ATTN, T_OPROJ, T_FC1, T_FC2, T_POOL };
 
+int m_bucket(int M) {
+  int b = 0;
+  while ((2 << b) <= M && b < VL_N_M_BUCKETS - 1) ++b;
+  return b;
+}
+
+// Tile configuration for GEMM operation op (0 patch .. 4 fc2) at M rows.
+int gemm_cfg_for(const vl_model* m, int op, int M) {
+  return m->tuning[op][m_bucket(M)];
+}
+
 hipError_t take_event(vl_model* m, hipEvent_t* ev) {
   if (!m->free_events.empty()) {
     *ev = m->free_events.back();
@@ -274,7 +286,7 @@ vl_status run_encoder(vl_model* m, const Plan& p, const float* pix, float* emb, 
                       pe, s));
     else
       VL_HIP(gemm_bf16(static_cast<const bf16_t*>(QH), m->Kpad, m->patch_w, m->Kpad, false, T,
-                       D, m->Kpad, OP_PATCH, pe, s));
+                       D, m->Kpad, OP_PATCH, gemm_cfg_for(m, 0, T), pe, s));
   });
 
   for (const Layer& ly : m->layers) {
@@ -304,13 +316,17 @@ vl_status run_encoder(vl_model* m, const Plan& p, const float* pix, float* emb, 
     } else {
       const bf16_t* y = static_cast<const bf16_t*>(Y);
       const bf16_t* qh = static_cast<const bf16_t*>(QH);
-      VL_TIMED(T_QKV, VL_HIP(gemm_bf16(y, D, ly.qkv_w, D, fp8, T, 3 * D, D, OP_QKV, e1, s)));
+      VL_TIMED(T_QKV, VL_HIP(gemm_bf16(y, D, ly.qkv_w, D, fp8, T, 3 * D, D, OP_QKV,
+                                       gemm_cfg_for(m, 1, T), e1, s)));
       VL_TIMED(T_ATTN, VL_HIP(attention_bf16(qh, static_cast<bf16_t*>(Y), d_imgs, d_items,
                                              p.n_items, m->heads, m->hd, s)));
-      VL_TIMED(T_OPROJ, VL_HIP(gemm_bf16(y, D, ly.o_w, D, fp8, T, D, D, OP_OPROJ, e2, s)));
+      VL_TIMED(T_OPROJ, VL_HIP(gemm_bf16(y, D, ly.o_w, D, fp8, T, D, D, OP_OPROJ,
+                                         gemm_cfg_for(m, 2, T), e2, s)));
       VL_TIMED(T_LN, VL_HIP(layernorm_rows(X, ly.ln2_g, ly.ln2_b, eps, Y, true, T, D, s)));
-      VL_TIMED(T_FC1, VL_HIP(gemm_bf16(y, D, ly.fc1_w, D, fp8, T, F, D, OP_FC1, e3, s)));
-      VL_TIMED(T_FC2, VL_HIP(gemm_bf16(qh, F, ly.fc2_w, F, fp8, T, D, F, OP_FC2, e4, s)));
+      VL_TIMED(T_FC1, VL_HIP(gemm_bf16(y, D, ly.fc1_w, D, fp8, T, F, D, OP_FC1,
+                                       gemm_cfg_for(m, 3, T), e3, s)));
+      VL_TIMED(T_FC2, VL_HIP(gemm_bf16(qh, F, ly.fc2_w, F, fp8, T, D, F, OP_FC2,
+                                       gemm_cfg_for(m, 4, T), e4, s)));
     }
   }
   VL_TIMED(T_POOL, VL_HIP(pool_project(X, d_imgs, p.n, m->lnf_g, m->lnf_b, eps, m->proj, D,
@@ -499,6 +515,8 @@ vl_status vl_model_create(const vl_config* cfg, vl_precision prec, const float* 
   m->lnf_g = f(d_lnf_g);
   m->lnf_b = f(d_lnf_b);
   m->proj = f(d_proj);
+  for (auto& row : m->tuning)
+    for (auto& v : row) v = -1;
   m->ring.resize(8);
   for (Staging& r : m->ring) chk(hipEventCreateWithFlags(&r.ev, hipEventDisableTiming), "hipEventCreate");
   if (st != VL_OK) {
@@ -635,6 +653,103 @@ vl_status vl_encode_images(vl_model* m, const float* pix, const int32_t* hs, con
     it = m->graphs.emplace(key, ge).first;
   }
   VL_HIP(hipGraphLaunch(it->second.exec, s));
+  return VL_OK;
+}
+
+int32_t vl_gemm_config_count(void) { return N_GEMM_CFGS; }
+
+const char* vl_gemm_config_name(int32_t cfg) {
+  return cfg >= 0 && cfg < N_GEMM_CFGS ? gemm_cfg_name(cfg) : nullptr;
+}
+
+vl_status vl_model_get_tuning(const vl_model* m, int32_t* table) {
+  if (!m || !table) return fail(VL_ERR_INVALID_ARG, "NULL argument");
+  std::memcpy(table, m->tuning, sizeof(m->tuning));
+  return VL_OK;
+}
+
+vl_status vl_model_set_tuning(vl_model* m, const int32_t* table) {
+  if (!m || !table) return fail(VL_ERR_INVALID_ARG, "NULL argument");
+  for (int i = 0; i < VL_N_GEMM_OPS * VL_N_M_BUCKETS; ++i)
+    if (table[i] < -1 || table[i] >= N_GEMM_CFGS)
+      return fail(VL_ERR_INVALID_ARG, "tuning entry " + std::to_string(i) + " is not a configuration id");
+  std::lock_guard<std::mutex> lk(m->mu);
+  (void)hipDeviceSynchronize();
+  destroy_graphs(m);
+  std::memcpy(m->tuning, table, sizeof(m->tuning));
+  return VL_OK;
+}
+
+vl_status vl_model_autotune(vl_model* m, const float* pix, const int32_t* hs, const int32_t* wsz,
+                            int32_t n, float* emb, void* ws, size_t ws_bytes, int32_t reps,
+                            void* stream) {
+  if (!m) return fail(VL_ERR_INVALID_ARG, "model is NULL");
+  if (m->prec == VL_FP32) return fail(VL_ERR_UNSUPPORTED, "FP32 models have a single GEMM");
+  if (reps < 1) return fail(VL_ERR_INVALID_ARG, "reps must be >= 1");
+  if (!pix || !emb || !ws) return fail(VL_ERR_INVALID_ARG, "pixels, emb_out or workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(VL_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  Plan p;
+  std::string why;
+  if (!make_plan(m, n, hs, wsz, &p, &why)) return fail(VL_ERR_INVALID_ARG, why);
+  if (ws_bytes < p.total) return fail(VL_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  std::lock_guard<std::mutex> lk(m->mu);
+  const bool timing = m->timing;
+  m->timing = false;
+  vl_status st = stage_descriptors(m, p, w, s);
+  if (st == VL_OK) st = run_encoder(m, p, pix, emb, w, s);
+  m->timing = timing;
+  if (st != VL_OK) return st;
+  const bool fp8 = m->prec == VL_FP8W_BF16A;
+  const int T = p.T, D = m->D, F = m->F;
+  const Layer& ly = m->layers.empty() ? Layer{} : m->layers[0];
+  const bf16_t* Y = reinterpret_cast<const bf16_t*>(w + p.off_Y);
+  bf16_t* QH = reinterpret_cast<bf16_t*>(w + p.off_QH);
+  float* X = reinterpret_cast<float*>(w + p.off_X);
+  const int2* tok = reinterpret_cast<const int2*>(w + p.off_tok);
+  hipEvent_t e0, e1;
+  VL_HIP(hipEventCreate(&e0));
+  VL_HIP(hipEventCreate(&e1));
+  struct OpShape { int op, N, K; const bf16_t* A; int lda; const void* B; bool b8; EpiArgs e; };
+  std::vector<OpShape> shapes;
+  {
+    EpiArgs pe;
+    pe.bias = m->patch_b; pe.out = X; pe.ldo = D; pe.tok_info = tok;
+    pe.imgs = reinterpret_cast<const ImgDesc*>(w); pe.cls = m->cls; pe.pos = m->pos; pe.base_grid = m->g0;
+    shapes.push_back({OP_PATCH, D, m->Kpad, QH, m->Kpad, m->patch_w, false, pe});
+  }
+  if (!m->layers.empty()) {
+    EpiArgs e1a; e1a.bias = ly.qkv_b; e1a.wscale = ly.qkv_s; e1a.out = QH; e1a.ldo = 3 * D;
+    EpiArgs e2a; e2a.bias = ly.o_b; e2a.wscale = ly.o_s; e2a.out = X; e2a.ldo = D;
+    EpiArgs e3a; e3a.bias = ly.fc1_b; e3a.wscale = ly.fc1_s; e3a.out = QH; e3a.ldo = F;
+    EpiArgs e4a; e4a.bias = ly.fc2_b; e4a.wscale = ly.fc2_s; e4a.out = X; e4a.ldo = D;
+    shapes.push_back({OP_QKV, 3 * D, D, Y, D, ly.qkv_w, fp8, e1a});
+    shapes.push_back({OP_OPROJ, D, D, Y, D, ly.o_w, fp8, e2a});
+    shapes.push_back({OP_FC1, F, D, Y, D, ly.fc1_w, fp8, e3a});
+    shapes.push_back({OP_FC2, D, F, QH, F, ly.fc2_w, fp8, e4a});
+  }
+  const int b = m_bucket(T);
+  for (const OpShape& o : shapes) {
+    float best = 1e30f;
+    int best_cfg = -1;
+    for (int cfg = 0; cfg < N_GEMM_CFGS; ++cfg) {
+      hipError_t err = gemm_bf16(o.A, o.lda, o.B, o.K, o.b8, T, o.N, o.K, o.op, cfg, o.e, s);
+      if (err != hipSuccess) continue;
+      VL_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < reps; ++r) VL_HIP(gemm_bf16(o.A, o.lda, o.B, o.K, o.b8, T, o.N, o.K, o.op, cfg, o.e, s));
+      VL_HIP(hipEventRecord(e1, s));
+      VL_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      VL_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) { best = ms; best_cfg = cfg; }
+    }
+    m->tuning[o.op][b] = best_cfg;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipDeviceSynchronize();
+  destroy_graphs(m);
   return VL_OK;
 }
 

@@ -1,0 +1,492 @@
+// Dense contractions (kernel templates) C[M,N] = A[M,K] . B[N,K]^T with fused epilogues.
+//
+// BF16 path: MFMA v_mfma_f32_32x32x16_bf16 on gfx950.  A workgroup owns a
+// BM x BN output tile and walks K in steps of 64 through double-buffered LDS
+// tiles; global loads of the next K step are issued before the MFMAs of the
+// current one.  LDS rows are 64 BF16 (128 B) with the eight 16-byte chunks of
+// a row XOR-swizzled by (row & 7), so the 32 rows one MFMA operand read
+// touches spread across the banks.  The weight tile feeds the MFMA's first
+// operand and the activation tile the second, so each lane ends up owning one
+// activation row and groups of four consecutive output columns: the
+// epilogue then reads bias / writes output with 8- or 16-byte vectors.
+//
+// FP32 path: classic LDS-tiled FMA kernel (64 x 64 tile, 4 x 4 per thread),
+// the plain FP32 baseline and the logit GEMM of the scoring head.
+// BF16 / FP32 GEMM kernel templates shared by the per-configuration
+// translation units (gemm_cfg_*.hip) and the FP32 unit (gemm.hip).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace vl {
+
+// ---------------------------------------------------------------- epilogue
+enum EpiKind { EPI_BIAS, EPI_BIAS_GELU, EPI_BIAS_RESID, EPI_PATCH, EPI_SCALE_BIAS };
+template <int OP>
+struct OpEpi {
+  static constexpr int kind = OP == OP_PATCH ? EPI_PATCH
+                              : OP == OP_QKV ? EPI_BIAS
+                              : OP == OP_FC1 ? EPI_BIAS_GELU
+                              : OP == OP_LOGITS ? EPI_SCALE_BIAS
+                                                : EPI_BIAS_RESID;
+};
+
+template <int EPI, bool OUT_BF16>
+__device__ __forceinline__ void epi_store4(const EpiArgs& e, int m, int n, float v0, float v1,
+                                           float v2, float v3) {
+  float v[4] = {v0, v1, v2, v3};
+  if (EPI == EPI_SCALE_BIAS) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = e.alpha * v[j] + e.beta;
+    *reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n) =
+        make_float4(v[0], v[1], v[2], v[3]);
+    return;
+  }
+  if (e.wscale) {
+    const float4 ws = *reinterpret_cast<const float4*>(e.wscale + n);
+    v[0] *= ws.x; v[1] *= ws.y; v[2] *= ws.z; v[3] *= ws.w;
+  }
+  if (EPI == EPI_PATCH) {
+    const int2 ti = e.tok_info[m];
+    float* X = static_cast<float*>(e.out) + (size_t)m * e.ldo + n;
+    float4 add;
+    if (ti.y == 0) {
+      const float4 c = *reinterpret_cast<const float4*>(e.cls + n);
+      const float4 p = *reinterpret_cast<const float4*>(e.pos + n);
+      add = make_float4(c.x + p.x, c.y + p.y, c.z + p.z, c.w + p.w);
+    } else {
+      const ImgDesc d = e.imgs[ti.x];
+      const int g0 = e.base_grid;
+      const int pidx = ti.y - 1;
+      const int r = pidx / d.gw, q = pidx - r * d.gw;
+      float sy = ((float)r + 0.5f) * (float)g0 / (float)d.gh - 0.5f;
+      float sx = ((float)q + 0.5f) * (float)g0 / (float)d.gw - 0.5f;
+      sy = fminf(fmaxf(sy, 0.f), (float)(g0 - 1));
+      sx = fminf(fmaxf(sx, 0.f), (float)(g0 - 1));
+      const int y0 = (int)sy, x0 = (int)sx;
+      const int y1 = min(y0 + 1, g0 - 1), x1 = min(x0 + 1, g0 - 1);
+      const float wy = sy - (float)y0, wx = sx - (float)x0;
+      const int D = e.ldo;
+      const float4 p00 = *reinterpret_cast<const float4*>(e.pos + (size_t)(1 + y0 * g0 + x0) * D + n);
+      const float4 p01 = *reinterpret_cast<const float4*>(e.pos + (size_t)(1 + y0 * g0 + x1) * D + n);
+      const float4 p10 = *reinterpret_cast<const float4*>(e.pos + (size_t)(1 + y1 * g0 + x0) * D + n);
+      const float4 p11 = *reinterpret_cast<const float4*>(e.pos + (size_t)(1 + y1 * g0 + x1) * D + n);
+      const float4 b = *reinterpret_cast<const float4*>(e.bias + n);
+      const float a00 = (1.f - wy) * (1.f - wx), a01 = (1.f - wy) * wx;
+      const float a10 = wy * (1.f - wx), a11 = wy * wx;
+      add.x = b.x + a00 * p00.x + a01 * p01.x + a10 * p10.x + a11 * p11.x;
+      add.y = b.y + a00 * p00.y + a01 * p01.y + a10 * p10.y + a11 * p11.y;
+      add.z = b.z + a00 * p00.z + a01 * p01.z + a10 * p10.z + a11 * p11.z;
+      add.w = b.w + a00 * p00.w + a01 * p01.w + a10 * p10.w + a11 * p11.w;
+    }
+    *reinterpret_cast<float4*>(X) = make_float4(v[0] + add.x, v[1] + add.y, v[2] + add.z,
+                                                v[3] + add.w);
+    return;
+  }
+  const float4 b = *reinterpret_cast<const float4*>(e.bias + n);
+  v[0] += b.x; v[1] += b.y; v[2] += b.z; v[3] += b.w;
+  if (EPI == EPI_BIAS_RESID) {
+    float4* X = reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n);
+    float4 x = *X;
+    x.x += v[0]; x.y += v[1]; x.z += v[2]; x.w += v[3];
+    *X = x;
+    return;
+  }
+  if (EPI == EPI_BIAS_GELU) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = gelu_erf(v[j]);
+  }
+  if (OUT_BF16) {
+    u32x2 pk;
+    pk.x = pack_bf16x2(v[0], v[1]);
+    pk.y = pack_bf16x2(v[2], v[3]);
+    *reinterpret_cast<u32x2*>(static_cast<bf16_t*>(e.out) + (size_t)m * e.ldo + n) = pk;
+  } else {
+    *reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n) =
+        make_float4(v[0], v[1], v[2], v[3]);
+  }
+}
+
+// ------------------------------------------------------------ BF16 MFMA GEMM
+constexpr int BK = 64;  // K step (BF16 elements) per LDS tile
+
+__device__ __forceinline__ int swz(int row, int chunk) {  // element offset in a tile
+  return row * BK + ((chunk ^ (row & 7)) << 3);
+}
+
+template <int BM, int BN, int WGM, int WGN, bool B_FP8, int OP>
+__global__ __launch_bounds__(WGM* WGN * 64) void k_gemm_bf16(
+    const bf16_t* __restrict__ A, int lda, const void* __restrict__ Bv, int ldb, int M,
+    int N, int K, EpiArgs e) {
+  constexpr int EPI = OpEpi<OP>::kind;
+  constexpr bool OUT_BF16 = OP == OP_QKV || OP == OP_FC1;
+  constexpr int NT = WGM * WGN * 64;
+  constexpr int WM = BM / WGM;   // activation rows per wave
+  constexpr int WN = BN / WGN;   // output columns per wave
+  constexpr int TM = WM / 32;
+  constexpr int TN = WN / 32;
+  constexpr int CA = BM * 8 / NT;                      // 16-B chunks of A per thread
+  constexpr int CB = B_FP8 ? BN * 4 / NT : BN * 8 / NT;  // 16-B chunks of B per thread
+  static_assert(CA * NT == BM * 8, "A tile / threads");
+  static_assert(CB >= 1, "B tile / threads");
+
+  __shared__ __attribute__((aligned(16))) bf16_t sA[2][BM * BK];
+  __shared__ __attribute__((aligned(16))) bf16_t sB[2][BN * BK];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int m0 = blockIdx.x * BM;
+  const int n0 = blockIdx.y * BN;
+
+  // This thread's 16-B chunks: chunk c = tid + i*NT sits in tile row
+  // c / 8 (A, BF16 B) or c / 4 (e4m3 B) and chunk column c % 8 (c % 4).
+  // Rows past M / N are clamped to the last row (loaded, never stored).
+  constexpr int RA = NT / 8;                       // row stride between i's
+  constexpr int RB = B_FP8 ? NT / 4 : NT / 8;
+  const int a_row0 = tid >> 3, a_kc = tid & 7;
+  const int b_row0 = B_FP8 ? (tid >> 2) : (tid >> 3);
+  const int b_kc = B_FP8 ? (tid & 3) : (tid & 7);
+  const bf16_t* Ab = A + (size_t)m0 * lda;
+  const char* Bb = static_cast<const char*>(Bv) + (size_t)n0 * ldb * (B_FP8 ? 1 : 2);
+  const int a_lim = M - 1 - m0, b_lim = N - 1 - n0;
+
+  u32x4 ra[CA], rb[CB];
+  auto load_tile = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < CA; ++i) {
+      const int row = min(a_row0 + i * RA, a_lim);
+      ra[i] = *reinterpret_cast<const u32x4*>(Ab + row * lda + k0 + a_kc * 8);
+    }
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+      const int row = min(b_row0 + i * RB, b_lim);
+      if (B_FP8)
+        rb[i] = *reinterpret_cast<const u32x4*>(Bb + row * ldb + k0 + b_kc * 16);
+      else
+        rb[i] = *reinterpret_cast<const u32x4*>(Bb + 2 * (row * ldb + k0 + b_kc * 8));
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < CA; ++i)
+      *reinterpret_cast<u32x4*>(&sA[buf][swz(a_row0 + i * RA, a_kc)]) = ra[i];
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+      const int row = b_row0 + i * RB;
+      if (B_FP8) {
+        u32x4 lo, hi;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const uint32_t x = rb[i][w];
+          const uint32_t h0 = e4m3_to_bf16_bits(x & 0xFF) | (e4m3_to_bf16_bits((x >> 8) & 0xFF) << 16);
+          const uint32_t h1 = e4m3_to_bf16_bits((x >> 16) & 0xFF) | (e4m3_to_bf16_bits(x >> 24) << 16);
+          if (w < 2) { lo[2 * w] = h0; lo[2 * w + 1] = h1; }
+          else { hi[2 * (w - 2)] = h0; hi[2 * (w - 2) + 1] = h1; }
+        }
+        *reinterpret_cast<u32x4*>(&sB[buf][swz(row, 2 * b_kc)]) = lo;
+        *reinterpret_cast<u32x4*>(&sB[buf][swz(row, 2 * b_kc + 1)]) = hi;
+      } else {
+        *reinterpret_cast<u32x4*>(&sB[buf][swz(row, b_kc)]) = rb[i];
+      }
+    }
+  };
+
+  f32x16 acc[TN][TM];
+#pragma unroll
+  for (int a = 0; a < TN; ++a)
+#pragma unroll
+    for (int b = 0; b < TM; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+  const int l32 = lane & 31, g = lane >> 5;
+  const int KT = K / BK;
+  load_tile(0);
+  store_tile(0);
+  __syncthreads();
+  for (int kt = 0; kt < KT; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < KT) load_tile((kt + 1) * BK);
+    const bf16_t* tA = sA[cur];
+    const bf16_t* tB = sB[cur];
+#pragma unroll
+    for (int kk = 0; kk < BK / 16; ++kk) {
+      bf16x8 fw[TN], fx[TM];
+#pragma unroll
+      for (int a = 0; a < TN; ++a)
+        fw[a] = *reinterpret_cast<const bf16x8*>(&tB[swz(wn * WN + a * 32 + l32, 2 * kk + g)]);
+#pragma unroll
+      for (int b = 0; b < TM; ++b)
+        fx[b] = *reinterpret_cast<const bf16x8*>(&tA[swz(wm * WM + b * 32 + l32, 2 * kk + g)]);
+#pragma unroll
+      for (int a = 0; a < TN; ++a)
+#pragma unroll
+        for (int b = 0; b < TM; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fw[a], fx[b], acc[a][b], 0, 0, 0);
+    }
+    if (kt + 1 < KT) store_tile(cur ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue: acc[a][b][r] is C[m, n] with m = row of lane, n = 8(r/4)+4g+r%4.
+#pragma unroll
+  for (int b = 0; b < TM; ++b) {
+    const int m = m0 + wm * WM + b * 32 + l32;
+    if (m >= M) continue;
+#pragma unroll
+    for (int a = 0; a < TN; ++a) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int n = n0 + wn * WN + a * 32 + 8 * q + 4 * g;
+        if (n < N)
+          epi_store4<EPI, OUT_BF16>(e, m, n, acc[a][b][4 * q + 0], acc[a][b][4 * q + 1],
+                                    acc[a][b][4 * q + 2], acc[a][b][4 * q + 3]);
+      }
+    }
+  }
+}
+
+// ------------------------------------------- BF16 MFMA GEMM, direct-to-LDS
+// Same contraction and epilogues, for BF16 weights.  Tiles are fetched with
+// buffer_load ... lds (16 bytes per lane straight into LDS, no staging
+// registers): one wave instruction fills 8 tile rows (1 KB), lane l taking
+// row l/8 and physical chunk l%8, i.e. logical chunk (l%8) ^ (l/8) under the
+// row-XOR swizzle.  Buffer resources are bounded by the matrix end, so rows
+// past M / N read as zero.  Output tiles are assigned XCD by XCD: workgroup
+// ids are dealt round-robin to the 8 XCDs, so a contiguous range of tiles is
+// given to each XCD and walked in groups of GROUP_M row tiles, letting the
+// tiles resident on one XCD share A rows and B rows in its L2.
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+extern "C" __device__ void llvm_amdgcn_raw_buffer_load_lds(
+    i32x4 rsrc, __attribute__((address_space(3))) uint32_t* lds, int size, int voffset,
+    int soffset, int offset, int aux) __asm("llvm.amdgcn.raw.buffer.load.lds");
+
+__device__ __forceinline__ i32x4 buffer_rsrc(const void* base, uint64_t bytes) {
+  const uint64_t p = reinterpret_cast<uint64_t>(base);
+  i32x4 r;
+  r[0] = (int32_t)(uint32_t)(p & 0xffffffffu);
+  r[1] = (int32_t)(uint32_t)(p >> 32);        // stride 0
+  r[2] = (int32_t)(uint32_t)(bytes > 0xffffffffull ? 0xffffffffull : bytes);
+  r[3] = 0x00020000;
+  r[0] = __builtin_amdgcn_readfirstlane(r[0]);
+  r[1] = __builtin_amdgcn_readfirstlane(r[1]);
+  r[2] = __builtin_amdgcn_readfirstlane(r[2]);
+  return r;
+}
+
+__device__ __forceinline__ void xcd_tile(int gm, int gn, int group_m, int* tm, int* tn) {
+  const int total = gm * gn;
+  const int bid = blockIdx.x;
+  const int xcd = bid & 7, local = bid >> 3;
+  const int q = total >> 3, r = total & 7;
+  const int id = xcd * q + min(xcd, r) + local;
+  const int per_group = group_m * gn;
+  const int g = id / per_group;
+  const int first = g * group_m;
+  const int gsz = min(gm - first, group_m);
+  const int w = id - g * per_group;
+  *tm = first + w % gsz;
+  *tn = w / gsz;
+}
+
+// e4m3 B tiles: rows of 64 bytes (BK codes) whose four 16-byte chunks are
+// XOR-swizzled by (row >> 2) & 3; a fragment read takes 8 codes (ds_read_b64)
+// and widens them with v_cvt_scalef32_pk_bf16_fp8 (scale 1: exact).
+__device__ __forceinline__ int swz8(int row, int kk, int g) {  // byte offset in an e4m3 tile
+  return row * BK + ((kk ^ ((row >> 2) & 3)) << 4) + (g << 3);
+}
+
+template <int BM, int BN, int WGM, int WGN, bool B_FP8, int OP>
+__global__ __launch_bounds__(WGM* WGN * 64)
+__attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_bf16_dl(
+    const bf16_t* __restrict__ A, int lda, const void* __restrict__ Bv, int ldb, int M, int N,
+    int K, int gm, int gn, EpiArgs e) {
+  constexpr int EPI = OpEpi<OP>::kind;
+  constexpr bool OUT_BF16 = OP == OP_QKV || OP == OP_FC1;
+  constexpr int NW = WGM * WGN;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int TM = WM / 32, TN = WN / 32;
+  constexpr int BROWS = B_FP8 ? 16 : 8;               // B rows per load instruction
+  constexpr int IA = BM / 8 / NW, IB = BN / BROWS / NW;  // load instructions per wave per tile
+  static_assert(IA * NW * 8 == BM && IB * NW * BROWS == BN, "tile rows / waves");
+  constexpr int BES = B_FP8 ? 1 : 2;                    // bytes per B element
+
+  __shared__ __attribute__((aligned(1024))) bf16_t sA[2][BM * BK];
+  __shared__ __attribute__((aligned(1024))) uint8_t sB[2][BN * BK * BES];
+
+  int tm_, tn_;
+  xcd_tile(gm, gn, 8, &tm_, &tn_);
+  const int m0 = tm_ * BM, n0 = tn_ * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+
+  const i32x4 ra = buffer_rsrc(A + (size_t)m0 * lda, (uint64_t)(M - m0) * lda * 2);
+  const i32x4 rb = buffer_rsrc(static_cast<const char*>(Bv) + (size_t)n0 * ldb * BES,
+                               (uint64_t)(N - n0) * ldb * BES);
+  // Lane's byte offset inside an 8-row group: row l/8, logical chunk (l%8)^(l/8).
+  const int lrow = lane >> 3, lchunk = (lane & 7) ^ (lane >> 3);
+  const int a_off = lrow * lda * 2 + lchunk * 16;
+  // e4m3 B: 16-row groups, lane row l/4, physical chunk l%4, logical chunk
+  // (l%4) ^ ((l/16)%4).
+  const int b_off = B_FP8 ? (lane >> 2) * ldb + (((lane & 3) ^ ((lane >> 4) & 3)) << 4)
+                          : lrow * ldb * 2 + lchunk * 16;
+
+  auto issue = [&](int buf, int k0) {
+#pragma unroll
+    for (int i = 0; i < IA; ++i) {
+      const int grp = wave + i * NW;  // 8-row group index
+      llvm_amdgcn_raw_buffer_load_lds(
+          ra, (__attribute__((address_space(3))) uint32_t*)(&sA[buf][grp * 8 * BK]), 16,
+          a_off + grp * 8 * lda * 2 + k0 * 2, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < IB; ++i) {
+      const int grp = wave + i * NW;
+      llvm_amdgcn_raw_buffer_load_lds(
+          rb, (__attribute__((address_space(3))) uint32_t*)(&sB[buf][grp * BROWS * BK * BES]), 16,
+          b_off + (grp * BROWS * ldb + k0) * BES, 0, 0, 0);
+    }
+  };
+
+  f32x16 acc[TN][TM];
+#pragma unroll
+  for (int a = 0; a < TN; ++a)
+#pragma unroll
+    for (int b = 0; b < TM; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+  const int l32 = lane & 31, g = lane >> 5;
+  const int KT = K / BK;
+  issue(0, 0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  for (int kt = 0; kt < KT; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < KT) issue(cur ^ 1, (kt + 1) * BK);
+    const bf16_t* tA = sA[cur];
+    const uint8_t* tB = sB[cur];
+    // Fragments of K sub-step kk are read while the MFMAs of kk-1 run; the
+    // scheduling groups interleave one LDS read per MFMA.
+    bf16x8 fw0[TN], fx0[TM], fw1[TN], fx1[TM];
+    auto ldfrag = [&](bf16x8* fw, bf16x8* fx, int kk) {
+#pragma unroll
+      for (int a = 0; a < TN; ++a) {
+        const int row = wn * WN + a * 32 + l32;
+        if (B_FP8) {
+          const u32x2 c8 = *reinterpret_cast<const u32x2*>(&tB[swz8(row, kk, g)]);
+          typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+          const b2 h0 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(c8.x, 1.0f, false);
+          const b2 h1 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(c8.x, 1.0f, true);
+          const b2 h2 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(c8.y, 1.0f, false);
+          const b2 h3 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(c8.y, 1.0f, true);
+          bf16x8 f;
+          f[0] = h0[0]; f[1] = h0[1]; f[2] = h1[0]; f[3] = h1[1];
+          f[4] = h2[0]; f[5] = h2[1]; f[6] = h3[0]; f[7] = h3[1];
+          fw[a] = f;
+        } else {
+          fw[a] = *reinterpret_cast<const bf16x8*>(
+              reinterpret_cast<const bf16_t*>(tB) + swz(row, 2 * kk + g));
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < TM; ++b)
+        fx[b] = *reinterpret_cast<const bf16x8*>(&tA[swz(wm * WM + b * 32 + l32, 2 * kk + g)]);
+    };
+    auto mma = [&](const bf16x8* fw, const bf16x8* fx) {
+#pragma unroll
+      for (int a = 0; a < TN; ++a)
+#pragma unroll
+        for (int b = 0; b < TM; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fw[a], fx[b], acc[a][b], 0, 0, 0);
+    };
+    ldfrag(fw0, fx0, 0);
+    ldfrag(fw1, fx1, 1);
+    mma(fw0, fx0);
+    ldfrag(fw0, fx0, 2);
+    mma(fw1, fx1);
+    ldfrag(fw1, fx1, 3);
+    mma(fw0, fx0);
+    mma(fw1, fx1);
+    // Pipeline: the next tile's loads, the reads of sub-step 0, then each
+    // sub-step's MFMAs with the next sub-step's reads threaded one per MFMA.
+    constexpr int NF = TN + TM, NM = TN * TM;
+    __builtin_amdgcn_sched_group_barrier(0x100, NF, 0);
+#pragma unroll
+    for (int st = 0; st < 3; ++st) {
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      if (NM > NF) __builtin_amdgcn_sched_group_barrier(0x008, NM - NF, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, NM, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int b = 0; b < TM; ++b) {
+    const int m = m0 + wm * WM + b * 32 + l32;
+    if (m >= M) continue;
+#pragma unroll
+    for (int a = 0; a < TN; ++a) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int n = n0 + wn * WN + a * 32 + 8 * q + 4 * g;
+        if (n < N)
+          epi_store4<EPI, OUT_BF16>(e, m, n, acc[a][b][4 * q + 0], acc[a][b][4 * q + 1],
+                                    acc[a][b][4 * q + 2], acc[a][b][4 * q + 3]);
+      }
+    }
+  }
+}
+
+template <int BM, int BN, int WGM, int WGN, bool B_FP8>
+static hipError_t launch_bf16_dl(const bf16_t* A, int lda, const void* B, int ldb, int M,
+                                 int N, int K, int op, const EpiArgs& e, hipStream_t s) {
+  const int gm = (M + BM - 1) / BM, gn = (N + BN - 1) / BN;
+  dim3 grid(gm * gn), block(WGM * WGN * 64);
+#define VL_GEMM_CASE(OP)                                                                     \
+  case OP:                                                                                   \
+    hipLaunchKernelGGL((k_gemm_bf16_dl<BM, BN, WGM, WGN, B_FP8, OP>), grid, block, 0, s, A,  \
+                       lda, B, ldb, M, N, K, gm, gn, e);                                     \
+    break;
+  switch (op) {
+    VL_GEMM_CASE(OP_PATCH)
+    VL_GEMM_CASE(OP_QKV)
+    VL_GEMM_CASE(OP_OPROJ)
+    VL_GEMM_CASE(OP_FC1)
+    VL_GEMM_CASE(OP_FC2)
+    default: return hipErrorInvalidValue;
+  }
+#undef VL_GEMM_CASE
+  return hipGetLastError();
+}
+
+template <int BM, int BN, int WGM, int WGN, bool B_FP8>
+static hipError_t launch_bf16(const bf16_t* A, int lda, const void* B, int ldb, int M, int N,
+                              int K, int op, const EpiArgs& e, hipStream_t s) {
+  dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN);
+  dim3 block(WGM * WGN * 64);
+#define VL_GEMM_CASE(OP)                                                                   \
+  case OP:                                                                                 \
+    hipLaunchKernelGGL((k_gemm_bf16<BM, BN, WGM, WGN, B_FP8, OP>), grid, block, 0, s, A, lda, \
+                       B, ldb, M, N, K, e);                                                \
+    break;
+  switch (op) {
+    VL_GEMM_CASE(OP_PATCH)
+    VL_GEMM_CASE(OP_QKV)
+    VL_GEMM_CASE(OP_OPROJ)
+    VL_GEMM_CASE(OP_FC1)
+    VL_GEMM_CASE(OP_FC2)
+    default: return hipErrorInvalidValue;
+  }
+#undef VL_GEMM_CASE
+  return hipGetLastError();
+}
+
+}  // namespace vl

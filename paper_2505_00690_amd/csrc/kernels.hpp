@@ -48,11 +48,28 @@ struct EpiArgs {
   float alpha = 1.f, beta = 0.f;
 };
 
+// Tile configurations of the BF16 GEMM.  Every configuration accumulates K
+// in the same order (one MFMA per 16 K values, K ascending), so all give
+// bitwise identical results and the choice may depend on the batch size.
+enum GemmCfg {
+  CFG_DL_256x256_W2x4 = 0,
+  CFG_DL_256x256_W4x2 = 1,
+  CFG_DL_256x256_W2x2 = 2,
+  CFG_DL_128x128_W2x2 = 3,
+  CFG_DL_256x128_W2x2 = 4,
+  CFG_DL_128x256_W2x2 = 5,
+  CFG_REG_128x128_W2x2 = 6,
+  N_GEMM_CFGS = 7
+};
+const char* gemm_cfg_name(int cfg);
+// Configuration used when none is tuned for an operation.
+int gemm_cfg_heuristic(int M, int N, int K, bool b_fp8);
+
 // C[M,N] = A[M,K] . B[N,K]^T with BF16 A and BF16 (or e4m3 when b_fp8) B,
 // FP32 accumulation, BF16 output for OP_QKV / OP_FC1.  K % 64 == 0,
-// N % 8 == 0.
+// N % 8 == 0.  cfg < 0 selects the heuristic configuration.
 hipError_t gemm_bf16(const bf16_t* A, int lda, const void* B, int ldb, bool b_fp8,
-                     int M, int N, int K, int op, const EpiArgs& e, hipStream_t s);
+                     int M, int N, int K, int op, int cfg, const EpiArgs& e, hipStream_t s);
 
 // The same contraction in FP32 (FMA), output FP32.  K % 16 == 0, N % 4 == 0.
 hipError_t gemm_f32(const float* A, int lda, const float* B, int ldb, int M, int N,

@@ -21,6 +21,8 @@ __all__ = [
     "vl_abi_version", "vl_weights_count", "vl_model_create", "vl_model_destroy",
     "vl_model_set_option", "vl_encode_workspace_bytes", "vl_encode_images", "vl_score",
     "vl_status_string", "vl_last_error_message", "Encoder", "EXPORTED_SYMBOLS",
+    "vl_gemm_config_count", "vl_gemm_config_name", "vl_model_get_tuning",
+    "vl_model_set_tuning", "vl_model_autotune", "GEMM_OPS",
 ]
 
 VL_FP32, VL_BF16, VL_FP8W_BF16A = 0, 1, 2
@@ -36,7 +38,11 @@ EXPORTED_SYMBOLS = (
     "vl_abi_version", "vl_status_string", "vl_last_error_message", "vl_weights_count",
     "vl_model_create", "vl_model_destroy", "vl_model_set_option",
     "vl_encode_workspace_bytes", "vl_encode_images", "vl_score", "vl_model_op_times",
+    "vl_gemm_config_count", "vl_gemm_config_name", "vl_model_get_tuning",
+    "vl_model_set_tuning", "vl_model_autotune",
 )
+VL_N_GEMM_OPS, VL_N_M_BUCKETS = 5, 25
+GEMM_OPS = ("patch_embed", "qkv_gemm", "oproj_gemm", "fc1_gemm", "fc2_gemm")
 
 
 def library_path() -> str:
@@ -101,6 +107,16 @@ def lib() -> ctypes.CDLL:
     L.vl_model_op_times.restype = ctypes.c_int
     L.vl_model_op_times.argtypes = [_vp, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+    L.vl_gemm_config_count.restype = _i32
+    L.vl_gemm_config_count.argtypes = []
+    L.vl_gemm_config_name.restype = ctypes.c_char_p
+    L.vl_gemm_config_name.argtypes = [_i32]
+    L.vl_model_get_tuning.restype = ctypes.c_int
+    L.vl_model_get_tuning.argtypes = [_vp, _pi32]
+    L.vl_model_set_tuning.restype = ctypes.c_int
+    L.vl_model_set_tuning.argtypes = [_vp, _pi32]
+    L.vl_model_autotune.restype = ctypes.c_int
+    L.vl_model_autotune.argtypes = [_vp, _vp, _pi32, _pi32, _i32, _vp, _vp, _sz, _i32, _vp]
     L.vl_score.restype = ctypes.c_int
     L.vl_score.argtypes = [_vp, _i32, _vp, _i32, _i32, ctypes.c_int, _f32, _f32, _vp, _vp, _vp]
     _LIB = L
@@ -176,6 +192,40 @@ def vl_model_op_times(handle, reset: bool = False):
     return {OP_NAMES[i]: (float(ms[i]), int(n[i])) for i in range(VL_N_OPS)}
 
 
+def vl_gemm_config_count() -> int:
+    return int(lib().vl_gemm_config_count())
+
+
+def vl_gemm_config_name(cfg: int) -> Optional[str]:
+    r = lib().vl_gemm_config_name(int(cfg))
+    return r.decode() if r else None
+
+
+def vl_model_get_tuning(handle):
+    """Tuning table as a list of VL_N_GEMM_OPS rows of VL_N_M_BUCKETS ids."""
+    t = (ctypes.c_int32 * (VL_N_GEMM_OPS * VL_N_M_BUCKETS))()
+    _check(lib().vl_model_get_tuning(handle, t))
+    return [list(t[i * VL_N_M_BUCKETS:(i + 1) * VL_N_M_BUCKETS]) for i in range(VL_N_GEMM_OPS)]
+
+
+def vl_model_set_tuning(handle, table) -> None:
+    flat = [int(v) for row in table for v in row]
+    if len(flat) != VL_N_GEMM_OPS * VL_N_M_BUCKETS:
+        raise ValueError("tuning table has the wrong size")
+    _check(lib().vl_model_set_tuning(handle, (ctypes.c_int32 * len(flat))(*flat)))
+
+
+def vl_model_autotune(handle, pixels: torch.Tensor, heights: Sequence[int],
+                      widths: Sequence[int], emb_out: torch.Tensor, workspace: torch.Tensor,
+                      reps: int = 5, stream=None) -> None:
+    _check(lib().vl_model_autotune(handle, _ptr(pixels, torch.float32, "pixels"),
+                                   _i32_array(heights), _i32_array(widths), len(heights),
+                                   _ptr(emb_out, torch.float32, "emb_out"),
+                                   _ptr(workspace, None, "workspace"),
+                                   workspace.numel() * workspace.element_size(), int(reps),
+                                   _stream(stream)))
+
+
 def vl_encode_workspace_bytes(handle, heights: Sequence[int], widths: Sequence[int]) -> int:
     return int(lib().vl_encode_workspace_bytes(handle, len(heights), _i32_array(heights),
                                                _i32_array(widths)))
@@ -239,6 +289,31 @@ class Encoder:
         if self._ws is None or self._ws.numel() < nbytes:
             self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         return self._ws
+
+    def autotune(self, pixels: torch.Tensor, sizes: Sequence[Tuple[int, int]],
+                 reps: int = 5) -> dict:
+        """Time every GEMM tile configuration on this batch shape and keep
+        the fastest; returns {op: {bucket: config name}} of the table."""
+        n = len(sizes)
+        out = torch.empty((n, self.cfg.proj_dim), dtype=torch.float32, device=self.device)
+        ws = self.workspace(self.workspace_bytes(sizes))
+        vl_model_autotune(self.handle, pixels, [h for h, _ in sizes], [w for _, w in sizes],
+                          out, ws, reps)
+        return self.tuning()
+
+    def tuning(self) -> dict:
+        t = vl_model_get_tuning(self.handle)
+        return {GEMM_OPS[i]: {str(b): vl_gemm_config_name(c) for b, c in enumerate(row) if c >= 0}
+                for i, row in enumerate(t)}
+
+    def set_tuning(self, named: dict) -> None:
+        """Inverse of tuning(): {op: {bucket: config name}}."""
+        ids = {vl_gemm_config_name(i): i for i in range(vl_gemm_config_count())}
+        table = [[-1] * VL_N_M_BUCKETS for _ in range(VL_N_GEMM_OPS)]
+        for op, row in named.items():
+            for b, name in row.items():
+                table[GEMM_OPS.index(op)][int(b)] = ids[name]
+        vl_model_set_tuning(self.handle, table)
 
     def encode(self, pixels: torch.Tensor, sizes: Sequence[Tuple[int, int]],
                out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:

@@ -256,3 +256,31 @@ def test_serving_mix_equals_alone(V):
         emb_mix, top_mix = res.output
         assert torch.equal(emb_mix, alone), res.rid
         assert torch.equal(top_mix, top), res.rid
+
+
+# ------------------------------------------------------------- autotuner
+@pytest.mark.parametrize("precision", ["bf16", "fp8w"])
+def test_every_gemm_config_bitwise_identical_and_autotune(V, precision):
+    """Each GEMM tile configuration, forced for every operation, gives the
+    same bits; the autotuner's choice therefore changes speed only."""
+    enc = V.Encoder(synth.MODELS["b16"], torch.from_numpy(blob("b16", 1001)).cuda(), precision)
+    imgs = synth.make_images([(224, 224)] * 6 + [(336, 336)] * 2, 2500)
+    pix = torch.from_numpy(pack(imgs)).cuda()
+    sizes = sizes_of(imgs)
+    ref = enc.encode(pix, sizes).clone()
+    T = sum(1 + (h // 16) * (w // 16) for h, w in sizes)
+    bucket = T.bit_length() - 1
+    for cfg in range(V.vl_gemm_config_count()):
+        table = [[-1] * V.VL_N_M_BUCKETS for _ in range(V.VL_N_GEMM_OPS)]
+        for op in range(V.VL_N_GEMM_OPS):
+            table[op][bucket] = cfg
+        V.vl_model_set_tuning(enc.handle, table)
+        got = enc.encode(pix, sizes)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), V.vl_gemm_config_name(cfg)
+    tuned = enc.autotune(pix, sizes, reps=2)
+    assert set(tuned) == set(V.GEMM_OPS) and all(str(bucket) in r for r in tuned.values())
+    got = enc.encode(pix, sizes)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    enc.close()
