@@ -122,6 +122,9 @@ def serving_leg(torch, vl, n_requests: int, warmup_requests: int, slots: int,
     pool = {r: [torch.from_numpy(im.reshape(-1)).cuda()
                 for im in synth.make_images([(r, r)] * 32, seeds["images"] + r)]
             for r in wl.resolutions}
+    # tune the GEMM tiles once on a representative batch (32 images, mixed sizes)
+    tsizes = [(r, r) for r in wl.resolutions for _ in range(8)]
+    enc.autotune(torch.cat([pool[h][k % 32] for k, (h, _) in enumerate(tsizes)]), tsizes, reps=2)
     ex = GpuExecutor(enc, texts, wl.head, wl.scale, wl.bias, slots)
     budget = int(budget_gib * 2 ** 30)
     sched = Scheduler(ex, budget, slots=slots, max_batch_images=max_batch_images)
@@ -170,11 +173,15 @@ def main(argv=None) -> int:
                                                              "b16_mixed"])
     ap.add_argument("--precision", default=None, help="fp32 | bf16 | fp8w (default: workload's)")
     ap.add_argument("--no-graphs", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="use the built-in tile heuristic")
     ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the plain FP32 path")
     ap.add_argument("--cpu-sample", type=int, default=None, help="images for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-steps", type=int, default=3)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving (p50/p99) leg")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device-to-device copy of this many MiB first, so "
+                         "a counter run can scale FETCH_SIZE / WRITE_SIZE by a copy of known size")
     ap.add_argument("--serve-requests", type=int, default=1200)
     ap.add_argument("--serve-slots", type=int, default=2)
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
@@ -209,6 +216,16 @@ def main(argv=None) -> int:
     print(f"# inputs generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration_mib > 0:
+        n_el = args.copy_calibration_mib * 2 ** 20 // 4
+        src = torch.ones(n_el, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy calibration: {args.copy_calibration_mib} MiB read + written",
+              file=sys.stderr, flush=True)
+        del src, dst
     w = torch.from_numpy(blob).to(dev)
     pix = torch.from_numpy(np.concatenate([im.reshape(-1) for im in images])).to(dev)
     tx = torch.from_numpy(texts).to(dev)
@@ -219,6 +236,10 @@ def main(argv=None) -> int:
     stream = torch.cuda.current_stream()
 
     enc = vl.Encoder(c, w, prec, graphs=not args.no_graphs)
+    tuned = None
+    if prec != "fp32" and not args.no_autotune:
+        tuned = enc.autotune(pix, sizes, reps=3)
+        print(f"# autotuned GEMM tiles: {tuned}", file=sys.stderr, flush=True)
 
     def step(e):
         e.encode(pix, sizes, out=emb)
@@ -269,7 +290,8 @@ def main(argv=None) -> int:
         "data": "synthetic (seeded U[0,1] pixels, N(0,0.02^2) weights, unit random texts)",
         "config": {"workload": args.workload, "model": wl.model, "batch": n,
                    "resolutions": sorted(set(h for h, _ in sizes)), "precision": prec,
-                   "head": wl.head, "n_texts": wl.n_texts, "graphs": not args.no_graphs},
+                   "head": wl.head, "n_texts": wl.n_texts, "graphs": not args.no_graphs,
+                   "gemm_tiles": tuned},
         "encoder_tflops": total_flops / (ms / 1e3) / 1e12,
         "mfu_bf16": total_flops / (ms / 1e3) / BF16_PEAK,
         "op_ms_per_step": breakdown,

@@ -24,10 +24,14 @@ namespace vl {
 constexpr int ATT_Q = 128;   // queries per workgroup
 constexpr int ATT_KV = 64;   // keys per LDS tile
 
+// sK[key][HD]: 16-B chunks of a row swizzled; for HD = 64 by
+// (key ^ (key >> 3)) & 7, which keeps 8 (or 16) consecutive keys read at one
+// logical chunk on distinct banks; for HD = 32 by key & 3.
 template <int HD>
-__device__ __forceinline__ int k_off(int key, int chunk) {  // sK[key][HD], 16-B chunks swizzled
+__device__ __forceinline__ int k_off(int key, int chunk) {
   constexpr int NC = HD / 8;
-  return key * HD + ((chunk ^ (key & (NC - 1))) << 3);
+  const int f = NC == 8 ? ((key ^ (key >> 3)) & 7) : (key & (NC - 1));
+  return key * HD + ((chunk ^ f) << 3);
 }
 // sVt[d][64 keys]: 16-B chunks of a row swizzled by (d ^ (d >> 3)) & 7, so
 // both the transposing stores (8 rows d = 8c + e at one key) and the
@@ -46,8 +50,10 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
   constexpr int KLOADS = ATT_KV * NCH / 256;   // K chunks per thread
   constexpr int VTHREADS = 32 * NCH;           // threads staging V: key pair x chunk
   static_assert(KLOADS >= 1 && VTHREADS <= 256, "tile / threads");
-  __shared__ __attribute__((aligned(16))) bf16_t sK[2][ATT_KV * HD];
-  __shared__ __attribute__((aligned(16))) bf16_t sVt[2][HD * ATT_KV];
+  // Three-stage K / V ring: while tile kt's softmax and P.V run, tile kt+1
+  // is read for the next scores and tile kt+2 is being staged.
+  __shared__ __attribute__((aligned(16))) bf16_t sK[3][ATT_KV * HD];
+  __shared__ __attribute__((aligned(16))) bf16_t sVt[3][HD * ATT_KV];
 
   const AttnItem it = items[blockIdx.x];
   const int h = blockIdx.y;
@@ -119,28 +125,40 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
 #pragma unroll
     for (int r = 0; r < 16; ++r) o[a][r] = 0.f;
 
+  // S^T blocks of one key tile: s[kb][r] = S[key kb*32 + 8(r/4) + 4g + r%4][query].
+  auto scores = [&](const bf16_t* tK, f32x16* s) {
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s[kb][r] = 0.f;
+#pragma unroll
+      for (int c = 0; c < HD / 16; ++c) {
+        const bf16x8 kf = *reinterpret_cast<const bf16x8*>(&tK[k_off<HD>(kb * 32 + l32, 2 * c + g)]);
+        s[kb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kf, qf[c], s[kb], 0, 0, 0);
+      }
+    }
+  };
+
+  // Software pipeline: the scores of tile kt+1 are issued to the matrix
+  // cores before the softmax of tile kt runs on the vector ALUs (the two are
+  // independent), then P.V of tile kt.
   const int KT = (N + ATT_KV - 1) / ATT_KV;
   load_kv(0);
   store_kv(0);
+  if (KT > 1) {
+    load_kv(ATT_KV);
+    store_kv(1);
+  }
   __syncthreads();
+  f32x16 s_cur[2], s_nxt[2];
+  if (wave_active) scores(sK[0], s_cur);
   for (int kt = 0; kt < KT; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < KT) load_kv((kt + 1) * ATT_KV);
+    const int cur = kt % 3;
+    if (kt + 2 < KT) load_kv((kt + 2) * ATT_KV);
     if (wave_active) {
-      const bf16_t* tK = sK[cur];
+      if (kt + 1 < KT) scores(sK[(kt + 1) % 3], s_nxt);
       const bf16_t* tV = sVt[cur];
-      // S^T blocks: s[kb][r] = S[key kb*32 + 8(r/4) + 4g + r%4][query].
-      f32x16 s[2];
-#pragma unroll
-      for (int kb = 0; kb < 2; ++kb) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) s[kb][r] = 0.f;
-#pragma unroll
-        for (int c = 0; c < HD / 16; ++c) {
-          const bf16x8 kf = *reinterpret_cast<const bf16x8*>(&tK[k_off<HD>(kb * 32 + l32, 2 * c + g)]);
-          s[kb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kf, qf[c], s[kb], 0, 0, 0);
-        }
-      }
+      f32x16* s = s_cur;
       const int kbase = kt * ATT_KV;
       if (kbase + ATT_KV > N) {            // keys past the image: excluded
 #pragma unroll
@@ -197,8 +215,12 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
                                                          0, 0, 0);
         }
       }
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb) s_cur[kb] = s_nxt[kb];
     }
-    if (kt + 1 < KT) store_kv(cur ^ 1);
+    // Stage kt+2 overwrites the buffer of tile kt-1, last read before the
+    // previous barrier.
+    if (kt + 2 < KT) store_kv((kt + 2) % 3);
     __syncthreads();
   }
   if (!wave_active || q >= N) return;

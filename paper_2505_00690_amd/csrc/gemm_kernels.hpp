@@ -110,8 +110,15 @@ __device__ __forceinline__ void epi_store4(const EpiArgs& e, int m, int n, float
 // ------------------------------------------------------------ BF16 MFMA GEMM
 constexpr int BK = 64;  // K step (BF16 elements) per LDS tile
 
+// LDS tile layout: rows of 64 BF16 (128 B); the eight 16-byte chunks of row r
+// are permuted by XOR with f(r) = (r ^ (r >> 3)) & 7.  An MFMA operand read
+// takes one chunk from each of 32 consecutive rows; f makes any 8 consecutive
+// rows hit 8 distinct chunk positions and any 16 consecutive rows hit 16
+// distinct (row parity, chunk) positions, i.e. distinct banks whether the
+// LDS serves 8 lanes over 32 banks or 16 lanes over 64 banks per pass.
+__device__ __forceinline__ int swz_f(int row) { return (row ^ (row >> 3)) & 7; }
 __device__ __forceinline__ int swz(int row, int chunk) {  // element offset in a tile
-  return row * BK + ((chunk ^ (row & 7)) << 3);
+  return row * BK + ((chunk ^ swz_f(row)) << 3);
 }
 
 template <int BM, int BN, int WGM, int WGN, bool B_FP8, int OP>
@@ -263,6 +270,29 @@ extern "C" __device__ void llvm_amdgcn_raw_buffer_load_lds(
     i32x4 rsrc, __attribute__((address_space(3))) uint32_t* lds, int size, int voffset,
     int soffset, int offset, int aux) __asm("llvm.amdgcn.raw.buffer.load.lds");
 
+// One 16-byte-per-lane direct-to-LDS load: lane i's 16 bytes from
+// rsrc + voffset land at LDS byte lds_base + 16 i.  Issued as inline
+// assembly so the compiler's wait-count pass does not treat it as an LDS
+// store and force vmcnt(0) before every later LDS read; the kernels wait for
+// these loads themselves (s_waitcnt vmcnt(n) before their barrier).
+__device__ __forceinline__ void dma16(i32x4 rsrc, const void* lds_base, int voffset) {
+  // C-style cast: generic -> LDS address space (yields the LDS byte offset)
+  const auto* p3 = (const __attribute__((address_space(3))) char*)(lds_base);
+  const uint32_t lds =
+      __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(reinterpret_cast<uintptr_t>(p3)));
+  asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, 0 offen lds"
+               :
+               : "s"(lds), "v"(voffset), "s"(rsrc)
+               : "memory", "m0");
+}
+
+// Workgroup barrier without the compiler's memory fence (which would also
+// wait for every outstanding global load): LDS reads of this wave are
+// drained first, global-to-LDS loads are waited for explicitly by callers.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 __device__ __forceinline__ i32x4 buffer_rsrc(const void* base, uint64_t bytes) {
   const uint64_t p = reinterpret_cast<uint64_t>(base);
   i32x4 r;
@@ -325,28 +355,27 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
   const i32x4 ra = buffer_rsrc(A + (size_t)m0 * lda, (uint64_t)(M - m0) * lda * 2);
   const i32x4 rb = buffer_rsrc(static_cast<const char*>(Bv) + (size_t)n0 * ldb * BES,
                                (uint64_t)(N - n0) * ldb * BES);
-  // Lane's byte offset inside an 8-row group: row l/8, logical chunk (l%8)^(l/8).
+  // Lane's place inside an 8-row group g8: row 8*g8 + l/8, physical chunk
+  // l%8, hence logical chunk (l%8) ^ f(row) = (l%8) ^ (l/8) ^ (g8%8).
   const int lrow = lane >> 3, lchunk = (lane & 7) ^ (lane >> 3);
-  const int a_off = lrow * lda * 2 + lchunk * 16;
+  const int a_off = lrow * lda * 2;
   // e4m3 B: 16-row groups, lane row l/4, physical chunk l%4, logical chunk
   // (l%4) ^ ((l/16)%4).
   const int b_off = B_FP8 ? (lane >> 2) * ldb + (((lane & 3) ^ ((lane >> 4) & 3)) << 4)
-                          : lrow * ldb * 2 + lchunk * 16;
+                          : lrow * ldb * 2;
 
   auto issue = [&](int buf, int k0) {
 #pragma unroll
     for (int i = 0; i < IA; ++i) {
       const int grp = wave + i * NW;  // 8-row group index
-      llvm_amdgcn_raw_buffer_load_lds(
-          ra, (__attribute__((address_space(3))) uint32_t*)(&sA[buf][grp * 8 * BK]), 16,
-          a_off + grp * 8 * lda * 2 + k0 * 2, 0, 0, 0);
+      dma16(ra, &sA[buf][grp * 8 * BK],
+            a_off + grp * 8 * lda * 2 + k0 * 2 + ((lchunk ^ (grp & 7)) << 4));
     }
 #pragma unroll
     for (int i = 0; i < IB; ++i) {
       const int grp = wave + i * NW;
-      llvm_amdgcn_raw_buffer_load_lds(
-          rb, (__attribute__((address_space(3))) uint32_t*)(&sB[buf][grp * BROWS * BK * BES]), 16,
-          b_off + (grp * BROWS * ldb + k0) * BES, 0, 0, 0);
+      dma16(rb, &sB[buf][grp * BROWS * BK * BES],
+            b_off + (grp * BROWS * ldb + k0) * BES + (B_FP8 ? 0 : ((lchunk ^ (grp & 7)) << 4)));
     }
   };
 
@@ -362,7 +391,7 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
   const int KT = K / BK;
   issue(0, 0);
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
+  lds_barrier();
   for (int kt = 0; kt < KT; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < KT) issue(cur ^ 1, (kt + 1) * BK);
@@ -425,7 +454,7 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
     }
     __builtin_amdgcn_sched_group_barrier(0x008, NM, 0);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
+    lds_barrier();
   }
 
 #pragma unroll
@@ -443,6 +472,175 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
       }
     }
   }
+}
+
+// ------------------------------- BF16 MFMA GEMM, 4-stage direct-to-LDS ring
+// BF16 weights only.  K advances in tiles of 32 through a ring of STAGES LDS
+// buffers; the loads of tile kt + STAGES - 1 are issued before the MFMAs of
+// tile kt, so global latency is covered by STAGES - 1 tiles of compute, and
+// a single barrier per tile both publishes the next tile and retires the
+// buffer the next issue overwrites.  LDS rows are 32 BF16 (64 B): the four
+// 16-byte chunks of row r are XOR-permuted by (r >> 2) & 3, which puts 16
+// consecutive rows read at one logical chunk on 16 distinct 16-byte bank
+// groups.  One load instruction fills 16 rows; lane l takes row l/4 of the
+// group and physical chunk l%4, i.e. logical chunk (l%4) ^ ((l/16)%4).
+constexpr int PBK = 32;
+
+__device__ __forceinline__ int pswz(int row, int chunk) {  // element offset
+  return row * PBK + ((chunk ^ ((row >> 2) & 3)) << 3);
+}
+
+template <int BM, int BN, int WGM, int WGN, int STAGES, int OP>
+__global__ __launch_bounds__(WGM* WGN * 64)
+__attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_bf16_pipe(
+    const bf16_t* __restrict__ A, int lda, const bf16_t* __restrict__ B, int ldb, int M, int N,
+    int K, int gm, int gn, EpiArgs e) {
+  constexpr int EPI = OpEpi<OP>::kind;
+  constexpr bool OUT_BF16 = OP == OP_QKV || OP == OP_FC1;
+  constexpr int NW = WGM * WGN;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int TM = WM / 32, TN = WN / 32;
+  constexpr int IA = BM / 16 / NW, IB = BN / 16 / NW;  // load instructions per wave per tile
+  static_assert(IA * NW * 16 == BM && IB * NW * 16 == BN, "tile rows / waves");
+
+  __shared__ __attribute__((aligned(1024))) bf16_t sA[STAGES][BM * PBK];
+  __shared__ __attribute__((aligned(1024))) bf16_t sB[STAGES][BN * PBK];
+
+  int tm_, tn_;
+  xcd_tile(gm, gn, 8, &tm_, &tn_);
+  const int m0 = tm_ * BM, n0 = tn_ * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+
+  const i32x4 ra = buffer_rsrc(A + (size_t)m0 * lda, (uint64_t)(M - m0) * lda * 2);
+  const i32x4 rb = buffer_rsrc(B + (size_t)n0 * ldb, (uint64_t)(N - n0) * ldb * 2);
+  const int lchunk = (lane & 3) ^ ((lane >> 4) & 3);
+  const int a_off = (lane >> 2) * lda * 2 + lchunk * 16;
+  const int b_off = (lane >> 2) * ldb * 2 + lchunk * 16;
+
+  auto issue = [&](int buf, int k0) {
+#pragma unroll
+    for (int i = 0; i < IA; ++i) {
+      const int grp = wave + i * NW;  // 16-row group index
+      dma16(ra, &sA[buf][grp * 16 * PBK], a_off + grp * 16 * lda * 2 + k0 * 2);
+    }
+#pragma unroll
+    for (int i = 0; i < IB; ++i) {
+      const int grp = wave + i * NW;
+      dma16(rb, &sB[buf][grp * 16 * PBK], b_off + grp * 16 * ldb * 2 + k0 * 2);
+    }
+  };
+
+  f32x16 acc[TN][TM];
+#pragma unroll
+  for (int a = 0; a < TN; ++a)
+#pragma unroll
+    for (int b = 0; b < TM; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+  const int l32 = lane & 31, g = lane >> 5;
+  const int KT = K / PBK;
+  // Prologue: STAGES - 1 tiles in flight.
+#pragma unroll
+  for (int st = 0; st < STAGES - 1; ++st)
+    if (st < KT) issue(st, st * PBK);
+  // Tile 0 complete: at most (STAGES - 2) tiles of this wave's loads pending.
+  if (KT >= STAGES - 1) {
+    if constexpr (STAGES == 4) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * (IA + IB)) : "memory");
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  } else {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  }
+  lds_barrier();
+  for (int kt = 0; kt < KT; ++kt) {
+    const int cur = kt % STAGES;
+    const bool more = kt + STAGES - 1 < KT;
+    if (more) issue((kt + STAGES - 1) % STAGES, (kt + STAGES - 1) * PBK);
+    const bf16_t* tA = sA[cur];
+    const bf16_t* tB = sB[cur];
+    bf16x8 fw0[TN], fx0[TM], fw1[TN], fx1[TM];
+#pragma unroll
+    for (int a = 0; a < TN; ++a)
+      fw0[a] = *reinterpret_cast<const bf16x8*>(&tB[pswz(wn * WN + a * 32 + l32, g)]);
+#pragma unroll
+    for (int b = 0; b < TM; ++b)
+      fx0[b] = *reinterpret_cast<const bf16x8*>(&tA[pswz(wm * WM + b * 32 + l32, g)]);
+#pragma unroll
+    for (int a = 0; a < TN; ++a)
+      fw1[a] = *reinterpret_cast<const bf16x8*>(&tB[pswz(wn * WN + a * 32 + l32, 2 + g)]);
+#pragma unroll
+    for (int b = 0; b < TM; ++b)
+      fx1[b] = *reinterpret_cast<const bf16x8*>(&tA[pswz(wm * WM + b * 32 + l32, 2 + g)]);
+#pragma unroll
+    for (int a = 0; a < TN; ++a)
+#pragma unroll
+      for (int b = 0; b < TM; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fw0[a], fx0[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < TN; ++a)
+#pragma unroll
+      for (int b = 0; b < TM; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fw1[a], fx1[b], acc[a][b], 0, 0, 0);
+    constexpr int NF = TN + TM, NM = TN * TM;
+    __builtin_amdgcn_sched_group_barrier(0x100, NF, 0);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+    if (NM > NF) __builtin_amdgcn_sched_group_barrier(0x008, NM - NF, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, NM, 0);
+    // Tile kt+1 must be complete; younger tiles may stay in flight.
+    if (more) {
+      if constexpr (STAGES == 4) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * (IA + IB)) : "memory");
+      else if constexpr (STAGES == 3) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(IA + IB) : "memory");
+      else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    } else {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+    lds_barrier();
+  }
+
+#pragma unroll
+  for (int b = 0; b < TM; ++b) {
+    const int m = m0 + wm * WM + b * 32 + l32;
+    if (m >= M) continue;
+#pragma unroll
+    for (int a = 0; a < TN; ++a) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int n = n0 + wn * WN + a * 32 + 8 * q + 4 * g;
+        if (n < N)
+          epi_store4<EPI, OUT_BF16>(e, m, n, acc[a][b][4 * q + 0], acc[a][b][4 * q + 1],
+                                    acc[a][b][4 * q + 2], acc[a][b][4 * q + 3]);
+      }
+    }
+  }
+}
+
+template <int BM, int BN, int WGM, int WGN, int STAGES>
+static hipError_t launch_bf16_pipe(const bf16_t* A, int lda, const void* B, int ldb, int M,
+                                   int N, int K, int op, const EpiArgs& e, hipStream_t s) {
+  if (K % PBK) return hipErrorInvalidValue;
+  const int gm = (M + BM - 1) / BM, gn = (N + BN - 1) / BN;
+  dim3 grid(gm * gn), block(WGM * WGN * 64);
+  const bf16_t* Bb = static_cast<const bf16_t*>(B);
+#define VL_GEMM_CASE(OP)                                                                       \
+  case OP:                                                                                     \
+    hipLaunchKernelGGL((k_gemm_bf16_pipe<BM, BN, WGM, WGN, STAGES, OP>), grid, block, 0, s, A, \
+                       lda, Bb, ldb, M, N, K, gm, gn, e);                                      \
+    break;
+  switch (op) {
+    VL_GEMM_CASE(OP_PATCH)
+    VL_GEMM_CASE(OP_QKV)
+    VL_GEMM_CASE(OP_OPROJ)
+    VL_GEMM_CASE(OP_FC1)
+    VL_GEMM_CASE(OP_FC2)
+    default: return hipErrorInvalidValue;
+  }
+#undef VL_GEMM_CASE
+  return hipGetLastError();
 }
 
 template <int BM, int BN, int WGM, int WGN, bool B_FP8>
