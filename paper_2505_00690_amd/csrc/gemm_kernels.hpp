@@ -94,7 +94,7 @@ __device__ __forceinline__ void epi_store4(const EpiArgs& e, int m, int n, float
   }
   if (EPI == EPI_BIAS_GELU) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = gelu_erf(v[j]);
+    for (int j = 0; j < 4; ++j) v[j] = OUT_BF16 ? gelu_as7126(v[j]) : gelu_erf(v[j]);
   }
   if (OUT_BF16) {
     u32x2 pk;
@@ -389,72 +389,93 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
 
   const int l32 = lane & 31, g = lane >> 5;
   const int KT = K / BK;
+  // Fragments of K sub-step kk (16 K values) of the current tile.  Each
+  // fragment row's byte offset in a tile buffer is precomputed with the
+  // swizzle and the lane's half g folded in: BF16 chunk (2kk + g) ^ f(row)
+  // of a 128-byte row is (offset ^ (kk << 5)); e4m3 chunk kk ^ f8(row) of a
+  // 64-byte row is (offset ^ (kk << 4)).
+  int offA[TM], offB[TN];
+#pragma unroll
+  for (int b = 0; b < TM; ++b) {
+    const int row = wm * WM + b * 32 + l32;
+    offA[b] = row * (BK * 2) + ((g ^ swz_f(row)) << 4);
+  }
+#pragma unroll
+  for (int a = 0; a < TN; ++a) {
+    const int row = wn * WN + a * 32 + l32;
+    offB[a] = B_FP8 ? row * BK + (((row >> 2) & 3) << 4) + (g << 3)
+                    : row * (BK * 2) + ((g ^ swz_f(row)) << 4);
+  }
+  bf16x8 fw0[TN], fx0[TM], fw1[TN], fx1[TM];
+  auto ldfrag = [&](bf16x8* fw, bf16x8* fx, int buf, int kk) {
+    const char* tA = reinterpret_cast<const char*>(sA[buf]);
+    const char* tB = reinterpret_cast<const char*>(sB[buf]);
+#pragma unroll
+    for (int a = 0; a < TN; ++a) {
+      if (B_FP8) {
+        const u32x2 c8 = *reinterpret_cast<const u32x2*>(tB + (offB[a] ^ (kk << 4)));
+        typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+        const b2 h0 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(c8.x, 1.0f, false);
+        const b2 h1 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(c8.x, 1.0f, true);
+        const b2 h2 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(c8.y, 1.0f, false);
+        const b2 h3 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(c8.y, 1.0f, true);
+        bf16x8 f;
+        f[0] = h0[0]; f[1] = h0[1]; f[2] = h1[0]; f[3] = h1[1];
+        f[4] = h2[0]; f[5] = h2[1]; f[6] = h3[0]; f[7] = h3[1];
+        fw[a] = f;
+      } else {
+        fw[a] = *reinterpret_cast<const bf16x8*>(tB + (offB[a] ^ (kk << 5)));
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < TM; ++b)
+      fx[b] = *reinterpret_cast<const bf16x8*>(tA + (offA[b] ^ (kk << 5)));
+  };
+  auto mma = [&](const bf16x8* fw, const bf16x8* fx) {
+#pragma unroll
+    for (int a = 0; a < TN; ++a)
+#pragma unroll
+      for (int b = 0; b < TM; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fw[a], fx[b], acc[a][b], 0, 0, 0);
+  };
+  // One MFMA, one LDS read, ... then the remaining MFMAs.
+  constexpr int NF = TN + TM, NM = TN * TM;
+  auto interleave = [&]() {
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+    if (NM > NF) __builtin_amdgcn_sched_group_barrier(0x008, NM - NF, 0);
+  };
+
+  // Pipeline across tiles: the last sub-step's MFMAs of tile kt run after the
+  // barrier, overlapping the first LDS reads of tile kt+1, so the matrix
+  // cores do not drain at every barrier.
   issue(0, 0);
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   lds_barrier();
+  ldfrag(fw0, fx0, 0, 0);
   for (int kt = 0; kt < KT; ++kt) {
     const int cur = kt & 1;
-    if (kt + 1 < KT) issue(cur ^ 1, (kt + 1) * BK);
-    const bf16_t* tA = sA[cur];
-    const uint8_t* tB = sB[cur];
-    // Fragments of K sub-step kk are read while the MFMAs of kk-1 run; the
-    // scheduling groups interleave one LDS read per MFMA.
-    bf16x8 fw0[TN], fx0[TM], fw1[TN], fx1[TM];
-    auto ldfrag = [&](bf16x8* fw, bf16x8* fx, int kk) {
-#pragma unroll
-      for (int a = 0; a < TN; ++a) {
-        const int row = wn * WN + a * 32 + l32;
-        if (B_FP8) {
-          const u32x2 c8 = *reinterpret_cast<const u32x2*>(&tB[swz8(row, kk, g)]);
-          typedef __bf16 b2 __attribute__((ext_vector_type(2)));
-          const b2 h0 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(c8.x, 1.0f, false);
-          const b2 h1 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(c8.x, 1.0f, true);
-          const b2 h2 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(c8.y, 1.0f, false);
-          const b2 h3 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(c8.y, 1.0f, true);
-          bf16x8 f;
-          f[0] = h0[0]; f[1] = h0[1]; f[2] = h1[0]; f[3] = h1[1];
-          f[4] = h2[0]; f[5] = h2[1]; f[6] = h3[0]; f[7] = h3[1];
-          fw[a] = f;
-        } else {
-          fw[a] = *reinterpret_cast<const bf16x8*>(
-              reinterpret_cast<const bf16_t*>(tB) + swz(row, 2 * kk + g));
-        }
-      }
-#pragma unroll
-      for (int b = 0; b < TM; ++b)
-        fx[b] = *reinterpret_cast<const bf16x8*>(&tA[swz(wm * WM + b * 32 + l32, 2 * kk + g)]);
-    };
-    auto mma = [&](const bf16x8* fw, const bf16x8* fx) {
-#pragma unroll
-      for (int a = 0; a < TN; ++a)
-#pragma unroll
-        for (int b = 0; b < TM; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fw[a], fx[b], acc[a][b], 0, 0, 0);
-    };
-    ldfrag(fw0, fx0, 0);
-    ldfrag(fw1, fx1, 1);
+    const bool more = kt + 1 < KT;
+    if (more) issue(cur ^ 1, (kt + 1) * BK);
+    ldfrag(fw1, fx1, cur, 1);
     mma(fw0, fx0);
-    ldfrag(fw0, fx0, 2);
+    interleave();
+    ldfrag(fw0, fx0, cur, 2);
     mma(fw1, fx1);
-    ldfrag(fw1, fx1, 3);
+    interleave();
+    ldfrag(fw1, fx1, cur, 3);
     mma(fw0, fx0);
-    mma(fw1, fx1);
-    // Pipeline: the next tile's loads, the reads of sub-step 0, then each
-    // sub-step's MFMAs with the next sub-step's reads threaded one per MFMA.
-    constexpr int NF = TN + TM, NM = TN * TM;
-    __builtin_amdgcn_sched_group_barrier(0x100, NF, 0);
-#pragma unroll
-    for (int st = 0; st < 3; ++st) {
-#pragma unroll
-      for (int i = 0; i < NF; ++i) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-      }
-      if (NM > NF) __builtin_amdgcn_sched_group_barrier(0x008, NM - NF, 0);
-    }
-    __builtin_amdgcn_sched_group_barrier(0x008, NM, 0);
+    interleave();
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     lds_barrier();
+    // (On the last tile these reads fetch stale fragments that are never
+    // used; reading unconditionally keeps the accumulators out of a branch.)
+    ldfrag(fw0, fx0, cur ^ 1, 0);
+    mma(fw1, fx1);
+    interleave();
   }
 
 #pragma unroll
