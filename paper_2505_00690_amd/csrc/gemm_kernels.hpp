@@ -42,11 +42,10 @@ __device__ __forceinline__ void epi_store4(const EpiArgs& e, int m, int n, float
         make_float4(v[0], v[1], v[2], v[3]);
     return;
   }
-  if (e.wscale) {
-    const float4 ws = *reinterpret_cast<const float4*>(e.wscale + n);
-    v[0] *= ws.x; v[1] *= ws.y; v[2] *= ws.z; v[3] *= ws.w;
-  }
+  float4 ws = make_float4(1.f, 1.f, 1.f, 1.f);
+  if (e.wscale) ws = *reinterpret_cast<const float4*>(e.wscale + n);
   if (EPI == EPI_PATCH) {
+    v[0] *= ws.x; v[1] *= ws.y; v[2] *= ws.z; v[3] *= ws.w;
     const int2 ti = e.tok_info[m];
     float* X = static_cast<float*>(e.out) + (size_t)m * e.ldo + n;
     float4 add;
@@ -83,8 +82,12 @@ __device__ __forceinline__ void epi_store4(const EpiArgs& e, int m, int n, float
                                                 v[3] + add.w);
     return;
   }
+  // acc * weight scale + bias as one fused operation (scale 1 without
+  // per-row weight scales); the staged epilogue of the direct-to-LDS kernel
+  // does the same, so every configuration agrees bitwise.
   const float4 b = *reinterpret_cast<const float4*>(e.bias + n);
-  v[0] += b.x; v[1] += b.y; v[2] += b.z; v[3] += b.w;
+  v[0] = __builtin_fmaf(v[0], ws.x, b.x); v[1] = __builtin_fmaf(v[1], ws.y, b.y);
+  v[2] = __builtin_fmaf(v[2], ws.z, b.z); v[3] = __builtin_fmaf(v[3], ws.w, b.w);
   if (EPI == EPI_BIAS_RESID) {
     float4* X = reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n);
     float4 x = *X;
@@ -270,19 +273,24 @@ extern "C" __device__ void llvm_amdgcn_raw_buffer_load_lds(
     i32x4 rsrc, __attribute__((address_space(3))) uint32_t* lds, int size, int voffset,
     int soffset, int offset, int aux) __asm("llvm.amdgcn.raw.buffer.load.lds");
 
+// LDS byte offset of a __shared__ object.  A generic pointer into LDS is the
+// shared aperture base (high 32 bits) plus the LDS offset (low 32 bits), so
+// truncation yields the offset without the null check an address-space cast
+// would add.
+__device__ __forceinline__ uint32_t lds_offset(const void* p) {
+  return static_cast<uint32_t>(reinterpret_cast<uintptr_t>(p));
+}
+
 // One 16-byte-per-lane direct-to-LDS load: lane i's 16 bytes from
-// rsrc + voffset land at LDS byte lds_base + 16 i.  Issued as inline
-// assembly so the compiler's wait-count pass does not treat it as an LDS
-// store and force vmcnt(0) before every later LDS read; the kernels wait for
-// these loads themselves (s_waitcnt vmcnt(n) before their barrier).
-__device__ __forceinline__ void dma16(i32x4 rsrc, const void* lds_base, int voffset) {
-  // C-style cast: generic -> LDS address space (yields the LDS byte offset)
-  const auto* p3 = (const __attribute__((address_space(3))) char*)(lds_base);
-  const uint32_t lds =
-      __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(reinterpret_cast<uintptr_t>(p3)));
-  asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, 0 offen lds"
+// rsrc + voffset + soffset land at LDS byte lds + 16 i (lds and soffset
+// wave-uniform).  Issued as inline assembly so the compiler's wait-count pass
+// does not treat it as an LDS store and force vmcnt(0) before every later LDS
+// read; the kernels wait for these loads themselves (s_waitcnt vmcnt(n)
+// before their barrier).
+__device__ __forceinline__ void dma16(i32x4 rsrc, uint32_t lds, int voffset, int soffset) {
+  asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, %3 offen lds"
                :
-               : "s"(lds), "v"(voffset), "s"(rsrc)
+               : "s"(lds), "v"(voffset), "s"(rsrc), "s"(soffset)
                : "memory", "m0");
 }
 
@@ -328,7 +336,7 @@ __device__ __forceinline__ int swz8(int row, int kk, int g) {  // byte offset in
   return row * BK + ((kk ^ ((row >> 2) & 3)) << 4) + (g << 3);
 }
 
-template <int BM, int BN, int WGM, int WGN, bool B_FP8, int OP>
+template <int BM, int BN, int WGM, int WGN, bool B_FP8, int OP, int RPM>
 __global__ __launch_bounds__(WGM* WGN * 64)
 __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_bf16_dl(
     const bf16_t* __restrict__ A, int lda, const void* __restrict__ Bv, int ldb, int M, int N,
@@ -343,13 +351,19 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
   static_assert(IA * NW * 8 == BM && IB * NW * BROWS == BN, "tile rows / waves");
   constexpr int BES = B_FP8 ? 1 : 2;                    // bytes per B element
 
-  __shared__ __attribute__((aligned(1024))) bf16_t sA[2][BM * BK];
-  __shared__ __attribute__((aligned(1024))) uint8_t sB[2][BN * BK * BES];
+  // One LDS arena: double-buffered operand tiles during the K loop, then
+  // per-wave epilogue staging slabs (32 rows x WN FP32 each).
+  constexpr int LDS_AB = 2 * BM * BK * 2 + 2 * BN * BK * BES;
+  constexpr int LDS_EPI = NW * 32 * WN * 4;
+  __shared__ __attribute__((aligned(1024))) char smem[LDS_AB > LDS_EPI ? LDS_AB : LDS_EPI];
+  bf16_t(*sA)[BM * BK] = reinterpret_cast<bf16_t(*)[BM * BK]>(smem);
+  uint8_t(*sB)[BN * BK * BES] = reinterpret_cast<uint8_t(*)[BN * BK * BES]>(smem + 2 * BM * BK * 2);
 
   int tm_, tn_;
   xcd_tile(gm, gn, 8, &tm_, &tn_);
   const int m0 = tm_ * BM, n0 = tn_ * BN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WGN, wn = wave % WGN;
 
   const i32x4 ra = buffer_rsrc(A + (size_t)m0 * lda, (uint64_t)(M - m0) * lda * 2);
@@ -364,18 +378,20 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
   const int b_off = B_FP8 ? (lane >> 2) * ldb + (((lane & 3) ^ ((lane >> 4) & 3)) << 4)
                           : lrow * ldb * 2;
 
+  const uint32_t ldsA = lds_offset(&sA[0][0]), ldsB = lds_offset(&sB[0][0]);
   auto issue = [&](int buf, int k0) {
 #pragma unroll
     for (int i = 0; i < IA; ++i) {
       const int grp = wave + i * NW;  // 8-row group index
-      dma16(ra, &sA[buf][grp * 8 * BK],
-            a_off + grp * 8 * lda * 2 + k0 * 2 + ((lchunk ^ (grp & 7)) << 4));
+      dma16(ra, ldsA + (buf * BM * BK + grp * 8 * BK) * 2,
+            a_off + grp * 8 * lda * 2 + ((lchunk ^ (grp & 7)) << 4), k0 * 2);
     }
 #pragma unroll
     for (int i = 0; i < IB; ++i) {
       const int grp = wave + i * NW;
-      dma16(rb, &sB[buf][grp * BROWS * BK * BES],
-            b_off + (grp * BROWS * ldb + k0) * BES + (B_FP8 ? 0 : ((lchunk ^ (grp & 7)) << 4)));
+      dma16(rb, ldsB + (buf * BN * BK + grp * BROWS * BK) * BES,
+            b_off + grp * BROWS * ldb * BES + (B_FP8 ? 0 : ((lchunk ^ (grp & 7)) << 4)),
+            k0 * BES);
     }
   };
 
@@ -438,15 +454,18 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
       for (int b = 0; b < TM; ++b)
         acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fw[a], fx[b], acc[a][b], 0, 0, 0);
   };
-  // One MFMA, one LDS read, ... then the remaining MFMAs.
+  // One MFMA, RPM LDS reads, ... then the remaining MFMAs: all of the next
+  // sub-step's reads are in flight early in the current one.
   constexpr int NF = TN + TM, NM = TN * TM;
+  static_assert(NF % RPM == 0, "reads per MFMA must divide the fragment count");
+  constexpr int NG = NF / RPM;  // MFMAs that carry reads
   auto interleave = [&]() {
 #pragma unroll
-    for (int i = 0; i < NF; ++i) {
+    for (int i = 0; i < NG; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, RPM, 0);
     }
-    if (NM > NF) __builtin_amdgcn_sched_group_barrier(0x008, NM - NF, 0);
+    if (NM > NG) __builtin_amdgcn_sched_group_barrier(0x008, NM - NG, 0);
   };
 
   // Pipeline across tiles: the last sub-step's MFMAs of tile kt run after the
@@ -478,201 +497,98 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
     interleave();
   }
 
+  // Epilogue.  The accumulator layout gives each lane one row and 4-column
+  // groups spread over the wave tile, so direct stores would touch 32 rows
+  // per instruction.  Instead each 32-row slab of the wave's tile goes
+  // through a wave-private LDS slab (row r's 16-byte chunks XOR-permuted by
+  // r & 15: the 16 lanes of one LDS pass hit 16 distinct chunk positions
+  // both when writing a column of rows and when reading along a row) and is
+  // read back row-major: consecutive lanes own consecutive 16-byte column
+  // chunks, so bias / residual loads and output stores are full-line
+  // accesses, and each lane's columns (hence its bias) stay fixed.
+  lds_barrier();  // all waves are done with the operand tiles
+  constexpr int CPR = WN / 4;    // 16-byte FP32 chunks per staged row
+  static_assert(CPR >= 16 && 64 % CPR == 0, "staging layout needs WN in {64, 128}");
+  constexpr int RPP = 64 / CPR;  // rows per read-back pass
+  constexpr int NP = 32 / RPP;   // passes per slab
+  constexpr int NB = NP < 8 ? NP : 8;  // passes per batch of global loads
+  float* stage = reinterpret_cast<float*>(smem) + wave * 32 * WN;
+  const int rc = lane % CPR, rr = lane / CPR;
+  const int n = n0 + wn * WN + 4 * rc;
+  const bool n_ok = n < N;
+  float4 bias4 = make_float4(0.f, 0.f, 0.f, 0.f), ws4 = make_float4(1.f, 1.f, 1.f, 1.f);
+  if (EPI != EPI_PATCH && n_ok) {
+    bias4 = *reinterpret_cast<const float4*>(e.bias + n);
+    if (e.wscale) ws4 = *reinterpret_cast<const float4*>(e.wscale + n);
+  }
 #pragma unroll
   for (int b = 0; b < TM; ++b) {
-    const int m = m0 + wm * WM + b * 32 + l32;
-    if (m >= M) continue;
 #pragma unroll
-    for (int a = 0; a < TN; ++a) {
+    for (int a = 0; a < TN; ++a)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int n = n0 + wn * WN + a * 32 + 8 * q + 4 * g;
-        if (n < N)
-          epi_store4<EPI, OUT_BF16>(e, m, n, acc[a][b][4 * q + 0], acc[a][b][4 * q + 1],
-                                    acc[a][b][4 * q + 2], acc[a][b][4 * q + 3]);
+        const int c = a * 8 + 2 * q + g;  // columns a*32 + 8q + 4g .. +3
+        *reinterpret_cast<float4*>(stage + l32 * WN + ((c ^ (l32 & 15)) << 2)) =
+            make_float4(acc[a][b][4 * q + 0], acc[a][b][4 * q + 1], acc[a][b][4 * q + 2],
+                        acc[a][b][4 * q + 3]);
+      }
+    const int mb = m0 + wm * WM + b * 32 + rr;
+#pragma unroll
+    for (int p0 = 0; p0 < NP; p0 += NB) {
+      float4 v[NB], x[NB];
+#pragma unroll
+      for (int p = 0; p < NB; ++p) {
+        const int row = (p0 + p) * RPP + rr;
+        v[p] = *reinterpret_cast<const float4*>(stage + row * WN + ((rc ^ (row & 15)) << 2));
+      }
+      if (EPI == EPI_BIAS_RESID) {
+#pragma unroll
+        for (int p = 0; p < NB; ++p) {
+          const int m = mb + (p0 + p) * RPP;
+          if (m < M && n_ok)
+            x[p] = *reinterpret_cast<const float4*>(static_cast<const float*>(e.out) +
+                                                    (size_t)m * e.ldo + n);
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < NB; ++p) {
+        const int m = mb + (p0 + p) * RPP;
+        if (m >= M || !n_ok) continue;
+        if (EPI == EPI_PATCH) {
+          epi_store4<EPI, OUT_BF16>(e, m, n, v[p].x, v[p].y, v[p].z, v[p].w);
+          continue;
+        }
+        float4 y = make_float4(__builtin_fmaf(v[p].x, ws4.x, bias4.x),
+                               __builtin_fmaf(v[p].y, ws4.y, bias4.y),
+                               __builtin_fmaf(v[p].z, ws4.z, bias4.z),
+                               __builtin_fmaf(v[p].w, ws4.w, bias4.w));
+        if (EPI == EPI_BIAS_RESID) {
+          *reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n) =
+              make_float4(x[p].x + y.x, x[p].y + y.y, x[p].z + y.z, x[p].w + y.w);
+          continue;
+        }
+        if (EPI == EPI_BIAS_GELU) {
+          y.x = gelu_as7126(y.x); y.y = gelu_as7126(y.y);
+          y.z = gelu_as7126(y.z); y.w = gelu_as7126(y.w);
+        }
+        u32x2 pk;
+        pk.x = pack_bf16x2(y.x, y.y);
+        pk.y = pack_bf16x2(y.z, y.w);
+        *reinterpret_cast<u32x2*>(static_cast<bf16_t*>(e.out) + (size_t)m * e.ldo + n) = pk;
       }
     }
   }
 }
 
-// ------------------------------- BF16 MFMA GEMM, 4-stage direct-to-LDS ring
-// BF16 weights only.  K advances in tiles of 32 through a ring of STAGES LDS
-// buffers; the loads of tile kt + STAGES - 1 are issued before the MFMAs of
-// tile kt, so global latency is covered by STAGES - 1 tiles of compute, and
-// a single barrier per tile both publishes the next tile and retires the
-// buffer the next issue overwrites.  LDS rows are 32 BF16 (64 B): the four
-// 16-byte chunks of row r are XOR-permuted by (r >> 2) & 3, which puts 16
-// consecutive rows read at one logical chunk on 16 distinct 16-byte bank
-// groups.  One load instruction fills 16 rows; lane l takes row l/4 of the
-// group and physical chunk l%4, i.e. logical chunk (l%4) ^ ((l/16)%4).
-constexpr int PBK = 32;
-
-__device__ __forceinline__ int pswz(int row, int chunk) {  // element offset
-  return row * PBK + ((chunk ^ ((row >> 2) & 3)) << 3);
-}
-
-template <int BM, int BN, int WGM, int WGN, int STAGES, int OP>
-__global__ __launch_bounds__(WGM* WGN * 64)
-__attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_bf16_pipe(
-    const bf16_t* __restrict__ A, int lda, const bf16_t* __restrict__ B, int ldb, int M, int N,
-    int K, int gm, int gn, EpiArgs e) {
-  constexpr int EPI = OpEpi<OP>::kind;
-  constexpr bool OUT_BF16 = OP == OP_QKV || OP == OP_FC1;
-  constexpr int NW = WGM * WGN;
-  constexpr int WM = BM / WGM, WN = BN / WGN;
-  constexpr int TM = WM / 32, TN = WN / 32;
-  constexpr int IA = BM / 16 / NW, IB = BN / 16 / NW;  // load instructions per wave per tile
-  static_assert(IA * NW * 16 == BM && IB * NW * 16 == BN, "tile rows / waves");
-
-  __shared__ __attribute__((aligned(1024))) bf16_t sA[STAGES][BM * PBK];
-  __shared__ __attribute__((aligned(1024))) bf16_t sB[STAGES][BN * PBK];
-
-  int tm_, tn_;
-  xcd_tile(gm, gn, 8, &tm_, &tn_);
-  const int m0 = tm_ * BM, n0 = tn_ * BN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave / WGN, wn = wave % WGN;
-
-  const i32x4 ra = buffer_rsrc(A + (size_t)m0 * lda, (uint64_t)(M - m0) * lda * 2);
-  const i32x4 rb = buffer_rsrc(B + (size_t)n0 * ldb, (uint64_t)(N - n0) * ldb * 2);
-  const int lchunk = (lane & 3) ^ ((lane >> 4) & 3);
-  const int a_off = (lane >> 2) * lda * 2 + lchunk * 16;
-  const int b_off = (lane >> 2) * ldb * 2 + lchunk * 16;
-
-  auto issue = [&](int buf, int k0) {
-#pragma unroll
-    for (int i = 0; i < IA; ++i) {
-      const int grp = wave + i * NW;  // 16-row group index
-      dma16(ra, &sA[buf][grp * 16 * PBK], a_off + grp * 16 * lda * 2 + k0 * 2);
-    }
-#pragma unroll
-    for (int i = 0; i < IB; ++i) {
-      const int grp = wave + i * NW;
-      dma16(rb, &sB[buf][grp * 16 * PBK], b_off + grp * 16 * ldb * 2 + k0 * 2);
-    }
-  };
-
-  f32x16 acc[TN][TM];
-#pragma unroll
-  for (int a = 0; a < TN; ++a)
-#pragma unroll
-    for (int b = 0; b < TM; ++b)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
-
-  const int l32 = lane & 31, g = lane >> 5;
-  const int KT = K / PBK;
-  // Prologue: STAGES - 1 tiles in flight.
-#pragma unroll
-  for (int st = 0; st < STAGES - 1; ++st)
-    if (st < KT) issue(st, st * PBK);
-  // Tile 0 complete: at most (STAGES - 2) tiles of this wave's loads pending.
-  if (KT >= STAGES - 1) {
-    if constexpr (STAGES == 4) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * (IA + IB)) : "memory");
-    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  } else {
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  }
-  lds_barrier();
-  for (int kt = 0; kt < KT; ++kt) {
-    const int cur = kt % STAGES;
-    const bool more = kt + STAGES - 1 < KT;
-    if (more) issue((kt + STAGES - 1) % STAGES, (kt + STAGES - 1) * PBK);
-    const bf16_t* tA = sA[cur];
-    const bf16_t* tB = sB[cur];
-    bf16x8 fw0[TN], fx0[TM], fw1[TN], fx1[TM];
-#pragma unroll
-    for (int a = 0; a < TN; ++a)
-      fw0[a] = *reinterpret_cast<const bf16x8*>(&tB[pswz(wn * WN + a * 32 + l32, g)]);
-#pragma unroll
-    for (int b = 0; b < TM; ++b)
-      fx0[b] = *reinterpret_cast<const bf16x8*>(&tA[pswz(wm * WM + b * 32 + l32, g)]);
-#pragma unroll
-    for (int a = 0; a < TN; ++a)
-      fw1[a] = *reinterpret_cast<const bf16x8*>(&tB[pswz(wn * WN + a * 32 + l32, 2 + g)]);
-#pragma unroll
-    for (int b = 0; b < TM; ++b)
-      fx1[b] = *reinterpret_cast<const bf16x8*>(&tA[pswz(wm * WM + b * 32 + l32, 2 + g)]);
-#pragma unroll
-    for (int a = 0; a < TN; ++a)
-#pragma unroll
-      for (int b = 0; b < TM; ++b)
-        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fw0[a], fx0[b], acc[a][b], 0, 0, 0);
-#pragma unroll
-    for (int a = 0; a < TN; ++a)
-#pragma unroll
-      for (int b = 0; b < TM; ++b)
-        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fw1[a], fx1[b], acc[a][b], 0, 0, 0);
-    constexpr int NF = TN + TM, NM = TN * TM;
-    __builtin_amdgcn_sched_group_barrier(0x100, NF, 0);
-#pragma unroll
-    for (int i = 0; i < NF; ++i) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-    }
-    if (NM > NF) __builtin_amdgcn_sched_group_barrier(0x008, NM - NF, 0);
-    __builtin_amdgcn_sched_group_barrier(0x008, NM, 0);
-    // Tile kt+1 must be complete; younger tiles may stay in flight.
-    if (more) {
-      if constexpr (STAGES == 4) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * (IA + IB)) : "memory");
-      else if constexpr (STAGES == 3) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(IA + IB) : "memory");
-      else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    } else {
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    }
-    lds_barrier();
-  }
-
-#pragma unroll
-  for (int b = 0; b < TM; ++b) {
-    const int m = m0 + wm * WM + b * 32 + l32;
-    if (m >= M) continue;
-#pragma unroll
-    for (int a = 0; a < TN; ++a) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int n = n0 + wn * WN + a * 32 + 8 * q + 4 * g;
-        if (n < N)
-          epi_store4<EPI, OUT_BF16>(e, m, n, acc[a][b][4 * q + 0], acc[a][b][4 * q + 1],
-                                    acc[a][b][4 * q + 2], acc[a][b][4 * q + 3]);
-      }
-    }
-  }
-}
-
-template <int BM, int BN, int WGM, int WGN, int STAGES>
-static hipError_t launch_bf16_pipe(const bf16_t* A, int lda, const void* B, int ldb, int M,
-                                   int N, int K, int op, const EpiArgs& e, hipStream_t s) {
-  if (K % PBK) return hipErrorInvalidValue;
-  const int gm = (M + BM - 1) / BM, gn = (N + BN - 1) / BN;
-  dim3 grid(gm * gn), block(WGM * WGN * 64);
-  const bf16_t* Bb = static_cast<const bf16_t*>(B);
-#define VL_GEMM_CASE(OP)                                                                       \
-  case OP:                                                                                     \
-    hipLaunchKernelGGL((k_gemm_bf16_pipe<BM, BN, WGM, WGN, STAGES, OP>), grid, block, 0, s, A, \
-                       lda, Bb, ldb, M, N, K, gm, gn, e);                                      \
-    break;
-  switch (op) {
-    VL_GEMM_CASE(OP_PATCH)
-    VL_GEMM_CASE(OP_QKV)
-    VL_GEMM_CASE(OP_OPROJ)
-    VL_GEMM_CASE(OP_FC1)
-    VL_GEMM_CASE(OP_FC2)
-    default: return hipErrorInvalidValue;
-  }
-#undef VL_GEMM_CASE
-  return hipGetLastError();
-}
-
-template <int BM, int BN, int WGM, int WGN, bool B_FP8>
+template <int BM, int BN, int WGM, int WGN, bool B_FP8, int RPM = 2>
 static hipError_t launch_bf16_dl(const bf16_t* A, int lda, const void* B, int ldb, int M,
                                  int N, int K, int op, const EpiArgs& e, hipStream_t s) {
   const int gm = (M + BM - 1) / BM, gn = (N + BN - 1) / BN;
   dim3 grid(gm * gn), block(WGM * WGN * 64);
-#define VL_GEMM_CASE(OP)                                                                     \
-  case OP:                                                                                   \
-    hipLaunchKernelGGL((k_gemm_bf16_dl<BM, BN, WGM, WGN, B_FP8, OP>), grid, block, 0, s, A,  \
-                       lda, B, ldb, M, N, K, gm, gn, e);                                     \
+#define VL_GEMM_CASE(OP)                                                                         \
+  case OP:                                                                                       \
+    hipLaunchKernelGGL((k_gemm_bf16_dl<BM, BN, WGM, WGN, B_FP8, OP, RPM>), grid, block, 0, s, A, \
+                       lda, B, ldb, M, N, K, gm, gn, e);                                         \
     break;
   switch (op) {
     VL_GEMM_CASE(OP_PATCH)
