@@ -31,19 +31,33 @@ hipError_t gemm_launch_cfg5(const bf16_t*, int, const void*, int, bool, int, int
                                const EpiArgs&, hipStream_t);
 hipError_t gemm_launch_cfg6(const bf16_t*, int, const void*, int, bool, int, int, int, int,
                                const EpiArgs&, hipStream_t);
+hipError_t gemm_launch_cfg7(const bf16_t*, int, const void*, int, bool, int, int, int, int,
+                               const EpiArgs&, hipStream_t);
 
 const char* gemm_cfg_name(int cfg) {
-  static const char* names[N_GEMM_CFGS] = {"DL_256x256_W2x4", "DL_256x256_W4x2", "DL_256x256_W2x2", "DL_128x128_W2x2", "DL_256x128_W2x2", "DL_128x256_W2x2", "REG_128x128_W2x2"};
+  static const char* names[N_GEMM_CFGS] = {"DL_256x256_W2x4", "DL_256x256_W4x2", "DL_256x256_W2x2", "DL_128x128_W2x2", "DL_256x128_W2x2", "DL_128x256_W2x2", "REG_128x128_W2x2", "DL_192x256_W2x4"};
   return cfg >= 0 && cfg < N_GEMM_CFGS ? names[cfg] : "unknown";
 }
 
 int gemm_cfg_heuristic(int M, int N, int K, bool b_fp8) {
   (void)K;
   (void)b_fp8;
-  // 256 x 256 tiles once the tile grid covers the 256 CUs about twice;
-  // 128 x 128 tiles for smaller problems.
-  const long tiles256 = (long)((M + 255) / 256) * ((N + 255) / 256);
-  return tiles256 >= 512 ? CFG_DL_256x256_W2x4 : CFG_DL_128x128_W2x2;
+  // Estimated time in units of one 256 x 256 tile on one CU: rounds of tiles
+  // over the 256 CUs times the relative tile time (area / relative
+  // efficiency, from measurements on gfx950).  Small grids fall back to
+  // 128 x 128 tiles.
+  struct C { int cfg, bm, bn; double eff; };
+  static const C cands[] = {{CFG_DL_256x256_W2x4, 256, 256, 1.0},
+                            {CFG_DL_192x256_W2x4, 192, 256, 0.9},
+                            {CFG_DL_128x128_W2x2, 128, 128, 0.55}};
+  int best = CFG_DL_128x128_W2x2;
+  double best_t = 1e300;
+  for (const C& c : cands) {
+    const long tiles = (long)((M + c.bm - 1) / c.bm) * ((N + c.bn - 1) / c.bn);
+    const double t = (double)((tiles + 255) / 256) * (c.bm * c.bn) / (65536.0 * c.eff);
+    if (t < best_t) { best_t = t; best = c.cfg; }
+  }
+  return best;
 }
 
 hipError_t gemm_bf16(const bf16_t* A, int lda, const void* B, int ldb, bool b_fp8, int M, int N,
@@ -59,6 +73,7 @@ hipError_t gemm_bf16(const bf16_t* A, int lda, const void* B, int ldb, bool b_fp
     case 4: return gemm_launch_cfg4(A, lda, B, ldb, b_fp8, M, N, K, op, e, s);
     case 5: return gemm_launch_cfg5(A, lda, B, ldb, b_fp8, M, N, K, op, e, s);
     case 6: return gemm_launch_cfg6(A, lda, B, ldb, b_fp8, M, N, K, op, e, s);
+    case 7: return gemm_launch_cfg7(A, lda, B, ldb, b_fp8, M, N, K, op, e, s);
   }
   return hipErrorInvalidValue;
 }

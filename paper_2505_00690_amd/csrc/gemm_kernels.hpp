@@ -346,6 +346,7 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
   constexpr int NW = WGM * WGN;
   constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int TM = WM / 32, TN = WN / 32;
+  static_assert(WM % 32 == 0 && WN % 32 == 0, "wave tile must be whole 32x32 blocks");
   constexpr int BROWS = B_FP8 ? 16 : 8;               // B rows per load instruction
   constexpr int IA = BM / 8 / NW, IB = BN / BROWS / NW;  // load instructions per wave per tile
   static_assert(IA * NW * 8 == BM && IB * NW * BROWS == BN, "tile rows / waves");
@@ -454,16 +455,17 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
       for (int b = 0; b < TM; ++b)
         acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fw[a], fx[b], acc[a][b], 0, 0, 0);
   };
-  // One MFMA, RPM LDS reads, ... then the remaining MFMAs: all of the next
+  // One MFMA, RPM LDS reads (1 when RPM does not divide the fragment count),
+  // ... then the remaining MFMAs: all of the next
   // sub-step's reads are in flight early in the current one.
   constexpr int NF = TN + TM, NM = TN * TM;
-  static_assert(NF % RPM == 0, "reads per MFMA must divide the fragment count");
-  constexpr int NG = NF / RPM;  // MFMAs that carry reads
+  constexpr int RPM_ = NF % RPM == 0 ? RPM : 1;
+  constexpr int NG = NF / RPM_;  // MFMAs that carry reads
   auto interleave = [&]() {
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x100, RPM, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, RPM_, 0);
     }
     if (NM > NG) __builtin_amdgcn_sched_group_barrier(0x008, NM - NG, 0);
   };

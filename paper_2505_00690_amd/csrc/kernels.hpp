@@ -59,7 +59,8 @@ enum GemmCfg {
   CFG_DL_256x128_W2x2 = 4,
   CFG_DL_128x256_W2x2 = 5,
   CFG_REG_128x128_W2x2 = 6,
-  N_GEMM_CFGS = 7
+  CFG_DL_192x256_W2x4 = 7,
+  N_GEMM_CFGS = 8
 };
 const char* gemm_cfg_name(int cfg);
 // Configuration used when none is tuned for an operation.
