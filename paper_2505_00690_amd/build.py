@@ -39,9 +39,16 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+# Per-source extra flags.  attention.hip: keep MFMA accumulators in VGPRs
+# (the softmax works on the score accumulators with vector ALU ops, so
+# accumulation registers would only add copies and cost occupancy).
+EXTRA_FLAGS = {"attention.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc(), *HIPCC_FLAGS, *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src),
+           "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)

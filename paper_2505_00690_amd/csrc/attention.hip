@@ -3,42 +3,57 @@
 // attention is restricted to the tokens of one image).
 //
 // BF16 kernel (flash-style, MFMA).  A workgroup of four waves owns up to
-// 128 queries of one (image, head); each wave owns 32 queries.  Keys and
-// values stream through LDS in tiles of 64 tokens (double buffered, the next
-// tile's global loads issued before the current tile's MFMAs).  Scores are
-// computed transposed, S^T = K Q^T (v_mfma_f32_32x32x16_bf16), so a lane owns
-// one query and 16 of the 32 keys of an MFMA block: the row max and row sum of
-// the online softmax are in-lane reductions plus one exchange with lane^32.
-// The output is accumulated transposed too, O^T += V^T P^T, so P^T is fed to
-// the MFMA straight from the score registers (rounded to BF16) and the
-// per-query rescale factor is lane-local.  V is written to LDS transposed
-// (d-major) for that operand.  Softmax statistics stay in FP32; exponentials
-// are exp2 of log2(e)-prescaled scores.
+// 128 queries of one (image, head); each wave owns 32 queries.  Key and value
+// tiles of 64 tokens stream through a three-stage LDS ring by direct-to-LDS
+// loads issued two tiles ahead; both are kept row-major (token x head dim,
+// 16-byte chunks of a row XOR-permuted by a function of the row so the
+// operand reads below are bank-conflict free).  Scores are computed
+// transposed, S^T = K Q^T (v_mfma_f32_32x32x16_bf16), so a lane owns one
+// query and 16 of the 32 keys of an MFMA block: row max and row sum of the
+// online softmax are in-lane reductions plus one exchange with lane^32.  The
+// output is accumulated transposed too, O^T += V^T P^T: P^T goes to the MFMA
+// straight from the score registers (rounded to BF16) and the V^T operand is
+// read from the row-major value tile with the LDS transpose read
+// (ds_read_b64_tr_b16), which hands each lane one head-dim column at four
+// tokens.  Softmax statistics stay in FP32; exponentials are exp2 of
+// log2(e)-prescaled scores, and the running max is only raised when a tile
+// exceeds it by more than 2^8 (the normaliser cancels the reference point;
+// this bounds every exponential by 2^8 and makes rescaling rare).
 //
 // FP32 kernel: one thread per query, K/V tiles of 32 tokens in LDS, online
 // softmax per tile; the plain FP32 baseline.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace vl {
 
 constexpr int ATT_Q = 128;   // queries per workgroup
 constexpr int ATT_KV = 64;   // keys per LDS tile
+constexpr int ATT_ST = 3;    // LDS ring stages
+constexpr float ATT_TAU = 8.f;  // lazy-rescale threshold (log2 units)
 
-// sK[key][HD]: 16-B chunks of a row swizzled; for HD = 64 by
-// (key ^ (key >> 3)) & 7, which keeps 8 (or 16) consecutive keys read at one
-// logical chunk on distinct banks; for HD = 32 by key & 3.
-template <int HD>
-__device__ __forceinline__ int k_off(int key, int chunk) {
-  constexpr int NC = HD / 8;
-  const int f = NC == 8 ? ((key ^ (key >> 3)) & 7) : (key & (NC - 1));
-  return key * HD + ((chunk ^ f) << 3);
-}
-// sVt[d][64 keys]: 16-B chunks of a row swizzled by (d ^ (d >> 3)) & 7, so
-// both the transposing stores (8 rows d = 8c + e at one key) and the
-// fragment reads (32 consecutive rows d at one key chunk) spread over banks.
-__device__ __forceinline__ int vt_off(int d, int key) {
-  return d * ATT_KV + ((((key >> 3) ^ ((d ^ (d >> 3)) & 7))) << 3) + (key & 7);
-}
+// Row-major K / V tile of 64 tokens x HD BF16 (HD/8 16-byte chunks per row),
+// chunk c of row r stored at position c ^ f(r).  Key tiles: f(r) =
+// (r ^ (r >> 3)) & 7 for HD = 64, (r >> 2) & 3 for HD = 32, so 16
+// consecutive rows read at one logical chunk (the K operand) hit distinct
+// banks.  Value tiles: f(r) = r & 7 for HD = 64, no permutation for HD = 32;
+// the four consecutive rows of one transpose read then hit distinct banks,
+// and f depends only on r mod 8, so a lane's read offsets for all 16-row
+// groups differ by immediates.
+template <int HD, bool VALUE>
+struct KvTile {
+  static constexpr int NCH = HD / 8;
+  static constexpr int ROWB = HD * 2;
+  static constexpr int BYTES = 64 * ROWB;
+  __device__ static int f(int r) {
+    if (VALUE) return NCH == 8 ? (r & 7) : 0;
+    return NCH == 8 ? ((r ^ (r >> 3)) & 7) : ((r >> 2) & 3);
+  }
+  __device__ static int off(int r, int chunk) { return r * ROWB + ((chunk ^ f(r)) << 4); }
+};
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
 
 template <int HD>
 __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qkv,
@@ -46,14 +61,13 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
                                                    const ImgDesc* __restrict__ imgs,
                                                    const AttnItem* __restrict__ items,
                                                    int heads) {
-  constexpr int NCH = HD / 8;                  // 16-B chunks per row of one head
-  constexpr int KLOADS = ATT_KV * NCH / 256;   // K chunks per thread
-  constexpr int VTHREADS = 32 * NCH;           // threads staging V: key pair x chunk
-  static_assert(KLOADS >= 1 && VTHREADS <= 256, "tile / threads");
-  // Three-stage K / V ring: while tile kt's softmax and P.V run, tile kt+1
-  // is read for the next scores and tile kt+2 is being staged.
-  __shared__ __attribute__((aligned(16))) bf16_t sK[3][ATT_KV * HD];
-  __shared__ __attribute__((aligned(16))) bf16_t sVt[3][HD * ATT_KV];
+  using T = KvTile<HD, false>;
+  using TV = KvTile<HD, true>;
+  constexpr int RPI = 1024 / T::ROWB;          // tile rows per 1 KB load instruction
+  constexpr int LPW = ATT_KV / RPI / 4;        // K (and V) load instructions per wave
+  static_assert(LPW >= 1 && LPW * RPI * 4 == ATT_KV, "tile / waves");
+  __shared__ __attribute__((aligned(1024))) char sK[ATT_ST][T::BYTES];
+  __shared__ __attribute__((aligned(1024))) char sV[ATT_ST][T::BYTES];
 
   const AttnItem it = items[blockIdx.x];
   const int h = blockIdx.y;
@@ -63,12 +77,11 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
   const int ld = 3 * D;
   const bf16_t* base = qkv + (size_t)dsc.tok_start * ld;
   const bf16_t* Qp = base + h * HD;
-  const bf16_t* Kp = base + D + h * HD;
-  const bf16_t* Vp = base + 2 * D + h * HD;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l32 = lane & 31, g = lane >> 5;
-  const int qw = it.q0 + wave * 32;           // first query of this wave
+  const int qw = it.q0 + wave * 32;            // first query of this wave
   const bool wave_active = qw < N;
   const int q = qw + l32;                      // this lane's query
   const int qc = min(q, N - 1);
@@ -78,150 +91,167 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
 #pragma unroll
   for (int c = 0; c < HD / 16; ++c)
     qf[c] = *reinterpret_cast<const bf16x8*>(Qp + (size_t)qc * ld + 16 * c + 8 * g);
+  // Wait for Q here with a wait the compiler sees (vmcnt(0)): otherwise its
+  // wait-count pass, unaware of the direct-to-LDS loads below, keeps
+  // waiting for Q at the score MFMAs of every tile and drains the prefetch.
+  __builtin_amdgcn_s_waitcnt(0x0F70);
 
-  // Staging: K chunk id = tid + i*256 -> key id / NCH, chunk id % NCH.
-  // V: thread (key pair vp = tid / NCH, chunk vc = tid % NCH) loads rows
-  // 2vp and 2vp+1 (coalesced: NCH consecutive lanes cover a row) and stores
-  // them transposed as 32-bit key pairs.
-  const int vp = tid / NCH, vc = tid % NCH;
-  u32x4 rk[KLOADS], rv0, rv1;
-  auto load_kv = [&](int kbase) {
+  // Direct-to-LDS loads: instruction i of this wave fills tile rows
+  // R = (wave * LPW + i) * RPI ..; lane l takes row R + l / NCH and physical
+  // chunk l % NCH, i.e. logical chunk (l % NCH) ^ f(row).  Rows past the
+  // image read as zero (buffer bound).
+  const i32x4 rk = buffer_rsrc(base + D + h * HD, (uint64_t)N * ld * 2);
+  const i32x4 rv = buffer_rsrc(base + 2 * D + h * HD, (uint64_t)N * ld * 2);
+  int goffK[LPW], goffV[LPW];
 #pragma unroll
-    for (int i = 0; i < KLOADS; ++i) {
-      const int id = tid + i * 256;
-      const int key = min(kbase + id / NCH, N - 1);
-      rk[i] = *reinterpret_cast<const u32x4*>(Kp + (size_t)key * ld + (id % NCH) * 8);
-    }
-    if (tid < VTHREADS) {
-      const int k0 = min(kbase + 2 * vp, N - 1), k1 = min(kbase + 2 * vp + 1, N - 1);
-      rv0 = *reinterpret_cast<const u32x4*>(Vp + (size_t)k0 * ld + vc * 8);
-      rv1 = *reinterpret_cast<const u32x4*>(Vp + (size_t)k1 * ld + vc * 8);
+  for (int i = 0; i < LPW; ++i) {
+    const int row = (wave * LPW + i) * RPI + lane / T::NCH;
+    goffK[i] = row * ld * 2 + (((lane % T::NCH) ^ T::f(row)) << 4);
+    goffV[i] = row * ld * 2 + (((lane % T::NCH) ^ TV::f(row)) << 4);
+  }
+  const uint32_t ldsK = lds_offset(&sK[0][0]), ldsV = lds_offset(&sV[0][0]);
+  auto issue = [&](int kt, int st) {
+    const int kb = kt * ATT_KV * ld * 2;
+#pragma unroll
+    for (int i = 0; i < LPW; ++i) {
+      const uint32_t lo = st * T::BYTES + (wave * LPW + i) * 1024;
+      dma16(rk, ldsK + lo, goffK[i] + kb, 0);
+      dma16(rv, ldsV + lo, goffV[i] + kb, 0);
     }
   };
-  auto store_kv = [&](int buf) {
+
+  // K operand (scores): lane reads row 32kb + l32, logical chunk 2c + g.
+  int koff[2][HD / 16];
 #pragma unroll
-    for (int i = 0; i < KLOADS; ++i) {
-      const int id = tid + i * 256;
-      *reinterpret_cast<u32x4*>(&sK[buf][k_off<HD>(id / NCH, id % NCH)]) = rk[i];
-    }
-    if (tid < VTHREADS) {
+  for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        const uint32_t a = rv0[w], b = rv1[w];
-        // element 2w (low halves) and 2w+1 (high halves) of the chunk
-        *reinterpret_cast<uint32_t*>(&sVt[buf][vt_off(vc * 8 + 2 * w, 2 * vp)]) =
-            (a & 0xFFFFu) | (b << 16);
-        *reinterpret_cast<uint32_t*>(&sVt[buf][vt_off(vc * 8 + 2 * w + 1, 2 * vp)]) =
-            (a >> 16) | (b & 0xFFFF0000u);
-      }
-    }
-  };
+    for (int c = 0; c < HD / 16; ++c) koff[kb][c] = T::off(32 * kb + l32, 2 * c + g);
+  // V^T operand: per 16-key chunk jj and 32-column block a, two transpose
+  // reads.  Within each 16-lane group (g = group / 2, column half dh =
+  // group % 2) lane i supplies the 8 bytes at token 16jj + 8hf + 4g + i/4
+  // (hf = 0, 1 for the two reads), columns 32a + 16dh + 4(i%4) .. +3, and
+  // receives column 32a + 16dh + i at the four tokens 16jj + 8hf + 4g +
+  // (0..3): the same token order as the P^T fragment below.  With the value
+  // tile's permutation the offset is vbase[a] + (16jj + 8hf) * row bytes.
+  const int grp = lane >> 4, li = lane & 15;
+  const int tg = grp >> 1, dh = grp & 1;
+  int vbase[HD / 32];
+#pragma unroll
+  for (int a = 0; a < HD / 32; ++a) {
+    const int col = 32 * a + 16 * dh + 4 * (li & 3);
+    vbase[a] = TV::off(4 * tg + (li >> 2), col >> 3) + (col & 7) * 2;
+  }
 
   const float sl2 = 1.4426950408889634f / sqrtf((float)HD);  // log2(e)/sqrt(d)
-  float m_run = -INFINITY, l_run = 0.f;   // running max (log2 units) and sum
+  float m_run = -INFINITY, l_run = 0.f;   // reference max (log2 units), sum
   f32x16 o[HD / 32];
 #pragma unroll
   for (int a = 0; a < HD / 32; ++a)
 #pragma unroll
     for (int r = 0; r < 16; ++r) o[a][r] = 0.f;
 
-  // S^T blocks of one key tile: s[kb][r] = S[key kb*32 + 8(r/4) + 4g + r%4][query].
-  auto scores = [&](const bf16_t* tK, f32x16* s) {
+  const int KT = (N + ATT_KV - 1) / ATT_KV;
+  // One key tile; the ring stage is a compile-time constant so every LDS
+  // address is a per-lane base plus an immediate.
+  auto tile = [&](auto stage, int kt) {
+    constexpr int st = decltype(stage)::value;
+    // Tile kt must have landed; tile kt+1's loads may stay in flight.
+    if (kt + 1 < KT) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * LPW) : "memory");
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    lds_barrier();
+    // Stage (st+2)%3 held tile kt-1, whose readers all passed the barrier.
+    if (kt + 2 < KT) issue(kt + 2, (st + 2) % ATT_ST);
+    if (!wave_active) return;
+    const char* tK = sK[st];
+    // S^T blocks: s[kb][r] = S[key 32kb + 8(r/4) + 4g + r%4][query].
+    f32x16 s[2];
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) s[kb][r] = 0.f;
 #pragma unroll
       for (int c = 0; c < HD / 16; ++c) {
-        const bf16x8 kf = *reinterpret_cast<const bf16x8*>(&tK[k_off<HD>(kb * 32 + l32, 2 * c + g)]);
+        const bf16x8 kf = *reinterpret_cast<const bf16x8*>(tK + koff[kb][c]);
         s[kb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kf, qf[c], s[kb], 0, 0, 0);
       }
     }
+    // All V^T fragments of the tile, read while the softmax runs.
+    bf16x8 vf[4][HD / 32];
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+      for (int a = 0; a < HD / 32; ++a) {
+        typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+        const uint32_t vb = ldsV + st * TV::BYTES + vbase[a] + 16 * jj * TV::ROWB;
+        const s16x4 v0 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(uintptr_t)vb);
+        const s16x4 v1 =
+            __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(uintptr_t)(vb + 8 * TV::ROWB));
+        u32x4 vk;
+        vk[0] = __builtin_bit_cast(u32x2, v0).x; vk[1] = __builtin_bit_cast(u32x2, v0).y;
+        vk[2] = __builtin_bit_cast(u32x2, v1).x; vk[3] = __builtin_bit_cast(u32x2, v1).y;
+        vf[jj][a] = __builtin_bit_cast(bf16x8, vk);
+      }
+    const int kbase = kt * ATT_KV;
+    if (kbase + ATT_KV > N) {            // keys past the image: excluded
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          if (kbase + kb * 32 + 8 * (r >> 2) + 4 * g + (r & 3) >= N) s[kb][r] = -INFINITY;
+    }
+    // Row max: three-input maxima (inline so no NaN-quieting copies are
+    // inserted; scores are never NaN).
+    float mt = s[0][0];
+#pragma unroll
+    for (int i = 1; i < 31; i += 2) {
+      const float x = s[i >> 4][i & 15], y = s[(i + 1) >> 4][(i + 1) & 15];
+      asm("v_max3_f32 %0, %1, %2, %3" : "=v"(mt) : "v"(mt), "v"(x), "v"(y));
+    }
+    asm("v_max_f32 %0, %1, %2" : "=v"(mt) : "v"(mt), "v"(s[1][15]));
+    mt = fmaxf(mt, __shfl_xor(mt, 32, 64)) * sl2;
+    if (__any(mt > m_run + ATT_TAU)) {
+      const float m_new = fmaxf(m_run, mt);
+      const float alpha = __builtin_amdgcn_exp2f(m_run - m_new);
+      l_run *= alpha;
+#pragma unroll
+      for (int a = 0; a < HD / 32; ++a)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) o[a][r] *= alpha;
+      m_run = m_new;
+    }
+    const float nm = -m_run;
+    float ls0 = 0.f, ls1 = 0.f;
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float p = __builtin_amdgcn_exp2f(fmaf(s[kb][r], sl2, nm));
+        s[kb][r] = p;
+        if (r & 1) ls1 += p; else ls0 += p;
+      }
+    l_run += ls0 + ls1;
+    // O^T += V^T P^T over four 16-key chunks jj; chunk jj = 2kb + hh uses
+    // s[kb][8hh .. 8hh+7]: keys 16jj + 8(e/4) + 4g + e%4 for element e.
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int kb = jj >> 1, hh = jj & 1;
+      u32x4 pk;
+#pragma unroll
+      for (int w = 0; w < 4; ++w)
+        pk[w] = pack_bf16x2(s[kb][8 * hh + 2 * w], s[kb][8 * hh + 2 * w + 1]);
+      const bf16x8 pf = __builtin_bit_cast(bf16x8, pk);
+#pragma unroll
+      for (int a = 0; a < HD / 32; ++a)
+        o[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vf[jj][a], pf, o[a], 0, 0, 0);
+    }
   };
 
-  // Software pipeline: the scores of tile kt+1 are issued to the matrix
-  // cores before the softmax of tile kt runs on the vector ALUs (the two are
-  // independent), then P.V of tile kt.
-  const int KT = (N + ATT_KV - 1) / ATT_KV;
-  load_kv(0);
-  store_kv(0);
-  if (KT > 1) {
-    load_kv(ATT_KV);
-    store_kv(1);
-  }
-  __syncthreads();
-  f32x16 s_cur[2], s_nxt[2];
-  if (wave_active) scores(sK[0], s_cur);
-  for (int kt = 0; kt < KT; ++kt) {
-    const int cur = kt % 3;
-    if (kt + 2 < KT) load_kv((kt + 2) * ATT_KV);
-    if (wave_active) {
-      if (kt + 1 < KT) scores(sK[(kt + 1) % 3], s_nxt);
-      const bf16_t* tV = sVt[cur];
-      f32x16* s = s_cur;
-      const int kbase = kt * ATT_KV;
-      if (kbase + ATT_KV > N) {            // keys past the image: excluded
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-          for (int r = 0; r < 16; ++r)
-            if (kbase + kb * 32 + 8 * (r >> 2) + 4 * g + (r & 3) >= N) s[kb][r] = -INFINITY;
-      }
-      float mt = s[0][0];
-#pragma unroll
-      for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) mt = fmaxf(mt, s[kb][r]);
-      mt = fmaxf(mt, __shfl_xor(mt, 32, 64));
-      const float m_new = fmaxf(m_run, mt * sl2);
-      const float nm = -m_new;
-      if (__any(m_new != m_run)) {         // rescale only when some max moved
-        const float alpha = __builtin_amdgcn_exp2f(m_run - m_new);
-        l_run *= alpha;
-#pragma unroll
-        for (int a = 0; a < HD / 32; ++a)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) o[a][r] *= alpha;
-      }
-      m_run = m_new;
-      float ls = 0.f;
-#pragma unroll
-      for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const float p = __builtin_amdgcn_exp2f(fmaf(s[kb][r], sl2, nm));
-          s[kb][r] = p;
-          ls += p;
-        }
-      l_run += ls;
-      // O^T += V^T P^T over four 16-key chunks j; chunk j = 2kb + hh uses
-      // s[kb][8hh .. 8hh+7]: keys 16j + 8(e/4) + 4g + e%4 for element e.
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int kb = j >> 1, hh = j & 1;
-        u32x4 pk;
-#pragma unroll
-        for (int w = 0; w < 4; ++w)
-          pk[w] = pack_bf16x2(s[kb][8 * hh + 2 * w], s[kb][8 * hh + 2 * w + 1]);
-        const bf16x8 pf = __builtin_bit_cast(bf16x8, pk);
-#pragma unroll
-        for (int a = 0; a < HD / 32; ++a) {
-          const int d = a * 32 + l32;
-          const u32x2 v0 = *reinterpret_cast<const u32x2*>(&tV[vt_off(d, 16 * j + 4 * g)]);
-          const u32x2 v1 = *reinterpret_cast<const u32x2*>(&tV[vt_off(d, 16 * j + 8 + 4 * g)]);
-          u32x4 vk;
-          vk[0] = v0.x; vk[1] = v0.y; vk[2] = v1.x; vk[3] = v1.y;
-          o[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, vk), pf, o[a],
-                                                         0, 0, 0);
-        }
-      }
-#pragma unroll
-      for (int kb = 0; kb < 2; ++kb) s_cur[kb] = s_nxt[kb];
-    }
-    // Stage kt+2 overwrites the buffer of tile kt-1, last read before the
-    // previous barrier.
-    if (kt + 2 < KT) store_kv((kt + 2) % 3);
-    __syncthreads();
+  issue(0, 0);
+  if (KT > 1) issue(1, 1);
+  for (int kt = 0; kt < KT; kt += ATT_ST) {
+    tile(std::integral_constant<int, 0>(), kt);
+    if (kt + 1 < KT) tile(std::integral_constant<int, 1>(), kt + 1);
+    if (kt + 2 < KT) tile(std::integral_constant<int, 2>(), kt + 2);
   }
   if (!wave_active || q >= N) return;
   const float lt = l_run + __shfl_xor(l_run, 32, 64);

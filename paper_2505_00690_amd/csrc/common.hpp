@@ -85,4 +85,51 @@ __device__ __forceinline__ float gelu_as7126(float x) {
   return 0.5f * x * (1.0f + erf_z);
 }
 
+// ------------------------------------------------ direct-to-LDS loads (gfx950)
+// buffer_load_dwordx4 ... lds: 16 bytes per lane go from global memory
+// straight into LDS (no VGPR round trip).  The buffer resource bounds the
+// access: offsets at or past num_records read as zero.
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+
+// LDS byte offset of a __shared__ object.  A generic pointer into LDS is the
+// shared aperture base (high 32 bits) plus the LDS offset (low 32 bits), so
+// truncation yields the offset without the null check an address-space cast
+// would add.
+__device__ __forceinline__ uint32_t lds_offset(const void* p) {
+  return static_cast<uint32_t>(reinterpret_cast<uintptr_t>(p));
+}
+
+// One 16-byte-per-lane direct-to-LDS load: lane i's 16 bytes from
+// rsrc + voffset + soffset land at LDS byte lds + 16 i (lds and soffset
+// wave-uniform).  Issued as inline assembly so the compiler's wait-count pass
+// does not treat it as an LDS store and force vmcnt(0) before every later LDS
+// read; the kernels wait for these loads themselves (s_waitcnt vmcnt(n)
+// before their barrier).
+__device__ __forceinline__ void dma16(i32x4 rsrc, uint32_t lds, int voffset, int soffset) {
+  asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, %3 offen lds"
+               :
+               : "s"(lds), "v"(voffset), "s"(rsrc), "s"(soffset)
+               : "memory", "m0");
+}
+
+// Workgroup barrier without the compiler's memory fence (which would also
+// wait for every outstanding global load): LDS reads of this wave are
+// drained first, global-to-LDS loads are waited for explicitly by callers.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+__device__ __forceinline__ i32x4 buffer_rsrc(const void* base, uint64_t bytes) {
+  const uint64_t p = reinterpret_cast<uint64_t>(base);
+  i32x4 r;
+  r[0] = (int32_t)(uint32_t)(p & 0xffffffffu);
+  r[1] = (int32_t)(uint32_t)(p >> 32);        // stride 0
+  r[2] = (int32_t)(uint32_t)(bytes > 0xffffffffull ? 0xffffffffull : bytes);
+  r[3] = 0x00020000;
+  r[0] = __builtin_amdgcn_readfirstlane(r[0]);
+  r[1] = __builtin_amdgcn_readfirstlane(r[1]);
+  r[2] = __builtin_amdgcn_readfirstlane(r[2]);
+  return r;
+}
+
 }  // namespace vl

@@ -268,52 +268,6 @@ __global__ __launch_bounds__(WGM* WGN * 64) void k_gemm_bf16(
 // ids are dealt round-robin to the 8 XCDs, so a contiguous range of tiles is
 // given to each XCD and walked in groups of GROUP_M row tiles, letting the
 // tiles resident on one XCD share A rows and B rows in its L2.
-typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-extern "C" __device__ void llvm_amdgcn_raw_buffer_load_lds(
-    i32x4 rsrc, __attribute__((address_space(3))) uint32_t* lds, int size, int voffset,
-    int soffset, int offset, int aux) __asm("llvm.amdgcn.raw.buffer.load.lds");
-
-// LDS byte offset of a __shared__ object.  A generic pointer into LDS is the
-// shared aperture base (high 32 bits) plus the LDS offset (low 32 bits), so
-// truncation yields the offset without the null check an address-space cast
-// would add.
-__device__ __forceinline__ uint32_t lds_offset(const void* p) {
-  return static_cast<uint32_t>(reinterpret_cast<uintptr_t>(p));
-}
-
-// One 16-byte-per-lane direct-to-LDS load: lane i's 16 bytes from
-// rsrc + voffset + soffset land at LDS byte lds + 16 i (lds and soffset
-// wave-uniform).  Issued as inline assembly so the compiler's wait-count pass
-// does not treat it as an LDS store and force vmcnt(0) before every later LDS
-// read; the kernels wait for these loads themselves (s_waitcnt vmcnt(n)
-// before their barrier).
-__device__ __forceinline__ void dma16(i32x4 rsrc, uint32_t lds, int voffset, int soffset) {
-  asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, %3 offen lds"
-               :
-               : "s"(lds), "v"(voffset), "s"(rsrc), "s"(soffset)
-               : "memory", "m0");
-}
-
-// Workgroup barrier without the compiler's memory fence (which would also
-// wait for every outstanding global load): LDS reads of this wave are
-// drained first, global-to-LDS loads are waited for explicitly by callers.
-__device__ __forceinline__ void lds_barrier() {
-  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
-
-__device__ __forceinline__ i32x4 buffer_rsrc(const void* base, uint64_t bytes) {
-  const uint64_t p = reinterpret_cast<uint64_t>(base);
-  i32x4 r;
-  r[0] = (int32_t)(uint32_t)(p & 0xffffffffu);
-  r[1] = (int32_t)(uint32_t)(p >> 32);        // stride 0
-  r[2] = (int32_t)(uint32_t)(bytes > 0xffffffffull ? 0xffffffffull : bytes);
-  r[3] = 0x00020000;
-  r[0] = __builtin_amdgcn_readfirstlane(r[0]);
-  r[1] = __builtin_amdgcn_readfirstlane(r[1]);
-  r[2] = __builtin_amdgcn_readfirstlane(r[2]);
-  return r;
-}
-
 __device__ __forceinline__ void xcd_tile(int gm, int gn, int group_m, int* tm, int* tn) {
   const int total = gm * gn;
   const int bid = blockIdx.x;
