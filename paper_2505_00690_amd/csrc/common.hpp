@@ -63,26 +63,25 @@ __device__ __forceinline__ float gelu_erf(float x) {
   return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
 }
 
-// The same GELU with erf from Abramowitz & Stegun, Handbook of Mathematical
-// Functions, formula 7.1.26 (|error of erf| <= 1.5e-7): for z >= 0,
-// erf(z) = 1 - (a1 t + a2 t^2 + a3 t^3 + a4 t^4 + a5 t^5) exp(-z^2),
-// t = 1 / (1 + p z), odd extension for z < 0.  Branch-free, one reciprocal
-// and one exp2; in FP32 the GELU error stays below 5e-7 absolute, far under
-// the BF16 rounding of the outputs it feeds.  Used where the GEMM output is
-// BF16; the FP32 path keeps erff.
-__device__ __forceinline__ float gelu_as7126(float x) {
-  const float z = x * 0.70710678118654752f;
-  const float az = fabsf(z);
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, az, 1.0f));
-  float poly = fmaf(1.061405429f, t, -1.453152027f);
-  poly = fmaf(poly, t, 1.421413741f);
-  poly = fmaf(poly, t, -0.284496736f);
-  poly = fmaf(poly, t, 0.254829592f);
-  poly *= t;
-  const float e = __builtin_amdgcn_exp2f(-(az * az) * 1.4426950408889634f);
-  const float erf_abs = fmaf(-poly, e, 1.0f);
-  const float erf_z = __builtin_copysignf(erf_abs, z);
-  return 0.5f * x * (1.0f + erf_z);
+// GELU(x) = x * Phi(x) for the BF16-output epilogue, with all-FMA-pipe
+// arithmetic: Phi(x) - 1/2 ~= t * P(t^2), t = x clamped to [-4.5, 4.5], P an
+// even-power polynomial of degree 8 in t^2 (coefficients from
+// fit_gelu_poly.py; |error| of Phi <= 2.5e-5 including the clamp, i.e. a
+// relative GELU error far below the BF16 rounding of the output).  The FP32
+// path keeps erff.
+__device__ __forceinline__ float gelu_poly(float x) {
+  const float t = __builtin_amdgcn_fmed3f(x, -4.5f, 4.5f);
+  const float u = t * t;
+  float p = 3.806312210e-11f;
+  p = fmaf(p, u, -4.002815412e-09f);
+  p = fmaf(p, u, 1.846330520e-07f);
+  p = fmaf(p, u, -4.960022125e-06f);
+  p = fmaf(p, u, 8.727943350e-05f);
+  p = fmaf(p, u, -1.076754532e-03f);
+  p = fmaf(p, u, 9.729534388e-03f);
+  p = fmaf(p, u, -6.624048948e-02f);
+  p = fmaf(p, u, 3.988665044e-01f);
+  return fmaf(x, t * p, 0.5f * x);
 }
 
 // ------------------------------------------------ direct-to-LDS loads (gfx950)

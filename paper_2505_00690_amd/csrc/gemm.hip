@@ -33,9 +33,12 @@ hipError_t gemm_launch_cfg6(const bf16_t*, int, const void*, int, bool, int, int
                                const EpiArgs&, hipStream_t);
 hipError_t gemm_launch_cfg7(const bf16_t*, int, const void*, int, bool, int, int, int, int,
                                const EpiArgs&, hipStream_t);
+hipError_t gemm_launch_cfg8(const bf16_t*, int, const void*, int, bool, int, int, int, int,
+                               const EpiArgs&, hipStream_t);
 
 const char* gemm_cfg_name(int cfg) {
-  static const char* names[N_GEMM_CFGS] = {"DL_256x256_W2x4", "DL_256x256_W4x2", "DL_256x256_W2x2", "DL_128x128_W2x2", "DL_256x128_W2x2", "DL_128x256_W2x2", "REG_128x128_W2x2", "DL_192x256_W2x4"};
+  static const char* names[N_GEMM_CFGS] = {"DL_256x256_W2x4", "DL_256x256_W4x2", "DL_256x256_W2x2", "DL_128x128_W2x2", "DL_256x128_W2x2", "DL_128x256_W2x2", "REG_128x128_W2x2", "DL_192x256_W2x4",
+                                           "DL_160x256_W1x8"};
   return cfg >= 0 && cfg < N_GEMM_CFGS ? names[cfg] : "unknown";
 }
 
@@ -49,6 +52,7 @@ int gemm_cfg_heuristic(int M, int N, int K, bool b_fp8) {
   struct C { int cfg, bm, bn; double eff; };
   static const C cands[] = {{CFG_DL_256x256_W2x4, 256, 256, 1.0},
                             {CFG_DL_192x256_W2x4, 192, 256, 0.9},
+                            {CFG_DL_160x256_W1x8, 160, 256, 0.85},
                             {CFG_DL_128x128_W2x2, 128, 128, 0.55}};
   int best = CFG_DL_128x128_W2x2;
   double best_t = 1e300;
@@ -74,6 +78,7 @@ hipError_t gemm_bf16(const bf16_t* A, int lda, const void* B, int ldb, bool b_fp
     case 5: return gemm_launch_cfg5(A, lda, B, ldb, b_fp8, M, N, K, op, e, s);
     case 6: return gemm_launch_cfg6(A, lda, B, ldb, b_fp8, M, N, K, op, e, s);
     case 7: return gemm_launch_cfg7(A, lda, B, ldb, b_fp8, M, N, K, op, e, s);
+    case 8: return gemm_launch_cfg8(A, lda, B, ldb, b_fp8, M, N, K, op, e, s);
   }
   return hipErrorInvalidValue;
 }

@@ -97,7 +97,7 @@ __device__ __forceinline__ void epi_store4(const EpiArgs& e, int m, int n, float
   }
   if (EPI == EPI_BIAS_GELU) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = OUT_BF16 ? gelu_as7126(v[j]) : gelu_erf(v[j]);
+    for (int j = 0; j < 4; ++j) v[j] = OUT_BF16 ? gelu_poly(v[j]) : gelu_erf(v[j]);
   }
   if (OUT_BF16) {
     u32x2 pk;
@@ -302,8 +302,12 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
   constexpr int TM = WM / 32, TN = WN / 32;
   static_assert(WM % 32 == 0 && WN % 32 == 0, "wave tile must be whole 32x32 blocks");
   constexpr int BROWS = B_FP8 ? 16 : 8;               // B rows per load instruction
-  constexpr int IA = BM / 8 / NW, IB = BN / BROWS / NW;  // load instructions per wave per tile
-  static_assert(IA * NW * 8 == BM && IB * NW * BROWS == BN, "tile rows / waves");
+  // Load instructions per wave per tile (the last round may cover only some
+  // waves when the row groups do not divide evenly; that test is
+  // wave-uniform).
+  constexpr int GA = BM / 8, GB = BN / BROWS;  // row groups of A / B per tile
+  constexpr int IA = (GA + NW - 1) / NW, IB = (GB + NW - 1) / NW;
+  static_assert(GA * 8 == BM && GB * BROWS == BN, "tile rows / load groups");
   constexpr int BES = B_FP8 ? 1 : 2;                    // bytes per B element
 
   // One LDS arena: double-buffered operand tiles during the K loop, then
@@ -338,12 +342,14 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
 #pragma unroll
     for (int i = 0; i < IA; ++i) {
       const int grp = wave + i * NW;  // 8-row group index
+      if (GA % NW != 0 && grp >= GA) break;
       dma16(ra, ldsA + (buf * BM * BK + grp * 8 * BK) * 2,
             a_off + grp * 8 * lda * 2 + ((lchunk ^ (grp & 7)) << 4), k0 * 2);
     }
 #pragma unroll
     for (int i = 0; i < IB; ++i) {
       const int grp = wave + i * NW;
+      if (GB % NW != 0 && grp >= GB) break;
       dma16(rb, ldsB + (buf * BN * BK + grp * BROWS * BK) * BES,
             b_off + grp * BROWS * ldb * BES + (B_FP8 ? 0 : ((lchunk ^ (grp & 7)) << 4)),
             k0 * BES);
@@ -457,14 +463,16 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
   // groups spread over the wave tile, so direct stores would touch 32 rows
   // per instruction.  Instead each 32-row slab of the wave's tile goes
   // through a wave-private LDS slab (row r's 16-byte chunks XOR-permuted by
-  // r & 15: the 16 lanes of one LDS pass hit 16 distinct chunk positions
-  // both when writing a column of rows and when reading along a row) and is
+  // r & 15, or by (r >> 1) & 7 for 8-chunk rows: the 16 lanes of one LDS
+  // pass hit distinct banks both when writing a column of rows and when
+  // reading along a row) and is
   // read back row-major: consecutive lanes own consecutive 16-byte column
   // chunks, so bias / residual loads and output stores are full-line
   // accesses, and each lane's columns (hence its bias) stay fixed.
   lds_barrier();  // all waves are done with the operand tiles
   constexpr int CPR = WN / 4;    // 16-byte FP32 chunks per staged row
-  static_assert(CPR >= 16 && 64 % CPR == 0, "staging layout needs WN in {64, 128}");
+  static_assert(CPR >= 8 && 64 % CPR == 0, "staging layout needs WN in {32, 64, 128}");
+  auto sw = [](int r) { return CPR >= 16 ? (r & 15) : ((r >> 1) & 7); };
   constexpr int RPP = 64 / CPR;  // rows per read-back pass
   constexpr int NP = 32 / RPP;   // passes per slab
   constexpr int NB = NP < 8 ? NP : 8;  // passes per batch of global loads
@@ -484,7 +492,7 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int c = a * 8 + 2 * q + g;  // columns a*32 + 8q + 4g .. +3
-        *reinterpret_cast<float4*>(stage + l32 * WN + ((c ^ (l32 & 15)) << 2)) =
+        *reinterpret_cast<float4*>(stage + l32 * WN + ((c ^ sw(l32)) << 2)) =
             make_float4(acc[a][b][4 * q + 0], acc[a][b][4 * q + 1], acc[a][b][4 * q + 2],
                         acc[a][b][4 * q + 3]);
       }
@@ -495,7 +503,7 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
 #pragma unroll
       for (int p = 0; p < NB; ++p) {
         const int row = (p0 + p) * RPP + rr;
-        v[p] = *reinterpret_cast<const float4*>(stage + row * WN + ((rc ^ (row & 15)) << 2));
+        v[p] = *reinterpret_cast<const float4*>(stage + row * WN + ((rc ^ sw(row)) << 2));
       }
       if (EPI == EPI_BIAS_RESID) {
 #pragma unroll
@@ -524,8 +532,8 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
           continue;
         }
         if (EPI == EPI_BIAS_GELU) {
-          y.x = gelu_as7126(y.x); y.y = gelu_as7126(y.y);
-          y.z = gelu_as7126(y.z); y.w = gelu_as7126(y.w);
+          y.x = gelu_poly(y.x); y.y = gelu_poly(y.y);
+          y.z = gelu_poly(y.z); y.w = gelu_poly(y.w);
         }
         u32x2 pk;
         pk.x = pack_bf16x2(y.x, y.y);
