@@ -59,9 +59,11 @@ def op_flops(c: synth.ModelConfig, sizes, op: str) -> float:
     }.get(op, 0.0)
 
 
-def traffic_from_profile(op: str, workload: str):
+def traffic_from_profile(op: str, workload: str, configs=None):
     """HBM bytes per launch from a committed rocprofv3 counter summary, or
-    None when there is none or the kernel source changed since."""
+    None when there is none, the kernel source changed since, or the op now
+    runs another tile configuration.  FETCH_SIZE / WRITE_SIZE are each scaled
+    by the factor a plain copy of known size measured in the same run."""
     path = os.path.join(ROOT, "profiles", f"traffic_{op}_{workload}.md")
     if not os.path.exists(path):
         return None
@@ -77,7 +79,9 @@ def traffic_from_profile(op: str, workload: str):
         return None
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
         return None
-    return (rec["fetch_kib"] + rec["write_kib"]) * 1024.0 * rec["copy_factor"]
+    if configs is not None and rec.get("config") not in configs:
+        return None
+    return (rec["fetch_kib"] * rec["fetch_factor"] + rec["write_kib"] * rec["write_factor"]) * 1024.0
 
 
 def cpu_baseline(wl: synth.Workload, blob: np.ndarray, images, texts, n_sample: int):
@@ -277,7 +281,9 @@ def main(argv=None) -> int:
                 "peak": BF16_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / BF16_PEAK,
                 "avg_launch_ms": avg_s * 1e3,
                 "flops_per_launch": op_flops(c, sizes, dom),
-                "traffic": traffic_from_profile(dom, args.workload)}
+                "traffic": traffic_from_profile(
+                    dom, args.workload,
+                    set(tuned[dom].values()) if tuned and dom in tuned else None)}
     if prec == "fp32":
         roofline.update({"peak": FP32_PEAK / 1e12, "frac": achieved / FP32_PEAK, "bound": "alu"})
 
