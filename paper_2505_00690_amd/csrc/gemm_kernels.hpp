@@ -16,6 +16,7 @@
 // translation units (gemm_cfg_*.hip) and the FP32 unit (gemm.hip).
 #pragma once
 
+
 #include "kernels.hpp"
 
 namespace vl {
@@ -268,9 +269,9 @@ __global__ __launch_bounds__(WGM* WGN * 64) void k_gemm_bf16(
 // ids are dealt round-robin to the 8 XCDs, so a contiguous range of tiles is
 // given to each XCD and walked in groups of GROUP_M row tiles, letting the
 // tiles resident on one XCD share A rows and B rows in its L2.
-__device__ __forceinline__ void xcd_tile(int gm, int gn, int group_m, int* tm, int* tn) {
+__device__ __forceinline__ void xcd_tile_of(int bid, int gm, int gn, int group_m, int* tm,
+                                            int* tn) {
   const int total = gm * gn;
-  const int bid = blockIdx.x;
   const int xcd = bid & 7, local = bid >> 3;
   const int q = total >> 3, r = total & 7;
   const int id = xcd * q + min(xcd, r) + local;
@@ -281,6 +282,9 @@ __device__ __forceinline__ void xcd_tile(int gm, int gn, int group_m, int* tm, i
   const int w = id - g * per_group;
   *tm = first + w % gsz;
   *tn = w / gsz;
+}
+__device__ __forceinline__ void xcd_tile(int gm, int gn, int group_m, int* tm, int* tn) {
+  xcd_tile_of(blockIdx.x, gm, gn, group_m, tm, tn);
 }
 
 // e4m3 B tiles: rows of 64 bytes (BK codes) whose four 16-byte chunks are
@@ -544,6 +548,8 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
   }
 }
 
+
+
 template <int BM, int BN, int WGM, int WGN, bool B_FP8, int RPM = 2>
 static hipError_t launch_bf16_dl(const bf16_t* A, int lda, const void* B, int ldb, int M,
                                  int N, int K, int op, const EpiArgs& e, hipStream_t s) {
@@ -565,6 +571,7 @@ static hipError_t launch_bf16_dl(const bf16_t* A, int lda, const void* B, int ld
 #undef VL_GEMM_CASE
   return hipGetLastError();
 }
+
 
 template <int BM, int BN, int WGM, int WGN, bool B_FP8>
 static hipError_t launch_bf16(const bf16_t* A, int lda, const void* B, int ldb, int M, int N,
