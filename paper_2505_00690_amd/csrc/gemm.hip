@@ -38,7 +38,7 @@ hipError_t gemm_launch_cfg8(const bf16_t*, int, const void*, int, bool, int, int
 
 const char* gemm_cfg_name(int cfg) {
   static const char* names[N_GEMM_CFGS] = {"DL_256x256_W2x4", "DL_256x256_W4x2", "DL_256x256_W2x2", "DL_128x128_W2x2", "DL_256x128_W2x2", "DL_128x256_W2x2", "REG_128x128_W2x2", "DL_192x256_W2x4",
-                                           "DL_160x256_W1x8"};
+                                           "DL3_160x256_W1x8"};
   return cfg >= 0 && cfg < N_GEMM_CFGS ? names[cfg] : "unknown";
 }
 
@@ -52,7 +52,7 @@ int gemm_cfg_heuristic(int M, int N, int K, bool b_fp8) {
   struct C { int cfg, bm, bn; double eff; };
   static const C cands[] = {{CFG_DL_256x256_W2x4, 256, 256, 1.0},
                             {CFG_DL_192x256_W2x4, 192, 256, 0.9},
-                            {CFG_DL_160x256_W1x8, 160, 256, 0.85},
+                            {CFG_DL3_160x256_W1x8, 160, 256, 0.85},
                             {CFG_DL_128x128_W2x2, 128, 128, 0.55}};
   int best = CFG_DL_128x128_W2x2;
   double best_t = 1e300;

@@ -294,7 +294,7 @@ __device__ __forceinline__ int swz8(int row, int kk, int g) {  // byte offset in
   return row * BK + ((kk ^ ((row >> 2) & 3)) << 4) + (g << 3);
 }
 
-template <int BM, int BN, int WGM, int WGN, bool B_FP8, int OP, int RPM>
+template <int BM, int BN, int WGM, int WGN, bool B_FP8, int OP, int RPM, int ST>
 __global__ __launch_bounds__(WGM* WGN * 64)
 __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_bf16_dl(
     const bf16_t* __restrict__ A, int lda, const void* __restrict__ Bv, int ldb, int M, int N,
@@ -314,13 +314,14 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
   static_assert(GA * 8 == BM && GB * BROWS == BN, "tile rows / load groups");
   constexpr int BES = B_FP8 ? 1 : 2;                    // bytes per B element
 
-  // One LDS arena: double-buffered operand tiles during the K loop, then
+  // One LDS arena: a ring of ST operand tile pairs during the K loop, then
   // per-wave epilogue staging slabs (32 rows x WN FP32 each).
-  constexpr int LDS_AB = 2 * BM * BK * 2 + 2 * BN * BK * BES;
+  static_assert(ST == 2 || ST == 3, "two or three K tiles in flight");
+  constexpr int LDS_AB = ST * (BM * BK * 2 + BN * BK * BES);
   constexpr int LDS_EPI = NW * 32 * WN * 4;
   __shared__ __attribute__((aligned(1024))) char smem[LDS_AB > LDS_EPI ? LDS_AB : LDS_EPI];
   bf16_t(*sA)[BM * BK] = reinterpret_cast<bf16_t(*)[BM * BK]>(smem);
-  uint8_t(*sB)[BN * BK * BES] = reinterpret_cast<uint8_t(*)[BN * BK * BES]>(smem + 2 * BM * BK * 2);
+  uint8_t(*sB)[BN * BK * BES] = reinterpret_cast<uint8_t(*)[BN * BK * BES]>(smem + ST * BM * BK * 2);
 
   int tm_, tn_;
   xcd_tile(gm, gn, 8, &tm_, &tn_);
@@ -434,17 +435,33 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
     if (NM > NG) __builtin_amdgcn_sched_group_barrier(0x008, NM - NG, 0);
   };
 
+  // Loads of one tile by this wave (fewer for the waves past the last full
+  // round of row groups); with three stages the wait before a barrier leaves
+  // exactly the next tile's loads in flight.
+  const int n_ld = (GA % NW == 0 || wave < GA % NW ? IA : IA - 1) +
+                   (GB % NW == 0 || wave < GB % NW ? IB : IB - 1);
+  auto wait_all_but_one_tile = [&]() {
+    if (n_ld == IA + IB) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(IA + IB) : "memory");
+    else if (n_ld == IA + IB - 1) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(IA + IB - 1) : "memory");
+    else asm volatile("s_waitcnt vmcnt(%0)" ::"n"(IA + IB - 2) : "memory");
+  };
+
   // Pipeline across tiles: the last sub-step's MFMAs of tile kt run after the
   // barrier, overlapping the first LDS reads of tile kt+1, so the matrix
-  // cores do not drain at every barrier.
+  // cores do not drain at every barrier.  Loads run ST - 1 tiles ahead.
   issue(0, 0);
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  if (ST == 3 && KT > 1) {
+    issue(1, BK);
+    wait_all_but_one_tile();
+  } else {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  }
   lds_barrier();
   ldfrag(fw0, fx0, 0, 0);
   for (int kt = 0; kt < KT; ++kt) {
-    const int cur = kt & 1;
-    const bool more = kt + 1 < KT;
-    if (more) issue(cur ^ 1, (kt + 1) * BK);
+    const int cur = ST == 2 ? (kt & 1) : kt % 3;
+    const int nxt = ST == 2 ? (cur ^ 1) : (cur == 2 ? 0 : cur + 1);
+    if (kt + ST - 1 < KT) issue(ST == 2 ? nxt : (nxt == 2 ? 0 : nxt + 1), (kt + ST - 1) * BK);
     ldfrag(fw1, fx1, cur, 1);
     mma(fw0, fx0);
     interleave();
@@ -454,11 +471,14 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
     ldfrag(fw1, fx1, cur, 3);
     mma(fw0, fx0);
     interleave();
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // Tile kt+1 must have landed (the stage being filled for kt+2 held tile
+    // kt-1, whose readers all passed the previous barrier).
+    if (ST == 3 && kt + 2 < KT) wait_all_but_one_tile();
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     lds_barrier();
     // (On the last tile these reads fetch stale fragments that are never
     // used; reading unconditionally keeps the accumulators out of a branch.)
-    ldfrag(fw0, fx0, cur ^ 1, 0);
+    ldfrag(fw0, fx0, nxt, 0);
     mma(fw1, fx1);
     interleave();
   }
@@ -550,15 +570,15 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
 
 
 
-template <int BM, int BN, int WGM, int WGN, bool B_FP8, int RPM = 2>
+template <int BM, int BN, int WGM, int WGN, bool B_FP8, int RPM = 2, int ST = 2>
 static hipError_t launch_bf16_dl(const bf16_t* A, int lda, const void* B, int ldb, int M,
                                  int N, int K, int op, const EpiArgs& e, hipStream_t s) {
   const int gm = (M + BM - 1) / BM, gn = (N + BN - 1) / BN;
   dim3 grid(gm * gn), block(WGM * WGN * 64);
-#define VL_GEMM_CASE(OP)                                                                         \
-  case OP:                                                                                       \
-    hipLaunchKernelGGL((k_gemm_bf16_dl<BM, BN, WGM, WGN, B_FP8, OP, RPM>), grid, block, 0, s, A, \
-                       lda, B, ldb, M, N, K, gm, gn, e);                                         \
+#define VL_GEMM_CASE(OP)                                                                  \
+  case OP:                                                                                \
+    hipLaunchKernelGGL((k_gemm_bf16_dl<BM, BN, WGM, WGN, B_FP8, OP, RPM, ST>), grid, block, \
+                       0, s, A, lda, B, ldb, M, N, K, gm, gn, e);                         \
     break;
   switch (op) {
     VL_GEMM_CASE(OP_PATCH)

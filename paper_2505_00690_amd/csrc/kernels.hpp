@@ -60,7 +60,7 @@ enum GemmCfg {
   CFG_DL_128x256_W2x2 = 5,
   CFG_REG_128x128_W2x2 = 6,
   CFG_DL_192x256_W2x4 = 7,
-  CFG_DL_160x256_W1x8 = 8,
+  CFG_DL3_160x256_W1x8 = 8,
   N_GEMM_CFGS = 9
 };
 const char* gemm_cfg_name(int cfg);
