@@ -45,7 +45,8 @@ def flops_per_image(c: synth.ModelConfig, res: int) -> float:
 
 
 def op_flops(c: synth.ModelConfig, sizes, op: str) -> float:
-    """Algorithmic FLOPs of one launch of an encoder operation."""
+    """Algorithmic FLOPs of one layer's worth of an encoder operation over the
+    whole batch (one launch, or two for a two-part batch)."""
     D, F = c.width, c.mlp
     toks = [1 + (h // c.patch) * (w // c.patch) for h, w in sizes]
     T = sum(toks)
@@ -178,6 +179,8 @@ def main(argv=None) -> int:
     ap.add_argument("--precision", default=None, help="fp32 | bf16 | fp8w (default: workload's)")
     ap.add_argument("--no-graphs", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in tile heuristic")
+    ap.add_argument("--split", action="store_true",
+                    help="run the batch as two overlapping parts on two streams")
     ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the plain FP32 path")
     ap.add_argument("--cpu-sample", type=int, default=None, help="images for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -239,7 +242,7 @@ def main(argv=None) -> int:
     top1 = torch.empty(n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
 
-    enc = vl.Encoder(c, w, prec, graphs=not args.no_graphs)
+    enc = vl.Encoder(c, w, prec, graphs=not args.no_graphs, split=args.split)
     tuned = None
     if prec != "fp32" and not args.no_autotune:
         tuned = enc.autotune(pix, sizes, reps=3)
@@ -275,12 +278,15 @@ def main(argv=None) -> int:
     gemm_like = ["qkv_gemm", "oproj_gemm", "fc1_gemm", "fc2_gemm", "attention"]
     dom = max(gemm_like, key=lambda k: ops[k][0])
     avg_s = ops[dom][0] / ops[dom][1] / 1e3
-    achieved = op_flops(c, sizes, dom) / avg_s
+    # (a two-part batch launches every op twice per layer: per-launch work is
+    # the op's work per step over its launches per step)
+    flops_launch = op_flops(c, sizes, dom) * c.layers / (ops[dom][1] / args.timing_steps)
+    achieved = flops_launch / avg_s
     fp8_note = prec == "fp8w"
     roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved / 1e12,
                 "peak": BF16_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / BF16_PEAK,
                 "avg_launch_ms": avg_s * 1e3,
-                "flops_per_launch": op_flops(c, sizes, dom),
+                "flops_per_launch": flops_launch,
                 "traffic": traffic_from_profile(
                     dom, args.workload,
                     set(tuned[dom].values()) if tuned and dom in tuned else None)}
@@ -297,6 +303,7 @@ def main(argv=None) -> int:
         "config": {"workload": args.workload, "model": wl.model, "batch": n,
                    "resolutions": sorted(set(h for h, _ in sizes)), "precision": prec,
                    "head": wl.head, "n_texts": wl.n_texts, "graphs": not args.no_graphs,
+                   "two_part_split": args.split,
                    "gemm_tiles": tuned},
         "encoder_tflops": total_flops / (ms / 1e3) / 1e12,
         "mfu_bf16": total_flops / (ms / 1e3) / BF16_PEAK,

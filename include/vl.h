@@ -127,11 +127,20 @@ void vl_model_destroy(vl_model* m);
  *   VL_OPT_GRAPHS : 1 = capture each distinct call (shapes, pointers,
  *                   stream) into a HIP graph on first use and replay it.
  *   VL_OPT_TIMING : 1 = bracket every kernel launch of vl_encode_images
- *                   with HIP events on the call's stream and accumulate
+ *                   with HIP events on the stream it runs on and accumulate
  *                   per-operation device time (read with
  *                   vl_model_op_times).  Calls made while timing is on are
- *                   launched eagerly even if VL_OPT_GRAPHS is set.        */
-typedef enum vl_option { VL_OPT_GRAPHS = 0, VL_OPT_TIMING = 1 } vl_option;
+ *                   launched eagerly even if VL_OPT_GRAPHS is set.
+ *   VL_OPT_SPLIT  : 1 = run a BF16 or FP8-weight batch of at least 4096
+ *                   tokens as two parts of consecutive images (about half
+ *                   the tokens each); the second part runs on a stream the
+ *                   library owns, forked from and joined back into the
+ *                   call's stream, so the parts overlap.  Outputs are
+ *                   bitwise identical to a one-part run.  0 = one part on
+ *                   the call's stream.  Changing it drops cached graphs.
+ *                   (On MI355X at ViT-L/14@336, batch 32, it measured
+ *                   between -2 % and +3 % against one part.)             */
+typedef enum vl_option { VL_OPT_GRAPHS = 0, VL_OPT_TIMING = 1, VL_OPT_SPLIT = 2 } vl_option;
 vl_status vl_model_set_option(vl_model* m, vl_option opt, int64_t value);
 
 /* Operations of the encoder, as reported by vl_model_op_times:

@@ -93,6 +93,11 @@ struct vl_model {
   double op_ms[VL_N_OPS] = {};
   int64_t op_launches[VL_N_OPS] = {};
   hipStream_t capture = nullptr;  // private stream graphs are captured on
+  // Two-part batches (off by default): the second part runs on this stream,
+  // forked from and joined back into the caller's stream with the two events.
+  bool split = false;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int32_t tuning[VL_N_GEMM_OPS][VL_N_M_BUCKETS];
 };
 
@@ -124,12 +129,27 @@ size_t weights_count(const vl_config& c) {
 }
 
 // ----------------------------------------------------------------- planning
+// A batch runs as one or two parts.  A part is a run of consecutive images
+// with its own descriptors (token starts relative to the part) and its own
+// regions of every activation buffer, so two parts never share memory and
+// can run concurrently on two streams.  Every kernel works per token row or
+// per image with a fixed accumulation order, so a part computes exactly what
+// the whole batch would for its images.
+constexpr int64_t kSplitMinTokens = 4096;  // split batches of at least this many tokens
+
+struct Part {
+  int i0 = 0, n = 0, T = 0, max_ntok = 0, n_items = 0;
+  size_t off_imgs = 0, off_items = 0;                       // in the descriptor region
+  size_t off_tok = 0, off_X = 0, off_Y = 0, off_QH = 0, off_E = 0;  // in the workspace
+};
+
 struct Plan {
-  int n = 0, T = 0, max_ntok = 0, n_items = 0;
-  std::vector<ImgDesc> imgs;
-  std::vector<AttnItem> items;
-  size_t desc_bytes = 0;   // imgs + items
-  size_t off_tok = 0, off_X = 0, off_Y = 0, off_QH = 0, off_E = 0, total = 0;
+  int n = 0, T = 0;
+  std::vector<int32_t> hw;          // (H, W) per image, for graph keys
+  std::vector<char> desc;           // host image of the descriptor region
+  size_t desc_bytes = 0;
+  std::vector<Part> parts;
+  size_t total = 0;
 };
 
 bool make_plan(const vl_model* m, int32_t n, const int32_t* hs, const int32_t* ws, Plan* p,
@@ -137,45 +157,82 @@ bool make_plan(const vl_model* m, int32_t n, const int32_t* hs, const int32_t* w
   if (n <= 0) { *why = "n_images must be > 0"; return false; }
   if (!hs || !ws) { *why = "heights/widths are NULL"; return false; }
   p->n = n;
-  p->imgs.resize(n);
-  p->items.clear();
-  int64_t pix = 0;
-  int64_t T = 0;
-  int max_ntok = 0;
+  p->hw.resize(2 * (size_t)n);
+  std::vector<ImgDesc> imgs(n);
+  int64_t pix = 0, T = 0;
   for (int i = 0; i < n; ++i) {
     const int H = hs[i], W = ws[i];
     if (H < m->P || W < m->P) { *why = "image " + std::to_string(i) + " smaller than one patch"; return false; }
     const int gh = H / m->P, gw = W / m->P;
     const int64_t ntok = 1 + (int64_t)gh * gw;
     if (ntok > kMaxTokens) { *why = "image " + std::to_string(i) + " has more than 1024 patches"; return false; }
-    ImgDesc& d = p->imgs[i];
+    ImgDesc& d = imgs[i];
     d.pix_off = pix;
     d.H = H; d.W = W; d.gh = gh; d.gw = gw;
-    d.tok_start = (int32_t)T;
+    d.tok_start = (int32_t)T;   // absolute for now
     d.ntok = (int32_t)ntok;
     pix += 3LL * H * W;
     T += ntok;
-    max_ntok = std::max<int>(max_ntok, (int)ntok);
-    for (int q0 = 0; q0 < ntok; q0 += kAttnQ) p->items.push_back(AttnItem{i, q0});
+    p->hw[2 * i] = H;
+    p->hw[2 * i + 1] = W;
   }
   if (T > (1LL << 24)) { *why = "batch exceeds 2^24 tokens"; return false; }
   p->T = (int)T;
-  p->max_ntok = max_ntok;
-  p->n_items = (int)p->items.size();
-  p->desc_bytes = sizeof(ImgDesc) * n + sizeof(AttnItem) * p->items.size();
+  // Part boundaries: one part, or two holding about half the tokens each.
+  std::vector<int> cut = {0};
+  if (m->split && m->prec != VL_FP32 && n >= 2 && T >= kSplitMinTokens) {
+    int n1 = 1;
+    while (n1 < n - 1 && imgs[n1].tok_start < T / 2) ++n1;
+    cut.push_back(n1);
+  }
+  cut.push_back(n);
+  // Descriptor region: per part, its image descriptors then its attention
+  // items (16-byte aligned).
+  auto a16 = [](size_t x) { return (x + 15) / 16 * 16; };
+  p->parts.clear();
+  std::vector<std::vector<AttnItem>> items(cut.size() - 1);
+  size_t doff = 0;
+  for (size_t k = 0; k + 1 < cut.size(); ++k) {
+    Part q;
+    q.i0 = cut[k];
+    q.n = cut[k + 1] - cut[k];
+    const int t0 = imgs[q.i0].tok_start;
+    for (int i = q.i0; i < cut[k + 1]; ++i) {
+      imgs[i].tok_start -= t0;
+      q.T += imgs[i].ntok;
+      q.max_ntok = std::max<int>(q.max_ntok, imgs[i].ntok);
+      for (int q0 = 0; q0 < imgs[i].ntok; q0 += kAttnQ) items[k].push_back(AttnItem{i - q.i0, q0});
+    }
+    q.n_items = (int)items[k].size();
+    q.off_imgs = doff;
+    doff = a16(doff + sizeof(ImgDesc) * q.n);
+    q.off_items = doff;
+    doff = a16(doff + sizeof(AttnItem) * q.n_items);
+    p->parts.push_back(q);
+  }
+  p->desc_bytes = doff;
+  p->desc.assign(doff, 0);
+  for (size_t k = 0; k < p->parts.size(); ++k) {
+    const Part& q = p->parts[k];
+    std::memcpy(p->desc.data() + q.off_imgs, imgs.data() + q.i0, sizeof(ImgDesc) * q.n);
+    std::memcpy(p->desc.data() + q.off_items, items[k].data(), sizeof(AttnItem) * q.n_items);
+  }
+  // Workspace: the descriptor region, then each part's activation regions.
   const size_t es = m->prec == VL_FP32 ? 4 : 2;
-  size_t off = align_up(p->desc_bytes);
-  p->off_tok = off;
-  off += align_up(sizeof(int2) * T);
-  p->off_X = off;
-  off += align_up(4ull * T * m->D);
-  p->off_Y = off;
-  off += align_up(es * T * m->D);
-  p->off_QH = off;
   const size_t qh_cols = std::max<size_t>({(size_t)3 * m->D, (size_t)m->F, (size_t)m->Kpad});
-  off += align_up(es * T * qh_cols);
-  p->off_E = off;
-  off += align_up(4ull * n * m->Pd);
+  size_t off = align_up(p->desc_bytes);
+  for (Part& q : p->parts) {
+    q.off_tok = off;
+    off += align_up(sizeof(int2) * q.T);
+    q.off_X = off;
+    off += align_up(4ull * q.T * m->D);
+    q.off_Y = off;
+    off += align_up(es * q.T * m->D);
+    q.off_QH = off;
+    off += align_up(es * q.T * qh_cols);
+    q.off_E = off;
+    off += align_up(4ull * q.n * m->Pd);
+  }
   p->total = off;
   return true;
 }
@@ -194,9 +251,7 @@ vl_status stage_descriptors(vl_model* m, const Plan& p, void* dst, hipStream_t s
     st.cap = std::max<size_t>(p.desc_bytes, 16384);
     VL_HIP(hipHostMalloc(&st.host, st.cap, hipHostMallocDefault));
   }
-  std::memcpy(st.host, p.imgs.data(), sizeof(ImgDesc) * p.n);
-  std::memcpy(static_cast<char*>(st.host) + sizeof(ImgDesc) * p.n, p.items.data(),
-              sizeof(AttnItem) * p.items.size());
+  std::memcpy(st.host, p.desc.data(), p.desc_bytes);
   VL_HIP(hipMemcpyAsync(dst, st.host, p.desc_bytes, hipMemcpyHostToDevice, s));
   VL_HIP(hipEventRecord(st.ev, s));
   st.pending = true;
@@ -255,13 +310,13 @@ struct OpScope {
     VL_HIP(sc_.close());                                  \
   } while (0)
 
-// The kernel sequence of one encode call.
-vl_status run_encoder(vl_model* m, const Plan& p, const float* pix, float* emb, char* ws,
-                      hipStream_t s) {
+// The kernel sequence of one part of an encode call.
+vl_status run_part(vl_model* m, const Part& p, const float* pix, float* emb, char* ws,
+                   hipStream_t s, hipEvent_t after_first_qkv = nullptr) {
   const bool f32 = m->prec == VL_FP32;
   const bool fp8 = m->prec == VL_FP8W_BF16A;
-  const ImgDesc* d_imgs = reinterpret_cast<const ImgDesc*>(ws);
-  const AttnItem* d_items = reinterpret_cast<const AttnItem*>(ws + sizeof(ImgDesc) * p.n);
+  const ImgDesc* d_imgs = reinterpret_cast<const ImgDesc*>(ws + p.off_imgs);
+  const AttnItem* d_items = reinterpret_cast<const AttnItem*>(ws + p.off_items);
   int2* tok = reinterpret_cast<int2*>(ws + p.off_tok);
   float* X = reinterpret_cast<float*>(ws + p.off_X);
   void* Y = ws + p.off_Y;
@@ -318,6 +373,7 @@ vl_status run_encoder(vl_model* m, const Plan& p, const float* pix, float* emb, 
       const bf16_t* qh = static_cast<const bf16_t*>(QH);
       VL_TIMED(T_QKV, VL_HIP(gemm_bf16(y, D, ly.qkv_w, D, fp8, T, 3 * D, D, OP_QKV,
                                        gemm_cfg_for(m, 1, T), e1, s)));
+      if (after_first_qkv && &ly == &m->layers[0]) VL_HIP(hipEventRecord(after_first_qkv, s));
       VL_TIMED(T_ATTN, VL_HIP(attention_bf16(qh, static_cast<bf16_t*>(Y), d_imgs, d_items,
                                              p.n_items, m->heads, m->hd, s)));
       VL_TIMED(T_OPROJ, VL_HIP(gemm_bf16(y, D, ly.o_w, D, fp8, T, D, D, OP_OPROJ,
@@ -330,9 +386,33 @@ vl_status run_encoder(vl_model* m, const Plan& p, const float* pix, float* emb, 
     }
   }
   VL_TIMED(T_POOL, VL_HIP(pool_project(X, d_imgs, p.n, m->lnf_g, m->lnf_b, eps, m->proj, D,
-                                        m->Pd, reinterpret_cast<float*>(ws + p.off_E), emb,
-                                        s)));
+                                        m->Pd, reinterpret_cast<float*>(ws + p.off_E),
+                                        emb + (size_t)p.i0 * m->Pd, s)));
   return VL_OK;
+}
+
+// The kernel sequence of one encode call: a single part on the caller's
+// stream, or two parts on the caller's stream and the model's side stream,
+// forked after everything already on the caller's stream (the descriptor
+// upload) and joined back before the call returns.  The two parts then
+// overlap one another's tile-round tails, epilogue store bursts and
+// non-MFMA phases.
+vl_status run_encoder(vl_model* m, const Plan& p, const float* pix, float* emb, char* ws,
+                      hipStream_t s) {
+  if (p.parts.size() == 1) return run_part(m, p.parts[0], pix, emb, ws, s);
+  if (!m->side) VL_HIP(hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking));
+  if (!m->ev_fork) VL_HIP(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
+  if (!m->ev_join) VL_HIP(hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming));
+  // The second part starts once the first has finished its first QKV GEMM,
+  // so the two sequences run about one operation out of phase.
+  vl_status st = run_part(m, p.parts[0], pix, emb, ws, s, m->layers.empty() ? nullptr : m->ev_fork);
+  if (m->layers.empty()) VL_HIP(hipEventRecord(m->ev_fork, s));
+  VL_HIP(hipStreamWaitEvent(m->side, m->ev_fork, 0));
+  vl_status st2 = run_part(m, p.parts[1], pix, emb, ws, m->side);
+  // Join even after an enqueue error, so a capture still ends cleanly.
+  VL_HIP(hipEventRecord(m->ev_join, m->side));
+  VL_HIP(hipStreamWaitEvent(s, m->ev_join, 0));
+  return st != VL_OK ? st : st2;
 }
 
 std::string graph_key(const Plan& p, const void* pix, const void* emb, const void* ws,
@@ -342,7 +422,9 @@ std::string graph_key(const Plan& p, const void* pix, const void* emb, const voi
   auto put = [&](const void* v, size_t n) { k.append(static_cast<const char*>(v), n); };
   put(&pix, sizeof pix); put(&emb, sizeof emb); put(&ws, sizeof ws); put(&ws_bytes, sizeof ws_bytes);
   put(&s, sizeof s); put(&p.n, sizeof p.n);
-  for (const ImgDesc& d : p.imgs) { put(&d.H, 4); put(&d.W, 4); }
+  const size_t np = p.parts.size();
+  put(&np, sizeof np);
+  put(p.hw.data(), sizeof(int32_t) * p.hw.size());
   return k;
 }
 
@@ -541,6 +623,9 @@ void vl_model_destroy(vl_model* m) {
     if (r.ev) (void)hipEventDestroy(r.ev);
   }
   if (m->capture) (void)hipStreamDestroy(m->capture);
+  if (m->side) (void)hipStreamDestroy(m->side);
+  if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
+  if (m->ev_join) (void)hipEventDestroy(m->ev_join);
   if (m->wmem) (void)hipFree(m->wmem);
   delete m;
 }
@@ -558,6 +643,11 @@ vl_status vl_model_set_option(vl_model* m, vl_option opt, int64_t value) {
       return VL_OK;
     case VL_OPT_TIMING:
       m->timing = value != 0;
+      return VL_OK;
+    case VL_OPT_SPLIT:
+      (void)hipDeviceSynchronize();
+      destroy_graphs(m);
+      m->split = value != 0;
       return VL_OK;
   }
   return fail(VL_ERR_INVALID_ARG, "unknown option");
@@ -632,9 +722,7 @@ vl_status vl_encode_images(vl_model* m, const float* pix, const int32_t* hs, con
     hipStream_t cs = m->capture;
     GraphEntry ge;
     VL_HIP(hipHostMalloc(&ge.host, std::max<size_t>(p.desc_bytes, 256), hipHostMallocDefault));
-    std::memcpy(ge.host, p.imgs.data(), sizeof(ImgDesc) * p.n);
-    std::memcpy(static_cast<char*>(ge.host) + sizeof(ImgDesc) * p.n, p.items.data(),
-                sizeof(AttnItem) * p.items.size());
+    std::memcpy(ge.host, p.desc.data(), p.desc_bytes);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) { (void)hipHostFree(ge.host); return hip_fail(e, "hipStreamBeginCapture"); }
@@ -702,49 +790,59 @@ vl_status vl_model_autotune(vl_model* m, const float* pix, const int32_t* hs, co
   m->timing = timing;
   if (st != VL_OK) return st;
   const bool fp8 = m->prec == VL_FP8W_BF16A;
-  const int T = p.T, D = m->D, F = m->F;
+  const int D = m->D, F = m->F;
   const Layer& ly = m->layers.empty() ? Layer{} : m->layers[0];
-  const bf16_t* Y = reinterpret_cast<const bf16_t*>(w + p.off_Y);
-  bf16_t* QH = reinterpret_cast<bf16_t*>(w + p.off_QH);
-  float* X = reinterpret_cast<float*>(w + p.off_X);
-  const int2* tok = reinterpret_cast<const int2*>(w + p.off_tok);
   hipEvent_t e0, e1;
   VL_HIP(hipEventCreate(&e0));
   VL_HIP(hipEventCreate(&e1));
-  struct OpShape { int op, N, K; const bf16_t* A; int lda; const void* B; bool b8; EpiArgs e; };
-  std::vector<OpShape> shapes;
-  {
-    EpiArgs pe;
-    pe.bias = m->patch_b; pe.out = X; pe.ldo = D; pe.tok_info = tok;
-    pe.imgs = reinterpret_cast<const ImgDesc*>(w); pe.cls = m->cls; pe.pos = m->pos; pe.base_grid = m->g0;
-    shapes.push_back({OP_PATCH, D, m->Kpad, QH, m->Kpad, m->patch_w, false, pe});
-  }
-  if (!m->layers.empty()) {
-    EpiArgs e1a; e1a.bias = ly.qkv_b; e1a.wscale = ly.qkv_s; e1a.out = QH; e1a.ldo = 3 * D;
-    EpiArgs e2a; e2a.bias = ly.o_b; e2a.wscale = ly.o_s; e2a.out = X; e2a.ldo = D;
-    EpiArgs e3a; e3a.bias = ly.fc1_b; e3a.wscale = ly.fc1_s; e3a.out = QH; e3a.ldo = F;
-    EpiArgs e4a; e4a.bias = ly.fc2_b; e4a.wscale = ly.fc2_s; e4a.out = X; e4a.ldo = D;
-    shapes.push_back({OP_QKV, 3 * D, D, Y, D, ly.qkv_w, fp8, e1a});
-    shapes.push_back({OP_OPROJ, D, D, Y, D, ly.o_w, fp8, e2a});
-    shapes.push_back({OP_FC1, F, D, Y, D, ly.fc1_w, fp8, e3a});
-    shapes.push_back({OP_FC2, D, F, QH, F, ly.fc2_w, fp8, e4a});
-  }
-  const int b = m_bucket(T);
-  for (const OpShape& o : shapes) {
-    float best = 1e30f;
-    int best_cfg = -1;
-    for (int cfg = 0; cfg < N_GEMM_CFGS; ++cfg) {
-      hipError_t err = gemm_bf16(o.A, o.lda, o.B, o.K, o.b8, T, o.N, o.K, o.op, cfg, o.e, s);
-      if (err != hipSuccess) continue;
-      VL_HIP(hipEventRecord(e0, s));
-      for (int r = 0; r < reps; ++r) VL_HIP(gemm_bf16(o.A, o.lda, o.B, o.K, o.b8, T, o.N, o.K, o.op, cfg, o.e, s));
-      VL_HIP(hipEventRecord(e1, s));
-      VL_HIP(hipEventSynchronize(e1));
-      float ms = 0.f;
-      VL_HIP(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best) { best = ms; best_cfg = cfg; }
+  // Tune each distinct part size (M bucket) on that part's buffers, which
+  // the run above filled with this batch's activations.
+  bool tuned[VL_N_M_BUCKETS] = {};
+  for (const Part& q : p.parts) {
+    const int T = q.T;
+    const int b = m_bucket(T);
+    if (tuned[b]) continue;
+    tuned[b] = true;
+    const bf16_t* Y = reinterpret_cast<const bf16_t*>(w + q.off_Y);
+    bf16_t* QH = reinterpret_cast<bf16_t*>(w + q.off_QH);
+    float* X = reinterpret_cast<float*>(w + q.off_X);
+    const int2* tok = reinterpret_cast<const int2*>(w + q.off_tok);
+    struct OpShape { int op, N, K; const bf16_t* A; int lda; const void* B; bool b8; EpiArgs e; };
+    std::vector<OpShape> shapes;
+    {
+      EpiArgs pe;
+      pe.bias = m->patch_b; pe.out = X; pe.ldo = D; pe.tok_info = tok;
+      pe.imgs = reinterpret_cast<const ImgDesc*>(w + q.off_imgs); pe.cls = m->cls; pe.pos = m->pos;
+      pe.base_grid = m->g0;
+      shapes.push_back({OP_PATCH, D, m->Kpad, QH, m->Kpad, m->patch_w, false, pe});
     }
-    m->tuning[o.op][b] = best_cfg;
+    if (!m->layers.empty()) {
+      EpiArgs e1a; e1a.bias = ly.qkv_b; e1a.wscale = ly.qkv_s; e1a.out = QH; e1a.ldo = 3 * D;
+      EpiArgs e2a; e2a.bias = ly.o_b; e2a.wscale = ly.o_s; e2a.out = X; e2a.ldo = D;
+      EpiArgs e3a; e3a.bias = ly.fc1_b; e3a.wscale = ly.fc1_s; e3a.out = QH; e3a.ldo = F;
+      EpiArgs e4a; e4a.bias = ly.fc2_b; e4a.wscale = ly.fc2_s; e4a.out = X; e4a.ldo = D;
+      shapes.push_back({OP_QKV, 3 * D, D, Y, D, ly.qkv_w, fp8, e1a});
+      shapes.push_back({OP_OPROJ, D, D, Y, D, ly.o_w, fp8, e2a});
+      shapes.push_back({OP_FC1, F, D, Y, D, ly.fc1_w, fp8, e3a});
+      shapes.push_back({OP_FC2, D, F, QH, F, ly.fc2_w, fp8, e4a});
+    }
+    for (const OpShape& o : shapes) {
+      float best = 1e30f;
+      int best_cfg = -1;
+      for (int cfg = 0; cfg < N_GEMM_CFGS; ++cfg) {
+        hipError_t err = gemm_bf16(o.A, o.lda, o.B, o.K, o.b8, T, o.N, o.K, o.op, cfg, o.e, s);
+        if (err != hipSuccess) continue;
+        VL_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r)
+          VL_HIP(gemm_bf16(o.A, o.lda, o.B, o.K, o.b8, T, o.N, o.K, o.op, cfg, o.e, s));
+        VL_HIP(hipEventRecord(e1, s));
+        VL_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        VL_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) { best = ms; best_cfg = cfg; }
+      }
+      m->tuning[o.op][b] = best_cfg;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -16,7 +16,7 @@ import torch
 
 __all__ = [
     "VlError", "VlConfig", "lib", "library_path", "VL_FP32", "VL_BF16", "VL_FP8W_BF16A",
-    "VL_HEAD_SOFTMAX", "VL_HEAD_SIGMOID", "VL_OPT_GRAPHS", "VL_OPT_TIMING",
+    "VL_HEAD_SOFTMAX", "VL_HEAD_SIGMOID", "VL_OPT_GRAPHS", "VL_OPT_TIMING", "VL_OPT_SPLIT",
     "VL_N_OPS", "OP_NAMES", "vl_model_op_times", "PRECISIONS", "HEADS",
     "vl_abi_version", "vl_weights_count", "vl_model_create", "vl_model_destroy",
     "vl_model_set_option", "vl_encode_workspace_bytes", "vl_encode_images", "vl_score",
@@ -27,7 +27,7 @@ __all__ = [
 
 VL_FP32, VL_BF16, VL_FP8W_BF16A = 0, 1, 2
 VL_HEAD_SOFTMAX, VL_HEAD_SIGMOID = 0, 1
-VL_OPT_GRAPHS, VL_OPT_TIMING = 0, 1
+VL_OPT_GRAPHS, VL_OPT_TIMING, VL_OPT_SPLIT = 0, 1, 2
 VL_N_OPS = 8
 OP_NAMES = ("patch_embed", "layernorm", "qkv_gemm", "attention", "oproj_gemm", "fc1_gemm",
             "fc2_gemm", "pool_proj_l2")
@@ -262,12 +262,14 @@ class Encoder:
     a reusable workspace tensor."""
 
     def __init__(self, cfg, weights: torch.Tensor, precision: str = "bf16",
-                 graphs: bool = False, stream=None):
+                 graphs: bool = False, stream=None, split: bool = False):
         self.cfg = cfg
         self.precision = precision
         self.handle = vl_model_create(cfg, precision, weights, stream)
         if graphs:
             vl_model_set_option(self.handle, VL_OPT_GRAPHS, 1)
+        if split:
+            vl_model_set_option(self.handle, VL_OPT_SPLIT, 1)
         self._ws: Optional[torch.Tensor] = None
         self.device = weights.device
 

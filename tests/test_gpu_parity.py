@@ -140,6 +140,32 @@ def test_graph_replay_matches_eager(V):
         assert np.array_equal(out.cpu().numpy(), eager)
 
 
+def test_two_part_split_bitwise(V):
+    """A batch above the split threshold runs as two parts on two streams;
+    every embedding equals the one-part run bit for bit, eager and replayed
+    from a captured graph (fork / join inside the capture)."""
+    sizes = [(224, 224)] * 20 + [(160, 224), (224, 96)] * 10
+    assert sum(1 + (h // 16) * (w // 16) for h, w in sizes) >= 4096
+    imgs = synth.make_images(sizes, 2400)
+    pix = torch.from_numpy(pack(imgs)).cuda()
+    w = torch.from_numpy(blob("tiny", 1000)).cuda()
+    for prec in ("bf16", "fp8w"):
+        one = V.Encoder(synth.MODELS["tiny"], w, prec, split=False)
+        ref = one.encode(pix, sizes_of(imgs)).cpu().numpy()
+        two = V.Encoder(synth.MODELS["tiny"], w, prec, split=True)
+        out = two.encode(pix, sizes_of(imgs)).cpu().numpy()
+        assert np.array_equal(out, ref), prec
+        g = V.Encoder(synth.MODELS["tiny"], w, prec, graphs=True, split=True)
+        res = torch.empty((len(imgs), 128), device="cuda")
+        for _ in range(3):
+            res.zero_()
+            g.encode(pix, sizes_of(imgs), out=res)
+            torch.cuda.synchronize()
+            assert np.array_equal(res.cpu().numpy(), ref), prec
+        for e in (one, two, g):
+            e.close()
+
+
 # --------------------------------------------------------------- scoring
 @pytest.mark.parametrize("head,scale,bias,m", [("softmax", 100.0, 0.0, 16),
                                                ("softmax", 100.0, 0.0, 1000),
