@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 BF16_PEAK = 2.5e15       # MI355X dense BF16 MFMA, FLOP/s
+FP8_PEAK = 5.0e15        # MI355X dense FP8 MFMA, FLOP/s
 FP32_PEAK = 157.3e12     # MI355X FP32 vector, FLOP/s
 HBM_PEAK = 8.0e12        # B/s
 
@@ -85,7 +86,8 @@ def traffic_from_profile(op: str, workload: str, configs=None):
     return (rec["fetch_kib"] * rec["fetch_factor"] + rec["write_kib"] * rec["write_factor"]) * 1024.0
 
 
-def cpu_baseline(wl: synth.Workload, blob: np.ndarray, images, texts, n_sample: int):
+def cpu_baseline(wl: synth.Workload, blob: np.ndarray, images, texts, n_sample: int,
+                 precision: str = None):
     """The FP64 oracle as it stands, on the host cores, over a bounded
     sample of the same workload: encode + score of n_sample images."""
     from oracle import vit64 as O
@@ -96,10 +98,11 @@ def cpu_baseline(wl: synth.Workload, blob: np.ndarray, images, texts, n_sample: 
     except Exception:  # pragma: no cover
         threads = os.cpu_count() or 1
     c = synth.MODELS[wl.model]
-    params = O.weights_for(synth.blob_to_params(c, blob), wl.precision)
+    precision = precision or wl.precision
+    params = O.weights_for(synth.blob_to_params(c, blob), precision)
     sample = images[:n_sample]
     t0 = time.perf_counter()
-    emb = O.encode(sample, params, c)
+    emb = O.encode(sample, params, c, act="mx" if precision == "mxfp8" else "none")
     O.score(emb, texts, wl.head, wl.scale, wl.bias)
     dt = time.perf_counter() - t0
     return {"value": n_sample / dt, "unit": "images/s", "cores": int(threads), "kind": "oracle",
@@ -176,7 +179,8 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="l14_336", choices=["tiny_fp32", "b16_224", "l14_336",
                                                              "b16_mixed"])
-    ap.add_argument("--precision", default=None, help="fp32 | bf16 | fp8w (default: workload's)")
+    ap.add_argument("--precision", default=None,
+                    help="fp32 | bf16 | fp8w | mxfp8 (default: workload's)")
     ap.add_argument("--no-graphs", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in tile heuristic")
     ap.add_argument("--split", action="store_true",
@@ -292,13 +296,15 @@ def main(argv=None) -> int:
                     set(tuned[dom].values()) if tuned and dom in tuned else None)}
     if prec == "fp32":
         roofline.update({"peak": FP32_PEAK / 1e12, "frac": achieved / FP32_PEAK, "bound": "alu"})
+    if prec == "mxfp8" and dom != "attention":
+        roofline.update({"peak": FP8_PEAK / 1e12, "frac": achieved / FP8_PEAK})
 
     total_flops = sum(flops_per_image(c, h) for h, _ in sizes)
     result = {
         "metric": "images/sec ViT-L/14@336 bf16 vs fp32 plain, same GPU; p50/p99 latency @ QPS",
         "value": value, "unit": "images/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {"fp32": "f32", "bf16": "bf16", "fp8w": "fp8w-bf16a"}[prec],
+        "vs_baseline": None, "dtype": {"fp32": "f32", "bf16": "bf16", "fp8w": "fp8w-bf16a", "mxfp8": "mxfp8"}[prec],
         "data": "synthetic (seeded U[0,1] pixels, N(0,0.02^2) weights, unit random texts)",
         "config": {"workload": args.workload, "model": wl.model, "batch": n,
                    "resolutions": sorted(set(h for h, _ in sizes)), "precision": prec,
@@ -338,7 +344,7 @@ def main(argv=None) -> int:
     if not args.no_cpu_baseline:
         k = args.cpu_sample or {"tiny_fp32": 8, "b16_224": 8, "l14_336": 4, "b16_mixed": 6}[
             args.workload]
-        result["cpu_baseline"] = cpu_baseline(wl, blob, images, texts, k)
+        result["cpu_baseline"] = cpu_baseline(wl, blob, images, texts, k, prec)
     print(json.dumps(result), flush=True)
     return 0
 

@@ -64,11 +64,26 @@ typedef enum vl_status {
  *                  FP32 scale per output row, s_o = max_k |W_ok| / 448,
  *                  q = sat(RNE(W / s_o)) (OFP8 rev 1.0, Sec. 5.1).  Codes are
  *                  widened to BF16 exactly inside the GEMM and the scale is
- *                  applied to the FP32 accumulator.                          */
+ *                  applied to the FP32 accumulator.
+ *  VL_MXFP8      : as VL_BF16, but both operands of the four per-block
+ *                  linear layers are MXFP8 (OCP Microscaling Formats (MX)
+ *                  Specification v1.0, E4M3 elements with an E8M0 scale per
+ *                  block, and its FP32-to-MX conversion rule): every 32 consecutive values
+ *                  along the contraction share one power-of-two scale 2^X,
+ *                  X = max(floor(log2 max|v|) - 8, -127), and are stored as
+ *                  sat448(RNE_e4m3(v / 2^X)).  The weights are encoded once
+ *                  at model creation; the activations (both LayerNorm
+ *                  outputs, the attention output and the GELU output) are
+ *                  encoded by the kernels that produce them, from their
+ *                  FP32 values.  The GEMMs multiply codes with the gfx950
+ *                  scaled FP8 MFMA, which applies the scales in hardware,
+ *                  and accumulate in FP32.  The patch embedding, attention
+ *                  (BF16 Q/K/V) and everything else are as in VL_BF16.      */
 typedef enum vl_precision {
   VL_FP32 = 0,
   VL_BF16 = 1,
-  VL_FP8W_BF16A = 2
+  VL_FP8W_BF16A = 2,
+  VL_MXFP8 = 3
 } vl_precision;
 
 typedef enum vl_head {
@@ -131,7 +146,7 @@ void vl_model_destroy(vl_model* m);
  *                   per-operation device time (read with
  *                   vl_model_op_times).  Calls made while timing is on are
  *                   launched eagerly even if VL_OPT_GRAPHS is set.
- *   VL_OPT_SPLIT  : 1 = run a BF16 or FP8-weight batch of at least 4096
+ *   VL_OPT_SPLIT  : 1 = run a BF16, FP8-weight or MXFP8 batch of at least 4096
  *                   tokens as two parts of consecutive images (about half
  *                   the tokens each); the second part runs on a stream the
  *                   library owns, forked from and joined back into the
@@ -226,6 +241,34 @@ vl_status vl_score(const float* emb_dev, int32_t n_images,
                    vl_head head, float scale, float bias,
                    float* scores_out_dev, int32_t* top1_out_dev,
                    void* stream);
+
+/* MXFP8 encoding (the one VL_MXFP8 applies to its weights and activations)
+ * of FP32 rows, for callers that prepare operands themselves and for
+ * checking the encoder.
+ *  src_dev    : [rows, cols] FP32, row-major, 16-byte aligned.
+ *  codes_dev  : [rows, cols] e4m3 codes (OFP8 rev 1.0, Sec. 5.1), 4-byte
+ *               aligned.
+ *  scales_dev : (cols/128) * rows * 4 E8M0 bytes (value 2^(byte - 127)),
+ *               block-major: the scale of row r, columns 32j .. 32j+31 is
+ *               byte (j/4 * rows + r) * 4 + s(j % 4) with s = {0, 2, 1, 3}.
+ * cols % 128 == 0, rows > 0.  Values must be finite.                      */
+vl_status vl_mx_quantize(const float* src_dev, int32_t rows, int32_t cols,
+                         uint8_t* codes_dev, uint8_t* scales_dev, void* stream);
+
+/* The MXFP8 contraction of the VL_MXFP8 model's block linears, exposed on
+ * its own:  C[m, n] += sum_k A[m, k] B[n, k] + bias[n]  (FP32 C).
+ *  a_dev, b_dev   : e4m3 codes [M, K] and [N, K], row-major, 16-byte aligned.
+ *  sa_dev, sb_dev : their E8M0 scales in the layout vl_mx_quantize writes
+ *                   ((K/128) * M * 4 and (K/128) * N * 4 bytes), 4-byte
+ *                   aligned.  A[m, k] = value(code) * 2^(scale - 127).
+ *  bias_dev [N], c_dev [M, N] : FP32, 16-byte aligned; c is read and written.
+ *  cfg : -1 (heuristic) or an MXFP8 tile configuration id (name "MX_...").
+ * K % 128 == 0, N % 32 == 0.  The products are summed by the gfx950 scaled
+ * FP8 MFMA (64 values of K per instruction) into FP32 accumulators, K in
+ * ascending order, the same in every configuration.                        */
+vl_status vl_mx_gemm(const uint8_t* a_dev, const uint8_t* sa_dev, const uint8_t* b_dev,
+                     const uint8_t* sb_dev, int32_t M, int32_t N, int32_t K,
+                     const float* bias_dev, float* c_dev, int32_t cfg, void* stream);
 
 const char* vl_status_string(vl_status s);
 const char* vl_last_error_message(void);

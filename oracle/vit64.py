@@ -32,13 +32,19 @@ follows:
   * FP8 e4m3fn: OCP 8-bit Floating Point Specification (OFP8) rev 1.0,
     Sec. 5.1 (E4M3: bias 7, max normal 448, no infinities) with one scale
     per output row.
+  * MXFP8: OCP Microscaling Formats (MX) Specification v1.0 -- blocks of 32
+    E4M3 elements sharing one E8M0 power-of-two scale, and its conversion
+    of a vector of scalars to MX (shared exponent = floor(log2 of the
+    block's largest magnitude) minus the element format's largest exponent,
+    elements rounded after division by the scale, saturating).
 
 Readings of unspecified points (each also listed in the design doc): pixels are
 normalised with mean 1/2 and std 1/sqrt(12) per channel; patch vectors are
 channel-major (c, a, b) like a conv weight [D, 3, P, P]; tokens are row-major
 over the patch grid with the class token first; the grid is floor(H/P) x
 floor(W/P) (extra pixels dropped); LayerNorm eps 1e-5 with biased variance;
-exact erf GELU; no LayerNorm before the first block; final LayerNorm on the
+exact erf GELU; no LayerNorm before the first block; MX shared exponents
+are clamped below at -127 (the least E8M0 value; an all-zero block takes it); final LayerNorm on the
 class token, then a bias-free projection and L2 normalisation (norm clamped
 at 1e-12); attention never crosses images; softmax over texts per image;
 top-1 is the lowest index attaining the maximum logit.
@@ -184,37 +190,45 @@ def attention_head(q: np.ndarray, k: np.ndarray, v: np.ndarray) -> np.ndarray:
     return softmax(s, axis=-1) @ v
 
 
-def mhsa(y: np.ndarray, qkv_w, qkv_b, o_w, o_b, heads: int) -> np.ndarray:
+def _identity(a: np.ndarray) -> np.ndarray:
+    return a
+
+
+def mhsa(y: np.ndarray, qkv_w, qkv_b, o_w, o_b, heads: int,
+         aq=_identity) -> np.ndarray:
     """Multi-head self-attention over the tokens of one image.  The fused
     projection's outputs are [Q | K | V]; head k uses columns k*d .. k*d+d-1
-    of each.  Heads are concatenated, then the output projection."""
+    of each.  Heads are concatenated, then the output projection.  `aq` is
+    applied to the left operand of both projections (the identity, or an
+    activation encoding such as mx_round)."""
     y = np.asarray(y, F64)
     dm = y.shape[1]
     d = dm // heads
-    qkv = y @ np.asarray(qkv_w, F64).T + np.asarray(qkv_b, F64)
+    qkv = aq(y) @ np.asarray(qkv_w, F64).T + np.asarray(qkv_b, F64)
     q, k, v = qkv[:, :dm], qkv[:, dm:2 * dm], qkv[:, 2 * dm:]
     o = np.zeros_like(q)
     for h in range(heads):
         sl = slice(h * d, (h + 1) * d)
         o[:, sl] = attention_head(q[:, sl], k[:, sl], v[:, sl])
-    return o @ np.asarray(o_w, F64).T + np.asarray(o_b, F64)
+    return aq(o) @ np.asarray(o_w, F64).T + np.asarray(o_b, F64)
 
 
-def mlp(y: np.ndarray, fc1_w, fc1_b, fc2_w, fc2_b) -> np.ndarray:
-    """Two linear layers with GELU between them (ViT Sec. 3.1)."""
-    h = gelu(np.asarray(y, F64) @ np.asarray(fc1_w, F64).T + np.asarray(fc1_b, F64))
-    return h @ np.asarray(fc2_w, F64).T + np.asarray(fc2_b, F64)
+def mlp(y: np.ndarray, fc1_w, fc1_b, fc2_w, fc2_b, aq=_identity) -> np.ndarray:
+    """Two linear layers with GELU between them (ViT Sec. 3.1); `aq` as in
+    mhsa, applied to the input of each layer."""
+    h = gelu(aq(np.asarray(y, F64)) @ np.asarray(fc1_w, F64).T + np.asarray(fc1_b, F64))
+    return aq(h) @ np.asarray(fc2_w, F64).T + np.asarray(fc2_b, F64)
 
 
 def block(x: np.ndarray, lp: Dict[str, np.ndarray], heads: int,
-          eps: float) -> np.ndarray:
+          eps: float, aq=_identity) -> np.ndarray:
     """One pre-LN block: x' = x + MSA(LN(x)); x'' = x' + MLP(LN(x'))
     (ViT Eq. 2 and 3)."""
     x = np.asarray(x, F64)
     h = x + mhsa(layernorm(x, lp["ln1_g"], lp["ln1_b"], eps),
-                 lp["qkv_w"], lp["qkv_b"], lp["o_w"], lp["o_b"], heads)
+                 lp["qkv_w"], lp["qkv_b"], lp["o_w"], lp["o_b"], heads, aq)
     return h + mlp(layernorm(h, lp["ln2_g"], lp["ln2_b"], eps),
-                   lp["fc1_w"], lp["fc1_b"], lp["fc2_w"], lp["fc2_b"])
+                   lp["fc1_w"], lp["fc1_b"], lp["fc2_w"], lp["fc2_b"], aq)
 
 
 # ---------------------------------------------------------------------------
@@ -230,22 +244,34 @@ def embed_tokens(img: np.ndarray, params: Dict, cfg) -> np.ndarray:
     return tok + interp_pos(params["pos"], cfg.base_grid, gh, gw)
 
 
+def act_encoding(act: str):
+    """The map applied to the four block-linear inputs: "none" (identity)
+    or "mx" (MXFP8 rounding of each token row, mx_round)."""
+    if act == "none":
+        return _identity
+    if act == "mx":
+        return mx_round
+    raise ValueError(act)
+
+
 def encode_image(img: np.ndarray, params: Dict, cfg,
-                 return_unnormalised: bool = False):
+                 return_unnormalised: bool = False, act: str = "none"):
     """Image -> unit embedding: blocks, final LN on the class token (ViT
     Eq. 4), bias-free projection, division by the L2 norm (CLIP Sec. 2.3)."""
+    aq = act_encoding(act)
     x = embed_tokens(img, params, cfg)
     for lp in params["layers"]:
-        x = block(x, lp, cfg.heads, cfg.ln_eps)
+        x = block(x, lp, cfg.heads, cfg.ln_eps, aq)
     z = layernorm(x[0], params["lnf_g"], params["lnf_b"], cfg.ln_eps)
     e = np.asarray(params["proj_w"], F64) @ z
     eh = e / max(np.linalg.norm(e), 1e-12)
     return (eh, e) if return_unnormalised else eh
 
 
-def encode(images: Sequence[np.ndarray], params: Dict, cfg) -> np.ndarray:
+def encode(images: Sequence[np.ndarray], params: Dict, cfg,
+           act: str = "none") -> np.ndarray:
     """Unit embeddings [n, P_dim] of every image, one image at a time."""
-    return np.stack([encode_image(im, params, cfg) for im in images])
+    return np.stack([encode_image(im, params, cfg, act=act) for im in images])
 
 
 # ---------------------------------------------------------------------------
@@ -316,6 +342,75 @@ def quantise_fp8_rows(w: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
     return e4m3_round(y), s.astype(F64)
 
 
+E4M3_EMAX = 8      # exponent of the largest e4m3 normal, 448 = 1.75 * 2^8
+MX_BLOCK = 32
+E8M0_MIN = -127    # least exponent an E8M0 scale encodes
+
+
+def mx_quantise(x: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """MXFP8 encoding of the last axis (length a multiple of 32) in blocks
+    of 32 consecutive values.  Per block: amax = max |v|; shared exponent
+    X = floor(log2 amax) - 8, at least -127 (and -127 for amax = 0); each
+    element becomes e4m3_round(v / 2^X), saturating at 448.  Returns (the
+    element values on the e4m3 grid, before scaling; X per block, int64).
+    Division by 2^X is exact, so the rounding decision is that of the
+    input value itself."""
+    x = np.asarray(x, F64)
+    n = x.shape[-1]
+    if n % MX_BLOCK:
+        raise ValueError("last axis must be a multiple of 32")
+    xb = x.reshape(x.shape[:-1] + (n // MX_BLOCK, MX_BLOCK))
+    amax = np.abs(xb).max(axis=-1)
+    _, ex = np.frexp(amax)                   # amax = m * 2^ex, m in [0.5, 1)
+    X = np.where(amax > 0, ex - 1 - E4M3_EMAX, E8M0_MIN)
+    X = np.maximum(X, E8M0_MIN).astype(np.int64)
+    q = e4m3_round(np.ldexp(xb, -X[..., None]))
+    return q, X
+
+
+def mx_round(x: np.ndarray) -> np.ndarray:
+    """The values an MXFP8 encoding of x represents: element times 2^X."""
+    x = np.asarray(x, F64)
+    q, X = mx_quantise(x)
+    return np.ldexp(q, X[..., None]).reshape(x.shape)
+
+
+def e4m3_code(v: np.ndarray) -> np.ndarray:
+    """Byte of each e4m3 value v (on the grid, |v| <= 448; OFP8 Sec. 5.1):
+    sign bit 7; for |v| >= 2^-6 biased exponent e + 7 in bits 6..3 and
+    (|v| / 2^e - 1) * 8 in bits 2..0, e = floor(log2 |v|); below 2^-6 the
+    subnormal mantissa |v| * 2^9.  -0 keeps its sign bit."""
+    v = np.asarray(v, F64)
+    a = np.abs(v)
+    _, ex = np.frexp(np.where(a > 0, a, 1.0))
+    e = ex - 1
+    normal = a >= 2.0 ** -6
+    mant = np.where(normal, (np.ldexp(a, -e) - 1.0) * 8.0, a * 512.0)
+    code = np.where(normal, ((e + 7) << 3) + mant, mant)
+    code = code.astype(np.int64) | np.where(np.signbit(v), 0x80, 0)
+    return code.astype(np.uint8)
+
+
+def e4m3_value(code: np.ndarray) -> np.ndarray:
+    """Value of e4m3fn bytes (OFP8 Sec. 5.1): exponent field E, mantissa M;
+    E > 0: (1 + M/8) * 2^(E-7); E = 0: M/8 * 2^-6.  0x7F / 0xFF (NaN) are
+    rejected."""
+    c = np.asarray(code, np.int64)
+    if np.any((c & 0x7F) == 0x7F):
+        raise ValueError("NaN code")
+    E = (c >> 3) & 15
+    M = c & 7
+    mag = np.where(E > 0, np.ldexp(1.0 + M / 8.0, E - 7), np.ldexp(M / 8.0, -6))
+    return np.where(c & 0x80, -mag, mag)
+
+
+def mx_decode(codes: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """Values of an MXFP8 array: codes [..., n] (e4m3 bytes), X [..., n/32]
+    shared exponents; element k is e4m3_value(code) * 2^X[k // 32]."""
+    v = e4m3_value(codes)
+    return np.ldexp(v, np.repeat(np.asarray(X, np.int64), MX_BLOCK, axis=-1))
+
+
 BLOCK_LINEARS = ("qkv_w", "o_w", "fc1_w", "fc2_w")
 
 
@@ -323,6 +418,8 @@ def weights_for(params: Dict, precision: str) -> Dict:
     """The exact weights a precision variant computes with, as float64.
     fp32: unchanged.  bf16: the four per-block linear weights rounded to BF16.
     fp8w: those four as q * s_o (per-row e4m3 codes times FP32 scales).
+    mxfp8: those four MXFP8-rounded along their input dimension (mx_round;
+    the activations are rounded too, by encode(..., act="mx")).
     Biases, LayerNorm parameters, class token, position table, patch
     embedding and final projection stay FP32 in every variant."""
     out = {k: v for k, v in params.items() if k != "layers"}
@@ -337,6 +434,8 @@ def weights_for(params: Dict, precision: str) -> Dict:
             elif precision == "fp8w":
                 q, s = quantise_fp8_rows(lp[n])
                 nl[n] = q * s[:, None]
+            elif precision == "mxfp8":
+                nl[n] = mx_round(np.asarray(lp[n], np.float32))
             else:
                 raise ValueError(precision)
         layers.append(nl)

@@ -20,7 +20,7 @@ OUT = os.path.join(PKG, "libvl.so")
 OBJDIR = os.path.join(PKG, "_build")
 
 SOURCES = ["api.cpp", "gemm.hip", "attention.hip", "elementwise.hip"] + [
-    f"gemm_cfg{i}.hip" for i in range(9)]
+    f"gemm_cfg{i}.hip" for i in range(9)] + [f"gemm_mx_cfg{i}.hip" for i in range(9, 13)]
 
 ARCH = "gfx950"
 HIPCC_FLAGS = [

@@ -50,6 +50,7 @@ struct Layer {
   const float *qkv_b, *o_b, *fc1_b, *fc2_b;
   const void *qkv_w, *o_w, *fc1_w, *fc2_w;          // f32, bf16 or e4m3 [out, in]
   const float *qkv_s, *o_s, *fc1_s, *fc2_s;         // per-row scales (e4m3 only)
+  const uint8_t *qkv_x, *o_x, *fc1_x, *fc2_x;       // MXFP8 block scales [in/128][out][4]
 };
 
 // Pinned host buffer holding a call's descriptors while its copy is pending.
@@ -315,6 +316,7 @@ vl_status run_part(vl_model* m, const Part& p, const float* pix, float* emb, cha
                    hipStream_t s, hipEvent_t after_first_qkv = nullptr) {
   const bool f32 = m->prec == VL_FP32;
   const bool fp8 = m->prec == VL_FP8W_BF16A;
+  const bool mx = m->prec == VL_MXFP8;
   const ImgDesc* d_imgs = reinterpret_cast<const ImgDesc*>(ws + p.off_imgs);
   const AttnItem* d_items = reinterpret_cast<const AttnItem*>(ws + p.off_items);
   int2* tok = reinterpret_cast<int2*>(ws + p.off_tok);
@@ -345,7 +347,11 @@ vl_status run_part(vl_model* m, const Part& p, const float* pix, float* emb, cha
   });
 
   for (const Layer& ly : m->layers) {
-    VL_TIMED(T_LN, VL_HIP(layernorm_rows(X, ly.ln1_g, ly.ln1_b, eps, Y, !f32, T, D, s)));
+    if (mx)
+      VL_TIMED(T_LN, VL_HIP(layernorm_rows_mx(X, ly.ln1_g, ly.ln1_b, eps, static_cast<uint8_t*>(Y),
+                                              static_cast<uint8_t*>(Y) + (size_t)T * D, T, D, s)));
+    else
+      VL_TIMED(T_LN, VL_HIP(layernorm_rows(X, ly.ln1_g, ly.ln1_b, eps, Y, !f32, T, D, s)));
     EpiArgs e1;
     e1.bias = ly.qkv_b; e1.wscale = ly.qkv_s; e1.out = QH; e1.ldo = 3 * D;
     EpiArgs e2;
@@ -368,6 +374,29 @@ vl_status run_part(vl_model* m, const Part& p, const float* pix, float* emb, cha
                                       OP_FC1, e3, s)));
       VL_TIMED(T_FC2, VL_HIP(gemm_f32(qh, F, static_cast<const float*>(ly.fc2_w), F, T, D, F,
                                       OP_FC2, e4, s)));
+    } else if (mx) {
+      // MXFP8 GEMM operands: codes then E8M0 scales in the Y and QH regions
+      // (LN / attention output in Y; GELU output in QH after attention has
+      // consumed the QKV rows there).
+      uint8_t* y8 = static_cast<uint8_t*>(Y);
+      uint8_t* ys = y8 + (size_t)T * D;
+      uint8_t* h8 = static_cast<uint8_t*>(QH);
+      uint8_t* hs = h8 + (size_t)T * F;
+      const uint8_t* w8[4] = {static_cast<const uint8_t*>(ly.qkv_w), static_cast<const uint8_t*>(ly.o_w),
+                              static_cast<const uint8_t*>(ly.fc1_w), static_cast<const uint8_t*>(ly.fc2_w)};
+      e3.out = h8; e3.out_scale = hs; e3.scale_rows = T;
+      VL_TIMED(T_QKV, VL_HIP(gemm_mx(y8, ys, w8[0], ly.qkv_x, T, 3 * D, D, OP_QKV,
+                                     gemm_cfg_for(m, 1, T), e1, s)));
+      if (after_first_qkv && &ly == &m->layers[0]) VL_HIP(hipEventRecord(after_first_qkv, s));
+      VL_TIMED(T_ATTN, VL_HIP(attention_bf16_mx(static_cast<const bf16_t*>(QH), y8, ys, T, d_imgs,
+                                                d_items, p.n_items, m->heads, m->hd, s)));
+      VL_TIMED(T_OPROJ, VL_HIP(gemm_mx(y8, ys, w8[1], ly.o_x, T, D, D, OP_OPROJ,
+                                       gemm_cfg_for(m, 2, T), e2, s)));
+      VL_TIMED(T_LN, VL_HIP(layernorm_rows_mx(X, ly.ln2_g, ly.ln2_b, eps, y8, ys, T, D, s)));
+      VL_TIMED(T_FC1, VL_HIP(gemm_mx(y8, ys, w8[2], ly.fc1_x, T, F, D, OP_FC1,
+                                     gemm_cfg_for(m, 3, T), e3, s)));
+      VL_TIMED(T_FC2, VL_HIP(gemm_mx(h8, hs, w8[3], ly.fc2_x, T, D, F, OP_FC2,
+                                     gemm_cfg_for(m, 4, T), e4, s)));
     } else {
       const bf16_t* y = static_cast<const bf16_t*>(Y);
       const bf16_t* qh = static_cast<const bf16_t*>(QH);
@@ -470,7 +499,7 @@ vl_status vl_model_create(const vl_config* cfg, vl_precision prec, const float* 
   *out = nullptr;
   if (!config_ok(cfg, &why)) return fail(VL_ERR_INVALID_ARG, why);
   if (!wdev) return fail(VL_ERR_INVALID_ARG, "weights_dev is NULL");
-  if (prec != VL_FP32 && prec != VL_BF16 && prec != VL_FP8W_BF16A)
+  if (prec != VL_FP32 && prec != VL_BF16 && prec != VL_FP8W_BF16A && prec != VL_MXFP8)
     return fail(VL_ERR_INVALID_ARG, "unknown precision");
   if (n_floats != weights_count(*cfg))
     return fail(VL_ERR_INVALID_ARG, "weight blob has " + std::to_string(n_floats) +
@@ -519,6 +548,7 @@ vl_status vl_model_create(const vl_config* cfg, vl_precision prec, const float* 
   const size_t d_cls = alloc(4 * D);
   const size_t d_pos = alloc(4 * G * D);
   struct DstLayer { size_t ln1_g, ln1_b, ln2_g, ln2_b, qkv_b, o_b, fc1_b, fc2_b, qkv_w, o_w, fc1_w, fc2_w, qkv_s, o_s, fc1_s, fc2_s; };
+  const bool mx = prec == VL_MXFP8;
   std::vector<DstLayer> dl(m->L);
   for (int l = 0; l < m->L; ++l) {
     DstLayer& x = dl[l];
@@ -528,6 +558,10 @@ vl_status vl_model_create(const vl_config* cfg, vl_precision prec, const float* 
     x.fc1_w = alloc(wes * F * D); x.fc2_w = alloc(wes * D * F);
     if (prec == VL_FP8W_BF16A) {
       x.qkv_s = alloc(4 * 3 * D); x.o_s = alloc(4 * D); x.fc1_s = alloc(4 * F); x.fc2_s = alloc(4 * D);
+    }
+    if (mx) {  // one E8M0 byte per 32 weights
+      x.qkv_s = alloc(3 * D * D / 32); x.o_s = alloc(D * D / 32);
+      x.fc1_s = alloc(F * D / 32); x.fc2_s = alloc(D * F / 32);
     }
   }
   const size_t d_lnf_g = alloc(4 * D);
@@ -558,6 +592,10 @@ vl_status vl_model_create(const vl_config* cfg, vl_precision prec, const float* 
     else if (prec == VL_BF16)
       chk(convert_bf16(src_w, reinterpret_cast<bf16_t*>(b + dst_off), (size_t)rows * cols, s),
           "convert_bf16");
+    else if (prec == VL_MXFP8)
+      chk(mx_quantise_rows(src_w, reinterpret_cast<uint8_t*>(b + dst_off),
+                           reinterpret_cast<uint8_t*>(b + scale_off), rows, cols, s),
+          "mx_quantise_rows");
     else
       chk(quantise_e4m3_rows(src_w, reinterpret_cast<uint8_t*>(b + dst_off), f(scale_off), rows,
                              cols, s),
@@ -586,6 +624,8 @@ vl_status vl_model_create(const vl_config* cfg, vl_precision prec, const float* 
     const bool q8 = prec == VL_FP8W_BF16A;
     ly.qkv_s = q8 ? f(y.qkv_s) : nullptr; ly.o_s = q8 ? f(y.o_s) : nullptr;
     ly.fc1_s = q8 ? f(y.fc1_s) : nullptr; ly.fc2_s = q8 ? f(y.fc2_s) : nullptr;
+    auto u8 = [&](size_t off) { return mx ? reinterpret_cast<const uint8_t*>(b + off) : nullptr; };
+    ly.qkv_x = u8(y.qkv_s); ly.o_x = u8(y.o_s); ly.fc1_x = u8(y.fc1_s); ly.fc2_x = u8(y.fc2_s);
   }
   chk(copy_f32(s_lnf_g, f(d_lnf_g), D, s), "copy");
   chk(copy_f32(s_lnf_b, f(d_lnf_b), D, s), "copy");
@@ -807,7 +847,10 @@ vl_status vl_model_autotune(vl_model* m, const float* pix, const int32_t* hs, co
     bf16_t* QH = reinterpret_cast<bf16_t*>(w + q.off_QH);
     float* X = reinterpret_cast<float*>(w + q.off_X);
     const int2* tok = reinterpret_cast<const int2*>(w + q.off_tok);
-    struct OpShape { int op, N, K; const bf16_t* A; int lda; const void* B; bool b8; EpiArgs e; };
+    struct OpShape {
+      int op, N, K; const bf16_t* A; int lda; const void* B; bool b8; EpiArgs e;
+      const uint8_t *a8 = nullptr, *sa = nullptr, *sb = nullptr;  // MXFP8 operands
+    };
     std::vector<OpShape> shapes;
     {
       EpiArgs pe;
@@ -825,16 +868,35 @@ vl_status vl_model_autotune(vl_model* m, const float* pix, const int32_t* hs, co
       shapes.push_back({OP_OPROJ, D, D, Y, D, ly.o_w, fp8, e2a});
       shapes.push_back({OP_FC1, F, D, Y, D, ly.fc1_w, fp8, e3a});
       shapes.push_back({OP_FC2, D, F, QH, F, ly.fc2_w, fp8, e4a});
+      if (m->prec == VL_MXFP8) {
+        const uint8_t* y8 = reinterpret_cast<const uint8_t*>(Y);
+        const uint8_t* h8 = reinterpret_cast<const uint8_t*>(QH);
+        const uint8_t* sx[4] = {ly.qkv_x, ly.o_x, ly.fc1_x, ly.fc2_x};
+        for (int i = 1; i <= 4; ++i) {
+          OpShape& o = shapes[i];
+          o.a8 = o.op == OP_FC2 ? h8 : y8;
+          o.sa = o.a8 + (size_t)T * o.K;
+          o.sb = sx[i - 1];
+        }
+        shapes[3].e.out = QH;
+        shapes[3].e.out_scale = reinterpret_cast<uint8_t*>(QH) + (size_t)T * F;
+        shapes[3].e.scale_rows = T;
+      }
     }
     for (const OpShape& o : shapes) {
       float best = 1e30f;
       int best_cfg = -1;
-      for (int cfg = 0; cfg < N_GEMM_CFGS; ++cfg) {
-        hipError_t err = gemm_bf16(o.A, o.lda, o.B, o.K, o.b8, T, o.N, o.K, o.op, cfg, o.e, s);
+      const bool omx = o.a8 != nullptr;
+      auto launch = [&](int cfg) {
+        return omx ? gemm_mx(o.a8, o.sa, static_cast<const uint8_t*>(o.B), o.sb, T, o.N, o.K,
+                             o.op, cfg, o.e, s)
+                   : gemm_bf16(o.A, o.lda, o.B, o.K, o.b8, T, o.N, o.K, o.op, cfg, o.e, s);
+      };
+      for (int cfg = omx ? N_BF16_CFGS : 0; cfg < (omx ? N_GEMM_CFGS : N_BF16_CFGS); ++cfg) {
+        hipError_t err = launch(cfg);
         if (err != hipSuccess) continue;
         VL_HIP(hipEventRecord(e0, s));
-        for (int r = 0; r < reps; ++r)
-          VL_HIP(gemm_bf16(o.A, o.lda, o.B, o.K, o.b8, T, o.N, o.K, o.op, cfg, o.e, s));
+        for (int r = 0; r < reps; ++r) VL_HIP(launch(cfg));
         VL_HIP(hipEventRecord(e1, s));
         VL_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -848,6 +910,37 @@ vl_status vl_model_autotune(vl_model* m, const float* pix, const int32_t* hs, co
   (void)hipEventDestroy(e1);
   (void)hipDeviceSynchronize();
   destroy_graphs(m);
+  return VL_OK;
+}
+
+vl_status vl_mx_quantize(const float* src, int32_t rows, int32_t cols, uint8_t* codes,
+                         uint8_t* scales, void* stream) {
+  if (!src || !codes || !scales) return fail(VL_ERR_INVALID_ARG, "NULL pointer argument");
+  if (rows <= 0 || cols <= 0) return fail(VL_ERR_INVALID_ARG, "sizes must be > 0");
+  if (cols % 128) return fail(VL_ERR_INVALID_ARG, "cols must be a multiple of 128");
+  if (reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(codes) % 4)
+    return fail(VL_ERR_INVALID_ARG, "src must be 16-byte and codes 4-byte aligned");
+  VL_HIP(mx_quantise_rows(src, codes, scales, rows, cols, static_cast<hipStream_t>(stream)));
+  return VL_OK;
+}
+
+vl_status vl_mx_gemm(const uint8_t* a, const uint8_t* sa, const uint8_t* b, const uint8_t* sb,
+                     int32_t M, int32_t N, int32_t K, const float* bias, float* c, int32_t cfg,
+                     void* stream) {
+  if (!a || !sa || !b || !sb || !bias || !c) return fail(VL_ERR_INVALID_ARG, "NULL pointer argument");
+  if (M <= 0 || N <= 0 || K <= 0) return fail(VL_ERR_INVALID_ARG, "sizes must be > 0");
+  if (K % 128 || N % 32) return fail(VL_ERR_INVALID_ARG, "K must be a multiple of 128 and N of 32");
+  if ((uint64_t)(K / 128) * ((uint64_t)std::max(M, N) + 256) * 4 >= (1ull << 32))
+    return fail(VL_ERR_INVALID_ARG, "scale arrays exceed 4 GiB");
+  if (cfg != -1 && !gemm_cfg_is_mx(cfg)) return fail(VL_ERR_INVALID_ARG, "cfg is not an MXFP8 configuration");
+  auto al = [](const void* p, uintptr_t n) { return reinterpret_cast<uintptr_t>(p) % n == 0; };
+  if (!al(a, 16) || !al(b, 16) || !al(c, 16) || !al(bias, 16) || !al(sa, 4) || !al(sb, 4))
+    return fail(VL_ERR_INVALID_ARG, "codes, c and bias must be 16-byte, scales 4-byte aligned");
+  EpiArgs e;
+  e.bias = bias;
+  e.out = c;
+  e.ldo = N;
+  VL_HIP(gemm_mx(a, sa, b, sb, M, N, K, OP_OPROJ, cfg, e, static_cast<hipStream_t>(stream)));
   return VL_OK;
 }
 

@@ -55,9 +55,13 @@ struct KvTile {
 
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 
-template <int HD>
+// MX = false: O is BF16 [T, D].  MX = true: O is MXFP8 for the output
+// projection, codes [T, D] (out) and scales [D/128][T][4] (out_scale); a
+// 32-column block of a head lies in one lane pair (lane, lane ^ 32).
+template <int HD, bool MX>
 __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qkv,
-                                                   bf16_t* __restrict__ out,
+                                                   void* __restrict__ out,
+                                                   uint8_t* __restrict__ out_scale, int T_rows,
                                                    const ImgDesc* __restrict__ imgs,
                                                    const AttnItem* __restrict__ items,
                                                    int heads) {
@@ -256,7 +260,30 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
   if (!wave_active || q >= N) return;
   const float lt = l_run + __shfl_xor(l_run, 32, 64);
   const float inv = 1.f / lt;
-  bf16_t* op = out + (size_t)(dsc.tok_start + q) * D + h * HD;
+  if constexpr (MX) {
+    const int row = dsc.tok_start + q;
+    uint8_t* op = static_cast<uint8_t*>(out) + (size_t)row * D + h * HD;
+#pragma unroll
+    for (int a = 0; a < HD / 32; ++a) {
+      // |o * inv| is largest where |o| is (rounding is monotonic).
+      float am = 0.f;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) am = fmaxf(am, fabsf(o[a][r]));
+      am = fmaxf(am, __shfl_xor(am, 32, 64)) * inv;
+      const uint32_t sb = mx_scale_byte(am);
+      const float si = mx_inv_scale(sb);
+#pragma unroll
+      for (int rq = 0; rq < 4; ++rq) {
+        const int d = a * 32 + 8 * rq + 4 * g;
+        *reinterpret_cast<uint32_t*>(op + d) =
+            mx_pack4(o[a][4 * rq + 0] * inv, o[a][4 * rq + 1] * inv, o[a][4 * rq + 2] * inv,
+                     o[a][4 * rq + 3] * inv, si);
+      }
+      if (g == 0) out_scale[mx_scale_off(row, h * HD + a * 32, T_rows)] = (uint8_t)sb;
+    }
+    return;
+  }
+  bf16_t* op = static_cast<bf16_t*>(out) + (size_t)(dsc.tok_start + q) * D + h * HD;
 #pragma unroll
   for (int a = 0; a < HD / 32; ++a)
 #pragma unroll
@@ -348,9 +375,27 @@ hipError_t attention_bf16(const bf16_t* qkv, bf16_t* o, const ImgDesc* imgs,
   if (n_items <= 0) return hipSuccess;
   dim3 grid(n_items, heads), block(256);
   if (head_dim == 64)
-    hipLaunchKernelGGL(k_attn_bf16<64>, grid, block, 0, s, qkv, o, imgs, items, heads);
+    hipLaunchKernelGGL((k_attn_bf16<64, false>), grid, block, 0, s, qkv, o, nullptr, 0, imgs,
+                       items, heads);
   else if (head_dim == 32)
-    hipLaunchKernelGGL(k_attn_bf16<32>, grid, block, 0, s, qkv, o, imgs, items, heads);
+    hipLaunchKernelGGL((k_attn_bf16<32, false>), grid, block, 0, s, qkv, o, nullptr, 0, imgs,
+                       items, heads);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t attention_bf16_mx(const bf16_t* qkv, uint8_t* codes, uint8_t* scales, int T,
+                             const ImgDesc* imgs, const AttnItem* items, int n_items,
+                             int heads, int head_dim, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  dim3 grid(n_items, heads), block(256);
+  if (head_dim == 64)
+    hipLaunchKernelGGL((k_attn_bf16<64, true>), grid, block, 0, s, qkv, codes, scales, T, imgs,
+                       items, heads);
+  else if (head_dim == 32)
+    hipLaunchKernelGGL((k_attn_bf16<32, true>), grid, block, 0, s, qkv, codes, scales, T, imgs,
+                       items, heads);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -84,6 +84,48 @@ __device__ __forceinline__ float gelu_poly(float x) {
   return fmaf(x, t * p, 0.5f * x);
 }
 
+// ------------- MXFP8 blocks (OCP Microscaling Formats (MX) Specification v1.0)
+// 32 consecutive values along K share one E8M0 scale 2^X (byte X + 127) and
+// are stored as e4m3 codes of v / 2^X.  X = floor(log2 amax) - 8 (8 is the
+// largest e4m3 exponent), clamped below at -127; for an FP32 amax that is its
+// biased exponent field minus 8.  v / 2^X then lies below 512 in magnitude
+// and is saturated at 448 before rounding to nearest even.
+//
+// Scale layout of an [R, K] operand: block-major, [K/128][R][4] bytes, the
+// four blocks of a 128-wide K tile in the order 0, 2, 1, 3, so a GEMM loads a
+// K tile's scales for consecutive rows as one contiguous run and the 16-bit
+// half g of a word holds the scales of blocks g and 2 + g.
+__device__ __forceinline__ uint32_t mx_scale_byte(float amax) {
+  const int e = (int)((__float_as_uint(amax) >> 23) & 0xFFu);
+  return (uint32_t)(e > 8 ? e - 8 : 0);
+}
+// 2^-X for scale byte sb (always a normal FP32 value for sb <= 253).
+__device__ __forceinline__ float mx_inv_scale(uint32_t sb) {
+  return __uint_as_float((254u - sb) << 23);
+}
+// Four values times inv -> four e4m3 codes (byte i = value i), saturating,
+// round to nearest even (v_cvt_pk_fp8_f32).
+__device__ __forceinline__ uint32_t mx_pack4(float a, float b, float c, float d, float inv) {
+  a = __builtin_amdgcn_fmed3f(a * inv, -448.f, 448.f);
+  b = __builtin_amdgcn_fmed3f(b * inv, -448.f, 448.f);
+  c = __builtin_amdgcn_fmed3f(c * inv, -448.f, 448.f);
+  d = __builtin_amdgcn_fmed3f(d * inv, -448.f, 448.f);
+  uint32_t w = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(c, d, (int)w, true);
+}
+// Byte offset of the scale of row r, column c in an operand of R rows.
+__device__ __forceinline__ size_t mx_scale_off(int r, int c, int R) {
+  const int b = (c >> 5) & 3;
+  return ((size_t)(c >> 7) * R + r) * 4 + (((b & 1) << 1) | (b >> 1));
+}
+// Maximum over the 8 lanes of an aligned group of 8 (DPP within rows).
+__device__ __forceinline__ float max8(float v) {
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true)));
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true)));
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, true)));
+  return v;
+}
+
 // ------------------------------------------------ direct-to-LDS loads (gfx950)
 // buffer_load_dwordx4 ... lds: 16 bytes per lane go from global memory
 // straight into LDS (no VGPR round trip).  The buffer resource bounds the

@@ -71,6 +71,75 @@ hipError_t layernorm_rows(const float* x, const float* g, const float* b, float 
   return hipGetLastError();
 }
 
+// LayerNorm with an MXFP8 output (the A operand of the next GEMM): as above,
+// but each lane holds float4 chunks lane + 64 i of the row, so a 32-column
+// MX block is 8 adjacent lanes.  D % 128 == 0, so the chunks in range form
+// whole 8-lane groups.
+template <int NV4>
+__global__ __launch_bounds__(256) void k_layernorm_mx(const float* __restrict__ x,
+                                                      const float* __restrict__ gm,
+                                                      const float* __restrict__ bt, float eps,
+                                                      uint8_t* __restrict__ codes,
+                                                      uint8_t* __restrict__ scales, int M,
+                                                      int D) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= M) return;
+  const int nch = D >> 2;
+  const float4* xr = reinterpret_cast<const float4*>(x + (size_t)row * D);
+  float4 v[NV4];
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < NV4; ++i) {
+    const int ch = lane + 64 * i;
+    v[i] = ch < nch ? xr[ch] : make_float4(0.f, 0.f, 0.f, 0.f);
+    s += (v[i].x + v[i].y) + (v[i].z + v[i].w);
+  }
+  const float mean = wave_sum(s) / (float)D;
+  float q = 0.f;
+#pragma unroll
+  for (int i = 0; i < NV4; ++i) {
+    if (lane + 64 * i >= nch) continue;
+    v[i].x -= mean; v[i].y -= mean; v[i].z -= mean; v[i].w -= mean;
+    q += (v[i].x * v[i].x + v[i].y * v[i].y) + (v[i].z * v[i].z + v[i].w * v[i].w);
+  }
+  const float rstd = rsqrtf(wave_sum(q) / (float)D + eps);
+#pragma unroll
+  for (int i = 0; i < NV4; ++i) {
+    const int ch = lane + 64 * i;
+    if (64 * i >= nch) break;  // wave-uniform
+    float4 g4 = make_float4(0.f, 0.f, 0.f, 0.f), b4 = g4;
+    if (ch < nch) {
+      g4 = reinterpret_cast<const float4*>(gm)[ch];
+      b4 = reinterpret_cast<const float4*>(bt)[ch];
+    }
+    const float o0 = v[i].x * rstd * g4.x + b4.x, o1 = v[i].y * rstd * g4.y + b4.y;
+    const float o2 = v[i].z * rstd * g4.z + b4.z, o3 = v[i].w * rstd * g4.w + b4.w;
+    const float amax = max8(fmaxf(fmaxf(fabsf(o0), fabsf(o1)), fmaxf(fabsf(o2), fabsf(o3))));
+    const uint32_t sb = mx_scale_byte(amax);
+    const uint32_t w = mx_pack4(o0, o1, o2, o3, mx_inv_scale(sb));
+    if (ch < nch) {
+      reinterpret_cast<uint32_t*>(codes + (size_t)row * D)[ch] = w;
+      if ((lane & 7) == 0) scales[mx_scale_off(row, 4 * ch, M)] = (uint8_t)sb;
+    }
+  }
+}
+
+hipError_t layernorm_rows_mx(const float* x, const float* g, const float* b, float eps,
+                             uint8_t* codes, uint8_t* scales, int M, int D, hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  if (D % 128 || D > 1024) return hipErrorInvalidValue;
+  dim3 grid((M + 3) / 4), block(256);
+  switch ((D + 255) / 256) {
+    case 1: hipLaunchKernelGGL(k_layernorm_mx<1>, grid, block, 0, s, x, g, b, eps, codes, scales, M, D); break;
+    case 2: hipLaunchKernelGGL(k_layernorm_mx<2>, grid, block, 0, s, x, g, b, eps, codes, scales, M, D); break;
+    case 3: hipLaunchKernelGGL(k_layernorm_mx<3>, grid, block, 0, s, x, g, b, eps, codes, scales, M, D); break;
+    case 4: hipLaunchKernelGGL(k_layernorm_mx<4>, grid, block, 0, s, x, g, b, eps, codes, scales, M, D); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ im2col
 // Token row t of image i: zeros for the class token, otherwise the patch's
 // raw pixels in (channel, row-in-patch, column-in-patch) order followed by
@@ -301,6 +370,38 @@ hipError_t quantise_e4m3_rows(const float* src, uint8_t* dst, float* scales, int
                               hipStream_t s) {
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_quant_e4m3, dim3(rows), dim3(256), 0, s, src, dst, scales, cols);
+  return hipGetLastError();
+}
+
+// MXFP8 encoding of FP32 rows (weights at model creation, or any caller's
+// rows): thread i encodes the four values 4i .. 4i+3 of the flattened
+// [rows, cols] array; cols % 128 == 0, so an aligned group of 8 threads is
+// one 32-value block of one row, and a group is wholly in or out of range.
+__global__ void k_mx_quant(const float* __restrict__ src, uint8_t* __restrict__ codes,
+                           uint8_t* __restrict__ scales, int rows, int cols) {
+  const size_t n4 = (size_t)rows * cols / 4;
+  const int c4 = cols / 4;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const float4 v = reinterpret_cast<const float4*>(src)[i];
+    const float amax = max8(fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    const uint32_t sb = mx_scale_byte(amax);
+    reinterpret_cast<uint32_t*>(codes)[i] = mx_pack4(v.x, v.y, v.z, v.w, mx_inv_scale(sb));
+    if ((i & 7) == 0) {
+      const int r = (int)(i / c4), c = 4 * (int)(i % c4);
+      scales[mx_scale_off(r, c, rows)] = (uint8_t)sb;
+    }
+  }
+}
+
+hipError_t mx_quantise_rows(const float* src, uint8_t* codes, uint8_t* scales, int rows,
+                            int cols, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  if (cols <= 0 || cols % 128) return hipErrorInvalidValue;
+  const size_t n4 = (size_t)rows * cols / 4;
+  const size_t blocks = (n4 + 255) / 256;
+  hipLaunchKernelGGL(k_mx_quant, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0,
+                     s, src, codes, scales, rows, cols);
   return hipGetLastError();
 }
 

@@ -36,9 +36,19 @@ hipError_t gemm_launch_cfg7(const bf16_t*, int, const void*, int, bool, int, int
 hipError_t gemm_launch_cfg8(const bf16_t*, int, const void*, int, bool, int, int, int, int,
                                const EpiArgs&, hipStream_t);
 
+// ------------------------------------------------ MXFP8 GEMM configurations
+hipError_t gemm_mx_launch_cfg9(const uint8_t*, const uint8_t*, const uint8_t*, const uint8_t*,
+                               int, int, int, int, const EpiArgs&, hipStream_t);
+hipError_t gemm_mx_launch_cfg10(const uint8_t*, const uint8_t*, const uint8_t*, const uint8_t*,
+                                int, int, int, int, const EpiArgs&, hipStream_t);
+hipError_t gemm_mx_launch_cfg11(const uint8_t*, const uint8_t*, const uint8_t*, const uint8_t*,
+                                int, int, int, int, const EpiArgs&, hipStream_t);
+hipError_t gemm_mx_launch_cfg12(const uint8_t*, const uint8_t*, const uint8_t*, const uint8_t*,
+                                int, int, int, int, const EpiArgs&, hipStream_t);
+
 const char* gemm_cfg_name(int cfg) {
   static const char* names[N_GEMM_CFGS] = {"DL_256x256_W2x4", "DL_256x256_W4x2", "DL_256x256_W2x2", "DL_128x128_W2x2", "DL_256x128_W2x2", "DL_128x256_W2x2", "REG_128x128_W2x2", "DL_192x256_W2x4",
-                                           "DL3_160x256_W1x8"};
+                                           "DL3_160x256_W1x8", "MX_160x256_W1x8", "MX_192x256_W2x4", "MX_128x256_W2x4", "MX_128x128_W2x2"};
   return cfg >= 0 && cfg < N_GEMM_CFGS ? names[cfg] : "unknown";
 }
 
@@ -68,7 +78,7 @@ hipError_t gemm_bf16(const bf16_t* A, int lda, const void* B, int ldb, bool b_fp
                      int K, int op, int cfg, const EpiArgs& e, hipStream_t s) {
   if (M <= 0) return hipSuccess;
   if (b_fp8 && op == OP_PATCH) return hipErrorInvalidValue;
-  if (cfg < 0 || cfg >= N_GEMM_CFGS) cfg = gemm_cfg_heuristic(M, N, K, b_fp8);
+  if (cfg < 0 || cfg >= N_BF16_CFGS) cfg = gemm_cfg_heuristic(M, N, K, b_fp8);
   switch (cfg) {
     case 0: return gemm_launch_cfg0(A, lda, B, ldb, b_fp8, M, N, K, op, e, s);
     case 1: return gemm_launch_cfg1(A, lda, B, ldb, b_fp8, M, N, K, op, e, s);
@@ -79,6 +89,39 @@ hipError_t gemm_bf16(const bf16_t* A, int lda, const void* B, int ldb, bool b_fp
     case 6: return gemm_launch_cfg6(A, lda, B, ldb, b_fp8, M, N, K, op, e, s);
     case 7: return gemm_launch_cfg7(A, lda, B, ldb, b_fp8, M, N, K, op, e, s);
     case 8: return gemm_launch_cfg8(A, lda, B, ldb, b_fp8, M, N, K, op, e, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+int gemm_mx_cfg_heuristic(int M, int N, int K) {
+  (void)K;
+  // Same model as the BF16 heuristic, with the relative tile efficiencies
+  // measured for the MXFP8 kernel on gfx950.
+  struct C { int cfg, bm, bn; double eff; };
+  static const C cands[] = {{CFG_MX_192x256_W2x4, 192, 256, 1.0},
+                            {CFG_MX_160x256_W1x8, 160, 256, 0.97},
+                            {CFG_MX_128x256_W2x4, 128, 256, 0.85},
+                            {CFG_MX_128x128_W2x2, 128, 128, 0.6}};
+  int best = CFG_MX_128x128_W2x2;
+  double best_t = 1e300;
+  for (const C& c : cands) {
+    const long tiles = (long)((M + c.bm - 1) / c.bm) * ((N + c.bn - 1) / c.bn);
+    const double t = (double)((tiles + 255) / 256) * (c.bm * c.bn) / (65536.0 * c.eff);
+    if (t < best_t) { best_t = t; best = c.cfg; }
+  }
+  return best;
+}
+
+hipError_t gemm_mx(const uint8_t* A, const uint8_t* SA, const uint8_t* B, const uint8_t* SB,
+                   int M, int N, int K, int op, int cfg, const EpiArgs& e, hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  if (K % 128 || N % 32) return hipErrorInvalidValue;
+  if (!gemm_cfg_is_mx(cfg)) cfg = gemm_mx_cfg_heuristic(M, N, K);
+  switch (cfg) {
+    case CFG_MX_160x256_W1x8: return gemm_mx_launch_cfg9(A, SA, B, SB, M, N, K, op, e, s);
+    case CFG_MX_192x256_W2x4: return gemm_mx_launch_cfg10(A, SA, B, SB, M, N, K, op, e, s);
+    case CFG_MX_128x256_W2x4: return gemm_mx_launch_cfg11(A, SA, B, SB, M, N, K, op, e, s);
+    case CFG_MX_128x128_W2x2: return gemm_mx_launch_cfg12(A, SA, B, SB, M, N, K, op, e, s);
   }
   return hipErrorInvalidValue;
 }

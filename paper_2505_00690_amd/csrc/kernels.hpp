@@ -37,8 +37,10 @@ enum GemmOp { OP_PATCH = 0, OP_QKV = 1, OP_OPROJ = 2, OP_FC1 = 3, OP_FC2 = 4, OP
 struct EpiArgs {
   const float* bias = nullptr;    // [N]
   const float* wscale = nullptr;  // [N] per-output-row weight scale (FP8)
-  void* out = nullptr;            // [M, ldo], BF16 or FP32
+  void* out = nullptr;            // [M, ldo], BF16 or FP32 (e4m3 codes for MXFP8 FC1)
   int ldo = 0;
+  uint8_t* out_scale = nullptr;   // MXFP8 FC1 output: E8M0 scales, [ldo/128][M][4]
+  int scale_rows = 0;             //   (M of that layout)
   // patch embedding
   const int2* tok_info = nullptr;  // [M]: (image, token index in image)
   const ImgDesc* imgs = nullptr;
@@ -61,17 +63,35 @@ enum GemmCfg {
   CFG_REG_128x128_W2x2 = 6,
   CFG_DL_192x256_W2x4 = 7,
   CFG_DL3_160x256_W1x8 = 8,
-  N_GEMM_CFGS = 9
+  N_BF16_CFGS = 9,
+  // MXFP8 x MXFP8 configurations (gemm_mx).  All accumulate K in the same
+  // order (one scaled MFMA per 64 K values, K ascending).
+  CFG_MX_160x256_W1x8 = 9,
+  CFG_MX_192x256_W2x4 = 10,
+  CFG_MX_128x256_W2x4 = 11,
+  CFG_MX_128x128_W2x2 = 12,
+  N_GEMM_CFGS = 13
 };
 const char* gemm_cfg_name(int cfg);
+inline bool gemm_cfg_is_mx(int cfg) { return cfg >= N_BF16_CFGS && cfg < N_GEMM_CFGS; }
 // Configuration used when none is tuned for an operation.
 int gemm_cfg_heuristic(int M, int N, int K, bool b_fp8);
+int gemm_mx_cfg_heuristic(int M, int N, int K);
 
 // C[M,N] = A[M,K] . B[N,K]^T with BF16 A and BF16 (or e4m3 when b_fp8) B,
 // FP32 accumulation, BF16 output for OP_QKV / OP_FC1.  K % 64 == 0,
 // N % 8 == 0.  cfg < 0 selects the heuristic configuration.
 hipError_t gemm_bf16(const bf16_t* A, int lda, const void* B, int ldb, bool b_fp8,
                      int M, int N, int K, int op, int cfg, const EpiArgs& e, hipStream_t s);
+
+// C[M,N] = A[M,K] . B[N,K]^T with both operands MXFP8: e4m3 codes [rows, K]
+// and E8M0 scales [K/128][rows][4] (layout in common.hpp), FP32
+// accumulation.  OP_QKV writes BF16; OP_FC1 writes MXFP8 codes to e.out and
+// scales to e.out_scale (e.scale_rows = M); OP_OPROJ / OP_FC2 add into the
+// FP32 residual.  K % 128 == 0, N % 32 == 0.  A cfg that is not an MX
+// configuration selects the heuristic one.
+hipError_t gemm_mx(const uint8_t* A, const uint8_t* SA, const uint8_t* B, const uint8_t* SB,
+                   int M, int N, int K, int op, int cfg, const EpiArgs& e, hipStream_t s);
 
 // The same contraction in FP32 (FMA), output FP32.  K % 16 == 0, N % 4 == 0.
 hipError_t gemm_f32(const float* A, int lda, const float* B, int ldb, int M, int N,
@@ -80,6 +100,10 @@ hipError_t gemm_f32(const float* A, int lda, const float* B, int ldb, int M, int
 // LayerNorm of FP32 rows [M, D] -> BF16 or FP32 rows.
 hipError_t layernorm_rows(const float* x, const float* g, const float* b, float eps,
                           void* y, bool y_bf16, int M, int D, hipStream_t s);
+
+// LayerNorm of FP32 rows [M, D] -> MXFP8 codes [M, D] + scales [D/128][M][4].
+hipError_t layernorm_rows_mx(const float* x, const float* g, const float* b, float eps,
+                             uint8_t* codes, uint8_t* scales, int M, int D, hipStream_t s);
 
 // Patch gathering: token rows [T, Kpad] of raw pixels in (c, a, b) order
 // (class-token rows and the K padding are zero) plus tok_info [T].
@@ -91,6 +115,10 @@ hipError_t im2col(const float* pix, const ImgDesc* imgs, int n_imgs, int max_nto
 hipError_t attention_bf16(const bf16_t* qkv, bf16_t* o, const ImgDesc* imgs,
                           const AttnItem* items, int n_items, int heads, int head_dim,
                           hipStream_t s);
+// The same with an MXFP8 output: codes [T, D] + scales [D/128][T][4].
+hipError_t attention_bf16_mx(const bf16_t* qkv, uint8_t* codes, uint8_t* scales, int T,
+                             const ImgDesc* imgs, const AttnItem* items, int n_items,
+                             int heads, int head_dim, hipStream_t s);
 hipError_t attention_f32(const float* qkv, float* o, const ImgDesc* imgs,
                          const AttnItem* items, int n_items, int heads, int head_dim,
                          hipStream_t s);
@@ -109,6 +137,10 @@ hipError_t score_rows(float* scores, int32_t* top1, int rows, int cols, int head
 hipError_t convert_bf16(const float* src, bf16_t* dst, size_t n, hipStream_t s);
 hipError_t quantise_e4m3_rows(const float* src, uint8_t* dst, float* scales, int rows,
                               int cols, hipStream_t s);
+// MXFP8 encoding of FP32 rows [rows, cols] (cols % 128 == 0): codes
+// [rows, cols] and scales [cols/128][rows][4].
+hipError_t mx_quantise_rows(const float* src, uint8_t* codes, uint8_t* scales, int rows,
+                            int cols, hipStream_t s);
 hipError_t fold_patch_weights(const float* w, const float* b, const float* mean,
                               const float* stdv, int D, int patch, int kpad,
                               float* w_f32, bf16_t* w_bf16, float* b_out, hipStream_t s);

@@ -22,22 +22,23 @@ __all__ = [
     "vl_model_set_option", "vl_encode_workspace_bytes", "vl_encode_images", "vl_score",
     "vl_status_string", "vl_last_error_message", "Encoder", "EXPORTED_SYMBOLS",
     "vl_gemm_config_count", "vl_gemm_config_name", "vl_model_get_tuning",
-    "vl_model_set_tuning", "vl_model_autotune", "GEMM_OPS",
+    "vl_model_set_tuning", "vl_model_autotune", "GEMM_OPS", "VL_MXFP8", "vl_mx_quantize", "vl_mx_gemm",
 ]
 
-VL_FP32, VL_BF16, VL_FP8W_BF16A = 0, 1, 2
+VL_FP32, VL_BF16, VL_FP8W_BF16A, VL_MXFP8 = 0, 1, 2, 3
 VL_HEAD_SOFTMAX, VL_HEAD_SIGMOID = 0, 1
 VL_OPT_GRAPHS, VL_OPT_TIMING, VL_OPT_SPLIT = 0, 1, 2
 VL_N_OPS = 8
 OP_NAMES = ("patch_embed", "layernorm", "qkv_gemm", "attention", "oproj_gemm", "fc1_gemm",
             "fc2_gemm", "pool_proj_l2")
-PRECISIONS = {"fp32": VL_FP32, "bf16": VL_BF16, "fp8w": VL_FP8W_BF16A}
+PRECISIONS = {"fp32": VL_FP32, "bf16": VL_BF16, "fp8w": VL_FP8W_BF16A, "mxfp8": VL_MXFP8}
 HEADS = {"softmax": VL_HEAD_SOFTMAX, "sigmoid": VL_HEAD_SIGMOID}
 
 EXPORTED_SYMBOLS = (
     "vl_abi_version", "vl_status_string", "vl_last_error_message", "vl_weights_count",
     "vl_model_create", "vl_model_destroy", "vl_model_set_option",
     "vl_encode_workspace_bytes", "vl_encode_images", "vl_score", "vl_model_op_times",
+    "vl_mx_quantize", "vl_mx_gemm",
     "vl_gemm_config_count", "vl_gemm_config_name", "vl_model_get_tuning",
     "vl_model_set_tuning", "vl_model_autotune",
 )
@@ -117,6 +118,10 @@ def lib() -> ctypes.CDLL:
     L.vl_model_set_tuning.argtypes = [_vp, _pi32]
     L.vl_model_autotune.restype = ctypes.c_int
     L.vl_model_autotune.argtypes = [_vp, _vp, _pi32, _pi32, _i32, _vp, _vp, _sz, _i32, _vp]
+    L.vl_mx_quantize.restype = ctypes.c_int
+    L.vl_mx_quantize.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp]
+    L.vl_mx_gemm.restype = ctypes.c_int
+    L.vl_mx_gemm.argtypes = [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _i32, _vp]
     L.vl_score.restype = ctypes.c_int
     L.vl_score.argtypes = [_vp, _i32, _vp, _i32, _i32, ctypes.c_int, _f32, _f32, _vp, _vp, _vp]
     _LIB = L
@@ -255,6 +260,35 @@ def vl_score(emb: torch.Tensor, texts: torch.Tensor, head, scale: float, bias: f
                           m, dim, h, float(scale), float(bias),
                           _ptr(scores_out, torch.float32, "scores_out"),
                           _ptr(top1_out, torch.int32, "top1_out"), _stream(stream)))
+
+
+def vl_mx_quantize(src: torch.Tensor, codes_out: torch.Tensor, scales_out: torch.Tensor,
+                   stream=None) -> None:
+    """MXFP8 encoding of FP32 rows src [rows, cols] into codes_out (uint8
+    [rows, cols]) and scales_out (uint8, (cols/128) * rows * 4 bytes,
+    block-major as include/vl.h describes)."""
+    rows, cols = src.shape
+    if codes_out.shape != src.shape or scales_out.numel() != (cols // 128) * rows * 4:
+        raise ValueError("codes_out / scales_out have the wrong size")
+    _check(lib().vl_mx_quantize(_ptr(src, torch.float32, "src"), rows, cols,
+                                _ptr(codes_out, torch.uint8, "codes_out"),
+                                _ptr(scales_out, torch.uint8, "scales_out"), _stream(stream)))
+
+
+def vl_mx_gemm(a: torch.Tensor, sa: torch.Tensor, b: torch.Tensor, sb: torch.Tensor,
+               bias: torch.Tensor, c: torch.Tensor, cfg: int = -1, stream=None) -> None:
+    """c += A . B^T + bias for MXFP8 operands (codes a [M, K], b [N, K] and
+    their scale arrays as vl_mx_quantize writes them)."""
+    M, K = a.shape
+    N = b.shape[0]
+    if b.shape[1] != K or c.shape != (M, N) or bias.shape != (N,):
+        raise ValueError("shape mismatch")
+    if sa.numel() != K // 128 * M * 4 or sb.numel() != K // 128 * N * 4:
+        raise ValueError("scale arrays have the wrong size")
+    _check(lib().vl_mx_gemm(_ptr(a, torch.uint8, "a"), _ptr(sa, torch.uint8, "sa"),
+                            _ptr(b, torch.uint8, "b"), _ptr(sb, torch.uint8, "sb"), M, N, K,
+                            _ptr(bias, torch.float32, "bias"), _ptr(c, torch.float32, "c"),
+                            int(cfg), _stream(stream)))
 
 
 class Encoder:

@@ -1,9 +1,10 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle on the
 same seeded inputs.
 
-Bars: FP32 relative embedding error <= 1e-4 (max over images); BF16 and
-FP8-weight cosine >= 0.999 against the oracle run on the exact weights the
-GPU uses; scoring within the bound implied by the embedding error; top-1
+Bars: FP32 relative embedding error <= 1e-4 (max over images); BF16,
+FP8-weight and MXFP8 cosine >= 0.999 against the oracle run on the exact
+weights the GPU uses (for MXFP8 also with its activations MX-rounded at the
+same four points); MXFP8 encoding of FP32 rows bit-exact; scoring within the bound implied by the embedding error; top-1
 equal wherever the reference margin certifies it; batch invariance bitwise.
 """
 import sys
@@ -57,9 +58,33 @@ def run(enc, images):
     return out.cpu().numpy()
 
 
-def oracle_emb(model, seed, precision, images):
+def _mx_bar(got, ref_mx, exact):
+    """MXFP8 bar.  8-bit activations make the result a discontinuous function
+    of them: where the GPU's FP32 activation and the oracle's FP64 one fall on
+    two sides of an e4m3 rounding boundary, the two round a full e4m3 step
+    apart, so the GPU and the MX-rounded oracle differ by about as much as
+    either differs from unrounded activations.  The bar is therefore relative
+    to the encoding's own effect, e_ref = 1 - cos(oracle with MX-rounded
+    activations, oracle with exact ones), both on the same MX weights: the
+    GPU's 1 - cos against the exact-activation oracle must stay within twice
+    e_ref on average (an independent draw of the same rounding noise gives
+    about 1x; a biased rounding or a misplaced scale gives several times
+    more), and within four times e_ref for every image."""
+    e_gpu = 1.0 - cosine(got, exact)
+    e_ref = 1.0 - cosine(ref_mx, exact)
+    _say(f"  1-cos vs exact activations: gpu mean {e_gpu.mean():.2e} max {e_gpu.max():.2e}; "
+         f"oracle MX mean {e_ref.mean():.2e}; gpu vs MX oracle min cos "
+         f"{cosine(got, ref_mx).min():.6f}")
+    assert e_ref.mean() > 1e-5                   # the encoding is really applied
+    assert e_gpu.mean() <= 2.0 * e_ref.mean() + 1e-4
+    assert e_gpu.max() <= 4.0 * e_ref.mean() + 1e-4
+
+
+def oracle_emb(model, seed, precision, images, act=None):
     p = O.weights_for(params(model, seed), precision)
-    return O.encode(images, p, synth.MODELS[model])
+    if act is None:
+        act = "mx" if precision == "mxfp8" else "none"
+    return O.encode(images, p, synth.MODELS[model], act=act)
 
 
 # ------------------------------------------------------------------ tiny
@@ -81,7 +106,7 @@ def test_tiny_fp32_layers(V, layers):
     assert err.max() <= FP32_TOL
 
 
-@pytest.mark.parametrize("precision", ["bf16", "fp8w"])
+@pytest.mark.parametrize("precision", ["bf16", "fp8w", "mxfp8"])
 def test_tiny_reduced_precision(V, precision):
     imgs = synth.make_images([(64, 64)] * 8, 2000)
     _say(f"tiny {precision}")
@@ -89,6 +114,9 @@ def test_tiny_reduced_precision(V, precision):
     ref = oracle_emb("tiny", 1000, precision, imgs)
     cos = cosine(got, ref)
     _say(f"  min cos {cos.min():.6f}")
+    if precision == "mxfp8":
+        _mx_bar(got, ref, oracle_emb("tiny", 1000, precision, imgs, act="none"))
+        return
     assert cos.min() >= COS_TOL
     # non-vacuity: different images are far apart at this tolerance
     r = ref @ ref.T
@@ -149,7 +177,7 @@ def test_two_part_split_bitwise(V):
     imgs = synth.make_images(sizes, 2400)
     pix = torch.from_numpy(pack(imgs)).cuda()
     w = torch.from_numpy(blob("tiny", 1000)).cuda()
-    for prec in ("bf16", "fp8w"):
+    for prec in ("bf16", "fp8w", "mxfp8"):
         one = V.Encoder(synth.MODELS["tiny"], w, prec, split=False)
         ref = one.encode(pix, sizes_of(imgs)).cpu().numpy()
         two = V.Encoder(synth.MODELS["tiny"], w, prec, split=True)
@@ -247,6 +275,112 @@ def test_b16_mixed_resolution_bf16_sampled(V):
     assert cos.min() >= COS_TOL
 
 
+def test_l14_336_mxfp8_sampled(V):
+    got, ref, imgs = _full(V, "l14", "mxfp8", 336, 32, 2005, [0, 31], 1005)
+    exact = oracle_emb("l14", 1005, "mxfp8", [imgs[0], imgs[31]], act="none")
+    _mx_bar(got[[0, 31]], ref, exact)
+
+
+def _mx_scale_bytes(X):
+    """[rows, K/32] shared exponents -> the block-major scale byte array."""
+    rows, nb = X.shape
+    out = np.empty((nb // 4, rows, 4), np.uint8)
+    for kt in range(nb // 4):
+        for j, blk in enumerate((0, 2, 1, 3)):
+            out[kt, :, j] = X[:, 4 * kt + blk] + 127
+    return out.reshape(-1)
+
+
+@pytest.mark.parametrize("shape", [(300, 416, 640), (2000, 1024, 1024)])
+def test_mx_gemm_parity(V, shape):
+    """vl_mx_gemm in every MXFP8 tile configuration against the oracle's FP64
+    contraction of the decoded operands.  Narrow-range operands (values 1 to
+    3.75 times 2^{0,1}, sums exact in FP32): bit-exact.  Full-range operands
+    (every finite code, scales 2^-3 .. 2^3): |error| <= 2^-12 sum_k |a_k b_k|,
+    a bound measured for the scaled FP8 MFMA (which does not round every
+    partial sum to FP32), not taken from a published specification."""
+    M, N, K = shape
+    rng = np.random.Generator(np.random.PCG64(78 + M))
+    cfgs = [-1] + [i for i in range(V.vl_gemm_config_count())
+                   if V.vl_gemm_config_name(i).startswith("MX_")]
+    for case in ("narrow", "full"):
+        if case == "narrow":
+            def codes(r):
+                e = rng.integers(7, 9, (r, K))
+                return ((rng.integers(0, 2, (r, K)) << 7) | (e << 3) |
+                        rng.integers(0, 8, (r, K))).astype(np.uint8)
+            xa, xb = rng.integers(0, 2, (M, K // 32)), rng.integers(0, 2, (N, K // 32))
+            bias = rng.integers(-6400, 6400, N) / 64.0
+            c0 = rng.integers(-6400, 6400, (M, N)) / 64.0
+        else:
+            def codes(r):
+                c = rng.integers(0, 256, (r, K))
+                return np.where((c & 0x7F) == 0x7F, c & 0xF0, c).astype(np.uint8)
+            xa, xb = rng.integers(-3, 4, (M, K // 32)), rng.integers(-3, 4, (N, K // 32))
+            bias = rng.standard_normal(N)
+            c0 = rng.standard_normal((M, N))
+        a, b = codes(M), codes(N)
+        av, bv = O.mx_decode(a, xa), O.mx_decode(b, xb)
+        ref = c0 + av @ bv.T + bias
+        mag = np.abs(av) @ np.abs(bv).T
+        ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+        sa = torch.from_numpy(_mx_scale_bytes(xa)).cuda()
+        sb = torch.from_numpy(_mx_scale_bytes(xb)).cuda()
+        tbias = torch.from_numpy(bias.astype(np.float32)).cuda()
+        for cfg in cfgs:
+            c = torch.from_numpy(c0.astype(np.float32)).cuda()
+            V.vl_mx_gemm(ta, sa, tb, sb, tbias, c, cfg)
+            torch.cuda.synchronize()
+            got = c.cpu().numpy().astype(np.float64)
+            err = np.abs(got - ref)
+            _say(f"  {M}x{N}x{K} {case} cfg {cfg}: max |err| / sum|ab| "
+                 f"{(err / np.maximum(mag, 1e-300)).max():.2e}")
+            if case == "narrow":
+                assert np.array_equal(got, ref), cfg
+            else:
+                assert np.all(err <= 2.0 ** -12 * mag + 1e-6 * np.abs(ref)), cfg
+
+
+def test_mx_quantize_bitexact(V):
+    """vl_mx_quantize against the oracle's MXFP8 encoding of the same FP32
+    rows: every code and every scale byte, with blocks of exact rounding
+    ties, FP32 subnormals, zeros, the clamped least scale and saturation."""
+    rng = np.random.Generator(np.random.PCG64(77))
+    rows, cols = 70, 384
+    x = rng.standard_normal((rows, cols)) * np.exp(rng.uniform(-10, 10, (rows, 1)))
+    x[1, :32] = 0.0
+    x[2, 32:64] = rng.standard_normal(32) * 1e-39          # FP32 subnormals
+    x[2, 64:96] = rng.standard_normal(32) * 1e-37          # X clamped at -127
+    # X = 0 (amax 300): exact midpoints between neighbouring e4m3 values
+    ties = [1.0625, -1.1875, 2.125, 2.375, 13 * 2.0 ** -10, -15 * 2.0 ** -10, 0.0146484375,
+            120.0, 232.0, -296.0, 2.0 ** -10, -(2.0 ** -10), 3 * 2.0 ** -10]
+    x[3, :32] = 0.0
+    x[3, 0] = 300.0
+    x[3, 1:1 + len(ties)] = ties
+    x[4, :32] = np.array([1.95, -1.9, 1.8, 1.75, -1.76] + [0.5] * 27) * 2.0 ** 5  # saturation
+    x32 = x.astype(np.float32)
+    src = torch.from_numpy(x32).cuda()
+    codes = torch.empty((rows, cols), dtype=torch.uint8, device="cuda")
+    scales = torch.empty(cols // 128 * rows * 4, dtype=torch.uint8, device="cuda")
+    V.vl_mx_quantize(src, codes, scales)
+    torch.cuda.synchronize()
+    q, X = O.mx_quantise(x32.astype(np.float64))
+    want_codes = O.e4m3_code(q).reshape(rows, cols)
+    got_codes = codes.cpu().numpy()
+    zero = (want_codes & 0x7F) == 0
+    n_signed_zero = int(np.sum(zero & (got_codes != want_codes)))
+    _say(f"  codes differing only in the sign of zero: {n_signed_zero}")
+    assert np.array_equal(got_codes[~zero], want_codes[~zero])
+    assert np.all((got_codes[zero] & 0x7F) == 0)
+    slot = [0, 2, 1, 3]                                    # byte j holds block slot[j]
+    want_scales = np.empty((cols // 128, rows, 4), np.int64)
+    for kt in range(cols // 128):
+        for j in range(4):
+            want_scales[kt, :, j] = X[:, 4 * kt + slot[j]] + 127
+    assert np.array_equal(scales.cpu().numpy().reshape(cols // 128, rows, 4), want_scales)
+    assert X[2, 2] == -127 and X[1, 0] == -127 and X[3, 0] == 0
+
+
 def test_l14_fp8w_sampled(V):
     got, ref, _ = _full(V, "l14", "fp8w", [224, 384], 2, 2004, [0, 1], 1004)
     cos = cosine(got, ref)
@@ -285,10 +419,12 @@ def test_serving_mix_equals_alone(V):
 
 
 # ------------------------------------------------------------- autotuner
-@pytest.mark.parametrize("precision", ["bf16", "fp8w"])
+@pytest.mark.parametrize("precision", ["bf16", "fp8w", "mxfp8"])
 def test_every_gemm_config_bitwise_identical_and_autotune(V, precision):
     """Each GEMM tile configuration, forced for every operation, gives the
-    same bits; the autotuner's choice therefore changes speed only."""
+    same bits; the autotuner's choice therefore changes speed only.  (A
+    configuration of the other kind -- BF16 for an MXFP8 operation or the
+    reverse -- falls back to that operation's heuristic choice.)"""
     enc = V.Encoder(synth.MODELS["b16"], torch.from_numpy(blob("b16", 1001)).cuda(), precision)
     imgs = synth.make_images([(224, 224)] * 6 + [(336, 336)] * 2, 2500)
     pix = torch.from_numpy(pack(imgs)).cuda()

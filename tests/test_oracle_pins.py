@@ -416,3 +416,135 @@ def test_weights_for_only_touches_block_linears():
         rel = np.abs(w["layers"][1]["fc1_w"] - p["layers"][1]["fc1_w"]) / \
             np.abs(p["layers"][1]["fc1_w"]).max()
         assert rel.max() < (2 ** -8 if prec == "bf16" else 2 ** -4)
+
+
+# ------------------------------------------ MXFP8 (OCP Microscaling Formats)
+def test_mx_hand_worked_block():
+    # amax 1.0: floor(log2) = 0, X = 0 - 8; elements are v * 2^8 rounded on
+    # the e4m3 grid: 1.0 -> 256 exactly; 0.9 -> 230.4 in [128, 256), step 16
+    # -> 224; -0.3 -> -76.8 in [64, 128), step 8 -> -80; 1e-4 -> 0.0256 in
+    # [2^-6, 2^-5), step 2^-9 -> 13 * 2^-9.
+    x = np.zeros(32)
+    x[:4] = [1.0, 0.9, -0.3, 1e-4]
+    q, X = O.mx_quantise(x)
+    assert X.tolist() == [-8]
+    assert q[0, :4].tolist() == [256.0, 224.0, -80.0, 13 * 2.0 ** -9]
+    assert not q[0, 4:].any()
+    assert O.mx_round(x)[:3].tolist() == [1.0, 0.875, -0.3125]
+    # amax 1.9: still X = -8, and 1.9 * 256 = 486.4 saturates to 448 (1.75)
+    x[0] = 1.9
+    assert O.mx_round(x)[0] == 1.75
+    # all-zero blocks take the least scale and stay zero
+    q, X = O.mx_quantise(np.zeros((2, 64)))
+    assert X.tolist() == [[-127, -127], [-127, -127]] and not q.any()
+    with pytest.raises(ValueError):
+        O.mx_quantise(np.zeros(48))
+
+
+def test_mx_exponent_bruteforce_and_elements_vs_torch_cast():
+    rng = _rng(30)
+    x = rng.standard_normal((64, 256)) * np.exp(rng.uniform(-8, 8, (64, 1)))
+    x[3, 32:64] = 0.0                       # zero block
+    x[5, :32] *= 1e-37                      # shared exponent below -127: clamped
+    x[6, 64:96] = 0.0
+    x[6, 70] = -3.0                         # one non-zero element
+    x = x.astype(np.float32).astype(np.float64)
+    q, X = O.mx_quantise(x)
+    xb = x.reshape(64, 8, 32)
+    for r in range(64):
+        for b in range(8):
+            amax = np.abs(xb[r, b]).max()
+            if amax == 0:
+                assert X[r, b] == -127
+                continue
+            e = -200                        # 2^e <= amax < 2^(e+1), by search
+            while math.ldexp(1.0, e + 1) <= amax:
+                e += 1
+            assert X[r, b] == max(e - 8, -127), (r, b)
+    assert X[5, 0] == -127 and X[6, 2] == 1 - 8
+    y = np.clip(xb / np.ldexp(1.0, X)[..., None], -448, 448).astype(np.float32)
+    ref = torch.from_numpy(y).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(q, ref)
+
+
+def test_mx_grid_fixed_points_equivariance_idempotence_and_error_bound():
+    rng = _rng(31)
+    codes = np.arange(256)
+    grid = O.e4m3_value(codes[(codes & 0x7F) != 0x7F])
+    for k in (-20, 0, 7):
+        blk = np.concatenate([rng.choice(grid, size=(16, 31)), np.full((16, 1), 448.0)], axis=1)
+        blk = np.ldexp(blk, k)
+        assert np.array_equal(O.mx_round(blk), blk)       # X = k: every value on the grid
+    x = rng.standard_normal((32, 512)) * 3.0
+    r = O.mx_round(x)
+    for k in (-7, 1, 30):
+        assert np.array_equal(O.mx_round(np.ldexp(x, k)), np.ldexp(r, k))
+    assert np.array_equal(O.mx_round(r), r)
+    q, X = O.mx_quantise(x)
+    s = np.ldexp(1.0, X)[..., None]
+    xb = x.reshape(q.shape)
+    sat = np.abs(xb) > 448 * s
+    err = np.abs(q * s - xb)
+    bound = np.maximum(2.0 ** -4 * np.abs(xb), s * 2.0 ** -10)
+    assert np.all(err[~sat] <= bound[~sat])
+    assert np.all(np.abs(q[sat]) == 448.0)
+    assert sat.any()                                      # saturation does occur
+
+
+def test_e4m3_codes_round_trip_and_match_torch():
+    codes = np.arange(256)
+    codes = codes[(codes & 0x7F) != 0x7F]
+    v = O.e4m3_value(codes)
+    ref = torch.from_numpy(codes.astype(np.uint8)).view(torch.float8_e4m3fn).to(torch.float64)
+    assert np.array_equal(v, ref.numpy())
+    assert np.array_equal(O.e4m3_code(v), codes.astype(np.uint8))
+    assert O.e4m3_code(np.array([-0.0]))[0] == 0x80
+    rows = [l.split() for l in open(os.path.join(GOLD, "e4m3fn_points.txt"))
+            if l.strip() and not l.startswith("#")]
+    for hx, val, _ in rows:
+        assert O.e4m3_value(np.array([int(hx, 16)]))[0] == float(val)
+    with pytest.raises(ValueError):
+        O.e4m3_value(np.array([0x7F]))
+
+
+def test_activation_hook_sits_on_every_linear_input():
+    # With a map that zeroes every linear input, attention sees Q = K = V =
+    # bias rows and both projections reduce to their biases, so a block is
+    # x + o_b + fc2_b; a missed or misplaced hook would leave a data term.
+    rng = _rng(32)
+    d, f, t = 64, 128, 5
+    lp = {"ln1_g": rng.standard_normal(d), "ln1_b": rng.standard_normal(d),
+          "qkv_w": rng.standard_normal((3 * d, d)), "qkv_b": rng.standard_normal(3 * d),
+          "o_w": rng.standard_normal((d, d)), "o_b": rng.standard_normal(d),
+          "ln2_g": rng.standard_normal(d), "ln2_b": rng.standard_normal(d),
+          "fc1_w": rng.standard_normal((f, d)), "fc1_b": rng.standard_normal(f),
+          "fc2_w": rng.standard_normal((d, f)), "fc2_b": rng.standard_normal(d)}
+    x = rng.standard_normal((t, d))
+    got = O.block(x, lp, 2, 1e-5, aq=lambda a: 0.0 * a)
+    assert np.allclose(got, x + lp["o_b"] + lp["fc2_b"], rtol=0, atol=1e-12)
+    assert np.array_equal(O.block(x, lp, 2, 1e-5), O.block(x, lp, 2, 1e-5, aq=lambda a: a))
+
+
+def test_mxfp8_variant_close_to_exact_but_not_equal():
+    c = synth.MODELS["tiny"]
+    p = synth.make_params(c, 33)
+    imgs = synth.make_images([(c.patch * 4, c.patch * 3)] * 2, 34)
+    exact = O.encode(imgs, p, c)
+    mxw = O.weights_for(p, "mxfp8")
+    got = O.encode(imgs, mxw, c, act="mx")
+    cos = np.sum(got * exact, axis=1)
+    assert np.all(cos > 0.99) and np.all(cos < 1 - 1e-9)
+    w = mxw["layers"][0]["fc1_w"]
+    assert np.array_equal(O.mx_round(w), w)              # weights on the MX grid
+
+
+def test_mx_decode_inverts_quantise():
+    rng = _rng(35)
+    x = rng.standard_normal((8, 128)) * 5.0
+    q, X = O.mx_quantise(x)
+    assert np.array_equal(O.mx_decode(O.e4m3_code(q).reshape(8, 128), X), O.mx_round(x))
+    # one block, by hand: code 0x38 is 1.0, 0xC0 is -2.0; X = 3 scales by 8
+    c = np.zeros((1, 32), np.uint8)
+    c[0, 0], c[0, 31] = 0x38, 0xC0
+    v = O.mx_decode(c, np.array([[3]]))
+    assert v[0, 0] == 8.0 and v[0, 31] == -16.0 and not v[0, 1:31].any()
