@@ -292,7 +292,7 @@ def main(argv=None) -> int:
                 "avg_launch_ms": avg_s * 1e3,
                 "flops_per_launch": flops_launch,
                 "traffic": traffic_from_profile(
-                    dom, args.workload,
+                    dom, args.workload + ("_mxfp8" if prec == "mxfp8" else ""),
                     set(tuned[dom].values()) if tuned and dom in tuned else None)}
     if prec == "fp32":
         roofline.update({"peak": FP32_PEAK / 1e12, "frac": achieved / FP32_PEAK, "bound": "alu"})

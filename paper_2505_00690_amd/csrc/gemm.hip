@@ -99,7 +99,7 @@ int gemm_mx_cfg_heuristic(int M, int N, int K) {
   // measured for the MXFP8 kernel on gfx950.
   struct C { int cfg, bm, bn; double eff; };
   static const C cands[] = {{CFG_MX_192x256_W2x4, 192, 256, 1.0},
-                            {CFG_MX_160x256_W1x8, 160, 256, 0.97},
+                            {CFG_MX_160x256_W1x8, 160, 256, 0.95},
                             {CFG_MX_128x256_W2x4, 128, 256, 0.85},
                             {CFG_MX_128x128_W2x2, 128, 128, 0.6}};
   int best = CFG_MX_128x128_W2x2;

@@ -25,7 +25,31 @@ namespace vl {
 typedef int32_t i32x8 __attribute__((ext_vector_type(8)));
 constexpr int MXK = 128;  // K elements (bytes) per LDS tile
 
-template <int BM, int BN, int WGM, int WGN, int OP>
+// Wait until at most n of this wave's global loads are outstanding (n is
+// wave-uniform; s_waitcnt takes an immediate).
+__device__ __forceinline__ void wait_vm_le(int n) {
+  switch (n) {
+    case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+    case 1: asm volatile("s_waitcnt vmcnt(1)" ::: "memory"); break;
+    case 2: asm volatile("s_waitcnt vmcnt(2)" ::: "memory"); break;
+    case 3: asm volatile("s_waitcnt vmcnt(3)" ::: "memory"); break;
+    case 4: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
+    case 5: asm volatile("s_waitcnt vmcnt(5)" ::: "memory"); break;
+    case 6: asm volatile("s_waitcnt vmcnt(6)" ::: "memory"); break;
+    case 7: asm volatile("s_waitcnt vmcnt(7)" ::: "memory"); break;
+    case 8: asm volatile("s_waitcnt vmcnt(8)" ::: "memory"); break;
+    case 9: asm volatile("s_waitcnt vmcnt(9)" ::: "memory"); break;
+    case 10: asm volatile("s_waitcnt vmcnt(10)" ::: "memory"); break;
+    case 11: asm volatile("s_waitcnt vmcnt(11)" ::: "memory"); break;
+    case 12: asm volatile("s_waitcnt vmcnt(12)" ::: "memory"); break;
+    case 13: asm volatile("s_waitcnt vmcnt(13)" ::: "memory"); break;
+    case 14: asm volatile("s_waitcnt vmcnt(14)" ::: "memory"); break;
+    case 15: asm volatile("s_waitcnt vmcnt(15)" ::: "memory"); break;
+    default: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+  }
+}
+
+template <int BM, int BN, int WGM, int WGN, int OP, int ST>
 __global__ __launch_bounds__(WGM* WGN * 64)
 __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_mx(
     const uint8_t* __restrict__ A, const uint8_t* __restrict__ SA, const uint8_t* __restrict__ B,
@@ -38,14 +62,15 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_m
   constexpr int GA = BM / 8, GB = BN / 8;          // 8-row groups per tile
   constexpr int IA = (GA + NW - 1) / NW, IB = (GB + NW - 1) / NW;
   static_assert(BM * 4 <= 1024 && BN * 4 <= 1024, "one load instruction per scale tile");
+  static_assert(ST >= 2 && ST <= 4, "two to four K tiles in the LDS ring");
   constexpr int TILE_A = BM * MXK, TILE_B = BN * MXK, TILE_S = 1024;
-  constexpr int LDS_AB = 2 * (TILE_A + TILE_B + 2 * TILE_S);
+  constexpr int LDS_AB = ST * (TILE_A + TILE_B + 2 * TILE_S);
   constexpr int LDS_EPI = NW * 32 * WN * 4;
   __shared__ __attribute__((aligned(1024))) char smem[LDS_AB > LDS_EPI ? LDS_AB : LDS_EPI];
   char* const sA = smem;
-  char* const sB = smem + 2 * TILE_A;
-  char* const sSA = smem + 2 * (TILE_A + TILE_B);
-  char* const sSB = sSA + 2 * TILE_S;
+  char* const sB = smem + ST * TILE_A;
+  char* const sSA = smem + ST * (TILE_A + TILE_B);
+  char* const sSB = sSA + ST * TILE_S;
 
   int tm_, tn_;
   xcd_tile(gm, gn, 8, &tm_, &tn_);
@@ -164,21 +189,33 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_m
     if (NM > NG) __builtin_amdgcn_sched_group_barrier(0x008, NM - NG, 0);
   };
 
-  issue(0, 0);
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  // Global loads of one K tile by this wave: its operand row groups, plus
+  // the scale tile for waves 0 (A) and NW - 1 (B).  Loads complete in issue
+  // order, so "at most k tiles outstanding" is vmcnt <= k * n_ld.
+  const int n_ld = (GA % NW == 0 || wave < GA % NW ? IA : IA - 1) +
+                   (GB % NW == 0 || wave < GB % NW ? IB : IB - 1) + (wave == 0) +
+                   (wave == NW - 1);
+  // Loads run ST - 1 tiles ahead.  Tile kt + ST - 1 goes into the stage of
+  // tile kt - 1, whose readers all passed the barrier of iteration kt - 1.
+  for (int i = 0; i < ST - 1 && i < KT; ++i) issue(i, i);
+  wait_vm_le(n_ld * (KT - 1 < ST - 2 ? KT - 1 : ST - 2));
   lds_barrier();
   ldfrag(f0, 0, 0);
+  int cur = 0;
   for (int kt = 0; kt < KT; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < KT) issue(cur ^ 1, kt + 1);
+    const int nxt = cur + 1 == ST ? 0 : cur + 1;
+    if (kt + ST - 1 < KT) issue(cur == 0 ? ST - 1 : cur - 1, kt + ST - 1);
     ldfrag(f1, cur, 1);
     mma0(f0);
     interleave();
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // tile kt + 1 must have landed; later tiles may still be in flight
+    const int ahead = KT - 2 - kt < ST - 2 ? KT - 2 - kt : ST - 2;
+    wait_vm_le(ahead > 0 ? n_ld * ahead : 0);
     lds_barrier();
-    ldfrag(f0, cur ^ 1, 0);   // next tile (stale on the last; never used)
+    ldfrag(f0, nxt, 0);   // next tile (stale on the last; never used)
     mma1(f1);
     interleave();
+    cur = nxt;
   }
 
   // Epilogue: as in k_gemm_bf16_dl (scales were applied inside the MFMA).
@@ -261,7 +298,7 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_m
   }
 }
 
-template <int BM, int BN, int WGM, int WGN>
+template <int BM, int BN, int WGM, int WGN, int ST = 2>
 static hipError_t launch_mx(const uint8_t* A, const uint8_t* SA, const uint8_t* B,
                             const uint8_t* SB, int M, int N, int K, int op, const EpiArgs& e,
                             hipStream_t s) {
@@ -273,7 +310,7 @@ static hipError_t launch_mx(const uint8_t* A, const uint8_t* SA, const uint8_t* 
   dim3 grid(gm * gn), block(WGM * WGN * 64);
 #define VL_MX_CASE(OP)                                                                  \
   case OP:                                                                              \
-    hipLaunchKernelGGL((k_gemm_mx<BM, BN, WGM, WGN, OP>), grid, block, 0, s, A, SA, B, SB, \
+    hipLaunchKernelGGL((k_gemm_mx<BM, BN, WGM, WGN, OP, ST>), grid, block, 0, s, A, SA, B, SB, \
                        M, N, K, gm, gn, e);                                             \
     break;
   switch (op) {

