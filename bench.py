@@ -111,6 +111,38 @@ def cpu_baseline(wl: synth.Workload, blob: np.ndarray, images, texts, n_sample: 
                       f"{wl.head} scoring vs {len(texts)} texts; {dt:.1f} s"}
 
 
+def text_leg(torch, vl, n_texts: int, steps: int, seed: int = 3002):
+    """The text tower: CLIP ViT-L/14-shaped (width 768, 12 causal blocks,
+    context 77), BF16, HIP graphs; n_texts prompt-length token sequences
+    (U{5..20} tokens, one in ten at 77) encoded in one call, as the texts the
+    scoring head keeps resident are produced."""
+    c = synth.TEXT_MODELS["l14_text"]
+    w = torch.from_numpy(synth.make_text_blob(c, seed)).cuda()
+    lens = synth.draw_text_lengths(n_texts, c.ctx, seed + 1)
+    ids = torch.from_numpy(np.concatenate(synth.make_token_ids(lens, c.vocab, seed + 2))).cuda()
+    enc = vl.TextEncoder(c, w, "bf16", graphs=True)
+    del w
+    out = torch.empty((n_texts, c.proj_dim), dtype=torch.float32, device="cuda")
+    for _ in range(2):
+        enc.encode(ids, lens, out=out)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        enc.encode(ids, lens, out=out)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    T = int(sum(lens))
+    D, F = c.width, c.mlp
+    flops = c.layers * (2.0 * T * D * (3 * D + D + 2 * F) + sum(2.0 * n * (n + 1) * D for n in lens))
+    enc.close()
+    return {"value": n_texts / (ms / 1e3), "unit": "texts/s", "ms_per_call": ms,
+            "texts": n_texts, "tokens": T, "model": c.name, "precision": "bf16",
+            "tflops": flops / (ms / 1e3) / 1e12, "steps": steps}
+
+
 def serving_leg(torch, vl, n_requests: int, warmup_requests: int, slots: int,
                 budget_gib: float, max_batch_images: int):
     """The serving workload: ViT-L/14 with e4m3 per-row weights and BF16
@@ -190,6 +222,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-steps", type=int, default=3)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving (p50/p99) leg")
+    ap.add_argument("--no-text", action="store_true", help="skip the text-tower leg")
+    ap.add_argument("--text-steps", type=int, default=5)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB first, so "
                          "a counter run can scale FETCH_SIZE / WRITE_SIZE by a copy of known size")
@@ -335,6 +369,10 @@ def main(argv=None) -> int:
                                "ms_per_step": ms32, "steps": args.fp32_steps,
                                "speedup_of_value": ms32 / ms}
         del enc32
+
+    if not args.no_text:
+        result["text_tower"] = text_leg(torch, vl, wl.n_texts, args.text_steps)
+        print(f"# text tower: {json.dumps(result['text_tower'])}", file=sys.stderr, flush=True)
 
     if not args.no_serve:
         result["serving"] = serving_leg(torch, vl, args.serve_requests, 100, args.serve_slots,

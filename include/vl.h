@@ -138,6 +138,60 @@ vl_status vl_model_create(const vl_config* cfg, vl_precision prec,
  * device first, so in-flight work that reads the model finishes. NULL ok. */
 void vl_model_destroy(vl_model* m);
 
+/* ---- Text tower ---------------------------------------------------------
+ * The text encoder of a contrastive model (CLIP, Radford et al. 2021,
+ * Sec. 2.4): token embedding plus a learned absolute position embedding, L
+ * pre-LN blocks identical to the image tower's except that self-attention
+ * is causal (token i attends to tokens 0..i of its own sequence), then the
+ * final LayerNorm of the sequence's last token (its end-of-text token),
+ * the bias-free projection and L2 normalisation.  The embeddings it returns
+ * are the `texts` operand of vl_score.                                      */
+typedef struct vl_text_config {
+  int32_t vocab;     /* token table rows                                    */
+  int32_t ctx;       /* longest sequence (position table rows), <= 1024     */
+  int32_t width;     /* width % 128 == 0, head_dim 32 or 64, width <= 1024  */
+  int32_t layers;
+  int32_t heads;
+  int32_t mlp;       /* mlp % 128 == 0                                      */
+  int32_t proj_dim;  /* % 4 == 0, <= 1024                                   */
+  float ln_eps;
+} vl_text_config;
+
+/* FP32 values in a text model's weight blob, 0 if cfg is invalid.  Layout,
+ * tensors back to back, C-contiguous:
+ *   tok_emb [vocab, D]  pos [ctx, D]
+ *   per block: as for images (ln1_g .. fc2_b)
+ *   lnf_g [D]  lnf_b [D]  proj_w [P_dim, D]                                */
+size_t vl_text_weights_count(const vl_text_config* cfg);
+
+/* Build a text model; arguments, precisions and errors as vl_model_create.
+ * The handle works with vl_model_destroy, vl_model_set_option and
+ * vl_model_op_times (operation 0 is then the token embedding); GEMM tiles
+ * use the built-in heuristic or vl_model_set_tuning (the autotuner takes
+ * images only).                                                             */
+vl_status vl_text_model_create(const vl_text_config* cfg, vl_precision prec,
+                               const float* weights_dev, size_t n_floats,
+                               void* stream, vl_model** out);
+
+/* Workspace bytes for vl_encode_texts of n_texts sequences of the given
+ * lengths (host array); 0 on invalid input or a non-text model.           */
+size_t vl_text_workspace_bytes(const vl_model* m, int32_t n_texts,
+                               const int32_t* lengths);
+
+/* Encode n_texts token sequences.
+ *  ids_dev     : int32 token ids of all sequences back to back (sequence i
+ *                has lengths[i] ids, 1 <= lengths[i] <= ctx, ending with its
+ *                end-of-text token), 4-byte aligned.  Ids outside
+ *                [0, vocab) are clamped into it (never read out of bounds).
+ *  lengths     : host array of n_texts lengths (1 <= n_texts <= 65535).
+ *  emb_out_dev : [n_texts, proj_dim] FP32 unit rows, 16-byte aligned.
+ *  workspace_dev : >= vl_text_workspace_bytes(...), 256-byte aligned.
+ * Sequences are packed into one token stream; attention never crosses
+ * sequences.                                                                */
+vl_status vl_encode_texts(vl_model* m, const int32_t* ids_dev, const int32_t* lengths,
+                          int32_t n_texts, float* emb_out_dev, void* workspace_dev,
+                          size_t workspace_bytes, void* stream);
+
 /* Options (all off by default).
  *   VL_OPT_GRAPHS : 1 = capture each distinct call (shapes, pointers,
  *                   stream) into a HIP graph on first use and replay it.
@@ -215,6 +269,7 @@ size_t vl_encode_workspace_bytes(const vl_model* m, int32_t n_images,
  *               (channel, row, column), values as given (normalisation is
  *               applied inside).  The patch grid is floor(H/P) x floor(W/P);
  *               pixels past the last whole patch are ignored.
+ *  n_images   : 1 .. 65535.
  *  heights, widths : host arrays; each side >= patch and the grid must have
  *               at most 1024 patches (1025 tokens).
  *  emb_out_dev : [n_images, proj_dim] FP32, each row unit-L2 (norm clamped

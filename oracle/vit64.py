@@ -194,13 +194,24 @@ def _identity(a: np.ndarray) -> np.ndarray:
     return a
 
 
+def causal_attention_head(q: np.ndarray, k: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """Masked self-attention for one head of one text sequence (the CLIP
+    text encoder's masked self-attention, CLIP Sec. 2.4): token i takes the
+    softmax over keys 0..i of q_i.k_j / sqrt(d); later keys get weight 0."""
+    n, d = q.shape
+    s = (q @ k.T) / math.sqrt(d)
+    s = np.where(np.tril(np.ones((n, n), dtype=bool)), s, -np.inf)
+    return softmax(s, axis=-1) @ v
+
+
 def mhsa(y: np.ndarray, qkv_w, qkv_b, o_w, o_b, heads: int,
-         aq=_identity) -> np.ndarray:
+         aq=_identity, causal: bool = False) -> np.ndarray:
     """Multi-head self-attention over the tokens of one image.  The fused
     projection's outputs are [Q | K | V]; head k uses columns k*d .. k*d+d-1
     of each.  Heads are concatenated, then the output projection.  `aq` is
     applied to the left operand of both projections (the identity, or an
-    activation encoding such as mx_round)."""
+    activation encoding such as mx_round).  causal selects the masked form
+    (text tower)."""
     y = np.asarray(y, F64)
     dm = y.shape[1]
     d = dm // heads
@@ -209,7 +220,8 @@ def mhsa(y: np.ndarray, qkv_w, qkv_b, o_w, o_b, heads: int,
     o = np.zeros_like(q)
     for h in range(heads):
         sl = slice(h * d, (h + 1) * d)
-        o[:, sl] = attention_head(q[:, sl], k[:, sl], v[:, sl])
+        head = causal_attention_head if causal else attention_head
+        o[:, sl] = head(q[:, sl], k[:, sl], v[:, sl])
     return aq(o) @ np.asarray(o_w, F64).T + np.asarray(o_b, F64)
 
 
@@ -221,12 +233,12 @@ def mlp(y: np.ndarray, fc1_w, fc1_b, fc2_w, fc2_b, aq=_identity) -> np.ndarray:
 
 
 def block(x: np.ndarray, lp: Dict[str, np.ndarray], heads: int,
-          eps: float, aq=_identity) -> np.ndarray:
+          eps: float, aq=_identity, causal: bool = False) -> np.ndarray:
     """One pre-LN block: x' = x + MSA(LN(x)); x'' = x' + MLP(LN(x'))
     (ViT Eq. 2 and 3)."""
     x = np.asarray(x, F64)
     h = x + mhsa(layernorm(x, lp["ln1_g"], lp["ln1_b"], eps),
-                 lp["qkv_w"], lp["qkv_b"], lp["o_w"], lp["o_b"], heads, aq)
+                 lp["qkv_w"], lp["qkv_b"], lp["o_w"], lp["o_b"], heads, aq, causal)
     return h + mlp(layernorm(h, lp["ln2_g"], lp["ln2_b"], eps),
                    lp["fc1_w"], lp["fc1_b"], lp["fc2_w"], lp["fc2_b"], aq)
 
@@ -272,6 +284,35 @@ def encode(images: Sequence[np.ndarray], params: Dict, cfg,
            act: str = "none") -> np.ndarray:
     """Unit embeddings [n, P_dim] of every image, one image at a time."""
     return np.stack([encode_image(im, params, cfg, act=act) for im in images])
+
+
+# ---------------------------------------------------------------------------
+# Text tower (CLIP Sec. 2.4)
+# ---------------------------------------------------------------------------
+def text_hidden(ids: np.ndarray, params: Dict, cfg, act: str = "none") -> np.ndarray:
+    """Token embeddings plus learned absolute positions, then the pre-LN
+    blocks with masked (causal) self-attention.  Returns [len, D]."""
+    ids = np.asarray(ids, np.int64)
+    aq = act_encoding(act)
+    x = np.asarray(params["tok_emb"], F64)[ids] + np.asarray(params["pos"], F64)[:len(ids)]
+    for lp in params["layers"]:
+        x = block(x, lp, cfg.heads, cfg.ln_eps, aq, causal=True)
+    return x
+
+
+def encode_text(ids: np.ndarray, params: Dict, cfg, act: str = "none") -> np.ndarray:
+    """Unit text embedding: the last token's (the end-of-text token's) final
+    activations, LayerNorm, bias-free projection, L2 normalisation."""
+    x = text_hidden(ids, params, cfg, act)
+    z = layernorm(x[-1], params["lnf_g"], params["lnf_b"], cfg.ln_eps)
+    e = np.asarray(params["proj_w"], F64) @ z
+    return e / max(np.linalg.norm(e), 1e-12)
+
+
+def encode_texts(seqs: Sequence[np.ndarray], params: Dict, cfg,
+                 act: str = "none") -> np.ndarray:
+    """Unit embeddings [n, P_dim] of every token sequence, one at a time."""
+    return np.stack([encode_text(s, params, cfg, act) for s in seqs])
 
 
 # ---------------------------------------------------------------------------

@@ -44,6 +44,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 constexpr int kMaxTokens = 1025;   // 32 x 32 patches + class token
 constexpr int kAttnQ = 128;        // queries per attention work item
+constexpr int kMaxItems = 65535;   // images / texts per call (grid y of the gather kernels)
 
 struct Layer {
   const float *ln1_g, *ln1_b, *ln2_g, *ln2_b;
@@ -76,6 +77,11 @@ struct TimedLaunch {
 struct vl_model {
   vl_config cfg;
   vl_precision prec;
+  // Text models (vl_text_model_create): token table [vocab, D], position
+  // table [ctx, D] (in `pos`), causal attention, last-token pooling.
+  bool text = false;
+  int vocab = 0, ctx = 0;
+  const float* tok_emb = nullptr;
   int device = 0;
   int D, F, heads, hd, L, P, Pd, g0, Kpe, Kpad;
   char* wmem = nullptr;
@@ -121,6 +127,29 @@ bool config_ok(const vl_config* c, std::string* why) {
   return true;
 }
 
+bool text_config_ok(const vl_text_config* c, std::string* why) {
+  if (!c) { *why = "cfg is NULL"; return false; }
+  if (c->vocab < 1 || c->ctx < 1 || c->width <= 0 || c->layers < 0 || c->heads <= 0 ||
+      c->mlp <= 0 || c->proj_dim <= 0) {
+    *why = "non-positive dimension in cfg";
+    return false;
+  }
+  if (c->ctx > 1024) { *why = "ctx must be <= 1024"; return false; }
+  if (c->width % c->heads) { *why = "width % heads != 0"; return false; }
+  if (c->width % 128 || c->mlp % 128) { *why = "width and mlp must be multiples of 128"; return false; }
+  if (c->proj_dim % 4 || c->proj_dim > 1024) { *why = "proj_dim must be a multiple of 4, <= 1024"; return false; }
+  if (!(c->ln_eps >= 0.f)) { *why = "ln_eps must be >= 0"; return false; }
+  return true;
+}
+
+size_t text_weights_count(const vl_text_config& c) {
+  const size_t D = c.width, F = c.mlp;
+  size_t n = (size_t)c.vocab * D + (size_t)c.ctx * D;
+  n += (size_t)c.layers * (2 * D + 3 * D * D + 3 * D + D * D + D + 2 * D + F * D + F + D * F + D);
+  n += 2 * D + (size_t)c.proj_dim * D;
+  return n;
+}
+
 size_t weights_count(const vl_config& c) {
   const size_t D = c.width, F = c.mlp, P = c.patch, g = c.base_grid;
   size_t n = D * 3 * P * P + D + D + (1 + g * g) * D;
@@ -153,31 +182,11 @@ struct Plan {
   size_t total = 0;
 };
 
-bool make_plan(const vl_model* m, int32_t n, const int32_t* hs, const int32_t* ws, Plan* p,
-               std::string* why) {
-  if (n <= 0) { *why = "n_images must be > 0"; return false; }
-  if (!hs || !ws) { *why = "heights/widths are NULL"; return false; }
-  p->n = n;
-  p->hw.resize(2 * (size_t)n);
-  std::vector<ImgDesc> imgs(n);
-  int64_t pix = 0, T = 0;
-  for (int i = 0; i < n; ++i) {
-    const int H = hs[i], W = ws[i];
-    if (H < m->P || W < m->P) { *why = "image " + std::to_string(i) + " smaller than one patch"; return false; }
-    const int gh = H / m->P, gw = W / m->P;
-    const int64_t ntok = 1 + (int64_t)gh * gw;
-    if (ntok > kMaxTokens) { *why = "image " + std::to_string(i) + " has more than 1024 patches"; return false; }
-    ImgDesc& d = imgs[i];
-    d.pix_off = pix;
-    d.H = H; d.W = W; d.gh = gh; d.gw = gw;
-    d.tok_start = (int32_t)T;   // absolute for now
-    d.ntok = (int32_t)ntok;
-    pix += 3LL * H * W;
-    T += ntok;
-    p->hw[2 * i] = H;
-    p->hw[2 * i + 1] = W;
-  }
-  if (T > (1LL << 24)) { *why = "batch exceeds 2^24 tokens"; return false; }
+// The common tail of planning: part boundaries, attention work items, the
+// descriptor blob and the workspace regions.  imgs[] hold absolute token
+// starts on entry.
+bool finish_plan(const vl_model* m, std::vector<ImgDesc>& imgs, int64_t T, Plan* p) {
+  const int n = (int)imgs.size();
   p->T = (int)T;
   // Part boundaries: one part, or two holding about half the tokens each.
   std::vector<int> cut = {0};
@@ -236,6 +245,66 @@ bool make_plan(const vl_model* m, int32_t n, const int32_t* hs, const int32_t* w
   }
   p->total = off;
   return true;
+}
+
+bool make_plan(const vl_model* m, int32_t n, const int32_t* hs, const int32_t* ws, Plan* p,
+               std::string* why) {
+  if (m->text) { *why = "this model encodes texts (vl_encode_texts)"; return false; }
+  if (n <= 0) { *why = "n_images must be > 0"; return false; }
+  if (n > kMaxItems) { *why = "n_images must be <= 65535 (split larger batches)"; return false; }
+  if (!hs || !ws) { *why = "heights/widths are NULL"; return false; }
+  p->n = n;
+  p->hw.resize(2 * (size_t)n);
+  std::vector<ImgDesc> imgs(n);
+  int64_t pix = 0, T = 0;
+  for (int i = 0; i < n; ++i) {
+    const int H = hs[i], W = ws[i];
+    if (H < m->P || W < m->P) { *why = "image " + std::to_string(i) + " smaller than one patch"; return false; }
+    const int gh = H / m->P, gw = W / m->P;
+    const int64_t ntok = 1 + (int64_t)gh * gw;
+    if (ntok > kMaxTokens) { *why = "image " + std::to_string(i) + " has more than 1024 patches"; return false; }
+    ImgDesc& d = imgs[i];
+    d.pix_off = pix;
+    d.H = H; d.W = W; d.gh = gh; d.gw = gw;
+    d.tok_start = (int32_t)T;   // absolute for now
+    d.ntok = (int32_t)ntok;
+    pix += 3LL * H * W;
+    T += ntok;
+    p->hw[2 * i] = H;
+    p->hw[2 * i + 1] = W;
+  }
+  if (T > (1LL << 24)) { *why = "batch exceeds 2^24 tokens"; return false; }
+  return finish_plan(m, imgs, T, p);
+}
+
+// Text batches: one descriptor per sequence (tokens tok_start .. +ntok-1 of
+// the packed id stream); graph keys use (length, 0) per sequence.
+bool make_text_plan(const vl_model* m, int32_t n, const int32_t* lens, Plan* p,
+                    std::string* why) {
+  if (!m->text) { *why = "this model encodes images (vl_encode_images)"; return false; }
+  if (n <= 0) { *why = "n_texts must be > 0"; return false; }
+  if (n > kMaxItems) { *why = "n_texts must be <= 65535 (split larger batches)"; return false; }
+  if (!lens) { *why = "lengths is NULL"; return false; }
+  p->n = n;
+  p->hw.assign(2 * (size_t)n, 0);
+  std::vector<ImgDesc> seqs(n);
+  int64_t T = 0;
+  for (int i = 0; i < n; ++i) {
+    if (lens[i] < 1 || lens[i] > m->ctx) {
+      *why = "text " + std::to_string(i) + " has length " + std::to_string(lens[i]) +
+             ", not in 1.." + std::to_string(m->ctx);
+      return false;
+    }
+    ImgDesc& d = seqs[i];
+    d.pix_off = T;   // offset of the sequence's ids in the packed id stream
+    d.H = d.W = d.gh = d.gw = 0;
+    d.tok_start = (int32_t)T;
+    d.ntok = lens[i];
+    T += lens[i];
+    p->hw[2 * i] = lens[i];
+  }
+  if (T > (1LL << 24)) { *why = "batch exceeds 2^24 tokens"; return false; }
+  return finish_plan(m, seqs, T, p);
 }
 
 // Upload the plan's descriptors with an async copy from pinned memory.
@@ -312,7 +381,7 @@ struct OpScope {
   } while (0)
 
 // The kernel sequence of one part of an encode call.
-vl_status run_part(vl_model* m, const Part& p, const float* pix, float* emb, char* ws,
+vl_status run_part(vl_model* m, const Part& p, const void* in, float* emb, char* ws,
                    hipStream_t s, hipEvent_t after_first_qkv = nullptr) {
   const bool f32 = m->prec == VL_FP32;
   const bool fp8 = m->prec == VL_FP8W_BF16A;
@@ -335,8 +404,12 @@ vl_status run_part(vl_model* m, const Part& p, const float* pix, float* emb, cha
   pe.cls = m->cls;
   pe.pos = m->pos;
   pe.base_grid = m->g0;
-  VL_TIMED(T_PATCH, {
-    VL_HIP(im2col(pix, d_imgs, p.n, p.max_ntok, m->P, m->Kpad, QH, !f32, tok, s));
+  if (m->text)
+    VL_TIMED(T_PATCH, VL_HIP(text_embed(static_cast<const int32_t*>(in), d_imgs, p.n, p.max_ntok,
+                                        m->tok_emb, m->pos, m->vocab, D, X, tok, s)));
+  else VL_TIMED(T_PATCH, {
+    VL_HIP(im2col(static_cast<const float*>(in), d_imgs, p.n, p.max_ntok, m->P, m->Kpad, QH,
+                  !f32, tok, s));
     if (f32)
       VL_HIP(gemm_f32(static_cast<const float*>(QH), m->Kpad,
                       static_cast<const float*>(m->patch_w), m->Kpad, T, D, m->Kpad, OP_PATCH,
@@ -366,7 +439,7 @@ vl_status run_part(vl_model* m, const Part& p, const float* pix, float* emb, cha
       VL_TIMED(T_QKV, VL_HIP(gemm_f32(y, D, static_cast<const float*>(ly.qkv_w), D, T, 3 * D, D,
                                       OP_QKV, e1, s)));
       VL_TIMED(T_ATTN, VL_HIP(attention_f32(qh, static_cast<float*>(Y), d_imgs, d_items,
-                                            p.n_items, m->heads, m->hd, s)));
+                                            p.n_items, m->heads, m->hd, m->text, s)));
       VL_TIMED(T_OPROJ, VL_HIP(gemm_f32(y, D, static_cast<const float*>(ly.o_w), D, T, D, D,
                                         OP_OPROJ, e2, s)));
       VL_TIMED(T_LN, VL_HIP(layernorm_rows(X, ly.ln2_g, ly.ln2_b, eps, Y, false, T, D, s)));
@@ -389,7 +462,8 @@ vl_status run_part(vl_model* m, const Part& p, const float* pix, float* emb, cha
                                      gemm_cfg_for(m, 1, T), e1, s)));
       if (after_first_qkv && &ly == &m->layers[0]) VL_HIP(hipEventRecord(after_first_qkv, s));
       VL_TIMED(T_ATTN, VL_HIP(attention_bf16_mx(static_cast<const bf16_t*>(QH), y8, ys, T, d_imgs,
-                                                d_items, p.n_items, m->heads, m->hd, s)));
+                                                d_items, p.n_items, m->heads, m->hd, m->text,
+                                                s)));
       VL_TIMED(T_OPROJ, VL_HIP(gemm_mx(y8, ys, w8[1], ly.o_x, T, D, D, OP_OPROJ,
                                        gemm_cfg_for(m, 2, T), e2, s)));
       VL_TIMED(T_LN, VL_HIP(layernorm_rows_mx(X, ly.ln2_g, ly.ln2_b, eps, y8, ys, T, D, s)));
@@ -404,7 +478,7 @@ vl_status run_part(vl_model* m, const Part& p, const float* pix, float* emb, cha
                                        gemm_cfg_for(m, 1, T), e1, s)));
       if (after_first_qkv && &ly == &m->layers[0]) VL_HIP(hipEventRecord(after_first_qkv, s));
       VL_TIMED(T_ATTN, VL_HIP(attention_bf16(qh, static_cast<bf16_t*>(Y), d_imgs, d_items,
-                                             p.n_items, m->heads, m->hd, s)));
+                                             p.n_items, m->heads, m->hd, m->text, s)));
       VL_TIMED(T_OPROJ, VL_HIP(gemm_bf16(y, D, ly.o_w, D, fp8, T, D, D, OP_OPROJ,
                                          gemm_cfg_for(m, 2, T), e2, s)));
       VL_TIMED(T_LN, VL_HIP(layernorm_rows(X, ly.ln2_g, ly.ln2_b, eps, Y, true, T, D, s)));
@@ -415,7 +489,7 @@ vl_status run_part(vl_model* m, const Part& p, const float* pix, float* emb, cha
     }
   }
   VL_TIMED(T_POOL, VL_HIP(pool_project(X, d_imgs, p.n, m->lnf_g, m->lnf_b, eps, m->proj, D,
-                                        m->Pd, reinterpret_cast<float*>(ws + p.off_E),
+                                        m->Pd, m->text, reinterpret_cast<float*>(ws + p.off_E),
                                         emb + (size_t)p.i0 * m->Pd, s)));
   return VL_OK;
 }
@@ -426,7 +500,7 @@ vl_status run_part(vl_model* m, const Part& p, const float* pix, float* emb, cha
 // upload) and joined back before the call returns.  The two parts then
 // overlap one another's tile-round tails, epilogue store bursts and
 // non-MFMA phases.
-vl_status run_encoder(vl_model* m, const Plan& p, const float* pix, float* emb, char* ws,
+vl_status run_encoder(vl_model* m, const Plan& p, const void* pix, float* emb, char* ws,
                       hipStream_t s) {
   if (p.parts.size() == 1) return run_part(m, p.parts[0], pix, emb, ws, s);
   if (!m->side) VL_HIP(hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking));
@@ -492,39 +566,25 @@ size_t vl_weights_count(const vl_config* cfg) {
   return weights_count(*cfg);
 }
 
-vl_status vl_model_create(const vl_config* cfg, vl_precision prec, const float* wdev,
-                          size_t n_floats, void* stream, vl_model** out) {
-  std::string why;
-  if (!out) return fail(VL_ERR_INVALID_ARG, "out is NULL");
-  *out = nullptr;
-  if (!config_ok(cfg, &why)) return fail(VL_ERR_INVALID_ARG, why);
-  if (!wdev) return fail(VL_ERR_INVALID_ARG, "weights_dev is NULL");
-  if (prec != VL_FP32 && prec != VL_BF16 && prec != VL_FP8W_BF16A && prec != VL_MXFP8)
-    return fail(VL_ERR_INVALID_ARG, "unknown precision");
-  if (n_floats != weights_count(*cfg))
-    return fail(VL_ERR_INVALID_ARG, "weight blob has " + std::to_string(n_floats) +
-                                        " floats, expected " + std::to_string(weights_count(*cfg)));
-  const int hd = cfg->width / cfg->heads;
-  if (hd != 32 && hd != 64) return fail(VL_ERR_UNSUPPORTED, "head_dim must be 32 or 64");
-  if (cfg->width > 1024) return fail(VL_ERR_UNSUPPORTED, "width must be <= 1024");
-
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  vl_model* m = new vl_model();
-  m->cfg = *cfg;
-  m->prec = prec;
-  if (hipGetDevice(&m->device) != hipSuccess) { delete m; return fail(VL_ERR_DEVICE, "hipGetDevice failed"); }
-  m->D = cfg->width; m->F = cfg->mlp; m->heads = cfg->heads; m->hd = hd; m->L = cfg->layers;
-  m->P = cfg->patch; m->Pd = cfg->proj_dim; m->g0 = cfg->base_grid;
-  m->Kpe = 3 * m->P * m->P;
-  m->Kpad = (m->Kpe + 63) / 64 * 64;
-  const size_t D = m->D, F = m->F, G = 1 + (size_t)m->g0 * m->g0;
+// Device copy of a model's weights in its precision (one hipMalloc), from the
+// FP32 blob; m holds the dimensions.  Frees m on failure.
+static vl_status build_weights(vl_model* m, const float* wdev, hipStream_t s, vl_model** out) {
+  const vl_precision prec = m->prec;
+  const size_t D = m->D, F = m->F;
+  // position rows: image class token + g0 x g0 grid, or text context length
+  const size_t G = m->text ? (size_t)m->ctx : 1 + (size_t)m->g0 * m->g0;
 
   // Source offsets in the FP32 blob (layout in include/vl.h).
   size_t o = 0;
   auto take = [&](size_t n) { size_t r = o; o += n; return wdev + r; };
-  const float* s_patch_w = take(D * m->Kpe);
-  const float* s_patch_b = take(D);
-  const float* s_cls = take(D);
+  const float *s_patch_w = nullptr, *s_patch_b = nullptr, *s_cls = nullptr, *s_tok = nullptr;
+  if (m->text) {
+    s_tok = take((size_t)m->vocab * D);
+  } else {
+    s_patch_w = take(D * m->Kpe);
+    s_patch_b = take(D);
+    s_cls = take(D);
+  }
   const float* s_pos = take(G * D);
   struct SrcLayer { const float *ln1_g, *ln1_b, *qkv_w, *qkv_b, *o_w, *o_b, *ln2_g, *ln2_b, *fc1_w, *fc1_b, *fc2_w, *fc2_b; };
   std::vector<SrcLayer> src(m->L);
@@ -543,9 +603,10 @@ vl_status vl_model_create(const vl_config* cfg, vl_precision prec, const float* 
   const size_t pes = prec == VL_FP32 ? 4 : 2;
   size_t sz = 0;
   auto alloc = [&](size_t bytes) { size_t r = sz; sz += align_up(bytes); return r; };
-  const size_t d_patch_w = alloc(pes * D * m->Kpad);
-  const size_t d_patch_b = alloc(4 * D);
-  const size_t d_cls = alloc(4 * D);
+  const size_t d_patch_w = m->text ? 0 : alloc(pes * D * m->Kpad);
+  const size_t d_patch_b = m->text ? 0 : alloc(4 * D);
+  const size_t d_cls = m->text ? 0 : alloc(4 * D);
+  const size_t d_tok = m->text ? alloc(4 * (size_t)m->vocab * D) : 0;
   const size_t d_pos = alloc(4 * G * D);
   struct DstLayer { size_t ln1_g, ln1_b, ln2_g, ln2_b, qkv_b, o_b, fc1_b, fc2_b, qkv_w, o_w, fc1_w, fc2_w, qkv_s, o_s, fc1_s, fc2_s; };
   const bool mx = prec == VL_MXFP8;
@@ -579,12 +640,16 @@ vl_status vl_model_create(const vl_config* cfg, vl_precision prec, const float* 
   auto chk = [&](hipError_t e, const char* what) {
     if (st == VL_OK && e != hipSuccess) st = hip_fail(e, what);
   };
-  chk(fold_patch_weights(s_patch_w, s_patch_b, cfg->chan_mean, cfg->chan_std, m->D, m->P, m->Kpad,
-                         prec == VL_FP32 ? f(d_patch_w) : nullptr,
-                         prec == VL_FP32 ? nullptr : reinterpret_cast<bf16_t*>(b + d_patch_w),
-                         f(d_patch_b), s),
-      "fold_patch_weights");
-  chk(copy_f32(s_cls, f(d_cls), D, s), "copy cls");
+  if (m->text) {
+    chk(copy_f32(s_tok, f(d_tok), (size_t)m->vocab * D, s), "copy token table");
+  } else {
+    chk(fold_patch_weights(s_patch_w, s_patch_b, m->cfg.chan_mean, m->cfg.chan_std, m->D, m->P,
+                           m->Kpad, prec == VL_FP32 ? f(d_patch_w) : nullptr,
+                           prec == VL_FP32 ? nullptr : reinterpret_cast<bf16_t*>(b + d_patch_w),
+                           f(d_patch_b), s),
+        "fold_patch_weights");
+    chk(copy_f32(s_cls, f(d_cls), D, s), "copy cls");
+  }
   chk(copy_f32(s_pos, f(d_pos), G * D, s), "copy pos");
   auto conv_w = [&](const float* src_w, size_t dst_off, size_t scale_off, int rows, int cols) {
     if (prec == VL_FP32)
@@ -630,9 +695,13 @@ vl_status vl_model_create(const vl_config* cfg, vl_precision prec, const float* 
   chk(copy_f32(s_lnf_g, f(d_lnf_g), D, s), "copy");
   chk(copy_f32(s_lnf_b, f(d_lnf_b), D, s), "copy");
   chk(copy_f32(s_proj, f(d_proj), (size_t)m->Pd * D, s), "copy");
-  m->patch_w = b + d_patch_w;
-  m->patch_b = f(d_patch_b);
-  m->cls = f(d_cls);
+  if (m->text) {
+    m->tok_emb = f(d_tok);
+  } else {
+    m->patch_w = b + d_patch_w;
+    m->patch_b = f(d_patch_b);
+    m->cls = f(d_cls);
+  }
   m->pos = f(d_pos);
   m->lnf_g = f(d_lnf_g);
   m->lnf_b = f(d_lnf_b);
@@ -647,6 +716,68 @@ vl_status vl_model_create(const vl_config* cfg, vl_precision prec, const float* 
   }
   *out = m;
   return VL_OK;
+}
+
+size_t vl_text_weights_count(const vl_text_config* cfg) {
+  std::string why;
+  if (!text_config_ok(cfg, &why)) return 0;
+  return text_weights_count(*cfg);
+}
+
+vl_status vl_text_model_create(const vl_text_config* cfg, vl_precision prec, const float* wdev,
+                               size_t n_floats, void* stream, vl_model** out) {
+  std::string why;
+  if (!out) return fail(VL_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!text_config_ok(cfg, &why)) return fail(VL_ERR_INVALID_ARG, why);
+  if (!wdev) return fail(VL_ERR_INVALID_ARG, "weights_dev is NULL");
+  if (prec != VL_FP32 && prec != VL_BF16 && prec != VL_FP8W_BF16A && prec != VL_MXFP8)
+    return fail(VL_ERR_INVALID_ARG, "unknown precision");
+  if (n_floats != text_weights_count(*cfg))
+    return fail(VL_ERR_INVALID_ARG, "weight blob has " + std::to_string(n_floats) +
+                                        " floats, expected " +
+                                        std::to_string(text_weights_count(*cfg)));
+  const int hd = cfg->width / cfg->heads;
+  if (hd != 32 && hd != 64) return fail(VL_ERR_UNSUPPORTED, "head_dim must be 32 or 64");
+  if (cfg->width > 1024) return fail(VL_ERR_UNSUPPORTED, "width must be <= 1024");
+  vl_model* m = new vl_model();
+  m->text = true;
+  m->prec = prec;
+  if (hipGetDevice(&m->device) != hipSuccess) { delete m; return fail(VL_ERR_DEVICE, "hipGetDevice failed"); }
+  m->cfg = vl_config{};
+  m->cfg.ln_eps = cfg->ln_eps;
+  m->vocab = cfg->vocab; m->ctx = cfg->ctx;
+  m->D = cfg->width; m->F = cfg->mlp; m->heads = cfg->heads; m->hd = hd; m->L = cfg->layers;
+  m->Pd = cfg->proj_dim;
+  m->P = 0; m->g0 = 0; m->Kpe = 0; m->Kpad = 0;
+  return build_weights(m, wdev, static_cast<hipStream_t>(stream), out);
+}
+
+vl_status vl_model_create(const vl_config* cfg, vl_precision prec, const float* wdev,
+                          size_t n_floats, void* stream, vl_model** out) {
+  std::string why;
+  if (!out) return fail(VL_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!config_ok(cfg, &why)) return fail(VL_ERR_INVALID_ARG, why);
+  if (!wdev) return fail(VL_ERR_INVALID_ARG, "weights_dev is NULL");
+  if (prec != VL_FP32 && prec != VL_BF16 && prec != VL_FP8W_BF16A && prec != VL_MXFP8)
+    return fail(VL_ERR_INVALID_ARG, "unknown precision");
+  if (n_floats != weights_count(*cfg))
+    return fail(VL_ERR_INVALID_ARG, "weight blob has " + std::to_string(n_floats) +
+                                        " floats, expected " + std::to_string(weights_count(*cfg)));
+  const int hd = cfg->width / cfg->heads;
+  if (hd != 32 && hd != 64) return fail(VL_ERR_UNSUPPORTED, "head_dim must be 32 or 64");
+  if (cfg->width > 1024) return fail(VL_ERR_UNSUPPORTED, "width must be <= 1024");
+
+  vl_model* m = new vl_model();
+  m->cfg = *cfg;
+  m->prec = prec;
+  if (hipGetDevice(&m->device) != hipSuccess) { delete m; return fail(VL_ERR_DEVICE, "hipGetDevice failed"); }
+  m->D = cfg->width; m->F = cfg->mlp; m->heads = cfg->heads; m->hd = hd; m->L = cfg->layers;
+  m->P = cfg->patch; m->Pd = cfg->proj_dim; m->g0 = cfg->base_grid;
+  m->Kpe = 3 * m->P * m->P;
+  m->Kpad = (m->Kpe + 63) / 64 * 64;
+  return build_weights(m, wdev, static_cast<hipStream_t>(stream), out);
 }
 
 void vl_model_destroy(vl_model* m) {
@@ -726,19 +857,9 @@ size_t vl_encode_workspace_bytes(const vl_model* m, int32_t n, const int32_t* hs
   return p.total;
 }
 
-vl_status vl_encode_images(vl_model* m, const float* pix, const int32_t* hs, const int32_t* wsz,
-                           int32_t n, float* emb, void* ws, size_t ws_bytes, void* stream) {
-  if (!m) return fail(VL_ERR_INVALID_ARG, "model is NULL");
-  if (!pix || !emb || !ws) return fail(VL_ERR_INVALID_ARG, "pixels, emb_out or workspace is NULL");
-  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(VL_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-  if (reinterpret_cast<uintptr_t>(pix) % 16 || reinterpret_cast<uintptr_t>(emb) % 16)
-    return fail(VL_ERR_INVALID_ARG, "pixels and emb_out must be 16-byte aligned");
-  Plan p;
-  std::string why;
-  if (!make_plan(m, n, hs, wsz, &p, &why)) return fail(VL_ERR_INVALID_ARG, why);
-  if (ws_bytes < p.total)
-    return fail(VL_ERR_WORKSPACE_TOO_SMALL, "workspace has " + std::to_string(ws_bytes) +
-                                                " bytes, needs " + std::to_string(p.total));
+// Enqueue (or capture and replay) the kernel sequence of a planned batch.
+static vl_status encode_planned(vl_model* m, const Plan& p, const void* pix, float* emb, void* ws,
+                                size_t ws_bytes, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
   std::lock_guard<std::mutex> lk(m->mu);
@@ -782,6 +903,46 @@ vl_status vl_encode_images(vl_model* m, const float* pix, const int32_t* hs, con
   }
   VL_HIP(hipGraphLaunch(it->second.exec, s));
   return VL_OK;
+}
+
+vl_status vl_encode_images(vl_model* m, const float* pix, const int32_t* hs, const int32_t* wsz,
+                           int32_t n, float* emb, void* ws, size_t ws_bytes, void* stream) {
+  if (!m) return fail(VL_ERR_INVALID_ARG, "model is NULL");
+  if (!pix || !emb || !ws) return fail(VL_ERR_INVALID_ARG, "pixels, emb_out or workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(VL_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (reinterpret_cast<uintptr_t>(pix) % 16 || reinterpret_cast<uintptr_t>(emb) % 16)
+    return fail(VL_ERR_INVALID_ARG, "pixels and emb_out must be 16-byte aligned");
+  Plan p;
+  std::string why;
+  if (!make_plan(m, n, hs, wsz, &p, &why)) return fail(VL_ERR_INVALID_ARG, why);
+  if (ws_bytes < p.total)
+    return fail(VL_ERR_WORKSPACE_TOO_SMALL, "workspace has " + std::to_string(ws_bytes) +
+                                                " bytes, needs " + std::to_string(p.total));
+  return encode_planned(m, p, pix, emb, ws, ws_bytes, stream);
+}
+
+size_t vl_text_workspace_bytes(const vl_model* m, int32_t n, const int32_t* lens) {
+  if (!m) return 0;
+  Plan p;
+  std::string why;
+  if (!make_text_plan(m, n, lens, &p, &why)) return 0;
+  return p.total;
+}
+
+vl_status vl_encode_texts(vl_model* m, const int32_t* ids, const int32_t* lens, int32_t n,
+                          float* emb, void* ws, size_t ws_bytes, void* stream) {
+  if (!m) return fail(VL_ERR_INVALID_ARG, "model is NULL");
+  if (!ids || !emb || !ws) return fail(VL_ERR_INVALID_ARG, "ids, emb_out or workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(VL_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (reinterpret_cast<uintptr_t>(ids) % 4 || reinterpret_cast<uintptr_t>(emb) % 16)
+    return fail(VL_ERR_INVALID_ARG, "ids must be 4-byte and emb_out 16-byte aligned");
+  Plan p;
+  std::string why;
+  if (!make_text_plan(m, n, lens, &p, &why)) return fail(VL_ERR_INVALID_ARG, why);
+  if (ws_bytes < p.total)
+    return fail(VL_ERR_WORKSPACE_TOO_SMALL, "workspace has " + std::to_string(ws_bytes) +
+                                                " bytes, needs " + std::to_string(p.total));
+  return encode_planned(m, p, ids, emb, ws, ws_bytes, stream);
 }
 
 int32_t vl_gemm_config_count(void) { return N_GEMM_CFGS; }

@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
                                                    uint8_t* __restrict__ out_scale, int T_rows,
                                                    const ImgDesc* __restrict__ imgs,
                                                    const AttnItem* __restrict__ items,
-                                                   int heads) {
+                                                   int heads, int causal) {
   using T = KvTile<HD, false>;
   using TV = KvTile<HD, true>;
   constexpr int RPI = 1024 / T::ROWB;          // tile rows per 1 KB load instruction
@@ -154,7 +154,10 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
 #pragma unroll
     for (int r = 0; r < 16; ++r) o[a][r] = 0.f;
 
-  const int KT = (N + ATT_KV - 1) / ATT_KV;
+  // Causal: query q sees keys 0..q, so this workgroup needs keys below its
+  // last query only.
+  const int kv_end = causal ? min(N, it.q0 + ATT_Q) : N;
+  const int KT = (kv_end + ATT_KV - 1) / ATT_KV;
   // One key tile; the ring stage is a compile-time constant so every LDS
   // address is a per-lane base plus an immediate.
   auto tile = [&](auto stage, int kt) {
@@ -196,12 +199,15 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
         vf[jj][a] = __builtin_bit_cast(bf16x8, vk);
       }
     const int kbase = kt * ATT_KV;
-    if (kbase + ATT_KV > N) {            // keys past the image: excluded
+    // keys past the sequence, and with a causal mask keys after the query
+    // (every query keeps key 0, so no row is ever fully masked)
+    const int kmax = causal ? min(N - 1, q) : N - 1;
+    if (kbase + ATT_KV - 1 > (causal ? min(N - 1, qw) : N - 1)) {
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-          if (kbase + kb * 32 + 8 * (r >> 2) + 4 * g + (r & 3) >= N) s[kb][r] = -INFINITY;
+          if (kbase + kb * 32 + 8 * (r >> 2) + 4 * g + (r & 3) > kmax) s[kb][r] = -INFINITY;
     }
     // Row max: three-input maxima (inline so no NaN-quieting copies are
     // inserted; scores are never NaN).
@@ -304,7 +310,7 @@ __global__ __launch_bounds__(ATT_Q) void k_attn_f32(const float* __restrict__ qk
                                                     float* __restrict__ out,
                                                     const ImgDesc* __restrict__ imgs,
                                                     const AttnItem* __restrict__ items,
-                                                    int heads) {
+                                                    int heads, int causal) {
   __shared__ float sK[F32_KV][HD];
   __shared__ float sV[F32_KV][HD];
   const AttnItem it = items[blockIdx.x];
@@ -325,7 +331,9 @@ __global__ __launch_bounds__(ATT_Q) void k_attn_f32(const float* __restrict__ qk
   }
   const float sc = 1.f / sqrtf((float)HD);
   float m_run = -INFINITY, l_run = 0.f;
-  for (int k0 = 0; k0 < N; k0 += F32_KV) {
+  const int kv_end = causal ? min(N, it.q0 + ATT_Q) : N;
+  const int kmax = causal ? min(N - 1, q) : N - 1;   // last key this query sees
+  for (int k0 = 0; k0 < kv_end; k0 += F32_KV) {
     __syncthreads();
     for (int idx = tid; idx < F32_KV * HD / 4; idx += ATT_Q) {
       const int key = idx / (HD / 4), d = (idx % (HD / 4)) * 4;
@@ -343,7 +351,7 @@ __global__ __launch_bounds__(ATT_Q) void k_attn_f32(const float* __restrict__ qk
       float a = 0.f;
 #pragma unroll
       for (int d = 0; d < HD; ++d) a = fmaf(qv[d], sK[j][d], a);
-      s[j] = (k0 + j < N) ? a * sc : -INFINITY;
+      s[j] = (k0 + j <= kmax) ? a * sc : -INFINITY;
       mt = fmaxf(mt, s[j]);
     }
     const float m_new = fmaxf(m_run, mt);
@@ -371,15 +379,15 @@ __global__ __launch_bounds__(ATT_Q) void k_attn_f32(const float* __restrict__ qk
 
 hipError_t attention_bf16(const bf16_t* qkv, bf16_t* o, const ImgDesc* imgs,
                           const AttnItem* items, int n_items, int heads, int head_dim,
-                          hipStream_t s) {
+                          bool causal, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   dim3 grid(n_items, heads), block(256);
   if (head_dim == 64)
     hipLaunchKernelGGL((k_attn_bf16<64, false>), grid, block, 0, s, qkv, o, nullptr, 0, imgs,
-                       items, heads);
+                       items, heads, (int)causal);
   else if (head_dim == 32)
     hipLaunchKernelGGL((k_attn_bf16<32, false>), grid, block, 0, s, qkv, o, nullptr, 0, imgs,
-                       items, heads);
+                       items, heads, (int)causal);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -387,15 +395,15 @@ hipError_t attention_bf16(const bf16_t* qkv, bf16_t* o, const ImgDesc* imgs,
 
 hipError_t attention_bf16_mx(const bf16_t* qkv, uint8_t* codes, uint8_t* scales, int T,
                              const ImgDesc* imgs, const AttnItem* items, int n_items,
-                             int heads, int head_dim, hipStream_t s) {
+                             int heads, int head_dim, bool causal, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   dim3 grid(n_items, heads), block(256);
   if (head_dim == 64)
     hipLaunchKernelGGL((k_attn_bf16<64, true>), grid, block, 0, s, qkv, codes, scales, T, imgs,
-                       items, heads);
+                       items, heads, (int)causal);
   else if (head_dim == 32)
     hipLaunchKernelGGL((k_attn_bf16<32, true>), grid, block, 0, s, qkv, codes, scales, T, imgs,
-                       items, heads);
+                       items, heads, (int)causal);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -403,13 +411,15 @@ hipError_t attention_bf16_mx(const bf16_t* qkv, uint8_t* codes, uint8_t* scales,
 
 hipError_t attention_f32(const float* qkv, float* o, const ImgDesc* imgs,
                          const AttnItem* items, int n_items, int heads, int head_dim,
-                         hipStream_t s) {
+                         bool causal, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   dim3 grid(n_items, heads), block(ATT_Q);
   if (head_dim == 64)
-    hipLaunchKernelGGL(k_attn_f32<64>, grid, block, 0, s, qkv, o, imgs, items, heads);
+    hipLaunchKernelGGL(k_attn_f32<64>, grid, block, 0, s, qkv, o, imgs, items, heads,
+                       (int)causal);
   else if (head_dim == 32)
-    hipLaunchKernelGGL(k_attn_f32<32>, grid, block, 0, s, qkv, o, imgs, items, heads);
+    hipLaunchKernelGGL(k_attn_f32<32>, grid, block, 0, s, qkv, o, imgs, items, heads,
+                       (int)causal);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -140,6 +140,43 @@ hipError_t layernorm_rows_mx(const float* x, const float* g, const float* b, flo
   return hipGetLastError();
 }
 
+// ------------------------------------------------------- token embedding
+// Text sequences: X[t] = tok_emb[id(t)] + pos[i] for token i of a sequence
+// (row-gather of the learned tables), plus tok_info[t] = (sequence, i).  A
+// descriptor's pix_off is the offset of its ids in the packed id stream.
+// Grid (token within sequence, sequence); one workgroup of 64 lanes per
+// token, float4 columns.  Ids are clamped into [0, vocab) so a bad id cannot
+// read outside the table.
+__global__ __launch_bounds__(64) void k_text_embed(const int32_t* __restrict__ ids,
+                                                   const ImgDesc* __restrict__ seqs,
+                                                   const float* __restrict__ tok_emb,
+                                                   const float* __restrict__ pos, int vocab,
+                                                   int D, float* __restrict__ X,
+                                                   int2* __restrict__ tok_info) {
+  const ImgDesc d = seqs[blockIdx.y];
+  const int i = blockIdx.x;
+  if (i >= d.ntok) return;
+  const int t = d.tok_start + i;                     // row in this part's X
+  const int id = min(max(ids[d.pix_off + i], 0), vocab - 1);  // ids: whole batch
+  const float4* er = reinterpret_cast<const float4*>(tok_emb + (size_t)id * D);
+  const float4* pr = reinterpret_cast<const float4*>(pos + (size_t)i * D);
+  float4* xr = reinterpret_cast<float4*>(X + (size_t)t * D);
+  for (int c = threadIdx.x; c < D / 4; c += 64) {
+    const float4 a = er[c], b = pr[c];
+    xr[c] = make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+  }
+  if (threadIdx.x == 0) tok_info[t] = make_int2((int)blockIdx.y, i);
+}
+
+hipError_t text_embed(const int32_t* ids, const ImgDesc* seqs, int n_seqs, int max_len,
+                      const float* tok_emb, const float* pos, int vocab, int D, float* X,
+                      int2* tok_info, hipStream_t s) {
+  if (n_seqs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_text_embed, dim3(max_len, n_seqs), dim3(64), 0, s, ids, seqs, tok_emb, pos,
+                     vocab, D, X, tok_info);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ im2col
 // Token row t of image i: zeros for the class token, otherwise the patch's
 // raw pixels in (channel, row-in-patch, column-in-patch) order followed by
@@ -202,22 +239,25 @@ __device__ __forceinline__ float block_reduce(float v, float* red, Op op) {
 }
 
 // ----------------------------------------------------- pool + LN + proj + L2
-// Class-token pooling, final LayerNorm (ViT Eq. 4) and bias-free projection,
-// FP32.  Grid (image, chunk of 64 projection outputs): each workgroup
-// normalises its image's class-token row in LDS (cheap, D <= 1024) and
-// produces 64 outputs, one dot product of length D per output, 16 per wave.
+// Pooling, final LayerNorm (ViT Eq. 4) and bias-free projection, FP32.  The
+// pooled row is a sequence's first (the image class token) or, with
+// pool_last, its last (the text end-of-text token).  Grid (sequence, chunk of
+// 64 projection outputs): each workgroup normalises the pooled row in LDS
+// (cheap, D <= 1024) and produces 64 outputs, one dot product of length D per
+// output, 16 per wave.
 __global__ __launch_bounds__(256) void k_pool_project(const float* __restrict__ x,
                                                       const ImgDesc* __restrict__ imgs,
                                                       const float* __restrict__ gm,
                                                       const float* __restrict__ bt, float eps,
                                                       const float* __restrict__ proj, int D,
-                                                      int P, float* __restrict__ e_out) {
+                                                      int P, float* __restrict__ e_out,
+                                                      int pool_last) {
   __shared__ float z[1024];
   __shared__ float red[4];
   const int tid = threadIdx.x;
   const int img = blockIdx.x;
   const ImgDesc d = imgs[img];
-  const float* xr = x + (size_t)d.tok_start * D;
+  const float* xr = x + (size_t)(d.tok_start + (pool_last ? d.ntok - 1 : 0)) * D;
   float s = 0.f;
   for (int c = tid; c < D; c += 256) {
     z[c] = xr[c];
@@ -260,10 +300,10 @@ __global__ __launch_bounds__(256) void k_l2_normalise(const float* __restrict__ 
 
 hipError_t pool_project(const float* x, const ImgDesc* imgs, int n_imgs, const float* g,
                         const float* b, float eps, const float* proj, int D, int P,
-                        float* e_tmp, float* emb, hipStream_t s) {
+                        bool pool_last, float* e_tmp, float* emb, hipStream_t s) {
   if (n_imgs <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_pool_project, dim3(n_imgs, (P + 63) / 64), dim3(256), 0, s, x, imgs, g,
-                     b, eps, proj, D, P, e_tmp);
+                     b, eps, proj, D, P, e_tmp, (int)pool_last);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_l2_normalise, dim3((n_imgs + 3) / 4), dim3(256), 0, s, e_tmp, emb, n_imgs,

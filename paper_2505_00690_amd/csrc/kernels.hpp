@@ -111,23 +111,31 @@ hipError_t im2col(const float* pix, const ImgDesc* imgs, int n_imgs, int max_nto
                   int patch, int kpad, void* out, bool out_bf16, int2* tok_info,
                   hipStream_t s);
 
-// Multi-head self-attention over a packed QKV buffer [T, 3D] -> O [T, D].
+// Multi-head self-attention over a packed QKV buffer [T, 3D] -> O [T, D],
+// within each descriptor's token range; causal: token i attends to 0..i.
 hipError_t attention_bf16(const bf16_t* qkv, bf16_t* o, const ImgDesc* imgs,
                           const AttnItem* items, int n_items, int heads, int head_dim,
-                          hipStream_t s);
+                          bool causal, hipStream_t s);
 // The same with an MXFP8 output: codes [T, D] + scales [D/128][T][4].
 hipError_t attention_bf16_mx(const bf16_t* qkv, uint8_t* codes, uint8_t* scales, int T,
                              const ImgDesc* imgs, const AttnItem* items, int n_items,
-                             int heads, int head_dim, hipStream_t s);
+                             int heads, int head_dim, bool causal, hipStream_t s);
 hipError_t attention_f32(const float* qkv, float* o, const ImgDesc* imgs,
                          const AttnItem* items, int n_items, int heads, int head_dim,
-                         hipStream_t s);
+                         bool causal, hipStream_t s);
 
-// Class-token pooling, final LayerNorm, projection [P, D] into e_tmp
+// Pooling of each sequence's first (class token) or last (pool_last: the
+// text end-of-text token) row, final LayerNorm, projection [P, D] into e_tmp
 // [n, P], then L2 normalisation into emb [n, P].
 hipError_t pool_project(const float* x, const ImgDesc* imgs, int n_imgs, const float* g,
                         const float* b, float eps, const float* proj, int D, int P,
-                        float* e_tmp, float* emb, hipStream_t s);
+                        bool pool_last, float* e_tmp, float* emb, hipStream_t s);
+
+// Token embedding of packed text sequences (descriptors: tok_start, ntok):
+// X [T, D] = tok_emb[id] + pos[index in sequence], and tok_info [T].
+hipError_t text_embed(const int32_t* ids, const ImgDesc* seqs, int n_seqs, int max_len,
+                      const float* tok_emb, const float* pos, int vocab, int D, float* X,
+                      int2* tok_info, hipStream_t s);
 
 // Per-row softmax / sigmoid of logits in place, and the row argmax.
 hipError_t score_rows(float* scores, int32_t* top1, int rows, int cols, int head,

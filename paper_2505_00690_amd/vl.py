@@ -22,7 +22,9 @@ __all__ = [
     "vl_model_set_option", "vl_encode_workspace_bytes", "vl_encode_images", "vl_score",
     "vl_status_string", "vl_last_error_message", "Encoder", "EXPORTED_SYMBOLS",
     "vl_gemm_config_count", "vl_gemm_config_name", "vl_model_get_tuning",
-    "vl_model_set_tuning", "vl_model_autotune", "GEMM_OPS", "VL_MXFP8", "vl_mx_quantize", "vl_mx_gemm",
+    "vl_model_set_tuning", "vl_model_autotune", "GEMM_OPS", "VL_MXFP8", "vl_mx_quantize",
+    "vl_mx_gemm", "VlTextConfig", "vl_text_weights_count", "vl_text_model_create",
+    "vl_text_workspace_bytes", "vl_encode_texts", "TextEncoder",
 ]
 
 VL_FP32, VL_BF16, VL_FP8W_BF16A, VL_MXFP8 = 0, 1, 2, 3
@@ -38,7 +40,8 @@ EXPORTED_SYMBOLS = (
     "vl_abi_version", "vl_status_string", "vl_last_error_message", "vl_weights_count",
     "vl_model_create", "vl_model_destroy", "vl_model_set_option",
     "vl_encode_workspace_bytes", "vl_encode_images", "vl_score", "vl_model_op_times",
-    "vl_mx_quantize", "vl_mx_gemm",
+    "vl_mx_quantize", "vl_mx_gemm", "vl_text_weights_count", "vl_text_model_create",
+    "vl_text_workspace_bytes", "vl_encode_texts",
     "vl_gemm_config_count", "vl_gemm_config_name", "vl_model_get_tuning",
     "vl_model_set_tuning", "vl_model_autotune",
 )
@@ -69,6 +72,19 @@ class VlConfig(ctypes.Structure):
         return cls(int(c.patch), int(c.width), int(c.layers), int(c.heads), int(c.mlp),
                    int(c.proj_dim), int(c.base_grid), float(c.ln_eps),
                    (ctypes.c_float * 3)(*c.chan_mean), (ctypes.c_float * 3)(*c.chan_std))
+
+
+class VlTextConfig(ctypes.Structure):
+    _fields_ = [
+        ("vocab", ctypes.c_int32), ("ctx", ctypes.c_int32), ("width", ctypes.c_int32),
+        ("layers", ctypes.c_int32), ("heads", ctypes.c_int32), ("mlp", ctypes.c_int32),
+        ("proj_dim", ctypes.c_int32), ("ln_eps", ctypes.c_float),
+    ]
+
+    @classmethod
+    def from_model(cls, c) -> "VlTextConfig":
+        return cls(int(c.vocab), int(c.ctx), int(c.width), int(c.layers), int(c.heads),
+                   int(c.mlp), int(c.proj_dim), float(c.ln_eps))
 
 
 _LIB: Optional[ctypes.CDLL] = None
@@ -120,6 +136,15 @@ def lib() -> ctypes.CDLL:
     L.vl_model_autotune.argtypes = [_vp, _vp, _pi32, _pi32, _i32, _vp, _vp, _sz, _i32, _vp]
     L.vl_mx_quantize.restype = ctypes.c_int
     L.vl_mx_quantize.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp]
+    L.vl_text_weights_count.restype = _sz
+    L.vl_text_weights_count.argtypes = [ctypes.POINTER(VlTextConfig)]
+    L.vl_text_model_create.restype = ctypes.c_int
+    L.vl_text_model_create.argtypes = [ctypes.POINTER(VlTextConfig), ctypes.c_int, _vp, _sz, _vp,
+                                       ctypes.POINTER(_vp)]
+    L.vl_text_workspace_bytes.restype = _sz
+    L.vl_text_workspace_bytes.argtypes = [_vp, _i32, _pi32]
+    L.vl_encode_texts.restype = ctypes.c_int
+    L.vl_encode_texts.argtypes = [_vp, _vp, _pi32, _i32, _vp, _vp, _sz, _vp]
     L.vl_mx_gemm.restype = ctypes.c_int
     L.vl_mx_gemm.argtypes = [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _i32, _vp]
     L.vl_score.restype = ctypes.c_int
@@ -248,6 +273,35 @@ def vl_encode_images(handle, pixels: torch.Tensor, heights: Sequence[int],
                                   workspace.numel() * workspace.element_size(), _stream(stream)))
 
 
+def vl_text_weights_count(cfg) -> int:
+    c = cfg if isinstance(cfg, VlTextConfig) else VlTextConfig.from_model(cfg)
+    return int(lib().vl_text_weights_count(ctypes.byref(c)))
+
+
+def vl_text_model_create(cfg, precision, weights: torch.Tensor, stream=None) -> ctypes.c_void_p:
+    c = cfg if isinstance(cfg, VlTextConfig) else VlTextConfig.from_model(cfg)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    handle = ctypes.c_void_p()
+    _check(lib().vl_text_model_create(ctypes.byref(c), prec,
+                                      _ptr(weights, torch.float32, "weights"), weights.numel(),
+                                      _stream(stream), ctypes.byref(handle)))
+    return handle
+
+
+def vl_text_workspace_bytes(handle, lengths: Sequence[int]) -> int:
+    return int(lib().vl_text_workspace_bytes(handle, len(lengths), _i32_array(lengths)))
+
+
+def vl_encode_texts(handle, ids: torch.Tensor, lengths: Sequence[int], emb_out: torch.Tensor,
+                    workspace: torch.Tensor, stream=None) -> None:
+    if ids.numel() != sum(int(x) for x in lengths):
+        raise ValueError("ids must hold sum(lengths) tokens")
+    _check(lib().vl_encode_texts(handle, _ptr(ids, torch.int32, "ids"), _i32_array(lengths),
+                                 len(lengths), _ptr(emb_out, torch.float32, "emb_out"),
+                                 _ptr(workspace, None, "workspace"),
+                                 workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
 def vl_score(emb: torch.Tensor, texts: torch.Tensor, head, scale: float, bias: float,
              scores_out: torch.Tensor, top1_out: Optional[torch.Tensor] = None,
              stream=None) -> None:
@@ -364,4 +418,45 @@ class Encoder:
         ws = self.workspace(need)
         vl_encode_images(self.handle, pixels, [h for h, _ in sizes], [w for _, w in sizes], out,
                          ws, stream)
+        return out
+
+
+class TextEncoder:
+    """Owns a text-model handle built from an FP32 weight blob on the device,
+    plus a reusable workspace tensor."""
+
+    def __init__(self, cfg, weights: torch.Tensor, precision: str = "bf16",
+                 graphs: bool = False, stream=None):
+        self.cfg = cfg
+        self.precision = precision
+        self.handle = vl_text_model_create(cfg, precision, weights, stream)
+        if graphs:
+            vl_model_set_option(self.handle, VL_OPT_GRAPHS, 1)
+        self._ws: Optional[torch.Tensor] = None
+        self.device = weights.device
+
+    def close(self) -> None:
+        if self.handle is not None and self.handle.value:
+            vl_model_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def encode(self, ids: torch.Tensor, lengths: Sequence[int],
+               out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """ids: int32 device tensor of all sequences' token ids back to back;
+        lengths: tokens per sequence.  Returns [n, proj_dim] unit embeddings."""
+        n = len(lengths)
+        if out is None:
+            out = torch.empty((n, self.cfg.proj_dim), dtype=torch.float32, device=self.device)
+        need = vl_text_workspace_bytes(self.handle, lengths)
+        if need == 0:
+            raise VlError(1, "invalid text lengths")
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        vl_encode_texts(self.handle, ids, lengths, out, self._ws, stream)
         return out

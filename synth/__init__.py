@@ -26,7 +26,9 @@ __all__ = [
     "ModelConfig", "Workload", "MODELS", "WORKLOADS",
     "weight_layout", "weight_count", "make_blob", "make_params", "params_to_blob",
     "blob_to_params", "make_images", "make_texts", "draw_resolutions",
-    "draw_requests", "seeds_for",
+    "draw_requests", "seeds_for", "TextConfig", "TEXT_MODELS", "text_weight_layout",
+    "text_weight_count", "make_text_blob", "text_blob_to_params", "make_token_ids",
+    "draw_text_lengths",
 ]
 
 
@@ -275,3 +277,109 @@ def draw_requests(n: int, qps: float, choices: Sequence[int], seed: int,
     res = rng.integers(0, len(choices), size=n)
     return [Request(float(t[i]), [(int(choices[res[i]]),) * 2] * int(counts[i]))
             for i in range(n)]
+
+
+
+# ---------------------------------------------------------------------------
+# Text tower (causal transformer over token ids).
+# ---------------------------------------------------------------------------
+@dataclass(frozen=True)
+class TextConfig:
+    """Dimensions of a text tower: token table rows, context length (position
+    table rows), width D, L blocks, h heads, MLP width F, projection width."""
+    name: str
+    vocab: int
+    ctx: int
+    width: int
+    layers: int
+    heads: int
+    mlp: int
+    proj_dim: int
+    ln_eps: float = 1e-5
+
+    @property
+    def head_dim(self) -> int:
+        return self.width // self.heads
+
+
+TEXT_MODELS: Dict[str, TextConfig] = {
+    "tiny_text": TextConfig("tiny_text", vocab=1000, ctx=77, width=128, layers=2, heads=4,
+                            mlp=512, proj_dim=128),
+    # the CLIP ViT-L/14 text tower's shape
+    "l14_text": TextConfig("l14_text", vocab=49408, ctx=77, width=768, layers=12, heads=12,
+                           mlp=3072, proj_dim=768),
+}
+
+
+def text_weight_layout(c: TextConfig) -> List[Tuple[str, Tuple[int, ...]]]:
+    """(name, shape) in blob order: tok_emb [V, D], pos [ctx, D], the blocks
+    as for images, lnf_g, lnf_b, proj_w [P_dim, D]."""
+    D, F = c.width, c.mlp
+    bs = {"ln1_g": (D,), "ln1_b": (D,), "qkv_w": (3 * D, D), "qkv_b": (3 * D,),
+          "o_w": (D, D), "o_b": (D,), "ln2_g": (D,), "ln2_b": (D,),
+          "fc1_w": (F, D), "fc1_b": (F,), "fc2_w": (D, F), "fc2_b": (D,)}
+    out: List[Tuple[str, Tuple[int, ...]]] = [("tok_emb", (c.vocab, D)), ("pos", (c.ctx, D))]
+    for l in range(c.layers):
+        out += [(f"{l}.{n}", bs[n]) for n in _BLOCK_TENSORS]
+    out += [("lnf_g", (D,)), ("lnf_b", (D,)), ("proj_w", (c.proj_dim, D))]
+    return out
+
+
+def text_weight_count(c: TextConfig) -> int:
+    return int(sum(int(np.prod(s)) for _, s in text_weight_layout(c)))
+
+
+def make_text_blob(c: TextConfig, seed: int, std: float = 0.02) -> np.ndarray:
+    """Random-init text weights in blob order, drawn like make_blob: N(0,
+    std^2) everywhere, plus 1 on every LayerNorm gain."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    blob = np.empty(text_weight_count(c), np.float32)
+    _fill_normal(rng, blob, std)
+    o = 0
+    for name, shape in text_weight_layout(c):
+        n = int(np.prod(shape))
+        if name.endswith("_g"):
+            blob[o:o + n] += np.float32(1.0)
+        o += n
+    return blob
+
+
+def text_blob_to_params(c: TextConfig, blob: np.ndarray) -> Dict[str, object]:
+    blob = np.asarray(blob, dtype=np.float32).reshape(-1)
+    assert blob.size == text_weight_count(c)
+    p: Dict[str, object] = {"layers": [dict() for _ in range(c.layers)]}
+    o = 0
+    for name, shape in text_weight_layout(c):
+        n = int(np.prod(shape))
+        a = blob[o:o + n].reshape(shape)
+        o += n
+        if "." in name:
+            l, t = name.split(".", 1)
+            p["layers"][int(l)][t] = a
+        else:
+            p[name] = a
+    return p
+
+
+def draw_text_lengths(n: int, ctx: int, seed: int) -> List[int]:
+    """Prompt-like token counts: U{5..20} (short class prompts), with one in
+    ten sequences at the full context length."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lens = rng.integers(5, 21, size=n)
+    full = rng.random(n) < 0.1
+    return [int(ctx if f else min(l, ctx)) for l, f in zip(lens, full)]
+
+
+def make_token_ids(lengths: Sequence[int], vocab: int, seed: int) -> List[np.ndarray]:
+    """One int32 id sequence per length: start-of-text (vocab - 2), uniform
+    ids below vocab - 2, end-of-text (vocab - 1) last; a length-1 sequence
+    is just the end-of-text token."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for L in lengths:
+        ids = rng.integers(0, vocab - 2, size=L).astype(np.int32)
+        if L >= 2:
+            ids[0] = vocab - 2
+        ids[-1] = vocab - 1
+        out.append(ids)
+    return out

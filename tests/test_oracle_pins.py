@@ -557,3 +557,84 @@ def test_mx_decode_inverts_quantise():
     c[0, 0], c[0, 31] = 0x38, 0xC0
     v = O.mx_decode(c, np.array([[3]]))
     assert v[0, 0] == 8.0 and v[0, 31] == -16.0 and not v[0, 1:31].any()
+
+
+# ----------------------------------------------------------------- text tower
+def _text_setup(seed):
+    c = synth.TEXT_MODELS["tiny_text"]
+    p = synth.text_blob_to_params(c, synth.make_text_blob(c, seed))
+    return c, p
+
+
+def test_causal_attention_bruteforce_rows():
+    # row i by hand: softmax over the prefix 0..i only
+    rng = _rng(40)
+    n, d = 7, 8
+    q, k, v = (rng.standard_normal((n, d)) for _ in range(3))
+    got = O.causal_attention_head(q, k, v)
+    for i in range(n):
+        s = np.array([q[i] @ k[j] / math.sqrt(d) for j in range(i + 1)])
+        w = np.exp(s - s.max())
+        w /= w.sum()
+        assert np.allclose(got[i], sum(w[j] * v[j] for j in range(i + 1)), rtol=0, atol=1e-14)
+    assert np.array_equal(got[0], v[0])          # token 0 sees only itself
+
+
+def test_text_tower_matches_torch_causal_layers():
+    """Text tower against PyTorch modules: embedding lookup, pre-LN
+    TransformerEncoderLayer with the square subsequent (causal) mask,
+    layer_norm of the last token, linear projection; float64."""
+    c, p = _text_setup(41)
+    f = lambda a: torch.from_numpy(np.asarray(a, np.float64))  # noqa: E731
+    layers = []
+    for lp in p["layers"]:
+        L = torch.nn.TransformerEncoderLayer(c.width, c.heads, c.mlp, dropout=0.0,
+                                             activation="gelu", layer_norm_eps=c.ln_eps,
+                                             batch_first=True, norm_first=True).eval()
+        with torch.no_grad():
+            L.self_attn.in_proj_weight.copy_(f(lp["qkv_w"]))
+            L.self_attn.in_proj_bias.copy_(f(lp["qkv_b"]))
+            L.self_attn.out_proj.weight.copy_(f(lp["o_w"]))
+            L.self_attn.out_proj.bias.copy_(f(lp["o_b"]))
+            L.linear1.weight.copy_(f(lp["fc1_w"]))
+            L.linear1.bias.copy_(f(lp["fc1_b"]))
+            L.linear2.weight.copy_(f(lp["fc2_w"]))
+            L.linear2.bias.copy_(f(lp["fc2_b"]))
+            L.norm1.weight.copy_(f(lp["ln1_g"]))
+            L.norm1.bias.copy_(f(lp["ln1_b"]))
+            L.norm2.weight.copy_(f(lp["ln2_g"]))
+            L.norm2.bias.copy_(f(lp["ln2_b"]))
+        layers.append(L)
+    emb = torch.nn.Embedding(c.vocab, c.width)
+    with torch.no_grad():
+        emb.weight.copy_(f(p["tok_emb"]))
+    for ids in synth.make_token_ids([1, 6, 19, c.ctx], c.vocab, 42):
+        n = len(ids)
+        mask = torch.nn.Transformer.generate_square_subsequent_mask(n, dtype=torch.float64)
+        with torch.no_grad():
+            t = (emb(torch.from_numpy(ids.astype(np.int64))) + f(p["pos"])[:n])[None]
+            for L in layers:
+                t = L(t, src_mask=mask, is_causal=True)
+            z = torch.nn.functional.layer_norm(t[0, -1], (c.width,), f(p["lnf_g"]),
+                                               f(p["lnf_b"]), c.ln_eps)
+            e = torch.nn.functional.linear(z, f(p["proj_w"]))
+            e = (e / e.norm()).numpy()
+        assert np.max(np.abs(O.encode_text(ids, p, c) - e)) <= 1e-12
+
+
+def test_text_prefix_invariance_and_last_token_pooling():
+    # causal: a prefix's hidden states do not depend on later tokens, so the
+    # embedding of a prefix equals pooling the full sequence at its end
+    c, p = _text_setup(43)
+    ids = synth.make_token_ids([30], c.vocab, 44)[0]
+    full = O.text_hidden(ids, p, c)
+    for k in (1, 2, 11, 29):
+        assert np.allclose(O.text_hidden(ids[:k], p, c), full[:k], rtol=0, atol=1e-13)
+        z = O.layernorm(full[k - 1], p["lnf_g"], p["lnf_b"], c.ln_eps)
+        e = np.asarray(p["proj_w"], np.float64) @ z
+        assert np.allclose(O.encode_text(ids[:k], p, c), e / np.linalg.norm(e), atol=1e-13)
+    # and the later tokens do change the last position (not vacuous)
+    other = ids.copy()
+    other[5] = (other[5] + 1) % (c.vocab - 2)
+    assert not np.allclose(O.text_hidden(other, p, c)[-1], full[-1], atol=1e-6)
+    assert np.allclose(O.text_hidden(other, p, c)[:5], full[:5], rtol=0, atol=1e-13)
