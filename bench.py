@@ -38,7 +38,7 @@ def flops_per_image(c: synth.ModelConfig, res: int) -> float:
     npch = g * g
     n = npch + 1
     D, F = c.width, c.mlp
-    f = 2.0 * npch * 3 * c.patch ** 2 * D
+    f = 2.0 * npch * c.channels * c.patch ** 2 * D
     per_layer = 2.0 * n * D * 3 * D + 4.0 * n * n * D + 2.0 * n * D * D + 4.0 * n * D * F
     f += c.layers * per_layer
     f += 2.0 * D * c.proj_dim
@@ -57,7 +57,7 @@ def op_flops(c: synth.ModelConfig, sizes, op: str) -> float:
         "fc1_gemm": 2.0 * T * D * F,
         "fc2_gemm": 2.0 * T * F * D,
         "attention": sum(4.0 * n * n * D for n in toks),
-        "patch_embed": sum(2.0 * (n - 1) * 3 * c.patch ** 2 * D for n in toks),
+        "patch_embed": sum(2.0 * (n - 1) * c.channels * c.patch ** 2 * D for n in toks),
     }.get(op, 0.0)
 
 
@@ -143,6 +143,37 @@ def text_leg(torch, vl, n_texts: int, steps: int, seed: int = 3002):
             "tflops": flops / (ms / 1e3) / 1e12, "steps": steps}
 
 
+def rgbd_leg(torch, vl, steps: int, n_env: int = 256, w_seed: int = 1006, i_seed: int = 2006):
+    """The navigation benchmark's observation batch: one RGB-D 128x128 frame
+    (4 planes) per environment for 256 environments on one GPU, encoded by
+    a ViT-S/16-shaped tower in BF16 with HIP graphs (the policy network
+    itself is not specified, so the encoder size is a choice)."""
+    c = synth.MODELS["rgbd_s16"]
+    w = torch.from_numpy(synth.make_blob(c, w_seed)).cuda()
+    imgs = synth.make_images([(128, 128)] * n_env, i_seed, channels=c.channels)
+    pix = torch.from_numpy(np.concatenate([im.reshape(-1) for im in imgs])).cuda()
+    sizes = [(128, 128)] * n_env
+    enc = vl.Encoder(c, w, "bf16", graphs=True)
+    del w
+    out = torch.empty((n_env, c.proj_dim), dtype=torch.float32, device="cuda")
+    for _ in range(2):
+        enc.encode(pix, sizes, out=out)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        enc.encode(pix, sizes, out=out)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    flops = n_env * flops_per_image(c, 128)
+    enc.close()
+    return {"value": n_env / (ms / 1e3), "unit": "observations/s", "ms_per_batch": ms,
+            "environments": n_env, "frame": "4x128x128", "model": c.name, "precision": "bf16",
+            "tflops": flops / (ms / 1e3) / 1e12, "steps": steps}
+
+
 def serving_leg(torch, vl, n_requests: int, warmup_requests: int, slots: int,
                 budget_gib: float, max_batch_images: int):
     """The serving workload: ViT-L/14 with e4m3 per-row weights and BF16
@@ -223,6 +254,7 @@ def main(argv=None) -> int:
     ap.add_argument("--timing-steps", type=int, default=3)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving (p50/p99) leg")
     ap.add_argument("--no-text", action="store_true", help="skip the text-tower leg")
+    ap.add_argument("--no-rgbd", action="store_true", help="skip the RGB-D observation leg")
     ap.add_argument("--text-steps", type=int, default=5)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB first, so "
@@ -373,6 +405,10 @@ def main(argv=None) -> int:
     if not args.no_text:
         result["text_tower"] = text_leg(torch, vl, wl.n_texts, args.text_steps)
         print(f"# text tower: {json.dumps(result['text_tower'])}", file=sys.stderr, flush=True)
+
+    if not args.no_rgbd:
+        result["rgbd_observations"] = rgbd_leg(torch, vl, args.text_steps)
+        print(f"# rgbd: {json.dumps(result['rgbd_observations'])}", file=sys.stderr, flush=True)
 
     if not args.no_serve:
         result["serving"] = serving_leg(torch, vl, args.serve_requests, 100, args.serve_slots,

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define VL_ABI_VERSION 1
+#define VL_ABI_VERSION 2
 
 typedef enum vl_status {
   VL_OK = 0,
@@ -94,7 +94,10 @@ typedef enum vl_head {
 /* Model dimensions.  width % heads == 0 and head_dim = width/heads must be
  * 32 or 64; width % 128 == 0; mlp % 128 == 0; proj_dim % 4 == 0;
  * width <= 1024.  ln_eps is the LayerNorm epsilon (biased variance).
- * Pixels are normalised as (x - chan_mean[c]) / chan_std[c].               */
+ * channels: input planes per pixel, 1..4 (3 for RGB; 4 for the RGB-D
+ * observations of the paper's navigation benchmark, Appendix, observation
+ * spaces).  Pixels are normalised as (x - chan_mean[c]) / chan_std[c] for
+ * c < channels (entries past `channels` are ignored).                      */
 typedef struct vl_config {
   int32_t patch;
   int32_t width;
@@ -104,15 +107,16 @@ typedef struct vl_config {
   int32_t proj_dim;
   int32_t base_grid; /* the position table covers base_grid x base_grid  */
   float ln_eps;
-  float chan_mean[3];
-  float chan_std[3];
+  float chan_mean[4];
+  float chan_std[4];
+  int32_t channels;
 } vl_config;
 
 typedef struct vl_model vl_model; /* opaque; immutable after creation */
 
 /* Number of FP32 values in the weight blob for `cfg`, 0 if cfg is invalid.
  * Blob layout: tensors back to back, each C-contiguous, in this order
- *   patch_w [D,3,P,P]  patch_b [D]  cls [D]  pos [1+g0*g0, D]
+ *   patch_w [D,C,P,P]  patch_b [D]  cls [D]  pos [1+g0*g0, D]   (C = channels)
  *   for each of the L blocks:
  *     ln1_g [D] ln1_b [D] qkv_w [3D,D] qkv_b [3D] o_w [D,D] o_b [D]
  *     ln2_g [D] ln2_b [D] fc1_w [F,D] fc1_b [F] fc2_w [D,F] fc2_b [D]
@@ -265,7 +269,7 @@ size_t vl_encode_workspace_bytes(const vl_model* m, int32_t n_images,
                                  const int32_t* heights, const int32_t* widths);
 
 /* Encode n_images images.
- *  pixels_dev : FP32 images back to back, image i is [3, H_i, W_i]
+ *  pixels_dev : FP32 images back to back, image i is [C, H_i, W_i]
  *               (channel, row, column), values as given (normalisation is
  *               applied inside).  The patch grid is floor(H/P) x floor(W/P);
  *               pixels past the last whole patch are ignored.

@@ -101,7 +101,7 @@ def sigmoid(x: np.ndarray) -> np.ndarray:
 # ---------------------------------------------------------------------------
 def normalise_pixels(img: np.ndarray, mean: Sequence[float],
                      std: Sequence[float]) -> np.ndarray:
-    """x_hat[c] = (x[c] - mean_c) / std_c for a [3, H, W] image."""
+    """x_hat[c] = (x[c] - mean_c) / std_c for a [C, H, W] image."""
     img = np.asarray(img, F64)
     m = np.asarray(mean, F64)[:, None, None]
     s = np.asarray(std, F64)[:, None, None]

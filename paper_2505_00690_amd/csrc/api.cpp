@@ -122,7 +122,8 @@ bool config_ok(const vl_config* c, std::string* why) {
   if (c->proj_dim % 4) { *why = "proj_dim must be a multiple of 4"; return false; }
   if (c->proj_dim > 1024) { *why = "proj_dim must be <= 1024"; return false; }
   if (!(c->ln_eps >= 0.f)) { *why = "ln_eps must be >= 0"; return false; }
-  for (int i = 0; i < 3; ++i)
+  if (c->channels < 1 || c->channels > 4) { *why = "channels must be 1..4"; return false; }
+  for (int i = 0; i < c->channels; ++i)
     if (!(c->chan_std[i] > 0.f)) { *why = "chan_std must be > 0"; return false; }
   return true;
 }
@@ -152,7 +153,7 @@ size_t text_weights_count(const vl_text_config& c) {
 
 size_t weights_count(const vl_config& c) {
   const size_t D = c.width, F = c.mlp, P = c.patch, g = c.base_grid;
-  size_t n = D * 3 * P * P + D + D + (1 + g * g) * D;
+  size_t n = D * c.channels * P * P + D + D + (1 + g * g) * D;
   n += (size_t)c.layers * (2 * D + 3 * D * D + 3 * D + D * D + D + 2 * D + F * D + F + D * F + D);
   n += 2 * D + (size_t)c.proj_dim * D;
   return n;
@@ -268,7 +269,7 @@ bool make_plan(const vl_model* m, int32_t n, const int32_t* hs, const int32_t* w
     d.H = H; d.W = W; d.gh = gh; d.gw = gw;
     d.tok_start = (int32_t)T;   // absolute for now
     d.ntok = (int32_t)ntok;
-    pix += 3LL * H * W;
+    pix += (int64_t)m->cfg.channels * H * W;
     T += ntok;
     p->hw[2 * i] = H;
     p->hw[2 * i + 1] = W;
@@ -408,8 +409,8 @@ vl_status run_part(vl_model* m, const Part& p, const void* in, float* emb, char*
     VL_TIMED(T_PATCH, VL_HIP(text_embed(static_cast<const int32_t*>(in), d_imgs, p.n, p.max_ntok,
                                         m->tok_emb, m->pos, m->vocab, D, X, tok, s)));
   else VL_TIMED(T_PATCH, {
-    VL_HIP(im2col(static_cast<const float*>(in), d_imgs, p.n, p.max_ntok, m->P, m->Kpad, QH,
-                  !f32, tok, s));
+    VL_HIP(im2col(static_cast<const float*>(in), d_imgs, p.n, p.max_ntok, m->cfg.channels, m->P,
+                  m->Kpad, QH, !f32, tok, s));
     if (f32)
       VL_HIP(gemm_f32(static_cast<const float*>(QH), m->Kpad,
                       static_cast<const float*>(m->patch_w), m->Kpad, T, D, m->Kpad, OP_PATCH,
@@ -643,8 +644,8 @@ static vl_status build_weights(vl_model* m, const float* wdev, hipStream_t s, vl
   if (m->text) {
     chk(copy_f32(s_tok, f(d_tok), (size_t)m->vocab * D, s), "copy token table");
   } else {
-    chk(fold_patch_weights(s_patch_w, s_patch_b, m->cfg.chan_mean, m->cfg.chan_std, m->D, m->P,
-                           m->Kpad, prec == VL_FP32 ? f(d_patch_w) : nullptr,
+    chk(fold_patch_weights(s_patch_w, s_patch_b, m->cfg.chan_mean, m->cfg.chan_std,
+                           m->cfg.channels, m->D, m->P, m->Kpad, prec == VL_FP32 ? f(d_patch_w) : nullptr,
                            prec == VL_FP32 ? nullptr : reinterpret_cast<bf16_t*>(b + d_patch_w),
                            f(d_patch_b), s),
         "fold_patch_weights");
@@ -775,7 +776,7 @@ vl_status vl_model_create(const vl_config* cfg, vl_precision prec, const float* 
   if (hipGetDevice(&m->device) != hipSuccess) { delete m; return fail(VL_ERR_DEVICE, "hipGetDevice failed"); }
   m->D = cfg->width; m->F = cfg->mlp; m->heads = cfg->heads; m->hd = hd; m->L = cfg->layers;
   m->P = cfg->patch; m->Pd = cfg->proj_dim; m->g0 = cfg->base_grid;
-  m->Kpe = 3 * m->P * m->P;
+  m->Kpe = cfg->channels * m->P * m->P;
   m->Kpad = (m->Kpe + 63) / 64 * 64;
   return build_weights(m, wdev, static_cast<hipStream_t>(stream), out);
 }

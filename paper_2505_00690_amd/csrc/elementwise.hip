@@ -183,8 +183,8 @@ hipError_t text_embed(const int32_t* ids, const ImgDesc* seqs, int n_seqs, int m
 // zero padding to kpad.  One wave per token; blockIdx.y is the image.
 template <bool OUT_BF16>
 __global__ __launch_bounds__(256) void k_im2col(const float* __restrict__ pix,
-                                                const ImgDesc* __restrict__ imgs, int patch,
-                                                int kpad, void* __restrict__ out,
+                                                const ImgDesc* __restrict__ imgs, int chans,
+                                                int patch, int kpad, void* __restrict__ out,
                                                 int2* __restrict__ tok_info) {
   const ImgDesc d = imgs[blockIdx.y];
   const int tok = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void k_im2col(const float* __restrict__ pix,
   if (tok >= d.ntok) return;
   const int t = d.tok_start + tok;
   if (lane == 0) tok_info[t] = make_int2(blockIdx.y, tok);
-  const int pp = patch * patch, kreal = 3 * pp;
+  const int pp = patch * patch, kreal = chans * pp;
   int r = 0, q = 0;
   if (tok > 0) {
     r = (tok - 1) / d.gw;
@@ -213,14 +213,16 @@ __global__ __launch_bounds__(256) void k_im2col(const float* __restrict__ pix,
   }
 }
 
-hipError_t im2col(const float* pix, const ImgDesc* imgs, int n_imgs, int max_ntok, int patch,
-                  int kpad, void* out, bool out_bf16, int2* tok_info, hipStream_t s) {
+hipError_t im2col(const float* pix, const ImgDesc* imgs, int n_imgs, int max_ntok, int chans,
+                  int patch, int kpad, void* out, bool out_bf16, int2* tok_info, hipStream_t s) {
   if (n_imgs <= 0) return hipSuccess;
   dim3 grid((max_ntok + 3) / 4, n_imgs), block(256);
   if (out_bf16)
-    hipLaunchKernelGGL(k_im2col<true>, grid, block, 0, s, pix, imgs, patch, kpad, out, tok_info);
+    hipLaunchKernelGGL(k_im2col<true>, grid, block, 0, s, pix, imgs, chans, patch, kpad, out,
+                       tok_info);
   else
-    hipLaunchKernelGGL(k_im2col<false>, grid, block, 0, s, pix, imgs, patch, kpad, out, tok_info);
+    hipLaunchKernelGGL(k_im2col<false>, grid, block, 0, s, pix, imgs, chans, patch, kpad, out,
+                       tok_info);
   return hipGetLastError();
 }
 
@@ -449,22 +451,22 @@ hipError_t mx_quantise_rows(const float* src, uint8_t* codes, uint8_t* scales, i
 // b'[d] = b[d] - sum_{c,a,b} W[d,c,a,b] * mean_c / std_c.  Output rows are
 // padded with zeros to kpad columns.  One workgroup per output channel d.
 __global__ __launch_bounds__(256) void k_fold_patch(const float* __restrict__ w,
-                                                    const float* __restrict__ b, float3 mean,
-                                                    float3 stdv, int pp, int kpad,
+                                                    const float* __restrict__ b, float4 mean,
+                                                    float4 stdv, int chans, int pp, int kpad,
                                                     float* __restrict__ w32,
                                                     bf16_t* __restrict__ w16,
                                                     float* __restrict__ bout) {
   __shared__ float red[4];
   const int d = blockIdx.x;
-  const int kreal = 3 * pp;
+  const int kreal = chans * pp;
   const float* wr = w + (size_t)d * kreal;
   float acc = 0.f;
   for (int k = threadIdx.x; k < kpad; k += 256) {
     float v = 0.f;
     if (k < kreal) {
       const int c = k / pp;
-      const float sd = c == 0 ? stdv.x : (c == 1 ? stdv.y : stdv.z);
-      const float mu = c == 0 ? mean.x : (c == 1 ? mean.y : mean.z);
+      const float sd = c == 0 ? stdv.x : (c == 1 ? stdv.y : (c == 2 ? stdv.z : stdv.w));
+      const float mu = c == 0 ? mean.x : (c == 1 ? mean.y : (c == 2 ? mean.z : mean.w));
       v = wr[k] / sd;
       acc = fmaf(v, mu, acc);
     }
@@ -476,11 +478,14 @@ __global__ __launch_bounds__(256) void k_fold_patch(const float* __restrict__ w,
 }
 
 hipError_t fold_patch_weights(const float* w, const float* b, const float* mean,
-                              const float* stdv, int D, int patch, int kpad, float* w_f32,
-                              bf16_t* w_bf16, float* b_out, hipStream_t s) {
+                              const float* stdv, int chans, int D, int patch, int kpad,
+                              float* w_f32, bf16_t* w_bf16, float* b_out, hipStream_t s) {
+  if (chans < 1 || chans > 4) return hipErrorInvalidValue;
+  float mu[4] = {0.f, 0.f, 0.f, 0.f}, sd[4] = {1.f, 1.f, 1.f, 1.f};
+  for (int c = 0; c < chans; ++c) { mu[c] = mean[c]; sd[c] = stdv[c]; }
   hipLaunchKernelGGL(k_fold_patch, dim3(D), dim3(256), 0, s, w, b,
-                     make_float3(mean[0], mean[1], mean[2]), make_float3(stdv[0], stdv[1], stdv[2]),
-                     patch * patch, kpad, w_f32, w_bf16, b_out);
+                     make_float4(mu[0], mu[1], mu[2], mu[3]), make_float4(sd[0], sd[1], sd[2], sd[3]),
+                     chans, patch * patch, kpad, w_f32, w_bf16, b_out);
   return hipGetLastError();
 }
 

@@ -106,8 +106,9 @@ hipError_t layernorm_rows_mx(const float* x, const float* g, const float* b, flo
                              uint8_t* codes, uint8_t* scales, int M, int D, hipStream_t s);
 
 // Patch gathering: token rows [T, Kpad] of raw pixels in (c, a, b) order
-// (class-token rows and the K padding are zero) plus tok_info [T].
-hipError_t im2col(const float* pix, const ImgDesc* imgs, int n_imgs, int max_ntok,
+// over `chans` input planes (class-token rows and the K padding are zero)
+// plus tok_info [T].
+hipError_t im2col(const float* pix, const ImgDesc* imgs, int n_imgs, int max_ntok, int chans,
                   int patch, int kpad, void* out, bool out_bf16, int2* tok_info,
                   hipStream_t s);
 
@@ -150,7 +151,7 @@ hipError_t quantise_e4m3_rows(const float* src, uint8_t* dst, float* scales, int
 hipError_t mx_quantise_rows(const float* src, uint8_t* codes, uint8_t* scales, int rows,
                             int cols, hipStream_t s);
 hipError_t fold_patch_weights(const float* w, const float* b, const float* mean,
-                              const float* stdv, int D, int patch, int kpad,
+                              const float* stdv, int chans, int D, int patch, int kpad,
                               float* w_f32, bf16_t* w_bf16, float* b_out, hipStream_t s);
 hipError_t copy_f32(const float* src, float* dst, size_t n, hipStream_t s);
 

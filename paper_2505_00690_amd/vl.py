@@ -64,14 +64,18 @@ class VlConfig(ctypes.Structure):
         ("patch", ctypes.c_int32), ("width", ctypes.c_int32), ("layers", ctypes.c_int32),
         ("heads", ctypes.c_int32), ("mlp", ctypes.c_int32), ("proj_dim", ctypes.c_int32),
         ("base_grid", ctypes.c_int32), ("ln_eps", ctypes.c_float),
-        ("chan_mean", ctypes.c_float * 3), ("chan_std", ctypes.c_float * 3),
+        ("chan_mean", ctypes.c_float * 4), ("chan_std", ctypes.c_float * 4),
+        ("channels", ctypes.c_int32),
     ]
 
     @classmethod
     def from_model(cls, c) -> "VlConfig":
+        ch = int(getattr(c, "channels", 3))
+        mean = list(c.chan_mean)[:ch] + [0.0] * (4 - ch)
+        std = list(c.chan_std)[:ch] + [1.0] * (4 - ch)
         return cls(int(c.patch), int(c.width), int(c.layers), int(c.heads), int(c.mlp),
                    int(c.proj_dim), int(c.base_grid), float(c.ln_eps),
-                   (ctypes.c_float * 3)(*c.chan_mean), (ctypes.c_float * 3)(*c.chan_std))
+                   (ctypes.c_float * 4)(*mean), (ctypes.c_float * 4)(*std), ch)
 
 
 class VlTextConfig(ctypes.Structure):
@@ -407,7 +411,7 @@ class Encoder:
 
     def encode(self, pixels: torch.Tensor, sizes: Sequence[Tuple[int, int]],
                out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-        """pixels: flat FP32 device tensor holding the [3,H,W] images back to
+        """pixels: flat FP32 device tensor holding the [C,H,W] images back to
         back; sizes: their (H, W).  Returns [n, proj_dim] unit embeddings."""
         n = len(sizes)
         if out is None:

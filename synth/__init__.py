@@ -35,7 +35,8 @@ __all__ = [
 @dataclass(frozen=True)
 class ModelConfig:
     """Dimensions of a ViT image tower (patch P, width D, L blocks, h heads,
-    MLP width F, projection width P_dim, base position grid g0 x g0)."""
+    MLP width F, projection width P_dim, base position grid g0 x g0, input
+    planes C)."""
     name: str
     patch: int
     width: int
@@ -47,9 +48,10 @@ class ModelConfig:
     ln_eps: float = 1e-5
     # Per-channel pixel statistics.  Pixels are U[0,1]; its exact mean is 1/2
     # and its exact standard deviation is 1/sqrt(12).
-    chan_mean: Tuple[float, float, float] = (0.5, 0.5, 0.5)
-    chan_std: Tuple[float, float, float] = (
+    chan_mean: Tuple[float, ...] = (0.5, 0.5, 0.5)
+    chan_std: Tuple[float, ...] = (
         0.28867513459481287, 0.28867513459481287, 0.28867513459481287)
+    channels: int = 3
 
     @property
     def head_dim(self) -> int:
@@ -67,6 +69,15 @@ MODELS: Dict[str, ModelConfig] = {
                        mlp=3072, proj_dim=512, base_grid=14),
     "l14": ModelConfig("l14", patch=14, width=1024, layers=24, heads=16,
                        mlp=4096, proj_dim=768, base_grid=24),
+    # RGB-D (4 planes) observation encoders for the navigation benchmark's
+    # 128x128 frames: a ViT-S/16-shaped tower (the policy network is not
+    # specified, so its size is a choice) and a tiny one for checks.
+    "rgbd_s16": ModelConfig("rgbd_s16", patch=16, width=384, layers=12, heads=6, mlp=1536,
+                            proj_dim=256, base_grid=8, chan_mean=(0.5,) * 4,
+                            chan_std=(0.28867513459481287,) * 4, channels=4),
+    "tiny_rgbd": ModelConfig("tiny_rgbd", patch=16, width=128, layers=2, heads=4, mlp=512,
+                             proj_dim=128, base_grid=4, chan_mean=(0.5,) * 4,
+                             chan_std=(0.28867513459481287,) * 4, channels=4),
 }
 
 
@@ -107,7 +118,7 @@ def seeds_for(workload: Workload) -> Dict[str, int]:
 # ---------------------------------------------------------------------------
 # Weight blob layout.  One FP32 array, tensors back to back, each C-contiguous,
 # in exactly this order (documented identically in include/vl.h):
-#   patch_w [D,3,P,P], patch_b [D], cls [D], pos [1+g0*g0, D],
+#   patch_w [D,C,P,P], patch_b [D], cls [D], pos [1+g0*g0, D],
 #   per block: ln1_g [D], ln1_b [D], qkv_w [3D,D], qkv_b [3D], o_w [D,D],
 #              o_b [D], ln2_g [D], ln2_b [D], fc1_w [F,D], fc1_b [F],
 #              fc2_w [D,F], fc2_b [D],
@@ -129,7 +140,7 @@ def weight_layout(c: ModelConfig) -> List[Tuple[str, Tuple[int, ...]]]:
     """(name, shape) in blob order; block tensors are named '<layer>.<name>'."""
     D, P = c.width, c.patch
     out: List[Tuple[str, Tuple[int, ...]]] = [
-        ("patch_w", (D, 3, P, P)), ("patch_b", (D,)), ("cls", (D,)),
+        ("patch_w", (D, c.channels, P, P)), ("patch_b", (D,)), ("cls", (D,)),
         ("pos", (1 + c.base_grid * c.base_grid, D))]
     bs = _block_shapes(c)
     for l in range(c.layers):
@@ -234,12 +245,14 @@ def blob_to_params(c: ModelConfig, blob: np.ndarray) -> Dict[str, object]:
 # ---------------------------------------------------------------------------
 # Images, texts, resolutions, requests.
 # ---------------------------------------------------------------------------
-def make_images(sizes: Sequence[Tuple[int, int]], seed: int) -> List[np.ndarray]:
-    """One FP32 [3,H,W] array per (H, W), pixels iid U[0,1)."""
+def make_images(sizes: Sequence[Tuple[int, int]], seed: int,
+                channels: int = 3) -> List[np.ndarray]:
+    """One FP32 [C,H,W] array per (H, W), pixels iid U[0,1) (for RGB-D the
+    depth plane is drawn the same way, as a normalised depth)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     for (h, w) in sizes:
-        a = np.empty((3, h, w), np.float32)
+        a = np.empty((channels, h, w), np.float32)
         _fill_uniform(rng, a)
         out.append(a)
     return out

@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported(V):
 
 
 def test_abi_version_and_status_strings(V):
-    assert V.vl_abi_version() == 1
+    assert V.vl_abi_version() == 2
     assert V.vl_status_string(0) == "ok"
     assert V.vl_status_string(3) == "workspace too small"
 

@@ -448,3 +448,36 @@ def test_every_gemm_config_bitwise_identical_and_autotune(V, precision):
     torch.cuda.synchronize()
     assert torch.equal(got, ref)
     enc.close()
+
+
+# ------------------------------------------------------- RGB-D observations
+def test_rgbd_tiny_fp32_ragged(V):
+    """Four input planes (RGB + depth) through the patch gather and the
+    folded normalisation, FP32, with sides that are not patch multiples."""
+    c = synth.MODELS["tiny_rgbd"]
+    imgs = synth.make_images([(128, 128), (70, 50), (16, 16), (64, 96)], 2600, channels=4)
+    w = torch.from_numpy(synth.make_blob(c, 1600)).cuda()
+    enc = V.Encoder(c, w, "fp32")
+    got = run(enc, imgs)
+    ref = O.encode(imgs, synth.make_params(c, 1600), c)
+    err = rel_err(got, ref)
+    _say(f"  tiny rgbd fp32 max rel err {err.max():.3e}")
+    assert err.max() <= FP32_TOL
+    enc.close()
+
+
+def test_rgbd_nav_bf16_sampled(V):
+    """The navigation benchmark's observation batch: 256 environments, one
+    RGB-D 128x128 frame each, ViT-S/16-shaped encoder, BF16; oracle on
+    three of the frames."""
+    c = synth.MODELS["rgbd_s16"]
+    imgs = synth.make_images([(128, 128)] * 256, 2601, channels=4)
+    w = torch.from_numpy(synth.make_blob(c, 1601)).cuda()
+    enc = V.Encoder(c, w, "bf16")
+    got = run(enc, imgs)
+    sample = [0, 100, 255]
+    ref = O.encode([imgs[i] for i in sample], O.weights_for(synth.make_params(c, 1601), "bf16"), c)
+    cos = cosine(got[sample], ref)
+    _say(f"  rgbd nav bf16 min cos {cos.min():.6f}")
+    assert cos.min() >= COS_TOL
+    enc.close()

@@ -248,10 +248,10 @@ def test_pos_interp_reproduces_linear_ramp_in_interior():
 
 
 # ------------------------------------------------------------- whole encoder
-def _tiny_setup(seed=12):
-    c = synth.MODELS["tiny"]
+def _tiny_setup(seed=12, model="tiny"):
+    c = synth.MODELS[model]
     p = synth.make_params(c, seed)
-    imgs = synth.make_images([(64, 64)] * 3, seed + 1)
+    imgs = synth.make_images([(64, 64)] * 3, seed + 1, channels=c.channels)
     return c, p, imgs
 
 
@@ -291,10 +291,13 @@ def test_embeddings_unit_norm_and_not_degenerate():
     assert off.max() < 0.99, "different images must not collapse to one embedding"
 
 
-def test_encoder_matches_torch_modules():
+@pytest.mark.parametrize("model", ["tiny", "tiny_rgbd"])
+def test_encoder_matches_torch_modules(model):
     """Whole forward against PyTorch library modules (conv patchify,
-    pre-LN TransformerEncoderLayer, layer_norm, linear), all float64."""
-    c, p, imgs = _tiny_setup(15)
+    pre-LN TransformerEncoderLayer, layer_norm, linear), all float64; RGB
+    and 4-plane RGB-D inputs."""
+    c, p, imgs = _tiny_setup(15, model)
+    assert imgs[0].shape[0] == c.channels
     f = lambda a: torch.from_numpy(np.asarray(a, np.float64))  # noqa: E731
     layers = []
     for lp in p["layers"]:
