@@ -110,7 +110,22 @@ typedef struct vl_config {
   float chan_mean[4];
   float chan_std[4];
   int32_t channels;
+  int32_t pool;      /* vl_pool                                            */
 } vl_config;
+
+/* Pooling of the final token states into one vector per image.
+ *  VL_POOL_CLS : final LayerNorm of the class token (ViT Eq. 4, CLIP).
+ *  VL_POOL_MAP : multi-head attention pooling with a learned query (the
+ *                SigLIP image tower's head; pooling by multihead attention,
+ *                Lee et al. 2019, Set Transformer, Sec. 3.2): the final
+ *                LayerNorm on every token, then one attention of the learned
+ *                probe (projected by its own Q weights) over the image's
+ *                tokens (own K/V projections, `heads` heads), the output
+ *                projection, then x + MLP(LN(x)) with GELU and width `mlp`.
+ *                The K/V projection runs as a BF16 GEMM in every precision
+ *                but VL_FP32; the rest of the head is FP32.
+ * Either is followed by the bias-free projection and L2 normalisation.    */
+typedef enum vl_pool { VL_POOL_CLS = 0, VL_POOL_MAP = 1 } vl_pool;
 
 typedef struct vl_model vl_model; /* opaque; immutable after creation */
 
@@ -120,7 +135,11 @@ typedef struct vl_model vl_model; /* opaque; immutable after creation */
  *   for each of the L blocks:
  *     ln1_g [D] ln1_b [D] qkv_w [3D,D] qkv_b [3D] o_w [D,D] o_b [D]
  *     ln2_g [D] ln2_b [D] fc1_w [F,D] fc1_b [F] fc2_w [D,F] fc2_b [D]
- *   lnf_g [D]  lnf_b [D]  proj_w [P_dim, D]
+ *   lnf_g [D]  lnf_b [D]
+ *   with VL_POOL_MAP only: probe [D]  q_w [D,D] q_b [D]  kv_w [2D,D]
+ *     kv_b [2D] (rows [K | V])  o_w [D,D] o_b [D]  ln_g [D] ln_b [D]
+ *     fc1_w [F,D] fc1_b [F]  fc2_w [D,F] fc2_b [D]
+ *   proj_w [P_dim, D]
  * Linear weights are [out, in] (y = x W^T + b).  qkv_w's rows are
  * [Q | K | V]; head k uses rows/columns k*d .. k*d+d-1 of each part.  The
  * position table's row 0 belongs to the class token; rows 1.. are the

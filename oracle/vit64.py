@@ -266,15 +266,44 @@ def act_encoding(act: str):
     raise ValueError(act)
 
 
+def map_head(x: np.ndarray, params: Dict, heads: int, eps: float) -> np.ndarray:
+    """Multi-head attention pooling with a learned query (pooling by
+    multihead attention, Lee et al. 2019, Sec. 3.2, as the SigLIP image
+    tower's head uses it): q = probe W_q^T + b_q; K, V from the tokens by
+    W_kv; per head softmax(q k^T / sqrt(d)) v; output projection; then
+    x + MLP(LN(x)) with GELU.  x: [N, D] final-LayerNormed tokens."""
+    x = np.asarray(x, F64)
+    dm = x.shape[1]
+    d = dm // heads
+    q = np.asarray(params["map_probe"], F64) @ np.asarray(params["map_q_w"], F64).T + \
+        np.asarray(params["map_q_b"], F64)
+    kv = x @ np.asarray(params["map_kv_w"], F64).T + np.asarray(params["map_kv_b"], F64)
+    k, v = kv[:, :dm], kv[:, dm:]
+    o = np.zeros(dm)
+    for h in range(heads):
+        sl = slice(h * d, (h + 1) * d)
+        o[sl] = attention_head(q[None, sl], k[:, sl], v[:, sl])[0]
+    y = o @ np.asarray(params["map_o_w"], F64).T + np.asarray(params["map_o_b"], F64)
+    z = layernorm(y, params["map_ln_g"], params["map_ln_b"], eps)
+    return y + mlp(z[None], params["map_fc1_w"], params["map_fc1_b"], params["map_fc2_w"],
+                   params["map_fc2_b"])[0]
+
+
 def encode_image(img: np.ndarray, params: Dict, cfg,
                  return_unnormalised: bool = False, act: str = "none"):
-    """Image -> unit embedding: blocks, final LN on the class token (ViT
-    Eq. 4), bias-free projection, division by the L2 norm (CLIP Sec. 2.3)."""
+    """Image -> unit embedding: blocks, then either the final LN on the class
+    token (ViT Eq. 4) or, for pool == "map", the final LN on every token and
+    the attention-pooling head; bias-free projection, division by the L2
+    norm (CLIP Sec. 2.3)."""
     aq = act_encoding(act)
     x = embed_tokens(img, params, cfg)
     for lp in params["layers"]:
         x = block(x, lp, cfg.heads, cfg.ln_eps, aq)
-    z = layernorm(x[0], params["lnf_g"], params["lnf_b"], cfg.ln_eps)
+    if getattr(cfg, "pool", "cls") == "map":
+        z = map_head(layernorm(x, params["lnf_g"], params["lnf_b"], cfg.ln_eps), params,
+                     cfg.heads, cfg.ln_eps)
+    else:
+        z = layernorm(x[0], params["lnf_g"], params["lnf_b"], cfg.ln_eps)
     e = np.asarray(params["proj_w"], F64) @ z
     eh = e / max(np.linalg.norm(e), 1e-12)
     return (eh, e) if return_unnormalised else eh
@@ -462,7 +491,9 @@ def weights_for(params: Dict, precision: str) -> Dict:
     mxfp8: those four MXFP8-rounded along their input dimension (mx_round;
     the activations are rounded too, by encode(..., act="mx")).
     Biases, LayerNorm parameters, class token, position table, patch
-    embedding and final projection stay FP32 in every variant."""
+    embedding and final projection stay FP32 in every variant; an
+    attention-pooling head's K/V projection is rounded to BF16 in every
+    variant but fp32 (its other weights stay FP32)."""
     out = {k: v for k, v in params.items() if k != "layers"}
     layers = []
     for lp in params["layers"]:
@@ -481,4 +512,6 @@ def weights_for(params: Dict, precision: str) -> Dict:
                 raise ValueError(precision)
         layers.append(nl)
     out["layers"] = layers
+    if "map_kv_w" in params and precision != "fp32":
+        out["map_kv_w"] = bf16_round(params["map_kv_w"])
     return out

@@ -88,6 +88,13 @@ struct vl_model {
   size_t wbytes = 0;
   const void* patch_w = nullptr;  // folded [D, Kpad], f32 or bf16
   const float *patch_b, *cls, *pos, *lnf_g, *lnf_b, *proj;
+  // MAP pooling head (VL_POOL_MAP): projected probe q = probe W_q^T + b_q
+  // (FP32, computed once), K/V projection [2D, D] (BF16, FP32 for VL_FP32),
+  // and the FP32 output projection, LayerNorm and MLP.
+  const float *map_q = nullptr, *map_kv_b = nullptr, *map_o_w = nullptr, *map_o_b = nullptr;
+  const float *map_ln_g = nullptr, *map_ln_b = nullptr, *map_fc1_w = nullptr, *map_fc1_b = nullptr;
+  const float *map_fc2_w = nullptr, *map_fc2_b = nullptr;
+  const void* map_kv_w = nullptr;
   std::vector<Layer> layers;
   bool use_graphs = false;
   std::mutex mu;
@@ -123,6 +130,7 @@ bool config_ok(const vl_config* c, std::string* why) {
   if (c->proj_dim > 1024) { *why = "proj_dim must be <= 1024"; return false; }
   if (!(c->ln_eps >= 0.f)) { *why = "ln_eps must be >= 0"; return false; }
   if (c->channels < 1 || c->channels > 4) { *why = "channels must be 1..4"; return false; }
+  if (c->pool != VL_POOL_CLS && c->pool != VL_POOL_MAP) { *why = "unknown pool"; return false; }
   for (int i = 0; i < c->channels; ++i)
     if (!(c->chan_std[i] > 0.f)) { *why = "chan_std must be > 0"; return false; }
   return true;
@@ -156,6 +164,8 @@ size_t weights_count(const vl_config& c) {
   size_t n = D * c.channels * P * P + D + D + (1 + g * g) * D;
   n += (size_t)c.layers * (2 * D + 3 * D * D + 3 * D + D * D + D + 2 * D + F * D + F + D * F + D);
   n += 2 * D + (size_t)c.proj_dim * D;
+  if (c.pool == VL_POOL_MAP) n += D + (D * D + D) + (2 * D * D + 2 * D) + (D * D + D) + 2 * D +
+                                  (F * D + F) + (D * F + D);
   return n;
 }
 
@@ -172,6 +182,7 @@ struct Part {
   int i0 = 0, n = 0, T = 0, max_ntok = 0, n_items = 0;
   size_t off_imgs = 0, off_items = 0;                       // in the descriptor region
   size_t off_tok = 0, off_X = 0, off_Y = 0, off_QH = 0, off_E = 0;  // in the workspace
+  size_t off_map = 0;   // MAP pooling: per image O, x, LN(x) [n, D] and MLP hidden [n, F]
 };
 
 struct Plan {
@@ -243,6 +254,10 @@ bool finish_plan(const vl_model* m, std::vector<ImgDesc>& imgs, int64_t T, Plan*
     off += align_up(es * q.T * qh_cols);
     q.off_E = off;
     off += align_up(4ull * q.n * m->Pd);
+    if (!m->text && m->cfg.pool == VL_POOL_MAP) {
+      q.off_map = off;
+      off += align_up(4ull * q.n * (3 * (size_t)m->D + m->F));
+    }
   }
   p->total = off;
   return true;
@@ -489,6 +504,38 @@ vl_status run_part(vl_model* m, const Part& p, const void* in, float* emb, char*
                                        gemm_cfg_for(m, 4, T), e4, s)));
     }
   }
+  if (!m->text && m->cfg.pool == VL_POOL_MAP) {
+    // MAP head: LN_f on every token -> K/V projection -> probe attention ->
+    // output projection -> x + MLP(LN(x)) -> projection -> L2.
+    float* mo = reinterpret_cast<float*>(ws + p.off_map);
+    float* mx1 = mo + (size_t)p.n * D;
+    float* my = mx1 + (size_t)p.n * D;
+    float* mh = my + (size_t)p.n * D;
+    float* e = reinterpret_cast<float*>(ws + p.off_E);
+    VL_TIMED(T_POOL, {
+      VL_HIP(layernorm_rows(X, m->lnf_g, m->lnf_b, eps, Y, !f32, T, D, s));
+      EpiArgs ekv;
+      ekv.bias = m->map_kv_b; ekv.out = QH; ekv.ldo = 2 * D;
+      if (f32)
+        VL_HIP(gemm_f32(static_cast<const float*>(Y), D, static_cast<const float*>(m->map_kv_w), D,
+                        T, 2 * D, D, OP_QKV, ekv, s));
+      else
+        VL_HIP(gemm_bf16(static_cast<const bf16_t*>(Y), D, m->map_kv_w, D, false, T, 2 * D, D,
+                         OP_QKV, -1, ekv, s));
+      VL_HIP(map_attention(QH, !f32, m->map_q, d_imgs, p.n, m->heads, m->hd, mo, s));
+      EpiArgs e1; e1.bias = m->map_o_b; e1.out = mx1; e1.ldo = D;
+      VL_HIP(gemm_f32(mo, D, m->map_o_w, D, p.n, D, D, OP_QKV, e1, s));
+      VL_HIP(layernorm_rows(mx1, m->map_ln_g, m->map_ln_b, eps, my, false, p.n, D, s));
+      EpiArgs e2; e2.bias = m->map_fc1_b; e2.out = mh; e2.ldo = F;
+      VL_HIP(gemm_f32(my, D, m->map_fc1_w, D, p.n, F, D, OP_FC1, e2, s));
+      EpiArgs e3; e3.bias = m->map_fc2_b; e3.out = mx1; e3.ldo = D;
+      VL_HIP(gemm_f32(mh, F, m->map_fc2_w, F, p.n, D, F, OP_FC2, e3, s));
+      EpiArgs e4; e4.out = e; e4.ldo = m->Pd;
+      VL_HIP(gemm_f32(mx1, D, m->proj, D, p.n, m->Pd, D, OP_LOGITS, e4, s));
+      VL_HIP(l2_normalise_rows(e, emb + (size_t)p.i0 * m->Pd, p.n, m->Pd, s));
+    });
+    return VL_OK;
+  }
   VL_TIMED(T_POOL, VL_HIP(pool_project(X, d_imgs, p.n, m->lnf_g, m->lnf_b, eps, m->proj, D,
                                         m->Pd, m->text, reinterpret_cast<float*>(ws + p.off_E),
                                         emb + (size_t)p.i0 * m->Pd, s)));
@@ -597,6 +644,14 @@ static vl_status build_weights(vl_model* m, const float* wdev, hipStream_t s, vl
   }
   const float* s_lnf_g = take(D);
   const float* s_lnf_b = take(D);
+  const bool map = !m->text && m->cfg.pool == VL_POOL_MAP;
+  struct SrcMap { const float *probe, *q_w, *q_b, *kv_w, *kv_b, *o_w, *o_b, *ln_g, *ln_b, *fc1_w, *fc1_b, *fc2_w, *fc2_b; } sm{};
+  if (map) {
+    sm.probe = take(D); sm.q_w = take(D * D); sm.q_b = take(D);
+    sm.kv_w = take(2 * D * D); sm.kv_b = take(2 * D); sm.o_w = take(D * D); sm.o_b = take(D);
+    sm.ln_g = take(D); sm.ln_b = take(D); sm.fc1_w = take(F * D); sm.fc1_b = take(F);
+    sm.fc2_w = take(D * F); sm.fc2_b = take(D);
+  }
   const float* s_proj = take((size_t)m->Pd * D);
 
   // Destination layout.
@@ -629,6 +684,13 @@ static vl_status build_weights(vl_model* m, const float* wdev, hipStream_t s, vl
   const size_t d_lnf_g = alloc(4 * D);
   const size_t d_lnf_b = alloc(4 * D);
   const size_t d_proj = alloc(4 * (size_t)m->Pd * D);
+  struct DstMap { size_t q, kv_w, kv_b, o_w, o_b, ln_g, ln_b, fc1_w, fc1_b, fc2_w, fc2_b; } dm{};
+  if (map) {
+    dm.q = alloc(4 * D); dm.kv_w = alloc(pes * 2 * D * D); dm.kv_b = alloc(4 * 2 * D);
+    dm.o_w = alloc(4 * D * D); dm.o_b = alloc(4 * D); dm.ln_g = alloc(4 * D); dm.ln_b = alloc(4 * D);
+    dm.fc1_w = alloc(4 * F * D); dm.fc1_b = alloc(4 * F); dm.fc2_w = alloc(4 * D * F);
+    dm.fc2_b = alloc(4 * D);
+  }
   m->wbytes = sz;
   {
     hipError_t e = hipMalloc(&m->wmem, sz);
@@ -696,6 +758,31 @@ static vl_status build_weights(vl_model* m, const float* wdev, hipStream_t s, vl
   chk(copy_f32(s_lnf_g, f(d_lnf_g), D, s), "copy");
   chk(copy_f32(s_lnf_b, f(d_lnf_b), D, s), "copy");
   chk(copy_f32(s_proj, f(d_proj), (size_t)m->Pd * D, s), "copy");
+  if (map) {
+    // q = probe W_q^T + b_q once (FP32 GEMM, one row)
+    EpiArgs eq;
+    eq.bias = sm.q_b;
+    eq.out = f(dm.q);
+    eq.ldo = (int)D;
+    chk(gemm_f32(sm.probe, (int)D, sm.q_w, (int)D, 1, (int)D, (int)D, OP_QKV, eq, s), "map query");
+    if (prec == VL_FP32)
+      chk(copy_f32(sm.kv_w, f(dm.kv_w), 2 * D * D, s), "copy");
+    else
+      chk(convert_bf16(sm.kv_w, reinterpret_cast<bf16_t*>(b + dm.kv_w), 2 * D * D, s), "convert_bf16");
+    chk(copy_f32(sm.kv_b, f(dm.kv_b), 2 * D, s), "copy");
+    chk(copy_f32(sm.o_w, f(dm.o_w), D * D, s), "copy");
+    chk(copy_f32(sm.o_b, f(dm.o_b), D, s), "copy");
+    chk(copy_f32(sm.ln_g, f(dm.ln_g), D, s), "copy");
+    chk(copy_f32(sm.ln_b, f(dm.ln_b), D, s), "copy");
+    chk(copy_f32(sm.fc1_w, f(dm.fc1_w), F * D, s), "copy");
+    chk(copy_f32(sm.fc1_b, f(dm.fc1_b), F, s), "copy");
+    chk(copy_f32(sm.fc2_w, f(dm.fc2_w), D * F, s), "copy");
+    chk(copy_f32(sm.fc2_b, f(dm.fc2_b), D, s), "copy");
+    m->map_q = f(dm.q); m->map_kv_w = b + dm.kv_w; m->map_kv_b = f(dm.kv_b);
+    m->map_o_w = f(dm.o_w); m->map_o_b = f(dm.o_b); m->map_ln_g = f(dm.ln_g); m->map_ln_b = f(dm.ln_b);
+    m->map_fc1_w = f(dm.fc1_w); m->map_fc1_b = f(dm.fc1_b); m->map_fc2_w = f(dm.fc2_w);
+    m->map_fc2_b = f(dm.fc2_b);
+  }
   if (m->text) {
     m->tok_emb = f(d_tok);
   } else {

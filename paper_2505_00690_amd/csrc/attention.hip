@@ -377,6 +377,82 @@ __global__ __launch_bounds__(ATT_Q) void k_attn_f32(const float* __restrict__ qk
         make_float4(o[d] * inv, o[d + 1] * inv, o[d + 2] * inv, o[d + 3] * inv);
 }
 
+// ------------------------------------------------ attention pooling (MAP)
+// One learned query per head over all tokens of an image: s_j = q_h . K_jh /
+// sqrt(d), p = softmax_j(s), O_h = sum_j p_j V_jh (FP32 arithmetic).  kv is
+// [T, 2D] with K in columns 0..D-1 and V in D..2D-1, BF16 or FP32.  One
+// workgroup of 256 threads per (image, head): scores in LDS, then 256/d
+// groups of d threads sum strided token subsets of p_j V_j.
+template <typename TKV>
+__global__ __launch_bounds__(256) void k_map_attn(const TKV* __restrict__ kv,
+                                                  const float* __restrict__ q,
+                                                  const ImgDesc* __restrict__ imgs, int heads,
+                                                  int hd, float* __restrict__ out) {
+  __shared__ float sp[1025];
+  __shared__ float sq[64];
+  __shared__ float red[4];
+  __shared__ float part[256];
+  const ImgDesc d = imgs[blockIdx.x];
+  const int h = blockIdx.y, tid = threadIdx.x;
+  const int N = d.ntok, D = heads * hd, ld = 2 * D;
+  auto ld_f = [](const TKV* p) {
+    if constexpr (sizeof(TKV) == 2) return bf16_bits_to_f32(*reinterpret_cast<const uint16_t*>(p));
+    else return static_cast<float>(*p);
+  };
+  if (tid < hd) sq[tid] = q[h * hd + tid];
+  __syncthreads();
+  const TKV* base = kv + (size_t)d.tok_start * ld;
+  const float sc = 1.f / sqrtf((float)hd);
+  float mx = -INFINITY;
+  for (int j = tid; j < N; j += 256) {
+    const TKV* kr = base + (size_t)j * ld + h * hd;
+    float a = 0.f;
+    for (int c = 0; c < hd; ++c) a = fmaf(sq[c], ld_f(kr + c), a);
+    sp[j] = a * sc;
+    mx = fmaxf(mx, a * sc);
+  }
+  mx = wave_max(mx);
+  if ((tid & 63) == 0) red[tid >> 6] = mx;
+  __syncthreads();
+  mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  __syncthreads();
+  float sum = 0.f;
+  for (int j = tid; j < N; j += 256) {
+    const float p = expf(sp[j] - mx);
+    sp[j] = p;
+    sum += p;
+  }
+  sum = wave_sum(sum);
+  if ((tid & 63) == 0) red[tid >> 6] = sum;
+  __syncthreads();
+  sum = (red[0] + red[1]) + (red[2] + red[3]);
+  const int G = 256 / hd, grp = tid / hd, c = tid % hd;
+  float acc = 0.f;
+  if (grp < G)
+    for (int j = grp; j < N; j += G) acc = fmaf(sp[j], ld_f(base + (size_t)j * ld + D + h * hd + c), acc);
+  part[tid] = acc;
+  __syncthreads();
+  if (tid < hd) {
+    float o = 0.f;
+    for (int g = 0; g < G; ++g) o += part[g * hd + tid];
+    out[(size_t)blockIdx.x * D + h * hd + tid] = o / sum;
+  }
+}
+
+hipError_t map_attention(const void* kv, bool kv_bf16, const float* q, const ImgDesc* imgs,
+                         int n_imgs, int heads, int head_dim, float* out, hipStream_t s) {
+  if (n_imgs <= 0) return hipSuccess;
+  if (head_dim > 64 || 256 % head_dim) return hipErrorInvalidValue;
+  dim3 grid(n_imgs, heads), block(256);
+  if (kv_bf16)
+    hipLaunchKernelGGL(k_map_attn<bf16_t>, grid, block, 0, s, static_cast<const bf16_t*>(kv), q,
+                       imgs, heads, head_dim, out);
+  else
+    hipLaunchKernelGGL(k_map_attn<float>, grid, block, 0, s, static_cast<const float*>(kv), q,
+                       imgs, heads, head_dim, out);
+  return hipGetLastError();
+}
+
 hipError_t attention_bf16(const bf16_t* qkv, bf16_t* o, const ImgDesc* imgs,
                           const AttnItem* items, int n_items, int heads, int head_dim,
                           bool causal, hipStream_t s) {

@@ -313,6 +313,12 @@ hipError_t pool_project(const float* x, const ImgDesc* imgs, int n_imgs, const f
   return hipGetLastError();
 }
 
+hipError_t l2_normalise_rows(const float* e, float* out, int rows, int P, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_l2_normalise, dim3((rows + 3) / 4), dim3(256), 0, s, e, out, rows, P);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------- score heads
 // In place over logit rows: CLIP head = softmax over the row (texts), SigLIP
 // head = sigmoid of each logit.  top1 = lowest column index of the maximum.

@@ -132,6 +132,15 @@ hipError_t pool_project(const float* x, const ImgDesc* imgs, int n_imgs, const f
                         const float* b, float eps, const float* proj, int D, int P,
                         bool pool_last, float* e_tmp, float* emb, hipStream_t s);
 
+// Row-wise division of e [rows, P] by its L2 norm (clamped at 1e-12).
+hipError_t l2_normalise_rows(const float* e, float* out, int rows, int P, hipStream_t s);
+
+// Attention pooling with one query per head (MAP head): out [n, D] FP32 from
+// the query q [D] and kv [T, 2D] (K | V; BF16 when kv_bf16, else FP32) over
+// each image's tokens.  head_dim <= 64 and divides 256.
+hipError_t map_attention(const void* kv, bool kv_bf16, const float* q, const ImgDesc* imgs,
+                         int n_imgs, int heads, int head_dim, float* out, hipStream_t s);
+
 // Token embedding of packed text sequences (descriptors: tok_start, ntok):
 // X [T, D] = tok_emb[id] + pos[index in sequence], and tok_info [T].
 hipError_t text_embed(const int32_t* ids, const ImgDesc* seqs, int n_seqs, int max_len,

@@ -35,6 +35,8 @@ OP_NAMES = ("patch_embed", "layernorm", "qkv_gemm", "attention", "oproj_gemm", "
             "fc2_gemm", "pool_proj_l2")
 PRECISIONS = {"fp32": VL_FP32, "bf16": VL_BF16, "fp8w": VL_FP8W_BF16A, "mxfp8": VL_MXFP8}
 HEADS = {"softmax": VL_HEAD_SOFTMAX, "sigmoid": VL_HEAD_SIGMOID}
+VL_POOL_CLS, VL_POOL_MAP = 0, 1
+POOLS = {"cls": VL_POOL_CLS, "map": VL_POOL_MAP}
 
 EXPORTED_SYMBOLS = (
     "vl_abi_version", "vl_status_string", "vl_last_error_message", "vl_weights_count",
@@ -65,7 +67,7 @@ class VlConfig(ctypes.Structure):
         ("heads", ctypes.c_int32), ("mlp", ctypes.c_int32), ("proj_dim", ctypes.c_int32),
         ("base_grid", ctypes.c_int32), ("ln_eps", ctypes.c_float),
         ("chan_mean", ctypes.c_float * 4), ("chan_std", ctypes.c_float * 4),
-        ("channels", ctypes.c_int32),
+        ("channels", ctypes.c_int32), ("pool", ctypes.c_int32),
     ]
 
     @classmethod
@@ -75,7 +77,8 @@ class VlConfig(ctypes.Structure):
         std = list(c.chan_std)[:ch] + [1.0] * (4 - ch)
         return cls(int(c.patch), int(c.width), int(c.layers), int(c.heads), int(c.mlp),
                    int(c.proj_dim), int(c.base_grid), float(c.ln_eps),
-                   (ctypes.c_float * 4)(*mean), (ctypes.c_float * 4)(*std), ch)
+                   (ctypes.c_float * 4)(*mean), (ctypes.c_float * 4)(*std), ch,
+                   POOLS[getattr(c, "pool", "cls")])
 
 
 class VlTextConfig(ctypes.Structure):

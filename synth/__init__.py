@@ -52,6 +52,7 @@ class ModelConfig:
     chan_std: Tuple[float, ...] = (
         0.28867513459481287, 0.28867513459481287, 0.28867513459481287)
     channels: int = 3
+    pool: str = "cls"          # "cls" (class token) or "map" (attention pooling head)
 
     @property
     def head_dim(self) -> int:
@@ -75,6 +76,11 @@ MODELS: Dict[str, ModelConfig] = {
     "rgbd_s16": ModelConfig("rgbd_s16", patch=16, width=384, layers=12, heads=6, mlp=1536,
                             proj_dim=256, base_grid=8, chan_mean=(0.5,) * 4,
                             chan_std=(0.28867513459481287,) * 4, channels=4),
+    # attention-pooling (MAP) heads, as in SigLIP image towers
+    "tiny_map": ModelConfig("tiny_map", patch=16, width=128, layers=2, heads=4, mlp=512,
+                            proj_dim=128, base_grid=4, pool="map"),
+    "b16_map": ModelConfig("b16_map", patch=16, width=768, layers=12, heads=12, mlp=3072,
+                           proj_dim=768, base_grid=14, pool="map"),
     "tiny_rgbd": ModelConfig("tiny_rgbd", patch=16, width=128, layers=2, heads=4, mlp=512,
                              proj_dim=128, base_grid=4, chan_mean=(0.5,) * 4,
                              chan_std=(0.28867513459481287,) * 4, channels=4),
@@ -145,7 +151,15 @@ def weight_layout(c: ModelConfig) -> List[Tuple[str, Tuple[int, ...]]]:
     bs = _block_shapes(c)
     for l in range(c.layers):
         out += [(f"{l}.{n}", bs[n]) for n in _BLOCK_TENSORS]
-    out += [("lnf_g", (D,)), ("lnf_b", (D,)), ("proj_w", (c.proj_dim, D))]
+    out += [("lnf_g", (D,)), ("lnf_b", (D,))]
+    if c.pool == "map":
+        F = c.mlp
+        out += [("map_probe", (D,)), ("map_q_w", (D, D)), ("map_q_b", (D,)),
+                ("map_kv_w", (2 * D, D)), ("map_kv_b", (2 * D,)), ("map_o_w", (D, D)),
+                ("map_o_b", (D,)), ("map_ln_g", (D,)), ("map_ln_b", (D,)),
+                ("map_fc1_w", (F, D)), ("map_fc1_b", (F,)), ("map_fc2_w", (D, F)),
+                ("map_fc2_b", (D,))]
+    out += [("proj_w", (c.proj_dim, D))]
     return out
 
 

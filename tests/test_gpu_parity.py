@@ -481,3 +481,42 @@ def test_rgbd_nav_bf16_sampled(V):
     _say(f"  rgbd nav bf16 min cos {cos.min():.6f}")
     assert cos.min() >= COS_TOL
     enc.close()
+
+
+# -------------------------------------------------- attention pooling (MAP)
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "mxfp8"])
+def test_map_pool_tiny(V, precision):
+    """Learned-query attention pooling instead of the class token: final LN
+    on every token, K/V projection, probe attention, output projection and
+    residual MLP; mixed image sizes."""
+    c = synth.MODELS["tiny_map"]
+    imgs = synth.make_images([(64, 64), (128, 96), (16, 16), (64, 64)], 2700)
+    w = torch.from_numpy(synth.make_blob(c, 1700)).cuda()
+    enc = V.Encoder(c, w, precision)
+    got = run(enc, imgs)
+    p = O.weights_for(synth.make_params(c, 1700), precision)
+    if precision == "fp32":
+        err = rel_err(got, O.encode(imgs, p, c))
+        _say(f"  tiny map fp32 max rel err {err.max():.3e}")
+        assert err.max() <= FP32_TOL
+    elif precision == "bf16":
+        cos = cosine(got, O.encode(imgs, p, c))
+        _say(f"  tiny map bf16 min cos {cos.min():.6f}")
+        assert cos.min() >= COS_TOL
+    else:
+        _mx_bar(got, O.encode(imgs, p, c, act="mx"), O.encode(imgs, p, c))
+    enc.close()
+
+
+def test_map_pool_b16_bf16_sampled(V):
+    c = synth.MODELS["b16_map"]
+    imgs = synth.make_images([(224, 224)] * 64, 2701)
+    w = torch.from_numpy(synth.make_blob(c, 1701)).cuda()
+    enc = V.Encoder(c, w, "bf16")
+    got = run(enc, imgs)
+    sample = [0, 63]
+    ref = O.encode([imgs[i] for i in sample], O.weights_for(synth.make_params(c, 1701), "bf16"), c)
+    cos = cosine(got[sample], ref)
+    _say(f"  b16 map bf16 min cos {cos.min():.6f}")
+    assert cos.min() >= COS_TOL
+    enc.close()

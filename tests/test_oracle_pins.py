@@ -641,3 +641,41 @@ def test_text_prefix_invariance_and_last_token_pooling():
     other[5] = (other[5] + 1) % (c.vocab - 2)
     assert not np.allclose(O.text_hidden(other, p, c)[-1], full[-1], atol=1e-6)
     assert np.allclose(O.text_hidden(other, p, c)[:5], full[:5], rtol=0, atol=1e-13)
+
+
+# ------------------------------------------------------ attention pooling (MAP)
+def test_map_head_matches_torch_multihead_attention():
+    c = synth.MODELS["tiny_map"]
+    p = synth.make_params(c, 50)
+    x = _rng(51).standard_normal((37, c.width))
+    f = lambda a: torch.from_numpy(np.asarray(a, np.float64))  # noqa: E731
+    mha = torch.nn.MultiheadAttention(c.width, c.heads, batch_first=True)
+    with torch.no_grad():
+        mha.in_proj_weight.copy_(torch.cat([f(p["map_q_w"]), f(p["map_kv_w"])]))
+        mha.in_proj_bias.copy_(torch.cat([f(p["map_q_b"]), f(p["map_kv_b"])]))
+        mha.out_proj.weight.copy_(f(p["map_o_w"]))
+        mha.out_proj.bias.copy_(f(p["map_o_b"]))
+        y, _ = mha(f(p["map_probe"])[None, None], f(x)[None], f(x)[None], need_weights=False)
+        y = y[0, 0]
+        z = torch.nn.functional.layer_norm(y, (c.width,), f(p["map_ln_g"]), f(p["map_ln_b"]),
+                                           c.ln_eps)
+        hdn = torch.nn.functional.gelu(torch.nn.functional.linear(z, f(p["map_fc1_w"]),
+                                                                  f(p["map_fc1_b"])))
+        ref = (y + torch.nn.functional.linear(hdn, f(p["map_fc2_w"]), f(p["map_fc2_b"]))).numpy()
+    assert np.max(np.abs(O.map_head(x, p, c.heads, c.ln_eps) - ref)) <= 1e-12
+
+
+def test_map_head_identical_tokens_independent_of_count():
+    # uniform attention over copies of one token: the pooled vector is that
+    # token's V whatever the number of copies
+    c = synth.MODELS["tiny_map"]
+    p = synth.make_params(c, 52)
+    t = _rng(53).standard_normal(c.width)
+    outs = [O.map_head(np.tile(t, (n, 1)), p, c.heads, c.ln_eps) for n in (1, 2, 17, 65)]
+    for o in outs[1:]:
+        assert np.allclose(o, outs[0], rtol=0, atol=1e-12)
+    # the head adds exactly its own tensors to the blob
+    import dataclasses
+    D, F = c.width, c.mlp
+    extra = D + (D * D + D) + (2 * D * D + 2 * D) + (D * D + D) + 2 * D + (F * D + F) + (D * F + D)
+    assert synth.weight_count(c) - synth.weight_count(dataclasses.replace(c, pool="cls")) == extra
