@@ -320,6 +320,26 @@ vl_status vl_score(const float* emb_dev, int32_t n_images,
                    float* scores_out_dev, int32_t* top1_out_dev,
                    void* stream);
 
+/* Contrastive loss of n matched (image, text) pairs, e.g. the embeddings of
+ * a training batch, and its gradient.  Logits l_ij = scale <e_i, t_j> + bias;
+ *  VL_HEAD_SOFTMAX (CLIP, Radford et al. 2021, Sec. 2.3): L = the mean of
+ *    the image->text and text->image cross-entropies, target = the matching
+ *    pair (bias has no effect; its gradient is 0);
+ *  VL_HEAD_SIGMOID (SigLIP, Zhai et al. 2023, Eq. 1):
+ *    L = -(1/n) sum_ij log sigmoid(z_ij l_ij), z_ij = +1 if i == j else -1.
+ * Inputs emb_dev, texts_dev [n, dim] FP32 (any vectors; not normalised
+ * here).  Outputs (device): loss_dev[1]; d_emb_dev, d_texts_dev [n, dim] =
+ * dL/de, dL/dt; d_scale_bias_dev[2] = (dL/dscale, dL/dbias).  FP32
+ * throughout, deterministic.  dim % 16 == 0, 1 <= n <= 65535, scale > 0;
+ * arrays 16-byte aligned, workspace >= vl_contrastive_workspace_bytes(n,
+ * dim) bytes, 256-byte aligned (about 8 n^2 bytes).                         */
+size_t vl_contrastive_workspace_bytes(int32_t n, int32_t dim);
+vl_status vl_contrastive_loss(const float* emb_dev, const float* texts_dev, int32_t n,
+                              int32_t dim, vl_head head, float scale, float bias,
+                              float* loss_dev, float* d_emb_dev, float* d_texts_dev,
+                              float* d_scale_bias_dev, void* workspace_dev,
+                              size_t workspace_bytes, void* stream);
+
 /* MXFP8 encoding (the one VL_MXFP8 applies to its weights and activations)
  * of FP32 rows, for callers that prepare operands themselves and for
  * checking the encoder.

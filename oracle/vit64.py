@@ -368,6 +368,46 @@ def score(emb: np.ndarray, texts: np.ndarray, head: str, scale: float,
     return p, np.argmax(l, axis=1).astype(np.int32)
 
 
+def contrastive_loss(emb: np.ndarray, texts: np.ndarray, head: str, scale: float,
+                     bias: float = 0.0) -> float:
+    """Loss of n matched pairs with logits l_ij = scale <e_i, t_j> + bias.
+    softmax (CLIP Sec. 2.3): the mean of the row-wise (image -> text) and
+    column-wise (text -> image) cross-entropies with target j = i.
+    sigmoid (SigLIP Eq. 1): -(1/n) sum_ij log sigmoid(z_ij l_ij), z_ij = 1 if
+    i == j else -1."""
+    l = logits(emb, texts, scale, bias)
+    n = l.shape[0]
+    if head == "softmax":
+        lr = np.log(softmax(l, axis=1))
+        lc = np.log(softmax(l, axis=0))
+        return float(-(np.trace(lr) + np.trace(lc)) / (2 * n))
+    if head == "sigmoid":
+        z = 2.0 * np.eye(n) - 1.0
+        return float(np.sum(np.logaddexp(0.0, -z * l)) / n)   # -log sigmoid(x) = softplus(-x)
+    raise ValueError(head)
+
+
+def contrastive_grads(emb: np.ndarray, texts: np.ndarray, head: str, scale: float,
+                      bias: float = 0.0):
+    """Analytic gradient of contrastive_loss.  G = dL/dl:
+    softmax: (P_row - I) / 2n + (P_col - I) / 2n with P_row / P_col the
+    row- / column-wise softmax of l; sigmoid: -z sigmoid(-z l) / n.  Then
+    dL/de = scale G t, dL/dt = scale G^T e, dL/dscale = sum G <e_i, t_j>,
+    dL/dbias = sum G.  Returns (de, dt, dscale, dbias)."""
+    e = np.asarray(emb, F64)
+    t = np.asarray(texts, F64)
+    l = logits(e, t, scale, bias)
+    n = l.shape[0]
+    if head == "softmax":
+        g = (softmax(l, axis=1) - np.eye(n)) / (2 * n) + (softmax(l, axis=0) - np.eye(n)) / (2 * n)
+    elif head == "sigmoid":
+        z = 2.0 * np.eye(n) - 1.0
+        g = -z * sigmoid(-z * l) / n
+    else:
+        raise ValueError(head)
+    return scale * g @ t, scale * g.T @ e, float(np.sum(g * (e @ t.T))), float(np.sum(g))
+
+
 # ---------------------------------------------------------------------------
 # Number formats of the reduced-precision variants
 # ---------------------------------------------------------------------------

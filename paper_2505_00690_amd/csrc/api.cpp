@@ -1193,6 +1193,33 @@ vl_status vl_mx_gemm(const uint8_t* a, const uint8_t* sa, const uint8_t* b, cons
   return VL_OK;
 }
 
+size_t vl_contrastive_workspace_bytes(int32_t n, int32_t dim) {
+  if (n <= 0 || dim <= 0) return 0;
+  return contrastive_workspace_bytes(n, dim);
+}
+
+vl_status vl_contrastive_loss(const float* emb, const float* texts, int32_t n, int32_t dim,
+                              vl_head head, float scale, float bias, float* loss, float* d_emb,
+                              float* d_texts, float* d_scale_bias, void* ws, size_t ws_bytes,
+                              void* stream) {
+  if (!emb || !texts || !loss || !d_emb || !d_texts || !d_scale_bias || !ws)
+    return fail(VL_ERR_INVALID_ARG, "NULL pointer argument");
+  if (n <= 0 || dim <= 0) return fail(VL_ERR_INVALID_ARG, "sizes must be > 0");
+  if (n > 65535) return fail(VL_ERR_INVALID_ARG, "n must be <= 65535");
+  if (dim % 16) return fail(VL_ERR_INVALID_ARG, "dim must be a multiple of 16");
+  if (head != VL_HEAD_SOFTMAX && head != VL_HEAD_SIGMOID) return fail(VL_ERR_INVALID_ARG, "unknown head");
+  if (!std::isfinite(scale) || !(scale > 0.f) || !std::isfinite(bias))
+    return fail(VL_ERR_INVALID_ARG, "scale must be finite and > 0, bias finite");
+  auto al = [](const void* p, uintptr_t k) { return reinterpret_cast<uintptr_t>(p) % k == 0; };
+  if (!al(emb, 16) || !al(texts, 16) || !al(d_emb, 16) || !al(d_texts, 16) || !al(ws, kAlign))
+    return fail(VL_ERR_INVALID_ARG, "arrays must be 16-byte and the workspace 256-byte aligned");
+  if (ws_bytes < contrastive_workspace_bytes(n, dim))
+    return fail(VL_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
+  VL_HIP(contrastive_loss(emb, texts, n, dim, head == VL_HEAD_SOFTMAX ? 0 : 1, scale, bias, loss,
+                          d_emb, d_texts, d_scale_bias, ws, static_cast<hipStream_t>(stream)));
+  return VL_OK;
+}
+
 vl_status vl_score(const float* emb, int32_t n_images, const float* texts, int32_t n_texts,
                    int32_t dim, vl_head head, float scale, float bias, float* scores,
                    int32_t* top1, void* stream) {

@@ -151,6 +151,14 @@ hipError_t text_embed(const int32_t* ids, const ImgDesc* seqs, int n_seqs, int m
 hipError_t score_rows(float* scores, int32_t* top1, int rows, int cols, int head,
                       hipStream_t s);
 
+// Contrastive loss of n matched pairs (head 0 softmax, 1 sigmoid) with its
+// gradients: loss[1], dE/dT [n, dim], dsb = (dL/dscale, dL/dbias).  dim %
+// 16 == 0; ws holds contrastive_workspace_bytes(n, dim).
+size_t contrastive_workspace_bytes(int n, int dim);
+hipError_t contrastive_loss(const float* E, const float* T, int n, int dim, int head,
+                            float scale, float bias, float* loss, float* dE, float* dT,
+                            float* dsb, void* ws, hipStream_t s);
+
 // Weight preparation.
 hipError_t convert_bf16(const float* src, bf16_t* dst, size_t n, hipStream_t s);
 hipError_t quantise_e4m3_rows(const float* src, uint8_t* dst, float* scales, int rows,

@@ -24,7 +24,8 @@ __all__ = [
     "vl_gemm_config_count", "vl_gemm_config_name", "vl_model_get_tuning",
     "vl_model_set_tuning", "vl_model_autotune", "GEMM_OPS", "VL_MXFP8", "vl_mx_quantize",
     "vl_mx_gemm", "VlTextConfig", "vl_text_weights_count", "vl_text_model_create",
-    "vl_text_workspace_bytes", "vl_encode_texts", "TextEncoder",
+    "vl_text_workspace_bytes", "vl_encode_texts", "TextEncoder", "VL_POOL_CLS", "VL_POOL_MAP",
+    "POOLS", "vl_contrastive_workspace_bytes", "vl_contrastive_loss",
 ]
 
 VL_FP32, VL_BF16, VL_FP8W_BF16A, VL_MXFP8 = 0, 1, 2, 3
@@ -43,7 +44,8 @@ EXPORTED_SYMBOLS = (
     "vl_model_create", "vl_model_destroy", "vl_model_set_option",
     "vl_encode_workspace_bytes", "vl_encode_images", "vl_score", "vl_model_op_times",
     "vl_mx_quantize", "vl_mx_gemm", "vl_text_weights_count", "vl_text_model_create",
-    "vl_text_workspace_bytes", "vl_encode_texts",
+    "vl_text_workspace_bytes", "vl_encode_texts", "vl_contrastive_workspace_bytes",
+    "vl_contrastive_loss",
     "vl_gemm_config_count", "vl_gemm_config_name", "vl_model_get_tuning",
     "vl_model_set_tuning", "vl_model_autotune",
 )
@@ -152,6 +154,11 @@ def lib() -> ctypes.CDLL:
     L.vl_text_workspace_bytes.argtypes = [_vp, _i32, _pi32]
     L.vl_encode_texts.restype = ctypes.c_int
     L.vl_encode_texts.argtypes = [_vp, _vp, _pi32, _i32, _vp, _vp, _sz, _vp]
+    L.vl_contrastive_workspace_bytes.restype = _sz
+    L.vl_contrastive_workspace_bytes.argtypes = [_i32, _i32]
+    L.vl_contrastive_loss.restype = ctypes.c_int
+    L.vl_contrastive_loss.argtypes = [_vp, _vp, _i32, _i32, ctypes.c_int, _f32, _f32, _vp, _vp,
+                                      _vp, _vp, _vp, _sz, _vp]
     L.vl_mx_gemm.restype = ctypes.c_int
     L.vl_mx_gemm.argtypes = [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _i32, _vp]
     L.vl_score.restype = ctypes.c_int
@@ -307,6 +314,32 @@ def vl_encode_texts(handle, ids: torch.Tensor, lengths: Sequence[int], emb_out: 
                                  len(lengths), _ptr(emb_out, torch.float32, "emb_out"),
                                  _ptr(workspace, None, "workspace"),
                                  workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def vl_contrastive_workspace_bytes(n: int, dim: int) -> int:
+    return int(lib().vl_contrastive_workspace_bytes(n, dim))
+
+
+def vl_contrastive_loss(emb: torch.Tensor, texts: torch.Tensor, head, scale: float,
+                        bias: float = 0.0, stream=None):
+    """Loss and gradients of n matched pairs; returns (loss [1], d_emb,
+    d_texts, d_scale_bias [2]) as new device tensors."""
+    h = HEADS[head] if isinstance(head, str) else int(head)
+    n, dim = emb.shape
+    if texts.shape != emb.shape:
+        raise ValueError("emb and texts must have the same shape")
+    dev = emb.device
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    de = torch.empty_like(emb)
+    dt = torch.empty_like(texts)
+    dsb = torch.empty(2, dtype=torch.float32, device=dev)
+    nb = vl_contrastive_workspace_bytes(n, dim)
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+    _check(lib().vl_contrastive_loss(_ptr(emb, torch.float32, "emb"),
+                                     _ptr(texts, torch.float32, "texts"), n, dim, h,
+                                     float(scale), float(bias), _ptr(loss), _ptr(de), _ptr(dt),
+                                     _ptr(dsb), _ptr(ws), nb, _stream(stream)))
+    return loss, de, dt, dsb
 
 
 def vl_score(emb: torch.Tensor, texts: torch.Tensor, head, scale: float, bias: float,

@@ -520,3 +520,33 @@ def test_map_pool_b16_bf16_sampled(V):
     _say(f"  b16 map bf16 min cos {cos.min():.6f}")
     assert cos.min() >= COS_TOL
     enc.close()
+
+
+# ------------------------------------------------------ contrastive losses
+@pytest.mark.parametrize("head,scale,bias", [("softmax", 100.0, 0.0), ("sigmoid", 10.0, -10.0)])
+@pytest.mark.parametrize("n,dim", [(1, 16), (37, 128), (300, 768)])
+def test_contrastive_loss_and_grads(V, head, scale, bias, n, dim):
+    """Loss, dL/de, dL/dt, dL/dscale, dL/dbias against the oracle's analytic
+    forms (FP32 bar: relative 1e-4), ragged n included (K padding of the
+    gradient GEMMs)."""
+    rng = np.random.Generator(np.random.PCG64(90 + n))
+    e = rng.standard_normal((n, dim))
+    t = rng.standard_normal((n, dim))
+    e /= np.linalg.norm(e, axis=1, keepdims=True)
+    t /= np.linalg.norm(t, axis=1, keepdims=True)
+    t[: n // 2] = 0.7 * t[: n // 2] + 0.3 * e[: n // 2]      # some matched pairs agree
+    e32, t32 = e.astype(np.float32), t.astype(np.float32)
+    loss, de, dt, dsb = V.vl_contrastive_loss(torch.from_numpy(e32).cuda(),
+                                              torch.from_numpy(t32).cuda(), head, scale, bias)
+    torch.cuda.synchronize()
+    ref_l = O.contrastive_loss(e32, t32, head, scale, bias)
+    rde, rdt, rds, rdb = O.contrastive_grads(e32, t32, head, scale, bias)
+    got_l = float(loss.cpu()[0])
+    _say(f"  {head} n={n} dim={dim}: loss {got_l:.6f} vs {ref_l:.6f}")
+    assert abs(got_l - ref_l) <= 1e-4 * max(abs(ref_l), 1e-3)
+    for got, ref in ((de, rde), (dt, rdt)):
+        g = got.cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(g - ref) <= 1e-4 * max(np.linalg.norm(ref), 1e-6)
+    ds, db = dsb.cpu().numpy().astype(np.float64)
+    assert abs(ds - rds) <= 1e-4 * max(abs(rds), 1e-4)
+    assert abs(db - rdb) <= 1e-4 * max(abs(rdb), 1e-4)

@@ -679,3 +679,58 @@ def test_map_head_identical_tokens_independent_of_count():
     D, F = c.width, c.mlp
     extra = D + (D * D + D) + (2 * D * D + 2 * D) + (D * D + D) + 2 * D + (F * D + F) + (D * F + D)
     assert synth.weight_count(c) - synth.weight_count(dataclasses.replace(c, pool="cls")) == extra
+
+
+# -------------------------------------------------------- contrastive losses
+@pytest.mark.parametrize("head", ["softmax", "sigmoid"])
+def test_contrastive_grads_vs_torch_autograd_and_finite_differences(head):
+    rng = _rng(60)
+    n, d = 9, 16
+    e = rng.standard_normal((n, d)) * 0.3
+    t = rng.standard_normal((n, d)) * 0.3
+    scale, bias = 7.0, -2.0
+    E = torch.tensor(e, requires_grad=True)
+    T = torch.tensor(t, requires_grad=True)
+    s = torch.tensor(scale, requires_grad=True)
+    b = torch.tensor(bias, requires_grad=True)
+    l = s * E @ T.T + b
+    if head == "softmax":
+        tgt = torch.arange(n)
+        loss = (torch.nn.functional.cross_entropy(l, tgt) +
+                torch.nn.functional.cross_entropy(l.T, tgt)) / 2
+    else:
+        z = 2 * torch.eye(n, dtype=torch.float64) - 1
+        loss = -torch.nn.functional.logsigmoid(z * l).sum() / n
+    loss.backward()
+    assert abs(O.contrastive_loss(e, t, head, scale, bias) - loss.item()) <= 1e-13
+    de, dt, dsc, db = O.contrastive_grads(e, t, head, scale, bias)
+    assert np.allclose(de, E.grad.numpy(), rtol=0, atol=1e-13)
+    assert np.allclose(dt, T.grad.numpy(), rtol=0, atol=1e-13)
+    assert abs(dsc - s.grad.item()) <= 1e-12 and abs(db - b.grad.item()) <= 1e-12
+    # central differences on a few coordinates, independent of both
+    h = 1e-6
+    for (i, k) in [(0, 0), (4, 7), (8, 15)]:
+        ep, em = e.copy(), e.copy()
+        ep[i, k] += h
+        em[i, k] -= h
+        fd = (O.contrastive_loss(ep, t, head, scale, bias) -
+              O.contrastive_loss(em, t, head, scale, bias)) / (2 * h)
+        assert abs(fd - de[i, k]) <= 1e-7
+
+
+def test_contrastive_special_cases():
+    rng = _rng(61)
+    e = rng.standard_normal((1, 16))
+    t = rng.standard_normal((1, 16))
+    # one pair: the softmax over a single logit is 1, so loss and gradient vanish
+    assert O.contrastive_loss(e, t, "softmax", 10.0) == 0.0
+    de, dt, dsc, _ = O.contrastive_grads(e, t, "softmax", 10.0)
+    assert not de.any() and not dt.any() and dsc == 0.0
+    # sigmoid with one pair: softplus(-(scale <e,t> + b))
+    l = 3.0 * float(e[0] @ t[0]) + 0.5
+    assert abs(O.contrastive_loss(e, t, "sigmoid", 3.0, 0.5) - math.log1p(math.exp(-l))) <= 1e-14
+    # softmax ignores the bias; sigmoid does not
+    e2, t2 = rng.standard_normal((5, 16)), rng.standard_normal((5, 16))
+    assert abs(O.contrastive_loss(e2, t2, "softmax", 4.0, 3.0) -
+               O.contrastive_loss(e2, t2, "softmax", 4.0, 0.0)) <= 1e-13
+    assert O.contrastive_grads(e2, t2, "softmax", 4.0, 3.0)[3] == pytest.approx(0.0, abs=1e-15)
