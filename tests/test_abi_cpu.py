@@ -71,3 +71,43 @@ def test_invalid_arguments_rejected_on_host(V):
     assert lib.vl_score(None, 4, p, 16, 128, 0, 1.0, 0.0, p, None, None) == 1
     assert lib.vl_encode_images(None, p, None, None, 1, p, p, 0, None) == 1
     assert lib.vl_encode_workspace_bytes(None, 1, None, None) == 0
+
+
+def test_next_row_entry_points_validate_on_host(V):
+    """Argument checks of the text tower, attention pooling, MXFP8 and
+    contrastive-loss entry points happen before anything touches a device."""
+    lib = V.lib()
+    p = ctypes.c_void_p(256)
+    h = ctypes.c_void_p()
+    # text tower
+    tc = synth.TEXT_MODELS["tiny_text"]
+    assert V.vl_text_weights_count(tc) == synth.text_weight_count(tc)
+    cfg = V.VlTextConfig.from_model(tc)
+    assert lib.vl_text_model_create(ctypes.byref(cfg), 1, p, 5, None, ctypes.byref(h)) == 1
+    bad = V.VlTextConfig.from_model(synth.TextConfig("b", 10, 2000, 128, 1, 4, 512, 128))
+    assert lib.vl_text_weights_count(ctypes.byref(bad)) == 0            # ctx > 1024
+    assert lib.vl_encode_texts(None, p, None, 1, p, p, 0, None) == 1
+    assert lib.vl_text_workspace_bytes(None, 1, None) == 0
+    # attention pooling adds exactly its tensors to the image blob
+    for name in ("tiny_map", "b16_map"):
+        assert V.vl_weights_count(synth.MODELS[name]) == synth.weight_count(synth.MODELS[name])
+    ic = V.VlConfig.from_model(synth.MODELS["tiny"])
+    ic.pool = 7
+    assert lib.vl_weights_count(ctypes.byref(ic)) == 0
+    ic = V.VlConfig.from_model(synth.MODELS["tiny"])
+    ic.channels = 5
+    assert lib.vl_weights_count(ctypes.byref(ic)) == 0
+    # MXFP8
+    assert lib.vl_mx_quantize(p, 4, 100, p, p, None) == 1               # cols % 128
+    assert lib.vl_mx_gemm(p, p, p, p, 4, 48, 128, p, p, -1, None) == 1  # N % 32
+    assert lib.vl_mx_gemm(p, p, p, p, 4, 64, 100, p, p, -1, None) == 1  # K % 128
+    assert lib.vl_mx_gemm(p, p, p, p, 4, 64, 128, p, p, 0, None) == 1   # a BF16 config id
+    # contrastive losses
+    f = lambda *a: lib.vl_contrastive_loss(*a)  # noqa: E731
+    assert f(p, p, 8, 100, 0, 10.0, 0.0, p, p, p, p, p, 1 << 30, None) == 1     # dim % 16
+    assert f(p, p, 0, 128, 0, 10.0, 0.0, p, p, p, p, p, 1 << 30, None) == 1     # n
+    assert f(p, p, 8, 128, 0, 0.0, 0.0, p, p, p, p, p, 1 << 30, None) == 1      # scale
+    assert f(p, p, 8, 128, 9, 10.0, 0.0, p, p, p, p, p, 1 << 30, None) == 1     # head
+    assert f(p, p, 8, 128, 0, 10.0, 0.0, p, p, p, p, p, 16, None) == 3          # workspace
+    assert V.vl_contrastive_workspace_bytes(8, 128) > 0
+    assert V.vl_contrastive_workspace_bytes(0, 128) == 0

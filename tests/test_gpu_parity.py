@@ -550,3 +550,17 @@ def test_contrastive_loss_and_grads(V, head, scale, bias, n, dim):
     ds, db = dsb.cpu().numpy().astype(np.float64)
     assert abs(ds - rds) <= 1e-4 * max(abs(rds), 1e-4)
     assert abs(db - rdb) <= 1e-4 * max(abs(rdb), 1e-4)
+
+
+def test_map_pool_two_part_split_bitwise(V):
+    """Attention pooling runs per part: a batch above the split threshold
+    gives the same bits as one part."""
+    c = synth.MODELS["tiny_map"]
+    sizes = [(224, 224)] * 20 + [(160, 224), (224, 96)] * 10
+    imgs = synth.make_images(sizes, 2702)
+    w = torch.from_numpy(synth.make_blob(c, 1700)).cuda()
+    one = V.Encoder(c, w, "bf16", split=False)
+    two = V.Encoder(c, w, "bf16", split=True)
+    assert np.array_equal(run(one, imgs), run(two, imgs))
+    one.close()
+    two.close()
