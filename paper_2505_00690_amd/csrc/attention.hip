@@ -58,12 +58,8 @@ typedef short s16x4 __attribute__((ext_vector_type(4)));
 // MX = false: O is BF16 [T, D].  MX = true: O is MXFP8 for the output
 // projection, codes [T, D] (out) and scales [D/128][T][4] (out_scale); a
 // 32-column block of a head lies in one lane pair (lane, lane ^ 32).
-// At least three waves per SIMD (three workgroups per CU, which the 48 KB
-// LDS ring allows): the register budget (168) then keeps the accumulators
-// in VGPRs; the compiler's unconstrained choice (212 registers, two waves)
-// was 15 % slower.
 template <int HD, bool MX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_attn_bf16(const bf16_t* __restrict__ qkv,
+__global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qkv,
                                                    void* __restrict__ out,
                                                    uint8_t* __restrict__ out_scale, int T_rows,
                                                    const ImgDesc* __restrict__ imgs,
