@@ -524,20 +524,23 @@ vl_status run_part(vl_model* m, const Part& p, const void* in, float* emb, char*
                          OP_QKV, -1, ekv, s));
       VL_HIP(map_attention(QH, !f32, m->map_q, d_imgs, p.n, m->heads, m->hd, mo, s));
       EpiArgs e1; e1.bias = m->map_o_b; e1.out = mx1; e1.ldo = D;
-      VL_HIP(gemm_f32(mo, D, m->map_o_w, D, p.n, D, D, OP_QKV, e1, s));
+      VL_HIP(gemm_f32_rows(mo, D, m->map_o_w, D, p.n, D, D, OP_QKV, e1, s));
       VL_HIP(layernorm_rows(mx1, m->map_ln_g, m->map_ln_b, eps, my, false, p.n, D, s));
       EpiArgs e2; e2.bias = m->map_fc1_b; e2.out = mh; e2.ldo = F;
-      VL_HIP(gemm_f32(my, D, m->map_fc1_w, D, p.n, F, D, OP_FC1, e2, s));
+      VL_HIP(gemm_f32_rows(my, D, m->map_fc1_w, D, p.n, F, D, OP_FC1, e2, s));
       EpiArgs e3; e3.bias = m->map_fc2_b; e3.out = mx1; e3.ldo = D;
-      VL_HIP(gemm_f32(mh, F, m->map_fc2_w, F, p.n, D, F, OP_FC2, e3, s));
+      VL_HIP(gemm_f32_rows(mh, F, m->map_fc2_w, F, p.n, D, F, OP_FC2, e3, s));
       EpiArgs e4; e4.out = e; e4.ldo = m->Pd;
-      VL_HIP(gemm_f32(mx1, D, m->proj, D, p.n, m->Pd, D, OP_LOGITS, e4, s));
+      VL_HIP(gemm_f32_rows(mx1, D, m->proj, D, p.n, m->Pd, D, OP_LOGITS, e4, s));
       VL_HIP(l2_normalise_rows(e, emb + (size_t)p.i0 * m->Pd, p.n, m->Pd, s));
     });
     return VL_OK;
   }
+  // The QKV region is free after the last block and holds the n x D pooled
+  // rows (it is at least 3 x T x D x 2 bytes and T >= n).
   VL_TIMED(T_POOL, VL_HIP(pool_project(X, d_imgs, p.n, m->lnf_g, m->lnf_b, eps, m->proj, D,
-                                        m->Pd, m->text, reinterpret_cast<float*>(ws + p.off_E),
+                                        m->Pd, m->text, static_cast<float*>(QH),
+                                        reinterpret_cast<float*>(ws + p.off_E),
                                         emb + (size_t)p.i0 * m->Pd, s)));
   return VL_OK;
 }
@@ -1238,7 +1241,7 @@ vl_status vl_score(const float* emb, int32_t n_images, const float* texts, int32
   e.ldo = n_texts;
   e.alpha = scale;
   e.beta = bias;
-  VL_HIP(gemm_f32(emb, dim, texts, dim, n_images, n_texts, dim, OP_LOGITS, e, s));
+  VL_HIP(gemm_f32_rows(emb, dim, texts, dim, n_images, n_texts, dim, OP_LOGITS, e, s));
   VL_HIP(score_rows(scores, top1, n_images, n_texts, head == VL_HEAD_SOFTMAX ? 0 : 1, s));
   return VL_OK;
 }

@@ -241,50 +241,34 @@ __device__ __forceinline__ float block_reduce(float v, float* red, Op op) {
 }
 
 // ----------------------------------------------------- pool + LN + proj + L2
-// Pooling, final LayerNorm (ViT Eq. 4) and bias-free projection, FP32.  The
-// pooled row is a sequence's first (the image class token) or, with
-// pool_last, its last (the text end-of-text token).  Grid (sequence, chunk of
-// 64 projection outputs): each workgroup normalises the pooled row in LDS
-// (cheap, D <= 1024) and produces 64 outputs, one dot product of length D per
-// output, 16 per wave.
-__global__ __launch_bounds__(256) void k_pool_project(const float* __restrict__ x,
-                                                      const ImgDesc* __restrict__ imgs,
-                                                      const float* __restrict__ gm,
-                                                      const float* __restrict__ bt, float eps,
-                                                      const float* __restrict__ proj, int D,
-                                                      int P, float* __restrict__ e_out,
-                                                      int pool_last) {
-  __shared__ float z[1024];
+// Pooling, final LayerNorm (ViT Eq. 4), bias-free projection and L2
+// normalisation, FP32.  The pooled row is a sequence's first (the image class
+// token) or, with pool_last, its last (the text end-of-text token).
+//
+// Final LayerNorm of each sequence's pooled row into z [n, D]: one workgroup
+// per sequence, FP32 statistics with the biased variance.  The projection of
+// all pooled rows is then one few-rows GEMM, which reads the projection
+// matrix once per 8 sequences.
+__global__ __launch_bounds__(256) void k_pool_ln(const float* __restrict__ x,
+                                                 const ImgDesc* __restrict__ imgs,
+                                                 const float* __restrict__ gm,
+                                                 const float* __restrict__ bt, float eps, int D,
+                                                 float* __restrict__ z, int pool_last) {
   __shared__ float red[4];
   const int tid = threadIdx.x;
-  const int img = blockIdx.x;
-  const ImgDesc d = imgs[img];
+  const ImgDesc d = imgs[blockIdx.x];
   const float* xr = x + (size_t)(d.tok_start + (pool_last ? d.ntok - 1 : 0)) * D;
+  float* zr = z + (size_t)blockIdx.x * D;
   float s = 0.f;
-  for (int c = tid; c < D; c += 256) {
-    z[c] = xr[c];
-    s += z[c];
-  }
+  for (int c = tid; c < D; c += 256) s += xr[c];
   const float mean = block_reduce(s, red, [](float a, float b) { return a + b; }) / D;
   float q = 0.f;
   for (int c = tid; c < D; c += 256) {
-    const float v = z[c] - mean;
+    const float v = xr[c] - mean;
     q += v * v;
   }
   const float rstd = rsqrtf(block_reduce(q, red, [](float a, float b) { return a + b; }) / D + eps);
-  for (int c = tid; c < D; c += 256) z[c] = (z[c] - mean) * rstd * gm[c] + bt[c];
-  __syncthreads();
-  const int lane = tid & 63, w = tid >> 6;
-  const int p0 = blockIdx.y * 64 + w * 16;
-  for (int i = 0; i < 16; ++i) {
-    const int p = p0 + i;
-    if (p >= P) break;
-    const float* wr = proj + (size_t)p * D;
-    float a = 0.f;
-    for (int c = lane; c < D; c += 64) a = fmaf(wr[c], z[c], a);
-    a = wave_sum(a);
-    if (lane == 0) e_out[(size_t)img * P + p] = a;
-  }
+  for (int c = tid; c < D; c += 256) zr[c] = (xr[c] - mean) * rstd * gm[c] + bt[c];
 }
 
 // Row-wise division by the L2 norm (clamped at 1e-12).  One wave per row.
@@ -302,11 +286,16 @@ __global__ __launch_bounds__(256) void k_l2_normalise(const float* __restrict__ 
 
 hipError_t pool_project(const float* x, const ImgDesc* imgs, int n_imgs, const float* g,
                         const float* b, float eps, const float* proj, int D, int P,
-                        bool pool_last, float* e_tmp, float* emb, hipStream_t s) {
+                        bool pool_last, float* z, float* e_tmp, float* emb, hipStream_t s) {
   if (n_imgs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pool_project, dim3(n_imgs, (P + 63) / 64), dim3(256), 0, s, x, imgs, g,
-                     b, eps, proj, D, P, e_tmp, (int)pool_last);
+  hipLaunchKernelGGL(k_pool_ln, dim3(n_imgs), dim3(256), 0, s, x, imgs, g, b, eps, D, z,
+                     (int)pool_last);
   hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  // e_tmp = z . proj^T (the projection has no bias)
+  EpiArgs ep;
+  ep.out = e_tmp; ep.ldo = P;
+  err = gemm_f32_rows(z, D, proj, D, n_imgs, P, D, OP_LOGITS, ep, s);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_l2_normalise, dim3((n_imgs + 3) / 4), dim3(256), 0, s, e_tmp, emb, n_imgs,
                      P);

@@ -203,4 +203,99 @@ hipError_t gemm_f32(const float* A, int lda, const float* B, int ldb, int M, int
   return hipGetLastError();
 }
 
+// ------------------------------------------------ FP32 GEMM with few A rows
+// The small products of the heads (logits of a few images against many
+// texts, projections of pooled rows): A has few rows and B is the large
+// operand, so 64x64 tiles leave most CUs idle.  A workgroup owns 8 rows of A
+// (staged in LDS in K chunks) and 32 columns; thread (kq, column) sums its
+// column's products with the 8 rows over the float4 chunks kq, kq + 8, kq +
+// 16, ... of K, and the 8 partial sums of an output are added in kq order.
+// Every output is computed the same way whatever M is, so a row's result does
+// not depend on the other rows of the batch.
+constexpr int FR_M = 8, FR_N = 32, FR_KQ = 8, FR_KC = 512;
+
+template <int OP>
+__global__ __launch_bounds__(256) void k_gemm_f32_rows(const float* __restrict__ A, int lda,
+                                                       const float* __restrict__ B, int ldb,
+                                                       int M, int N, int K, EpiArgs e) {
+  constexpr int EPI = OpEpi<OP>::kind;
+  __shared__ float4 sA[FR_M][FR_KC / 4];
+  __shared__ float sP[FR_KQ][FR_M][FR_N + 1];
+  const int tid = threadIdx.x;
+  const int nl = tid & (FR_N - 1), kq = tid >> 5;
+  const int m0 = blockIdx.y * FR_M, n0 = blockIdx.x * FR_N;
+  const float* brow = B + (size_t)min(n0 + nl, N - 1) * ldb;
+  float acc[FR_M];
+#pragma unroll
+  for (int r = 0; r < FR_M; ++r) acc[r] = 0.f;
+  constexpr int NB = FR_KC / 4 / FR_KQ;   // B chunks per thread and K chunk
+  for (int k0 = 0; k0 < K; k0 += FR_KC) {
+    const int nc = min(FR_KC, K - k0) / 4;   // float4 chunks in this K chunk
+    // All of this thread's B loads of the K chunk are issued first, so their
+    // latencies overlap one another and the A staging.
+    float4 b[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int c = kq + FR_KQ * i;
+      b[i] = c < nc ? *reinterpret_cast<const float4*>(brow + k0 + 4 * c)
+                    : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    __syncthreads();                          // readers of the previous chunk are done
+    for (int i = tid; i < FR_M * nc; i += 256) {
+      const int r = i / nc, c = i - r * nc;
+      sA[r][c] = *reinterpret_cast<const float4*>(A + (size_t)min(m0 + r, M - 1) * lda + k0 + 4 * c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int c = kq + FR_KQ * i;
+      if (c >= nc) break;
+#pragma unroll
+      for (int r = 0; r < FR_M; ++r) {
+        const float4 a = sA[r][c];
+        acc[r] = fmaf(a.x, b[i].x, acc[r]);
+        acc[r] = fmaf(a.y, b[i].y, acc[r]);
+        acc[r] = fmaf(a.z, b[i].z, acc[r]);
+        acc[r] = fmaf(a.w, b[i].w, acc[r]);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < FR_M; ++r) sP[kq][r][nl] = acc[r];
+  __syncthreads();
+  if (tid >= FR_M * FR_N / 4) return;
+  const int r = tid / (FR_N / 4), nq = (tid % (FR_N / 4)) * 4;
+  const int m = m0 + r, n = n0 + nq;
+  if (m >= M || n >= N) return;
+  float v[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float t = sP[0][r][nq + j];
+#pragma unroll
+    for (int q = 1; q < FR_KQ; ++q) t += sP[q][r][nq + j];
+    v[j] = t;
+  }
+  epi_store4<EPI, false>(e, m, n, v[0], v[1], v[2], v[3]);
+}
+
+hipError_t gemm_f32_rows(const float* A, int lda, const float* B, int ldb, int M, int N, int K,
+                         int op, const EpiArgs& e, hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  dim3 grid((N + FR_N - 1) / FR_N, (M + FR_M - 1) / FR_M), block(256);
+#define VL_GEMM_CASE(OP)                                                                   \
+  case OP:                                                                                 \
+    hipLaunchKernelGGL(k_gemm_f32_rows<OP>, grid, block, 0, s, A, lda, B, ldb, M, N, K, e); \
+    break;
+  switch (op) {
+    VL_GEMM_CASE(OP_QKV)
+    VL_GEMM_CASE(OP_OPROJ)
+    VL_GEMM_CASE(OP_FC1)
+    VL_GEMM_CASE(OP_FC2)
+    VL_GEMM_CASE(OP_LOGITS)
+    default: return hipErrorInvalidValue;
+  }
+#undef VL_GEMM_CASE
+  return hipGetLastError();
+}
+
 }  // namespace vl

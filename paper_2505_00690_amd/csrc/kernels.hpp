@@ -97,6 +97,12 @@ hipError_t gemm_mx(const uint8_t* A, const uint8_t* SA, const uint8_t* B, const 
 hipError_t gemm_f32(const float* A, int lda, const float* B, int ldb, int M, int N,
                     int K, int op, const EpiArgs& e, hipStream_t s);
 
+// The same contraction for products whose A has few rows (M of a batch of
+// pooled rows or images): K % 4 == 0, N % 4 == 0, lda and ldb multiples of
+// 4; not OP_PATCH.  Each output's summation order is independent of M.
+hipError_t gemm_f32_rows(const float* A, int lda, const float* B, int ldb, int M, int N,
+                         int K, int op, const EpiArgs& e, hipStream_t s);
+
 // LayerNorm of FP32 rows [M, D] -> BF16 or FP32 rows.
 hipError_t layernorm_rows(const float* x, const float* g, const float* b, float eps,
                           void* y, bool y_bf16, int M, int D, hipStream_t s);
@@ -126,11 +132,12 @@ hipError_t attention_f32(const float* qkv, float* o, const ImgDesc* imgs,
                          bool causal, hipStream_t s);
 
 // Pooling of each sequence's first (class token) or last (pool_last: the
-// text end-of-text token) row, final LayerNorm, projection [P, D] into e_tmp
-// [n, P], then L2 normalisation into emb [n, P].
+// text end-of-text token) row, final LayerNorm into z [n, D] (scratch),
+// projection [P, D] into e_tmp [n, P], then L2 normalisation into emb [n, P].
+// D % 4 == 0, P % 4 == 0.
 hipError_t pool_project(const float* x, const ImgDesc* imgs, int n_imgs, const float* g,
                         const float* b, float eps, const float* proj, int D, int P,
-                        bool pool_last, float* e_tmp, float* emb, hipStream_t s);
+                        bool pool_last, float* z, float* e_tmp, float* emb, hipStream_t s);
 
 // Row-wise division of e [rows, P] by its L2 norm (clamped at 1e-12).
 hipError_t l2_normalise_rows(const float* e, float* out, int rows, int P, hipStream_t s);
