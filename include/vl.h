@@ -274,7 +274,10 @@ vl_status vl_model_set_tuning(vl_model* m, const int32_t* table);
 /* Autotune for one batch shape: runs one full vl_encode_images of the given
  * batch (so the workspace holds live operands), then times every
  * configuration of each GEMM operation over `reps` launches with HIP events
- * on `stream`, and stores the fastest for this batch's M bucket.  Arguments
+ * on `stream`, and stores the fastest for this batch's M bucket.  When every
+ * part of the batch falls in one M bucket, the choice for each block GEMM
+ * among the configurations within 5 % of its fastest is then made by timing
+ * `reps` whole encoder passes per candidate.  Arguments
  * as for vl_encode_images; emb_out_dev receives that encode's result.
  * Blocks until the timing is done.  VL_ERR_UNSUPPORTED for VL_FP32.       */
 vl_status vl_model_autotune(vl_model* m, const float* pixels_dev, const int32_t* heights,
