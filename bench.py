@@ -69,19 +69,21 @@ def traffic_from_profile(op: str, workload: str, configs=None):
     path = os.path.join(ROOT, "profiles", f"traffic_{op}_{workload}.md")
     if not os.path.exists(path):
         return None
+    # one record per measured tile configuration; the op's configuration
+    # picks its record (without a known configuration: the last record)
     rec = None
     for line in open(path):
         line = line.strip()
         if line.startswith("{") and '"fetch_kib"' in line:
-            rec = json.loads(line)
+            r = json.loads(line)
+            if configs is None or r.get("config") in configs:
+                rec = r
     if rec is None:
         return None
     src = os.path.join(ROOT, "paper_2505_00690_amd", "csrc", rec["source"])
     if not os.path.exists(src):
         return None
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
-        return None
-    if configs is not None and rec.get("config") not in configs:
         return None
     return (rec["fetch_kib"] * rec["fetch_factor"] + rec["write_kib"] * rec["write_factor"]) * 1024.0
 
@@ -246,6 +248,9 @@ def main(argv=None) -> int:
                     help="fp32 | bf16 | fp8w | mxfp8 (default: workload's)")
     ap.add_argument("--no-graphs", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in tile heuristic")
+    ap.add_argument("--gemm-tiles", default="",
+                    help="fixed tile configurations instead of autotuning, e.g. "
+                         "fc1_gemm=DL_256x256_W4x2,qkv_gemm=DL_256x256_W4x2 (other ops: heuristic)")
     ap.add_argument("--split", action="store_true",
                     help="run the batch as two overlapping parts on two streams")
     ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the plain FP32 path")
@@ -314,7 +319,15 @@ def main(argv=None) -> int:
 
     enc = vl.Encoder(c, w, prec, graphs=not args.no_graphs, split=args.split)
     tuned = None
-    if prec != "fp32" and not args.no_autotune:
+    if prec != "fp32" and args.gemm_tiles:
+        named = {}
+        for item in args.gemm_tiles.split(","):
+            op, cfg = item.split("=")
+            named[op.strip()] = {str(b): cfg.strip() for b in range(vl.VL_N_M_BUCKETS)}
+        enc.set_tuning(named)
+        tuned = named
+        print(f"# fixed GEMM tiles: {args.gemm_tiles}", file=sys.stderr, flush=True)
+    elif prec != "fp32" and not args.no_autotune:
         tuned = enc.autotune(pix, sizes, reps=3)
         print(f"# autotuned GEMM tiles: {tuned}", file=sys.stderr, flush=True)
 

@@ -195,14 +195,18 @@ def test_two_part_split_bitwise(V):
 
 
 # --------------------------------------------------------------- scoring
-@pytest.mark.parametrize("head,scale,bias,m", [("softmax", 100.0, 0.0, 16),
-                                               ("softmax", 100.0, 0.0, 1000),
-                                               ("sigmoid", 10.0, -10.0, 4096)])
-def test_score_heads(V, head, scale, bias, m):
+# dim 784 = 512 + 272: the logit GEMM stages K in 512-wide chunks, so this
+# case has a full chunk and a ragged one; 37 images are not a multiple of
+# the 8 rows a workgroup owns.
+@pytest.mark.parametrize("head,scale,bias,m,dim", [("softmax", 100.0, 0.0, 16, 128),
+                                                   ("softmax", 100.0, 0.0, 1000, 128),
+                                                   ("sigmoid", 10.0, -10.0, 4096, 128),
+                                                   ("softmax", 100.0, 0.0, 1000, 784)])
+def test_score_heads(V, head, scale, bias, m, dim):
     rng = np.random.Generator(np.random.PCG64(7))
-    e = rng.standard_normal((37, 128))
+    e = rng.standard_normal((37, dim))
     e = (e / np.linalg.norm(e, axis=1, keepdims=True)).astype(np.float32)
-    t = synth.make_texts(m, 128, 3000)
+    t = synth.make_texts(m, dim, 3000)
     t[5] = e[3]                       # an exact match: logit = scale
     ed, td = torch.from_numpy(e).cuda(), torch.from_numpy(t).cuda()
     sc = torch.empty((37, m), dtype=torch.float32, device="cuda")
