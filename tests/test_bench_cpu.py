@@ -1,0 +1,62 @@
+"""Host logic of bench.py: the single-GPU guard, the algorithmic FLOP model
+and how a committed counter summary is matched to the kernel it describes."""
+import hashlib
+import json
+import os
+
+import bench
+import synth
+
+
+def test_more_than_one_gpu_is_refused(capsys):
+    assert bench.main(["--gpus", "2"]) == 2
+    assert "one GPU" in capsys.readouterr().err
+
+
+def test_flop_model_matches_the_layer_shapes():
+    c = synth.MODELS["l14"]
+    sizes = [(336, 336)] * 32
+    T = 32 * (1 + (336 // 14) ** 2)
+    D, F = c.width, c.mlp
+    assert bench.op_flops(c, sizes, "fc1_gemm") == 2.0 * T * D * F
+    assert bench.op_flops(c, sizes, "qkv_gemm") == 2.0 * T * D * 3 * D
+    assert bench.op_flops(c, sizes, "attention") == 32 * 4.0 * 577 ** 2 * D
+    per_image = bench.flops_per_image(c, 336)
+    layer_ops = sum(bench.op_flops(c, sizes, op) for op in
+                    ("qkv_gemm", "oproj_gemm", "fc1_gemm", "fc2_gemm", "attention"))
+    # the per-image model adds the patch embedding and the projection
+    extra = 32 * (2.0 * 576 * 3 * 14 ** 2 * D + 2.0 * D * c.proj_dim)
+    assert abs(32 * per_image - (c.layers * layer_ops + extra)) <= 1e-9 * 32 * per_image
+
+
+def _profile(root, source_text, records):
+    os.makedirs(os.path.join(root, "profiles"))
+    os.makedirs(os.path.join(root, "paper_2505_00690_amd", "csrc"))
+    with open(os.path.join(root, "paper_2505_00690_amd", "csrc", "k.hpp"), "w") as f:
+        f.write(source_text)
+    sha = hashlib.sha256(b"kernel v1").hexdigest()
+    lines = ["# summary", ""]
+    for cfg, fetch, write in records:
+        lines.append(json.dumps({"fetch_kib": fetch, "write_kib": write, "fetch_factor": 2.0,
+                                 "write_factor": 1.0, "config": cfg, "source": "k.hpp",
+                                 "source_sha256": sha}))
+        lines.append("")
+    with open(os.path.join(root, "profiles", "traffic_fc1_gemm_w.md"), "w") as f:
+        f.write("\n".join(lines))
+
+
+def test_traffic_record_follows_the_tile_configuration(tmp_path, monkeypatch):
+    _profile(str(tmp_path), "kernel v1", [("A", 100.0, 10.0), ("B", 200.0, 20.0)])
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    f = bench.traffic_from_profile
+    assert f("fc1_gemm", "w", {"A"}) == (100.0 * 2 + 10.0) * 1024
+    assert f("fc1_gemm", "w", {"B"}) == (200.0 * 2 + 20.0) * 1024
+    assert f("fc1_gemm", "w", {"C"}) is None          # configuration never measured
+    assert f("fc1_gemm", "w") == (200.0 * 2 + 20.0) * 1024
+    assert f("fc2_gemm", "w") is None                 # no summary for the op
+
+
+def test_traffic_record_dropped_once_the_kernel_source_changes(tmp_path, monkeypatch):
+    _profile(str(tmp_path), "kernel v2", [("A", 100.0, 10.0)])
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.traffic_from_profile("fc1_gemm", "w", {"A"}) is None
