@@ -58,6 +58,16 @@ typedef short s16x4 __attribute__((ext_vector_type(4)));
 // MX = false: O is BF16 [T, D].  MX = true: O is MXFP8 for the output
 // projection, codes [T, D] (out) and scales [D/128][T][4] (out_scale); a
 // 32-column block of a head lies in one lane pair (lane, lane ^ 32).
+// Work items are dealt XCD by XCD: workgroup ids go round-robin to the 8
+// XCDs, so each XCD is given a contiguous range of (head, query block)
+// items, in which the query blocks of one (image, head) are consecutive and
+// share that image's key and value rows in the XCD's L2.
+__device__ __forceinline__ int xcd_linear(int bid, int total) {
+  const int xcd = bid & 7, local = bid >> 3;
+  const int q = total >> 3, r = total & 7;
+  return xcd * q + min(xcd, r) + local;
+}
+
 template <int HD, bool MX>
 __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qkv,
                                                    void* __restrict__ out,
@@ -73,8 +83,10 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
   __shared__ __attribute__((aligned(1024))) char sK[ATT_ST][T::BYTES];
   __shared__ __attribute__((aligned(1024))) char sV[ATT_ST][T::BYTES];
 
-  const AttnItem it = items[blockIdx.x];
-  const int h = blockIdx.y;
+  const int n_items = gridDim.x / heads;
+  const int wi = xcd_linear(blockIdx.x, gridDim.x);
+  const AttnItem it = items[wi % n_items];
+  const int h = wi / n_items;
   const ImgDesc dsc = imgs[it.img];
   const int N = dsc.ntok;
   const int D = heads * HD;
@@ -457,7 +469,7 @@ hipError_t attention_bf16(const bf16_t* qkv, bf16_t* o, const ImgDesc* imgs,
                           const AttnItem* items, int n_items, int heads, int head_dim,
                           bool causal, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  dim3 grid(n_items, heads), block(256);
+  dim3 grid(n_items * heads), block(256);
   if (head_dim == 64)
     hipLaunchKernelGGL((k_attn_bf16<64, false>), grid, block, 0, s, qkv, o, nullptr, 0, imgs,
                        items, heads, (int)causal);
@@ -473,7 +485,7 @@ hipError_t attention_bf16_mx(const bf16_t* qkv, uint8_t* codes, uint8_t* scales,
                              const ImgDesc* imgs, const AttnItem* items, int n_items,
                              int heads, int head_dim, bool causal, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  dim3 grid(n_items, heads), block(256);
+  dim3 grid(n_items * heads), block(256);
   if (head_dim == 64)
     hipLaunchKernelGGL((k_attn_bf16<64, true>), grid, block, 0, s, qkv, codes, scales, T, imgs,
                        items, heads, (int)causal);
