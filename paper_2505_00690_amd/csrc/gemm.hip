@@ -223,7 +223,8 @@ __global__ __launch_bounds__(256) void k_gemm_f32_rows(const float* __restrict__
   __shared__ float sP[FR_KQ][FR_M][FR_N + 1];
   const int tid = threadIdx.x;
   const int nl = tid & (FR_N - 1), kq = tid >> 5;
-  const int m0 = blockIdx.y * FR_M, n0 = blockIdx.x * FR_N;
+  const int nbn = (N + FR_N - 1) / FR_N;      // one-dimensional grid: no limit on M
+  const int m0 = (int)(blockIdx.x / nbn) * FR_M, n0 = (int)(blockIdx.x % nbn) * FR_N;
   const float* brow = B + (size_t)min(n0 + nl, N - 1) * ldb;
   float acc[FR_M];
 #pragma unroll
@@ -281,7 +282,9 @@ __global__ __launch_bounds__(256) void k_gemm_f32_rows(const float* __restrict__
 hipError_t gemm_f32_rows(const float* A, int lda, const float* B, int ldb, int M, int N, int K,
                          int op, const EpiArgs& e, hipStream_t s) {
   if (M <= 0) return hipSuccess;
-  dim3 grid((N + FR_N - 1) / FR_N, (M + FR_M - 1) / FR_M), block(256);
+  const int64_t blocks = (int64_t)((N + FR_N - 1) / FR_N) * ((M + FR_M - 1) / FR_M);
+  if (blocks > INT32_MAX) return hipErrorInvalidValue;
+  dim3 grid((unsigned)blocks), block(256);
 #define VL_GEMM_CASE(OP)                                                                   \
   case OP:                                                                                 \
     hipLaunchKernelGGL(k_gemm_f32_rows<OP>, grid, block, 0, s, A, lda, B, ldb, M, N, K, e); \
