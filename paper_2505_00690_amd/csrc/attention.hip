@@ -181,6 +181,10 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
     // Stage (st+2)%3 held tile kt-1, whose readers all passed the barrier.
     if (kt + 2 < KT) issue(kt + 2, (st + 2) % ATT_ST);
     if (!wave_active) return;
+    // With the causal mask a tile whose first key follows every query of the
+    // wave contributes nothing (all its probabilities are 0); the wave only
+    // keeps the ring moving for the other waves.
+    if (causal && kt * ATT_KV > qw + 31) return;
     const char* tK = sK[st];
     // S^T blocks: s[kb][r] = S[key 32kb + 8(r/4) + 4g + r%4][query].
     f32x16 s[2];
