@@ -199,17 +199,26 @@ __global__ __launch_bounds__(256) void k_im2col(const float* __restrict__ pix,
     q = (tok - 1) - r * d.gw;
   }
   const float* src = pix + d.pix_off;
+  // (c, a, b) of this lane's k, advanced by 64 per step with carries
+  // instead of two integer divisions per element.
+  int c = lane / pp, a = lane - c * pp;
+  int b = a % patch;
+  a /= patch;
+  const int dc = 64 / pp, drem = 64 - dc * pp;
+  const int da = drem / patch, db = drem - da * patch;
   for (int k = lane; k < kpad; k += 64) {
     float v = 0.f;
-    if (tok > 0 && k < kreal) {
-      const int c = k / pp, rem = k - c * pp;
-      const int a = rem / patch, b = rem - a * patch;
+    if (tok > 0 && k < kreal)
       v = src[(size_t)c * d.H * d.W + (size_t)(r * patch + a) * d.W + q * patch + b];
-    }
     if (OUT_BF16)
       static_cast<bf16_t*>(out)[(size_t)t * kpad + k] = (bf16_t)f32_to_bf16_bits(v);
     else
       static_cast<float*>(out)[(size_t)t * kpad + k] = v;
+    b += db;
+    a += da;
+    c += dc;
+    if (b >= patch) { b -= patch; ++a; }
+    if (a >= patch) { a -= patch; ++c; }
   }
 }
 
