@@ -267,7 +267,9 @@ def main(argv=None) -> int:
     ap.add_argument("--serve-requests", type=int, default=1200)
     ap.add_argument("--serve-slots", type=int, default=2)
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
-    ap.add_argument("--serve-max-batch", type=int, default=64)
+    ap.add_argument("--serve-max-batch", type=int, default=32,
+                    help="images per serving batch at most (32: same capacity as 64, "
+                         "shorter tail latency)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:

@@ -135,7 +135,7 @@ class Scheduler:
     run at once."""
 
     def __init__(self, executor: Executor, budget_bytes: int, slots: int = 2,
-                 max_batch_images: int = 64):
+                 max_batch_images: int = 32):
         if slots < 1 or budget_bytes <= 0 or max_batch_images < 1:
             raise ValueError("slots, budget and batch limit must be positive")
         self.ex = executor
