@@ -113,7 +113,7 @@ def cpu_baseline(wl: synth.Workload, blob: np.ndarray, images, texts, n_sample: 
                       f"{wl.head} scoring vs {len(texts)} texts; {dt:.1f} s"}
 
 
-def text_leg(torch, vl, n_texts: int, steps: int, seed: int = 3002):
+def text_leg(torch, vl, n_texts: int, steps: int, seed: int = 3002, split: bool = True):
     """The text tower: CLIP ViT-L/14-shaped (width 768, 12 causal blocks,
     context 77), BF16, HIP graphs; n_texts prompt-length token sequences
     (U{5..20} tokens, one in ten at 77) encoded in one call, as the texts the
@@ -123,6 +123,8 @@ def text_leg(torch, vl, n_texts: int, steps: int, seed: int = 3002):
     lens = synth.draw_text_lengths(n_texts, c.ctx, seed + 1)
     ids = torch.from_numpy(np.concatenate(synth.make_token_ids(lens, c.vocab, seed + 2))).cuda()
     enc = vl.TextEncoder(c, w, "bf16", graphs=True)
+    if split:
+        vl.vl_model_set_option(enc.handle, vl.VL_OPT_SPLIT, 1)
     del w
     out = torch.empty((n_texts, c.proj_dim), dtype=torch.float32, device="cuda")
     for _ in range(2):
@@ -142,10 +144,11 @@ def text_leg(torch, vl, n_texts: int, steps: int, seed: int = 3002):
     enc.close()
     return {"value": n_texts / (ms / 1e3), "unit": "texts/s", "ms_per_call": ms,
             "texts": n_texts, "tokens": T, "model": c.name, "precision": "bf16",
-            "tflops": flops / (ms / 1e3) / 1e12, "steps": steps}
+            "tflops": flops / (ms / 1e3) / 1e12, "steps": steps, "two_part_split": split}
 
 
-def rgbd_leg(torch, vl, steps: int, n_env: int = 256, w_seed: int = 1006, i_seed: int = 2006):
+def rgbd_leg(torch, vl, steps: int, n_env: int = 256, w_seed: int = 1006, i_seed: int = 2006,
+             split: bool = True):
     """The navigation benchmark's observation batch: one RGB-D 128x128 frame
     (4 planes) per environment for 256 environments on one GPU, encoded by
     a ViT-S/16-shaped tower in BF16 with HIP graphs (the policy network
@@ -155,7 +158,7 @@ def rgbd_leg(torch, vl, steps: int, n_env: int = 256, w_seed: int = 1006, i_seed
     imgs = synth.make_images([(128, 128)] * n_env, i_seed, channels=c.channels)
     pix = torch.from_numpy(np.concatenate([im.reshape(-1) for im in imgs])).cuda()
     sizes = [(128, 128)] * n_env
-    enc = vl.Encoder(c, w, "bf16", graphs=True)
+    enc = vl.Encoder(c, w, "bf16", graphs=True, split=split)
     del w
     out = torch.empty((n_env, c.proj_dim), dtype=torch.float32, device="cuda")
     for _ in range(2):
@@ -173,7 +176,7 @@ def rgbd_leg(torch, vl, steps: int, n_env: int = 256, w_seed: int = 1006, i_seed
     enc.close()
     return {"value": n_env / (ms / 1e3), "unit": "observations/s", "ms_per_batch": ms,
             "environments": n_env, "frame": "4x128x128", "model": c.name, "precision": "bf16",
-            "tflops": flops / (ms / 1e3) / 1e12, "steps": steps}
+            "tflops": flops / (ms / 1e3) / 1e12, "steps": steps, "two_part_split": split}
 
 
 def serving_leg(torch, vl, n_requests: int, warmup_requests: int, slots: int,
@@ -440,11 +443,13 @@ def main(argv=None) -> int:
         del enc32
 
     if not args.no_text:
-        result["text_tower"] = text_leg(torch, vl, wl.n_texts, args.text_steps)
+        result["text_tower"] = text_leg(torch, vl, wl.n_texts, args.text_steps,
+                                        split=not args.no_split)
         print(f"# text tower: {json.dumps(result['text_tower'])}", file=sys.stderr, flush=True)
 
     if not args.no_rgbd:
-        result["rgbd_observations"] = rgbd_leg(torch, vl, args.text_steps)
+        result["rgbd_observations"] = rgbd_leg(torch, vl, args.text_steps,
+                                               split=not args.no_split)
         print(f"# rgbd: {json.dumps(result['rgbd_observations'])}", file=sys.stderr, flush=True)
 
     if not args.no_serve:
