@@ -89,7 +89,7 @@ def traffic_from_profile(op: str, workload: str, configs=None):
 
 
 def cpu_baseline(wl: synth.Workload, blob: np.ndarray, images, texts, n_sample: int,
-                 precision: str = None):
+                 precision: str = None, one_thread: bool = True):
     """The FP64 oracle as it stands, on the host cores, over a bounded
     sample of the same workload: encode + score of n_sample images."""
     from oracle import vit64 as O
@@ -107,10 +107,64 @@ def cpu_baseline(wl: synth.Workload, blob: np.ndarray, images, texts, n_sample: 
     emb = O.encode(sample, params, c, act="mx" if precision == "mxfp8" else "none")
     O.score(emb, texts, wl.head, wl.scale, wl.bias)
     dt = time.perf_counter() - t0
-    return {"value": n_sample / dt, "unit": "images/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{n_sample} of {len(images)} images of the workload "
-                      f"({wl.model}, {images[0].shape[1]}x{images[0].shape[2]}), FP64 encode + "
-                      f"{wl.head} scoring vs {len(texts)} texts; {dt:.1f} s"}
+    out = {"value": n_sample / dt, "unit": "images/s", "cores": int(threads), "kind": "oracle",
+           "cpu": _cpu_model(),
+           "sample": f"{n_sample} of {len(images)} images of the workload "
+                     f"({wl.model}, {images[0].shape[1]}x{images[0].shape[2]}), FP64 encode + "
+                     f"{wl.head} scoring vs {len(texts)} texts; {dt:.1f} s"}
+    if one_thread:
+        # the same oracle on one BLAS thread, one image
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1):
+                t0 = time.perf_counter()
+                O.encode(sample[:1], params, c, act="mx" if precision == "mxfp8" else "none")
+                dt1 = time.perf_counter() - t0
+            out["value_1thread"] = 1.0 / dt1
+            out["sample_1thread"] = f"1 image on 1 BLAS thread; {dt1:.1f} s"
+        except ImportError:  # pragma: no cover
+            pass
+    return out, emb
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_error(got: np.ndarray, ref: np.ndarray, precision: str) -> dict:
+    """Error of GPU embeddings against the FP64 oracle's on the same images:
+    per-image relative error ||e - e_ref|| / ||e_ref|| and cosine."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    rel = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    cos = (got * ref).sum(1) / np.linalg.norm(got, axis=1) / np.linalg.norm(ref, axis=1)
+    bar = "rel err <= 1e-4" if precision == "fp32" else "cos >= 0.999"
+    return {"precision": precision, "images": int(len(ref)), "max_rel_err": float(rel.max()),
+            "min_cos": float(cos.min()), "bar": bar}
+
+
+def top1_agreement(top_a: np.ndarray, top_ref: np.ndarray, emb_a: np.ndarray,
+                   emb_ref: np.ndarray, texts: np.ndarray, scale: float, slack: float) -> dict:
+    """Top-1 agreement of a reduced-precision path with the FP32 path: raw,
+    and over the images whose FP32 top-1/top-2 logit gap exceeds 2 * scale *
+    (||e_a - e_ref|| + slack), where no embedding error of that size can
+    change the choice (slack: the FP32 path's own bound against the oracle)."""
+    l = scale * (np.asarray(emb_ref, np.float64) @ np.asarray(texts, np.float64).T)
+    srt = np.sort(l, axis=1)
+    gap = srt[:, -1] - srt[:, -2]
+    d = np.linalg.norm(np.asarray(emb_a, np.float64) - np.asarray(emb_ref, np.float64), axis=1)
+    cert = gap > 2.0 * scale * (d + slack)
+    agree = np.asarray(top_a) == np.asarray(top_ref)
+    return {"images": int(len(agree)), "raw": float(agree.mean()),
+            "certified_images": int(cert.sum()),
+            "certified_agree": float(agree[cert].mean()) if cert.any() else None,
+            "vs": "fp32 GPU path"}
 
 
 def text_leg(torch, vl, n_texts: int, steps: int, seed: int = 3002, split: bool = True):
@@ -260,6 +314,8 @@ def main(argv=None) -> int:
     ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the plain FP32 path")
     ap.add_argument("--cpu-sample", type=int, default=None, help="images for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-1thread", action="store_true",
+                    help="skip the one-thread oracle figure (one image)")
     ap.add_argument("--timing-steps", type=int, default=3)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving (p50/p99) leg")
     ap.add_argument("--no-text", action="store_true", help="skip the text-tower leg")
@@ -353,6 +409,8 @@ def main(argv=None) -> int:
     for _ in range(args.warmup):
         step(enc)
     torch.cuda.synchronize()
+    emb_main = emb.cpu().numpy()
+    top_main = top1.cpu().numpy()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
@@ -440,6 +498,9 @@ def main(argv=None) -> int:
         result["fp32_path"] = {"value": n / (ms32 / 1e3), "unit": "images/s",
                                "ms_per_step": ms32, "steps": args.fp32_steps,
                                "speedup_of_value": ms32 / ms}
+        emb32 = emb.cpu().numpy()
+        result["top1_agreement"] = top1_agreement(top_main, top1.cpu().numpy(), emb_main,
+                                                  emb32, texts, wl.scale, 1e-4)
         del enc32
 
     if not args.no_text:
@@ -460,7 +521,17 @@ def main(argv=None) -> int:
     if not args.no_cpu_baseline:
         k = args.cpu_sample or {"tiny_fp32": 8, "b16_224": 8, "l14_336": 4, "b16_mixed": 6}[
             args.workload]
-        result["cpu_baseline"] = cpu_baseline(wl, blob, images, texts, k, prec)
+        result["cpu_baseline"], ref = cpu_baseline(wl, blob, images, texts, k, prec,
+                                                   one_thread=not args.no_cpu_1thread)
+        # error against the FP64 oracle beside the throughput, on the same
+        # sample: the timed path, and the plain FP32 path on two images
+        errs = [oracle_error(emb_main[:k], ref, prec)]
+        if prec != "fp32" and "fp32_path" in result:
+            from oracle import vit64 as O
+            p32 = O.weights_for(synth.blob_to_params(c, blob), "fp32")
+            ref32 = O.encode(images[:2], p32, c)
+            errs.append(oracle_error(emb32[:2], ref32, "fp32"))
+        result["oracle_err"] = errs
     print(json.dumps(result), flush=True)
     return 0
 

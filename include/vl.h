@@ -157,8 +157,11 @@ vl_status vl_model_create(const vl_config* cfg, vl_precision prec,
                           const float* weights_dev, size_t n_floats,
                           void* stream, vl_model** out);
 
-/* Frees the model's device memory and cached graphs.  Synchronises the
- * device first, so in-flight work that reads the model finishes. NULL ok. */
+/* Frees the model's device memory and cached graphs.  First waits for the
+ * model's own enqueued work to finish: every call records an event on the
+ * stream it ran on (and creation on its stream), and destroy waits for the
+ * latest event of each such stream and for the model's internal stream; it
+ * does not synchronise the device.  NULL ok.                              */
 void vl_model_destroy(vl_model* m);
 
 /* ---- Text tower ---------------------------------------------------------
@@ -215,9 +218,14 @@ vl_status vl_encode_texts(vl_model* m, const int32_t* ids_dev, const int32_t* le
                           int32_t n_texts, float* emb_out_dev, void* workspace_dev,
                           size_t workspace_bytes, void* stream);
 
-/* Options (all off by default).
+/* Options (all off by default).  Setting an option waits only for the
+ * cached graphs it drops (each graph's last replay); it does not synchronise
+ * the device.
  *   VL_OPT_GRAPHS : 1 = capture each distinct call (shapes, pointers,
  *                   stream) into a HIP graph on first use and replay it.
+ *                   At most 64 graphs are kept per model; the least
+ *                   recently replayed one is dropped (after its last replay
+ *                   finishes) to make room.
  *   VL_OPT_TIMING : 1 = bracket every kernel launch of vl_encode_images
  *                   with HIP events on the stream it runs on and accumulate
  *                   per-operation device time (read with
@@ -271,6 +279,18 @@ const char* vl_gemm_config_name(int32_t cfg);
 vl_status vl_model_get_tuning(const vl_model* m, int32_t* table);
 vl_status vl_model_set_tuning(vl_model* m, const int32_t* table);
 
+/* Persist the tuning table as JSON (path: a file the call writes / reads):
+ *   {"abi": 2, "arch": "gfx950", "precision": "bf16", "text": false,
+ *    "width": D, "mlp": F, "patch_k": padded patch length,
+ *    "table": {"qkv_gemm": {"<M bucket>": "<configuration name>", ...}, ...}}
+ * Only tuned entries are written.  load validates the file against the
+ * model (ABI, device architecture, precision, image or text model, GEMM
+ * dimensions) and every name, then applies it as vl_model_set_tuning does;
+ * on any mismatch it returns VL_ERR_INVALID_ARG and leaves the table as it
+ * was.  Host-only calls (no device work).                                  */
+vl_status vl_model_save_tuning(const vl_model* m, const char* path);
+vl_status vl_model_load_tuning(vl_model* m, const char* path);
+
 /* Autotune for one batch shape: runs one full vl_encode_images of the given
  * batch (so the workspace holds live operands), then times every
  * configuration of each GEMM operation over `reps` launches with HIP events
@@ -316,12 +336,41 @@ vl_status vl_encode_images(vl_model* m, const float* pixels_dev,
  *                   or sigmoids of the logits.
  *  top1_out_dev   : [n_images] lowest index attaining the maximum logit, or
  *                   NULL.
- * dim % 4 == 0.  No workspace.                                             */
+ * dim % 4 == 0 and n_texts % 4 == 0 (scores rows are stored 16 bytes at a
+ * time); emb, texts and scores 16-byte aligned.  No workspace.             */
 vl_status vl_score(const float* emb_dev, int32_t n_images,
                    const float* texts_dev, int32_t n_texts, int32_t dim,
                    vl_head head, float scale, float bias,
                    float* scores_out_dev, int32_t* top1_out_dev,
                    void* stream);
+
+/* Multi-head scaled dot-product attention (Vaswani et al. 2017, Sec. 3.2.1
+ * Eq. 1 and Sec. 3.2.2) over packed variable-length sequences: the
+ * attention step of vl_encode_images (causal = 0) and vl_encode_texts
+ * (causal = 1), exposed on its own with the same kernels.
+ *  qkv_dev : [T, 3 * heads * head_dim] token rows [Q | K | V], head k using
+ *            columns k*head_dim .. (k+1)*head_dim-1 of each part; BF16 when
+ *            prec is VL_BF16, FP32 when VL_FP32; 16-byte aligned.
+ *            T = sum of lengths; sequence i occupies the lengths[i] rows
+ *            after sequence i-1.
+ *  lengths : host array of n_seqs lengths, each 1..4096; 1 <= n_seqs <= 65535.
+ *  heads   : 1..64; head_dim: 32 or 64 (else VL_ERR_UNSUPPORTED).
+ *  causal  : 0: every token attends to every token of its sequence;
+ *            1: token i attends to tokens 0..i of its sequence.
+ *  out_dev : [T, heads * head_dim], element type as qkv, 16-byte aligned:
+ *            softmax(q k^T / sqrt(head_dim)) v per head, never across
+ *            sequences.
+ *  workspace_dev : >= vl_attention_workspace_bytes(n_seqs, lengths) bytes,
+ *            256-byte aligned (per-sequence descriptors and work items).
+ * Softmax maximum and sum are FP32; the BF16 kernel multiplies BF16 Q, K,
+ * V and rounds the probabilities to BF16 before the product with V, with
+ * FP32 accumulation.  Asynchronous on `stream`; the descriptors are copied
+ * from a pinned host buffer the library owns.                              */
+size_t vl_attention_workspace_bytes(int32_t n_seqs, const int32_t* lengths);
+vl_status vl_attention(const void* qkv_dev, vl_precision prec, const int32_t* lengths,
+                       int32_t n_seqs, int32_t heads, int32_t head_dim, int32_t causal,
+                       void* out_dev, void* workspace_dev, size_t workspace_bytes,
+                       void* stream);
 
 /* Contrastive loss of n matched (image, text) pairs, e.g. the embeddings of
  * a training batch, and its gradient.  Logits l_ij = scale <e_i, t_j> + bias;

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cctype>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -64,8 +66,12 @@ struct Staging {
 
 struct GraphEntry {
   hipGraphExec_t exec = nullptr;
-  void* host = nullptr;  // pinned descriptors captured by the graph's copy node
+  void* host = nullptr;       // pinned descriptors captured by the graph's copy node
+  hipEvent_t done = nullptr;  // recorded after each replay: the graph is idle once it fires
+  uint64_t last_use = 0;      // replay clock, for least-recently-used eviction
 };
+
+constexpr size_t kMaxGraphs = 64;  // cached graphs per model
 
 struct TimedLaunch {
   int op;
@@ -101,6 +107,11 @@ struct vl_model {
   std::vector<Staging> ring;
   size_t ring_pos = 0;
   std::unordered_map<std::string, GraphEntry> graphs;
+  uint64_t graph_clock = 0;
+  // One event per stream the model has been used on, recorded at the end of
+  // every call on it: waiting for all of them waits for all of the model's
+  // enqueued work, without synchronising the device.
+  std::unordered_map<hipStream_t, hipEvent_t> last_use;
   bool timing = false;
   std::vector<TimedLaunch> timed;      // recorded, not yet harvested
   std::vector<hipEvent_t> free_events;
@@ -323,25 +334,35 @@ bool make_text_plan(const vl_model* m, int32_t n, const int32_t* lens, Plan* p,
   return finish_plan(m, seqs, T, p);
 }
 
-// Upload the plan's descriptors with an async copy from pinned memory.
-vl_status stage_descriptors(vl_model* m, const Plan& p, void* dst, hipStream_t s) {
-  Staging& st = m->ring[m->ring_pos];
-  m->ring_pos = (m->ring_pos + 1) % m->ring.size();
+// Async copy of `bytes` host bytes to dst through the next pinned buffer of
+// a staging ring; a buffer is reused once the copy it last served is done.
+vl_status stage_copy(std::vector<Staging>& ring, size_t& pos, const void* src, size_t bytes,
+                     void* dst, hipStream_t s) {
+  Staging& st = ring[pos];
+  pos = (pos + 1) % ring.size();
   if (st.pending) {
     VL_HIP(hipEventSynchronize(st.ev));
     st.pending = false;
   }
-  if (st.cap < p.desc_bytes) {
+  if (st.cap < bytes) {
     if (st.host) VL_HIP(hipHostFree(st.host));
     st.host = nullptr;
-    st.cap = std::max<size_t>(p.desc_bytes, 16384);
-    VL_HIP(hipHostMalloc(&st.host, st.cap, hipHostMallocDefault));
+    st.cap = 0;
+    const size_t cap = std::max<size_t>(bytes, 16384);
+    VL_HIP(hipHostMalloc(&st.host, cap, hipHostMallocDefault));
+    st.cap = cap;
   }
-  std::memcpy(st.host, p.desc.data(), p.desc_bytes);
-  VL_HIP(hipMemcpyAsync(dst, st.host, p.desc_bytes, hipMemcpyHostToDevice, s));
+  if (!st.ev) VL_HIP(hipEventCreateWithFlags(&st.ev, hipEventDisableTiming));
+  std::memcpy(st.host, src, bytes);
+  VL_HIP(hipMemcpyAsync(dst, st.host, bytes, hipMemcpyHostToDevice, s));
   VL_HIP(hipEventRecord(st.ev, s));
   st.pending = true;
   return VL_OK;
+}
+
+// Upload the plan's descriptors with an async copy from pinned memory.
+vl_status stage_descriptors(vl_model* m, const Plan& p, void* dst, hipStream_t s) {
+  return stage_copy(m->ring, m->ring_pos, p.desc.data(), p.desc_bytes, dst, s);
 }
 
 enum { T_PATCH = 0, T_LN, T_QKV, T_ATTN, T_OPROJ, T_FC1, T_FC2, T_POOL };
@@ -582,12 +603,38 @@ std::string graph_key(const Plan& p, const void* pix, const void* emb, const voi
   return k;
 }
 
-void destroy_graphs(vl_model* m) {
-  for (auto& kv : m->graphs) {
-    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
-    if (kv.second.host) (void)hipHostFree(kv.second.host);
+// Frees one cached graph once its last replay has finished.
+void release_graph(GraphEntry& g) {
+  if (g.done) {
+    (void)hipEventSynchronize(g.done);
+    (void)hipEventDestroy(g.done);
   }
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.host) (void)hipHostFree(g.host);
+  g = GraphEntry{};
+}
+
+void destroy_graphs(vl_model* m) {
+  for (auto& kv : m->graphs) release_graph(kv.second);
   m->graphs.clear();
+}
+
+// Drops the least recently replayed graph (waiting only for that graph).
+void evict_graph(vl_model* m) {
+  auto victim = m->graphs.end();
+  for (auto it = m->graphs.begin(); it != m->graphs.end(); ++it)
+    if (victim == m->graphs.end() || it->second.last_use < victim->second.last_use) victim = it;
+  if (victim == m->graphs.end()) return;
+  release_graph(victim->second);
+  m->graphs.erase(victim);
+}
+
+// Records that the model's work so far on stream s ends here.
+vl_status mark_use(vl_model* m, hipStream_t s) {
+  hipEvent_t& ev = m->last_use[s];
+  if (!ev) VL_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  VL_HIP(hipEventRecord(ev, s));
+  return VL_OK;
 }
 
 }  // namespace
@@ -801,6 +848,7 @@ static vl_status build_weights(vl_model* m, const float* wdev, hipStream_t s, vl
     for (auto& v : row) v = -1;
   m->ring.resize(8);
   for (Staging& r : m->ring) chk(hipEventCreateWithFlags(&r.ev, hipEventDisableTiming), "hipEventCreate");
+  if (st == VL_OK) st = mark_use(m, s);   // destroy waits for the conversion kernels
   if (st != VL_OK) {
     vl_model_destroy(m);
     return st;
@@ -873,7 +921,16 @@ vl_status vl_model_create(const vl_config* cfg, vl_precision prec, const float* 
 
 void vl_model_destroy(vl_model* m) {
   if (!m) return;
-  (void)hipDeviceSynchronize();
+  // Wait for the model's own enqueued work: every stream it was used on,
+  // its side stream, pending descriptor copies and cached graphs.
+  for (auto& kv : m->last_use) {
+    (void)hipEventSynchronize(kv.second);
+    (void)hipEventDestroy(kv.second);
+  }
+  m->last_use.clear();
+  if (m->side) (void)hipStreamSynchronize(m->side);
+  for (Staging& r : m->ring)
+    if (r.pending && r.ev) (void)hipEventSynchronize(r.ev);
   destroy_graphs(m);
   for (TimedLaunch& t : m->timed) {
     (void)hipEventDestroy(t.start);
@@ -898,16 +955,12 @@ vl_status vl_model_set_option(vl_model* m, vl_option opt, int64_t value) {
   switch (opt) {
     case VL_OPT_GRAPHS:
       m->use_graphs = value != 0;
-      if (!m->use_graphs) {
-        (void)hipDeviceSynchronize();
-        destroy_graphs(m);
-      }
+      if (!m->use_graphs) destroy_graphs(m);
       return VL_OK;
     case VL_OPT_TIMING:
       m->timing = value != 0;
       return VL_OK;
     case VL_OPT_SPLIT:
-      (void)hipDeviceSynchronize();
       destroy_graphs(m);
       m->split = value != 0;
       return VL_OK;
@@ -956,17 +1009,14 @@ static vl_status encode_planned(vl_model* m, const Plan& p, const void* pix, flo
   std::lock_guard<std::mutex> lk(m->mu);
   if (!m->use_graphs || m->timing) {
     vl_status st = stage_descriptors(m, p, w, s);
+    if (st == VL_OK) st = run_encoder(m, p, pix, emb, w, s);
     if (st != VL_OK) return st;
-    return run_encoder(m, p, pix, emb, w, s);
+    return mark_use(m, s);
   }
   const std::string key = graph_key(p, pix, emb, ws, ws_bytes, s);
   auto it = m->graphs.find(key);
   if (it == m->graphs.end()) {
-    if (m->graphs.size() >= 64) {
-      VL_HIP(hipStreamSynchronize(s));
-      (void)hipDeviceSynchronize();
-      destroy_graphs(m);
-    }
+    while (m->graphs.size() >= kMaxGraphs) evict_graph(m);
     // Capture on the model's private stream (the caller's stream may be the
     // null stream, which cannot be captured); the graph is replayed on the
     // caller's stream.  Capture records work without running it.
@@ -989,11 +1039,17 @@ static vl_status encode_planned(vl_model* m, const Plan& p, const void* pix, flo
       if (e != hipSuccess) st = hip_fail(e, "hipGraphInstantiate");
     }
     if (g) (void)hipGraphDestroy(g);
-    if (st != VL_OK) { (void)hipHostFree(ge.host); return st; }
+    if (st == VL_OK) {
+      e = hipEventCreateWithFlags(&ge.done, hipEventDisableTiming);
+      if (e != hipSuccess) st = hip_fail(e, "hipEventCreate");
+    }
+    if (st != VL_OK) { release_graph(ge); return st; }
     it = m->graphs.emplace(key, ge).first;
   }
   VL_HIP(hipGraphLaunch(it->second.exec, s));
-  return VL_OK;
+  VL_HIP(hipEventRecord(it->second.done, s));
+  it->second.last_use = ++m->graph_clock;
+  return mark_use(m, s);
 }
 
 vl_status vl_encode_images(vl_model* m, const float* pix, const int32_t* hs, const int32_t* wsz,
@@ -1054,7 +1110,6 @@ vl_status vl_model_set_tuning(vl_model* m, const int32_t* table) {
     if (table[i] < -1 || table[i] >= N_GEMM_CFGS)
       return fail(VL_ERR_INVALID_ARG, "tuning entry " + std::to_string(i) + " is not a configuration id");
   std::lock_guard<std::mutex> lk(m->mu);
-  (void)hipDeviceSynchronize();
   destroy_graphs(m);
   std::memcpy(m->tuning, table, sizeof(m->tuning));
   return VL_OK;
@@ -1199,7 +1254,10 @@ vl_status vl_model_autotune(vl_model* m, const float* pix, const int32_t* hs, co
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  (void)hipDeviceSynchronize();
+  if (st == VL_OK) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
+  }
   destroy_graphs(m);
   return st;
 }
@@ -1267,7 +1325,7 @@ vl_status vl_score(const float* emb, int32_t n_images, const float* texts, int32
                    int32_t* top1, void* stream) {
   if (!emb || !texts || !scores) return fail(VL_ERR_INVALID_ARG, "NULL pointer argument");
   if (n_images <= 0 || n_texts <= 0 || dim <= 0) return fail(VL_ERR_INVALID_ARG, "sizes must be > 0");
-  if (dim % 16) return fail(VL_ERR_INVALID_ARG, "dim must be a multiple of 16");
+  if (dim % 4) return fail(VL_ERR_INVALID_ARG, "dim must be a multiple of 4");
   if (n_texts % 4) return fail(VL_ERR_INVALID_ARG, "n_texts must be a multiple of 4");
   if (head != VL_HEAD_SOFTMAX && head != VL_HEAD_SIGMOID) return fail(VL_ERR_INVALID_ARG, "unknown head");
   if (!std::isfinite(scale) || !std::isfinite(bias)) return fail(VL_ERR_INVALID_ARG, "scale/bias not finite");
@@ -1283,6 +1341,276 @@ vl_status vl_score(const float* emb, int32_t n_images, const float* texts, int32
   VL_HIP(gemm_f32_rows(emb, dim, texts, dim, n_images, n_texts, dim, OP_LOGITS, e, s));
   VL_HIP(score_rows(scores, top1, n_images, n_texts, head == VL_HEAD_SOFTMAX ? 0 : 1, s));
   return VL_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- attention on its own
+namespace {
+
+constexpr int kMaxAttnLen = 4096;  // longest sequence vl_attention accepts
+
+// Descriptor blob of a vl_attention call: sequence descriptors then the
+// 128-query work items (16-byte aligned), as the encoder lays them out.
+bool attention_plan(int32_t n, const int32_t* lens, std::vector<char>* desc, size_t* off_items,
+                    int* n_items, int64_t* T, std::string* why) {
+  if (n <= 0 || n > kMaxItems) { *why = "n_seqs must be 1..65535"; return false; }
+  if (!lens) { *why = "lengths is NULL"; return false; }
+  std::vector<ImgDesc> seqs(n);
+  std::vector<AttnItem> items;
+  int64_t t = 0;
+  for (int i = 0; i < n; ++i) {
+    if (lens[i] < 1 || lens[i] > kMaxAttnLen) {
+      *why = "sequence " + std::to_string(i) + " has length " + std::to_string(lens[i]) +
+             ", not in 1..4096";
+      return false;
+    }
+    ImgDesc& d = seqs[i];
+    d.pix_off = 0;
+    d.H = d.W = d.gh = d.gw = 0;
+    d.tok_start = (int32_t)t;
+    d.ntok = lens[i];
+    for (int q0 = 0; q0 < lens[i]; q0 += kAttnQ) items.push_back(AttnItem{i, q0});
+    t += lens[i];
+  }
+  if (t > (1LL << 24)) { *why = "more than 2^24 tokens"; return false; }
+  const size_t a = (sizeof(ImgDesc) * n + 15) / 16 * 16;
+  desc->assign(a + sizeof(AttnItem) * items.size(), 0);
+  std::memcpy(desc->data(), seqs.data(), sizeof(ImgDesc) * n);
+  std::memcpy(desc->data() + a, items.data(), sizeof(AttnItem) * items.size());
+  *off_items = a;
+  *n_items = (int)items.size();
+  *T = t;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t vl_attention_workspace_bytes(int32_t n_seqs, const int32_t* lengths) {
+  std::vector<char> desc;
+  size_t off = 0;
+  int n_items = 0;
+  int64_t T = 0;
+  std::string why;
+  if (!attention_plan(n_seqs, lengths, &desc, &off, &n_items, &T, &why)) return 0;
+  return align_up(desc.size());
+}
+
+vl_status vl_attention(const void* qkv, vl_precision prec, const int32_t* lengths, int32_t n_seqs,
+                       int32_t heads, int32_t head_dim, int32_t causal, void* out, void* ws,
+                       size_t ws_bytes, void* stream) {
+  if (!qkv || !out || !ws) return fail(VL_ERR_INVALID_ARG, "qkv, out or workspace is NULL");
+  if (prec != VL_FP32 && prec != VL_BF16)
+    return fail(VL_ERR_INVALID_ARG, "precision must be VL_FP32 or VL_BF16");
+  if (heads < 1 || heads > 64) return fail(VL_ERR_INVALID_ARG, "heads must be 1..64");
+  if (head_dim != 32 && head_dim != 64) return fail(VL_ERR_UNSUPPORTED, "head_dim must be 32 or 64");
+  auto al = [](const void* p, uintptr_t k) { return reinterpret_cast<uintptr_t>(p) % k == 0; };
+  if (!al(qkv, 16) || !al(out, 16) || !al(ws, kAlign))
+    return fail(VL_ERR_INVALID_ARG, "qkv and out must be 16-byte, the workspace 256-byte aligned");
+  std::vector<char> desc;
+  size_t off_items = 0;
+  int n_items = 0;
+  int64_t T = 0;
+  std::string why;
+  if (!attention_plan(n_seqs, lengths, &desc, &off_items, &n_items, &T, &why))
+    return fail(VL_ERR_INVALID_ARG, why);
+  if (ws_bytes < align_up(desc.size()))
+    return fail(VL_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  {
+    // Descriptors go up through a library-wide ring of pinned buffers.
+    static std::mutex mu;
+    static std::vector<Staging> ring(8);
+    static size_t pos = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    vl_status st = stage_copy(ring, pos, desc.data(), desc.size(), w, s);
+    if (st != VL_OK) return st;
+  }
+  const ImgDesc* d_seqs = reinterpret_cast<const ImgDesc*>(w);
+  const AttnItem* d_items = reinterpret_cast<const AttnItem*>(w + off_items);
+  if (prec == VL_BF16)
+    VL_HIP(attention_bf16(static_cast<const bf16_t*>(qkv), static_cast<bf16_t*>(out), d_seqs,
+                          d_items, n_items, heads, head_dim, causal != 0, s));
+  else
+    VL_HIP(attention_f32(static_cast<const float*>(qkv), static_cast<float*>(out), d_seqs,
+                         d_items, n_items, heads, head_dim, causal != 0, s));
+  return VL_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ tuning table as JSON
+namespace {
+
+const char* kGemmOpNames[VL_N_GEMM_OPS] = {"patch_embed", "qkv_gemm", "oproj_gemm", "fc1_gemm",
+                                           "fc2_gemm"};
+const char* kPrecNames[4] = {"fp32", "bf16", "fp8w", "mxfp8"};
+
+std::string device_arch(int dev) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');   // drop feature suffixes such as ":sramecc+:xnack-"
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// A minimal JSON reader for the tuning file: objects, strings (no escapes
+// beyond \" and \\), numbers, true / false / null.  Arrays are not used.
+struct JVal {
+  enum Kind { NUL, NUM, STR, OBJ, BOOL } kind = NUL;
+  double num = 0;
+  std::string str;
+  std::vector<std::pair<std::string, JVal>> obj;
+  const JVal* get(const char* k) const {
+    for (const auto& kv : obj)
+      if (kv.first == k) return &kv.second;
+    return nullptr;
+  }
+};
+
+struct JParser {
+  const std::string& s;
+  size_t i = 0;
+  explicit JParser(const std::string& t) : s(t) {}
+  void ws() { while (i < s.size() && std::isspace((unsigned char)s[i])) ++i; }
+  bool str(std::string* out) {
+    ws();
+    if (i >= s.size() || s[i] != '"') return false;
+    ++i;
+    out->clear();
+    while (i < s.size() && s[i] != '"') {
+      if (s[i] == '\\') {
+        if (++i >= s.size()) return false;
+        if (s[i] != '"' && s[i] != '\\' && s[i] != '/') return false;
+      }
+      out->push_back(s[i++]);
+    }
+    if (i >= s.size()) return false;
+    ++i;
+    return true;
+  }
+  bool value(JVal* v, int depth) {
+    if (depth > 8) return false;
+    ws();
+    if (i >= s.size()) return false;
+    const char c = s[i];
+    if (c == '{') {
+      ++i;
+      v->kind = JVal::OBJ;
+      ws();
+      if (i < s.size() && s[i] == '}') { ++i; return true; }
+      for (;;) {
+        std::string k;
+        if (!str(&k)) return false;
+        ws();
+        if (i >= s.size() || s[i] != ':') return false;
+        ++i;
+        JVal x;
+        if (!value(&x, depth + 1)) return false;
+        v->obj.emplace_back(k, std::move(x));
+        ws();
+        if (i < s.size() && s[i] == ',') { ++i; continue; }
+        if (i < s.size() && s[i] == '}') { ++i; return true; }
+        return false;
+      }
+    }
+    if (c == '"') { v->kind = JVal::STR; return str(&v->str); }
+    if (s.compare(i, 4, "true") == 0) { v->kind = JVal::BOOL; v->num = 1; i += 4; return true; }
+    if (s.compare(i, 5, "false") == 0) { v->kind = JVal::BOOL; i += 5; return true; }
+    if (s.compare(i, 4, "null") == 0) { v->kind = JVal::NUL; i += 4; return true; }
+    const char* b = s.c_str() + i;
+    char* e = nullptr;
+    v->num = std::strtod(b, &e);
+    if (e == b) return false;
+    v->kind = JVal::NUM;
+    i += (size_t)(e - b);
+    return true;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+vl_status vl_model_save_tuning(const vl_model* m, const char* path) {
+  if (!m || !path) return fail(VL_ERR_INVALID_ARG, "NULL argument");
+  std::string j = "{\n  \"abi\": " + std::to_string(VL_ABI_VERSION) + ",\n";
+  j += "  \"arch\": \"" + device_arch(m->device) + "\",\n";
+  j += std::string("  \"precision\": \"") + kPrecNames[m->prec] + "\",\n";
+  j += "  \"text\": " + std::string(m->text ? "true" : "false") + ",\n";
+  j += "  \"width\": " + std::to_string(m->D) + ",\n  \"mlp\": " + std::to_string(m->F) +
+       ",\n  \"patch_k\": " + std::to_string(m->Kpad) + ",\n";
+  j += "  \"table\": {";
+  for (int op = 0; op < VL_N_GEMM_OPS; ++op) {
+    j += std::string(op ? ",\n" : "\n") + "    \"" + kGemmOpNames[op] + "\": {";
+    bool first = true;
+    for (int b = 0; b < VL_N_M_BUCKETS; ++b) {
+      const int c = m->tuning[op][b];
+      if (c < 0) continue;
+      j += std::string(first ? "" : ", ") + "\"" + std::to_string(b) + "\": \"" + gemm_cfg_name(c) +
+           "\"";
+      first = false;
+    }
+    j += "}";
+  }
+  j += "\n  }\n}\n";
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(VL_ERR_INVALID_ARG, std::string("cannot write ") + path);
+  const size_t n = std::fwrite(j.data(), 1, j.size(), f);
+  const int rc = std::fclose(f);
+  if (n != j.size() || rc != 0) return fail(VL_ERR_INVALID_ARG, std::string("cannot write ") + path);
+  return VL_OK;
+}
+
+vl_status vl_model_load_tuning(vl_model* m, const char* path) {
+  if (!m || !path) return fail(VL_ERR_INVALID_ARG, "NULL argument");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(VL_ERR_INVALID_ARG, std::string("cannot read ") + path);
+  std::string text;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof buf, f)) > 0 && text.size() < (1u << 20)) text.append(buf, n);
+  std::fclose(f);
+  JVal root;
+  JParser ps(text);
+  if (!ps.value(&root, 0) || root.kind != JVal::OBJ)
+    return fail(VL_ERR_INVALID_ARG, std::string(path) + " is not a JSON object");
+  auto num = [&](const char* k) { const JVal* v = root.get(k); return v && v->kind == JVal::NUM ? v->num : -1.0; };
+  auto strv = [&](const char* k) { const JVal* v = root.get(k); return v && v->kind == JVal::STR ? v->str : std::string(); };
+  const JVal* txt = root.get("text");
+  const bool is_text = txt && txt->kind == JVal::BOOL && txt->num != 0;
+  if ((int)num("abi") != VL_ABI_VERSION || strv("arch") != device_arch(m->device) ||
+      strv("precision") != kPrecNames[m->prec] || is_text != m->text ||
+      (int)num("width") != m->D || (int)num("mlp") != m->F || (int)num("patch_k") != m->Kpad)
+    return fail(VL_ERR_INVALID_ARG, std::string(path) +
+                                        " was tuned for another device, precision or model shape");
+  const JVal* table = root.get("table");
+  if (!table || table->kind != JVal::OBJ) return fail(VL_ERR_INVALID_ARG, "no \"table\" object");
+  int32_t t[VL_N_GEMM_OPS][VL_N_M_BUCKETS];
+  for (auto& row : t)
+    for (auto& v : row) v = -1;
+  for (const auto& kv : table->obj) {
+    int op = -1;
+    for (int k = 0; k < VL_N_GEMM_OPS; ++k)
+      if (kv.first == kGemmOpNames[k]) op = k;
+    if (op < 0 || kv.second.kind != JVal::OBJ)
+      return fail(VL_ERR_INVALID_ARG, "unknown GEMM operation \"" + kv.first + "\"");
+    for (const auto& e : kv.second.obj) {
+      char* end = nullptr;
+      const long b = std::strtol(e.first.c_str(), &end, 10);
+      if (end == e.first.c_str() || *end || b < 0 || b >= VL_N_M_BUCKETS)
+        return fail(VL_ERR_INVALID_ARG, "bad M bucket \"" + e.first + "\"");
+      int id = -1;
+      for (int c = 0; c < N_GEMM_CFGS; ++c)
+        if (e.second.kind == JVal::STR && e.second.str == gemm_cfg_name(c)) id = c;
+      if (id < 0) return fail(VL_ERR_INVALID_ARG, "unknown tile configuration in " + kv.first);
+      t[op][b] = id;
+    }
+  }
+  return vl_model_set_tuning(m, &t[0][0]);
 }
 
 }  // extern "C"

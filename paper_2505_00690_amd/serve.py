@@ -245,7 +245,9 @@ class GpuExecutor(Executor):
             sc = torch.empty((n, self.texts.shape[0]), dtype=torch.float32, device="cuda")
             top = torch.empty(n, dtype=torch.int32, device="cuda")
             vl.vl_encode_images(self.enc.handle, pix, [h for h, _ in sizes],
-                                [w for _, w in sizes], emb, ws, s)
+                                [w for _, w in sizes], emb, ws, s,
+                                channels=getattr(self.enc.cfg, "channels", 3),
+                                proj_dim=self.enc.cfg.proj_dim)
             vl.vl_score(emb, self.texts, self.head, self.scale, self.bias, sc, top, s)
             ev = torch.cuda.Event()
             ev.record(s)

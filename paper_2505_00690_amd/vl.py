@@ -26,6 +26,8 @@ __all__ = [
     "vl_mx_gemm", "VlTextConfig", "vl_text_weights_count", "vl_text_model_create",
     "vl_text_workspace_bytes", "vl_encode_texts", "TextEncoder", "VL_POOL_CLS", "VL_POOL_MAP",
     "POOLS", "vl_contrastive_workspace_bytes", "vl_contrastive_loss",
+    "vl_attention_workspace_bytes", "vl_attention", "vl_model_save_tuning",
+    "vl_model_load_tuning",
 ]
 
 VL_FP32, VL_BF16, VL_FP8W_BF16A, VL_MXFP8 = 0, 1, 2, 3
@@ -45,9 +47,9 @@ EXPORTED_SYMBOLS = (
     "vl_encode_workspace_bytes", "vl_encode_images", "vl_score", "vl_model_op_times",
     "vl_mx_quantize", "vl_mx_gemm", "vl_text_weights_count", "vl_text_model_create",
     "vl_text_workspace_bytes", "vl_encode_texts", "vl_contrastive_workspace_bytes",
-    "vl_contrastive_loss",
+    "vl_contrastive_loss", "vl_attention_workspace_bytes", "vl_attention",
     "vl_gemm_config_count", "vl_gemm_config_name", "vl_model_get_tuning",
-    "vl_model_set_tuning", "vl_model_autotune",
+    "vl_model_set_tuning", "vl_model_autotune", "vl_model_save_tuning", "vl_model_load_tuning",
 )
 VL_N_GEMM_OPS, VL_N_M_BUCKETS = 5, 25
 GEMM_OPS = ("patch_embed", "qkv_gemm", "oproj_gemm", "fc1_gemm", "fc2_gemm")
@@ -143,6 +145,10 @@ def lib() -> ctypes.CDLL:
     L.vl_model_set_tuning.argtypes = [_vp, _pi32]
     L.vl_model_autotune.restype = ctypes.c_int
     L.vl_model_autotune.argtypes = [_vp, _vp, _pi32, _pi32, _i32, _vp, _vp, _sz, _i32, _vp]
+    L.vl_model_save_tuning.restype = ctypes.c_int
+    L.vl_model_save_tuning.argtypes = [_vp, ctypes.c_char_p]
+    L.vl_model_load_tuning.restype = ctypes.c_int
+    L.vl_model_load_tuning.argtypes = [_vp, ctypes.c_char_p]
     L.vl_mx_quantize.restype = ctypes.c_int
     L.vl_mx_quantize.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp]
     L.vl_text_weights_count.restype = _sz
@@ -159,6 +165,11 @@ def lib() -> ctypes.CDLL:
     L.vl_contrastive_loss.restype = ctypes.c_int
     L.vl_contrastive_loss.argtypes = [_vp, _vp, _i32, _i32, ctypes.c_int, _f32, _f32, _vp, _vp,
                                       _vp, _vp, _vp, _sz, _vp]
+    L.vl_attention_workspace_bytes.restype = _sz
+    L.vl_attention_workspace_bytes.argtypes = [_i32, _pi32]
+    L.vl_attention.restype = ctypes.c_int
+    L.vl_attention.argtypes = [_vp, ctypes.c_int, _pi32, _i32, _i32, _i32, _i32, _vp, _vp, _sz,
+                               _vp]
     L.vl_mx_gemm.restype = ctypes.c_int
     L.vl_mx_gemm.argtypes = [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _i32, _vp]
     L.vl_score.restype = ctypes.c_int
@@ -259,9 +270,33 @@ def vl_model_set_tuning(handle, table) -> None:
     _check(lib().vl_model_set_tuning(handle, (ctypes.c_int32 * len(flat))(*flat)))
 
 
+def vl_model_save_tuning(handle, path: str) -> None:
+    _check(lib().vl_model_save_tuning(handle, os.fsencode(path)))
+
+
+def vl_model_load_tuning(handle, path: str) -> None:
+    _check(lib().vl_model_load_tuning(handle, os.fsencode(path)))
+
+
+def _need(t: torch.Tensor, name: str, shape=None, numel=None, dtype=None) -> None:
+    """Host-side size check of a tensor handed to the library, which cannot
+    check device buffer sizes itself (an undersized buffer would be read or
+    written out of bounds)."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, needs at least {numel}")
+
+
 def vl_model_autotune(handle, pixels: torch.Tensor, heights: Sequence[int],
                       widths: Sequence[int], emb_out: torch.Tensor, workspace: torch.Tensor,
-                      reps: int = 5, stream=None) -> None:
+                      reps: int = 5, stream=None, channels: int = 3,
+                      proj_dim: Optional[int] = None) -> None:
+    _check_encode_args(pixels, heights, widths, emb_out, channels, proj_dim)
     _check(lib().vl_model_autotune(handle, _ptr(pixels, torch.float32, "pixels"),
                                    _i32_array(heights), _i32_array(widths), len(heights),
                                    _ptr(emb_out, torch.float32, "emb_out"),
@@ -275,11 +310,25 @@ def vl_encode_workspace_bytes(handle, heights: Sequence[int], widths: Sequence[i
                                                _i32_array(widths)))
 
 
-def vl_encode_images(handle, pixels: torch.Tensor, heights: Sequence[int],
-                     widths: Sequence[int], emb_out: torch.Tensor, workspace: torch.Tensor,
-                     stream=None) -> None:
+def _check_encode_args(pixels, heights, widths, emb_out, channels, proj_dim) -> None:
     if len(heights) != len(widths):
         raise ValueError("heights and widths differ in length")
+    n = len(heights)
+    _need(pixels, "pixels", dtype=torch.float32,
+          numel=int(channels) * sum(int(h) * int(w) for h, w in zip(heights, widths)))
+    _need(emb_out, "emb_out", dtype=torch.float32)
+    if emb_out.dim() != 2 or emb_out.shape[0] != n or \
+            (proj_dim is not None and emb_out.shape[1] != int(proj_dim)):
+        raise ValueError(f"emb_out must be [{n}, {proj_dim if proj_dim else 'proj_dim'}], "
+                         f"got {tuple(emb_out.shape)}")
+
+
+def vl_encode_images(handle, pixels: torch.Tensor, heights: Sequence[int],
+                     widths: Sequence[int], emb_out: torch.Tensor, workspace: torch.Tensor,
+                     stream=None, channels: int = 3, proj_dim: Optional[int] = None) -> None:
+    """channels / proj_dim: the model's, for the host-side size checks of
+    pixels (channels * sum(H * W) floats) and emb_out ([n, proj_dim])."""
+    _check_encode_args(pixels, heights, widths, emb_out, channels, proj_dim)
     _check(lib().vl_encode_images(handle, _ptr(pixels, torch.float32, "pixels"),
                                   _i32_array(heights), _i32_array(widths), len(heights),
                                   _ptr(emb_out, torch.float32, "emb_out"),
@@ -310,6 +359,8 @@ def vl_encode_texts(handle, ids: torch.Tensor, lengths: Sequence[int], emb_out: 
                     workspace: torch.Tensor, stream=None) -> None:
     if ids.numel() != sum(int(x) for x in lengths):
         raise ValueError("ids must hold sum(lengths) tokens")
+    if emb_out.dim() != 2 or emb_out.shape[0] != len(lengths):
+        raise ValueError(f"emb_out must be [{len(lengths)}, proj_dim], got {tuple(emb_out.shape)}")
     _check(lib().vl_encode_texts(handle, _ptr(ids, torch.int32, "ids"), _i32_array(lengths),
                                  len(lengths), _ptr(emb_out, torch.float32, "emb_out"),
                                  _ptr(workspace, None, "workspace"),
@@ -346,14 +397,50 @@ def vl_score(emb: torch.Tensor, texts: torch.Tensor, head, scale: float, bias: f
              scores_out: torch.Tensor, top1_out: Optional[torch.Tensor] = None,
              stream=None) -> None:
     h = HEADS[head] if isinstance(head, str) else int(head)
+    if emb.dim() != 2 or texts.dim() != 2:
+        raise ValueError("emb and texts must be 2-D")
     n, dim = emb.shape
     m = texts.shape[0]
     if texts.shape[1] != dim:
         raise ValueError("emb and texts differ in width")
+    _need(scores_out, "scores_out", shape=(n, m), dtype=torch.float32)
+    if top1_out is not None:
+        _need(top1_out, "top1_out", shape=(n,), dtype=torch.int32)
     _check(lib().vl_score(_ptr(emb, torch.float32, "emb"), n, _ptr(texts, torch.float32, "texts"),
                           m, dim, h, float(scale), float(bias),
                           _ptr(scores_out, torch.float32, "scores_out"),
                           _ptr(top1_out, torch.int32, "top1_out"), _stream(stream)))
+
+
+def vl_attention_workspace_bytes(lengths: Sequence[int]) -> int:
+    return int(lib().vl_attention_workspace_bytes(len(lengths), _i32_array(lengths)))
+
+
+def vl_attention(qkv: torch.Tensor, lengths: Sequence[int], heads: int, head_dim: int,
+                 causal: bool, out: torch.Tensor, workspace: Optional[torch.Tensor] = None,
+                 stream=None) -> None:
+    """Multi-head attention of packed sequences: qkv [T, 3 * heads * head_dim]
+    (BF16 or FP32) -> out [T, heads * head_dim] of the same dtype."""
+    T = sum(int(x) for x in lengths)
+    D = int(heads) * int(head_dim)
+    if qkv.dtype not in (torch.bfloat16, torch.float32):
+        raise ValueError("qkv must be bfloat16 or float32")
+    if tuple(qkv.shape) != (T, 3 * D):
+        raise ValueError(f"qkv must be [{T}, {3 * D}], got {tuple(qkv.shape)}")
+    if tuple(out.shape) != (T, D) or out.dtype != qkv.dtype:
+        raise ValueError(f"out must be [{T}, {D}] {qkv.dtype}")
+    prec = VL_BF16 if qkv.dtype == torch.bfloat16 else VL_FP32
+    nb = vl_attention_workspace_bytes(lengths)
+    if nb == 0:
+        raise VlError(1, "invalid sequence lengths")
+    if workspace is None:
+        workspace = torch.empty(nb, dtype=torch.uint8, device=qkv.device)
+    elif workspace.numel() * workspace.element_size() < nb:
+        raise ValueError("workspace too small")
+    _check(lib().vl_attention(_ptr(qkv, None, "qkv"), prec, _i32_array(lengths), len(lengths),
+                              int(heads), int(head_dim), 1 if causal else 0, _ptr(out, None, "out"),
+                              _ptr(workspace, None, "workspace"),
+                              workspace.numel() * workspace.element_size(), _stream(stream)))
 
 
 def vl_mx_quantize(src: torch.Tensor, codes_out: torch.Tensor, scales_out: torch.Tensor,
@@ -400,6 +487,7 @@ class Encoder:
             vl_model_set_option(self.handle, VL_OPT_SPLIT, 1)
         self._ws: Optional[torch.Tensor] = None
         self.device = weights.device
+        self._channels = int(getattr(cfg, "channels", 3))
 
     def close(self) -> None:
         if self.handle is not None and self.handle.value:
@@ -421,14 +509,24 @@ class Encoder:
         return self._ws
 
     def autotune(self, pixels: torch.Tensor, sizes: Sequence[Tuple[int, int]],
-                 reps: int = 5) -> dict:
+                 reps: int = 5, cache: Optional[str] = None) -> dict:
         """Time every GEMM tile configuration on this batch shape and keep
-        the fastest; returns {op: {bucket: config name}} of the table."""
+        the fastest; returns {op: {bucket: config name}} of the table.  With
+        `cache` (a JSON path), a table saved there for this device, precision
+        and model shape is loaded instead of tuning, and a new one is saved."""
         n = len(sizes)
         out = torch.empty((n, self.cfg.proj_dim), dtype=torch.float32, device=self.device)
         ws = self.workspace(self.workspace_bytes(sizes))
+        if cache and os.path.exists(cache):
+            try:
+                vl_model_load_tuning(self.handle, cache)
+                return self.tuning()
+            except VlError:
+                pass                          # tuned elsewhere: tune again and rewrite
         vl_model_autotune(self.handle, pixels, [h for h, _ in sizes], [w for _, w in sizes],
-                          out, ws, reps)
+                          out, ws, reps, channels=self._channels, proj_dim=self.cfg.proj_dim)
+        if cache:
+            vl_model_save_tuning(self.handle, cache)
         return self.tuning()
 
     def tuning(self) -> dict:
@@ -457,7 +555,7 @@ class Encoder:
             raise VlError(1, "invalid batch shapes")
         ws = self.workspace(need)
         vl_encode_images(self.handle, pixels, [h for h, _ in sizes], [w for _, w in sizes], out,
-                         ws, stream)
+                         ws, stream, channels=self._channels, proj_dim=self.cfg.proj_dim)
         return out
 
 

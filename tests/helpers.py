@@ -45,3 +45,20 @@ def certified_top1(logits_ref: np.ndarray, emb_err: np.ndarray, scale: float):
     s = np.sort(logits_ref, axis=1)
     gap = s[:, -1] - s[:, -2]
     return gap > 2.0 * scale * emb_err
+
+
+def rescale_excursion(s_log2: np.ndarray, tile: int = 64) -> float:
+    """Largest amount, over the rows of a score matrix in log2 units, by which
+    a key tile's maximum exceeds the maximum of all earlier tiles (-inf
+    entries are masked keys).  Above 8, the BF16 attention kernel's lazy
+    rescale runs for that row."""
+    n = s_log2.shape[1]
+    run = np.max(s_log2[:, :tile], axis=1)
+    best = -np.inf
+    for t in range(1, (n + tile - 1) // tile):
+        tm = np.max(s_log2[:, tile * t:tile * (t + 1)], axis=1)
+        ok = np.isfinite(tm) & np.isfinite(run)
+        if ok.any():
+            best = max(best, float(np.max(tm[ok] - run[ok])))
+        run = np.maximum(run, tm)
+    return best

@@ -65,7 +65,13 @@ def test_invalid_arguments_rejected_on_host(V):
     # scoring argument checks happen before any launch
     p = ctypes.c_void_p(256)
     assert lib.vl_score(p, 4, p, 10, 128, 0, 1.0, 0.0, p, None, None) == 1   # n_texts % 4
-    assert lib.vl_score(p, 4, p, 16, 100, 0, 1.0, 0.0, p, None, None) == 1   # dim % 16
+    assert "n_texts" in V.vl_last_error_message()
+    assert lib.vl_score(p, 4, p, 16, 102, 0, 1.0, 0.0, p, None, None) == 1   # dim % 4
+    assert "dim" in V.vl_last_error_message()
+    # dim = 100 meets the documented dim % 4: only n_texts is then reported
+    assert lib.vl_score(p, 4, p, 10, 100, 0, 1.0, 0.0, p, None, None) == 1
+    assert "n_texts" in V.vl_last_error_message()
+    assert lib.vl_score(p, 4, p, 16, 128, 0, 1.0, 0.0, ctypes.c_void_p(260), None, None) == 1
     assert lib.vl_score(p, 0, p, 16, 128, 0, 1.0, 0.0, p, None, None) == 1
     assert lib.vl_score(p, 4, p, 16, 128, 5, 1.0, 0.0, p, None, None) == 1   # head
     assert lib.vl_score(None, 4, p, 16, 128, 0, 1.0, 0.0, p, None, None) == 1
@@ -111,3 +117,73 @@ def test_next_row_entry_points_validate_on_host(V):
     assert f(p, p, 8, 128, 0, 10.0, 0.0, p, p, p, p, p, 16, None) == 3          # workspace
     assert V.vl_contrastive_workspace_bytes(8, 128) > 0
     assert V.vl_contrastive_workspace_bytes(0, 128) == 0
+
+
+def test_attention_entry_point_validates_on_host(V):
+    """vl_attention's documented constraints, each checked on its own."""
+    lib = V.lib()
+    p = ctypes.c_void_p(256)
+    L = (ctypes.c_int32 * 2)(65, 577)
+    nb = lib.vl_attention_workspace_bytes(2, L)
+    assert nb >= 2 * 32 + (1 + 5) * 8 and nb % 256 == 0
+    assert lib.vl_attention_workspace_bytes(0, L) == 0
+    assert lib.vl_attention_workspace_bytes(1, (ctypes.c_int32 * 1)(0)) == 0
+    assert lib.vl_attention_workspace_bytes(1, (ctypes.c_int32 * 1)(4097)) == 0
+    assert lib.vl_attention_workspace_bytes(1, (ctypes.c_int32 * 1)(4096)) > 0
+    f = lambda *a: lib.vl_attention(*a)  # noqa: E731
+    assert f(p, 1, L, 2, 0, 64, 0, p, p, nb, None) == 1          # heads
+    assert f(p, 1, L, 2, 65, 64, 0, p, p, nb, None) == 1         # heads <= 64
+    assert f(p, 1, L, 2, 4, 48, 0, p, p, nb, None) == 2          # head_dim 32 / 64
+    assert f(p, 2, L, 2, 4, 64, 0, p, p, nb, None) == 1          # precision
+    assert f(None, 1, L, 2, 4, 64, 0, p, p, nb, None) == 1
+    assert f(p, 1, L, 2, 4, 64, 0, ctypes.c_void_p(264), p, nb, None) == 1    # out alignment
+    assert f(p, 1, L, 2, 4, 64, 0, p, ctypes.c_void_p(384), nb, None) == 1    # ws alignment
+    assert f(p, 1, L, 2, 4, 64, 0, p, p, nb - 1, None) == 3      # workspace too small
+    assert f(p, 1, (ctypes.c_int32 * 2)(65, 0), 2, 4, 64, 0, p, p, nb, None) == 1
+
+
+def test_tuning_file_entry_points_validate_on_host(V, tmp_path):
+    lib = V.lib()
+    assert lib.vl_model_save_tuning(None, str(tmp_path / "t.json").encode()) == 1
+    assert lib.vl_model_load_tuning(None, str(tmp_path / "t.json").encode()) == 1
+
+
+def test_binding_checks_buffer_sizes_before_the_call(V):
+    """The C ABI cannot see the size of a device buffer; the binding checks
+    every tensor against the shapes the call implies and raises ValueError
+    (checked here with host tensors, before any device pointer is taken)."""
+    import torch
+    emb = torch.zeros((3, 128))
+    texts = torch.zeros((16, 128))
+    with pytest.raises(ValueError, match="scores_out"):
+        V.vl_score(emb, texts, "softmax", 100.0, 0.0, torch.zeros((3, 15)))
+    with pytest.raises(ValueError, match="scores_out"):
+        V.vl_score(emb, texts, "softmax", 100.0, 0.0, torch.zeros((3, 16), dtype=torch.float64))
+    with pytest.raises(ValueError, match="top1_out"):
+        V.vl_score(emb, texts, "softmax", 100.0, 0.0, torch.zeros((3, 16)),
+                   torch.zeros(2, dtype=torch.int32))
+    with pytest.raises(ValueError, match="width"):
+        V.vl_score(emb, torch.zeros((16, 64)), "softmax", 100.0, 0.0, torch.zeros((3, 16)))
+    sizes_h, sizes_w = [64, 48], [64, 80]
+    need = 3 * (64 * 64 + 48 * 80)
+    ws = torch.zeros(16, dtype=torch.uint8)
+    with pytest.raises(ValueError, match="pixels"):
+        V.vl_encode_images(None, torch.zeros(need - 1), sizes_h, sizes_w, torch.zeros((2, 128)),
+                           ws, proj_dim=128)
+    with pytest.raises(ValueError, match="emb_out"):
+        V.vl_encode_images(None, torch.zeros(need), sizes_h, sizes_w, torch.zeros((2, 64)), ws,
+                           proj_dim=128)
+    with pytest.raises(ValueError, match="emb_out"):
+        V.vl_encode_images(None, torch.zeros(need), sizes_h, sizes_w, torch.zeros((3, 128)), ws)
+    with pytest.raises(ValueError, match="pixels"):      # four planes need more pixels
+        V.vl_encode_images(None, torch.zeros(need), sizes_h, sizes_w, torch.zeros((2, 128)), ws,
+                           channels=4)
+    with pytest.raises(ValueError, match="differ"):
+        V.vl_encode_images(None, torch.zeros(need), [64], [64, 80], torch.zeros((2, 128)), ws)
+    with pytest.raises(ValueError, match="qkv"):
+        V.vl_attention(torch.zeros((10, 3 * 128)), [5, 4], 2, 64, False, torch.zeros((9, 128)))
+    with pytest.raises(ValueError, match="out"):
+        V.vl_attention(torch.zeros((9, 3 * 128)), [5, 4], 2, 64, False, torch.zeros((9, 64)))
+    with pytest.raises(ValueError, match="emb_out"):
+        V.vl_encode_texts(None, torch.zeros(9, dtype=torch.int32), [5, 4], torch.zeros((3, 128)),
+                          ws)

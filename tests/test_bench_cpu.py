@@ -60,3 +60,27 @@ def test_traffic_record_dropped_once_the_kernel_source_changes(tmp_path, monkeyp
     _profile(str(tmp_path), "kernel v2", [("A", 100.0, 10.0)])
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.traffic_from_profile("fc1_gemm", "w", {"A"}) is None
+
+
+def test_oracle_error_and_top1_agreement_host_logic():
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(5))
+    ref = rng.standard_normal((6, 16))
+    ref /= np.linalg.norm(ref, axis=1, keepdims=True)
+    got = ref + 1e-3 * rng.standard_normal(ref.shape)
+    e = bench.oracle_error(got, ref, "bf16")
+    rel = np.linalg.norm(got - ref, axis=1)
+    assert abs(e["max_rel_err"] - rel.max()) < 1e-15 and e["images"] == 6
+    assert 0.999 < e["min_cos"] < 1.0
+    texts = rng.standard_normal((40, 16))
+    texts /= np.linalg.norm(texts, axis=1, keepdims=True)
+    top_ref = np.argmax(ref @ texts.T, axis=1)
+    top_a = top_ref.copy()
+    top_a[0] = (top_a[0] + 1) % 40                 # one disagreement
+    r = bench.top1_agreement(top_a, top_ref, got, ref, texts, 10.0, 1e-4)
+    assert r["images"] == 6 and abs(r["raw"] - 5 / 6) < 1e-12
+    # a row is certified only when its logit gap beats 2 * scale * (||d|| + slack)
+    l = 10.0 * ref @ texts.T
+    s = np.sort(l, axis=1)
+    cert = (s[:, -1] - s[:, -2]) > 2 * 10.0 * (np.linalg.norm(got - ref, axis=1) + 1e-4)
+    assert r["certified_images"] == int(cert.sum())

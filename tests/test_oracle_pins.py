@@ -430,6 +430,28 @@ def test_weights_for_only_touches_block_linears():
         assert rel.max() < (2 ** -8 if prec == "bf16" else 2 ** -4)
 
 
+def test_weights_for_map_head_rounds_only_kv_projection():
+    """With an attention-pooling head, every reduced precision rounds the
+    head's K/V projection (and only it) to BF16 -- checked against torch's
+    own BF16 cast, not the oracle's rounding -- while FP32 leaves it as is."""
+    c = synth.MODELS["tiny_map"]
+    p = synth.make_params(c, 21)
+    want = torch.from_numpy(np.asarray(p["map_kv_w"], np.float32)).to(torch.bfloat16)
+    want = want.to(torch.float64).numpy()
+    head = [k for k in p if k.startswith("map_")]
+    assert "map_kv_w" in head and len(head) == 13
+    for prec in ("bf16", "fp8w", "mxfp8"):
+        w = O.weights_for(p, prec)
+        assert np.array_equal(w["map_kv_w"], want), prec
+        assert not np.array_equal(w["map_kv_w"], p["map_kv_w"])
+        for k in head:
+            if k != "map_kv_w":
+                assert np.array_equal(w[k], p[k]), (prec, k)
+    w = O.weights_for(p, "fp32")
+    for k in head:
+        assert np.array_equal(w[k], p[k]), k
+
+
 # ------------------------------------------ MXFP8 (OCP Microscaling Formats)
 def test_mx_hand_worked_block():
     # amax 1.0: floor(log2) = 0, X = 0 - 8; elements are v * 2^8 rounded on
