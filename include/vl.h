@@ -392,6 +392,29 @@ vl_status vl_contrastive_loss(const float* emb_dev, const float* texts_dev, int3
                               float* d_scale_bias_dev, void* workspace_dev,
                               size_t workspace_bytes, void* stream);
 
+/* Allocation-free variant of vl_contrastive_loss, for callers that cannot
+ * allocate device memory or pass a workspace: code under HIP graph capture,
+ * tight training or serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels, results (bitwise) and errors as vl_contrastive_loss,
+ * minus the workspace: the kernels' scratch (logits, their transpose, the
+ * transposed embeddings, per-row partials) lives in a static device array of
+ * VL_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until the
+ * process ends.  Its device address is looked up once per device on the
+ * first call made with that device current.  The call allocates nothing
+ * (no hipMalloc / hipFree, no pinned memory, no events) and enqueues only
+ * kernels on `stream`.  Requires vl_contrastive_workspace_bytes(n, dim) <=
+ * VL_NOALLOC_SCRATCH_BYTES (n <= 2528 at dim 768, 2422 at dim 1024), else
+ * VL_ERR_WORKSPACE_TOO_SMALL with nothing enqueued.  Every call on one GPU
+ * shares that GPU's array and overwrites it (nothing in it needs to start
+ * at zero): calls that overlap on one GPU, i.e. are in flight at the same
+ * time on different streams, race and give undefined results; serialise
+ * them on one stream or order them with events.                            */
+#define VL_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+vl_status vl_contrastive_loss_noalloc(const float* emb_dev, const float* texts_dev, int32_t n,
+                                      int32_t dim, vl_head head, float scale, float bias,
+                                      float* loss_dev, float* d_emb_dev, float* d_texts_dev,
+                                      float* d_scale_bias_dev, void* stream);
+
 /* MXFP8 encoding (the one VL_MXFP8 applies to its weights and activations)
  * of FP32 rows, for callers that prepare operands themselves and for
  * checking the encoder.

@@ -42,6 +42,7 @@ vl_status hip_fail(hipError_t e, const char* what) {
   } while (0)
 
 constexpr size_t kAlign = 256;
+static_assert(kNoAllocScratchBytes == VL_NOALLOC_SCRATCH_BYTES, "scratch size in vl.h");
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 constexpr int kMaxTokens = 1025;   // 32 x 32 patches + class token
@@ -1315,6 +1316,35 @@ vl_status vl_contrastive_loss(const float* emb, const float* texts, int32_t n, i
     return fail(VL_ERR_INVALID_ARG, "arrays must be 16-byte and the workspace 256-byte aligned");
   if (ws_bytes < contrastive_workspace_bytes(n, dim))
     return fail(VL_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
+  VL_HIP(contrastive_loss(emb, texts, n, dim, head == VL_HEAD_SOFTMAX ? 0 : 1, scale, bias, loss,
+                          d_emb, d_texts, d_scale_bias, ws, static_cast<hipStream_t>(stream)));
+  return VL_OK;
+}
+
+vl_status vl_contrastive_loss_noalloc(const float* emb, const float* texts, int32_t n,
+                                      int32_t dim, vl_head head, float scale, float bias,
+                                      float* loss, float* d_emb, float* d_texts,
+                                      float* d_scale_bias, void* stream) {
+  if (!emb || !texts || !loss || !d_emb || !d_texts || !d_scale_bias)
+    return fail(VL_ERR_INVALID_ARG, "NULL pointer argument");
+  if (n <= 0 || dim <= 0) return fail(VL_ERR_INVALID_ARG, "sizes must be > 0");
+  if (n > 65535) return fail(VL_ERR_INVALID_ARG, "n must be <= 65535");
+  if (dim % 16) return fail(VL_ERR_INVALID_ARG, "dim must be a multiple of 16");
+  if (head != VL_HEAD_SOFTMAX && head != VL_HEAD_SIGMOID) return fail(VL_ERR_INVALID_ARG, "unknown head");
+  if (!std::isfinite(scale) || !(scale > 0.f) || !std::isfinite(bias))
+    return fail(VL_ERR_INVALID_ARG, "scale must be finite and > 0, bias finite");
+  auto al = [](const void* p, uintptr_t k) { return reinterpret_cast<uintptr_t>(p) % k == 0; };
+  if (!al(emb, 16) || !al(texts, 16) || !al(d_emb, 16) || !al(d_texts, 16))
+    return fail(VL_ERR_INVALID_ARG, "arrays must be 16-byte aligned");
+  const size_t need = contrastive_workspace_bytes(n, dim);
+  if (need > kNoAllocScratchBytes)
+    return fail(VL_ERR_WORKSPACE_TOO_SMALL,
+                "n = " + std::to_string(n) + ", dim = " + std::to_string(dim) + " needs " +
+                    std::to_string(need) + " bytes of scratch; the allocation-free entry point "
+                    "has " + std::to_string(kNoAllocScratchBytes) +
+                    " (use vl_contrastive_loss with a caller workspace)");
+  void* ws = nullptr;
+  VL_HIP(noalloc_scratch(&ws));
   VL_HIP(contrastive_loss(emb, texts, n, dim, head == VL_HEAD_SOFTMAX ? 0 : 1, scale, bias, loss,
                           d_emb, d_texts, d_scale_bias, ws, static_cast<hipStream_t>(stream)));
   return VL_OK;

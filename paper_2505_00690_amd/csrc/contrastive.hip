@@ -8,6 +8,8 @@
 // dL/dl (G) is formed element-wise from the logits and the row / column
 // log-sum-exps; the embedding gradients are the GEMMs scale * G T and
 // scale * G^T E.
+#include <mutex>
+
 #include "kernels.hpp"
 
 namespace vl {
@@ -212,6 +214,36 @@ hipError_t contrastive_loss(const float* E, const float* Tx, int n, int dim, int
   EpiArgs gt;
   gt.out = dT; gt.ldo = dim; gt.alpha = scale; gt.beta = 0.f;
   return gemm_f32(Gt, n16, Et, n16, n, dim, n16, OP_LOGITS, gt, s);
+}
+
+// Scratch of the allocation-free contrastive entry point: a file-scope
+// device array, one copy per GPU, alive until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol); it asks the runtime for the array's device
+// address once per device, with that device current, and uses that address.
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
 }
 
 }  // namespace vl

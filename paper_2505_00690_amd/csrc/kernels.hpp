@@ -162,6 +162,11 @@ hipError_t score_rows(float* scores, int32_t* top1, int rows, int cols, int head
 // gradients: loss[1], dE/dT [n, dim], dsb = (dL/dscale, dL/dbias).  dim %
 // 16 == 0; ws holds contrastive_workspace_bytes(n, dim).
 size_t contrastive_workspace_bytes(int n, int dim);
+// Size of the per-device scratch array of the allocation-free contrastive
+// entry point, and its device address on the current device (looked up on
+// the first call per device; never allocates).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+hipError_t noalloc_scratch(void** out);
 hipError_t contrastive_loss(const float* E, const float* T, int n, int dim, int head,
                             float scale, float bias, float* loss, float* dE, float* dT,
                             float* dsb, void* ws, hipStream_t s);

@@ -27,7 +27,7 @@ __all__ = [
     "vl_text_workspace_bytes", "vl_encode_texts", "TextEncoder", "VL_POOL_CLS", "VL_POOL_MAP",
     "POOLS", "vl_contrastive_workspace_bytes", "vl_contrastive_loss",
     "vl_attention_workspace_bytes", "vl_attention", "vl_model_save_tuning",
-    "vl_model_load_tuning",
+    "vl_model_load_tuning", "vl_contrastive_loss_noalloc", "VL_NOALLOC_SCRATCH_BYTES",
 ]
 
 VL_FP32, VL_BF16, VL_FP8W_BF16A, VL_MXFP8 = 0, 1, 2, 3
@@ -50,7 +50,9 @@ EXPORTED_SYMBOLS = (
     "vl_contrastive_loss", "vl_attention_workspace_bytes", "vl_attention",
     "vl_gemm_config_count", "vl_gemm_config_name", "vl_model_get_tuning",
     "vl_model_set_tuning", "vl_model_autotune", "vl_model_save_tuning", "vl_model_load_tuning",
+    "vl_contrastive_loss_noalloc",
 )
+VL_NOALLOC_SCRATCH_BYTES = 64 << 20
 VL_N_GEMM_OPS, VL_N_M_BUCKETS = 5, 25
 GEMM_OPS = ("patch_embed", "qkv_gemm", "oproj_gemm", "fc1_gemm", "fc2_gemm")
 
@@ -165,6 +167,9 @@ def lib() -> ctypes.CDLL:
     L.vl_contrastive_loss.restype = ctypes.c_int
     L.vl_contrastive_loss.argtypes = [_vp, _vp, _i32, _i32, ctypes.c_int, _f32, _f32, _vp, _vp,
                                       _vp, _vp, _vp, _sz, _vp]
+    L.vl_contrastive_loss_noalloc.restype = ctypes.c_int
+    L.vl_contrastive_loss_noalloc.argtypes = [_vp, _vp, _i32, _i32, ctypes.c_int, _f32, _f32,
+                                              _vp, _vp, _vp, _vp, _vp]
     L.vl_attention_workspace_bytes.restype = _sz
     L.vl_attention_workspace_bytes.argtypes = [_i32, _pi32]
     L.vl_attention.restype = ctypes.c_int
@@ -391,6 +396,28 @@ def vl_contrastive_loss(emb: torch.Tensor, texts: torch.Tensor, head, scale: flo
                                      float(scale), float(bias), _ptr(loss), _ptr(de), _ptr(dt),
                                      _ptr(dsb), _ptr(ws), nb, _stream(stream)))
     return loss, de, dt, dsb
+
+
+def vl_contrastive_loss_noalloc(emb: torch.Tensor, texts: torch.Tensor, head, scale: float,
+                                bias: float, loss: torch.Tensor, d_emb: torch.Tensor,
+                                d_texts: torch.Tensor, d_scale_bias: torch.Tensor,
+                                stream=None) -> None:
+    """vl_contrastive_loss into caller-provided outputs, with the library's
+    static per-device scratch instead of a workspace (nothing is allocated,
+    here or in the library).  Calls in flight together on one GPU race."""
+    h = HEADS[head] if isinstance(head, str) else int(head)
+    if emb.dim() != 2 or texts.shape != emb.shape:
+        raise ValueError("emb and texts must both be [n, dim]")
+    n, dim = emb.shape
+    for name, t, shape in (("loss", loss, (1,)), ("d_emb", d_emb, (n, dim)),
+                           ("d_texts", d_texts, (n, dim)), ("d_scale_bias", d_scale_bias, (2,))):
+        if tuple(t.shape) != shape:
+            raise ValueError(f"{name} must have shape {shape}, got {tuple(t.shape)}")
+    _check(lib().vl_contrastive_loss_noalloc(
+        _ptr(emb, torch.float32, "emb"), _ptr(texts, torch.float32, "texts"), n, dim, h,
+        float(scale), float(bias), _ptr(loss, torch.float32, "loss"),
+        _ptr(d_emb, torch.float32, "d_emb"), _ptr(d_texts, torch.float32, "d_texts"),
+        _ptr(d_scale_bias, torch.float32, "d_scale_bias"), _stream(stream)))
 
 
 def vl_score(emb: torch.Tensor, texts: torch.Tensor, head, scale: float, bias: float,

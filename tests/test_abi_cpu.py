@@ -117,6 +117,18 @@ def test_next_row_entry_points_validate_on_host(V):
     assert f(p, p, 8, 128, 0, 10.0, 0.0, p, p, p, p, p, 16, None) == 3          # workspace
     assert V.vl_contrastive_workspace_bytes(8, 128) > 0
     assert V.vl_contrastive_workspace_bytes(0, 128) == 0
+    # the allocation-free variant: same checks, and sizes past its static
+    # scratch are refused before the device is touched
+    g = lambda *a: lib.vl_contrastive_loss_noalloc(*a)  # noqa: E731
+    assert g(p, p, 8, 100, 0, 10.0, 0.0, p, p, p, p, None) == 1                 # dim % 16
+    assert g(p, p, 0, 128, 0, 10.0, 0.0, p, p, p, p, None) == 1                 # n
+    assert g(p, p, 8, 128, 0, -1.0, 0.0, p, p, p, p, None) == 1                 # scale
+    assert g(p, p, 8, 128, 2, 10.0, 0.0, p, p, p, p, None) == 1                 # head
+    assert g(None, p, 8, 128, 0, 10.0, 0.0, p, p, p, p, None) == 1              # NULL
+    assert V.vl_contrastive_workspace_bytes(2528, 768) <= V.VL_NOALLOC_SCRATCH_BYTES
+    assert V.vl_contrastive_workspace_bytes(2529, 768) > V.VL_NOALLOC_SCRATCH_BYTES
+    assert g(p, p, 2529, 768, 0, 10.0, 0.0, p, p, p, p, None) == 3
+    assert "scratch" in V.vl_last_error_message()
 
 
 def test_attention_entry_point_validates_on_host(V):
