@@ -105,7 +105,8 @@ class Executor:
 class ServeStats:
     results: List[Result] = field(default_factory=list)
     batches: int = 0
-    max_inflight: int = 0
+    max_inflight: int = 0               # batches on the device at once
+    max_inflight_images: int = 0        # images in those batches
     peak_budget: int = 0
     rejected: List[int] = field(default_factory=list)   # requests larger than the budget
     wall: float = 0.0
@@ -196,6 +197,9 @@ class Scheduler:
                 used += ws
                 st.batches += 1
                 st.max_inflight = max(st.max_inflight, len(running))
+                st.max_inflight_images = max(
+                    st.max_inflight_images,
+                    sum(len(r.sizes) for _, rs, _, _ in running.values() for r in rs))
                 st.peak_budget = max(st.peak_budget, used)
             # Idle: wait for the next arrival or completion.
             nxt = [t_start + pending[i].arrival] if i < len(pending) else []
@@ -228,7 +232,15 @@ class GpuExecutor(Executor):
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
 
     def workspace_bytes(self, sizes):
-        return self.enc.workspace_bytes(sizes)
+        """Device bytes a batch holds while it runs: the encoder workspace
+        plus the buffers launch() allocates (the packed pixels, counted even
+        when a single request's tensor is used as is, the embeddings, the
+        scores and the top-1 indices)."""
+        n = len(sizes)
+        chans = getattr(self.enc.cfg, "channels", 3)
+        io = 4 * chans * sum(h * w for h, w in sizes)
+        io += 4 * n * (self.enc.cfg.proj_dim + self.texts.shape[0] + 1)
+        return self.enc.workspace_bytes(sizes) + io
 
     def launch(self, reqs, slot):
         torch, vl = self.torch, self.vl

@@ -447,16 +447,47 @@ def test_serving_mix_equals_alone(V):
     torch.cuda.synchronize()
     assert len(st.results) == 24 and st.peak_budget <= budget
     _say(f"  serving: {st.batches} batches, max in flight {st.max_inflight}")
+    _check_mix_equals_alone(V, enc, texts, reqs, st)
+
+
+def _check_mix_equals_alone(V, enc, texts, reqs, st):
     for res in st.results:
         r = reqs[res.rid]
         alone = enc.encode(r.payload, r.sizes)
-        sc = torch.empty((len(r.sizes), 64), dtype=torch.float32, device="cuda")
+        sc = torch.empty((len(r.sizes), texts.shape[0]), dtype=torch.float32, device="cuda")
         top = torch.empty(len(r.sizes), dtype=torch.int32, device="cuda")
         V.vl_score(alone, texts, "sigmoid", 10.0, -10.0, sc, top)
         torch.cuda.synchronize()
         emb_mix, top_mix = res.output
         assert torch.equal(emb_mix, alone), res.rid
         assert torch.equal(top_mix, top), res.rid
+
+
+def test_serving_mix_equals_alone_l14_fp8w_mixed(V):
+    """The serving configuration itself: ViT-L/14 with e4m3 per-row weights,
+    8192 resident texts, requests of 1-16 images at 224/336/384/448 px.  The
+    first requests arrive together and the rest while those run, so two
+    batches of mixed resolutions are on the device at once (asserted, with at
+    least 32 images between them); every request's embeddings and top-1
+    equal the request run alone, bitwise."""
+    from paper_2505_00690_amd.serve import GpuExecutor, RealClock, Request, Scheduler
+    enc = encoder(V, "l14", 1004, "fp8w")
+    texts = torch.from_numpy(synth.make_texts(8192, 768, 3005)).cuda()
+    drawn = synth.draw_requests(10, 400.0, (224, 336, 384, 448), 5005, 4, 16)
+    reqs = []
+    for i, r in enumerate(drawn):
+        imgs = synth.make_images(r.sizes, 7100 + i)
+        arrival = 0.0 if i < 4 else r.arrival_s
+        reqs.append(Request(i, arrival, r.sizes, torch.from_numpy(pack(imgs)).cuda()))
+    torch.cuda.synchronize()
+    ex = GpuExecutor(enc, texts, "sigmoid", 10.0, -10.0, slots=2)
+    st = Scheduler(ex, 16 << 30, slots=2, max_batch_images=32).run(reqs, RealClock())
+    torch.cuda.synchronize()
+    _say(f"  serving l14 fp8w: {st.batches} batches, max in flight {st.max_inflight} "
+         f"batches / {st.max_inflight_images} images")
+    assert len(st.results) == len(reqs) and not st.rejected
+    assert st.max_inflight >= 2 and st.max_inflight_images >= 32
+    _check_mix_equals_alone(V, enc, texts, reqs, st)
 
 
 # ------------------------------------------------------------- autotuner
