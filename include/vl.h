@@ -330,6 +330,45 @@ vl_status vl_encode_images(vl_model* m, const float* pixels_dev,
                            void* workspace_dev, size_t workspace_bytes,
                            void* stream);
 
+/* ---- Contrastive training through the image tower ------------------------
+ * Gradients of a training loss with respect to every weight of the image
+ * tower, for a caller that forms the loss from the embeddings (for example
+ * with vl_contrastive_loss, CLIP Sec. 2.3 / SigLIP Eq. 1, which also returns
+ * dL/d(embedding)).  Two calls with the same pixels, shapes and workspace:
+ *   vl_encode_images_train    : the encoder forward (bitwise the same
+ *                               embeddings as vl_encode_images), keeping in
+ *                               the workspace what the backward pass reads;
+ *   vl_encode_images_backward : given d_emb_dev [n_images, proj_dim] FP32 =
+ *                               dL/d(unit embedding), writes grads_dev, an
+ *                               FP32 array of vl_weights_count(cfg) values
+ *                               in the weight blob's layout (16-byte
+ *                               aligned; overwritten, not accumulated),
+ *                               summed over the batch.
+ * The backward is the chain rule of each forward step (LayerNorm, GELU,
+ * attention, linear layers, patch embedding with the folded pixel
+ * normalisation, class token and position table, final LayerNorm,
+ * projection, L2 normalisation).  VL_FP32 models compute in FP32; VL_BF16
+ * models multiply BF16 operands (the kept activations, dL/dx of the
+ * residual stream, dGELU and dQKV rounded to BF16) with FP32 accumulation;
+ * LayerNorm, softmax and L2 statistics stay FP32.
+ * Supported: VL_FP32 and VL_BF16 image models with VL_POOL_CLS (else
+ * VL_ERR_UNSUPPORTED), every image at the base patch grid (floor(H/P) ==
+ * floor(W/P) == base_grid), at most 2^20 tokens.  The backward returns
+ * VL_ERR_INVALID_ARG unless the model's last vl_encode_images_train call had
+ * the same pixels pointer, shapes and workspace; the caller must not reuse
+ * that workspace in between.  Workspace: vl_train_workspace_bytes(...) bytes,
+ * 256-byte aligned (about 2 x (10 D + 2 F) bytes per token per block in BF16,
+ * twice that in FP32).  Asynchronous on `stream`.                          */
+size_t vl_train_workspace_bytes(const vl_model* m, int32_t n_images, const int32_t* heights,
+                                const int32_t* widths);
+vl_status vl_encode_images_train(vl_model* m, const float* pixels_dev, const int32_t* heights,
+                                 const int32_t* widths, int32_t n_images, float* emb_out_dev,
+                                 void* workspace_dev, size_t workspace_bytes, void* stream);
+vl_status vl_encode_images_backward(vl_model* m, const float* pixels_dev,
+                                    const int32_t* heights, const int32_t* widths,
+                                    int32_t n_images, const float* d_emb_dev, float* grads_dev,
+                                    void* workspace_dev, size_t workspace_bytes, void* stream);
+
 /* Score unit image embeddings against text embeddings, FP32 throughout.
  *  emb_dev   : [n_images, dim]   texts_dev : [n_texts, dim]  (row-major)
  *  scores_out_dev : [n_images, n_texts] probabilities (softmax over texts)

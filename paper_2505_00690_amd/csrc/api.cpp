@@ -125,6 +125,10 @@ struct vl_model {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int32_t tuning[VL_N_GEMM_OPS][VL_N_M_BUCKETS];
+  // The last vl_encode_images_train call (workspace, pixels, shapes): the
+  // backward pass must be given the same, since it reads what that forward
+  // kept in the workspace.
+  std::string train_key;
 };
 
 namespace {
@@ -209,12 +213,13 @@ struct Plan {
 // The common tail of planning: part boundaries, attention work items, the
 // descriptor blob and the workspace regions.  imgs[] hold absolute token
 // starts on entry.
-bool finish_plan(const vl_model* m, std::vector<ImgDesc>& imgs, int64_t T, Plan* p) {
+bool finish_plan(const vl_model* m, std::vector<ImgDesc>& imgs, int64_t T, Plan* p,
+                 bool one_part = false) {
   const int n = (int)imgs.size();
   p->T = (int)T;
   // Part boundaries: one part, or two holding about half the tokens each.
   std::vector<int> cut = {0};
-  if (m->split && m->prec != VL_FP32 && n >= 2 && T >= kSplitMinTokens) {
+  if (!one_part && m->split && m->prec != VL_FP32 && n >= 2 && T >= kSplitMinTokens) {
     int n1 = 1;
     while (n1 < n - 1 && imgs[n1].tok_start < T / 2) ++n1;
     cut.push_back(n1);
@@ -276,7 +281,7 @@ bool finish_plan(const vl_model* m, std::vector<ImgDesc>& imgs, int64_t T, Plan*
 }
 
 bool make_plan(const vl_model* m, int32_t n, const int32_t* hs, const int32_t* ws, Plan* p,
-               std::string* why) {
+               std::string* why, bool one_part = false) {
   if (m->text) { *why = "this model encodes texts (vl_encode_texts)"; return false; }
   if (n <= 0) { *why = "n_images must be > 0"; return false; }
   if (n > kMaxItems) { *why = "n_images must be <= 65535 (split larger batches)"; return false; }
@@ -302,7 +307,7 @@ bool make_plan(const vl_model* m, int32_t n, const int32_t* hs, const int32_t* w
     p->hw[2 * i + 1] = W;
   }
   if (T > (1LL << 24)) { *why = "batch exceeds 2^24 tokens"; return false; }
-  return finish_plan(m, imgs, T, p);
+  return finish_plan(m, imgs, T, p, one_part);
 }
 
 // Text batches: one descriptor per sequence (tokens tok_start .. +ntok-1 of
@@ -1641,6 +1646,400 @@ vl_status vl_model_load_tuning(vl_model* m, const char* path) {
     }
   }
   return vl_model_set_tuning(m, &t[0][0]);
+}
+
+}  // extern "C"
+
+// ================================================= training through the tower
+namespace {
+
+// Workspace of a training forward + backward: the one-part encode plan, then
+// per block the activations the backward reads, then the backward's scratch.
+struct TrainLayer { size_t xin, y1, qkv, o, h, y2, z1; };
+struct TrainPlan {
+  Plan p;
+  size_t off_items64 = 0;   // 64-token attention blocks, in the descriptor region
+  int n_items64 = 0;
+  int Tp = 0;               // T rounded up to 64 (K of the weight-gradient GEMMs)
+  std::vector<TrainLayer> layers;
+  size_t dX, dXb, gT, actT, dGf, dZ, dY, Wt, lse, dsum, part, pg, pb, de, zp, ppg, ppb, dwf;
+  size_t total = 0;
+};
+
+bool make_train_plan(const vl_model* m, int32_t n, const int32_t* hs, const int32_t* ws,
+                     TrainPlan* tp, std::string* why) {
+  if (m->text) { *why = "training covers the image tower"; return false; }
+  if (m->prec != VL_FP32 && m->prec != VL_BF16) {
+    *why = "training runs in VL_FP32 or VL_BF16";
+    return false;
+  }
+  if (m->cfg.pool != VL_POOL_CLS) { *why = "training covers class-token pooling"; return false; }
+  if (!make_plan(m, n, hs, ws, &tp->p, why, /*one_part=*/true)) return false;
+  for (int i = 0; i < n; ++i)
+    if (hs[i] / m->P != m->g0 || ws[i] / m->P != m->g0) {
+      *why = "image " + std::to_string(i) + ": training needs the base patch grid (" +
+             std::to_string(m->g0) + " x " + std::to_string(m->g0) + ")";
+      return false;
+    }
+  Plan& p = tp->p;
+  // (2^20 tokens: the transposes' grid spans T / 32 rows of workgroups)
+  if (p.T > (1 << 20)) { *why = "training batch exceeds 2^20 tokens"; return false; }
+  // 64-token blocks of every image for the attention backward
+  std::vector<AttnItem> it;
+  const ImgDesc* imgs = reinterpret_cast<const ImgDesc*>(p.desc.data() + p.parts[0].off_imgs);
+  for (int i = 0; i < n; ++i)
+    for (int t0 = 0; t0 < imgs[i].ntok; t0 += 64) it.push_back(AttnItem{i, t0});
+  tp->n_items64 = (int)it.size();
+  tp->off_items64 = (p.desc_bytes + 15) / 16 * 16;
+  const size_t new_desc = tp->off_items64 + sizeof(AttnItem) * it.size();
+  if (align_up(new_desc) > align_up(p.desc_bytes)) {
+    // the activation regions start after the descriptor region: move them
+    const size_t shift = align_up(new_desc) - align_up(p.desc_bytes);
+    for (Part& q : p.parts) {
+      q.off_tok += shift; q.off_X += shift; q.off_Y += shift; q.off_QH += shift; q.off_E += shift;
+    }
+    p.total += shift;
+  }
+  p.desc.resize(new_desc, 0);
+  std::memcpy(p.desc.data() + tp->off_items64, it.data(), sizeof(AttnItem) * it.size());
+  p.desc_bytes = new_desc;
+
+  const size_t T = p.T, D = m->D, F = m->F, es = m->prec == VL_FP32 ? 4 : 2;
+  const size_t Tp = (T + 63) / 64 * 64;
+  tp->Tp = (int)Tp;
+  size_t off = p.total;
+  auto take = [&](size_t bytes) { const size_t r = off; off += align_up(bytes); return r; };
+  tp->layers.resize(m->L);
+  for (TrainLayer& l : tp->layers) {
+    l.xin = take(4 * T * D); l.y1 = take(es * T * D); l.qkv = take(es * 3 * T * D);
+    l.o = take(es * T * D); l.h = take(4 * T * D); l.y2 = take(es * T * D); l.z1 = take(4 * T * F);
+  }
+  const size_t wide = std::max<size_t>({3 * D, F, (size_t)m->Kpad});
+  tp->dX = take(4 * T * D);
+  tp->dXb = es == 2 ? take(es * T * D) : tp->dX;
+  tp->gT = take(es * std::max<size_t>(3 * D, F) * Tp);
+  tp->actT = take(es * std::max<size_t>({D, F, (size_t)m->Kpad}) * Tp);
+  tp->dGf = take(4 * T * F);
+  tp->dZ = take(es * T * std::max<size_t>(3 * D, F));
+  tp->dY = take(4 * T * D);
+  tp->Wt = take(es * std::max<size_t>(3 * D * D, F * D));
+  tp->lse = take(4 * T * m->heads);
+  tp->dsum = take(4 * T * m->heads);
+  tp->part = take(4 * ((T + kColRows - 1) / kColRows) * wide);
+  tp->pg = take(4 * ((T + kLnRows - 1) / kLnRows) * D);
+  tp->pb = take(4 * ((T + kLnRows - 1) / kLnRows) * D);
+  tp->de = take(4 * (size_t)n * m->Pd);
+  tp->zp = take(4 * (size_t)n * D);
+  tp->ppg = take(4 * (size_t)n * D);
+  tp->ppb = take(4 * (size_t)n * D);
+  tp->dwf = take(4 * D * m->Kpad);
+  tp->total = off;
+  return true;
+}
+
+std::string train_key(const TrainPlan& tp, const void* pix, const void* ws, size_t ws_bytes) {
+  std::string k;
+  auto put = [&](const void* v, size_t b) { k.append(static_cast<const char*>(v), b); };
+  put(&pix, sizeof pix); put(&ws, sizeof ws); put(&ws_bytes, sizeof ws_bytes);
+  put(tp.p.hw.data(), sizeof(int32_t) * tp.p.hw.size());
+  return k;
+}
+
+// FP32 product C[M, N] = A[M, K] . B[N, K]^T in the model's arithmetic (FP32
+// FMA, or BF16 operands with FP32 accumulation on the MFMA kernel).
+vl_status gemm_into_f32(const vl_model* m, const void* A, int lda, const void* B, int ldb, int M,
+                        int N, int K, float* out, int ldo, hipStream_t s) {
+  EpiArgs e;
+  e.out = out; e.ldo = ldo; e.alpha = 1.f; e.beta = 0.f;
+  if (m->prec == VL_FP32)
+    VL_HIP(gemm_f32(static_cast<const float*>(A), lda, static_cast<const float*>(B), ldb, M, N, K,
+                    OP_LOGITS, e, s));
+  else
+    VL_HIP(gemm_bf16(static_cast<const bf16_t*>(A), lda, B, ldb, false, M, N, K, OP_LOGITS, -1, e,
+                     s));
+  return VL_OK;
+}
+
+// The training forward: the encoder's kernel sequence on one part, keeping
+// each block's input, LayerNorm outputs, Q/K/V, attention output, residual
+// after attention and FC1 pre-activation.  Every kernel and its arithmetic is
+// the inference forward's, so the embeddings agree with vl_encode_images
+// bitwise.
+vl_status run_train_forward(vl_model* m, const TrainPlan& tp, const float* pix, float* emb,
+                            char* ws, hipStream_t s) {
+  const Plan& pl = tp.p;
+  const Part& p = pl.parts[0];
+  const bool f32 = m->prec == VL_FP32;
+  const ImgDesc* d_imgs = reinterpret_cast<const ImgDesc*>(ws + p.off_imgs);
+  const AttnItem* d_items = reinterpret_cast<const AttnItem*>(ws + p.off_items);
+  int2* tok = reinterpret_cast<int2*>(ws + p.off_tok);
+  float* X = reinterpret_cast<float*>(ws + p.off_X);
+  void* QH = ws + p.off_QH;
+  const int T = p.T, D = m->D, F = m->F;
+  const float eps = m->cfg.ln_eps;
+  EpiArgs pe;
+  pe.bias = m->patch_b; pe.out = X; pe.ldo = D; pe.tok_info = tok; pe.imgs = d_imgs;
+  pe.cls = m->cls; pe.pos = m->pos; pe.base_grid = m->g0;
+  VL_HIP(im2col(pix, d_imgs, p.n, p.max_ntok, m->cfg.channels, m->P, m->Kpad, QH, !f32, tok, s));
+  if (f32)
+    VL_HIP(gemm_f32(static_cast<const float*>(QH), m->Kpad, static_cast<const float*>(m->patch_w),
+                    m->Kpad, T, D, m->Kpad, OP_PATCH, pe, s));
+  else
+    VL_HIP(gemm_bf16(static_cast<const bf16_t*>(QH), m->Kpad, m->patch_w, m->Kpad, false, T, D,
+                     m->Kpad, OP_PATCH, gemm_cfg_for(m, 0, T), pe, s));
+  for (int l = 0; l < m->L; ++l) {
+    const Layer& ly = m->layers[l];
+    const TrainLayer& sv = tp.layers[l];
+    void* y1 = ws + sv.y1;
+    void* qkv = ws + sv.qkv;
+    void* o = ws + sv.o;
+    void* y2 = ws + sv.y2;
+    float* z1 = reinterpret_cast<float*>(ws + sv.z1);
+    VL_HIP(copy_f32(X, reinterpret_cast<float*>(ws + sv.xin), (size_t)T * D, s));
+    VL_HIP(layernorm_rows(X, ly.ln1_g, ly.ln1_b, eps, y1, !f32, T, D, s));
+    EpiArgs e1; e1.bias = ly.qkv_b; e1.out = qkv; e1.ldo = 3 * D;
+    EpiArgs e2; e2.bias = ly.o_b; e2.out = X; e2.ldo = D;
+    EpiArgs e3; e3.bias = ly.fc1_b; e3.out = z1; e3.ldo = F;
+    EpiArgs e4; e4.bias = ly.fc2_b; e4.out = X; e4.ldo = D;
+    if (f32) {
+      VL_HIP(gemm_f32(static_cast<const float*>(y1), D, static_cast<const float*>(ly.qkv_w), D, T,
+                      3 * D, D, OP_QKV, e1, s));
+      VL_HIP(attention_f32(static_cast<const float*>(qkv), static_cast<float*>(o), d_imgs, d_items,
+                           p.n_items, m->heads, m->hd, false, s));
+      VL_HIP(gemm_f32(static_cast<const float*>(o), D, static_cast<const float*>(ly.o_w), D, T, D,
+                      D, OP_OPROJ, e2, s));
+    } else {
+      VL_HIP(gemm_bf16(static_cast<const bf16_t*>(y1), D, ly.qkv_w, D, false, T, 3 * D, D, OP_QKV,
+                       gemm_cfg_for(m, 1, T), e1, s));
+      VL_HIP(attention_bf16(static_cast<const bf16_t*>(qkv), static_cast<bf16_t*>(o), d_imgs,
+                            d_items, p.n_items, m->heads, m->hd, false, s));
+      VL_HIP(gemm_bf16(static_cast<const bf16_t*>(o), D, ly.o_w, D, false, T, D, D, OP_OPROJ,
+                       gemm_cfg_for(m, 2, T), e2, s));
+    }
+    VL_HIP(copy_f32(X, reinterpret_cast<float*>(ws + sv.h), (size_t)T * D, s));
+    VL_HIP(layernorm_rows(X, ly.ln2_g, ly.ln2_b, eps, y2, !f32, T, D, s));
+    if (f32) {
+      VL_HIP(gemm_f32(static_cast<const float*>(y2), D, static_cast<const float*>(ly.fc1_w), D, T,
+                      F, D, OP_FC1_PRE, e3, s));
+      VL_HIP(gelu_forward(z1, QH, false, (size_t)T * F, s));
+      VL_HIP(gemm_f32(static_cast<const float*>(QH), F, static_cast<const float*>(ly.fc2_w), F, T,
+                      D, F, OP_FC2, e4, s));
+    } else {
+      VL_HIP(gemm_bf16(static_cast<const bf16_t*>(y2), D, ly.fc1_w, D, false, T, F, D, OP_FC1_PRE,
+                       gemm_cfg_for(m, 3, T), e3, s));
+      VL_HIP(gelu_forward(z1, QH, true, (size_t)T * F, s));
+      VL_HIP(gemm_bf16(static_cast<const bf16_t*>(QH), F, ly.fc2_w, F, false, T, D, F, OP_FC2,
+                       gemm_cfg_for(m, 4, T), e4, s));
+    }
+  }
+  VL_HIP(pool_project(X, d_imgs, p.n, m->lnf_g, m->lnf_b, eps, m->proj, D, m->Pd, false,
+                      static_cast<float*>(QH), reinterpret_cast<float*>(ws + p.off_E), emb, s));
+  return VL_OK;
+}
+
+// Offsets (floats) of every tensor in the FP32 weight blob, hence in the
+// gradient blob (the same layout).
+struct BlobOffsets {
+  size_t patch_w, patch_b, cls, pos, lnf_g, lnf_b, proj;
+  struct L { size_t ln1_g, ln1_b, qkv_w, qkv_b, o_w, o_b, ln2_g, ln2_b, fc1_w, fc1_b, fc2_w, fc2_b; };
+  std::vector<L> layers;
+};
+
+BlobOffsets blob_offsets(const vl_model* m) {
+  BlobOffsets b;
+  const size_t D = m->D, F = m->F;
+  size_t o = 0;
+  auto take = [&](size_t n) { const size_t r = o; o += n; return r; };
+  b.patch_w = take(D * m->Kpe); b.patch_b = take(D); b.cls = take(D);
+  b.pos = take((1 + (size_t)m->g0 * m->g0) * D);
+  b.layers.resize(m->L);
+  for (auto& l : b.layers) {
+    l.ln1_g = take(D); l.ln1_b = take(D); l.qkv_w = take(3 * D * D); l.qkv_b = take(3 * D);
+    l.o_w = take(D * D); l.o_b = take(D); l.ln2_g = take(D); l.ln2_b = take(D);
+    l.fc1_w = take(F * D); l.fc1_b = take(F); l.fc2_w = take(D * F); l.fc2_b = take(D);
+  }
+  b.lnf_g = take(D); b.lnf_b = take(D);
+  b.proj = take((size_t)m->Pd * D);
+  return b;
+}
+
+// The backward pass, block by block in reverse.  dX is the gradient of the
+// residual stream; every linear layer's input gradient is a GEMM against the
+// transposed weight and its weight gradient a GEMM over the tokens (K = T,
+// zero-padded to a multiple of 64) of transposed operands; in the BF16 model
+// the GEMM operands (dX, dGELU, dQKV and the kept activations) are BF16 and
+// the accumulation FP32.
+vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const float* demb,
+                       float* grads, char* ws, hipStream_t s) {
+  const Part& p = tp.p.parts[0];
+  const bool f32 = m->prec == VL_FP32, bf = !f32;
+  const ImgDesc* d_imgs = reinterpret_cast<const ImgDesc*>(ws + p.off_imgs);
+  const AttnItem* d_items64 = reinterpret_cast<const AttnItem*>(ws + tp.off_items64);
+  int2* tok = reinterpret_cast<int2*>(ws + p.off_tok);
+  const float* X = reinterpret_cast<const float*>(ws + p.off_X);
+  void* QH = ws + p.off_QH;
+  const int T = p.T, D = m->D, F = m->F, Tp = tp.Tp;
+  const float eps = m->cfg.ln_eps;
+  float* dX = reinterpret_cast<float*>(ws + tp.dX);
+  void* dXb = ws + tp.dXb;
+  void* gT = ws + tp.gT;
+  void* actT = ws + tp.actT;
+  float* dGf = reinterpret_cast<float*>(ws + tp.dGf);
+  void* dZ = ws + tp.dZ;
+  float* dY = reinterpret_cast<float*>(ws + tp.dY);
+  void* Wt = ws + tp.Wt;
+  float* part = reinterpret_cast<float*>(ws + tp.part);
+  float* pg = reinterpret_cast<float*>(ws + tp.pg);
+  float* pb = reinterpret_cast<float*>(ws + tp.pb);
+  const BlobOffsets bo = blob_offsets(m);
+  auto G = [&](size_t off) { return grads + off; };
+
+  VL_HIP(fill_zero(dX, (size_t)T * D, s));
+  VL_HIP(pool_backward(X, d_imgs, p.n, reinterpret_cast<const float*>(ws + p.off_E), demb, m->proj,
+                       m->lnf_g, m->lnf_b, eps, D, m->Pd, reinterpret_cast<float*>(ws + tp.de),
+                       reinterpret_cast<float*>(ws + tp.zp), dX,
+                       reinterpret_cast<float*>(ws + tp.ppg), reinterpret_cast<float*>(ws + tp.ppb),
+                       part, G(bo.proj), G(bo.lnf_g), G(bo.lnf_b), s));
+  // dX in the GEMM operand type (BF16 copy, or dX itself) and transposed.
+  auto prep_dx = [&]() -> vl_status {
+    if (bf) VL_HIP(convert_bf16(dX, static_cast<bf16_t*>(dXb), (size_t)T * D, s));
+    VL_HIP(transpose_rows(dX, false, T, D, D, gT, bf, Tp, s));
+    return VL_OK;
+  };
+  for (int l = m->L - 1; l >= 0; --l) {
+    const Layer& ly = m->layers[l];
+    const TrainLayer& sv = tp.layers[l];
+    const BlobOffsets::L& go = bo.layers[l];
+    vl_status st;
+    // ---- FC2: x_out = h + GELU(z1) W2^T + b2
+    if ((st = prep_dx()) != VL_OK) return st;
+    VL_HIP(transpose_rows(ly.fc2_w, bf, D, F, F, Wt, bf, D, s));                 // W2^T [F, D]
+    if ((st = gemm_into_f32(m, dXb, D, Wt, D, T, F, D, dGf, F, s)) != VL_OK) return st;
+    VL_HIP(gelu_backward(dGf, reinterpret_cast<const float*>(ws + sv.z1), dZ, QH, bf,
+                         (size_t)T * F, s));                                     // dz1, g
+    VL_HIP(transpose_rows(QH, bf, T, F, F, actT, bf, Tp, s));                    // g^T
+    if ((st = gemm_into_f32(m, gT, Tp, actT, Tp, D, F, Tp, G(go.fc2_w), F, s)) != VL_OK) return st;
+    VL_HIP(colsum(dX, false, T, D, D, nullptr, part, G(go.fc2_b), s));
+    // ---- FC1: z1 = y2 W1^T + b1
+    VL_HIP(transpose_rows(ly.fc1_w, bf, F, D, D, Wt, bf, F, s));                 // W1^T [D, F]
+    if ((st = gemm_into_f32(m, dZ, F, Wt, F, T, D, F, dY, D, s)) != VL_OK) return st;
+    VL_HIP(transpose_rows(dZ, bf, T, F, F, gT, bf, Tp, s));
+    VL_HIP(transpose_rows(ws + sv.y2, bf, T, D, D, actT, bf, Tp, s));
+    if ((st = gemm_into_f32(m, gT, Tp, actT, Tp, F, D, Tp, G(go.fc1_w), D, s)) != VL_OK) return st;
+    VL_HIP(colsum(dZ, bf, T, F, F, nullptr, part, G(go.fc1_b), s));
+    // ---- LN2 (dX += LN2'(h) dY)
+    VL_HIP(layernorm_backward(reinterpret_cast<const float*>(ws + sv.h), ly.ln2_g, dY, eps, dX, T,
+                              D, pg, pb, G(go.ln2_g), G(go.ln2_b), s));
+    // ---- output projection: h = x + O Wo^T + bo
+    if ((st = prep_dx()) != VL_OK) return st;
+    VL_HIP(transpose_rows(ly.o_w, bf, D, D, D, Wt, bf, D, s));
+    if ((st = gemm_into_f32(m, dXb, D, Wt, D, T, D, D, dY, D, s)) != VL_OK) return st;   // dO
+    VL_HIP(transpose_rows(ws + sv.o, bf, T, D, D, actT, bf, Tp, s));
+    if ((st = gemm_into_f32(m, gT, Tp, actT, Tp, D, D, Tp, G(go.o_w), D, s)) != VL_OK) return st;
+    VL_HIP(colsum(dX, false, T, D, D, nullptr, part, G(go.o_b), s));
+    // ---- attention
+    VL_HIP(attention_backward(ws + sv.qkv, ws + sv.o, bf, dY, d_imgs, d_items64, tp.n_items64,
+                              m->heads, m->hd, dZ, reinterpret_cast<float*>(ws + tp.lse),
+                              reinterpret_cast<float*>(ws + tp.dsum), s));
+    // ---- QKV: [q|k|v] = y1 Wqkv^T + bqkv
+    VL_HIP(transpose_rows(ly.qkv_w, bf, 3 * D, D, D, Wt, bf, 3 * D, s));         // [D, 3D]
+    if ((st = gemm_into_f32(m, dZ, 3 * D, Wt, 3 * D, T, D, 3 * D, dY, D, s)) != VL_OK) return st;
+    VL_HIP(transpose_rows(dZ, bf, T, 3 * D, 3 * D, gT, bf, Tp, s));
+    VL_HIP(transpose_rows(ws + sv.y1, bf, T, D, D, actT, bf, Tp, s));
+    if ((st = gemm_into_f32(m, gT, Tp, actT, Tp, 3 * D, D, Tp, G(go.qkv_w), D, s)) != VL_OK)
+      return st;
+    VL_HIP(colsum(dZ, bf, T, 3 * D, 3 * D, nullptr, part, G(go.qkv_b), s));
+    // ---- LN1 (dX += LN1'(x) dY)
+    VL_HIP(layernorm_backward(reinterpret_cast<const float*>(ws + sv.xin), ly.ln1_g, dY, eps, dX,
+                              T, D, pg, pb, G(go.ln1_g), G(go.ln1_b), s));
+  }
+  // ---- token embedding: patches (gathered again), class token, positions
+  VL_HIP(im2col(pix, d_imgs, p.n, p.max_ntok, m->cfg.channels, m->P, m->Kpad, QH, bf, tok, s));
+  VL_HIP(transpose_rows(dX, false, T, D, D, gT, bf, Tp, s));
+  VL_HIP(transpose_rows(QH, bf, T, m->Kpad, m->Kpad, actT, bf, Tp, s));
+  float* dwf = reinterpret_cast<float*>(ws + tp.dwf);
+  {
+    const vl_status st = gemm_into_f32(m, gT, Tp, actT, Tp, D, m->Kpad, Tp, dwf, m->Kpad, s);
+    if (st != VL_OK) return st;
+  }
+  VL_HIP(colsum(dX, false, T, D, D, tok, part, G(bo.patch_b), s));
+  ChanNorm cn{};
+  for (int c = 0; c < 4; ++c) {
+    cn.mean[c] = c < m->cfg.channels ? m->cfg.chan_mean[c] : 0.f;
+    cn.std[c] = c < m->cfg.channels ? m->cfg.chan_std[c] : 1.f;
+  }
+  VL_HIP(embed_backward(dX, d_imgs, p.n, D, 1 + m->g0 * m->g0, dwf, m->Kpad, G(bo.patch_b), cn,
+                        m->Kpe, m->P * m->P, G(bo.pos), G(bo.cls), G(bo.patch_w), s));
+  return VL_OK;
+}
+
+vl_status check_train_args(vl_model* m, const float* pix, const void* a, const void* ws,
+                           int32_t n, const int32_t* hs, const int32_t* wsz, size_t ws_bytes,
+                           TrainPlan* tp) {
+  if (!m) return fail(VL_ERR_INVALID_ARG, "model is NULL");
+  if (!pix || !a || !ws) return fail(VL_ERR_INVALID_ARG, "NULL pointer argument");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(VL_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (reinterpret_cast<uintptr_t>(pix) % 16 || reinterpret_cast<uintptr_t>(a) % 16)
+    return fail(VL_ERR_INVALID_ARG, "pixels and embedding arrays must be 16-byte aligned");
+  std::string why;
+  if (!make_train_plan(m, n, hs, wsz, tp, &why)) {
+    const bool unsup = m->text || (m->prec != VL_FP32 && m->prec != VL_BF16) ||
+                       m->cfg.pool != VL_POOL_CLS;
+    return fail(unsup ? VL_ERR_UNSUPPORTED : VL_ERR_INVALID_ARG, why);
+  }
+  if (ws_bytes < tp->total)
+    return fail(VL_ERR_WORKSPACE_TOO_SMALL, "workspace has " + std::to_string(ws_bytes) +
+                                                " bytes, needs " + std::to_string(tp->total));
+  return VL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t vl_train_workspace_bytes(const vl_model* m, int32_t n, const int32_t* hs,
+                                const int32_t* wsz) {
+  if (!m) return 0;
+  TrainPlan tp;
+  std::string why;
+  if (!make_train_plan(m, n, hs, wsz, &tp, &why)) return 0;
+  return tp.total;
+}
+
+vl_status vl_encode_images_train(vl_model* m, const float* pix, const int32_t* hs,
+                                 const int32_t* wsz, int32_t n, float* emb, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  TrainPlan tp;
+  vl_status st = check_train_args(m, pix, emb, ws, n, hs, wsz, ws_bytes, &tp);
+  if (st != VL_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  std::lock_guard<std::mutex> lk(m->mu);
+  m->train_key.clear();
+  st = stage_descriptors(m, tp.p, w, s);
+  if (st == VL_OK) st = run_train_forward(m, tp, pix, emb, w, s);
+  if (st != VL_OK) return st;
+  m->train_key = train_key(tp, pix, ws, ws_bytes);
+  return mark_use(m, s);
+}
+
+vl_status vl_encode_images_backward(vl_model* m, const float* pix, const int32_t* hs,
+                                    const int32_t* wsz, int32_t n, const float* d_emb,
+                                    float* grads, void* ws, size_t ws_bytes, void* stream) {
+  TrainPlan tp;
+  vl_status st = check_train_args(m, pix, d_emb, ws, n, hs, wsz, ws_bytes, &tp);
+  if (st != VL_OK) return st;
+  if (!grads || reinterpret_cast<uintptr_t>(grads) % 16)
+    return fail(VL_ERR_INVALID_ARG, "grads must be non-NULL and 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(m->mu);
+  if (m->train_key != train_key(tp, pix, ws, ws_bytes))
+    return fail(VL_ERR_INVALID_ARG,
+                "no matching vl_encode_images_train call (same pixels, shapes and workspace) "
+                "precedes this backward pass");
+  st = run_backward(m, tp, pix, d_emb, grads, static_cast<char*>(ws), s);
+  if (st != VL_OK) return st;
+  return mark_use(m, s);
 }
 
 }  // extern "C"

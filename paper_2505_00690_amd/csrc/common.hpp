@@ -173,4 +173,19 @@ __device__ __forceinline__ i32x4 buffer_rsrc(const void* base, uint64_t bytes) {
   return r;
 }
 
+// Reduction over a 256-thread workgroup (4 waves) with `op`; every thread
+// gets the result.  red: 4 floats of LDS.  Safe to call back to back (the
+// first barrier waits for the previous call's readers).
+template <typename Op>
+__device__ __forceinline__ float block_reduce(float v, float* red, Op op) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  v = op(op(red[0], red[1]), op(red[2], red[3]));
+  return v;
+}
+
 }  // namespace vl

@@ -235,20 +235,6 @@ hipError_t im2col(const float* pix, const ImgDesc* imgs, int n_imgs, int max_nto
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------ block reduce
-template <typename Op>
-__device__ __forceinline__ float block_reduce(float v, float* red, Op op) {
-  // 256 threads = 4 waves
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
-  __syncthreads();
-  if (lane == 0) red[w] = v;
-  __syncthreads();
-  v = op(op(red[0], red[1]), op(red[2], red[3]));
-  return v;
-}
-
 // ----------------------------------------------------- pool + LN + proj + L2
 // Pooling, final LayerNorm (ViT Eq. 4), bias-free projection and L2
 // normalisation, FP32.  The pooled row is a sequence's first (the image class

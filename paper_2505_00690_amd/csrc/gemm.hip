@@ -197,6 +197,7 @@ hipError_t gemm_f32(const float* A, int lda, const float* B, int ldb, int M, int
     VL_GEMM_CASE(OP_FC1)
     VL_GEMM_CASE(OP_FC2)
     VL_GEMM_CASE(OP_LOGITS)
+    VL_GEMM_CASE(OP_FC1_PRE)
     default: return hipErrorInvalidValue;
   }
 #undef VL_GEMM_CASE

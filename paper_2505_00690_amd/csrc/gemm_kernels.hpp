@@ -22,13 +22,14 @@
 namespace vl {
 
 // ---------------------------------------------------------------- epilogue
-enum EpiKind { EPI_BIAS, EPI_BIAS_GELU, EPI_BIAS_RESID, EPI_PATCH, EPI_SCALE_BIAS };
+enum EpiKind { EPI_BIAS, EPI_BIAS_GELU, EPI_BIAS_RESID, EPI_PATCH, EPI_SCALE_BIAS, EPI_BIAS_F32 };
 template <int OP>
 struct OpEpi {
   static constexpr int kind = OP == OP_PATCH ? EPI_PATCH
                               : OP == OP_QKV ? EPI_BIAS
                               : OP == OP_FC1 ? EPI_BIAS_GELU
                               : OP == OP_LOGITS ? EPI_SCALE_BIAS
+                              : OP == OP_FC1_PRE ? EPI_BIAS_F32
                                                 : EPI_BIAS_RESID;
 };
 
@@ -94,6 +95,11 @@ __device__ __forceinline__ void epi_store4(const EpiArgs& e, int m, int n, float
     float4 x = *X;
     x.x += v[0]; x.y += v[1]; x.z += v[2]; x.w += v[3];
     *X = x;
+    return;
+  }
+  if (EPI == EPI_BIAS_F32) {
+    *reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n) =
+        make_float4(v[0], v[1], v[2], v[3]);
     return;
   }
   if (EPI == EPI_BIAS_GELU) {
@@ -505,7 +511,7 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
   const int n = n0 + wn * WN + 4 * rc;
   const bool n_ok = n < N;
   float4 bias4 = make_float4(0.f, 0.f, 0.f, 0.f), ws4 = make_float4(1.f, 1.f, 1.f, 1.f);
-  if (EPI != EPI_PATCH && n_ok) {
+  if (EPI != EPI_PATCH && EPI != EPI_SCALE_BIAS && n_ok) {
     bias4 = *reinterpret_cast<const float4*>(e.bias + n);
     if (e.wscale) ws4 = *reinterpret_cast<const float4*>(e.wscale + n);
   }
@@ -546,6 +552,12 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
           epi_store4<EPI, OUT_BF16>(e, m, n, v[p].x, v[p].y, v[p].z, v[p].w);
           continue;
         }
+        if (EPI == EPI_SCALE_BIAS) {
+          *reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n) =
+              make_float4(e.alpha * v[p].x + e.beta, e.alpha * v[p].y + e.beta,
+                          e.alpha * v[p].z + e.beta, e.alpha * v[p].w + e.beta);
+          continue;
+        }
         float4 y = make_float4(__builtin_fmaf(v[p].x, ws4.x, bias4.x),
                                __builtin_fmaf(v[p].y, ws4.y, bias4.y),
                                __builtin_fmaf(v[p].z, ws4.z, bias4.z),
@@ -553,6 +565,10 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
         if (EPI == EPI_BIAS_RESID) {
           *reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n) =
               make_float4(x[p].x + y.x, x[p].y + y.y, x[p].z + y.z, x[p].w + y.w);
+          continue;
+        }
+        if (EPI == EPI_BIAS_F32) {
+          *reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n) = y;
           continue;
         }
         if (EPI == EPI_BIAS_GELU) {
@@ -586,6 +602,8 @@ static hipError_t launch_bf16_dl(const bf16_t* A, int lda, const void* B, int ld
     VL_GEMM_CASE(OP_OPROJ)
     VL_GEMM_CASE(OP_FC1)
     VL_GEMM_CASE(OP_FC2)
+    VL_GEMM_CASE(OP_LOGITS)
+    VL_GEMM_CASE(OP_FC1_PRE)
     default: return hipErrorInvalidValue;
   }
 #undef VL_GEMM_CASE
@@ -609,6 +627,8 @@ static hipError_t launch_bf16(const bf16_t* A, int lda, const void* B, int ldb, 
     VL_GEMM_CASE(OP_OPROJ)
     VL_GEMM_CASE(OP_FC1)
     VL_GEMM_CASE(OP_FC2)
+    VL_GEMM_CASE(OP_LOGITS)
+    VL_GEMM_CASE(OP_FC1_PRE)
     default: return hipErrorInvalidValue;
   }
 #undef VL_GEMM_CASE

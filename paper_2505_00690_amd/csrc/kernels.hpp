@@ -32,7 +32,10 @@ struct AttnItem {
 //   OP_FC1    : out = GELU(acc * ws[n] + bias[n])        (BF16 / FP32 out)
 //   OP_FC2    : resid[m,n] += acc * ws[n] + bias[n]      (FP32)
 //   OP_LOGITS : out = alpha * acc + beta                 (FP32)
-enum GemmOp { OP_PATCH = 0, OP_QKV = 1, OP_OPROJ = 2, OP_FC1 = 3, OP_FC2 = 4, OP_LOGITS = 5 };
+//   OP_FC1_PRE: out = acc * ws[n] + bias[n]              (FP32 out; the FC1
+//               pre-activation the training forward keeps for the backward)
+enum GemmOp { OP_PATCH = 0, OP_QKV = 1, OP_OPROJ = 2, OP_FC1 = 3, OP_FC2 = 4, OP_LOGITS = 5,
+              OP_FC1_PRE = 6 };
 
 struct EpiArgs {
   const float* bias = nullptr;    // [N]
@@ -79,8 +82,9 @@ int gemm_cfg_heuristic(int M, int N, int K, bool b_fp8);
 int gemm_mx_cfg_heuristic(int M, int N, int K);
 
 // C[M,N] = A[M,K] . B[N,K]^T with BF16 A and BF16 (or e4m3 when b_fp8) B,
-// FP32 accumulation, BF16 output for OP_QKV / OP_FC1.  K % 64 == 0,
-// N % 8 == 0.  cfg < 0 selects the heuristic configuration.
+// FP32 accumulation, BF16 output for OP_QKV / OP_FC1, FP32 for OP_LOGITS /
+// OP_FC1_PRE.  K % 64 == 0, N % 8 == 0.  cfg < 0 selects the heuristic
+// configuration.
 hipError_t gemm_bf16(const bf16_t* A, int lda, const void* B, int ldb, bool b_fp8,
                      int M, int N, int K, int op, int cfg, const EpiArgs& e, hipStream_t s);
 
@@ -170,6 +174,50 @@ hipError_t noalloc_scratch(void** out);
 hipError_t contrastive_loss(const float* E, const float* T, int n, int dim, int head,
                             float scale, float bias, float* loss, float* dE, float* dT,
                             float* dsb, void* ws, hipStream_t s);
+
+// ---- training (contrastive training through the image tower)
+constexpr int kColRows = 256;  // rows per partial sum of colsum
+constexpr int kLnRows = 32;    // rows per partial sum of layernorm_backward
+struct ChanNorm { float mean[4], std[4]; };  // per-plane pixel normalisation
+
+// out[c][r] = in[r][c] (rows < rows), zero for rows <= r < ld_out; element
+// types BF16 or FP32 (BF16 -> FP32 is not offered).
+hipError_t transpose_rows(const void* in, bool in_bf16, int rows, int cols, int ld_in, void* out,
+                          bool out_bf16, int ld_out, hipStream_t s);
+// out[c] = sum over rows of in[r][c] (class-token rows skipped when tok is
+// given), via part [ceil(R / kColRows), C] in a fixed order.
+hipError_t colsum(const void* in, bool in_bf16, int R, int C, int ld, const int2* tok,
+                  float* part, float* out, hipStream_t s);
+// dx += LayerNorm backward of rows [R, D]; dgamma, dbeta (overwritten) via
+// partials pg, pb [ceil(R / kLnRows), D].
+hipError_t layernorm_backward(const float* x, const float* g, const float* dy, float eps,
+                              float* dx, int R, int D, float* pg, float* pb, float* dgamma,
+                              float* dbeta, hipStream_t s);
+// g = GELU(z) as the FC1 epilogue forms it (n even); backward dz = dg GELU'(z)
+// with g formed again.
+hipError_t gelu_forward(const float* z, void* g, bool g_bf16, size_t n, hipStream_t s);
+hipError_t gelu_backward(const float* dg, const float* z, void* dz, void* g, bool bf16, size_t n,
+                         hipStream_t s);
+// dQKV [T, 3D] of the attention of every image: items64 are (image, first
+// token) blocks of 64 tokens; lse and dsum [T, heads] are scratch.
+hipError_t attention_backward(const void* qkv, const void* o, bool bf16, const float* dO,
+                              const ImgDesc* imgs, const AttnItem* items64, int n_items,
+                              int heads, int head_dim, void* dqkv, float* lse, float* dsum,
+                              hipStream_t s);
+// Pooling head: de, z [n, *] scratch, the class rows of dX, and the
+// gradients of the projection and the final LayerNorm (pg, pb [n, D] and
+// part [ceil(n / kColRows), D] scratch).
+hipError_t pool_backward(const float* X, const ImgDesc* imgs, int n, const float* e,
+                         const float* demb, const float* proj, const float* g, const float* b,
+                         float eps, int D, int P, float* de, float* z, float* dX, float* pg,
+                         float* pb, float* part, float* d_proj, float* d_lnf_g, float* d_lnf_b,
+                         hipStream_t s);
+// Position table / class token (images at the base grid) and the unfolded
+// patch weights from the folded weights' gradient dwf [D, kpad].
+hipError_t embed_backward(const float* dX, const ImgDesc* imgs, int n, int D, int rows_pos,
+                          const float* dwf, int kpad, const float* db, ChanNorm cn, int kpe,
+                          int pp, float* d_pos, float* d_cls, float* d_patch_w, hipStream_t s);
+hipError_t fill_zero(float* p, size_t n, hipStream_t s);
 
 // Weight preparation.
 hipError_t convert_bf16(const float* src, bf16_t* dst, size_t n, hipStream_t s);

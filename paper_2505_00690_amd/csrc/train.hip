@@ -1,0 +1,651 @@
+// Kernels of contrastive training through the image tower: the pieces the
+// training forward adds (the FC1 activation taken from a kept FP32
+// pre-activation) and the backward pass -- the chain rule of each forward
+// definition:
+//   L2 normalisation  e_hat = e / |e|:  de = (de_hat - e_hat <e_hat, de_hat>) / |e|
+//   LayerNorm (Ba et al. 2016, Sec. 3):  dx = rstd (dxh - mean(dxh) - xh mean(dxh xh)),
+//       dxh = dy * gamma;  dgamma = sum dy xh,  dbeta = sum dy
+//   GELU (Hendrycks & Gimpel 2016):  GELU'(z) = Phi(z) + z phi(z)
+//   attention (Vaswani et al. 2017, Eq. 1):  dV = P^T dO,  dP = dO V^T,
+//       dS = P (dP - rowsum(dO O)),  dQ = dS K / sqrt(d),  dK = dS^T Q / sqrt(d)
+//   patch embedding / class token / position table (ViT Eq. 1).
+// The products of the linear layers run on the GEMM kernels (gemm.hip);
+// here are the transposes that feed them, the deterministic column sums of
+// the bias and LayerNorm gradients (per-block partial sums added in a fixed
+// order), the attention backward and the head / embedding pieces.
+#include "kernels.hpp"
+
+namespace vl {
+
+template <typename T>
+__device__ __forceinline__ float ldf(const T* p, size_t i);
+template <>
+__device__ __forceinline__ float ldf<float>(const float* p, size_t i) { return p[i]; }
+template <>
+__device__ __forceinline__ float ldf<bf16_t>(const bf16_t* p, size_t i) {
+  return bf16_bits_to_f32(p[i]);
+}
+template <typename T>
+__device__ __forceinline__ void stf(T* p, size_t i, float v);
+template <>
+__device__ __forceinline__ void stf<float>(float* p, size_t i, float v) { p[i] = v; }
+template <>
+__device__ __forceinline__ void stf<bf16_t>(bf16_t* p, size_t i, float v) {
+  p[i] = (bf16_t)f32_to_bf16_bits(v);
+}
+
+// ------------------------------------------------------------- transposes
+// out[c][r] = in[r][c] for r < rows, 0 for rows <= r < ld_out (the zero K
+// padding of a weight-gradient GEMM), c < cols.  32 x 32 tiles through LDS.
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_transpose(const TI* __restrict__ in, int rows, int cols,
+                                                   int ld_in, TO* __restrict__ out, int ld_out) {
+  __shared__ float t[32][33];
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k, c = c0 + tx;
+    t[k][tx] = (r < rows && c < cols) ? ldf(in, (size_t)r * ld_in + c) : 0.f;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int c = c0 + k, r = r0 + tx;
+    if (c < cols && r < ld_out) stf(out, (size_t)c * ld_out + r, t[tx][k]);
+  }
+}
+
+hipError_t transpose_rows(const void* in, bool in_bf16, int rows, int cols, int ld_in, void* out,
+                          bool out_bf16, int ld_out, hipStream_t s) {
+  if (cols <= 0 || ld_out <= 0) return hipSuccess;
+  dim3 grid((cols + 31) / 32, (ld_out + 31) / 32), block(256);
+  if (in_bf16 && out_bf16)
+    hipLaunchKernelGGL((k_transpose<bf16_t, bf16_t>), grid, block, 0, s,
+                       static_cast<const bf16_t*>(in), rows, cols, ld_in,
+                       static_cast<bf16_t*>(out), ld_out);
+  else if (!in_bf16 && out_bf16)
+    hipLaunchKernelGGL((k_transpose<float, bf16_t>), grid, block, 0, s,
+                       static_cast<const float*>(in), rows, cols, ld_in,
+                       static_cast<bf16_t*>(out), ld_out);
+  else if (!in_bf16 && !out_bf16)
+    hipLaunchKernelGGL((k_transpose<float, float>), grid, block, 0, s,
+                       static_cast<const float*>(in), rows, cols, ld_in,
+                       static_cast<float*>(out), ld_out);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ column sums
+// part[b][c] = sum of in[r][c] over the rows r of block b (kColRows rows,
+// ascending), skipping class-token rows when tok is given; then out[c] =
+// sum over b ascending.  Fixed order: the result does not depend on timing.
+template <typename T>
+__global__ __launch_bounds__(256) void k_colsum_part(const T* __restrict__ in, int R, int C,
+                                                     int ld, const int2* __restrict__ tok,
+                                                     float* __restrict__ part) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= C) return;
+  const int r0 = blockIdx.y * kColRows, r1 = min(R, r0 + kColRows);
+  float s = 0.f;
+  for (int r = r0; r < r1; ++r) {
+    if (tok && tok[r].y == 0) continue;
+    s += ldf(in, (size_t)r * ld + c);
+  }
+  part[(size_t)blockIdx.y * C + c] = s;
+}
+
+__global__ __launch_bounds__(256) void k_colsum_final(const float* __restrict__ part, int nb,
+                                                      int C, float* __restrict__ out) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= C) return;
+  float s = 0.f;
+  for (int b = 0; b < nb; ++b) s += part[(size_t)b * C + c];
+  out[c] = s;
+}
+
+hipError_t colsum_final(const float* part, int nb, int C, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_colsum_final, dim3((C + 255) / 256), dim3(256), 0, s, part, nb, C, out);
+  return hipGetLastError();
+}
+
+hipError_t colsum(const void* in, bool in_bf16, int R, int C, int ld, const int2* tok,
+                  float* part, float* out, hipStream_t s) {
+  const int nb = (R + kColRows - 1) / kColRows;
+  if (nb <= 0) return hipErrorInvalidValue;
+  dim3 grid((C + 255) / 256, nb), block(256);
+  if (in_bf16)
+    hipLaunchKernelGGL(k_colsum_part<bf16_t>, grid, block, 0, s, static_cast<const bf16_t*>(in),
+                       R, C, ld, tok, part);
+  else
+    hipLaunchKernelGGL(k_colsum_part<float>, grid, block, 0, s, static_cast<const float*>(in), R,
+                       C, ld, tok, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return colsum_final(part, nb, C, out, s);
+}
+
+// -------------------------------------------------------- LayerNorm backward
+// dx[r] += LN'(x[r]) dy[r] for rows r of [R, D] (statistics recomputed from x
+// in FP32 as the forward takes them), and per-block partial sums of
+// dgamma (dy * xh) and dbeta (dy) over the block's kLnRows rows.  One wave
+// per row; the four waves' partials are added in wave order.
+template <int NPER>
+__global__ __launch_bounds__(256) void k_ln_bwd(const float* __restrict__ x,
+                                                const float* __restrict__ gm,
+                                                const float* __restrict__ dy, float eps,
+                                                float* __restrict__ dx, int R,
+                                                float* __restrict__ pg, float* __restrict__ pb) {
+  constexpr int D = NPER * 64;
+  __shared__ float sg[4][D], sb[4][D];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float ag[NPER], ab[NPER];
+#pragma unroll
+  for (int i = 0; i < NPER; ++i) ag[i] = ab[i] = 0.f;
+  for (int rr = w; rr < kLnRows; rr += 4) {
+    const int r = blockIdx.x * kLnRows + rr;
+    if (r >= R) break;
+    const float* xr = x + (size_t)r * D;
+    const float* dr = dy + (size_t)r * D;
+    float v[NPER], d[NPER];
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < NPER; ++i) {
+      v[i] = xr[lane + 64 * i];
+      s += v[i];
+    }
+    const float mean = wave_sum(s) * (1.f / D);
+    float q = 0.f;
+#pragma unroll
+    for (int i = 0; i < NPER; ++i) {
+      v[i] -= mean;
+      q += v[i] * v[i];
+    }
+    const float rstd = rsqrtf(wave_sum(q) * (1.f / D) + eps);
+    float a = 0.f, b = 0.f;
+#pragma unroll
+    for (int i = 0; i < NPER; ++i) {
+      const int c = lane + 64 * i;
+      const float xh = v[i] * rstd;
+      const float g = dr[c];
+      const float dxh = g * gm[c];
+      ag[i] += g * xh;
+      ab[i] += g;
+      a += dxh;
+      b += dxh * xh;
+      v[i] = xh;
+      d[i] = dxh;
+    }
+    a = wave_sum(a) * (1.f / D);
+    b = wave_sum(b) * (1.f / D);
+    float* o = dx + (size_t)r * D;
+#pragma unroll
+    for (int i = 0; i < NPER; ++i) {
+      const int c = lane + 64 * i;
+      o[c] += rstd * (d[i] - a - v[i] * b);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NPER; ++i) {
+    sg[w][lane + 64 * i] = ag[i];
+    sb[w][lane + 64 * i] = ab[i];
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < D; c += 256) {
+    pg[(size_t)blockIdx.x * D + c] = (sg[0][c] + sg[1][c]) + (sg[2][c] + sg[3][c]);
+    pb[(size_t)blockIdx.x * D + c] = (sb[0][c] + sb[1][c]) + (sb[2][c] + sb[3][c]);
+  }
+}
+
+hipError_t layernorm_backward(const float* x, const float* g, const float* dy, float eps,
+                              float* dx, int R, int D, float* pg, float* pb, float* dgamma,
+                              float* dbeta, hipStream_t s) {
+  const int nb = (R + kLnRows - 1) / kLnRows;
+  if (nb <= 0) return hipErrorInvalidValue;
+  dim3 grid(nb), block(256);
+#define VL_LNB(N)                                                                              \
+  case N:                                                                                      \
+    hipLaunchKernelGGL(k_ln_bwd<N>, grid, block, 0, s, x, g, dy, eps, dx, R, pg, pb); break;
+  switch (D / 64) {
+    VL_LNB(2) VL_LNB(4) VL_LNB(6) VL_LNB(8) VL_LNB(10) VL_LNB(12) VL_LNB(14) VL_LNB(16)
+    default: return hipErrorInvalidValue;
+  }
+#undef VL_LNB
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = colsum_final(pg, nb, D, dgamma, s)) != hipSuccess) return e;
+  return colsum_final(pb, nb, D, dbeta, s);
+}
+
+// ------------------------------------------------------------------- GELU
+// Training forward: the FC1 activation from the kept FP32 pre-activation z,
+// exactly as the inference FC1 epilogue forms it (the polynomial Phi rounded
+// to BF16 pairs, or erf in FP32), so both forwards agree bitwise.
+template <bool OUT_BF16>
+__global__ __launch_bounds__(256) void k_gelu_fwd(const float* __restrict__ z, void* __restrict__ g,
+                                                  size_t n2) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n2) return;
+  const float2 v = reinterpret_cast<const float2*>(z)[i];
+  if (OUT_BF16)
+    static_cast<uint32_t*>(g)[i] = pack_bf16x2(gelu_poly(v.x), gelu_poly(v.y));
+  else
+    static_cast<float2*>(g)[i] = make_float2(gelu_erf(v.x), gelu_erf(v.y));
+}
+
+hipError_t gelu_forward(const float* z, void* g, bool g_bf16, size_t n, hipStream_t s) {
+  const size_t n2 = n / 2;  // n is even (the MLP width is a multiple of 128)
+  dim3 grid((unsigned)((n2 + 255) / 256)), block(256);
+  if (g_bf16) hipLaunchKernelGGL(k_gelu_fwd<true>, grid, block, 0, s, z, g, n2);
+  else hipLaunchKernelGGL(k_gelu_fwd<false>, grid, block, 0, s, z, g, n2);
+  return hipGetLastError();
+}
+
+// Backward: dz = dg (Phi(z) + z phi(z)), and the activation itself again
+// (g, as the forward formed it) for the weight gradient of FC2.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gelu_bwd(const float* __restrict__ dg,
+                                                  const float* __restrict__ z, T* __restrict__ dz,
+                                                  T* __restrict__ g, size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float v = z[i];
+  const float phi = 0.3989422804014327f * expf(-0.5f * v * v);
+  const float cdf = 0.5f * (1.0f + erff(v * 0.70710678118654752f));
+  stf(dz, i, dg[i] * (cdf + v * phi));
+  constexpr bool BF = sizeof(T) == 2;
+  stf(g, i, BF ? gelu_poly(v) : gelu_erf(v));
+}
+
+hipError_t gelu_backward(const float* dg, const float* z, void* dz, void* g, bool bf16, size_t n,
+                         hipStream_t s) {
+  dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  if (bf16)
+    hipLaunchKernelGGL(k_gelu_bwd<bf16_t>, grid, block, 0, s, dg, z, static_cast<bf16_t*>(dz),
+                       static_cast<bf16_t*>(g), n);
+  else
+    hipLaunchKernelGGL(k_gelu_bwd<float>, grid, block, 0, s, dg, z, static_cast<float*>(dz),
+                       static_cast<float*>(g), n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- attention backward
+// Tiles of 64 queries x 64 keys of one (image, head).  Thread t of a 256-wide
+// workgroup owns row t / 4 of the tile and the quarter t % 4 of its columns;
+// scores are recomputed from Q and K in FP32 (BF16 operands are widened).
+// dq pass: per 64-query block, first the row maximum and sum of
+// exponentials over all keys (log-sum-exp), then dQ; it also writes the
+// log-sum-exp and D = rowsum(dO * O) for the dk/dv pass, which walks all
+// query blocks per 64-key block.  No atomics: every output has one writer.
+constexpr int AB = 64;
+
+template <typename T, int HD>
+__global__ __launch_bounds__(256) void k_attn_bwd_dq(const T* __restrict__ qkv,
+                                                     const T* __restrict__ o,
+                                                     const float* __restrict__ dO,
+                                                     const ImgDesc* __restrict__ imgs,
+                                                     const AttnItem* __restrict__ items, int heads,
+                                                     T* __restrict__ dqkv, float* __restrict__ lse,
+                                                     float* __restrict__ dsum) {
+  constexpr int LD = HD + 1, KQ = HD / 4;
+  __shared__ float sQ[AB][LD], sdO[AB][LD], sK[AB][LD], sV[AB][LD], sS[AB][AB + 1];
+  const AttnItem it = items[blockIdx.x];
+  const int h = blockIdx.y;
+  const ImgDesc d = imgs[it.img];
+  const int N = d.ntok, base = d.tok_start;
+  const int DM = heads * HD, D3 = 3 * DM;
+  const float scale = 1.0f / sqrtf((float)HD);
+  const int tid = threadIdx.x, r = tid >> 2, cq = tid & 3;
+  const int nq = min(AB, N - it.q0);
+  for (int i = tid; i < AB * HD; i += 256) {
+    const int rr = i / HD, k = i - rr * HD;
+    const bool ok = rr < nq;
+    const size_t row = (size_t)(base + it.q0 + rr);
+    sQ[rr][k] = ok ? ldf(qkv, row * D3 + h * HD + k) : 0.f;
+    sdO[rr][k] = ok ? dO[row * DM + h * HD + k] : 0.f;
+    sV[rr][k] = ok ? ldf(o, row * DM + h * HD + k) : 0.f;   // O, for D
+  }
+  __syncthreads();
+  float dsv = 0.f;
+#pragma unroll
+  for (int k = 0; k < KQ; ++k) dsv += sdO[r][cq * KQ + k] * sV[r][cq * KQ + k];
+  dsv += __shfl_xor(dsv, 1);
+  dsv += __shfl_xor(dsv, 2);
+  __syncthreads();
+  auto load_kv = [&](int k0, int nk, bool with_v) {
+    for (int i = tid; i < AB * HD; i += 256) {
+      const int rr = i / HD, k = i - rr * HD;
+      const size_t row = (size_t)(base + k0 + rr);
+      sK[rr][k] = rr < nk ? ldf(qkv, row * D3 + DM + h * HD + k) : 0.f;
+      if (with_v) sV[rr][k] = rr < nk ? ldf(qkv, row * D3 + 2 * DM + h * HD + k) : 0.f;
+    }
+  };
+  // pass 1: log-sum-exp of the row over all keys of the image
+  float mrow = -INFINITY, lrow = 0.f;
+  for (int k0 = 0; k0 < N; k0 += AB) {
+    const int nk = min(AB, N - k0);
+    load_kv(k0, nk, false);
+    __syncthreads();
+    float sc[16];
+    float tmax = -INFINITY;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int c = cq * 16 + j;
+      float a = 0.f;
+#pragma unroll
+      for (int k = 0; k < HD; ++k) a += sQ[r][k] * sK[c][k];
+      sc[j] = c < nk ? a * scale : -INFINITY;
+      tmax = fmaxf(tmax, sc[j]);
+    }
+    tmax = fmaxf(tmax, __shfl_xor(tmax, 1));
+    tmax = fmaxf(tmax, __shfl_xor(tmax, 2));
+    const float mnew = fmaxf(mrow, tmax);
+    float ts = 0.f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) ts += expf(sc[j] - mnew);
+    ts += __shfl_xor(ts, 1);
+    ts += __shfl_xor(ts, 2);
+    lrow = lrow * expf(mrow - mnew) + ts;
+    mrow = mnew;
+    __syncthreads();
+  }
+  const float lse_r = mrow + logf(lrow);
+  // pass 2: dS and dQ
+  float dq[KQ];
+#pragma unroll
+  for (int k = 0; k < KQ; ++k) dq[k] = 0.f;
+  for (int k0 = 0; k0 < N; k0 += AB) {
+    const int nk = min(AB, N - k0);
+    load_kv(k0, nk, true);
+    __syncthreads();
+#pragma unroll 4
+    for (int j = 0; j < 16; ++j) {
+      const int c = cq * 16 + j;
+      float a = 0.f, b = 0.f;
+#pragma unroll
+      for (int k = 0; k < HD; ++k) {
+        a += sQ[r][k] * sK[c][k];
+        b += sdO[r][k] * sV[c][k];
+      }
+      const float p = c < nk ? expf(a * scale - lse_r) : 0.f;
+      sS[r][c] = p * (b - dsv);
+    }
+    __syncthreads();
+    for (int c = 0; c < nk; ++c) {
+      const float ds = sS[r][c];
+#pragma unroll
+      for (int k = 0; k < KQ; ++k) dq[k] += ds * sK[c][cq * KQ + k];
+    }
+    __syncthreads();
+  }
+  if (r < nq) {
+    const size_t row = (size_t)(base + it.q0 + r);
+#pragma unroll
+    for (int k = 0; k < KQ; ++k) stf(dqkv, row * D3 + h * HD + cq * KQ + k, dq[k] * scale);
+    if (cq == 0) {
+      lse[row * heads + h] = lse_r;
+      dsum[row * heads + h] = dsv;
+    }
+  }
+}
+
+template <typename T, int HD>
+__global__ __launch_bounds__(256) void k_attn_bwd_dkv(const T* __restrict__ qkv,
+                                                      const float* __restrict__ dO,
+                                                      const ImgDesc* __restrict__ imgs,
+                                                      const AttnItem* __restrict__ items, int heads,
+                                                      const float* __restrict__ lse,
+                                                      const float* __restrict__ dsum,
+                                                      T* __restrict__ dqkv) {
+  constexpr int LD = HD + 1, KQ = HD / 4;
+  __shared__ float sK[AB][LD], sV[AB][LD], sQ[AB][LD], sdO[AB][LD];
+  __shared__ float sP[AB][AB + 1], sDS[AB][AB + 1], sL[AB], sD[AB];
+  const AttnItem it = items[blockIdx.x];   // it.q0: first key of the block
+  const int h = blockIdx.y;
+  const ImgDesc d = imgs[it.img];
+  const int N = d.ntok, base = d.tok_start;
+  const int DM = heads * HD, D3 = 3 * DM;
+  const float scale = 1.0f / sqrtf((float)HD);
+  const int tid = threadIdx.x, c = tid >> 2, rq = tid & 3;
+  const int nk = min(AB, N - it.q0);
+  for (int i = tid; i < AB * HD; i += 256) {
+    const int rr = i / HD, k = i - rr * HD;
+    const size_t row = (size_t)(base + it.q0 + rr);
+    sK[rr][k] = rr < nk ? ldf(qkv, row * D3 + DM + h * HD + k) : 0.f;
+    sV[rr][k] = rr < nk ? ldf(qkv, row * D3 + 2 * DM + h * HD + k) : 0.f;
+  }
+  float dk[KQ], dv[KQ];
+#pragma unroll
+  for (int k = 0; k < KQ; ++k) dk[k] = dv[k] = 0.f;
+  for (int q0 = 0; q0 < N; q0 += AB) {
+    const int nq = min(AB, N - q0);
+    for (int i = tid; i < AB * HD; i += 256) {
+      const int rr = i / HD, k = i - rr * HD;
+      const size_t row = (size_t)(base + q0 + rr);
+      sQ[rr][k] = rr < nq ? ldf(qkv, row * D3 + h * HD + k) : 0.f;
+      sdO[rr][k] = rr < nq ? dO[row * DM + h * HD + k] : 0.f;
+    }
+    if (tid < AB) {
+      const size_t row = (size_t)(base + q0 + tid);
+      sL[tid] = tid < nq ? lse[row * heads + h] : 0.f;
+      sD[tid] = tid < nq ? dsum[row * heads + h] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int j = 0; j < 16; ++j) {
+      const int r = rq * 16 + j;
+      float a = 0.f, b = 0.f;
+#pragma unroll
+      for (int k = 0; k < HD; ++k) {
+        a += sQ[r][k] * sK[c][k];
+        b += sdO[r][k] * sV[c][k];
+      }
+      const bool ok = r < nq && c < nk;
+      const float p = ok ? expf(a * scale - sL[r]) : 0.f;
+      sP[c][r] = p;
+      sDS[c][r] = p * (b - sD[r]);
+    }
+    __syncthreads();
+    for (int r = 0; r < nq; ++r) {
+      const float p = sP[c][r], ds = sDS[c][r];
+#pragma unroll
+      for (int k = 0; k < KQ; ++k) {
+        dv[k] += p * sdO[r][rq * KQ + k];
+        dk[k] += ds * sQ[r][rq * KQ + k];
+      }
+    }
+    __syncthreads();
+  }
+  if (c < nk) {
+    const size_t row = (size_t)(base + it.q0 + c);
+#pragma unroll
+    for (int k = 0; k < KQ; ++k) {
+      stf(dqkv, row * D3 + DM + h * HD + rq * KQ + k, dk[k] * scale);
+      stf(dqkv, row * D3 + 2 * DM + h * HD + rq * KQ + k, dv[k]);
+    }
+  }
+}
+
+template <typename T, int HD>
+static void launch_attn_bwd(const void* qkv, const void* o, const float* dO, const ImgDesc* imgs,
+                            const AttnItem* items, int n_items, int heads, void* dqkv, float* lse,
+                            float* dsum, hipStream_t s) {
+  dim3 grid(n_items, heads), block(256);
+  hipLaunchKernelGGL((k_attn_bwd_dq<T, HD>), grid, block, 0, s, static_cast<const T*>(qkv),
+                     static_cast<const T*>(o), dO, imgs, items, heads, static_cast<T*>(dqkv), lse,
+                     dsum);
+  hipLaunchKernelGGL((k_attn_bwd_dkv<T, HD>), grid, block, 0, s, static_cast<const T*>(qkv), dO,
+                     imgs, items, heads, lse, dsum, static_cast<T*>(dqkv));
+}
+
+hipError_t attention_backward(const void* qkv, const void* o, bool bf16, const float* dO,
+                              const ImgDesc* imgs, const AttnItem* items64, int n_items,
+                              int heads, int head_dim, void* dqkv, float* lse, float* dsum,
+                              hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (head_dim == 64) {
+    if (bf16) launch_attn_bwd<bf16_t, 64>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s);
+    else launch_attn_bwd<float, 64>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s);
+  } else if (head_dim == 32) {
+    if (bf16) launch_attn_bwd<bf16_t, 32>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s);
+    else launch_attn_bwd<float, 32>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ pooling head backward
+// One workgroup per image: from the kept pre-normalisation embedding e and
+// the embedding gradient, de; the class token's final LayerNorm recomputed
+// (z, xh); dz = W_p^T de; the class row of dX; and the image's terms of the
+// final LayerNorm's parameter gradients (dz * xh, dz), summed over images
+// afterwards in image order.  D <= 1024 (four columns per thread), P <= 1024.
+__global__ __launch_bounds__(256) void k_pool_bwd(const float* __restrict__ X,
+                                                  const ImgDesc* __restrict__ imgs,
+                                                  const float* __restrict__ e,
+                                                  const float* __restrict__ demb,
+                                                  const float* __restrict__ proj,
+                                                  const float* __restrict__ gm,
+                                                  const float* __restrict__ bt, float eps, int D,
+                                                  int P, float* __restrict__ de_out,
+                                                  float* __restrict__ z_out,
+                                                  float* __restrict__ dX, float* __restrict__ pg,
+                                                  float* __restrict__ pb) {
+  __shared__ float red[4];
+  __shared__ float sde[1024];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const float* er = e + (size_t)i * P;
+  const float* dr = demb + (size_t)i * P;
+  auto sum = [](float a, float b) { return a + b; };
+  float n2 = 0.f, dot = 0.f;
+  for (int p = tid; p < P; p += 256) {
+    n2 += er[p] * er[p];
+    dot += er[p] * dr[p];
+  }
+  n2 = block_reduce(n2, red, sum);
+  dot = block_reduce(dot, red, sum);
+  const float inv = 1.f / fmaxf(sqrtf(n2), 1e-12f);
+  const float ehd = dot * inv;   // <e_hat, d e_hat>
+  for (int p = tid; p < P; p += 256) {
+    const float v = (dr[p] - er[p] * inv * ehd) * inv;
+    sde[p] = v;
+    de_out[(size_t)i * P + p] = v;
+  }
+  __syncthreads();
+  const ImgDesc d = imgs[i];
+  const float* xr = X + (size_t)d.tok_start * D;
+  float s = 0.f;
+  for (int c = tid; c < D; c += 256) s += xr[c];
+  const float mean = block_reduce(s, red, sum) / D;
+  float q = 0.f;
+  for (int c = tid; c < D; c += 256) {
+    const float v = xr[c] - mean;
+    q += v * v;
+  }
+  const float rstd = rsqrtf(block_reduce(q, red, sum) / D + eps);
+  float xh[4], dz[4];
+  float a = 0.f, b = 0.f;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = tid + 256 * j;
+    xh[j] = dz[j] = 0.f;
+    if (c >= D) continue;
+    xh[j] = (xr[c] - mean) * rstd;
+    z_out[(size_t)i * D + c] = xh[j] * gm[c] + bt[c];
+    float acc = 0.f;
+    for (int p = 0; p < P; ++p) acc += proj[(size_t)p * D + c] * sde[p];
+    dz[j] = acc;
+    const float dxh = acc * gm[c];
+    a += dxh;
+    b += dxh * xh[j];
+  }
+  a = block_reduce(a, red, sum) / D;
+  b = block_reduce(b, red, sum) / D;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = tid + 256 * j;
+    if (c >= D) continue;
+    dX[(size_t)d.tok_start * D + c] = rstd * (dz[j] * gm[c] - a - xh[j] * b);
+    pg[(size_t)i * D + c] = dz[j] * xh[j];
+    pb[(size_t)i * D + c] = dz[j];
+  }
+}
+
+// dW_p[p][c] = sum over images (ascending) of de[i][p] z[i][c].
+__global__ __launch_bounds__(256) void k_outer_sum(const float* __restrict__ de,
+                                                   const float* __restrict__ z, int n, int P,
+                                                   int D, float* __restrict__ out) {
+  const int c = blockIdx.x * 256 + threadIdx.x, p = blockIdx.y;
+  if (c >= D) return;
+  float s = 0.f;
+  for (int i = 0; i < n; ++i) s += de[(size_t)i * P + p] * z[(size_t)i * D + c];
+  out[(size_t)p * D + c] = s;
+}
+
+hipError_t pool_backward(const float* X, const ImgDesc* imgs, int n, const float* e,
+                         const float* demb, const float* proj, const float* g, const float* b,
+                         float eps, int D, int P, float* de, float* z, float* dX, float* pg,
+                         float* pb, float* part, float* d_proj, float* d_lnf_g, float* d_lnf_b,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_pool_bwd, dim3(n), dim3(256), 0, s, X, imgs, e, demb, proj, g, b, eps, D,
+                     P, de, z, dX, pg, pb);
+  hipLaunchKernelGGL(k_outer_sum, dim3((D + 255) / 256, P), dim3(256), 0, s, de, z, n, P, D,
+                     d_proj);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  if ((err = colsum(pg, false, n, D, D, nullptr, part, d_lnf_g, s)) != hipSuccess) return err;
+  return colsum(pb, false, n, D, D, nullptr, part, d_lnf_b, s);
+}
+
+// ------------------------------------------------- token embedding backward
+// Position table rows (images at the base grid, so token j of every image
+// uses row j): dpos[j] = sum over images of dX[tok_start + j]; row 0 is also
+// the class token's gradient.
+__global__ __launch_bounds__(256) void k_pos_grad(const float* __restrict__ dX,
+                                                  const ImgDesc* __restrict__ imgs, int n, int D,
+                                                  float* __restrict__ dpos,
+                                                  float* __restrict__ dcls) {
+  const int c = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+  if (c >= D) return;
+  float s = 0.f;
+  for (int i = 0; i < n; ++i) s += dX[(size_t)(imgs[i].tok_start + j) * D + c];
+  dpos[(size_t)j * D + c] = s;
+  if (j == 0) dcls[c] = s;
+}
+
+// Patch weights: the forward multiplies raw pixels by W / std (folded), so
+// dW[d][k] = (dWf[d][k] - mean_c db[d]) / std_c with c = k / (P*P), where dWf
+// is the gradient of the folded weights and db that of the patch bias.
+__global__ __launch_bounds__(256) void k_patch_w_grad(const float* __restrict__ dwf, int kpad,
+                                                      const float* __restrict__ db, ChanNorm cn,
+                                                      int kpe, int pp, int D,
+                                                      float* __restrict__ out) {
+  const int k = blockIdx.x * 256 + threadIdx.x, dd = blockIdx.y;
+  if (k >= kpe || dd >= D) return;
+  const int c = k / pp;
+  out[(size_t)dd * kpe + k] = (dwf[(size_t)dd * kpad + k] - cn.mean[c] * db[dd]) / cn.std[c];
+}
+
+hipError_t embed_backward(const float* dX, const ImgDesc* imgs, int n, int D, int rows_pos,
+                          const float* dwf, int kpad, const float* db, ChanNorm cn, int kpe,
+                          int pp, float* d_pos, float* d_cls, float* d_patch_w, hipStream_t s) {
+  hipLaunchKernelGGL(k_pos_grad, dim3((D + 255) / 256, rows_pos), dim3(256), 0, s, dX, imgs, n, D,
+                     d_pos, d_cls);
+  hipLaunchKernelGGL(k_patch_w_grad, dim3((kpe + 255) / 256, D), dim3(256), 0, s, dwf, kpad, db,
+                     cn, kpe, pp, D, d_patch_w);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------- misc
+__global__ __launch_bounds__(256) void k_fill_zero(float* __restrict__ p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
+hipError_t fill_zero(float* p, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace vl

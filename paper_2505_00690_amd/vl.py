@@ -28,6 +28,7 @@ __all__ = [
     "POOLS", "vl_contrastive_workspace_bytes", "vl_contrastive_loss",
     "vl_attention_workspace_bytes", "vl_attention", "vl_model_save_tuning",
     "vl_model_load_tuning", "vl_contrastive_loss_noalloc", "VL_NOALLOC_SCRATCH_BYTES",
+    "vl_train_workspace_bytes", "vl_encode_images_train", "vl_encode_images_backward", "Trainer",
 ]
 
 VL_FP32, VL_BF16, VL_FP8W_BF16A, VL_MXFP8 = 0, 1, 2, 3
@@ -50,7 +51,8 @@ EXPORTED_SYMBOLS = (
     "vl_contrastive_loss", "vl_attention_workspace_bytes", "vl_attention",
     "vl_gemm_config_count", "vl_gemm_config_name", "vl_model_get_tuning",
     "vl_model_set_tuning", "vl_model_autotune", "vl_model_save_tuning", "vl_model_load_tuning",
-    "vl_contrastive_loss_noalloc",
+    "vl_contrastive_loss_noalloc", "vl_train_workspace_bytes", "vl_encode_images_train",
+    "vl_encode_images_backward",
 )
 VL_NOALLOC_SCRATCH_BYTES = 64 << 20
 VL_N_GEMM_OPS, VL_N_M_BUCKETS = 5, 25
@@ -167,6 +169,13 @@ def lib() -> ctypes.CDLL:
     L.vl_contrastive_loss.restype = ctypes.c_int
     L.vl_contrastive_loss.argtypes = [_vp, _vp, _i32, _i32, ctypes.c_int, _f32, _f32, _vp, _vp,
                                       _vp, _vp, _vp, _sz, _vp]
+    L.vl_train_workspace_bytes.restype = _sz
+    L.vl_train_workspace_bytes.argtypes = [_vp, _i32, _pi32, _pi32]
+    L.vl_encode_images_train.restype = ctypes.c_int
+    L.vl_encode_images_train.argtypes = [_vp, _vp, _pi32, _pi32, _i32, _vp, _vp, _sz, _vp]
+    L.vl_encode_images_backward.restype = ctypes.c_int
+    L.vl_encode_images_backward.argtypes = [_vp, _vp, _pi32, _pi32, _i32, _vp, _vp, _vp, _sz,
+                                            _vp]
     L.vl_contrastive_loss_noalloc.restype = ctypes.c_int
     L.vl_contrastive_loss_noalloc.argtypes = [_vp, _vp, _i32, _i32, ctypes.c_int, _f32, _f32,
                                               _vp, _vp, _vp, _vp, _vp]
@@ -499,6 +508,38 @@ def vl_mx_gemm(a: torch.Tensor, sa: torch.Tensor, b: torch.Tensor, sb: torch.Ten
                             int(cfg), _stream(stream)))
 
 
+def vl_train_workspace_bytes(handle, heights: Sequence[int], widths: Sequence[int]) -> int:
+    return int(lib().vl_train_workspace_bytes(handle, len(heights), _i32_array(heights),
+                                              _i32_array(widths)))
+
+
+def vl_encode_images_train(handle, pixels: torch.Tensor, heights: Sequence[int],
+                           widths: Sequence[int], emb_out: torch.Tensor, workspace: torch.Tensor,
+                           stream=None, channels: int = 3, proj_dim=None) -> None:
+    _check_encode_args(pixels, heights, widths, emb_out, channels, proj_dim)
+    _check(lib().vl_encode_images_train(handle, _ptr(pixels, torch.float32, "pixels"),
+                                        _i32_array(heights), _i32_array(widths), len(heights),
+                                        _ptr(emb_out, torch.float32, "emb_out"),
+                                        _ptr(workspace, None, "workspace"),
+                                        workspace.numel() * workspace.element_size(),
+                                        _stream(stream)))
+
+
+def vl_encode_images_backward(handle, pixels: torch.Tensor, heights: Sequence[int],
+                              widths: Sequence[int], d_emb: torch.Tensor, grads_out: torch.Tensor,
+                              workspace: torch.Tensor, n_weights: int, stream=None,
+                              channels: int = 3, proj_dim=None) -> None:
+    _check_encode_args(pixels, heights, widths, d_emb, channels, proj_dim)
+    _need(grads_out, "grads_out", dtype=torch.float32, numel=int(n_weights))
+    _check(lib().vl_encode_images_backward(handle, _ptr(pixels, torch.float32, "pixels"),
+                                           _i32_array(heights), _i32_array(widths), len(heights),
+                                           _ptr(d_emb, torch.float32, "d_emb"),
+                                           _ptr(grads_out, torch.float32, "grads_out"),
+                                           _ptr(workspace, None, "workspace"),
+                                           workspace.numel() * workspace.element_size(),
+                                           _stream(stream)))
+
+
 class Encoder:
     """Owns a model handle built from an FP32 weight blob on the device, plus
     a reusable workspace tensor."""
@@ -625,3 +666,38 @@ class TextEncoder:
             self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
         vl_encode_texts(self.handle, ids, lengths, out, self._ws, stream)
         return out
+
+
+class Trainer(Encoder):
+    """An Encoder that also runs the training forward and the backward pass
+    (FP32 or BF16 models, class-token pooling, images at the base grid)."""
+
+    def train_workspace_bytes(self, sizes: Sequence[Tuple[int, int]]) -> int:
+        return vl_train_workspace_bytes(self.handle, [h for h, _ in sizes],
+                                        [w for _, w in sizes])
+
+    def forward(self, pixels: torch.Tensor, sizes: Sequence[Tuple[int, int]],
+                out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        n = len(sizes)
+        if out is None:
+            out = torch.empty((n, self.cfg.proj_dim), dtype=torch.float32, device=self.device)
+        need = self.train_workspace_bytes(sizes)
+        if need == 0:
+            raise VlError(1, "batch not supported for training")
+        ws = self.workspace(need)
+        vl_encode_images_train(self.handle, pixels, [h for h, _ in sizes], [w for _, w in sizes],
+                               out, ws, stream, channels=self._channels,
+                               proj_dim=self.cfg.proj_dim)
+        return out
+
+    def backward(self, pixels: torch.Tensor, sizes: Sequence[Tuple[int, int]],
+                 d_emb: torch.Tensor, grads_out: Optional[torch.Tensor] = None,
+                 stream=None) -> torch.Tensor:
+        nw = vl_weights_count(self.cfg)
+        if grads_out is None:
+            grads_out = torch.empty(nw, dtype=torch.float32, device=self.device)
+        ws = self.workspace(self.train_workspace_bytes(sizes))
+        vl_encode_images_backward(self.handle, pixels, [h for h, _ in sizes],
+                                  [w for _, w in sizes], d_emb, grads_out, ws, nw, stream,
+                                  channels=self._channels, proj_dim=self.cfg.proj_dim)
+        return grads_out

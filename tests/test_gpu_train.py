@@ -1,0 +1,159 @@
+"""GPU parity of contrastive training through the image tower: the training
+forward against the inference forward (bitwise), and every weight gradient of
+the backward pass against the FP64 oracle's chain rule (oracle/train64.py) on
+the same seeded inputs, with dL/d(embedding) from the library's contrastive
+loss fed to both.
+
+Bars: FP32 -- per tensor, max |g - g_ref| <= 1e-4 max |g_ref|; BF16 -- per
+tensor cosine >= 0.999 against the oracle on the exact BF16 weights."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import train64 as TR
+from oracle import vit64 as O
+
+from helpers import pack
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def V():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_00690_amd import vl
+    vl.lib()
+    return vl
+
+
+# 65 tokens per image (8 x 8 patches + class token): two 64-token attention
+# blocks, the second a one-token tail.
+SMALL = synth.ModelConfig("train_small", patch=8, width=128, layers=2, heads=4, mlp=512,
+                          proj_dim=64, base_grid=8)
+SMALL_HD64 = synth.ModelConfig("train_small64", patch=8, width=128, layers=1, heads=2, mlp=256,
+                               proj_dim=64, base_grid=8)
+# one ViT-L/14-shaped block at 336 px: 577 tokens, width 1024, 16 heads
+L14_1 = synth.ModelConfig("l14_1block", patch=14, width=1024, layers=1, heads=16, mlp=4096,
+                          proj_dim=768, base_grid=24)
+
+
+def _run(V, cfg, seed, sizes, precision, std):
+    p = synth.make_params(cfg, seed, std=std)
+    blob = torch.from_numpy(synth.params_to_blob(cfg, p)).cuda()
+    tr = V.Trainer(cfg, blob, precision)
+    imgs = synth.make_images(sizes, seed + 1)
+    pix = torch.from_numpy(pack(imgs)).cuda()
+    _say(f"train {cfg.name} {precision} n={len(sizes)} size={sizes[0]}")
+    emb = tr.forward(pix, sizes).clone()
+    texts = torch.from_numpy(synth.make_texts(len(sizes), cfg.proj_dim, seed + 2)).cuda()
+    _, de, _, _ = V.vl_contrastive_loss(emb, texts, "sigmoid", 10.0, -10.0)
+    grads = tr.backward(pix, sizes, de)
+    torch.cuda.synchronize()
+    de64 = de.cpu().numpy().astype(np.float64)
+    pw = O.weights_for(p, precision)
+    ref = TR.flatten_grads(TR.encode_backward(imgs, pw, cfg, de64), cfg, synth.weight_layout(cfg))
+    got = grads.cpu().numpy().astype(np.float64)
+    emb_ref = O.encode(imgs, pw, cfg)
+    tr.close()
+    return got, ref, emb.cpu().numpy(), emb_ref
+
+
+def _per_tensor(cfg, got, ref):
+    o = 0
+    for name, shape in synth.weight_layout(cfg):
+        n = int(np.prod(shape))
+        yield name, got[o:o + n], ref[o:o + n]
+        o += n
+
+
+def _check_fp32(cfg, got, ref):
+    worst = 0.0
+    for name, g, r in _per_tensor(cfg, got, ref):
+        scale = np.abs(r).max()
+        assert scale > 0, name
+        err = np.abs(g - r).max() / scale
+        worst = max(worst, err)
+        assert err <= 1e-4, (name, err)
+    _say(f"  fp32 worst per-tensor relative error {worst:.2e}")
+
+
+def _check_bf16(cfg, got, ref):
+    worst = 1.0
+    for name, g, r in _per_tensor(cfg, got, ref):
+        cos = float(g @ r / (np.linalg.norm(g) * np.linalg.norm(r)))
+        worst = min(worst, cos)
+        assert cos >= 0.999, (name, cos)
+    _say(f"  bf16 worst per-tensor cosine {worst:.6f}")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_train_forward_equals_inference_bitwise(V, precision):
+    """The training forward keeps activations but runs the same kernels with
+    the same arithmetic: embeddings equal vl_encode_images bit for bit."""
+    p = synth.make_params(SMALL, 60, std=0.1)
+    blob = torch.from_numpy(synth.params_to_blob(SMALL, p)).cuda()
+    sizes = [(64, 64)] * 5
+    pix = torch.from_numpy(pack(synth.make_images(sizes, 61))).cuda()
+    tr = V.Trainer(SMALL, blob, precision)
+    a = tr.forward(pix, sizes).clone()
+    b = tr.encode(pix, sizes).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    tr.close()
+
+
+@pytest.mark.parametrize("cfg,std", [(SMALL, 0.1), (SMALL_HD64, 0.2)])
+def test_backward_fp32_small(V, cfg, std):
+    """Every weight gradient, FP32, head width 32 and 64, 65-token images
+    (a ragged attention tile), 5 images (ragged token count)."""
+    got, ref, emb, emb_ref = _run(V, cfg, 62, [(64, 64)] * 5, "fp32", std)
+    assert np.abs(emb - emb_ref).max() <= 1e-4
+    _check_fp32(cfg, got, ref)
+
+
+@pytest.mark.parametrize("cfg,std", [(SMALL, 0.1), (SMALL_HD64, 0.2)])
+def test_backward_bf16_small(V, cfg, std):
+    got, ref, _, _ = _run(V, cfg, 63, [(64, 64)] * 5, "bf16", std)
+    _check_bf16(cfg, got, ref)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_backward_l14_one_block(V, precision):
+    """One ViT-L/14-shaped block at 336 px (577 tokens, ten 64-token
+    attention blocks per image), two images, N(0, 0.02^2) weights."""
+    got, ref, _, _ = _run(V, L14_1, 64, [(336, 336)] * 2, precision, 0.02)
+    if precision == "fp32":
+        _check_fp32(L14_1, got, ref)
+    else:
+        _check_bf16(L14_1, got, ref)
+
+
+def test_backward_needs_matching_train_call(V):
+    p = synth.make_params(SMALL, 65, std=0.1)
+    blob = torch.from_numpy(synth.params_to_blob(SMALL, p)).cuda()
+    tr = V.Trainer(SMALL, blob, "fp32")
+    sizes = [(64, 64)] * 2
+    pix = torch.from_numpy(pack(synth.make_images(sizes, 66))).cuda()
+    de = torch.zeros((2, SMALL.proj_dim), dtype=torch.float32, device="cuda")
+    with pytest.raises(V.VlError):
+        tr.backward(pix, sizes, de)                      # no training forward yet
+    tr.forward(pix, sizes)
+    with pytest.raises(V.VlError):
+        tr.backward(pix, [(64, 64)] * 1, de[:1])         # other shapes
+    pix2 = torch.zeros(3 * (80 * 64 + 64 * 64), dtype=torch.float32, device="cuda")
+    with pytest.raises(V.VlError):
+        tr.forward(pix2, [(80, 64), (64, 64)])           # not the base grid
+    tr.close()
+    mx = V.Trainer(SMALL, blob, "fp8w")
+    with pytest.raises(V.VlError) as ei:
+        mx.forward(pix, sizes)
+    mx.close()
