@@ -233,6 +233,71 @@ def rgbd_leg(torch, vl, steps: int, n_env: int = 256, w_seed: int = 1006, i_seed
             "tflops": flops / (ms / 1e3) / 1e12, "steps": steps, "two_part_split": split}
 
 
+def train_leg(torch, vl, steps: int, model: str = "l14", res: int = 336, batch: int = 32,
+              w_seed: int = 1002, i_seed: int = 2002, t_seed: int = 3007):
+    """Contrastive training step through the image tower: the training
+    forward (activations kept), the sigmoid loss of the batch against its
+    matched texts (SigLIP, scale 10, bias -10) with its embedding gradient,
+    and the backward pass to every weight gradient; BF16 operands, FP32
+    accumulation.  The optimizer update is the caller's and is not timed.
+    FLOPs credited: 3x the forward's (the usual training count; the score
+    recomputations of the attention backward are not credited)."""
+    c = synth.MODELS[model]
+    w = torch.from_numpy(synth.make_blob(c, w_seed)).cuda()
+    sizes = [(res, res)] * batch
+    imgs = synth.make_images(sizes, i_seed, channels=c.channels)
+    pix = torch.from_numpy(np.concatenate([im.reshape(-1) for im in imgs])).cuda()
+    texts = torch.from_numpy(synth.make_texts(batch, c.proj_dim, t_seed)).cuda()
+    tr = vl.Trainer(c, w, "bf16")
+    del w
+    emb = torch.empty((batch, c.proj_dim), dtype=torch.float32, device="cuda")
+    grads = torch.empty(vl.vl_weights_count(c), dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    de = torch.empty_like(emb)
+    dt = torch.empty_like(texts)
+    dsb = torch.empty(2, dtype=torch.float32, device="cuda")
+
+    def step(evs=None):
+        if evs:
+            evs[0].record()
+        tr.forward(pix, sizes, out=emb)
+        if evs:
+            evs[1].record()
+        vl.vl_contrastive_loss_noalloc(emb, texts, "sigmoid", 10.0, -10.0, loss, de, dt, dsb)
+        if evs:
+            evs[2].record()
+        tr.backward(pix, sizes, de, grads_out=grads)
+        if evs:
+            evs[3].record()
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    ph = np.zeros(3)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(steps):
+        step()
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / steps
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    step(evs)
+    torch.cuda.synchronize()
+    for k in range(3):
+        ph[k] = evs[k].elapsed_time(evs[k + 1])
+    flops = 3.0 * batch * flops_per_image(c, res)
+    g = grads.cpu().numpy()
+    tr.close()
+    return {"value": batch / (ms / 1e3), "unit": "images/s", "ms_per_step": ms,
+            "model": c.name, "resolution": res, "batch": batch, "precision": "bf16",
+            "loss": "sigmoid (scale 10, bias -10), matched random texts",
+            "ms_forward": ph[0], "ms_loss": ph[1], "ms_backward": ph[2],
+            "tflops_3x_forward": flops / (ms / 1e3) / 1e12,
+            "grads_finite": bool(np.isfinite(g).all()), "steps": steps,
+            "loss_value": float(loss.item())}
+
+
 def serving_leg(torch, vl, n_requests: int, warmup_requests: int, slots: int,
                 budget_gib: float, max_batch_images: int):
     """The serving workload: ViT-L/14 with e4m3 per-row weights and BF16
@@ -321,6 +386,9 @@ def main(argv=None) -> int:
     ap.add_argument("--no-text", action="store_true", help="skip the text-tower leg")
     ap.add_argument("--no-rgbd", action="store_true", help="skip the RGB-D observation leg")
     ap.add_argument("--text-steps", type=int, default=5)
+    ap.add_argument("--no-train", action="store_true",
+                    help="skip the contrastive training-step leg")
+    ap.add_argument("--train-steps", type=int, default=3)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB first, so "
                          "a counter run can scale FETCH_SIZE / WRITE_SIZE by a copy of known size")
@@ -512,6 +580,10 @@ def main(argv=None) -> int:
         result["rgbd_observations"] = rgbd_leg(torch, vl, args.text_steps,
                                                split=not args.no_split)
         print(f"# rgbd: {json.dumps(result['rgbd_observations'])}", file=sys.stderr, flush=True)
+
+    if not args.no_train:
+        result["train_step"] = train_leg(torch, vl, args.train_steps)
+        print(f"# train step: {json.dumps(result['train_step'])}", file=sys.stderr, flush=True)
 
     if not args.no_serve:
         result["serving"] = serving_leg(torch, vl, args.serve_requests, 100, args.serve_slots,

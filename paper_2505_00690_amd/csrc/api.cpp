@@ -1663,8 +1663,19 @@ struct TrainPlan {
   int Tp = 0;               // T rounded up to 64 (K of the weight-gradient GEMMs)
   std::vector<TrainLayer> layers;
   size_t dX, dXb, gT, actT, dGf, dZ, dY, Wt, lse, dsum, part, pg, pb, de, zp, ppg, ppb, dwf;
+  size_t wsplit = 0, wsplit_bytes = 0;   // split-K partial products of the weight gradients
   size_t total = 0;
 };
+
+// Splits of a weight-gradient GEMM [M, N] over K = Tp (BF16 models): enough
+// that the 256 x 256 tiles of all splits fill about two rounds of 256 CUs,
+// each split a multiple of 64 columns.  Returns (splits, columns per split).
+std::pair<int, int> wgrad_splits(int M, int N, int Tp) {
+  const int tiles = ((M + 255) / 256) * ((N + 255) / 256);
+  int want = std::max(1, std::min((512 + tiles - 1) / tiles, Tp / 64));
+  const int kc = ((Tp + want - 1) / want + 63) / 64 * 64;
+  return {(Tp + kc - 1) / kc, kc};
+}
 
 bool make_train_plan(const vl_model* m, int32_t n, const int32_t* hs, const int32_t* ws,
                      TrainPlan* tp, std::string* why) {
@@ -1733,6 +1744,16 @@ bool make_train_plan(const vl_model* m, int32_t n, const int32_t* hs, const int3
   tp->ppg = take(4 * (size_t)n * D);
   tp->ppb = take(4 * (size_t)n * D);
   tp->dwf = take(4 * D * m->Kpad);
+  if (es == 2) {
+    size_t mx = 0;
+    const size_t shapes[5][2] = {{D, F}, {F, D}, {D, D}, {3 * D, D}, {D, (size_t)m->Kpad}};
+    for (const auto& sh : shapes) {
+      const auto sp = wgrad_splits((int)sh[0], (int)sh[1], (int)Tp);
+      if (sp.first > 1) mx = std::max(mx, (size_t)sp.first * sh[0] * sh[1] * 4);
+    }
+    tp->wsplit_bytes = mx;
+    if (mx) tp->wsplit = take(mx);
+  }
   tp->total = off;
   return true;
 }
@@ -1863,6 +1884,27 @@ BlobOffsets blob_offsets(const vl_model* m) {
   return b;
 }
 
+// Weight gradient out [M, N] = A [M, Tp] . B [N, Tp]^T: in BF16 models a
+// split-K product (partials in the workspace, added in split order), so the
+// few output tiles of these GEMMs are spread over the CUs.
+vl_status wgrad_gemm(const vl_model* m, const TrainPlan& tp, char* ws, const void* A,
+                     const void* B, int M, int N, float* out, hipStream_t s) {
+  const int Tp = tp.Tp;
+  if (m->prec == VL_FP32) return gemm_into_f32(m, A, Tp, B, Tp, M, N, Tp, out, N, s);
+  const auto sp = wgrad_splits(M, N, Tp);
+  if (sp.first <= 1 || (size_t)sp.first * M * N * 4 > tp.wsplit_bytes)
+    return gemm_into_f32(m, A, Tp, B, Tp, M, N, Tp, out, N, s);
+  float* part = reinterpret_cast<float*>(ws + tp.wsplit);
+  EpiArgs e;
+  e.out = part; e.ldo = N; e.alpha = 1.f; e.beta = 0.f;
+  e.kc = sp.second;
+  e.zstride = (size_t)M * N;
+  VL_HIP(gemm_bf16(static_cast<const bf16_t*>(A), Tp, B, Tp, false, M, N, Tp, OP_LOGITS,
+                   CFG_DL_256x256_W2x4, e, s));
+  VL_HIP(sum_splits(part, sp.first, (size_t)M * N, out, s));
+  return VL_OK;
+}
+
 // The backward pass, block by block in reverse.  dX is the gradient of the
 // residual stream; every linear layer's input gradient is a GEMM against the
 // transposed weight and its weight gradient a GEMM over the tokens (K = T,
@@ -1918,14 +1960,14 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
     VL_HIP(gelu_backward(dGf, reinterpret_cast<const float*>(ws + sv.z1), dZ, QH, bf,
                          (size_t)T * F, s));                                     // dz1, g
     VL_HIP(transpose_rows(QH, bf, T, F, F, actT, bf, Tp, s));                    // g^T
-    if ((st = gemm_into_f32(m, gT, Tp, actT, Tp, D, F, Tp, G(go.fc2_w), F, s)) != VL_OK) return st;
+    if ((st = wgrad_gemm(m, tp, ws, gT, actT, D, F, G(go.fc2_w), s)) != VL_OK) return st;
     VL_HIP(colsum(dX, false, T, D, D, nullptr, part, G(go.fc2_b), s));
     // ---- FC1: z1 = y2 W1^T + b1
     VL_HIP(transpose_rows(ly.fc1_w, bf, F, D, D, Wt, bf, F, s));                 // W1^T [D, F]
     if ((st = gemm_into_f32(m, dZ, F, Wt, F, T, D, F, dY, D, s)) != VL_OK) return st;
     VL_HIP(transpose_rows(dZ, bf, T, F, F, gT, bf, Tp, s));
     VL_HIP(transpose_rows(ws + sv.y2, bf, T, D, D, actT, bf, Tp, s));
-    if ((st = gemm_into_f32(m, gT, Tp, actT, Tp, F, D, Tp, G(go.fc1_w), D, s)) != VL_OK) return st;
+    if ((st = wgrad_gemm(m, tp, ws, gT, actT, F, D, G(go.fc1_w), s)) != VL_OK) return st;
     VL_HIP(colsum(dZ, bf, T, F, F, nullptr, part, G(go.fc1_b), s));
     // ---- LN2 (dX += LN2'(h) dY)
     VL_HIP(layernorm_backward(reinterpret_cast<const float*>(ws + sv.h), ly.ln2_g, dY, eps, dX, T,
@@ -1935,7 +1977,7 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
     VL_HIP(transpose_rows(ly.o_w, bf, D, D, D, Wt, bf, D, s));
     if ((st = gemm_into_f32(m, dXb, D, Wt, D, T, D, D, dY, D, s)) != VL_OK) return st;   // dO
     VL_HIP(transpose_rows(ws + sv.o, bf, T, D, D, actT, bf, Tp, s));
-    if ((st = gemm_into_f32(m, gT, Tp, actT, Tp, D, D, Tp, G(go.o_w), D, s)) != VL_OK) return st;
+    if ((st = wgrad_gemm(m, tp, ws, gT, actT, D, D, G(go.o_w), s)) != VL_OK) return st;
     VL_HIP(colsum(dX, false, T, D, D, nullptr, part, G(go.o_b), s));
     // ---- attention
     VL_HIP(attention_backward(ws + sv.qkv, ws + sv.o, bf, dY, d_imgs, d_items64, tp.n_items64,
@@ -1946,8 +1988,7 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
     if ((st = gemm_into_f32(m, dZ, 3 * D, Wt, 3 * D, T, D, 3 * D, dY, D, s)) != VL_OK) return st;
     VL_HIP(transpose_rows(dZ, bf, T, 3 * D, 3 * D, gT, bf, Tp, s));
     VL_HIP(transpose_rows(ws + sv.y1, bf, T, D, D, actT, bf, Tp, s));
-    if ((st = gemm_into_f32(m, gT, Tp, actT, Tp, 3 * D, D, Tp, G(go.qkv_w), D, s)) != VL_OK)
-      return st;
+    if ((st = wgrad_gemm(m, tp, ws, gT, actT, 3 * D, D, G(go.qkv_w), s)) != VL_OK) return st;
     VL_HIP(colsum(dZ, bf, T, 3 * D, 3 * D, nullptr, part, G(go.qkv_b), s));
     // ---- LN1 (dX += LN1'(x) dY)
     VL_HIP(layernorm_backward(reinterpret_cast<const float*>(ws + sv.xin), ly.ln1_g, dY, eps, dX,
@@ -1959,7 +2000,7 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
   VL_HIP(transpose_rows(QH, bf, T, m->Kpad, m->Kpad, actT, bf, Tp, s));
   float* dwf = reinterpret_cast<float*>(ws + tp.dwf);
   {
-    const vl_status st = gemm_into_f32(m, gT, Tp, actT, Tp, D, m->Kpad, Tp, dwf, m->Kpad, s);
+    const vl_status st = wgrad_gemm(m, tp, ws, gT, actT, D, m->Kpad, dwf, s);
     if (st != VL_OK) return st;
   }
   VL_HIP(colsum(dX, false, T, D, D, tok, part, G(bo.patch_b), s));

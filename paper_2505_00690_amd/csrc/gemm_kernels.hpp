@@ -329,6 +329,13 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
   bf16_t(*sA)[BM * BK] = reinterpret_cast<bf16_t(*)[BM * BK]>(smem);
   uint8_t(*sB)[BN * BK * BES] = reinterpret_cast<uint8_t(*)[BN * BK * BES]>(smem + ST * BM * BK * 2);
 
+  if (EPI == EPI_SCALE_BIAS && e.kc > 0) {   // split-K: this split's K columns
+    const int k0 = blockIdx.y * e.kc;
+    A += k0;
+    Bv = static_cast<const char*>(Bv) + (size_t)k0 * BES;
+    K = min(e.kc, K - k0);
+    e.out = static_cast<float*>(e.out) + blockIdx.y * e.zstride;
+  }
   int tm_, tn_;
   xcd_tile(gm, gn, 8, &tm_, &tn_);
   const int m0 = tm_ * BM, n0 = tn_ * BN;
@@ -590,7 +597,8 @@ template <int BM, int BN, int WGM, int WGN, bool B_FP8, int RPM = 2, int ST = 2>
 static hipError_t launch_bf16_dl(const bf16_t* A, int lda, const void* B, int ldb, int M,
                                  int N, int K, int op, const EpiArgs& e, hipStream_t s) {
   const int gm = (M + BM - 1) / BM, gn = (N + BN - 1) / BN;
-  dim3 grid(gm * gn), block(WGM * WGN * 64);
+  dim3 grid(gm * gn, op == OP_LOGITS && e.kc > 0 ? (K + e.kc - 1) / e.kc : 1),
+      block(WGM * WGN * 64);
 #define VL_GEMM_CASE(OP)                                                                  \
   case OP:                                                                                \
     hipLaunchKernelGGL((k_gemm_bf16_dl<BM, BN, WGM, WGN, B_FP8, OP, RPM, ST>), grid, block, \

@@ -51,6 +51,11 @@ struct EpiArgs {
   const float* pos = nullptr;      // [1 + g0*g0, D]
   int base_grid = 0;
   float alpha = 1.f, beta = 0.f;
+  // Split-K (BF16 GEMM, OP_LOGITS only): with kc > 0 the launch has
+  // ceil(K / kc) splits in grid y; split z sums K columns [z kc, z kc + kc)
+  // and writes its FP32 partial product at out + z * zstride.
+  int kc = 0;
+  size_t zstride = 0;
 };
 
 // Tile configurations of the BF16 GEMM.  Every configuration accumulates K
@@ -218,6 +223,8 @@ hipError_t embed_backward(const float* dX, const ImgDesc* imgs, int n, int D, in
                           const float* dwf, int kpad, const float* db, ChanNorm cn, int kpe,
                           int pp, float* d_pos, float* d_cls, float* d_patch_w, hipStream_t s);
 hipError_t fill_zero(float* p, size_t n, hipStream_t s);
+// out[i] = sum over z = 0 .. splits-1 (ascending) of part[z * n + i].
+hipError_t sum_splits(const float* part, int splits, size_t n, float* out, hipStream_t s);
 
 // Weight preparation.
 hipError_t convert_bf16(const float* src, bf16_t* dst, size_t n, hipStream_t s);

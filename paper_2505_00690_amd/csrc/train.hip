@@ -94,17 +94,28 @@ __global__ __launch_bounds__(256) void k_colsum_part(const T* __restrict__ in, i
   part[(size_t)blockIdx.y * C + c] = s;
 }
 
+// Final pass: 16 columns per workgroup, 16 phases per column; phase k sums
+// the partials b = k, k + 16, ... in ascending order, then the 16 phase sums
+// are added in phase order.
 __global__ __launch_bounds__(256) void k_colsum_final(const float* __restrict__ part, int nb,
                                                       int C, float* __restrict__ out) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= C) return;
+  __shared__ float red[16][17];
+  const int cl = threadIdx.x & 15, ph = threadIdx.x >> 4;
+  const int c = blockIdx.x * 16 + cl;
   float s = 0.f;
-  for (int b = 0; b < nb; ++b) s += part[(size_t)b * C + c];
-  out[c] = s;
+  if (c < C)
+    for (int b = ph; b < nb; b += 16) s += part[(size_t)b * C + c];
+  red[ph][cl] = s;
+  __syncthreads();
+  if (ph == 0 && c < C) {
+    float t = 0.f;
+    for (int k = 0; k < 16; ++k) t += red[k][cl];
+    out[c] = t;
+  }
 }
 
 hipError_t colsum_final(const float* part, int nb, int C, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_colsum_final, dim3((C + 255) / 256), dim3(256), 0, s, part, nb, C, out);
+  hipLaunchKernelGGL(k_colsum_final, dim3((C + 15) / 16), dim3(256), 0, s, part, nb, C, out);
   return hipGetLastError();
 }
 
@@ -465,6 +476,346 @@ __global__ __launch_bounds__(256) void k_attn_bwd_dkv(const T* __restrict__ qkv,
   }
 }
 
+// ---- MFMA form (BF16 models).  v_mfma_f32_32x32x16_bf16 computes
+// C[i][j] += sum_k A[i][k] B[j][k] over 16 values of k: lane (l32, g) gives
+// A[l32][8g + e] and B[l32][8g + e] (e = 0..7) and receives column j = l32,
+// rows i = 8(r/4) + 4g + r%4 (r = 0..15) of C.  Hence an accumulator whose
+// rows run over a contraction index serves directly as a B operand (rows
+// 16hh + {4g .. 4g+3, 8+4g .. 8+4g+3} of a 32-row block are its elements
+// 8hh .. 8hh+7), provided the A operand supplies the same eight rows: the
+// gfx950 LDS transpose read gives exactly that from a row-major tile (the
+// forward attention kernel's value-operand read).
+//
+// dq kernel: a workgroup of two waves owns 64 queries of one (image, head),
+// a lane one query (B operands Q, dO of its row in registers).  Pass 1:
+// S^T = K Q^T per 64-key tile, the row maximum and sum of exponentials
+// (log-sum-exp, in log2 units of the scaled scores).  Pass 2: S^T and
+// dP^T = V dO^T again, dS^T = P^T (dP^T - D), dQ^T += K^T dS^T with K^T read
+// transposed from the key tile in LDS.  It also writes the log-sum-exp and
+// D = rowsum(dO O).  dkv kernel: two waves own 64 keys (lane: one key, K and
+// V rows in registers); per 64-query tile (Q and dO in LDS) S = Q K^T, dP =
+// dO V^T, P, dS, then dV^T += dO^T P and dK^T += Q^T dS with dO^T and Q^T
+// read transposed.  FP32 accumulation; P and dS rounded to BF16 as MFMA
+// operands; dO rounded to BF16 where it is an MFMA operand.
+template <int HD>
+struct TrTile {   // row-major 64 x HD BF16 tile; chunk c of row r at c ^ f(r)
+  static constexpr int NCH = HD / 8;
+  static constexpr int ROWB = HD * 2;
+  static constexpr int BYTES = 64 * ROWB;
+  __device__ static int f(int r) { return NCH == 8 ? (r & 7) : 0; }
+  __device__ static int off(int r, int chunk) { return r * ROWB + ((chunk ^ f(r)) << 4); }
+};
+
+typedef short s16x4b __attribute__((ext_vector_type(4)));
+
+// Transposed operand from a TrTile at LDS byte address `tile`: lane (column
+// 32a + l32, g) receives rows 16jj + 4g + 0..3 and 16jj + 8 + 4g + 0..3.
+template <int HD>
+__device__ __forceinline__ bf16x8 tr_frag(uint32_t tile, int a, int jj, int lane) {
+  using TT = TrTile<HD>;
+  const int grp = lane >> 4, li = lane & 15;
+  const int tg = grp >> 1, dh = grp & 1;
+  const int col = 32 * a + 16 * dh + 4 * (li & 3);
+  const uint32_t vb = tile + TT::off(4 * tg + (li >> 2), col >> 3) + (col & 7) * 2 +
+                      16 * jj * TT::ROWB;
+  typedef __attribute__((address_space(3))) s16x4b lds_s16x4;
+  const s16x4b v0 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(uintptr_t)vb);
+  const s16x4b v1 =
+      __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(uintptr_t)(vb + 8 * TT::ROWB));
+  u32x4 vk;
+  vk[0] = __builtin_bit_cast(u32x2, v0).x; vk[1] = __builtin_bit_cast(u32x2, v0).y;
+  vk[2] = __builtin_bit_cast(u32x2, v1).x; vk[3] = __builtin_bit_cast(u32x2, v1).y;
+  return __builtin_bit_cast(bf16x8, vk);
+}
+
+__device__ __forceinline__ bf16x8 pack8(const f32x16& c, int hh) {
+  u32x4 pk;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) pk[w] = pack_bf16x2(c[8 * hh + 2 * w], c[8 * hh + 2 * w + 1]);
+  return __builtin_bit_cast(bf16x8, pk);
+}
+
+__device__ __forceinline__ bf16x8 f32x8_to_bf16(float4 a, float4 b) {
+  u32x4 pk;
+  pk[0] = pack_bf16x2(a.x, a.y); pk[1] = pack_bf16x2(a.z, a.w);
+  pk[2] = pack_bf16x2(b.x, b.y); pk[3] = pack_bf16x2(b.z, b.w);
+  return __builtin_bit_cast(bf16x8, pk);
+}
+
+// Cooperative fill of a TrTile (128 threads) from rows r0.. of a BF16 or
+// FP32 (converted) matrix with row stride ld; rows >= nrows are zero.
+template <int HD, typename T>
+__device__ __forceinline__ void fill_tile(char* tile, const T* src, size_t ld, int nrows) {
+  using TT = TrTile<HD>;
+  for (int i = threadIdx.x; i < 64 * TT::NCH; i += 128) {
+    const int r = i / TT::NCH, c = i - r * TT::NCH;
+    bf16x8 v;
+    if (r < nrows) {
+      if constexpr (sizeof(T) == 2) {
+        v = *reinterpret_cast<const bf16x8*>(src + (size_t)r * ld + 8 * c);
+      } else {
+        const float4* p = reinterpret_cast<const float4*>(src + (size_t)r * ld + 8 * c);
+        v = f32x8_to_bf16(p[0], p[1]);
+      }
+    } else {
+      v = __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u});
+    }
+    *reinterpret_cast<bf16x8*>(tile + TT::off(r, c)) = v;
+  }
+}
+
+template <int HD>
+__global__ __launch_bounds__(128) void k_attn_bwd_dq_mfma(const bf16_t* __restrict__ qkv,
+                                                          const bf16_t* __restrict__ o,
+                                                          const float* __restrict__ dO,
+                                                          const ImgDesc* __restrict__ imgs,
+                                                          const AttnItem* __restrict__ items,
+                                                          int heads, bf16_t* __restrict__ dqkv,
+                                                          float* __restrict__ lse2_out,
+                                                          float* __restrict__ dsum_out) {
+  using TT = TrTile<HD>;
+  constexpr int NC = HD / 16, NA = HD / 32;
+  __shared__ __attribute__((aligned(16))) char sK[TT::BYTES];
+  const AttnItem it = items[blockIdx.x];
+  const int h = blockIdx.y;
+  const ImgDesc dsc = imgs[it.img];
+  const int N = dsc.ntok, DM = heads * HD, ld3 = 3 * DM;
+  const bf16_t* base = qkv + (size_t)dsc.tok_start * ld3 + h * HD;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l32 = lane & 31, g = lane >> 5;
+  const int q = it.q0 + 32 * wave + l32;
+  const bool qok = q < N;
+  const int qc = min(q, N - 1);
+  const size_t qrow = (size_t)dsc.tok_start + qc;
+  bf16x8 qf[NC], df[NC];
+  float dsv = 0.f;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int col = 16 * c + 8 * g;
+    qf[c] = *reinterpret_cast<const bf16x8*>(base + (size_t)qc * ld3 + col);
+    const float4* dp = reinterpret_cast<const float4*>(dO + qrow * DM + h * HD + col);
+    float4 x0 = dp[0], x1 = dp[1];
+    if (!qok) x0 = x1 = make_float4(0.f, 0.f, 0.f, 0.f);
+    df[c] = f32x8_to_bf16(x0, x1);
+    const bf16_t* op = o + qrow * DM + h * HD + col;
+    const float xs[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) dsv += xs[e] * bf16_bits_to_f32(op[e]);
+  }
+  dsv += __shfl_xor(dsv, 32, 64);
+  const float sl2 = 1.4426950408889634f / sqrtf((float)HD);
+  auto key_frag = [&](int row, int c) {   // K row fragment from global (row clamped)
+    return *reinterpret_cast<const bf16x8*>(base + DM + (size_t)min(row, N - 1) * ld3 + 16 * c +
+                                            8 * g);
+  };
+  // pass 1: log-sum-exp of each query's scaled scores (log2 units)
+  float m = -INFINITY, l = 0.f;
+  for (int k0 = 0; k0 < N; k0 += 64) {
+    f32x16 s[2];
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s[kb][r] = 0.f;
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        s[kb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(key_frag(k0 + 32 * kb + l32, c), qf[c],
+                                                        s[kb], 0, 0, 0);
+    }
+    float mt = -INFINITY;
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int key = k0 + 32 * kb + 8 * (r >> 2) + 4 * g + (r & 3);
+        s[kb][r] = key < N ? s[kb][r] * sl2 : -INFINITY;
+        mt = fmaxf(mt, s[kb][r]);
+      }
+    mt = fmaxf(mt, __shfl_xor(mt, 32, 64));
+    const float mn = fmaxf(m, mt);
+    float ts = 0.f;
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) ts += exp2f(s[kb][r] - mn);
+    l = l * exp2f(m - mn) + ts;
+    m = mn;
+  }
+  const float lse2 = m + log2f(l + __shfl_xor(l, 32, 64));
+  // pass 2: dS^T and dQ^T
+  f32x16 dq[NA];
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) dq[a][r] = 0.f;
+  const uint32_t ldsK = lds_offset(sK);
+  for (int k0 = 0; k0 < N; k0 += 64) {
+    __syncthreads();   // the previous tile's readers are done
+    fill_tile<HD>(sK, base + DM + (size_t)k0 * ld3, ld3, N - k0);
+    __syncthreads();
+    f32x16 s[2], dp[2];
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s[kb][r] = dp[kb][r] = 0.f;
+      const int row = 32 * kb + l32;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const bf16x8 kf = *reinterpret_cast<const bf16x8*>(sK + TT::off(row, 2 * c + g));
+        s[kb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kf, qf[c], s[kb], 0, 0, 0);
+        const bf16x8 vf = *reinterpret_cast<const bf16x8*>(
+            base + 2 * DM + (size_t)min(k0 + row, N - 1) * ld3 + 16 * c + 8 * g);
+        dp[kb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vf, df[c], dp[kb], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int key = k0 + 32 * kb + 8 * (r >> 2) + 4 * g + (r & 3);
+        const float p = key < N ? exp2f(fmaf(s[kb][r], sl2, -lse2)) : 0.f;
+        s[kb][r] = p * (dp[kb][r] - dsv);
+      }
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const bf16x8 dsf = pack8(s[jj >> 1], jj & 1);
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+        dq[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(tr_frag<HD>(ldsK, a, jj, lane), dsf,
+                                                        dq[a], 0, 0, 0);
+    }
+  }
+  if (!qok) return;
+  const float scale = 1.0f / sqrtf((float)HD);
+  const size_t row = (size_t)dsc.tok_start + q;
+  bf16_t* out = dqkv + row * ld3 + h * HD;
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int rq = 0; rq < 4; ++rq) {
+      u32x2 pk;
+      pk.x = pack_bf16x2(dq[a][4 * rq + 0] * scale, dq[a][4 * rq + 1] * scale);
+      pk.y = pack_bf16x2(dq[a][4 * rq + 2] * scale, dq[a][4 * rq + 3] * scale);
+      *reinterpret_cast<u32x2*>(out + a * 32 + 8 * rq + 4 * g) = pk;
+    }
+  if (g == 0) {
+    lse2_out[row * heads + h] = lse2;
+    dsum_out[row * heads + h] = dsv;
+  }
+}
+
+template <int HD>
+__global__ __launch_bounds__(128) void k_attn_bwd_dkv_mfma(const bf16_t* __restrict__ qkv,
+                                                           const float* __restrict__ dO,
+                                                           const ImgDesc* __restrict__ imgs,
+                                                           const AttnItem* __restrict__ items,
+                                                           int heads,
+                                                           const float* __restrict__ lse2,
+                                                           const float* __restrict__ dsum,
+                                                           bf16_t* __restrict__ dqkv) {
+  using TT = TrTile<HD>;
+  constexpr int NC = HD / 16, NA = HD / 32;
+  __shared__ __attribute__((aligned(16))) char sQ[TT::BYTES];
+  __shared__ __attribute__((aligned(16))) char sdO[TT::BYTES];
+  __shared__ float sL[64], sD[64];
+  const AttnItem it = items[blockIdx.x];   // it.q0: first key of the block
+  const int h = blockIdx.y;
+  const ImgDesc dsc = imgs[it.img];
+  const int N = dsc.ntok, DM = heads * HD, ld3 = 3 * DM;
+  const bf16_t* base = qkv + (size_t)dsc.tok_start * ld3 + h * HD;
+  const float* dbase = dO + (size_t)dsc.tok_start * DM + h * HD;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l32 = lane & 31, g = lane >> 5;
+  const int k = it.q0 + 32 * wave + l32;
+  const bool kok = k < N;
+  const int kc = min(k, N - 1);
+  bf16x8 kf[NC], vf[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    kf[c] = *reinterpret_cast<const bf16x8*>(base + DM + (size_t)kc * ld3 + 16 * c + 8 * g);
+    vf[c] = *reinterpret_cast<const bf16x8*>(base + 2 * DM + (size_t)kc * ld3 + 16 * c + 8 * g);
+  }
+  const float sl2 = 1.4426950408889634f / sqrtf((float)HD);
+  f32x16 dv[NA], dk[NA];
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) dv[a][r] = dk[a][r] = 0.f;
+  const uint32_t ldsQ = lds_offset(sQ), ldsO = lds_offset(sdO);
+  for (int q0 = 0; q0 < N; q0 += 64) {
+    const int nq = min(64, N - q0);
+    __syncthreads();
+    fill_tile<HD>(sQ, base + (size_t)q0 * ld3, ld3, nq);
+    fill_tile<HD>(sdO, dbase + (size_t)q0 * DM, DM, nq);
+    if (threadIdx.x < 64) {
+      const size_t row = (size_t)dsc.tok_start + q0 + threadIdx.x;
+      sL[threadIdx.x] = (int)threadIdx.x < nq ? lse2[row * heads + h] : 0.f;
+      sD[threadIdx.x] = (int)threadIdx.x < nq ? dsum[row * heads + h] : 0.f;
+    }
+    __syncthreads();
+    f32x16 s[2], dp[2];
+#pragma unroll
+    for (int qb = 0; qb < 2; ++qb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s[qb][r] = dp[qb][r] = 0.f;
+      const int row = 32 * qb + l32;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const bf16x8 qa = *reinterpret_cast<const bf16x8*>(sQ + TT::off(row, 2 * c + g));
+        s[qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa, kf[c], s[qb], 0, 0, 0);
+        const bf16x8 da = *reinterpret_cast<const bf16x8*>(sdO + TT::off(row, 2 * c + g));
+        dp[qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(da, vf[c], dp[qb], 0, 0, 0);
+      }
+    }
+    // s[qb][r] = S[query q0 + qi][key k], qi = 32qb + 8(r/4) + 4g + r%4
+#pragma unroll
+    for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int qi = 32 * qb + 8 * (r >> 2) + 4 * g + (r & 3);
+        const float p = (qi < nq && kok) ? exp2f(fmaf(s[qb][r], sl2, -sL[qi])) : 0.f;
+        s[qb][r] = p;
+        dp[qb][r] = p * (dp[qb][r] - sD[qi]);
+      }
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const bf16x8 pf = pack8(s[jj >> 1], jj & 1);
+      const bf16x8 dsf = pack8(dp[jj >> 1], jj & 1);
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        dv[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(tr_frag<HD>(ldsO, a, jj, lane), pf,
+                                                        dv[a], 0, 0, 0);
+        dk[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(tr_frag<HD>(ldsQ, a, jj, lane), dsf,
+                                                        dk[a], 0, 0, 0);
+      }
+    }
+  }
+  if (!kok) return;
+  const float scale = 1.0f / sqrtf((float)HD);
+  bf16_t* out = dqkv + ((size_t)dsc.tok_start + k) * ld3 + h * HD;
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int rq = 0; rq < 4; ++rq) {
+      u32x2 pk;
+      pk.x = pack_bf16x2(dk[a][4 * rq + 0] * scale, dk[a][4 * rq + 1] * scale);
+      pk.y = pack_bf16x2(dk[a][4 * rq + 2] * scale, dk[a][4 * rq + 3] * scale);
+      *reinterpret_cast<u32x2*>(out + DM + a * 32 + 8 * rq + 4 * g) = pk;
+      pk.x = pack_bf16x2(dv[a][4 * rq + 0], dv[a][4 * rq + 1]);
+      pk.y = pack_bf16x2(dv[a][4 * rq + 2], dv[a][4 * rq + 3]);
+      *reinterpret_cast<u32x2*>(out + 2 * DM + a * 32 + 8 * rq + 4 * g) = pk;
+    }
+}
+
+template <int HD>
+static void launch_attn_bwd_mfma(const void* qkv, const void* o, const float* dO,
+                                 const ImgDesc* imgs, const AttnItem* items, int n_items,
+                                 int heads, void* dqkv, float* lse, float* dsum, hipStream_t s) {
+  dim3 grid(n_items, heads), block(128);
+  hipLaunchKernelGGL(k_attn_bwd_dq_mfma<HD>, grid, block, 0, s, static_cast<const bf16_t*>(qkv),
+                     static_cast<const bf16_t*>(o), dO, imgs, items, heads,
+                     static_cast<bf16_t*>(dqkv), lse, dsum);
+  hipLaunchKernelGGL(k_attn_bwd_dkv_mfma<HD>, grid, block, 0, s, static_cast<const bf16_t*>(qkv),
+                     dO, imgs, items, heads, lse, dsum, static_cast<bf16_t*>(dqkv));
+}
+
 template <typename T, int HD>
 static void launch_attn_bwd(const void* qkv, const void* o, const float* dO, const ImgDesc* imgs,
                             const AttnItem* items, int n_items, int heads, void* dqkv, float* lse,
@@ -483,10 +834,10 @@ hipError_t attention_backward(const void* qkv, const void* o, bool bf16, const f
                               hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   if (head_dim == 64) {
-    if (bf16) launch_attn_bwd<bf16_t, 64>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s);
+    if (bf16) launch_attn_bwd_mfma<64>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s);
     else launch_attn_bwd<float, 64>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s);
   } else if (head_dim == 32) {
-    if (bf16) launch_attn_bwd<bf16_t, 32>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s);
+    if (bf16) launch_attn_bwd_mfma<32>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s);
     else launch_attn_bwd<float, 32>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s);
   } else {
     return hipErrorInvalidValue;
@@ -637,6 +988,22 @@ hipError_t embed_backward(const float* dX, const ImgDesc* imgs, int n, int D, in
 }
 
 // ------------------------------------------------------------------- misc
+__global__ __launch_bounds__(256) void k_sum_splits(const float* __restrict__ part, int splits,
+                                                    size_t n, float* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int z = 0; z < splits; ++z) s += part[(size_t)z * n + i];
+  out[i] = s;
+}
+
+hipError_t sum_splits(const float* part, int splits, size_t n, float* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
+                     splits, n, out);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_fill_zero(float* __restrict__ p, size_t n) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) p[i] = 0.f;
