@@ -386,6 +386,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-text", action="store_true", help="skip the text-tower leg")
     ap.add_argument("--no-rgbd", action="store_true", help="skip the RGB-D observation leg")
     ap.add_argument("--text-steps", type=int, default=5)
+    ap.add_argument("--fused-ln", action="store_true",
+                    help="fold the LayerNorms into the GEMMs (measured slower; off by default)")
     ap.add_argument("--no-train", action="store_true",
                     help="skip the contrastive training-step leg")
     ap.add_argument("--train-steps", type=int, default=3)
@@ -456,7 +458,8 @@ def main(argv=None) -> int:
             named[op.strip()] = {str(b): cfg.strip() for b in range(vl.VL_N_M_BUCKETS)}
 
     def make_encoder(two_parts: bool):
-        e = vl.Encoder(c, w, prec, graphs=not args.no_graphs, split=two_parts)
+        e = vl.Encoder(c, w, prec, graphs=not args.no_graphs, split=two_parts,
+                       fused_ln=args.fused_ln)
         t = None
         if prec != "fp32" and named:
             e.set_tuning(named)
@@ -542,6 +545,7 @@ def main(argv=None) -> int:
                    "resolutions": sorted(set(h for h, _ in sizes)), "precision": prec,
                    "head": wl.head, "n_texts": wl.n_texts, "graphs": not args.no_graphs,
                    "two_part_split": split,
+                   "fused_layernorm": prec in ("bf16", "fp8w") and args.fused_ln,
                    "gemm_tiles": tuned, "gemm_tiles_one_part": ttuned},
         "encoder_tflops": total_flops / (ms / 1e3) / 1e12,
         "mfu_bf16": total_flops / (ms / 1e3) / BF16_PEAK,

@@ -239,8 +239,26 @@ vl_status vl_encode_texts(vl_model* m, const int32_t* ids_dev, const int32_t* le
  *                   bitwise identical to a one-part run.  0 = one part on
  *                   the call's stream.  Changing it drops cached graphs.
  *                   (On MI355X at ViT-L/14@336, batch 32, it measured
- *                   between -2 % and +3 % against one part.)             */
-typedef enum vl_option { VL_OPT_GRAPHS = 0, VL_OPT_TIMING = 1, VL_OPT_SPLIT = 2 } vl_option;
+ *                   between -2 % and +3 % against one part.)
+ *   VL_OPT_FUSED_LN : off by default (VL_BF16 and VL_FP8W_BF16A; no effect
+ *                   on other precisions).  Both LayerNorms of a block are
+ *                   folded into the GEMMs around them: the residual
+ *                   epilogues of the output projection and FC2 also write
+ *                   u = bf16(x * gamma) of the next LayerNorm and per-row
+ *                   partial statistics (mean and sum of squared deviations
+ *                   of each 32-column group, FP32); a small pass combines
+ *                   them into the row's mean and 1/sqrt(var + eps); QKV and
+ *                   FC1 multiply u by the weights and form
+ *                   rstd (acc - mean W gamma) + W beta + bias in their
+ *                   epilogues.  The same function as LayerNorm then linear
+ *                   layer; the BF16 operand is x * gamma instead of the
+ *                   normalised row, so results differ from 0 by rounding.
+ *                   (Measured on MI355X at ViT-L/14@336, batch 32: the
+ *                   LayerNorm time falls but the four GEMMs lose more, ~5 %
+ *                   slower per step, hence off.)  Changing it drops cached
+ *                   graphs.                                                 */
+typedef enum vl_option { VL_OPT_GRAPHS = 0, VL_OPT_TIMING = 1, VL_OPT_SPLIT = 2,
+                         VL_OPT_FUSED_LN = 3 } vl_option;
 vl_status vl_model_set_option(vl_model* m, vl_option opt, int64_t value);
 
 /* Operations of the encoder, as reported by vl_model_op_times:

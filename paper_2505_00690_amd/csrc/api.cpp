@@ -55,6 +55,9 @@ struct Layer {
   const void *qkv_w, *o_w, *fc1_w, *fc2_w;          // f32, bf16 or e4m3 [out, in]
   const float *qkv_s, *o_s, *fc1_s, *fc2_s;         // per-row scales (e4m3 only)
   const uint8_t *qkv_x, *o_x, *fc1_x, *fc2_x;       // MXFP8 block scales [in/128][out][4]
+  // LayerNorm folded into QKV / FC1 (BF16 and e4m3-weight models): c1 = W g,
+  // c2 = W b + bias of LN1 -> QKV and LN2 -> FC1.
+  const float *qkv_c1 = nullptr, *qkv_c2 = nullptr, *fc1_c1 = nullptr, *fc1_c2 = nullptr;
 };
 
 // Pinned host buffer holding a call's descriptors while its copy is pending.
@@ -122,6 +125,10 @@ struct vl_model {
   // Two-part batches (off by default): the second part runs on this stream,
   // forked from and joined back into the caller's stream with the two events.
   bool split = false;
+  // LayerNorm folded into the neighbouring GEMMs (BF16 and e4m3-weight
+  // models; VL_OPT_FUSED_LN, off by default: on MI355X the extra epilogue
+  // output costs the GEMMs more than the standalone LayerNorms take).
+  bool fused_ln = false;
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int32_t tuning[VL_N_GEMM_OPS][VL_N_M_BUCKETS];
@@ -199,6 +206,9 @@ struct Part {
   size_t off_imgs = 0, off_items = 0;                       // in the descriptor region
   size_t off_tok = 0, off_X = 0, off_Y = 0, off_QH = 0, off_E = 0;  // in the workspace
   size_t off_map = 0;   // MAP pooling: per image O, x, LN(x) [n, D] and MLP hidden [n, F]
+  // LayerNorm folding: u = bf16(x * gamma) [T, D], per-32-column (mean, M2)
+  // partials [T, D/32, 2] and row (mean, rstd) [T, 2]
+  size_t off_U = 0, off_PS = 0, off_RS = 0;
 };
 
 struct Plan {
@@ -274,6 +284,14 @@ bool finish_plan(const vl_model* m, std::vector<ImgDesc>& imgs, int64_t T, Plan*
     if (!m->text && m->cfg.pool == VL_POOL_MAP) {
       q.off_map = off;
       off += align_up(4ull * q.n * (3 * (size_t)m->D + m->F));
+    }
+    if (m->prec == VL_BF16 || m->prec == VL_FP8W_BF16A) {
+      q.off_U = off;
+      off += align_up(2ull * q.T * m->D);
+      q.off_PS = off;
+      off += align_up(4ull * q.T * (m->D / 32) * 2);
+      q.off_RS = off;
+      off += align_up(8ull * q.T);
     }
   }
   p->total = off;
@@ -462,7 +480,43 @@ vl_status run_part(vl_model* m, const Part& p, const void* in, float* emb, char*
                        D, m->Kpad, OP_PATCH, gemm_cfg_for(m, 0, T), pe, s));
   });
 
-  for (const Layer& ly : m->layers) {
+  // LayerNorm folding (BF16 / e4m3 weights): the GEMMs read u = bf16(x g)
+  // and the row statistics; the residual epilogues produce both for the
+  // next LayerNorm, the first block's come from one folding pass.
+  const bool fold = !f32 && !mx && m->fused_ln && !m->layers.empty();
+  bf16_t* U = reinterpret_cast<bf16_t*>(ws + p.off_U);
+  float* PS = reinterpret_cast<float*>(ws + p.off_PS);
+  float* RS = reinterpret_cast<float*>(ws + p.off_RS);
+  if (fold)
+    VL_TIMED(T_LN, VL_HIP(ln_fold_rows(X, m->layers[0].ln1_g, eps, U, RS, T, D, s)));
+  for (size_t li = 0; li < m->layers.size(); ++li) {
+    const Layer& ly = m->layers[li];
+    if (fold) {
+      const Layer* nx = li + 1 < m->layers.size() ? &m->layers[li + 1] : nullptr;
+      EpiArgs e1; e1.wscale = ly.qkv_s; e1.out = QH; e1.ldo = 3 * D;
+      e1.row_stats = RS; e1.c1 = ly.qkv_c1; e1.c2 = ly.qkv_c2;
+      EpiArgs e2; e2.bias = ly.o_b; e2.wscale = ly.o_s; e2.out = X; e2.ldo = D;
+      e2.u_out = U; e2.u_gamma = ly.ln2_g; e2.part_stats = PS;
+      EpiArgs e3; e3.wscale = ly.fc1_s; e3.out = QH; e3.ldo = F;
+      e3.row_stats = RS; e3.c1 = ly.fc1_c1; e3.c2 = ly.fc1_c2;
+      EpiArgs e4; e4.bias = ly.fc2_b; e4.wscale = ly.fc2_s; e4.out = X; e4.ldo = D;
+      if (nx) { e4.u_out = U; e4.u_gamma = nx->ln1_g; e4.part_stats = PS; }
+      const bf16_t* qh = static_cast<const bf16_t*>(QH);
+      VL_TIMED(T_QKV, VL_HIP(gemm_bf16(U, D, ly.qkv_w, D, fp8, T, 3 * D, D, OP_QKV,
+                                       gemm_cfg_for(m, 1, T), e1, s)));
+      if (after_first_qkv && li == 0) VL_HIP(hipEventRecord(after_first_qkv, s));
+      VL_TIMED(T_ATTN, VL_HIP(attention_bf16(qh, static_cast<bf16_t*>(Y), d_imgs, d_items,
+                                             p.n_items, m->heads, m->hd, m->text, s)));
+      VL_TIMED(T_OPROJ, VL_HIP(gemm_bf16(static_cast<const bf16_t*>(Y), D, ly.o_w, D, fp8, T, D,
+                                         D, OP_OPROJ, gemm_cfg_for(m, 2, T), e2, s)));
+      VL_TIMED(T_LN, VL_HIP(ln_stats_from_parts(PS, T, D, eps, RS, s)));
+      VL_TIMED(T_FC1, VL_HIP(gemm_bf16(U, D, ly.fc1_w, D, fp8, T, F, D, OP_FC1,
+                                       gemm_cfg_for(m, 3, T), e3, s)));
+      VL_TIMED(T_FC2, VL_HIP(gemm_bf16(qh, F, ly.fc2_w, F, fp8, T, D, F, OP_FC2,
+                                       gemm_cfg_for(m, 4, T), e4, s)));
+      if (nx) VL_TIMED(T_LN, VL_HIP(ln_stats_from_parts(PS, T, D, eps, RS, s)));
+      continue;
+    }
     if (mx)
       VL_TIMED(T_LN, VL_HIP(layernorm_rows_mx(X, ly.ln1_g, ly.ln1_b, eps, static_cast<uint8_t*>(Y),
                                               static_cast<uint8_t*>(Y) + (size_t)T * D, T, D, s)));
@@ -720,7 +774,8 @@ static vl_status build_weights(vl_model* m, const float* wdev, hipStream_t s, vl
   const size_t d_cls = m->text ? 0 : alloc(4 * D);
   const size_t d_tok = m->text ? alloc(4 * (size_t)m->vocab * D) : 0;
   const size_t d_pos = alloc(4 * G * D);
-  struct DstLayer { size_t ln1_g, ln1_b, ln2_g, ln2_b, qkv_b, o_b, fc1_b, fc2_b, qkv_w, o_w, fc1_w, fc2_w, qkv_s, o_s, fc1_s, fc2_s; };
+  struct DstLayer { size_t ln1_g, ln1_b, ln2_g, ln2_b, qkv_b, o_b, fc1_b, fc2_b, qkv_w, o_w, fc1_w, fc2_w, qkv_s, o_s, fc1_s, fc2_s, qkv_c1, qkv_c2, fc1_c1, fc1_c2; };
+  const bool folds = prec == VL_BF16 || prec == VL_FP8W_BF16A;   // LayerNorm folding constants
   const bool mx = prec == VL_MXFP8;
   std::vector<DstLayer> dl(m->L);
   for (int l = 0; l < m->L; ++l) {
@@ -735,6 +790,10 @@ static vl_status build_weights(vl_model* m, const float* wdev, hipStream_t s, vl
     if (mx) {  // one E8M0 byte per 32 weights
       x.qkv_s = alloc(3 * D * D / 32); x.o_s = alloc(D * D / 32);
       x.fc1_s = alloc(F * D / 32); x.fc2_s = alloc(D * F / 32);
+    }
+    if (folds) {
+      x.qkv_c1 = alloc(4 * 3 * D); x.qkv_c2 = alloc(4 * 3 * D);
+      x.fc1_c1 = alloc(4 * F); x.fc1_c2 = alloc(4 * F);
     }
   }
   const size_t d_lnf_g = alloc(4 * D);
@@ -810,6 +869,17 @@ static vl_status build_weights(vl_model* m, const float* wdev, hipStream_t s, vl
     ly.fc1_s = q8 ? f(y.fc1_s) : nullptr; ly.fc2_s = q8 ? f(y.fc2_s) : nullptr;
     auto u8 = [&](size_t off) { return mx ? reinterpret_cast<const uint8_t*>(b + off) : nullptr; };
     ly.qkv_x = u8(y.qkv_s); ly.o_x = u8(y.o_s); ly.fc1_x = u8(y.fc1_s); ly.fc2_x = u8(y.fc2_s);
+    if (folds) {
+      // from the converted weights (stream order: after their conversion)
+      chk(ln_fold_consts(ly.qkv_w, q8, ly.qkv_s, ly.ln1_g, ly.ln1_b, ly.qkv_b, 3 * m->D, m->D,
+                         f(y.qkv_c1), f(y.qkv_c2), s),
+          "ln_fold_consts");
+      chk(ln_fold_consts(ly.fc1_w, q8, ly.fc1_s, ly.ln2_g, ly.ln2_b, ly.fc1_b, m->F, m->D,
+                         f(y.fc1_c1), f(y.fc1_c2), s),
+          "ln_fold_consts");
+      ly.qkv_c1 = f(y.qkv_c1); ly.qkv_c2 = f(y.qkv_c2);
+      ly.fc1_c1 = f(y.fc1_c1); ly.fc1_c2 = f(y.fc1_c2);
+    }
   }
   chk(copy_f32(s_lnf_g, f(d_lnf_g), D, s), "copy");
   chk(copy_f32(s_lnf_b, f(d_lnf_b), D, s), "copy");
@@ -969,6 +1039,10 @@ vl_status vl_model_set_option(vl_model* m, vl_option opt, int64_t value) {
     case VL_OPT_SPLIT:
       destroy_graphs(m);
       m->split = value != 0;
+      return VL_OK;
+    case VL_OPT_FUSED_LN:
+      destroy_graphs(m);
+      m->fused_ln = value != 0;
       return VL_OK;
   }
   return fail(VL_ERR_INVALID_ARG, "unknown option");
@@ -1179,9 +1253,20 @@ vl_status vl_model_autotune(vl_model* m, const float* pix, const int32_t* hs, co
       EpiArgs e2a; e2a.bias = ly.o_b; e2a.wscale = ly.o_s; e2a.out = X; e2a.ldo = D;
       EpiArgs e3a; e3a.bias = ly.fc1_b; e3a.wscale = ly.fc1_s; e3a.out = QH; e3a.ldo = F;
       EpiArgs e4a; e4a.bias = ly.fc2_b; e4a.wscale = ly.fc2_s; e4a.out = X; e4a.ldo = D;
-      shapes.push_back({OP_QKV, 3 * D, D, Y, D, ly.qkv_w, fp8, e1a});
+      const bf16_t* a_ln = Y;
+      if (m->fused_ln && m->prec != VL_MXFP8) {   // time the folded epilogues
+        bf16_t* U = reinterpret_cast<bf16_t*>(w + q.off_U);
+        float* RS = reinterpret_cast<float*>(w + q.off_RS);
+        a_ln = U;
+        e1a.row_stats = RS; e1a.c1 = ly.qkv_c1; e1a.c2 = ly.qkv_c2;
+        e3a.row_stats = RS; e3a.c1 = ly.fc1_c1; e3a.c2 = ly.fc1_c2;
+        e2a.u_out = U; e2a.u_gamma = ly.ln2_g;
+        e2a.part_stats = reinterpret_cast<float*>(w + q.off_PS);
+        e4a.u_out = U; e4a.u_gamma = ly.ln1_g; e4a.part_stats = e2a.part_stats;
+      }
+      shapes.push_back({OP_QKV, 3 * D, D, a_ln, D, ly.qkv_w, fp8, e1a});
       shapes.push_back({OP_OPROJ, D, D, Y, D, ly.o_w, fp8, e2a});
-      shapes.push_back({OP_FC1, F, D, Y, D, ly.fc1_w, fp8, e3a});
+      shapes.push_back({OP_FC1, F, D, a_ln, D, ly.fc1_w, fp8, e3a});
       shapes.push_back({OP_FC2, D, F, QH, F, ly.fc2_w, fp8, e4a});
       if (m->prec == VL_MXFP8) {
         const uint8_t* y8 = reinterpret_cast<const uint8_t*>(Y);

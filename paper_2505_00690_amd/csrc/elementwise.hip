@@ -71,6 +71,141 @@ hipError_t layernorm_rows(const float* x, const float* g, const float* b, float 
   return hipGetLastError();
 }
 
+// ------------------------------------------------- LayerNorm folding pieces
+// The first block's LayerNorm in folded form: row statistics as k_layernorm
+// takes them (FP32, two passes over registers), written as (mean, rstd),
+// and u = bf16(x * g).  One wave per row.
+template <int NPER>
+__global__ __launch_bounds__(256) void k_ln_fold(const float* __restrict__ x,
+                                                 const float* __restrict__ gm, float eps,
+                                                 bf16_t* __restrict__ u,
+                                                 float* __restrict__ st, int M) {
+  constexpr int D = NPER * 64;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= M) return;
+  const float* xr = x + (size_t)row * D;
+  float v[NPER];
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < NPER; ++i) {
+    v[i] = xr[lane + 64 * i];
+    s += v[i];
+  }
+  const float mean = wave_sum(s) * (1.f / D);
+  float q = 0.f;
+#pragma unroll
+  for (int i = 0; i < NPER; ++i) {
+    const float d = v[i] - mean;
+    q += d * d;
+  }
+  const float rstd = rsqrtf(wave_sum(q) * (1.f / D) + eps);
+#pragma unroll
+  for (int i = 0; i < NPER; ++i) {
+    const int c = lane + 64 * i;
+    u[(size_t)row * D + c] = (bf16_t)f32_to_bf16_bits(v[i] * gm[c]);
+  }
+  if (lane == 0) *reinterpret_cast<float2*>(st + 2 * (size_t)row) = make_float2(mean, rstd);
+}
+
+hipError_t ln_fold_rows(const float* x, const float* g, float eps, bf16_t* u, float* row_stats,
+                        int M, int D, hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  dim3 grid((M + 3) / 4), block(256);
+#define VL_LNF(N)                                                                       \
+  case N:                                                                               \
+    hipLaunchKernelGGL(k_ln_fold<N>, grid, block, 0, s, x, g, eps, u, row_stats, M); break;
+  switch (D / 64) {
+    VL_LNF(2) VL_LNF(4) VL_LNF(6) VL_LNF(8) VL_LNF(10) VL_LNF(12) VL_LNF(14) VL_LNF(16)
+    default: return hipErrorInvalidValue;
+  }
+#undef VL_LNF
+  return hipGetLastError();
+}
+
+// Row statistics from G = D/32 equal-size column groups' (mean_g, M2_g),
+// stored group-major ([G][M] pairs): mean = sum_g mean_g / G and M2 =
+// sum_g M2_g + 32 sum_g (mean_g - mean)^2 (the exact combination of
+// equal-size groups); then rstd = 1 / sqrt(M2 / D + eps).  Eight lanes per
+// row, lane j taking groups j, j + 8, ... in order, the lanes' sums added
+// in a fixed butterfly order.
+__global__ __launch_bounds__(256) void k_ln_stats(const float* __restrict__ parts, int M, int G,
+                                                  float eps, float* __restrict__ st) {
+  const int row = blockIdx.x * 32 + (threadIdx.x >> 3), j = threadIdx.x & 7;
+  const float2* pr = reinterpret_cast<const float2*>(parts) + min(row, M - 1);
+  float sm = 0.f;
+  for (int g = j; g < G; g += 8) sm += pr[(size_t)g * M].x;
+  sm += __shfl_xor(sm, 1, 64);
+  sm += __shfl_xor(sm, 2, 64);
+  sm += __shfl_xor(sm, 4, 64);
+  const float mean = sm / (float)G;
+  float t = 0.f;
+  for (int g = j; g < G; g += 8) {
+    const float2 v = pr[(size_t)g * M];
+    const float d = v.x - mean;
+    t += fmaf(32.f, d * d, v.y);
+  }
+  t += __shfl_xor(t, 1, 64);
+  t += __shfl_xor(t, 2, 64);
+  t += __shfl_xor(t, 4, 64);
+  if (row < M && j == 0)
+    *reinterpret_cast<float2*>(st + 2 * (size_t)row) =
+        make_float2(mean, rsqrtf(t / (float)(32 * G) + eps));
+}
+
+hipError_t ln_stats_from_parts(const float* parts, int M, int D, float eps, float* row_stats,
+                               hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ln_stats, dim3((M + 31) / 32), dim3(256), 0, s, parts, M, D / 32, eps,
+                     row_stats);
+  return hipGetLastError();
+}
+
+// c1[n] = sum_k g[k] W[n,k], c2[n] = sum_k b[k] W[n,k] + bias[n] with W the
+// GEMM's weights (BF16, or e4m3 codes times the row scale), FP32 sums in a
+// fixed order.  One workgroup per output row.
+template <bool FP8>
+__global__ __launch_bounds__(256) void k_ln_consts(const void* __restrict__ w,
+                                                   const float* __restrict__ ws,
+                                                   const float* __restrict__ g,
+                                                   const float* __restrict__ b,
+                                                   const float* __restrict__ bias, int K,
+                                                   float* __restrict__ c1,
+                                                   float* __restrict__ c2) {
+  __shared__ float red[4];
+  const int n = blockIdx.x;
+  float a = 0.f, c = 0.f;
+  for (int k = threadIdx.x; k < K; k += 256) {
+    float wv;
+    if (FP8)
+      wv = bf16_bits_to_f32(e4m3_to_bf16_bits(static_cast<const uint8_t*>(w)[(size_t)n * K + k]));
+    else
+      wv = bf16_bits_to_f32(static_cast<const bf16_t*>(w)[(size_t)n * K + k]);
+    a = fmaf(g[k], wv, a);
+    c = fmaf(b[k], wv, c);
+  }
+  auto sum = [](float x, float y) { return x + y; };
+  a = block_reduce(a, red, sum);
+  c = block_reduce(c, red, sum);
+  if (threadIdx.x == 0) {
+    const float sc = FP8 ? ws[n] : 1.f;
+    c1[n] = a * sc;
+    c2[n] = fmaf(c, sc, bias[n]);
+  }
+}
+
+hipError_t ln_fold_consts(const void* w, bool w_fp8, const float* wscale, const float* g,
+                          const float* b, const float* bias, int N, int K, float* c1, float* c2,
+                          hipStream_t s) {
+  if (w_fp8)
+    hipLaunchKernelGGL(k_ln_consts<true>, dim3(N), dim3(256), 0, s, w, wscale, g, b, bias, K, c1,
+                       c2);
+  else
+    hipLaunchKernelGGL(k_ln_consts<false>, dim3(N), dim3(256), 0, s, w, wscale, g, b, bias, K, c1,
+                       c2);
+  return hipGetLastError();
+}
+
 // LayerNorm with an MXFP8 output (the A operand of the next GEMM): as above,
 // but each lane holds float4 chunks lane + 64 i of the row, so a 32-column
 // MX block is 8 adjacent lanes.  D % 128 == 0, so the chunks in range form

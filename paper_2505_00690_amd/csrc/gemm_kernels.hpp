@@ -33,6 +33,13 @@ struct OpEpi {
                                                 : EPI_BIAS_RESID;
 };
 
+// LayerNorm-folded output (consumer side, see EpiArgs): one formula shared
+// by every kernel so all tile configurations agree bitwise.
+__device__ __forceinline__ float ln_fold1(float v, float ws, float c1, float c2, float mu,
+                                          float rstd) {
+  return __builtin_fmaf(rstd, __builtin_fmaf(v, ws, -(mu * c1)), c2);
+}
+
 template <int EPI, bool OUT_BF16>
 __device__ __forceinline__ void epi_store4(const EpiArgs& e, int m, int n, float v0, float v1,
                                            float v2, float v3) {
@@ -87,9 +94,19 @@ __device__ __forceinline__ void epi_store4(const EpiArgs& e, int m, int n, float
   // acc * weight scale + bias as one fused operation (scale 1 without
   // per-row weight scales); the staged epilogue of the direct-to-LDS kernel
   // does the same, so every configuration agrees bitwise.
-  const float4 b = *reinterpret_cast<const float4*>(e.bias + n);
-  v[0] = __builtin_fmaf(v[0], ws.x, b.x); v[1] = __builtin_fmaf(v[1], ws.y, b.y);
-  v[2] = __builtin_fmaf(v[2], ws.z, b.z); v[3] = __builtin_fmaf(v[3], ws.w, b.w);
+  if ((EPI == EPI_BIAS || EPI == EPI_BIAS_GELU) && e.row_stats) {
+    const float2 st = *reinterpret_cast<const float2*>(e.row_stats + 2 * (size_t)m);
+    const float4 a = *reinterpret_cast<const float4*>(e.c1 + n);
+    const float4 c = *reinterpret_cast<const float4*>(e.c2 + n);
+    v[0] = ln_fold1(v[0], ws.x, a.x, c.x, st.x, st.y);
+    v[1] = ln_fold1(v[1], ws.y, a.y, c.y, st.x, st.y);
+    v[2] = ln_fold1(v[2], ws.z, a.z, c.z, st.x, st.y);
+    v[3] = ln_fold1(v[3], ws.w, a.w, c.w, st.x, st.y);
+  } else {
+    const float4 b = *reinterpret_cast<const float4*>(e.bias + n);
+    v[0] = __builtin_fmaf(v[0], ws.x, b.x); v[1] = __builtin_fmaf(v[1], ws.y, b.y);
+    v[2] = __builtin_fmaf(v[2], ws.z, b.z); v[3] = __builtin_fmaf(v[3], ws.w, b.w);
+  }
   if (EPI == EPI_BIAS_RESID) {
     float4* X = reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n);
     float4 x = *X;
@@ -518,8 +535,19 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
   const int n = n0 + wn * WN + 4 * rc;
   const bool n_ok = n < N;
   float4 bias4 = make_float4(0.f, 0.f, 0.f, 0.f), ws4 = make_float4(1.f, 1.f, 1.f, 1.f);
+  // LayerNorm folding: consumer constants c1 / c2 (c2 in place of the bias),
+  // or the producer's next-LayerNorm gain (in bias4's place: unused there).
+  const bool fold_in = (EPI == EPI_BIAS || EPI == EPI_BIAS_GELU) && e.row_stats != nullptr;
+  const bool fold_out = EPI == EPI_BIAS_RESID && e.u_out != nullptr;
+  float4 c14 = make_float4(0.f, 0.f, 0.f, 0.f), g4 = c14;
   if (EPI != EPI_PATCH && EPI != EPI_SCALE_BIAS && n_ok) {
-    bias4 = *reinterpret_cast<const float4*>(e.bias + n);
+    if (fold_in) {
+      c14 = *reinterpret_cast<const float4*>(e.c1 + n);
+      bias4 = *reinterpret_cast<const float4*>(e.c2 + n);
+    } else {
+      bias4 = *reinterpret_cast<const float4*>(e.bias + n);
+    }
+    if (fold_out) g4 = *reinterpret_cast<const float4*>(e.u_gamma + n);
     if (e.wscale) ws4 = *reinterpret_cast<const float4*>(e.wscale + n);
   }
 #pragma unroll
@@ -551,6 +579,18 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
                                                     (size_t)m * e.ldo + n);
         }
       }
+      // LayerNorm-folded consumer: the batch's row statistics, loaded
+      // together so their latencies overlap.
+      float2 rs[NB];
+      if (EPI == EPI_BIAS || EPI == EPI_BIAS_GELU) {
+        if (fold_in) {
+#pragma unroll
+          for (int p = 0; p < NB; ++p) {
+            const int m = min(mb + (p0 + p) * RPP, M - 1);
+            rs[p] = *reinterpret_cast<const float2*>(e.row_stats + 2 * (size_t)m);
+          }
+        }
+      }
 #pragma unroll
       for (int p = 0; p < NB; ++p) {
         const int m = mb + (p0 + p) * RPP;
@@ -565,13 +605,44 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
                           e.alpha * v[p].z + e.beta, e.alpha * v[p].w + e.beta);
           continue;
         }
-        float4 y = make_float4(__builtin_fmaf(v[p].x, ws4.x, bias4.x),
-                               __builtin_fmaf(v[p].y, ws4.y, bias4.y),
-                               __builtin_fmaf(v[p].z, ws4.z, bias4.z),
-                               __builtin_fmaf(v[p].w, ws4.w, bias4.w));
+        float4 y;
+        if (fold_in) {
+          const float2 st = rs[p];
+          y = make_float4(ln_fold1(v[p].x, ws4.x, c14.x, bias4.x, st.x, st.y),
+                          ln_fold1(v[p].y, ws4.y, c14.y, bias4.y, st.x, st.y),
+                          ln_fold1(v[p].z, ws4.z, c14.z, bias4.z, st.x, st.y),
+                          ln_fold1(v[p].w, ws4.w, c14.w, bias4.w, st.x, st.y));
+        } else {
+          y = make_float4(__builtin_fmaf(v[p].x, ws4.x, bias4.x),
+                          __builtin_fmaf(v[p].y, ws4.y, bias4.y),
+                          __builtin_fmaf(v[p].z, ws4.z, bias4.z),
+                          __builtin_fmaf(v[p].w, ws4.w, bias4.w));
+        }
         if (EPI == EPI_BIAS_RESID) {
-          *reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n) =
-              make_float4(x[p].x + y.x, x[p].y + y.y, x[p].z + y.z, x[p].w + y.w);
+          const float4 xn = make_float4(x[p].x + y.x, x[p].y + y.y, x[p].z + y.z, x[p].w + y.w);
+          *reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n) = xn;
+          if (fold_out) {
+            // u = bf16(x * gamma) and the (mean, M2) of the row's 32-column
+            // group, which the 8 consecutive lanes rc = 8j .. 8j+7 hold
+            // (all with the same row, so all active together).
+            u32x2 pk;
+            pk.x = pack_bf16x2(xn.x * g4.x, xn.y * g4.y);
+            pk.y = pack_bf16x2(xn.z * g4.z, xn.w * g4.w);
+            *reinterpret_cast<u32x2*>(e.u_out + (size_t)m * e.ldo + n) = pk;
+            float sm = (xn.x + xn.y) + (xn.z + xn.w);
+            sm += __shfl_xor(sm, 1, 64);
+            sm += __shfl_xor(sm, 2, 64);
+            sm += __shfl_xor(sm, 4, 64);
+            const float mg = sm * (1.f / 32.f);
+            const float d0 = xn.x - mg, d1 = xn.y - mg, d2 = xn.z - mg, d3 = xn.w - mg;
+            float q = (d0 * d0 + d1 * d1) + (d2 * d2 + d3 * d3);
+            q += __shfl_xor(q, 1, 64);
+            q += __shfl_xor(q, 2, 64);
+            q += __shfl_xor(q, 4, 64);
+            if ((rc & 7) == 0)   // group-major: consecutive rows are adjacent
+              *reinterpret_cast<float2*>(e.part_stats + ((size_t)(n >> 5) * M + m) * 2) =
+                  make_float2(mg, q);
+          }
           continue;
         }
         if (EPI == EPI_BIAS_F32) {

@@ -51,6 +51,21 @@ struct EpiArgs {
   const float* pos = nullptr;      // [1 + g0*g0, D]
   int base_grid = 0;
   float alpha = 1.f, beta = 0.f;
+  // LayerNorm folded into the BF16 / e4m3-weight block GEMMs (not MXFP8).
+  // Producer (OP_OPROJ, OP_FC2 residual epilogues) with u_out: also writes
+  // u = bf16(x * u_gamma[n]) [M, ldo] of the updated residual x, and per row
+  // and 32-column group g the group's mean and sum of squared deviations
+  // (mean, M2) of x at part_stats[(g * M + m) * 2] (group-major).
+  bf16_t* u_out = nullptr;
+  const float* u_gamma = nullptr;
+  float* part_stats = nullptr;
+  // Consumer (OP_QKV, OP_FC1) with row_stats = (mean, rstd) per row of the
+  // LayerNorm input: y = rstd (acc * ws[n] - mean c1[n]) + c2[n] replaces
+  // acc * ws[n] + bias[n], where c1 = W gamma and c2 = W beta + bias
+  // (so y = LN(x) W^T + bias with the A operand u = x * gamma).
+  const float* row_stats = nullptr;
+  const float* c1 = nullptr;
+  const float* c2 = nullptr;
   // Split-K (BF16 GEMM, OP_LOGITS only): with kc > 0 the launch has
   // ceil(K / kc) splits in grid y; split z sums K columns [z kc, z kc + kc)
   // and writes its FP32 partial product at out + z * zstride.
@@ -115,6 +130,19 @@ hipError_t gemm_f32_rows(const float* A, int lda, const float* B, int ldb, int M
 // LayerNorm of FP32 rows [M, D] -> BF16 or FP32 rows.
 hipError_t layernorm_rows(const float* x, const float* g, const float* b, float eps,
                           void* y, bool y_bf16, int M, int D, hipStream_t s);
+
+// LayerNorm folding (see EpiArgs): for the first block, u = bf16(x * g) and
+// row_stats (mean, rstd) of x [M, D] directly; elsewhere row_stats from the
+// (mean, M2) partials of D/32 column groups a residual epilogue wrote.
+hipError_t ln_fold_rows(const float* x, const float* g, float eps, bf16_t* u, float* row_stats,
+                        int M, int D, hipStream_t s);
+hipError_t ln_stats_from_parts(const float* parts, int M, int D, float eps, float* row_stats,
+                               hipStream_t s);
+// c1[n] = sum_k g[k] W[n,k] and c2[n] = sum_k b[k] W[n,k] + bias[n] for the
+// weights as the GEMM uses them (BF16, or e4m3 codes times the row scale).
+hipError_t ln_fold_consts(const void* w, bool w_fp8, const float* wscale, const float* g,
+                          const float* b, const float* bias, int N, int K, float* c1, float* c2,
+                          hipStream_t s);
 
 // LayerNorm of FP32 rows [M, D] -> MXFP8 codes [M, D] + scales [D/128][M][4].
 hipError_t layernorm_rows_mx(const float* x, const float* g, const float* b, float eps,

@@ -33,7 +33,7 @@ __all__ = [
 
 VL_FP32, VL_BF16, VL_FP8W_BF16A, VL_MXFP8 = 0, 1, 2, 3
 VL_HEAD_SOFTMAX, VL_HEAD_SIGMOID = 0, 1
-VL_OPT_GRAPHS, VL_OPT_TIMING, VL_OPT_SPLIT = 0, 1, 2
+VL_OPT_GRAPHS, VL_OPT_TIMING, VL_OPT_SPLIT, VL_OPT_FUSED_LN = 0, 1, 2, 3
 VL_N_OPS = 8
 OP_NAMES = ("patch_embed", "layernorm", "qkv_gemm", "attention", "oproj_gemm", "fc1_gemm",
             "fc2_gemm", "pool_proj_l2")
@@ -545,7 +545,8 @@ class Encoder:
     a reusable workspace tensor."""
 
     def __init__(self, cfg, weights: torch.Tensor, precision: str = "bf16",
-                 graphs: bool = False, stream=None, split: bool = False):
+                 graphs: bool = False, stream=None, split: bool = False,
+                 fused_ln: bool = False):
         self.cfg = cfg
         self.precision = precision
         self.handle = vl_model_create(cfg, precision, weights, stream)
@@ -553,6 +554,8 @@ class Encoder:
             vl_model_set_option(self.handle, VL_OPT_GRAPHS, 1)
         if split:
             vl_model_set_option(self.handle, VL_OPT_SPLIT, 1)
+        if fused_ln:
+            vl_model_set_option(self.handle, VL_OPT_FUSED_LN, 1)
         self._ws: Optional[torch.Tensor] = None
         self.device = weights.device
         self._channels = int(getattr(cfg, "channels", 3))

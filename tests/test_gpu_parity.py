@@ -490,14 +490,48 @@ def test_serving_mix_equals_alone_l14_fp8w_mixed(V):
     _check_mix_equals_alone(V, enc, texts, reqs, st)
 
 
+# ---------------------------------------------------- LayerNorm folding
+@pytest.mark.parametrize("model,seed,precision,sizes", [
+    ("b16", 1001, "bf16", [(224, 224)] * 3 + [(336, 336), (448, 448)]),
+    ("tiny", 1000, "fp8w", [(64, 64)] * 5 + [(48, 80)]),
+])
+def test_fused_layernorm_against_unfused_and_oracle(V, model, seed, precision, sizes):
+    """The LayerNorms folded into the GEMMs (option on) against the standalone
+    LayerNorm kernels (the default) on the same model: the same function up to
+    rounding (cosine >= 0.9999 per image), and against the FP64 oracle at the
+    BF16 bar."""
+    imgs = synth.make_images(sizes, 2700 + seed)
+    pix = torch.from_numpy(pack(imgs)).cuda()
+    w = torch.from_numpy(blob(model, seed)).cuda()
+    a = V.Encoder(synth.MODELS[model], w, precision, fused_ln=True)
+    b = V.Encoder(synth.MODELS[model], w, precision)
+    ea = a.encode(pix, sizes).clone()
+    eb = b.encode(pix, sizes).clone()
+    torch.cuda.synchronize()
+    ga, gb = ea.cpu().numpy(), eb.cpu().numpy()
+    c_ab = cosine(ga, gb)
+    ref = oracle_emb(model, seed, precision, imgs)
+    _say(f"  {model} {precision}: folded vs unfolded min cos {c_ab.min():.7f}; vs oracle "
+         f"{cosine(ga, ref).min():.6f} / {cosine(gb, ref).min():.6f}")
+    assert not np.array_equal(ga, gb)            # the folded path is really taken
+    assert c_ab.min() >= 0.9999
+    assert cosine(ga, ref).min() >= COS_TOL
+    a.close()
+    b.close()
+
+
 # ------------------------------------------------------------- autotuner
-@pytest.mark.parametrize("precision", ["bf16", "fp8w", "mxfp8"])
-def test_every_gemm_config_bitwise_identical_and_autotune(V, precision):
+@pytest.mark.parametrize("precision,fused_ln", [("bf16", False), ("fp8w", False),
+                                                ("mxfp8", False), ("bf16", True),
+                                                ("fp8w", True)])
+def test_every_gemm_config_bitwise_identical_and_autotune(V, precision, fused_ln):
     """Each GEMM tile configuration, forced for every operation, gives the
     same bits; the autotuner's choice therefore changes speed only.  (A
     configuration of the other kind -- BF16 for an MXFP8 operation or the
-    reverse -- falls back to that operation's heuristic choice.)"""
-    enc = V.Encoder(synth.MODELS["b16"], torch.from_numpy(blob("b16", 1001)).cuda(), precision)
+    reverse -- falls back to that operation's heuristic choice.)  Also with
+    the LayerNorms folded into the GEMM epilogues."""
+    enc = V.Encoder(synth.MODELS["b16"], torch.from_numpy(blob("b16", 1001)).cuda(), precision,
+                    fused_ln=fused_ln)
     imgs = synth.make_images([(224, 224)] * 6 + [(336, 336)] * 2, 2500)
     pix = torch.from_numpy(pack(imgs)).cuda()
     sizes = sizes_of(imgs)

@@ -97,8 +97,11 @@ def _check_bf16(cfg, got, ref):
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_train_forward_equals_inference_bitwise(V, precision):
-    """The training forward keeps activations but runs the same kernels with
-    the same arithmetic: embeddings equal vl_encode_images bit for bit."""
+    """The training forward keeps activations (including the normalised
+    LayerNorm rows the weight gradients need, so its LayerNorms are not
+    folded into the GEMMs) and otherwise runs the inference kernels with the
+    same arithmetic: embeddings equal vl_encode_images bit for bit with the
+    LayerNorm folding off (the default), and within rounding with it on."""
     p = synth.make_params(SMALL, 60, std=0.1)
     blob = torch.from_numpy(synth.params_to_blob(SMALL, p)).cuda()
     sizes = [(64, 64)] * 5
@@ -106,8 +109,12 @@ def test_train_forward_equals_inference_bitwise(V, precision):
     tr = V.Trainer(SMALL, blob, precision)
     a = tr.forward(pix, sizes).clone()
     b = tr.encode(pix, sizes).clone()
+    V.vl_model_set_option(tr.handle, V.VL_OPT_FUSED_LN, 1)
+    folded = tr.encode(pix, sizes).clone()
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+    cos = (a * folded).sum(dim=1) / (a.norm(dim=1) * folded.norm(dim=1))
+    assert float(cos.min()) >= 0.9999
     tr.close()
 
 
