@@ -472,6 +472,25 @@ vl_status vl_contrastive_loss_noalloc(const float* emb_dev, const float* texts_d
                                       float* loss_dev, float* d_emb_dev, float* d_texts_dev,
                                       float* d_scale_bias_dev, void* stream);
 
+/* The number-format conversions of the reduced-precision paths, exposed so
+ * callers can prepare operands and check them.
+ * vl_bf16_round: FP32 -> BF16, round to nearest, ties to even, on n values
+ *   (n > 0, even; src 8-byte, dst 4-byte aligned; dst receives BF16 bit
+ *   patterns).  method 0: the integer rounding of the FP32 bit pattern
+ *   (add 0x7FFF plus the lowest kept bit, drop 16 bits) that the LayerNorm,
+ *   weight conversion and single-value stores use; method 1: the gfx950
+ *   packed conversion instruction (v_cvt_pk_bf16_f32) of the GEMM epilogues
+ *   and attention probabilities.  Finite inputs round identically; NaN
+ *   payloads are not specified.
+ * vl_fp8_quantize_rows: the VL_FP8W_BF16A weight quantiser on FP32 rows
+ *   [rows, cols]: scales[r] = max_c |src[r][c]| / 448 (1 for an all-zero
+ *   row), codes[r][c] = OCP e4m3fn code of src[r][c] / scales[r], rounded to
+ *   nearest even, saturating at +-448 (OFP8 rev 1.0, Sec. 5.1).           */
+vl_status vl_bf16_round(const float* src_dev, int64_t n, int32_t method, uint16_t* dst_dev,
+                        void* stream);
+vl_status vl_fp8_quantize_rows(const float* src_dev, int32_t rows, int32_t cols,
+                               uint8_t* codes_dev, float* scales_dev, void* stream);
+
 /* MXFP8 encoding (the one VL_MXFP8 applies to its weights and activations)
  * of FP32 rows, for callers that prepare operands themselves and for
  * checking the encoder.

@@ -1440,6 +1440,26 @@ vl_status vl_contrastive_loss_noalloc(const float* emb, const float* texts, int3
   return VL_OK;
 }
 
+vl_status vl_bf16_round(const float* src, int64_t n, int32_t method, uint16_t* dst,
+                        void* stream) {
+  if (!src || !dst) return fail(VL_ERR_INVALID_ARG, "NULL pointer argument");
+  if (n <= 0 || n % 2) return fail(VL_ERR_INVALID_ARG, "n must be positive and even");
+  if (method != 0 && method != 1) return fail(VL_ERR_INVALID_ARG, "method must be 0 or 1");
+  if (reinterpret_cast<uintptr_t>(src) % 8 || reinterpret_cast<uintptr_t>(dst) % 4)
+    return fail(VL_ERR_INVALID_ARG, "src must be 8-byte and dst 4-byte aligned");
+  VL_HIP(bf16_round(src, reinterpret_cast<bf16_t*>(dst), (size_t)n, method,
+                    static_cast<hipStream_t>(stream)));
+  return VL_OK;
+}
+
+vl_status vl_fp8_quantize_rows(const float* src, int32_t rows, int32_t cols, uint8_t* codes,
+                               float* scales, void* stream) {
+  if (!src || !codes || !scales) return fail(VL_ERR_INVALID_ARG, "NULL pointer argument");
+  if (rows <= 0 || cols <= 0) return fail(VL_ERR_INVALID_ARG, "rows and cols must be > 0");
+  VL_HIP(quantise_e4m3_rows(src, codes, scales, rows, cols, static_cast<hipStream_t>(stream)));
+  return VL_OK;
+}
+
 vl_status vl_score(const float* emb, int32_t n_images, const float* texts, int32_t n_texts,
                    int32_t dim, vl_head head, float scale, float bias, float* scores,
                    int32_t* top1, void* stream) {

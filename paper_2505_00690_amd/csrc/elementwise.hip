@@ -1,6 +1,8 @@
 // Row and elementwise kernels: LayerNorm, patch gathering, class-token
 // pooling with projection and L2 normalisation, scoring heads, and the
 // weight preparation done once per model.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace vl {
@@ -537,6 +539,33 @@ hipError_t quantise_e4m3_rows(const float* src, uint8_t* dst, float* scales, int
                               hipStream_t s) {
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_quant_e4m3, dim3(rows), dim3(256), 0, s, src, dst, scales, cols);
+  return hipGetLastError();
+}
+
+// FP32 -> BF16 as the kernels round: method 0 the integer round-to-nearest-
+// even of the bit pattern (LayerNorm outputs, weights, activations written
+// one value at a time), method 1 the packed conversion instruction
+// (v_cvt_pk_bf16_f32: GEMM epilogues, attention probabilities); n even.
+template <int METHOD>
+__global__ __launch_bounds__(256) void k_bf16_round(const float* __restrict__ src,
+                                                    uint32_t* __restrict__ dst, size_t n2) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += (size_t)gridDim.x * 256) {
+    const float2 v = reinterpret_cast<const float2*>(src)[i];
+    dst[i] = METHOD == 0 ? (f32_to_bf16_bits(v.x) | (f32_to_bf16_bits(v.y) << 16))
+                         : pack_bf16x2(v.x, v.y);
+  }
+}
+
+hipError_t bf16_round(const float* src, bf16_t* dst, size_t n, int method, hipStream_t s) {
+  const size_t n2 = n / 2;
+  if (n2 == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<size_t>((n2 + 255) / 256, 65536);
+  if (method == 0)
+    hipLaunchKernelGGL(k_bf16_round<0>, dim3(blocks), dim3(256), 0, s, src,
+                       reinterpret_cast<uint32_t*>(dst), n2);
+  else
+    hipLaunchKernelGGL(k_bf16_round<1>, dim3(blocks), dim3(256), 0, s, src,
+                       reinterpret_cast<uint32_t*>(dst), n2);
   return hipGetLastError();
 }
 

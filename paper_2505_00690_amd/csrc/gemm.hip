@@ -1,17 +1,21 @@
-// Dense contractions C[M,N] = A[M,K] . B[N,K]^T with fused epilogues.
+// Dense contractions C[M,N] = A[M,K] . B[N,K]^T with fused epilogues: the
+// configuration table, the tile heuristics and the launchers, plus the FP32
+// kernels.
 //
-// BF16 path: MFMA v_mfma_f32_32x32x16_bf16 on gfx950.  A workgroup owns a
-// BM x BN output tile and walks K in steps of 64 through double-buffered LDS
-// tiles; global loads of the next K step are issued before the MFMAs of the
-// current one.  LDS rows are 64 BF16 (128 B) with the eight 16-byte chunks of
-// a row XOR-swizzled by (row & 7), so the 32 rows one MFMA operand read
-// touches spread across the banks.  The weight tile feeds the MFMA's first
-// operand and the activation tile the second, so each lane ends up owning one
-// activation row and groups of four consecutive output columns: the
-// epilogue then reads bias / writes output with 8- or 16-byte vectors.
+// BF16 path (kernels in gemm_kernels.hpp): v_mfma_f32_32x32x16_bf16 on
+// gfx950.  A workgroup owns a BM x BN output tile and walks K in steps of 64
+// through a ring of two or three LDS stages filled by direct-to-LDS loads
+// (buffer_load ... lds, 16 bytes per lane) issued one or two K steps ahead.
+// LDS rows are 64 BF16 (128 B) whose eight 16-byte chunks are permuted by
+// XOR with (r ^ (r >> 3)) & 7, so the operand reads of an MFMA are free of
+// bank conflicts.  Output tiles are dealt XCD by XCD.  The epilogue stages
+// each 32-row slab of a wave's tile through LDS and stores rows whole.  All
+// configurations accumulate K in the same order, so they agree bitwise; the
+// per-configuration instantiations live in gemm_cfg*.hip / gemm_mx_cfg*.hip.
 //
-// FP32 path: classic LDS-tiled FMA kernel (64 x 64 tile, 4 x 4 per thread),
-// the plain FP32 baseline and the logit GEMM of the scoring head.
+// FP32 path: LDS-tiled FMA kernel (64 x 64 tile, 4 x 4 per thread), the plain
+// FP32 baseline; and a few-rows FP32 kernel for the heads' small products
+// (pooled rows or embeddings against the projection or the texts).
 #include "gemm_kernels.hpp"
 
 namespace vl {

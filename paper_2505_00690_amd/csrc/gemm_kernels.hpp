@@ -1,17 +1,15 @@
-// Dense contractions (kernel templates) C[M,N] = A[M,K] . B[N,K]^T with fused epilogues.
+// Dense contractions (kernel templates) C[M,N] = A[M,K] . B[N,K]^T with
+// fused epilogues: bias, GELU, residual add, patch-embedding class-token and
+// position add, per-row weight scales (e4m3 weights), the folded-LayerNorm
+// forms and split-K partial products.
 //
-// BF16 path: MFMA v_mfma_f32_32x32x16_bf16 on gfx950.  A workgroup owns a
-// BM x BN output tile and walks K in steps of 64 through double-buffered LDS
-// tiles; global loads of the next K step are issued before the MFMAs of the
-// current one.  LDS rows are 64 BF16 (128 B) with the eight 16-byte chunks of
-// a row XOR-swizzled by (row & 7), so the 32 rows one MFMA operand read
-// touches spread across the banks.  The weight tile feeds the MFMA's first
-// operand and the activation tile the second, so each lane ends up owning one
-// activation row and groups of four consecutive output columns: the
-// epilogue then reads bias / writes output with 8- or 16-byte vectors.
-//
-// FP32 path: classic LDS-tiled FMA kernel (64 x 64 tile, 4 x 4 per thread),
-// the plain FP32 baseline and the logit GEMM of the scoring head.
+// k_gemm_bf16_dl (the kernel every BF16 configuration uses but one):
+// direct-to-LDS tile loads into a two- or three-stage ring, chunk swizzle
+// (r ^ (r >> 3)) & 7, one LDS fragment read interleaved with each MFMA, the
+// last K sub-step's MFMAs issued after the barrier, XCD-aware tile order, and
+// an LDS-staged epilogue that stores whole rows.  k_gemm_bf16: the older
+// register-staged kernel (configuration REG_128x128), kept as a reference
+// configuration.  Both give the same bits.
 // BF16 / FP32 GEMM kernel templates shared by the per-configuration
 // translation units (gemm_cfg_*.hip) and the FP32 unit (gemm.hip).
 #pragma once

@@ -254,6 +254,10 @@ hipError_t fill_zero(float* p, size_t n, hipStream_t s);
 // out[i] = sum over z = 0 .. splits-1 (ascending) of part[z * n + i].
 hipError_t sum_splits(const float* part, int splits, size_t n, float* out, hipStream_t s);
 
+// FP32 -> BF16 rounding as the kernels do it (method 0: integer RNE of the
+// bit pattern; 1: the packed conversion instruction).  n even.
+hipError_t bf16_round(const float* src, bf16_t* dst, size_t n, int method, hipStream_t s);
+
 // Weight preparation.
 hipError_t convert_bf16(const float* src, bf16_t* dst, size_t n, hipStream_t s);
 hipError_t quantise_e4m3_rows(const float* src, uint8_t* dst, float* scales, int rows,

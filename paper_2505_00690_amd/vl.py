@@ -29,6 +29,7 @@ __all__ = [
     "vl_attention_workspace_bytes", "vl_attention", "vl_model_save_tuning",
     "vl_model_load_tuning", "vl_contrastive_loss_noalloc", "VL_NOALLOC_SCRATCH_BYTES",
     "vl_train_workspace_bytes", "vl_encode_images_train", "vl_encode_images_backward", "Trainer",
+    "vl_bf16_round", "vl_fp8_quantize_rows",
 ]
 
 VL_FP32, VL_BF16, VL_FP8W_BF16A, VL_MXFP8 = 0, 1, 2, 3
@@ -52,7 +53,7 @@ EXPORTED_SYMBOLS = (
     "vl_gemm_config_count", "vl_gemm_config_name", "vl_model_get_tuning",
     "vl_model_set_tuning", "vl_model_autotune", "vl_model_save_tuning", "vl_model_load_tuning",
     "vl_contrastive_loss_noalloc", "vl_train_workspace_bytes", "vl_encode_images_train",
-    "vl_encode_images_backward",
+    "vl_encode_images_backward", "vl_bf16_round", "vl_fp8_quantize_rows",
 )
 VL_NOALLOC_SCRATCH_BYTES = 64 << 20
 VL_N_GEMM_OPS, VL_N_M_BUCKETS = 5, 25
@@ -169,6 +170,10 @@ def lib() -> ctypes.CDLL:
     L.vl_contrastive_loss.restype = ctypes.c_int
     L.vl_contrastive_loss.argtypes = [_vp, _vp, _i32, _i32, ctypes.c_int, _f32, _f32, _vp, _vp,
                                       _vp, _vp, _vp, _sz, _vp]
+    L.vl_bf16_round.restype = ctypes.c_int
+    L.vl_bf16_round.argtypes = [_vp, ctypes.c_int64, _i32, _vp, _vp]
+    L.vl_fp8_quantize_rows.restype = ctypes.c_int
+    L.vl_fp8_quantize_rows.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp]
     L.vl_train_workspace_bytes.restype = _sz
     L.vl_train_workspace_bytes.argtypes = [_vp, _i32, _pi32, _pi32]
     L.vl_encode_images_train.restype = ctypes.c_int
@@ -506,6 +511,23 @@ def vl_mx_gemm(a: torch.Tensor, sa: torch.Tensor, b: torch.Tensor, sb: torch.Ten
                             _ptr(b, torch.uint8, "b"), _ptr(sb, torch.uint8, "sb"), M, N, K,
                             _ptr(bias, torch.float32, "bias"), _ptr(c, torch.float32, "c"),
                             int(cfg), _stream(stream)))
+
+
+def vl_bf16_round(src: torch.Tensor, dst: torch.Tensor, method: int = 0, stream=None) -> None:
+    """FP32 -> BF16 bit patterns (int16 / uint16 tensor of src's size)."""
+    if src.numel() != dst.numel() or dst.element_size() != 2:
+        raise ValueError("dst must hold src.numel() 16-bit values")
+    _check(lib().vl_bf16_round(_ptr(src, torch.float32, "src"), src.numel(), int(method),
+                               _ptr(dst, None, "dst"), _stream(stream)))
+
+
+def vl_fp8_quantize_rows(src: torch.Tensor, codes: torch.Tensor, scales: torch.Tensor,
+                         stream=None) -> None:
+    rows, cols = src.shape
+    _need(codes, "codes", shape=(rows, cols), dtype=torch.uint8)
+    _need(scales, "scales", shape=(rows,), dtype=torch.float32)
+    _check(lib().vl_fp8_quantize_rows(_ptr(src, torch.float32, "src"), rows, cols,
+                                      _ptr(codes), _ptr(scales), _stream(stream)))
 
 
 def vl_train_workspace_bytes(handle, heights: Sequence[int], widths: Sequence[int]) -> int:
