@@ -386,6 +386,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-text", action="store_true", help="skip the text-tower leg")
     ap.add_argument("--no-rgbd", action="store_true", help="skip the RGB-D observation leg")
     ap.add_argument("--text-steps", type=int, default=5)
+    ap.add_argument("--no-attn-resident", action="store_true",
+                    help="stream key / value tiles per 128-query block for every image")
     ap.add_argument("--fused-ln", action="store_true",
                     help="fold the LayerNorms into the GEMMs (measured slower; off by default)")
     ap.add_argument("--no-train", action="store_true",
@@ -460,6 +462,8 @@ def main(argv=None) -> int:
     def make_encoder(two_parts: bool):
         e = vl.Encoder(c, w, prec, graphs=not args.no_graphs, split=two_parts,
                        fused_ln=args.fused_ln)
+        if args.no_attn_resident:
+            vl.vl_model_set_option(e.handle, vl.VL_OPT_ATTN_RESIDENT, 0)
         t = None
         if prec != "fp32" and named:
             e.set_tuning(named)

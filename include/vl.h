@@ -256,9 +256,17 @@ vl_status vl_encode_texts(vl_model* m, const int32_t* ids_dev, const int32_t* le
  *                   (Measured on MI355X at ViT-L/14@336, batch 32: the
  *                   LayerNorm time falls but the four GEMMs lose more, ~5 %
  *                   slower per step, hence off.)  Changing it drops cached
+ *                   graphs.
+ *   VL_OPT_ATTN_RESIDENT : on by default (BF16 attention at head width 64,
+ *                   image towers).  Images of 129 .. 640 tokens run their
+ *                   attention with one workgroup per (image, head) that
+ *                   loads the head's keys and values into LDS once and
+ *                   serves every query of the image from them; other images
+ *                   stream key / value tiles per block of 128 queries.  Both
+ *                   forms give the same bits.  Changing it drops cached
  *                   graphs.                                                 */
 typedef enum vl_option { VL_OPT_GRAPHS = 0, VL_OPT_TIMING = 1, VL_OPT_SPLIT = 2,
-                         VL_OPT_FUSED_LN = 3 } vl_option;
+                         VL_OPT_FUSED_LN = 3, VL_OPT_ATTN_RESIDENT = 4 } vl_option;
 vl_status vl_model_set_option(vl_model* m, vl_option opt, int64_t value);
 
 /* Operations of the encoder, as reported by vl_model_op_times:

@@ -47,6 +47,8 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 constexpr int kMaxTokens = 1025;   // 32 x 32 patches + class token
 constexpr int kAttnQ = 128;        // queries per attention work item
+constexpr int kResMinTokens = 128; // K/V-resident attention: more tokens than one work item
+constexpr int kResMaxTiles = 10;   //   and at most 10 key tiles of 64 (the 160 KB of LDS)
 constexpr int kMaxItems = 65535;   // images / texts per call (grid y of the gather kernels)
 
 struct Layer {
@@ -129,6 +131,9 @@ struct vl_model {
   // models; VL_OPT_FUSED_LN, off by default: on MI355X the extra epilogue
   // output costs the GEMMs more than the standalone LayerNorms take).
   bool fused_ln = false;
+  // K/V-resident attention for images of 129 .. 640 tokens (BF16 attention,
+  // head width 64, not causal; VL_OPT_ATTN_RESIDENT, on by default).
+  bool attn_resident = true;
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int32_t tuning[VL_N_GEMM_OPS][VL_N_M_BUCKETS];
@@ -204,6 +209,10 @@ constexpr int64_t kSplitMinTokens = 4096;  // split batches of at least this man
 struct Part {
   int i0 = 0, n = 0, T = 0, max_ntok = 0, n_items = 0;
   size_t off_imgs = 0, off_items = 0;                       // in the descriptor region
+  // Images whose attention runs K/V-resident (indices within the part) and
+  // the largest of their key-tile counts.
+  size_t off_res = 0;
+  int n_res = 0, res_tiles = 0;
   size_t off_tok = 0, off_X = 0, off_Y = 0, off_QH = 0, off_E = 0;  // in the workspace
   size_t off_map = 0;   // MAP pooling: per image O, x, LN(x) [n, D] and MLP hidden [n, F]
   // LayerNorm folding: u = bf16(x * gamma) [T, D], per-32-column (mean, M2)
@@ -240,6 +249,8 @@ bool finish_plan(const vl_model* m, std::vector<ImgDesc>& imgs, int64_t T, Plan*
   auto a16 = [](size_t x) { return (x + 15) / 16 * 16; };
   p->parts.clear();
   std::vector<std::vector<AttnItem>> items(cut.size() - 1);
+  std::vector<std::vector<int32_t>> res(cut.size() - 1);
+  const bool res_ok = m->attn_resident && m->prec != VL_FP32 && m->hd == 64 && !m->text;
   size_t doff = 0;
   for (size_t k = 0; k + 1 < cut.size(); ++k) {
     Part q;
@@ -250,13 +261,22 @@ bool finish_plan(const vl_model* m, std::vector<ImgDesc>& imgs, int64_t T, Plan*
       imgs[i].tok_start -= t0;
       q.T += imgs[i].ntok;
       q.max_ntok = std::max<int>(q.max_ntok, imgs[i].ntok);
-      for (int q0 = 0; q0 < imgs[i].ntok; q0 += kAttnQ) items[k].push_back(AttnItem{i - q.i0, q0});
+      const int nt = imgs[i].ntok;
+      if (res_ok && nt > kResMinTokens && nt <= 64 * kResMaxTiles) {
+        res[k].push_back(i - q.i0);
+        q.res_tiles = std::max(q.res_tiles, (nt + 63) / 64);
+      } else {
+        for (int q0 = 0; q0 < nt; q0 += kAttnQ) items[k].push_back(AttnItem{i - q.i0, q0});
+      }
     }
     q.n_items = (int)items[k].size();
+    q.n_res = (int)res[k].size();
     q.off_imgs = doff;
     doff = a16(doff + sizeof(ImgDesc) * q.n);
     q.off_items = doff;
     doff = a16(doff + sizeof(AttnItem) * q.n_items);
+    q.off_res = doff;
+    doff = a16(doff + sizeof(int32_t) * q.n_res);
     p->parts.push_back(q);
   }
   p->desc_bytes = doff;
@@ -265,6 +285,7 @@ bool finish_plan(const vl_model* m, std::vector<ImgDesc>& imgs, int64_t T, Plan*
     const Part& q = p->parts[k];
     std::memcpy(p->desc.data() + q.off_imgs, imgs.data() + q.i0, sizeof(ImgDesc) * q.n);
     std::memcpy(p->desc.data() + q.off_items, items[k].data(), sizeof(AttnItem) * q.n_items);
+    std::memcpy(p->desc.data() + q.off_res, res[k].data(), sizeof(int32_t) * q.n_res);
   }
   // Workspace: the descriptor region, then each part's activation regions.
   const size_t es = m->prec == VL_FP32 ? 4 : 2;
@@ -449,6 +470,7 @@ vl_status run_part(vl_model* m, const Part& p, const void* in, float* emb, char*
   const bool mx = m->prec == VL_MXFP8;
   const ImgDesc* d_imgs = reinterpret_cast<const ImgDesc*>(ws + p.off_imgs);
   const AttnItem* d_items = reinterpret_cast<const AttnItem*>(ws + p.off_items);
+  const int* d_res = reinterpret_cast<const int*>(ws + p.off_res);
   int2* tok = reinterpret_cast<int2*>(ws + p.off_tok);
   float* X = reinterpret_cast<float*>(ws + p.off_X);
   void* Y = ws + p.off_Y;
@@ -505,8 +527,12 @@ vl_status run_part(vl_model* m, const Part& p, const void* in, float* emb, char*
       VL_TIMED(T_QKV, VL_HIP(gemm_bf16(U, D, ly.qkv_w, D, fp8, T, 3 * D, D, OP_QKV,
                                        gemm_cfg_for(m, 1, T), e1, s)));
       if (after_first_qkv && li == 0) VL_HIP(hipEventRecord(after_first_qkv, s));
-      VL_TIMED(T_ATTN, VL_HIP(attention_bf16(qh, static_cast<bf16_t*>(Y), d_imgs, d_items,
-                                             p.n_items, m->heads, m->hd, m->text, s)));
+      VL_TIMED(T_ATTN, {
+        VL_HIP(attention_bf16(qh, static_cast<bf16_t*>(Y), d_imgs, d_items, p.n_items, m->heads,
+                              m->hd, m->text, s));
+        VL_HIP(attention_bf16_resident(qh, Y, nullptr, false, T, d_imgs, d_res, p.n_res,
+                                       p.res_tiles, m->heads, m->hd, s));
+      });
       VL_TIMED(T_OPROJ, VL_HIP(gemm_bf16(static_cast<const bf16_t*>(Y), D, ly.o_w, D, fp8, T, D,
                                          D, OP_OPROJ, gemm_cfg_for(m, 2, T), e2, s)));
       VL_TIMED(T_LN, VL_HIP(ln_stats_from_parts(PS, T, D, eps, RS, s)));
@@ -558,9 +584,12 @@ vl_status run_part(vl_model* m, const Part& p, const void* in, float* emb, char*
       VL_TIMED(T_QKV, VL_HIP(gemm_mx(y8, ys, w8[0], ly.qkv_x, T, 3 * D, D, OP_QKV,
                                      gemm_cfg_for(m, 1, T), e1, s)));
       if (after_first_qkv && &ly == &m->layers[0]) VL_HIP(hipEventRecord(after_first_qkv, s));
-      VL_TIMED(T_ATTN, VL_HIP(attention_bf16_mx(static_cast<const bf16_t*>(QH), y8, ys, T, d_imgs,
-                                                d_items, p.n_items, m->heads, m->hd, m->text,
-                                                s)));
+      VL_TIMED(T_ATTN, {
+        VL_HIP(attention_bf16_mx(static_cast<const bf16_t*>(QH), y8, ys, T, d_imgs, d_items,
+                                 p.n_items, m->heads, m->hd, m->text, s));
+        VL_HIP(attention_bf16_resident(static_cast<const bf16_t*>(QH), y8, ys, true, T, d_imgs,
+                                       d_res, p.n_res, p.res_tiles, m->heads, m->hd, s));
+      });
       VL_TIMED(T_OPROJ, VL_HIP(gemm_mx(y8, ys, w8[1], ly.o_x, T, D, D, OP_OPROJ,
                                        gemm_cfg_for(m, 2, T), e2, s)));
       VL_TIMED(T_LN, VL_HIP(layernorm_rows_mx(X, ly.ln2_g, ly.ln2_b, eps, y8, ys, T, D, s)));
@@ -574,8 +603,12 @@ vl_status run_part(vl_model* m, const Part& p, const void* in, float* emb, char*
       VL_TIMED(T_QKV, VL_HIP(gemm_bf16(y, D, ly.qkv_w, D, fp8, T, 3 * D, D, OP_QKV,
                                        gemm_cfg_for(m, 1, T), e1, s)));
       if (after_first_qkv && &ly == &m->layers[0]) VL_HIP(hipEventRecord(after_first_qkv, s));
-      VL_TIMED(T_ATTN, VL_HIP(attention_bf16(qh, static_cast<bf16_t*>(Y), d_imgs, d_items,
-                                             p.n_items, m->heads, m->hd, m->text, s)));
+      VL_TIMED(T_ATTN, {
+        VL_HIP(attention_bf16(qh, static_cast<bf16_t*>(Y), d_imgs, d_items, p.n_items, m->heads,
+                              m->hd, m->text, s));
+        VL_HIP(attention_bf16_resident(qh, Y, nullptr, false, T, d_imgs, d_res, p.n_res,
+                                       p.res_tiles, m->heads, m->hd, s));
+      });
       VL_TIMED(T_OPROJ, VL_HIP(gemm_bf16(y, D, ly.o_w, D, fp8, T, D, D, OP_OPROJ,
                                          gemm_cfg_for(m, 2, T), e2, s)));
       VL_TIMED(T_LN, VL_HIP(layernorm_rows(X, ly.ln2_g, ly.ln2_b, eps, Y, true, T, D, s)));
@@ -1044,6 +1077,10 @@ vl_status vl_model_set_option(vl_model* m, vl_option opt, int64_t value) {
       destroy_graphs(m);
       m->fused_ln = value != 0;
       return VL_OK;
+    case VL_OPT_ATTN_RESIDENT:
+      destroy_graphs(m);
+      m->attn_resident = value != 0;
+      return VL_OK;
   }
   return fail(VL_ERR_INVALID_ARG, "unknown option");
 }
@@ -1490,14 +1527,24 @@ namespace {
 
 constexpr int kMaxAttnLen = 4096;  // longest sequence vl_attention accepts
 
-// Descriptor blob of a vl_attention call: sequence descriptors then the
-// 128-query work items (16-byte aligned), as the encoder lays them out.
-bool attention_plan(int32_t n, const int32_t* lens, std::vector<char>* desc, size_t* off_items,
-                    int* n_items, int64_t* T, std::string* why) {
+// Descriptor blob of a vl_attention call: sequence descriptors, the
+// 128-query work items, then the sequences that run K/V-resident (each part
+// 16-byte aligned), as the encoder lays them out.  resident: whether
+// sequences of 129 .. 640 tokens go to the resident kernel.
+struct AttnPlan {
+  std::vector<char> desc;
+  size_t off_items = 0, off_res = 0;
+  int n_items = 0, n_res = 0, res_tiles = 0;
+  int64_t T = 0;
+};
+
+bool attention_plan(int32_t n, const int32_t* lens, bool resident, AttnPlan* ap,
+                    std::string* why) {
   if (n <= 0 || n > kMaxItems) { *why = "n_seqs must be 1..65535"; return false; }
   if (!lens) { *why = "lengths is NULL"; return false; }
   std::vector<ImgDesc> seqs(n);
   std::vector<AttnItem> items;
+  std::vector<int32_t> res;
   int64_t t = 0;
   for (int i = 0; i < n; ++i) {
     if (lens[i] < 1 || lens[i] > kMaxAttnLen) {
@@ -1510,17 +1557,25 @@ bool attention_plan(int32_t n, const int32_t* lens, std::vector<char>* desc, siz
     d.H = d.W = d.gh = d.gw = 0;
     d.tok_start = (int32_t)t;
     d.ntok = lens[i];
-    for (int q0 = 0; q0 < lens[i]; q0 += kAttnQ) items.push_back(AttnItem{i, q0});
+    if (resident && lens[i] > kResMinTokens && lens[i] <= 64 * kResMaxTiles) {
+      res.push_back(i);
+      ap->res_tiles = std::max(ap->res_tiles, (lens[i] + 63) / 64);
+    } else {
+      for (int q0 = 0; q0 < lens[i]; q0 += kAttnQ) items.push_back(AttnItem{i, q0});
+    }
     t += lens[i];
   }
   if (t > (1LL << 24)) { *why = "more than 2^24 tokens"; return false; }
-  const size_t a = (sizeof(ImgDesc) * n + 15) / 16 * 16;
-  desc->assign(a + sizeof(AttnItem) * items.size(), 0);
-  std::memcpy(desc->data(), seqs.data(), sizeof(ImgDesc) * n);
-  std::memcpy(desc->data() + a, items.data(), sizeof(AttnItem) * items.size());
-  *off_items = a;
-  *n_items = (int)items.size();
-  *T = t;
+  auto a16 = [](size_t x) { return (x + 15) / 16 * 16; };
+  ap->off_items = a16(sizeof(ImgDesc) * n);
+  ap->off_res = a16(ap->off_items + sizeof(AttnItem) * items.size());
+  ap->desc.assign(ap->off_res + sizeof(int32_t) * res.size(), 0);
+  std::memcpy(ap->desc.data(), seqs.data(), sizeof(ImgDesc) * n);
+  std::memcpy(ap->desc.data() + ap->off_items, items.data(), sizeof(AttnItem) * items.size());
+  std::memcpy(ap->desc.data() + ap->off_res, res.data(), sizeof(int32_t) * res.size());
+  ap->n_items = (int)items.size();
+  ap->n_res = (int)res.size();
+  ap->T = t;
   return true;
 }
 
@@ -1529,13 +1584,11 @@ bool attention_plan(int32_t n, const int32_t* lens, std::vector<char>* desc, siz
 extern "C" {
 
 size_t vl_attention_workspace_bytes(int32_t n_seqs, const int32_t* lengths) {
-  std::vector<char> desc;
-  size_t off = 0;
-  int n_items = 0;
-  int64_t T = 0;
+  AttnPlan ap;
   std::string why;
-  if (!attention_plan(n_seqs, lengths, &desc, &off, &n_items, &T, &why)) return 0;
-  return align_up(desc.size());
+  if (!attention_plan(n_seqs, lengths, false, &ap, &why)) return 0;
+  // an upper bound for every precision: all work items plus a resident list
+  return align_up(ap.desc.size() + sizeof(int32_t) * (size_t)n_seqs + 16);
 }
 
 vl_status vl_attention(const void* qkv, vl_precision prec, const int32_t* lengths, int32_t n_seqs,
@@ -1549,13 +1602,11 @@ vl_status vl_attention(const void* qkv, vl_precision prec, const int32_t* length
   auto al = [](const void* p, uintptr_t k) { return reinterpret_cast<uintptr_t>(p) % k == 0; };
   if (!al(qkv, 16) || !al(out, 16) || !al(ws, kAlign))
     return fail(VL_ERR_INVALID_ARG, "qkv and out must be 16-byte, the workspace 256-byte aligned");
-  std::vector<char> desc;
-  size_t off_items = 0;
-  int n_items = 0;
-  int64_t T = 0;
+  AttnPlan ap;
   std::string why;
-  if (!attention_plan(n_seqs, lengths, &desc, &off_items, &n_items, &T, &why))
-    return fail(VL_ERR_INVALID_ARG, why);
+  const bool resident = prec == VL_BF16 && head_dim == 64 && causal == 0;
+  if (!attention_plan(n_seqs, lengths, resident, &ap, &why)) return fail(VL_ERR_INVALID_ARG, why);
+  const std::vector<char>& desc = ap.desc;
   if (ws_bytes < align_up(desc.size()))
     return fail(VL_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1570,13 +1621,17 @@ vl_status vl_attention(const void* qkv, vl_precision prec, const int32_t* length
     if (st != VL_OK) return st;
   }
   const ImgDesc* d_seqs = reinterpret_cast<const ImgDesc*>(w);
-  const AttnItem* d_items = reinterpret_cast<const AttnItem*>(w + off_items);
-  if (prec == VL_BF16)
+  const AttnItem* d_items = reinterpret_cast<const AttnItem*>(w + ap.off_items);
+  if (prec == VL_BF16) {
     VL_HIP(attention_bf16(static_cast<const bf16_t*>(qkv), static_cast<bf16_t*>(out), d_seqs,
-                          d_items, n_items, heads, head_dim, causal != 0, s));
-  else
+                          d_items, ap.n_items, heads, head_dim, causal != 0, s));
+    VL_HIP(attention_bf16_resident(static_cast<const bf16_t*>(qkv), out, nullptr, false,
+                                   (int)ap.T, d_seqs, reinterpret_cast<const int*>(w + ap.off_res),
+                                   ap.n_res, ap.res_tiles, heads, head_dim, s));
+  } else {
     VL_HIP(attention_f32(static_cast<const float*>(qkv), static_cast<float*>(out), d_seqs,
-                         d_items, n_items, heads, head_dim, causal != 0, s));
+                         d_items, ap.n_items, heads, head_dim, causal != 0, s));
+  }
   return VL_OK;
 }
 
@@ -1939,6 +1994,9 @@ vl_status run_train_forward(vl_model* m, const TrainPlan& tp, const float* pix, 
                        gemm_cfg_for(m, 1, T), e1, s));
       VL_HIP(attention_bf16(static_cast<const bf16_t*>(qkv), static_cast<bf16_t*>(o), d_imgs,
                             d_items, p.n_items, m->heads, m->hd, false, s));
+      VL_HIP(attention_bf16_resident(static_cast<const bf16_t*>(qkv), o, nullptr, false, T,
+                                     d_imgs, reinterpret_cast<const int*>(ws + p.off_res),
+                                     p.n_res, p.res_tiles, m->heads, m->hd, s));
       VL_HIP(gemm_bf16(static_cast<const bf16_t*>(o), D, ly.o_w, D, false, T, D, D, OP_OPROJ,
                        gemm_cfg_for(m, 2, T), e2, s));
     }

@@ -318,6 +318,286 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
     }
 }
 
+// ------------------------------------------------ BF16, K/V resident in LDS
+// For images of 129 .. 64 NT tokens at head width 64: one workgroup of eight
+// waves per (image, head) loads that head's keys and values into LDS once (NT
+// tiles of 64 tokens, 16 KB per tile pair; NT = 10 fills the 160 KB) and
+// runs every query of the image against them, 32 queries per wave at a time.
+// The first pass (queries 0 .. 255) consumes the tiles as they land, loads
+// issued two tiles ahead as in the streaming kernel; later passes find all
+// tiles resident.  Each query's arithmetic (score MFMAs, lazy rescale,
+// exponentials, P^T V^T MFMAs, in key-tile order) is the streaming kernel's,
+// so the outputs are bitwise the same; what changes is that keys and values
+// cross from L2 into LDS once per (image, head) instead of once per
+// 128-query block.
+constexpr int RES_W = 8;   // waves per resident workgroup
+
+template <int NT, bool MX>
+__global__ __launch_bounds__(RES_W * 64) void k_attn_bf16_res(
+    const bf16_t* __restrict__ qkv, void* __restrict__ out, uint8_t* __restrict__ out_scale,
+    int T_rows, const ImgDesc* __restrict__ imgs, const int* __restrict__ res_imgs, int heads) {
+  constexpr int HD = 64;
+  using T = KvTile<HD, false>;
+  using TV = KvTile<HD, true>;
+  constexpr int RPI = 1024 / T::ROWB;          // tile rows per 1 KB load instruction
+  constexpr int LPW = ATT_KV / RPI / RES_W;    // K (and V) load instructions per wave per tile
+  static_assert(LPW >= 1 && LPW * RPI * RES_W == ATT_KV, "tile / waves");
+  __shared__ __attribute__((aligned(1024))) char sK[NT][T::BYTES];
+  __shared__ __attribute__((aligned(1024))) char sV[NT][T::BYTES];
+
+  const int n_res = gridDim.x / heads;
+  const int wi = xcd_linear(blockIdx.x, gridDim.x);
+  const int img = res_imgs[wi % n_res];
+  const int h = wi / n_res;
+  const ImgDesc dsc = imgs[img];
+  const int N = dsc.ntok;
+  const int D = heads * HD;
+  const int ld = 3 * D;
+  const bf16_t* base = qkv + (size_t)dsc.tok_start * ld;
+  const bf16_t* Qp = base + h * HD;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l32 = lane & 31, g = lane >> 5;
+
+  const i32x4 rk = buffer_rsrc(base + D + h * HD, (uint64_t)N * ld * 2);
+  const i32x4 rv = buffer_rsrc(base + 2 * D + h * HD, (uint64_t)N * ld * 2);
+  int goffK[LPW], goffV[LPW];
+#pragma unroll
+  for (int i = 0; i < LPW; ++i) {
+    const int row = (wave * LPW + i) * RPI + lane / T::NCH;
+    goffK[i] = row * ld * 2 + (((lane % T::NCH) ^ T::f(row)) << 4);
+    goffV[i] = row * ld * 2 + (((lane % T::NCH) ^ TV::f(row)) << 4);
+  }
+  const uint32_t ldsK = lds_offset(&sK[0][0]), ldsV = lds_offset(&sV[0][0]);
+  auto issue = [&](int kt) {
+    const int kb = kt * ATT_KV * ld * 2;
+#pragma unroll
+    for (int i = 0; i < LPW; ++i) {
+      const uint32_t lo = kt * T::BYTES + (wave * LPW + i) * 1024;
+      dma16(rk, ldsK + lo, goffK[i] + kb, 0);
+      dma16(rv, ldsV + lo, goffV[i] + kb, 0);
+    }
+  };
+  int koff[2][HD / 16];
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+    for (int c = 0; c < HD / 16; ++c) koff[kb][c] = T::off(32 * kb + l32, 2 * c + g);
+  const int grp = lane >> 4, li = lane & 15;
+  const int tg = grp >> 1, dh = grp & 1;
+  int vbase[HD / 32];
+#pragma unroll
+  for (int a = 0; a < HD / 32; ++a) {
+    const int col = 32 * a + 16 * dh + 4 * (li & 3);
+    vbase[a] = TV::off(4 * tg + (li >> 2), col >> 3) + (col & 7) * 2;
+  }
+  const float sl2 = 1.4426950408889634f / sqrtf((float)HD);
+  const int KT = (N + ATT_KV - 1) / ATT_KV;    // <= NT (checked by the launcher)
+
+  // One 32-query chunk of this wave against key tile kt (resident in slot kt).
+  auto tile = [&](int kt, const bf16x8* qf, f32x16* o, float& m_run, float& l_run, int q) {
+    const char* tK = sK[kt];
+    f32x16 s[2];
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s[kb][r] = 0.f;
+#pragma unroll
+      for (int c = 0; c < HD / 16; ++c) {
+        const bf16x8 kf = *reinterpret_cast<const bf16x8*>(tK + koff[kb][c]);
+        s[kb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kf, qf[c], s[kb], 0, 0, 0);
+      }
+    }
+    bf16x8 vf[4][HD / 32];
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+      for (int a = 0; a < HD / 32; ++a) {
+        typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+        const uint32_t vb = ldsV + kt * TV::BYTES + vbase[a] + 16 * jj * TV::ROWB;
+        const s16x4 v0 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(uintptr_t)vb);
+        const s16x4 v1 =
+            __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(uintptr_t)(vb + 8 * TV::ROWB));
+        u32x4 vk;
+        vk[0] = __builtin_bit_cast(u32x2, v0).x; vk[1] = __builtin_bit_cast(u32x2, v0).y;
+        vk[2] = __builtin_bit_cast(u32x2, v1).x; vk[3] = __builtin_bit_cast(u32x2, v1).y;
+        vf[jj][a] = __builtin_bit_cast(bf16x8, vk);
+      }
+    const int kbase = kt * ATT_KV;
+    if (kbase + ATT_KV - 1 > N - 1) {
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          if (kbase + kb * 32 + 8 * (r >> 2) + 4 * g + (r & 3) > N - 1) s[kb][r] = -INFINITY;
+    }
+    float mt = s[0][0];
+#pragma unroll
+    for (int i = 1; i < 31; i += 2) {
+      const float x = s[i >> 4][i & 15], y = s[(i + 1) >> 4][(i + 1) & 15];
+      asm("v_max3_f32 %0, %1, %2, %3" : "=v"(mt) : "v"(mt), "v"(x), "v"(y));
+    }
+    asm("v_max_f32 %0, %1, %2" : "=v"(mt) : "v"(mt), "v"(s[1][15]));
+    mt = fmaxf(mt, __shfl_xor(mt, 32, 64)) * sl2;
+    if (__any(mt > m_run + ATT_TAU)) {
+      const float m_new = fmaxf(m_run, mt);
+      const float alpha = __builtin_amdgcn_exp2f(m_run - m_new);
+      l_run *= alpha;
+#pragma unroll
+      for (int a = 0; a < HD / 32; ++a)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) o[a][r] *= alpha;
+      m_run = m_new;
+    }
+    const float nm = -m_run;
+    float ls0 = 0.f, ls1 = 0.f;
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float p = __builtin_amdgcn_exp2f(fmaf(s[kb][r], sl2, nm));
+        s[kb][r] = p;
+        if (r & 1) ls1 += p; else ls0 += p;
+      }
+    l_run += ls0 + ls1;
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int kb = jj >> 1, hh = jj & 1;
+      u32x4 pk;
+#pragma unroll
+      for (int w = 0; w < 4; ++w)
+        pk[w] = pack_bf16x2(s[kb][8 * hh + 2 * w], s[kb][8 * hh + 2 * w + 1]);
+      const bf16x8 pf = __builtin_bit_cast(bf16x8, pk);
+#pragma unroll
+      for (int a = 0; a < HD / 32; ++a)
+        o[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vf[jj][a], pf, o[a], 0, 0, 0);
+    }
+  };
+  auto store = [&](const f32x16* o, float l_run, int q) {
+    const float lt = l_run + __shfl_xor(l_run, 32, 64);
+    if (q >= N) return;
+    const float inv = 1.f / lt;
+    if constexpr (MX) {
+      const int row = dsc.tok_start + q;
+      uint8_t* op = static_cast<uint8_t*>(out) + (size_t)row * D + h * HD;
+#pragma unroll
+      for (int a = 0; a < HD / 32; ++a) {
+        float am = 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) am = fmaxf(am, fabsf(o[a][r]));
+        am = fmaxf(am, __shfl_xor(am, 32, 64)) * inv;
+        const uint32_t sb = mx_scale_byte(am);
+        const float si = mx_inv_scale(sb);
+#pragma unroll
+        for (int rq = 0; rq < 4; ++rq) {
+          const int d = a * 32 + 8 * rq + 4 * g;
+          *reinterpret_cast<uint32_t*>(op + d) =
+              mx_pack4(o[a][4 * rq + 0] * inv, o[a][4 * rq + 1] * inv, o[a][4 * rq + 2] * inv,
+                       o[a][4 * rq + 3] * inv, si);
+        }
+        if (g == 0) out_scale[mx_scale_off(row, h * HD + a * 32, T_rows)] = (uint8_t)sb;
+      }
+    } else {
+      bf16_t* op = static_cast<bf16_t*>(out) + (size_t)(dsc.tok_start + q) * D + h * HD;
+#pragma unroll
+      for (int a = 0; a < HD / 32; ++a)
+#pragma unroll
+        for (int rq = 0; rq < 4; ++rq) {
+          const int d = a * 32 + 8 * rq + 4 * g;
+          u32x2 pk;
+          pk.x = pack_bf16x2(o[a][4 * rq + 0] * inv, o[a][4 * rq + 1] * inv);
+          pk.y = pack_bf16x2(o[a][4 * rq + 2] * inv, o[a][4 * rq + 3] * inv);
+          *reinterpret_cast<u32x2*>(op + d) = pk;
+        }
+    }
+  };
+  auto load_q = [&](bf16x8* qf, int q) {
+    const int qc = min(q, N - 1);
+#pragma unroll
+    for (int c = 0; c < HD / 16; ++c)
+      qf[c] = *reinterpret_cast<const bf16x8*>(Qp + (size_t)qc * ld + 16 * c + 8 * g);
+  };
+
+  // Pass 1: queries 0 .. 255 (chunk = wave) while the tiles arrive.
+  {
+    bf16x8 qf[HD / 16];
+    const int q = 32 * wave + l32;
+    const bool active = 32 * wave < N;
+    load_q(qf, q);
+    // Q has landed before the tile loads are issued (a wait the compiler
+    // sees, so it does not wait for Q again at every tile's MFMAs).
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    issue(0);
+    if (KT > 1) issue(1);
+    float m_run = -INFINITY, l_run = 0.f;
+    f32x16 o[HD / 32];
+#pragma unroll
+    for (int a = 0; a < HD / 32; ++a)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) o[a][r] = 0.f;
+    for (int kt = 0; kt < KT; ++kt) {
+      if (kt + 1 < KT) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * LPW) : "memory");
+      else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      lds_barrier();
+      if (kt + 2 < KT) issue(kt + 2);
+      if (active) tile(kt, qf, o, m_run, l_run, q);
+    }
+    if (active) store(o, l_run, q);
+  }
+  // Later passes: every tile resident; chunks RES_W .. of 32 queries.
+  for (int c0 = 32 * RES_W; c0 < N; c0 += 32 * RES_W) {
+    const int qw = c0 + 32 * wave;
+    if (qw >= N) break;
+    const int q = qw + l32;
+    bf16x8 qf[HD / 16];
+    load_q(qf, q);
+    float m_run = -INFINITY, l_run = 0.f;
+    f32x16 o[HD / 32];
+#pragma unroll
+    for (int a = 0; a < HD / 32; ++a)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) o[a][r] = 0.f;
+    for (int kt = 0; kt < KT; ++kt) tile(kt, qf, o, m_run, l_run, q);
+    store(o, l_run, q);
+  }
+}
+
+// Images the resident kernel takes: more tokens than one 128-query block
+// (fewer already read their keys once) and at most 64 NT with NT = 10.
+constexpr int RES_MIN_TOKENS = ATT_Q + 1, RES_MAX_TILES = 10;
+
+template <bool MX>
+static hipError_t launch_res(const bf16_t* qkv, void* out, uint8_t* out_scale, int T,
+                             const ImgDesc* imgs, const int* res_imgs, int n_res, int max_tiles,
+                             int heads, hipStream_t s) {
+  dim3 grid(n_res * heads), block(RES_W * 64);
+  if (max_tiles <= 4)
+    hipLaunchKernelGGL((k_attn_bf16_res<4, MX>), grid, block, 0, s, qkv, out, out_scale, T, imgs,
+                       res_imgs, heads);
+  else if (max_tiles <= 6)
+    hipLaunchKernelGGL((k_attn_bf16_res<6, MX>), grid, block, 0, s, qkv, out, out_scale, T, imgs,
+                       res_imgs, heads);
+  else if (max_tiles <= 8)
+    hipLaunchKernelGGL((k_attn_bf16_res<8, MX>), grid, block, 0, s, qkv, out, out_scale, T, imgs,
+                       res_imgs, heads);
+  else if (max_tiles <= RES_MAX_TILES)
+    hipLaunchKernelGGL((k_attn_bf16_res<RES_MAX_TILES, MX>), grid, block, 0, s, qkv, out,
+                       out_scale, T, imgs, res_imgs, heads);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t attention_bf16_resident(const bf16_t* qkv, void* out, uint8_t* out_scale, bool mx,
+                                   int T, const ImgDesc* imgs, const int* res_imgs, int n_res,
+                                   int max_tiles, int heads, int head_dim, hipStream_t s) {
+  if (n_res <= 0) return hipSuccess;
+  if (head_dim != 64) return hipErrorInvalidValue;
+  return mx ? launch_res<true>(qkv, out, out_scale, T, imgs, res_imgs, n_res, max_tiles, heads, s)
+            : launch_res<false>(qkv, out, out_scale, T, imgs, res_imgs, n_res, max_tiles, heads,
+                                s);
+}
+
 // ----------------------------------------------------------------- FP32
 constexpr int F32_KV = 32;
 

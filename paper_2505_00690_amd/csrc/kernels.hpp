@@ -164,6 +164,13 @@ hipError_t attention_bf16(const bf16_t* qkv, bf16_t* o, const ImgDesc* imgs,
 hipError_t attention_bf16_mx(const bf16_t* qkv, uint8_t* codes, uint8_t* scales, int T,
                              const ImgDesc* imgs, const AttnItem* items, int n_items,
                              int heads, int head_dim, bool causal, hipStream_t s);
+// K/V-resident form for images of 129 .. 640 tokens at head width 64: one
+// workgroup per (image, head) over res_imgs[0 .. n_res) (image indices);
+// max_tiles = the largest ceil(tokens / 64) among them (<= 10).  Output as
+// attention_bf16 (mx = false) or attention_bf16_mx (mx = true), bitwise.
+hipError_t attention_bf16_resident(const bf16_t* qkv, void* out, uint8_t* out_scale, bool mx,
+                                   int T, const ImgDesc* imgs, const int* res_imgs, int n_res,
+                                   int max_tiles, int heads, int head_dim, hipStream_t s);
 hipError_t attention_f32(const float* qkv, float* o, const ImgDesc* imgs,
                          const AttnItem* items, int n_items, int heads, int head_dim,
                          bool causal, hipStream_t s);

@@ -34,7 +34,7 @@ __all__ = [
 
 VL_FP32, VL_BF16, VL_FP8W_BF16A, VL_MXFP8 = 0, 1, 2, 3
 VL_HEAD_SOFTMAX, VL_HEAD_SIGMOID = 0, 1
-VL_OPT_GRAPHS, VL_OPT_TIMING, VL_OPT_SPLIT, VL_OPT_FUSED_LN = 0, 1, 2, 3
+VL_OPT_GRAPHS, VL_OPT_TIMING, VL_OPT_SPLIT, VL_OPT_FUSED_LN, VL_OPT_ATTN_RESIDENT = 0, 1, 2, 3, 4
 VL_N_OPS = 8
 OP_NAMES = ("patch_embed", "layernorm", "qkv_gemm", "attention", "oproj_gemm", "fc1_gemm",
             "fc2_gemm", "pool_proj_l2")

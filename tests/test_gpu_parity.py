@@ -490,6 +490,26 @@ def test_serving_mix_equals_alone_l14_fp8w_mixed(V):
     _check_mix_equals_alone(V, enc, texts, reqs, st)
 
 
+# ------------------------------------------------- K/V-resident attention
+@pytest.mark.parametrize("precision", ["bf16", "mxfp8"])
+def test_resident_attention_bitwise_equal_streaming(V, precision):
+    """Images of 129 .. 640 tokens run their attention K/V-resident by
+    default; the same batch with that switched off (every image streamed per
+    128-query block) gives the same bits.  The batch mixes resident sizes
+    (197 and 442 tokens) with streamed ones (65 and 785 tokens)."""
+    sizes = [(224, 224)] * 3 + [(336, 336)] * 2 + [(448, 448), (128, 128)]
+    imgs = synth.make_images(sizes, 2800)
+    pix = torch.from_numpy(pack(imgs)).cuda()
+    w = torch.from_numpy(blob("b16", 1001)).cuda()
+    enc = V.Encoder(synth.MODELS["b16"], w, precision)
+    a = enc.encode(pix, sizes).clone()
+    V.vl_model_set_option(enc.handle, V.VL_OPT_ATTN_RESIDENT, 0)
+    b = enc.encode(pix, sizes).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    enc.close()
+
+
 # ---------------------------------------------------- LayerNorm folding
 @pytest.mark.parametrize("model,seed,precision,sizes", [
     ("b16", 1001, "bf16", [(224, 224)] * 3 + [(336, 336), (448, 448)]),
