@@ -88,6 +88,96 @@ def traffic_from_profile(op: str, workload: str, configs=None):
     return (rec["fetch_kib"] * rec["fetch_factor"] + rec["write_kib"] * rec["write_factor"]) * 1024.0
 
 
+# ------------------------------------------------ profile summaries
+# The committed profiles/ summaries are written from rocprofv3 output by
+# these two functions (python bench.py --summarize-kernels DIR /
+# --summarize-traffic FETCH_DIR WRITE_DIR): kernel times per name and, for the
+# block kernels, per workgroup count; and per GEMM tile configuration the
+# FETCH_SIZE / WRITE_SIZE per dispatch, calibrated by a plain copy of known
+# size in the same run.
+_OPS = {"1": "qkv_gemm", "2": "oproj_gemm", "3": "fc1_gemm", "4": "fc2_gemm"}
+
+
+def _csv(dirpath: str, suffix: str):
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(dirpath, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise SystemExit(f"no *{suffix} under {dirpath}")
+    return list(csv.DictReader(open(files[0])))
+
+
+def _gemm_config(name: str):
+    """(op, tile configuration name) of a BF16 block-GEMM kernel name."""
+    import re
+    m = re.search(r"k_gemm_bf16_dl<(\d+), (\d+), (\d+), (\d+), false, (\d), \d, (\d)>", name)
+    if not m or m.group(5) not in _OPS:
+        return None
+    bm, bn, wm, wn, op, st = m.groups()
+    pre = "DL3" if st == "3" else "DL"
+    return _OPS[op], f"{pre}_{bm}x{bn}_W{wm}x{wn}"
+
+
+def summarize_kernels(dirpath: str) -> str:
+    rows = _csv(dirpath, "kernel_stats.csv")
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    out = ["| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        t = float(r["TotalDurationNs"])
+        out.append(f"| `{r['Name'].split('(')[0].replace('void ', '')}` | {r['Calls']} | "
+                   f"{t / 1e6:.3f} | {float(r['AverageNs']) / 1e3:.1f} | {100 * t / tot:.1f} |")
+    trace = _csv(dirpath, "kernel_trace.csv")
+    groups = {}
+    for r in trace:
+        n = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        if not any(k in n for k in ("k_gemm_bf16_dl", "k_attn_bf16", "k_layernorm")):
+            continue
+        wg = int(r["Grid_Size_X"]) // max(1, int(r["Workgroup_Size_X"]))
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        groups.setdefault((n, wg), []).append(d)
+    out += ["", "Block kernels by workgroup count:", "",
+            "| kernel | workgroups | launches | avg us |", "|---|---|---|---|"]
+    for (n, wg), ds in sorted(groups.items()):
+        out.append(f"| `{n}` | {wg} | {len(ds)} | {sum(ds) / len(ds):.1f} |")
+    return "\n".join(out)
+
+
+def summarize_traffic(fetch_dir: str, write_dir: str, copy_mib: int = 256) -> str:
+    """One JSON record per (GEMM op, tile configuration): mean FETCH_SIZE /
+    WRITE_SIZE per dispatch (KiB) and the copy calibration factors."""
+    def per_kernel(dirpath, counter):
+        acc = {}
+        for r in _csv(dirpath, "counter_collection.csv"):
+            if r["Counter_Name"] != counter:
+                continue
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        # the calibration copy is the largest copy dispatch of the run
+        cal = max((max(v) for k, v in acc.items() if "copyBuffer" in k), default=None)
+        if cal is None:
+            raise SystemExit(f"no calibration copy in the {counter} run")
+        return ({k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()},
+                cal)
+    fetch, nf, fcal = per_kernel(fetch_dir, "FETCH_SIZE")
+    write, _, wcal = per_kernel(write_dir, "WRITE_SIZE")
+    kib = copy_mib * 1024
+    ff, wf = kib / fcal, kib / wcal
+    src = "gemm_kernels.hpp"
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2505_00690_amd", "csrc", src),
+                              "rb").read()).hexdigest()
+    out = []
+    for k in sorted(fetch):
+        oc = _gemm_config(k)
+        if oc is None or k not in write:
+            continue
+        rec = {"op": oc[0], "fetch_kib": round(fetch[k], 1), "write_kib": round(write[k], 1),
+               "fetch_factor": round(ff, 4), "write_factor": round(wf, 4),
+               "copy_fetch_kib": round(fcal, 1), "copy_write_kib": round(wcal, 1),
+               "copy_kib": kib, "kernel": k.split("(")[0].replace("void vl::", ""),
+               "config": oc[1], "dispatches": nf[k], "source": src, "source_sha256": sha}
+        out.append(json.dumps(rec))
+    return "\n".join(out)
+
+
 def cpu_baseline(wl: synth.Workload, blob: np.ndarray, images, texts, n_sample: int,
                  precision: str = None, one_thread: bool = True):
     """The FP64 oracle as it stands, on the host cores, over a bounded
@@ -386,6 +476,12 @@ def main(argv=None) -> int:
     ap.add_argument("--no-text", action="store_true", help="skip the text-tower leg")
     ap.add_argument("--no-rgbd", action="store_true", help="skip the RGB-D observation leg")
     ap.add_argument("--text-steps", type=int, default=5)
+    ap.add_argument("--summarize-kernels", metavar="DIR", default=None,
+                    help="print the kernel-time tables of a rocprofv3 --kernel-trace --stats "
+                         "output directory and exit")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    default=None, help="print the GEMM traffic records of two rocprofv3 "
+                    "--pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
     ap.add_argument("--no-attn-resident", action="store_true",
                     help="stream key / value tiles per 128-query block for every image")
     ap.add_argument("--fused-ln", action="store_true",
@@ -403,6 +499,12 @@ def main(argv=None) -> int:
                     help="images per serving batch at most (32: same capacity as 64, "
                          "shorter tail latency)")
     args = ap.parse_args(argv)
+    if args.summarize_kernels:
+        print(summarize_kernels(args.summarize_kernels))
+        return 0
+    if args.summarize_traffic:
+        print(summarize_traffic(*args.summarize_traffic, args.copy_calibration_mib or 256))
+        return 0
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

@@ -84,3 +84,35 @@ def test_oracle_error_and_top1_agreement_host_logic():
     s = np.sort(l, axis=1)
     cert = (s[:, -1] - s[:, -2]) > 2 * 10.0 * (np.linalg.norm(got - ref, axis=1) + 1e-4)
     assert r["certified_images"] == int(cert.sum())
+
+
+def test_traffic_summary_from_counter_csvs(tmp_path):
+    """--summarize-traffic: the largest copy dispatch calibrates each counter,
+    GEMM kernel names map to (op, tile configuration), values are averaged
+    per dispatch."""
+    import csv
+    import json as _json
+
+    import bench
+
+    def write(d, counter, rows):
+        d.mkdir()
+        with open(d / "p_counter_collection.csv", "w", newline="") as f:
+            w = csv.writer(f)
+            w.writerow(["Kernel_Name", "Counter_Name", "Counter_Value"])
+            for name, v in rows:
+                w.writerow([name, counter, v])
+    k = "void vl::k_gemm_bf16_dl<256, 256, 4, 2, false, 3, 2, 2>(unsigned short const*, int)"
+    other = "void vl::k_layernorm<16, true>(float const*)"
+    write(tmp_path / "f", "FETCH_SIZE", [("__amd_rocclr_copyBuffer", 4.0),
+                                         ("__amd_rocclr_copyBuffer", 131072.0),
+                                         (k, 100.0), (k, 300.0), (other, 7.0)])
+    write(tmp_path / "w", "WRITE_SIZE", [("__amd_rocclr_copyBuffer", 262144.0), (k, 50.0),
+                                         (k, 50.0)])
+    recs = [_json.loads(l) for l in
+            bench.summarize_traffic(str(tmp_path / "f"), str(tmp_path / "w")).splitlines()]
+    assert len(recs) == 1
+    r = recs[0]
+    assert r["op"] == "fc1_gemm" and r["config"] == "DL_256x256_W4x2"
+    assert r["fetch_kib"] == 200.0 and r["write_kib"] == 50.0 and r["dispatches"] == 2
+    assert r["fetch_factor"] == 2.0 and r["write_factor"] == 1.0
