@@ -404,17 +404,17 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
   // swizzle and the lane's half g folded in: BF16 chunk (2kk + g) ^ f(row)
   // of a 128-byte row is (offset ^ (kk << 5)); e4m3 chunk kk ^ f8(row) of a
   // 64-byte row is (offset ^ (kk << 4)).
-  int offA[TM], offB[TN];
+  // Row r0 + 32b has the chunk permutation of row r0 + 32 (b & 1) (the
+  // swizzles depend on the row modulo 64), so the offset of fragment b is
+  // one of two per-lane bases plus an immediate of 32b rows: two live
+  // registers per operand instead of one per fragment.
+  int pA[2], pB[2];
 #pragma unroll
-  for (int b = 0; b < TM; ++b) {
-    const int row = wm * WM + b * 32 + l32;
-    offA[b] = row * (BK * 2) + ((g ^ swz_f(row)) << 4);
-  }
-#pragma unroll
-  for (int a = 0; a < TN; ++a) {
-    const int row = wn * WN + a * 32 + l32;
-    offB[a] = B_FP8 ? row * BK + (((row >> 2) & 3) << 4) + (g << 3)
-                    : row * (BK * 2) + ((g ^ swz_f(row)) << 4);
+  for (int j = 0; j < 2; ++j) {
+    const int ra = wm * WM + j * 32 + l32, rb = wn * WN + j * 32 + l32;
+    pA[j] = (wm * WM + l32) * (BK * 2) + ((g ^ swz_f(ra)) << 4);
+    pB[j] = B_FP8 ? (wn * WN + l32) * BK + (((rb >> 2) & 3) << 4) + (g << 3)
+                  : (wn * WN + l32) * (BK * 2) + ((g ^ swz_f(rb)) << 4);
   }
   bf16x8 fw0[TN], fx0[TM], fw1[TN], fx1[TM];
   auto ldfrag = [&](bf16x8* fw, bf16x8* fx, int buf, int kk) {
@@ -423,7 +423,8 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
 #pragma unroll
     for (int a = 0; a < TN; ++a) {
       if (B_FP8) {
-        const u32x2 c8 = *reinterpret_cast<const u32x2*>(tB + (offB[a] ^ (kk << 4)));
+        const u32x2 c8 =
+            *reinterpret_cast<const u32x2*>(tB + (pB[a & 1] ^ (kk << 4)) + a * 32 * BK);
         typedef __bf16 b2 __attribute__((ext_vector_type(2)));
         const b2 h0 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(c8.x, 1.0f, false);
         const b2 h1 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(c8.x, 1.0f, true);
@@ -434,12 +435,12 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
         f[4] = h2[0]; f[5] = h2[1]; f[6] = h3[0]; f[7] = h3[1];
         fw[a] = f;
       } else {
-        fw[a] = *reinterpret_cast<const bf16x8*>(tB + (offB[a] ^ (kk << 5)));
+        fw[a] = *reinterpret_cast<const bf16x8*>(tB + (pB[a & 1] ^ (kk << 5)) + a * 32 * BK * 2);
       }
     }
 #pragma unroll
     for (int b = 0; b < TM; ++b)
-      fx[b] = *reinterpret_cast<const bf16x8*>(tA + (offA[b] ^ (kk << 5)));
+      fx[b] = *reinterpret_cast<const bf16x8*>(tA + (pA[b & 1] ^ (kk << 5)) + b * 32 * BK * 2);
   };
   auto mma = [&](const bf16x8* fw, const bf16x8* fx) {
 #pragma unroll

@@ -216,7 +216,7 @@ hipError_t contrastive_loss(const float* E, const float* T, int n, int dim, int 
                             float* dsb, void* ws, hipStream_t s);
 
 // ---- training (contrastive training through the image tower)
-constexpr int kColRows = 256;  // rows per partial sum of colsum
+constexpr int kColRows = 64;   // rows per partial sum of colsum
 constexpr int kLnRows = 32;    // rows per partial sum of layernorm_backward
 struct ChanNorm { float mean[4], std[4]; };  // per-plane pixel normalisation
 
@@ -225,7 +225,8 @@ struct ChanNorm { float mean[4], std[4]; };  // per-plane pixel normalisation
 hipError_t transpose_rows(const void* in, bool in_bf16, int rows, int cols, int ld_in, void* out,
                           bool out_bf16, int ld_out, hipStream_t s);
 // out[c] = sum over rows of in[r][c] (class-token rows skipped when tok is
-// given), via part [ceil(R / kColRows), C] in a fixed order.
+// given), via part [ceil(R / kColRows), C] in a fixed order.  C % 4 == 0,
+// ld % 4 == 0.
 hipError_t colsum(const void* in, bool in_bf16, int R, int C, int ld, const int2* tok,
                   float* part, float* out, hipStream_t s);
 // dx += LayerNorm backward of rows [R, D]; dgamma, dbeta (overwritten) via

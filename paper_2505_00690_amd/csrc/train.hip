@@ -79,19 +79,28 @@ hipError_t transpose_rows(const void* in, bool in_bf16, int rows, int cols, int 
 // part[b][c] = sum of in[r][c] over the rows r of block b (kColRows rows,
 // ascending), skipping class-token rows when tok is given; then out[c] =
 // sum over b ascending.  Fixed order: the result does not depend on timing.
+// Four adjacent columns per thread (one 16- or 8-byte load per row).
+__device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+__device__ __forceinline__ float4 ld4(const bf16_t* p) {
+  const u32x2 v = *reinterpret_cast<const u32x2*>(p);
+  return make_float4(bf16_bits_to_f32(v.x & 0xFFFFu), bf16_bits_to_f32(v.x >> 16),
+                     bf16_bits_to_f32(v.y & 0xFFFFu), bf16_bits_to_f32(v.y >> 16));
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_colsum_part(const T* __restrict__ in, int R, int C,
                                                      int ld, const int2* __restrict__ tok,
                                                      float* __restrict__ part) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
+  const int c = 4 * (blockIdx.x * 256 + threadIdx.x);
   if (c >= C) return;
   const int r0 = blockIdx.y * kColRows, r1 = min(R, r0 + kColRows);
-  float s = 0.f;
+  float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
   for (int r = r0; r < r1; ++r) {
     if (tok && tok[r].y == 0) continue;
-    s += ldf(in, (size_t)r * ld + c);
+    const float4 v = ld4(in + (size_t)r * ld + c);
+    s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
   }
-  part[(size_t)blockIdx.y * C + c] = s;
+  *reinterpret_cast<float4*>(part + (size_t)blockIdx.y * C + c) = s;
 }
 
 // Final pass: 16 columns per workgroup, 16 phases per column; phase k sums
@@ -122,8 +131,8 @@ hipError_t colsum_final(const float* part, int nb, int C, float* out, hipStream_
 hipError_t colsum(const void* in, bool in_bf16, int R, int C, int ld, const int2* tok,
                   float* part, float* out, hipStream_t s) {
   const int nb = (R + kColRows - 1) / kColRows;
-  if (nb <= 0) return hipErrorInvalidValue;
-  dim3 grid((C + 255) / 256, nb), block(256);
+  if (nb <= 0 || C % 4 || ld % 4) return hipErrorInvalidValue;
+  dim3 grid((C / 4 + 255) / 256, nb), block(256);
   if (in_bf16)
     hipLaunchKernelGGL(k_colsum_part<bf16_t>, grid, block, 0, s, static_cast<const bf16_t*>(in),
                        R, C, ld, tok, part);
@@ -703,7 +712,7 @@ __global__ __launch_bounds__(128) void k_attn_bwd_dq_mfma(const bf16_t* __restri
 }
 
 template <int HD>
-__global__ __launch_bounds__(128) void k_attn_bwd_dkv_mfma(const bf16_t* __restrict__ qkv,
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void k_attn_bwd_dkv_mfma(const bf16_t* __restrict__ qkv,
                                                            const float* __restrict__ dO,
                                                            const ImgDesc* __restrict__ imgs,
                                                            const AttnItem* __restrict__ items,
@@ -750,40 +759,40 @@ __global__ __launch_bounds__(128) void k_attn_bwd_dkv_mfma(const bf16_t* __restr
       sD[threadIdx.x] = (int)threadIdx.x < nq ? dsum[row * heads + h] : 0.f;
     }
     __syncthreads();
-    f32x16 s[2], dp[2];
-#pragma unroll
+    // The 64 queries as two halves of 32 (fewer live registers): for half qb,
+    // s[r] = S[query q0 + qi][key k], qi = 32qb + 8(r/4) + 4g + r%4, then its
+    // two 16-query chunks jj = 2qb, 2qb + 1 of dV^T += dO^T P, dK^T += Q^T dS.
     for (int qb = 0; qb < 2; ++qb) {
+      f32x16 s, dp;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) s[qb][r] = dp[qb][r] = 0.f;
+      for (int r = 0; r < 16; ++r) s[r] = dp[r] = 0.f;
       const int row = 32 * qb + l32;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const bf16x8 qa = *reinterpret_cast<const bf16x8*>(sQ + TT::off(row, 2 * c + g));
-        s[qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa, kf[c], s[qb], 0, 0, 0);
+        s = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa, kf[c], s, 0, 0, 0);
         const bf16x8 da = *reinterpret_cast<const bf16x8*>(sdO + TT::off(row, 2 * c + g));
-        dp[qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(da, vf[c], dp[qb], 0, 0, 0);
+        dp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(da, vf[c], dp, 0, 0, 0);
       }
-    }
-    // s[qb][r] = S[query q0 + qi][key k], qi = 32qb + 8(r/4) + 4g + r%4
-#pragma unroll
-    for (int qb = 0; qb < 2; ++qb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int qi = 32 * qb + 8 * (r >> 2) + 4 * g + (r & 3);
-        const float p = (qi < nq && kok) ? exp2f(fmaf(s[qb][r], sl2, -sL[qi])) : 0.f;
-        s[qb][r] = p;
-        dp[qb][r] = p * (dp[qb][r] - sD[qi]);
+        const float p = (qi < nq && kok) ? exp2f(fmaf(s[r], sl2, -sL[qi])) : 0.f;
+        s[r] = p;
+        dp[r] = p * (dp[r] - sD[qi]);
       }
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      const bf16x8 pf = pack8(s[jj >> 1], jj & 1);
-      const bf16x8 dsf = pack8(dp[jj >> 1], jj & 1);
+      for (int hh = 0; hh < 2; ++hh) {
+        const int jj = 2 * qb + hh;
+        const bf16x8 pf = pack8(s, hh);
+        const bf16x8 dsf = pack8(dp, hh);
 #pragma unroll
-      for (int a = 0; a < NA; ++a) {
-        dv[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(tr_frag<HD>(ldsO, a, jj, lane), pf,
-                                                        dv[a], 0, 0, 0);
-        dk[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(tr_frag<HD>(ldsQ, a, jj, lane), dsf,
-                                                        dk[a], 0, 0, 0);
+        for (int a = 0; a < NA; ++a) {
+          dv[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(tr_frag<HD>(ldsO, a, jj, lane), pf,
+                                                          dv[a], 0, 0, 0);
+          dk[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(tr_frag<HD>(ldsQ, a, jj, lane), dsf,
+                                                          dk[a], 0, 0, 0);
+        }
       }
     }
   }
