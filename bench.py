@@ -389,12 +389,15 @@ def train_leg(torch, vl, steps: int, model: str = "l14", res: int = 336, batch: 
 
 
 def serving_leg(torch, vl, n_requests: int, warmup_requests: int, slots: int,
-                budget_gib: float, max_batch_images: int):
+                budget_gib: float, max_batch_images: int, graphs: bool = True):
     """The serving workload: ViT-L/14 with e4m3 per-row weights and BF16
     activations, 8192 resident texts, Poisson requests of 1-16 images at one
     of {224, 336, 384, 448} each.  Closed-loop capacity first (every request
     queued at t=0), then open-loop Poisson arrivals at 0.5x and 0.8x of that
-    capacity; nearest-rank p50/p99 of arrival-to-completion latency."""
+    capacity; nearest-rank p50/p99 of arrival-to-completion latency.  With
+    graphs, every batch replays the HIP graph of its capacity bucket on its
+    slot (captured on the bucket's first batch); each run reports the share
+    of its batches that replayed an existing graph."""
     from paper_2505_00690_amd.serve import GpuExecutor, RealClock, Request, Scheduler
     wl = synth.WORKLOADS["l14_serve"]
     c = synth.MODELS[wl.model]
@@ -410,7 +413,9 @@ def serving_leg(torch, vl, n_requests: int, warmup_requests: int, slots: int,
     # tune the GEMM tiles once on a representative batch (32 images, mixed sizes)
     tsizes = [(r, r) for r in wl.resolutions for _ in range(8)]
     enc.autotune(torch.cat([pool[h][k % 32] for k, (h, _) in enumerate(tsizes)]), tsizes, reps=2)
-    ex = GpuExecutor(enc, texts, wl.head, wl.scale, wl.bias, slots)
+    if graphs:   # after tuning: the tile choice is part of what a graph holds
+        vl.vl_model_set_option(enc.handle, vl.VL_OPT_GRAPHS, 1)
+    ex = GpuExecutor(enc, texts, wl.head, wl.scale, wl.bias, slots, keep_workspaces=graphs)
     budget = int(budget_gib * 2 ** 30)
     sched = Scheduler(ex, budget, slots=slots, max_batch_images=max_batch_images)
 
@@ -423,8 +428,10 @@ def serving_leg(torch, vl, n_requests: int, warmup_requests: int, slots: int,
         return out
 
     def run(reqs):
+        g0 = enc.graph_stats()
         st = sched.run(reqs, RealClock())
         torch.cuda.synchronize()
+        g1 = enc.graph_stats()
         keep = [x for x in st.results if x.rid >= warmup_requests]
         lat = sorted(x.latency for x in keep)
         imgs = sum(x.n_images for x in st.results)
@@ -432,11 +439,15 @@ def serving_leg(torch, vl, n_requests: int, warmup_requests: int, slots: int,
         return {"images_per_s": imgs / st.wall, "requests_per_s": len(st.results) / st.wall,
                 "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
                 "batches": st.batches, "max_inflight": st.max_inflight,
-                "peak_workspace_gib": st.peak_budget / 2 ** 30, "requests": len(st.results)}
+                "peak_workspace_gib": st.peak_budget / 2 ** 30, "requests": len(st.results),
+                "graph_captures": g1["captures"] - g0["captures"],
+                "graph_hit_rate": (1.0 - (g1["captures"] - g0["captures"]) / st.batches
+                                   if graphs and st.batches else None)}
 
     run(make(64, 1e9, seeds["arrivals"] + 99))   # warm-up (plans, allocator)
     cap = run(make(max(200, n_requests // 3), 1e9, seeds["arrivals"]))
     out = {"workload": "l14_serve", "precision": wl.precision, "slots": slots,
+           "graphs": graphs,
            "budget_gib": budget_gib, "max_batch_images": max_batch_images,
            "capacity": cap, "open_loop": []}
     for frac in (0.5, 0.8):
@@ -494,6 +505,8 @@ def main(argv=None) -> int:
                          "a counter run can scale FETCH_SIZE / WRITE_SIZE by a copy of known size")
     ap.add_argument("--serve-requests", type=int, default=1200)
     ap.add_argument("--serve-slots", type=int, default=2)
+    ap.add_argument("--serve-eager", action="store_true",
+                    help="serving leg without graph replay (eager launches)")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
     ap.add_argument("--serve-max-batch", type=int, default=32,
                     help="images per serving batch at most (32: same capacity as 64, "
@@ -697,7 +710,8 @@ def main(argv=None) -> int:
 
     if not args.no_serve:
         result["serving"] = serving_leg(torch, vl, args.serve_requests, 100, args.serve_slots,
-                                        args.serve_budget_gib, args.serve_max_batch)
+                                        args.serve_budget_gib, args.serve_max_batch,
+                                        graphs=not args.serve_eager)
         print(f"# serving: {json.dumps(result['serving'])}", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:

@@ -221,11 +221,27 @@ vl_status vl_encode_texts(vl_model* m, const int32_t* ids_dev, const int32_t* le
 /* Options (all off by default).  Setting an option waits only for the
  * cached graphs it drops (each graph's last replay); it does not synchronise
  * the device.
- *   VL_OPT_GRAPHS : 1 = capture each distinct call (shapes, pointers,
- *                   stream) into a HIP graph on first use and replay it.
- *                   At most 64 graphs are kept per model; the least
- *                   recently replayed one is dropped (after its last replay
- *                   finishes) to make room.
+ *   VL_OPT_GRAPHS : 1 = capture calls into HIP graphs on first use and
+ *                   replay them.  For VL_BF16 and VL_FP8W_BF16A image models
+ *                   with VL_POOL_CLS and VL_OPT_FUSED_LN off, a graph serves
+ *                   a capacity bucket: each part's token count is rounded
+ *                   up (counts <= 16 exact; above, to a multiple of a
+ *                   quarter of the power of two below, never reaching the
+ *                   next power of two) and its image count to a power of
+ *                   two; kernel grids are sized for the
+ *                   capacities, and the kernels read the call's counts,
+ *                   descriptors, pixel and output pointers from the
+ *                   workspace, uploaded ahead of the replay on the call's
+ *                   stream.  So different batches of one bucket (other
+ *                   image sizes, pixel and output buffers) replay one graph
+ *                   for a workspace and stream, with the same bits as an
+ *                   eager call.  vl_encode_workspace_bytes then returns the
+ *                   bucket's size (up to ~1/4 more), so query it after
+ *                   setting this option.  Other models key a graph on the
+ *                   exact call (shapes, pointers, stream).  At most 256
+ *                   graphs are kept per model; the least recently replayed
+ *                   one is dropped (after its last replay finishes) to make
+ *                   room.
  *   VL_OPT_TIMING : 1 = bracket every kernel launch of vl_encode_images
  *                   with HIP events on the stream it runs on and accumulate
  *                   per-operation device time (read with
@@ -283,6 +299,12 @@ vl_status vl_model_set_option(vl_model* m, vl_option opt, int64_t value);
  * NULL).  reset != 0 clears the totals afterwards.                         */
 vl_status vl_model_op_times(vl_model* m, double* ms_out, int64_t* launches_out,
                             int32_t reset);
+
+/* Graph cache counters since the model was created: graphs captured,
+ * replays (a captured graph's first launch counts as a replay), graphs
+ * held now.  Any pointer may be NULL.  Host-only.                          */
+vl_status vl_model_graph_stats(vl_model* m, int64_t* captures, int64_t* replays,
+                               int32_t* cached);
 
 /* ---- GEMM tile configurations and the autotuner ------------------------
  * The BF16 / e4m3-weight GEMMs (patch embedding, QKV, output projection,

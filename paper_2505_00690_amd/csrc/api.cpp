@@ -77,7 +77,7 @@ struct GraphEntry {
   uint64_t last_use = 0;      // replay clock, for least-recently-used eviction
 };
 
-constexpr size_t kMaxGraphs = 64;  // cached graphs per model
+constexpr size_t kMaxGraphs = 256;  // cached graphs per model
 
 struct TimedLaunch {
   int op;
@@ -114,6 +114,7 @@ struct vl_model {
   size_t ring_pos = 0;
   std::unordered_map<std::string, GraphEntry> graphs;
   uint64_t graph_clock = 0;
+  int64_t graph_captures = 0, graph_replays = 0;   // since creation
   // One event per stream the model has been used on, recorded at the end of
   // every call on it: waiting for all of them waits for all of the model's
   // enqueued work, without synchronising the device.
@@ -218,9 +219,16 @@ struct Part {
   // LayerNorm folding: u = bf16(x * gamma) [T, D], per-32-column (mean, M2)
   // partials [T, D/32, 2] and row (mean, rstd) [T, 2]
   size_t off_U = 0, off_PS = 0, off_RS = 0;
+  // Launch sizes and buffer regions.  Equal to the counts above, except in
+  // a bucketed plan, where they are the bucket's capacities and the kernels
+  // read the live counts from the part's BatchCounts record at off_bc.
+  bool bucketed = false;
+  int T_cap = 0, n_cap = 0, items_cap = 0, res_cap = 0, ntok_cap = 0, res_class = 0;
+  size_t off_bc = 0;
 };
 
 struct Plan {
+  bool bucketed = false;
   int n = 0, T = 0;
   std::vector<int32_t> hw;          // (H, W) per image, for graph keys
   std::vector<char> desc;           // host image of the descriptor region
@@ -229,13 +237,40 @@ struct Plan {
   size_t total = 0;
 };
 
+// Capacities of a bucketed plan.  Tokens: up to 16 as they are; above,
+// rounded up to a multiple of 2^(floor(log2 T) - 2) but kept below the next
+// power of two, so a bucket spans at most a quarter of its values and the
+// capacity has the floor(log2) of the count, which is what the GEMM tile
+// choice depends on.  Images: the next power of two.
+int cap_tokens(int T) {
+  if (T <= 16) return T;
+  const int k = 31 - __builtin_clz((unsigned)T);
+  const int step = 1 << (k - 2);
+  return std::min((T + step - 1) / step * step, (2 << k) - 1);
+}
+int cap_images(int n) {
+  int c = 1;
+  while (c < n) c <<= 1;
+  return std::min(c, kMaxItems);
+}
+
+// Whether the model's encode calls plan for capacity buckets: graph replay
+// on, and a kernel sequence whose launches all read live counts on the
+// device (BF16 or e4m3-weight image models with class-token pooling and
+// standalone LayerNorms).
+bool bucket_mode(const vl_model* m) {
+  return m->use_graphs && !m->text && (m->prec == VL_BF16 || m->prec == VL_FP8W_BF16A) &&
+         m->cfg.pool == VL_POOL_CLS && !m->fused_ln;
+}
+
 // The common tail of planning: part boundaries, attention work items, the
 // descriptor blob and the workspace regions.  imgs[] hold absolute token
 // starts on entry.
 bool finish_plan(const vl_model* m, std::vector<ImgDesc>& imgs, int64_t T, Plan* p,
-                 bool one_part = false) {
+                 bool one_part = false, bool bucketed = false) {
   const int n = (int)imgs.size();
   p->T = (int)T;
+  p->bucketed = bucketed;
   // Part boundaries: one part, or two holding about half the tokens each.
   std::vector<int> cut = {0};
   if (!one_part && m->split && m->prec != VL_FP32 && n >= 2 && T >= kSplitMinTokens) {
@@ -271,12 +306,30 @@ bool finish_plan(const vl_model* m, std::vector<ImgDesc>& imgs, int64_t T, Plan*
     }
     q.n_items = (int)items[k].size();
     q.n_res = (int)res[k].size();
+    q.T_cap = q.T; q.n_cap = q.n; q.items_cap = q.n_items; q.res_cap = q.n_res;
+    q.ntok_cap = q.max_ntok; q.res_class = q.res_tiles;
+    if (bucketed) {
+      // Every batch of the bucket fits: a part's streamed items number at
+      // most sum ceil(ntok / 128) <= T / 128 + n, its resident images at
+      // most n, each of at most kResMaxTiles key tiles, its images at most
+      // kMaxTokens tokens.  Both attention kernels are launched (their live
+      // counts may be 0).
+      q.T_cap = cap_tokens(q.T);
+      q.n_cap = cap_images(q.n);
+      q.items_cap = (q.T_cap + kAttnQ - 1) / kAttnQ + q.n_cap;
+      q.res_cap = res_ok ? q.n_cap : 0;
+      q.ntok_cap = kMaxTokens;
+      q.res_class = kResMaxTiles;
+      q.bucketed = true;
+      q.off_bc = doff;
+      doff = a16(doff + sizeof(BatchCounts));
+    }
     q.off_imgs = doff;
-    doff = a16(doff + sizeof(ImgDesc) * q.n);
+    doff = a16(doff + sizeof(ImgDesc) * q.n_cap);
     q.off_items = doff;
-    doff = a16(doff + sizeof(AttnItem) * q.n_items);
+    doff = a16(doff + sizeof(AttnItem) * q.items_cap);
     q.off_res = doff;
-    doff = a16(doff + sizeof(int32_t) * q.n_res);
+    doff = a16(doff + sizeof(int32_t) * q.res_cap);
     p->parts.push_back(q);
   }
   p->desc_bytes = doff;
@@ -286,33 +339,38 @@ bool finish_plan(const vl_model* m, std::vector<ImgDesc>& imgs, int64_t T, Plan*
     std::memcpy(p->desc.data() + q.off_imgs, imgs.data() + q.i0, sizeof(ImgDesc) * q.n);
     std::memcpy(p->desc.data() + q.off_items, items[k].data(), sizeof(AttnItem) * q.n_items);
     std::memcpy(p->desc.data() + q.off_res, res[k].data(), sizeof(int32_t) * q.n_res);
+    if (bucketed) {
+      BatchCounts bc{q.T, q.n, q.n_items, q.n_res, nullptr, nullptr};   // pointers: bind_batch
+      std::memcpy(p->desc.data() + q.off_bc, &bc, sizeof bc);
+    }
   }
   // Workspace: the descriptor region, then each part's activation regions.
   const size_t es = m->prec == VL_FP32 ? 4 : 2;
   const size_t qh_cols = std::max<size_t>({(size_t)3 * m->D, (size_t)m->F, (size_t)m->Kpad});
   size_t off = align_up(p->desc_bytes);
   for (Part& q : p->parts) {
+    const size_t Tc = q.T_cap, nc = q.n_cap;
     q.off_tok = off;
-    off += align_up(sizeof(int2) * q.T);
+    off += align_up(sizeof(int2) * Tc);
     q.off_X = off;
-    off += align_up(4ull * q.T * m->D);
+    off += align_up(4ull * Tc * m->D);
     q.off_Y = off;
-    off += align_up(es * q.T * m->D);
+    off += align_up(es * Tc * m->D);
     q.off_QH = off;
-    off += align_up(es * q.T * qh_cols);
+    off += align_up(es * Tc * qh_cols);
     q.off_E = off;
-    off += align_up(4ull * q.n * m->Pd);
+    off += align_up(4ull * nc * m->Pd);
     if (!m->text && m->cfg.pool == VL_POOL_MAP) {
       q.off_map = off;
-      off += align_up(4ull * q.n * (3 * (size_t)m->D + m->F));
+      off += align_up(4ull * nc * (3 * (size_t)m->D + m->F));
     }
     if (m->prec == VL_BF16 || m->prec == VL_FP8W_BF16A) {
       q.off_U = off;
-      off += align_up(2ull * q.T * m->D);
+      off += align_up(2ull * Tc * m->D);
       q.off_PS = off;
-      off += align_up(4ull * q.T * (m->D / 32) * 2);
+      off += align_up(4ull * Tc * (m->D / 32) * 2);
       q.off_RS = off;
-      off += align_up(8ull * q.T);
+      off += align_up(8ull * Tc);
     }
   }
   p->total = off;
@@ -320,7 +378,7 @@ bool finish_plan(const vl_model* m, std::vector<ImgDesc>& imgs, int64_t T, Plan*
 }
 
 bool make_plan(const vl_model* m, int32_t n, const int32_t* hs, const int32_t* ws, Plan* p,
-               std::string* why, bool one_part = false) {
+               std::string* why, bool one_part = false, bool bucketed = false) {
   if (m->text) { *why = "this model encodes texts (vl_encode_texts)"; return false; }
   if (n <= 0) { *why = "n_images must be > 0"; return false; }
   if (n > kMaxItems) { *why = "n_images must be <= 65535 (split larger batches)"; return false; }
@@ -346,7 +404,7 @@ bool make_plan(const vl_model* m, int32_t n, const int32_t* hs, const int32_t* w
     p->hw[2 * i + 1] = W;
   }
   if (T > (1LL << 24)) { *why = "batch exceeds 2^24 tokens"; return false; }
-  return finish_plan(m, imgs, T, p, one_part);
+  return finish_plan(m, imgs, T, p, one_part, bucketed);
 }
 
 // Text batches: one descriptor per sequence (tokens tok_start .. +ntok-1 of
@@ -403,6 +461,17 @@ vl_status stage_copy(std::vector<Staging>& ring, size_t& pos, const void* src, s
   VL_HIP(hipEventRecord(st.ev, s));
   st.pending = true;
   return VL_OK;
+}
+
+// A bucketed plan's per-call pointers: the pixel buffer and each part's
+// first output row, in the parts' BatchCounts records.
+void bind_batch(Plan& p, const void* pix, float* emb, int Pd) {
+  if (!p.bucketed) return;
+  for (const Part& q : p.parts) {
+    BatchCounts* bc = reinterpret_cast<BatchCounts*>(p.desc.data() + q.off_bc);
+    bc->pix = static_cast<const float*>(pix);
+    bc->emb = emb + (size_t)q.i0 * Pd;
+  }
 }
 
 // Upload the plan's descriptors with an async copy from pinned memory.
@@ -475,7 +544,11 @@ vl_status run_part(vl_model* m, const Part& p, const void* in, float* emb, char*
   float* X = reinterpret_cast<float*>(ws + p.off_X);
   void* Y = ws + p.off_Y;
   void* QH = ws + p.off_QH;
-  const int T = p.T, D = m->D, F = m->F;
+  // Launch sizes: the part's counts, or its bucket's capacities with the
+  // live counts in the device record bc.
+  const int T = p.T_cap, D = m->D, F = m->F;
+  const BatchCounts* bc = p.bucketed ? reinterpret_cast<const BatchCounts*>(ws + p.off_bc) : nullptr;
+  const int32_t* m_dev = bc ? &bc->T : nullptr;
   const float eps = m->cfg.ln_eps;
 
   EpiArgs pe;
@@ -487,12 +560,13 @@ vl_status run_part(vl_model* m, const Part& p, const void* in, float* emb, char*
   pe.cls = m->cls;
   pe.pos = m->pos;
   pe.base_grid = m->g0;
+  pe.m_dev = m_dev;
   if (m->text)
     VL_TIMED(T_PATCH, VL_HIP(text_embed(static_cast<const int32_t*>(in), d_imgs, p.n, p.max_ntok,
                                         m->tok_emb, m->pos, m->vocab, D, X, tok, s)));
   else VL_TIMED(T_PATCH, {
-    VL_HIP(im2col(static_cast<const float*>(in), d_imgs, p.n, p.max_ntok, m->cfg.channels, m->P,
-                  m->Kpad, QH, !f32, tok, s));
+    VL_HIP(im2col(static_cast<const float*>(in), d_imgs, p.n_cap, p.ntok_cap, m->cfg.channels,
+                  m->P, m->Kpad, QH, !f32, tok, s, bc));
     if (f32)
       VL_HIP(gemm_f32(static_cast<const float*>(QH), m->Kpad,
                       static_cast<const float*>(m->patch_w), m->Kpad, T, D, m->Kpad, OP_PATCH,
@@ -547,15 +621,15 @@ vl_status run_part(vl_model* m, const Part& p, const void* in, float* emb, char*
       VL_TIMED(T_LN, VL_HIP(layernorm_rows_mx(X, ly.ln1_g, ly.ln1_b, eps, static_cast<uint8_t*>(Y),
                                               static_cast<uint8_t*>(Y) + (size_t)T * D, T, D, s)));
     else
-      VL_TIMED(T_LN, VL_HIP(layernorm_rows(X, ly.ln1_g, ly.ln1_b, eps, Y, !f32, T, D, s)));
+      VL_TIMED(T_LN, VL_HIP(layernorm_rows(X, ly.ln1_g, ly.ln1_b, eps, Y, !f32, T, D, s, bc)));
     EpiArgs e1;
-    e1.bias = ly.qkv_b; e1.wscale = ly.qkv_s; e1.out = QH; e1.ldo = 3 * D;
+    e1.bias = ly.qkv_b; e1.wscale = ly.qkv_s; e1.out = QH; e1.ldo = 3 * D; e1.m_dev = m_dev;
     EpiArgs e2;
-    e2.bias = ly.o_b; e2.wscale = ly.o_s; e2.out = X; e2.ldo = D;
+    e2.bias = ly.o_b; e2.wscale = ly.o_s; e2.out = X; e2.ldo = D; e2.m_dev = m_dev;
     EpiArgs e3;
-    e3.bias = ly.fc1_b; e3.wscale = ly.fc1_s; e3.out = QH; e3.ldo = F;
+    e3.bias = ly.fc1_b; e3.wscale = ly.fc1_s; e3.out = QH; e3.ldo = F; e3.m_dev = m_dev;
     EpiArgs e4;
-    e4.bias = ly.fc2_b; e4.wscale = ly.fc2_s; e4.out = X; e4.ldo = D;
+    e4.bias = ly.fc2_b; e4.wscale = ly.fc2_s; e4.out = X; e4.ldo = D; e4.m_dev = m_dev;
     if (f32) {
       const float* y = static_cast<const float*>(Y);
       const float* qh = static_cast<const float*>(QH);
@@ -604,14 +678,14 @@ vl_status run_part(vl_model* m, const Part& p, const void* in, float* emb, char*
                                        gemm_cfg_for(m, 1, T), e1, s)));
       if (after_first_qkv && &ly == &m->layers[0]) VL_HIP(hipEventRecord(after_first_qkv, s));
       VL_TIMED(T_ATTN, {
-        VL_HIP(attention_bf16(qh, static_cast<bf16_t*>(Y), d_imgs, d_items, p.n_items, m->heads,
-                              m->hd, m->text, s));
-        VL_HIP(attention_bf16_resident(qh, Y, nullptr, false, T, d_imgs, d_res, p.n_res,
-                                       p.res_tiles, m->heads, m->hd, s));
+        VL_HIP(attention_bf16(qh, static_cast<bf16_t*>(Y), d_imgs, d_items, p.items_cap,
+                              m->heads, m->hd, m->text, s, bc));
+        VL_HIP(attention_bf16_resident(qh, Y, nullptr, false, T, d_imgs, d_res, p.res_cap,
+                                       p.res_class, m->heads, m->hd, s, bc));
       });
       VL_TIMED(T_OPROJ, VL_HIP(gemm_bf16(y, D, ly.o_w, D, fp8, T, D, D, OP_OPROJ,
                                          gemm_cfg_for(m, 2, T), e2, s)));
-      VL_TIMED(T_LN, VL_HIP(layernorm_rows(X, ly.ln2_g, ly.ln2_b, eps, Y, true, T, D, s)));
+      VL_TIMED(T_LN, VL_HIP(layernorm_rows(X, ly.ln2_g, ly.ln2_b, eps, Y, true, T, D, s, bc)));
       VL_TIMED(T_FC1, VL_HIP(gemm_bf16(y, D, ly.fc1_w, D, fp8, T, F, D, OP_FC1,
                                        gemm_cfg_for(m, 3, T), e3, s)));
       VL_TIMED(T_FC2, VL_HIP(gemm_bf16(qh, F, ly.fc2_w, F, fp8, T, D, F, OP_FC2,
@@ -652,10 +726,10 @@ vl_status run_part(vl_model* m, const Part& p, const void* in, float* emb, char*
   }
   // The QKV region is free after the last block and holds the n x D pooled
   // rows (it is at least 3 x T x D x 2 bytes and T >= n).
-  VL_TIMED(T_POOL, VL_HIP(pool_project(X, d_imgs, p.n, m->lnf_g, m->lnf_b, eps, m->proj, D,
+  VL_TIMED(T_POOL, VL_HIP(pool_project(X, d_imgs, p.n_cap, m->lnf_g, m->lnf_b, eps, m->proj, D,
                                         m->Pd, m->text, static_cast<float*>(QH),
                                         reinterpret_cast<float*>(ws + p.off_E),
-                                        emb + (size_t)p.i0 * m->Pd, s)));
+                                        emb + (size_t)p.i0 * m->Pd, s, bc)));
   return VL_OK;
 }
 
@@ -683,11 +757,25 @@ vl_status run_encoder(vl_model* m, const Plan& p, const void* pix, float* emb, c
   return st != VL_OK ? st : st2;
 }
 
+// Graph cache key.  A bucketed plan's graph serves every batch of its
+// bucket on this workspace and stream: the key is the parts' capacities;
+// pixels, outputs, counts and descriptors are read on the device.  Otherwise the key is the exact batch and its pointers.
 std::string graph_key(const Plan& p, const void* pix, const void* emb, const void* ws,
                       size_t ws_bytes, hipStream_t s) {
   std::string k;
   k.reserve(64 + 8 * p.n);
   auto put = [&](const void* v, size_t n) { k.append(static_cast<const char*>(v), n); };
+  if (p.bucketed) {
+    k.push_back('B');
+    put(&ws, sizeof ws);
+    put(&s, sizeof s);
+    for (const Part& q : p.parts) {
+      const int32_t c[2] = {q.T_cap, q.n_cap};
+      put(c, sizeof c);
+    }
+    return k;
+  }
+  k.push_back('E');
   put(&pix, sizeof pix); put(&emb, sizeof emb); put(&ws, sizeof ws); put(&ws_bytes, sizeof ws_bytes);
   put(&s, sizeof s); put(&p.n, sizeof p.n);
   const size_t np = p.parts.size();
@@ -1109,12 +1197,22 @@ vl_status vl_model_op_times(vl_model* m, double* ms_out, int64_t* launches_out, 
   return VL_OK;
 }
 
+vl_status vl_model_graph_stats(vl_model* m, int64_t* captures, int64_t* replays,
+                               int32_t* cached) {
+  if (!m) return fail(VL_ERR_INVALID_ARG, "model is NULL");
+  std::lock_guard<std::mutex> lk(m->mu);
+  if (captures) *captures = m->graph_captures;
+  if (replays) *replays = m->graph_replays;
+  if (cached) *cached = (int32_t)m->graphs.size();
+  return VL_OK;
+}
+
 size_t vl_encode_workspace_bytes(const vl_model* m, int32_t n, const int32_t* hs,
                                  const int32_t* ws) {
   if (!m) return 0;
   Plan p;
   std::string why;
-  if (!make_plan(m, n, hs, ws, &p, &why)) return 0;
+  if (!make_plan(m, n, hs, ws, &p, &why, false, bucket_mode(m))) return 0;
   return p.total;
 }
 
@@ -1130,6 +1228,12 @@ static vl_status encode_planned(vl_model* m, const Plan& p, const void* pix, flo
     if (st != VL_OK) return st;
     return mark_use(m, s);
   }
+  // A bucketed graph reads this call's descriptors, uploaded ahead of it on
+  // the same stream; an exact-key graph holds its own upload.
+  if (p.bucketed) {
+    const vl_status st0 = stage_descriptors(m, p, w, s);
+    if (st0 != VL_OK) return st0;
+  }
   const std::string key = graph_key(p, pix, emb, ws, ws_bytes, s);
   auto it = m->graphs.find(key);
   if (it == m->graphs.end()) {
@@ -1140,14 +1244,21 @@ static vl_status encode_planned(vl_model* m, const Plan& p, const void* pix, flo
     if (!m->capture) VL_HIP(hipStreamCreateWithFlags(&m->capture, hipStreamNonBlocking));
     hipStream_t cs = m->capture;
     GraphEntry ge;
-    VL_HIP(hipHostMalloc(&ge.host, std::max<size_t>(p.desc_bytes, 256), hipHostMallocDefault));
-    std::memcpy(ge.host, p.desc.data(), p.desc_bytes);
+    if (!p.bucketed) {
+      VL_HIP(hipHostMalloc(&ge.host, std::max<size_t>(p.desc_bytes, 256), hipHostMallocDefault));
+      std::memcpy(ge.host, p.desc.data(), p.desc_bytes);
+    }
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) { (void)hipHostFree(ge.host); return hip_fail(e, "hipStreamBeginCapture"); }
+    if (e != hipSuccess) {
+      if (ge.host) (void)hipHostFree(ge.host);
+      return hip_fail(e, "hipStreamBeginCapture");
+    }
     vl_status st = VL_OK;
-    e = hipMemcpyAsync(w, ge.host, p.desc_bytes, hipMemcpyHostToDevice, cs);
-    if (e != hipSuccess) st = hip_fail(e, "hipMemcpyAsync(descriptors)");
+    if (!p.bucketed) {
+      e = hipMemcpyAsync(w, ge.host, p.desc_bytes, hipMemcpyHostToDevice, cs);
+      if (e != hipSuccess) st = hip_fail(e, "hipMemcpyAsync(descriptors)");
+    }
     if (st == VL_OK) st = run_encoder(m, p, pix, emb, w, cs);
     e = hipStreamEndCapture(cs, &g);
     if (st == VL_OK && e != hipSuccess) st = hip_fail(e, "hipStreamEndCapture");
@@ -1162,10 +1273,12 @@ static vl_status encode_planned(vl_model* m, const Plan& p, const void* pix, flo
     }
     if (st != VL_OK) { release_graph(ge); return st; }
     it = m->graphs.emplace(key, ge).first;
+    ++m->graph_captures;
   }
   VL_HIP(hipGraphLaunch(it->second.exec, s));
   VL_HIP(hipEventRecord(it->second.done, s));
   it->second.last_use = ++m->graph_clock;
+  ++m->graph_replays;
   return mark_use(m, s);
 }
 
@@ -1178,10 +1291,12 @@ vl_status vl_encode_images(vl_model* m, const float* pix, const int32_t* hs, con
     return fail(VL_ERR_INVALID_ARG, "pixels and emb_out must be 16-byte aligned");
   Plan p;
   std::string why;
-  if (!make_plan(m, n, hs, wsz, &p, &why)) return fail(VL_ERR_INVALID_ARG, why);
+  if (!make_plan(m, n, hs, wsz, &p, &why, false, bucket_mode(m)))
+    return fail(VL_ERR_INVALID_ARG, why);
   if (ws_bytes < p.total)
     return fail(VL_ERR_WORKSPACE_TOO_SMALL, "workspace has " + std::to_string(ws_bytes) +
                                                 " bytes, needs " + std::to_string(p.total));
+  bind_batch(p, pix, emb, m->Pd);
   return encode_planned(m, p, pix, emb, ws, ws_bytes, stream);
 }
 

@@ -74,7 +74,8 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
                                                    uint8_t* __restrict__ out_scale, int T_rows,
                                                    const ImgDesc* __restrict__ imgs,
                                                    const AttnItem* __restrict__ items,
-                                                   int heads, int causal) {
+                                                   int heads, int causal,
+                                                   const BatchCounts* __restrict__ bc) {
   using T = KvTile<HD, false>;
   using TV = KvTile<HD, true>;
   constexpr int RPI = 1024 / T::ROWB;          // tile rows per 1 KB load instruction
@@ -83,8 +84,13 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
   __shared__ __attribute__((aligned(1024))) char sK[ATT_ST][T::BYTES];
   __shared__ __attribute__((aligned(1024))) char sV[ATT_ST][T::BYTES];
 
-  const int n_items = gridDim.x / heads;
-  const int wi = xcd_linear(blockIdx.x, gridDim.x);
+  int n_items = gridDim.x / heads, total = gridDim.x;
+  if (bc) {   // capacity launch: the live item count comes from the device
+    n_items = bc->n_items;
+    total = n_items * heads;
+    if (!xcd_live(blockIdx.x, total)) return;
+  }
+  const int wi = xcd_linear(blockIdx.x, total);
   const AttnItem it = items[wi % n_items];
   const int h = wi / n_items;
   const ImgDesc dsc = imgs[it.img];
@@ -335,7 +341,8 @@ constexpr int RES_W = 8;   // waves per resident workgroup
 template <int NT, bool MX>
 __global__ __launch_bounds__(RES_W * 64) void k_attn_bf16_res(
     const bf16_t* __restrict__ qkv, void* __restrict__ out, uint8_t* __restrict__ out_scale,
-    int T_rows, const ImgDesc* __restrict__ imgs, const int* __restrict__ res_imgs, int heads) {
+    int T_rows, const ImgDesc* __restrict__ imgs, const int* __restrict__ res_imgs, int heads,
+    const BatchCounts* __restrict__ bc) {
   constexpr int HD = 64;
   using T = KvTile<HD, false>;
   using TV = KvTile<HD, true>;
@@ -345,8 +352,13 @@ __global__ __launch_bounds__(RES_W * 64) void k_attn_bf16_res(
   __shared__ __attribute__((aligned(1024))) char sK[NT][T::BYTES];
   __shared__ __attribute__((aligned(1024))) char sV[NT][T::BYTES];
 
-  const int n_res = gridDim.x / heads;
-  const int wi = xcd_linear(blockIdx.x, gridDim.x);
+  int n_res = gridDim.x / heads, total = gridDim.x;
+  if (bc) {   // capacity launch: the live image count comes from the device
+    n_res = bc->n_res;
+    total = n_res * heads;
+    if (!xcd_live(blockIdx.x, total)) return;
+  }
+  const int wi = xcd_linear(blockIdx.x, total);
   const int img = res_imgs[wi % n_res];
   const int h = wi / n_res;
   const ImgDesc dsc = imgs[img];
@@ -569,20 +581,20 @@ constexpr int RES_MIN_TOKENS = ATT_Q + 1, RES_MAX_TILES = 10;
 template <bool MX>
 static hipError_t launch_res(const bf16_t* qkv, void* out, uint8_t* out_scale, int T,
                              const ImgDesc* imgs, const int* res_imgs, int n_res, int max_tiles,
-                             int heads, hipStream_t s) {
+                             int heads, hipStream_t s, const BatchCounts* bc) {
   dim3 grid(n_res * heads), block(RES_W * 64);
   if (max_tiles <= 4)
     hipLaunchKernelGGL((k_attn_bf16_res<4, MX>), grid, block, 0, s, qkv, out, out_scale, T, imgs,
-                       res_imgs, heads);
+                       res_imgs, heads, bc);
   else if (max_tiles <= 6)
     hipLaunchKernelGGL((k_attn_bf16_res<6, MX>), grid, block, 0, s, qkv, out, out_scale, T, imgs,
-                       res_imgs, heads);
+                       res_imgs, heads, bc);
   else if (max_tiles <= 8)
     hipLaunchKernelGGL((k_attn_bf16_res<8, MX>), grid, block, 0, s, qkv, out, out_scale, T, imgs,
-                       res_imgs, heads);
+                       res_imgs, heads, bc);
   else if (max_tiles <= RES_MAX_TILES)
     hipLaunchKernelGGL((k_attn_bf16_res<RES_MAX_TILES, MX>), grid, block, 0, s, qkv, out,
-                       out_scale, T, imgs, res_imgs, heads);
+                       out_scale, T, imgs, res_imgs, heads, bc);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -590,12 +602,14 @@ static hipError_t launch_res(const bf16_t* qkv, void* out, uint8_t* out_scale, i
 
 hipError_t attention_bf16_resident(const bf16_t* qkv, void* out, uint8_t* out_scale, bool mx,
                                    int T, const ImgDesc* imgs, const int* res_imgs, int n_res,
-                                   int max_tiles, int heads, int head_dim, hipStream_t s) {
+                                   int max_tiles, int heads, int head_dim, hipStream_t s,
+                                   const BatchCounts* bc) {
   if (n_res <= 0) return hipSuccess;
   if (head_dim != 64) return hipErrorInvalidValue;
-  return mx ? launch_res<true>(qkv, out, out_scale, T, imgs, res_imgs, n_res, max_tiles, heads, s)
+  return mx ? launch_res<true>(qkv, out, out_scale, T, imgs, res_imgs, n_res, max_tiles, heads, s,
+                               bc)
             : launch_res<false>(qkv, out, out_scale, T, imgs, res_imgs, n_res, max_tiles, heads,
-                                s);
+                                s, bc);
 }
 
 // ----------------------------------------------------------------- FP32
@@ -751,15 +765,15 @@ hipError_t map_attention(const void* kv, bool kv_bf16, const float* q, const Img
 
 hipError_t attention_bf16(const bf16_t* qkv, bf16_t* o, const ImgDesc* imgs,
                           const AttnItem* items, int n_items, int heads, int head_dim,
-                          bool causal, hipStream_t s) {
+                          bool causal, hipStream_t s, const BatchCounts* bc) {
   if (n_items <= 0) return hipSuccess;
   dim3 grid(n_items * heads), block(256);
   if (head_dim == 64)
     hipLaunchKernelGGL((k_attn_bf16<64, false>), grid, block, 0, s, qkv, o, nullptr, 0, imgs,
-                       items, heads, (int)causal);
+                       items, heads, (int)causal, bc);
   else if (head_dim == 32)
     hipLaunchKernelGGL((k_attn_bf16<32, false>), grid, block, 0, s, qkv, o, nullptr, 0, imgs,
-                       items, heads, (int)causal);
+                       items, heads, (int)causal, bc);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -772,10 +786,10 @@ hipError_t attention_bf16_mx(const bf16_t* qkv, uint8_t* codes, uint8_t* scales,
   dim3 grid(n_items * heads), block(256);
   if (head_dim == 64)
     hipLaunchKernelGGL((k_attn_bf16<64, true>), grid, block, 0, s, qkv, codes, scales, T, imgs,
-                       items, heads, (int)causal);
+                       items, heads, (int)causal, nullptr);
   else if (head_dim == 32)
     hipLaunchKernelGGL((k_attn_bf16<32, true>), grid, block, 0, s, qkv, codes, scales, T, imgs,
-                       items, heads, (int)causal);
+                       items, heads, (int)causal, nullptr);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

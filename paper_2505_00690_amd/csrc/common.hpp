@@ -188,4 +188,15 @@ __device__ __forceinline__ float block_reduce(float v, float* red, Op op) {
   return v;
 }
 
+// Workgroup ids are dealt round-robin to the 8 XCDs, and a kernel that gives
+// each XCD a contiguous range of `total` items hands XCD x total / 8 of them,
+// plus one when x < total % 8.  When the grid has more workgroups than
+// `total` (a launch sized for a capacity), the live workgroups of XCD x are
+// those with bid / 8 below that count, and all of them exist in any grid of
+// at least `total` workgroups.
+__device__ __forceinline__ bool xcd_live(int bid, int total) {
+  const int xcd = bid & 7, local = bid >> 3;
+  return local < (total >> 3) + (xcd < (total & 7) ? 1 : 0);
+}
+
 }  // namespace vl

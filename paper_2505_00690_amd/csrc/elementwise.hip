@@ -14,10 +14,12 @@ template <int NPER, bool OUT_BF16>
 __global__ __launch_bounds__(256) void k_layernorm(const float* __restrict__ x,
                                                    const float* __restrict__ gm,
                                                    const float* __restrict__ bt, float eps,
-                                                   void* __restrict__ y, int M) {
+                                                   void* __restrict__ y, int M,
+                                                   const BatchCounts* __restrict__ bc) {
   constexpr int D = NPER * 64;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
+  if (bc) M = bc->T;   // capacity launch: live rows
   if (row >= M) return;
   const float* xr = x + (size_t)row * D;
   float v[NPER];
@@ -48,26 +50,26 @@ __global__ __launch_bounds__(256) void k_layernorm(const float* __restrict__ x,
 
 template <int NPER>
 static void launch_ln(const float* x, const float* g, const float* b, float eps, void* y,
-                      bool y_bf16, int M, hipStream_t s) {
+                      bool y_bf16, int M, hipStream_t s, const BatchCounts* bc) {
   dim3 grid((M + 3) / 4), block(256);
   if (y_bf16)
-    hipLaunchKernelGGL((k_layernorm<NPER, true>), grid, block, 0, s, x, g, b, eps, y, M);
+    hipLaunchKernelGGL((k_layernorm<NPER, true>), grid, block, 0, s, x, g, b, eps, y, M, bc);
   else
-    hipLaunchKernelGGL((k_layernorm<NPER, false>), grid, block, 0, s, x, g, b, eps, y, M);
+    hipLaunchKernelGGL((k_layernorm<NPER, false>), grid, block, 0, s, x, g, b, eps, y, M, bc);
 }
 
 hipError_t layernorm_rows(const float* x, const float* g, const float* b, float eps, void* y,
-                          bool y_bf16, int M, int D, hipStream_t s) {
+                          bool y_bf16, int M, int D, hipStream_t s, const BatchCounts* bc) {
   if (M <= 0) return hipSuccess;
   switch (D / 64) {
-    case 2: launch_ln<2>(x, g, b, eps, y, y_bf16, M, s); break;
-    case 4: launch_ln<4>(x, g, b, eps, y, y_bf16, M, s); break;
-    case 6: launch_ln<6>(x, g, b, eps, y, y_bf16, M, s); break;
-    case 8: launch_ln<8>(x, g, b, eps, y, y_bf16, M, s); break;
-    case 10: launch_ln<10>(x, g, b, eps, y, y_bf16, M, s); break;
-    case 12: launch_ln<12>(x, g, b, eps, y, y_bf16, M, s); break;
-    case 14: launch_ln<14>(x, g, b, eps, y, y_bf16, M, s); break;
-    case 16: launch_ln<16>(x, g, b, eps, y, y_bf16, M, s); break;
+    case 2: launch_ln<2>(x, g, b, eps, y, y_bf16, M, s, bc); break;
+    case 4: launch_ln<4>(x, g, b, eps, y, y_bf16, M, s, bc); break;
+    case 6: launch_ln<6>(x, g, b, eps, y, y_bf16, M, s, bc); break;
+    case 8: launch_ln<8>(x, g, b, eps, y, y_bf16, M, s, bc); break;
+    case 10: launch_ln<10>(x, g, b, eps, y, y_bf16, M, s, bc); break;
+    case 12: launch_ln<12>(x, g, b, eps, y, y_bf16, M, s, bc); break;
+    case 14: launch_ln<14>(x, g, b, eps, y, y_bf16, M, s, bc); break;
+    case 16: launch_ln<16>(x, g, b, eps, y, y_bf16, M, s, bc); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -322,7 +324,12 @@ template <bool OUT_BF16>
 __global__ __launch_bounds__(256) void k_im2col(const float* __restrict__ pix,
                                                 const ImgDesc* __restrict__ imgs, int chans,
                                                 int patch, int kpad, void* __restrict__ out,
-                                                int2* __restrict__ tok_info) {
+                                                int2* __restrict__ tok_info,
+                                                const BatchCounts* __restrict__ bc) {
+  if (bc) {   // capacity launch: live images and the call's pixel buffer
+    if ((int)blockIdx.y >= bc->n) return;
+    pix = bc->pix;
+  }
   const ImgDesc d = imgs[blockIdx.y];
   const int tok = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -360,15 +367,16 @@ __global__ __launch_bounds__(256) void k_im2col(const float* __restrict__ pix,
 }
 
 hipError_t im2col(const float* pix, const ImgDesc* imgs, int n_imgs, int max_ntok, int chans,
-                  int patch, int kpad, void* out, bool out_bf16, int2* tok_info, hipStream_t s) {
+                  int patch, int kpad, void* out, bool out_bf16, int2* tok_info, hipStream_t s,
+                  const BatchCounts* bc) {
   if (n_imgs <= 0) return hipSuccess;
   dim3 grid((max_ntok + 3) / 4, n_imgs), block(256);
   if (out_bf16)
     hipLaunchKernelGGL(k_im2col<true>, grid, block, 0, s, pix, imgs, chans, patch, kpad, out,
-                       tok_info);
+                       tok_info, bc);
   else
     hipLaunchKernelGGL(k_im2col<false>, grid, block, 0, s, pix, imgs, chans, patch, kpad, out,
-                       tok_info);
+                       tok_info, bc);
   return hipGetLastError();
 }
 
@@ -385,8 +393,10 @@ __global__ __launch_bounds__(256) void k_pool_ln(const float* __restrict__ x,
                                                  const ImgDesc* __restrict__ imgs,
                                                  const float* __restrict__ gm,
                                                  const float* __restrict__ bt, float eps, int D,
-                                                 float* __restrict__ z, int pool_last) {
+                                                 float* __restrict__ z, int pool_last,
+                                                 const BatchCounts* __restrict__ bc) {
   __shared__ float red[4];
+  if (bc && (int)blockIdx.x >= bc->n) return;   // capacity launch: live sequences
   const int tid = threadIdx.x;
   const ImgDesc d = imgs[blockIdx.x];
   const float* xr = x + (size_t)(d.tok_start + (pool_last ? d.ntok - 1 : 0)) * D;
@@ -405,9 +415,14 @@ __global__ __launch_bounds__(256) void k_pool_ln(const float* __restrict__ x,
 
 // Row-wise division by the L2 norm (clamped at 1e-12).  One wave per row.
 __global__ __launch_bounds__(256) void k_l2_normalise(const float* __restrict__ e,
-                                                      float* __restrict__ out, int rows, int P) {
+                                                      float* __restrict__ out, int rows, int P,
+                                                      const BatchCounts* __restrict__ bc) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
+  if (bc) {   // capacity launch: live rows, written to the call's output
+    rows = bc->n;
+    out = bc->emb;
+  }
   if (row >= rows) return;
   const float* er = e + (size_t)row * P;
   float n2 = 0.f;
@@ -418,25 +433,29 @@ __global__ __launch_bounds__(256) void k_l2_normalise(const float* __restrict__ 
 
 hipError_t pool_project(const float* x, const ImgDesc* imgs, int n_imgs, const float* g,
                         const float* b, float eps, const float* proj, int D, int P,
-                        bool pool_last, float* z, float* e_tmp, float* emb, hipStream_t s) {
+                        bool pool_last, float* z, float* e_tmp, float* emb, hipStream_t s,
+                        const BatchCounts* bc) {
   if (n_imgs <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_pool_ln, dim3(n_imgs), dim3(256), 0, s, x, imgs, g, b, eps, D, z,
-                     (int)pool_last);
+                     (int)pool_last, bc);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   // e_tmp = z . proj^T (the projection has no bias)
   EpiArgs ep;
   ep.out = e_tmp; ep.ldo = P;
+  // (with bc, rows past the live count project unwritten z rows; no output
+  // depends on them)
   err = gemm_f32_rows(z, D, proj, D, n_imgs, P, D, OP_LOGITS, ep, s);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_l2_normalise, dim3((n_imgs + 3) / 4), dim3(256), 0, s, e_tmp, emb, n_imgs,
-                     P);
+                     P, bc);
   return hipGetLastError();
 }
 
 hipError_t l2_normalise_rows(const float* e, float* out, int rows, int P, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_l2_normalise, dim3((rows + 3) / 4), dim3(256), 0, s, e, out, rows, P);
+  hipLaunchKernelGGL(k_l2_normalise, dim3((rows + 3) / 4), dim3(256), 0, s, e, out, rows, P,
+                     nullptr);
   return hipGetLastError();
 }
 

@@ -351,6 +351,11 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
     K = min(e.kc, K - k0);
     e.out = static_cast<float*>(e.out) + blockIdx.y * e.zstride;
   }
+  if (e.m_dev) {   // capacity launch: the live row count comes from the device
+    M = *e.m_dev;
+    gm = (M + BM - 1) / BM;
+    if (!xcd_live(blockIdx.x, gm * gn)) return;
+  }
   int tm_, tn_;
   xcd_tile(gm, gn, 8, &tm_, &tn_);
   const int m0 = tm_ * BM, n0 = tn_ * BN;

@@ -24,6 +24,21 @@ struct AttnItem {
   int32_t q0;
 };
 
+// The live counts of one part of a batch, in device memory.  A launch
+// sequence captured once for a capacity bucket sizes its grids for the
+// capacities and passes a pointer to this record: each kernel reads the
+// counts of the call being replayed and its workgroups past them return at
+// once.  Launches outside such a sequence pass NULL.
+struct BatchCounts {
+  int32_t T;        // token rows
+  int32_t n;        // images
+  int32_t n_items;  // streamed attention work items
+  int32_t n_res;    // K/V-resident attention images
+  const float* pix; // the batch's pixel buffer (ImgDesc::pix_off is relative to it)
+  float* emb;       // this part's first output row
+};
+static_assert(sizeof(BatchCounts) == 32, "BatchCounts layout");
+
 // The contractions of the path.  Each has its own kernel instantiation (so
 // profiles name them apart) and a fixed epilogue:
 //   OP_PATCH  : X[m,n] = acc + (class token ? cls[n] : bias[n]) + pos(m,n)
@@ -71,6 +86,9 @@ struct EpiArgs {
   // and writes its FP32 partial product at out + z * zstride.
   int kc = 0;
   size_t zstride = 0;
+  // Capacity launches (BF16 GEMMs): the grid covers M rows, the live row
+  // count is *m_dev (<= M); tiles past it return at once.
+  const int32_t* m_dev = nullptr;
 };
 
 // Tile configurations of the BF16 GEMM.  Every configuration accumulates K
@@ -127,9 +145,11 @@ hipError_t gemm_f32(const float* A, int lda, const float* B, int ldb, int M, int
 hipError_t gemm_f32_rows(const float* A, int lda, const float* B, int ldb, int M, int N,
                          int K, int op, const EpiArgs& e, hipStream_t s);
 
-// LayerNorm of FP32 rows [M, D] -> BF16 or FP32 rows.
+// LayerNorm of FP32 rows [M, D] -> BF16 or FP32 rows (with bc: rows
+// [0, bc->T) of a grid sized for M).
 hipError_t layernorm_rows(const float* x, const float* g, const float* b, float eps,
-                          void* y, bool y_bf16, int M, int D, hipStream_t s);
+                          void* y, bool y_bf16, int M, int D, hipStream_t s,
+                          const BatchCounts* bc = nullptr);
 
 // LayerNorm folding (see EpiArgs): for the first block, u = bf16(x * g) and
 // row_stats (mean, rstd) of x [M, D] directly; elsewhere row_stats from the
@@ -150,16 +170,17 @@ hipError_t layernorm_rows_mx(const float* x, const float* g, const float* b, flo
 
 // Patch gathering: token rows [T, Kpad] of raw pixels in (c, a, b) order
 // over `chans` input planes (class-token rows and the K padding are zero)
-// plus tok_info [T].
+// plus tok_info [T].  With bc: images [0, bc->n) of bc->pix.
 hipError_t im2col(const float* pix, const ImgDesc* imgs, int n_imgs, int max_ntok, int chans,
                   int patch, int kpad, void* out, bool out_bf16, int2* tok_info,
-                  hipStream_t s);
+                  hipStream_t s, const BatchCounts* bc = nullptr);
 
 // Multi-head self-attention over a packed QKV buffer [T, 3D] -> O [T, D],
 // within each descriptor's token range; causal: token i attends to 0..i.
+// With bc: items [0, bc->n_items) of a grid sized for n_items.
 hipError_t attention_bf16(const bf16_t* qkv, bf16_t* o, const ImgDesc* imgs,
                           const AttnItem* items, int n_items, int heads, int head_dim,
-                          bool causal, hipStream_t s);
+                          bool causal, hipStream_t s, const BatchCounts* bc = nullptr);
 // The same with an MXFP8 output: codes [T, D] + scales [D/128][T][4].
 hipError_t attention_bf16_mx(const bf16_t* qkv, uint8_t* codes, uint8_t* scales, int T,
                              const ImgDesc* imgs, const AttnItem* items, int n_items,
@@ -168,9 +189,11 @@ hipError_t attention_bf16_mx(const bf16_t* qkv, uint8_t* codes, uint8_t* scales,
 // workgroup per (image, head) over res_imgs[0 .. n_res) (image indices);
 // max_tiles = the largest ceil(tokens / 64) among them (<= 10).  Output as
 // attention_bf16 (mx = false) or attention_bf16_mx (mx = true), bitwise.
+// With bc: images [0, bc->n_res) of a grid sized for n_res.
 hipError_t attention_bf16_resident(const bf16_t* qkv, void* out, uint8_t* out_scale, bool mx,
                                    int T, const ImgDesc* imgs, const int* res_imgs, int n_res,
-                                   int max_tiles, int heads, int head_dim, hipStream_t s);
+                                   int max_tiles, int heads, int head_dim, hipStream_t s,
+                                   const BatchCounts* bc = nullptr);
 hipError_t attention_f32(const float* qkv, float* o, const ImgDesc* imgs,
                          const AttnItem* items, int n_items, int heads, int head_dim,
                          bool causal, hipStream_t s);
@@ -178,10 +201,12 @@ hipError_t attention_f32(const float* qkv, float* o, const ImgDesc* imgs,
 // Pooling of each sequence's first (class token) or last (pool_last: the
 // text end-of-text token) row, final LayerNorm into z [n, D] (scratch),
 // projection [P, D] into e_tmp [n, P], then L2 normalisation into emb [n, P].
-// D % 4 == 0, P % 4 == 0.
+// D % 4 == 0, P % 4 == 0.  With bc: sequences [0, bc->n) of grids sized for
+// n_imgs, written to bc->emb (emb unused).
 hipError_t pool_project(const float* x, const ImgDesc* imgs, int n_imgs, const float* g,
                         const float* b, float eps, const float* proj, int D, int P,
-                        bool pool_last, float* z, float* e_tmp, float* emb, hipStream_t s);
+                        bool pool_last, float* z, float* e_tmp, float* emb, hipStream_t s,
+                        const BatchCounts* bc = nullptr);
 
 // Row-wise division of e [rows, P] by its L2 norm (clamped at 1e-12).
 hipError_t l2_normalise_rows(const float* e, float* out, int rows, int P, hipStream_t s);

@@ -222,7 +222,13 @@ class GpuExecutor(Executor):
     gathered into one packed buffer on the slot's stream.  Texts stay
     resident.  Outputs per request: (embeddings, top-1)."""
 
-    def __init__(self, encoder, texts, head: str, scale: float, bias: float, slots: int):
+    def __init__(self, encoder, texts, head: str, scale: float, bias: float, slots: int,
+                 keep_workspaces: bool = False):
+        """keep_workspaces: each slot keeps its encoder workspace across
+        batches (grown to the largest batch it has run), so an encoder with
+        graph replay on replays one graph per (slot, capacity bucket); the
+        device memory held is then up to `slots` of the largest workspace
+        admitted, beyond what the admission budget counts per batch."""
         import torch
         from . import vl
         self.torch, self.vl = torch, vl
@@ -230,6 +236,8 @@ class GpuExecutor(Executor):
         self.texts = texts
         self.head, self.scale, self.bias = head, scale, bias
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        self.keep = keep_workspaces
+        self.ws = [None] * slots
 
     def workspace_bytes(self, sizes):
         """Device bytes a batch holds while it runs: the encoder workspace
@@ -252,7 +260,13 @@ class GpuExecutor(Executor):
             for r in reqs:
                 parts.extend(r.payload if isinstance(r.payload, (list, tuple)) else [r.payload])
             pix = torch.cat(parts) if len(parts) > 1 else parts[0]
-            ws = torch.empty(self.enc.workspace_bytes(sizes), dtype=torch.uint8, device="cuda")
+            need = self.enc.workspace_bytes(sizes)
+            if self.keep:
+                if self.ws[slot] is None or self.ws[slot].numel() < need:
+                    self.ws[slot] = torch.empty(need, dtype=torch.uint8, device="cuda")
+                ws = self.ws[slot]
+            else:
+                ws = torch.empty(need, dtype=torch.uint8, device="cuda")
             emb = torch.empty((n, self.enc.cfg.proj_dim), dtype=torch.float32, device="cuda")
             sc = torch.empty((n, self.texts.shape[0]), dtype=torch.float32, device="cuda")
             top = torch.empty(n, dtype=torch.int32, device="cuda")

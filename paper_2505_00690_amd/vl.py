@@ -29,7 +29,7 @@ __all__ = [
     "vl_attention_workspace_bytes", "vl_attention", "vl_model_save_tuning",
     "vl_model_load_tuning", "vl_contrastive_loss_noalloc", "VL_NOALLOC_SCRATCH_BYTES",
     "vl_train_workspace_bytes", "vl_encode_images_train", "vl_encode_images_backward", "Trainer",
-    "vl_bf16_round", "vl_fp8_quantize_rows",
+    "vl_bf16_round", "vl_fp8_quantize_rows", "vl_model_graph_stats",
 ]
 
 VL_FP32, VL_BF16, VL_FP8W_BF16A, VL_MXFP8 = 0, 1, 2, 3
@@ -53,7 +53,7 @@ EXPORTED_SYMBOLS = (
     "vl_gemm_config_count", "vl_gemm_config_name", "vl_model_get_tuning",
     "vl_model_set_tuning", "vl_model_autotune", "vl_model_save_tuning", "vl_model_load_tuning",
     "vl_contrastive_loss_noalloc", "vl_train_workspace_bytes", "vl_encode_images_train",
-    "vl_encode_images_backward", "vl_bf16_round", "vl_fp8_quantize_rows",
+    "vl_encode_images_backward", "vl_bf16_round", "vl_fp8_quantize_rows", "vl_model_graph_stats",
 )
 VL_NOALLOC_SCRATCH_BYTES = 64 << 20
 VL_N_GEMM_OPS, VL_N_M_BUCKETS = 5, 25
@@ -140,6 +140,9 @@ def lib() -> ctypes.CDLL:
     L.vl_model_op_times.restype = ctypes.c_int
     L.vl_model_op_times.argtypes = [_vp, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+    L.vl_model_graph_stats.restype = ctypes.c_int
+    L.vl_model_graph_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_int64), _pi32]
     L.vl_gemm_config_count.restype = _i32
     L.vl_gemm_config_count.argtypes = []
     L.vl_gemm_config_name.restype = ctypes.c_char_p
@@ -264,6 +267,14 @@ def vl_model_op_times(handle, reset: bool = False):
     n = (ctypes.c_int64 * VL_N_OPS)()
     _check(lib().vl_model_op_times(handle, ms, n, 1 if reset else 0))
     return {OP_NAMES[i]: (float(ms[i]), int(n[i])) for i in range(VL_N_OPS)}
+
+
+def vl_model_graph_stats(handle) -> dict:
+    """Graph cache counters: {"captures", "replays", "cached"}."""
+    c, r = ctypes.c_int64(0), ctypes.c_int64(0)
+    k = ctypes.c_int32(0)
+    _check(lib().vl_model_graph_stats(handle, ctypes.byref(c), ctypes.byref(r), ctypes.byref(k)))
+    return {"captures": int(c.value), "replays": int(r.value), "cached": int(k.value)}
 
 
 def vl_gemm_config_count() -> int:
@@ -621,6 +632,9 @@ class Encoder:
         if cache:
             vl_model_save_tuning(self.handle, cache)
         return self.tuning()
+
+    def graph_stats(self) -> dict:
+        return vl_model_graph_stats(self.handle)
 
     def tuning(self) -> dict:
         t = vl_model_get_tuning(self.handle)

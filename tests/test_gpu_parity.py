@@ -171,6 +171,55 @@ def test_graph_replay_matches_eager(V):
         assert np.array_equal(out.cpu().numpy(), eager)
 
 
+def _graph_counts(V, enc):
+    st = V.vl_model_graph_stats(enc.handle)
+    return st["captures"], st["replays"]
+
+
+def test_bucketed_graph_serves_batches_of_one_bucket(V):
+    """With graph replay on, a BF16 or e4m3-weight image model keeps one graph
+    per capacity bucket (per part: tokens rounded up to a quarter octave,
+    images to a power of two), workspace and stream.  Different batches of
+    one bucket -- other image sizes and mixes of K/V-resident and streamed
+    attention, other pixel and output buffers -- replay that graph and give
+    the eager call's bits; a batch of another bucket captures its own."""
+    w = torch.from_numpy(blob("b16", 1001)).cuda()
+    eager = V.Encoder(synth.MODELS["b16"], w, "bf16")
+    genc = V.Encoder(synth.MODELS["b16"], w, "bf16", graphs=True)
+    # 541 and 529 tokens (capacity 640), 4 images each; tokens per image:
+    # 197, 101, 193, 50 and 183, 170, 111, 65 (resident: more than 128)
+    a = [(224, 224), (160, 160), (256, 192), (112, 112)]
+    b = [(224, 208), (208, 208), (176, 160), (128, 128)]
+    c = [(96, 96)] * 6                                   # 222 tokens, 6 images
+    assert genc.workspace_bytes(a) == genc.workspace_bytes(b) > eager.workspace_bytes(a)
+    seen = []
+    for k, (sizes, seed) in enumerate([(a, 2950), (b, 2951), (a, 2952), (c, 2953), (b, 2954)]):
+        imgs = synth.make_images(sizes, seed)
+        pix = torch.from_numpy(pack(imgs)).cuda()
+        ref = eager.encode(pix, sizes).cpu().numpy()
+        got = genc.encode(pix, sizes).cpu().numpy()
+        seen.append(_graph_counts(V, genc))
+        _say(f"  bucketed graph call {k}: captures, replays = {seen[-1]}")
+        assert np.array_equal(got, ref), k
+    assert seen == [(1, 1), (1, 2), (1, 3), (2, 4), (2, 5)]
+    # two parts on two streams (tiny, e4m3 weights): 24 images of 197 tokens,
+    # then 12 pairs of 197 + 211 tokens; parts of 12 images, 2364 and 2448
+    # tokens per part (capacity 2560 tokens, 16 images)
+    wt = torch.from_numpy(blob("tiny", 1000)).cuda()
+    e2 = V.Encoder(synth.MODELS["tiny"], wt, "fp8w", split=True)
+    g2 = V.Encoder(synth.MODELS["tiny"], wt, "fp8w", split=True, graphs=True)
+    for k, (sizes, seed) in enumerate([([(224, 224)] * 24, 2960),
+                                       ([(224, 224), (240, 224)] * 12, 2961)]):
+        imgs = synth.make_images(sizes, seed)
+        pix = torch.from_numpy(pack(imgs)).cuda()
+        ref = e2.encode(pix, sizes).cpu().numpy()
+        got = g2.encode(pix, sizes).cpu().numpy()
+        assert np.array_equal(got, ref), k
+    assert _graph_counts(V, g2) == (1, 2)
+    for e in (eager, genc, e2, g2):
+        e.close()
+
+
 def test_two_part_split_bitwise(V):
     """A batch above the split threshold runs as two parts on two streams;
     every embedding equals the one-part run bit for bit, eager and replayed
