@@ -18,6 +18,7 @@
 
 #include "../../include/vl.h"
 #include "kernels.hpp"
+#include "plan.hpp"
 
 using namespace vl;
 
@@ -41,15 +42,7 @@ vl_status hip_fail(hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail(e_, #call);  \
   } while (0)
 
-constexpr size_t kAlign = 256;
 static_assert(kNoAllocScratchBytes == VL_NOALLOC_SCRATCH_BYTES, "scratch size in vl.h");
-inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-constexpr int kMaxTokens = 1025;   // 32 x 32 patches + class token
-constexpr int kAttnQ = 128;        // queries per attention work item
-constexpr int kResMinTokens = 128; // K/V-resident attention: more tokens than one work item
-constexpr int kResMaxTiles = 10;   //   and at most 10 key tiles of 64 (the 160 KB of LDS)
-constexpr int kMaxItems = 65535;   // images / texts per call (grid y of the gather kernels)
 
 struct Layer {
   const float *ln1_g, *ln1_b, *ln2_g, *ln2_b;
@@ -199,59 +192,29 @@ size_t weights_count(const vl_config& c) {
 }
 
 // ----------------------------------------------------------------- planning
-// A batch runs as one or two parts.  A part is a run of consecutive images
-// with its own descriptors (token starts relative to the part) and its own
-// regions of every activation buffer, so two parts never share memory and
-// can run concurrently on two streams.  Every kernel works per token row or
-// per image with a fixed accumulation order, so a part computes exactly what
-// the whole batch would for its images.
-constexpr int64_t kSplitMinTokens = 4096;  // split batches of at least this many tokens
-
-struct Part {
-  int i0 = 0, n = 0, T = 0, max_ntok = 0, n_items = 0;
-  size_t off_imgs = 0, off_items = 0;                       // in the descriptor region
-  // Images whose attention runs K/V-resident (indices within the part) and
-  // the largest of their key-tile counts.
-  size_t off_res = 0;
-  int n_res = 0, res_tiles = 0;
-  size_t off_tok = 0, off_X = 0, off_Y = 0, off_QH = 0, off_E = 0;  // in the workspace
-  size_t off_map = 0;   // MAP pooling: per image O, x, LN(x) [n, D] and MLP hidden [n, F]
-  // LayerNorm folding: u = bf16(x * gamma) [T, D], per-32-column (mean, M2)
-  // partials [T, D/32, 2] and row (mean, rstd) [T, 2]
-  size_t off_U = 0, off_PS = 0, off_RS = 0;
-  // Launch sizes and buffer regions.  Equal to the counts above, except in
-  // a bucketed plan, where they are the bucket's capacities and the kernels
-  // read the live counts from the part's BatchCounts record at off_bc.
-  bool bucketed = false;
-  int T_cap = 0, n_cap = 0, items_cap = 0, res_cap = 0, ntok_cap = 0, res_class = 0;
-  size_t off_bc = 0;
-};
-
-struct Plan {
-  bool bucketed = false;
-  int n = 0, T = 0;
-  std::vector<int32_t> hw;          // (H, W) per image, for graph keys
-  std::vector<char> desc;           // host image of the descriptor region
-  size_t desc_bytes = 0;
-  std::vector<Part> parts;
-  size_t total = 0;
-};
-
-// Capacities of a bucketed plan.  Tokens: up to 16 as they are; above,
-// rounded up to a multiple of 2^(floor(log2 T) - 2) but kept below the next
-// power of two, so a bucket spans at most a quarter of its values and the
-// capacity has the floor(log2) of the count, which is what the GEMM tile
-// choice depends on.  Images: the next power of two.
-int cap_tokens(int T) {
-  if (T <= 16) return T;
-  const int k = 31 - __builtin_clz((unsigned)T);
-  const int step = 1 << (k - 2);
-  return std::min((T + step - 1) / step * step, (2 << k) - 1);
+// The planner itself is host-only code (plan.hpp); these give it the
+// model's view.
+PlanModel plan_model(const vl_model* m) {
+  PlanModel pm;
+  pm.text = m->text;
+  pm.split = m->split && m->prec != VL_FP32;
+  pm.resident = m->attn_resident && m->prec != VL_FP32 && m->hd == 64 && !m->text;
+  pm.map_pool = !m->text && m->cfg.pool == VL_POOL_MAP;
+  pm.fold_buffers = m->prec == VL_BF16 || m->prec == VL_FP8W_BF16A;
+  pm.es = m->prec == VL_FP32 ? 4 : 2;
+  pm.D = m->D; pm.F = m->F; pm.Kpad = m->Kpad; pm.Pd = m->Pd;
+  pm.P = m->P; pm.channels = m->cfg.channels; pm.ctx = m->ctx;
+  return pm;
 }
-int cap_images(int n) {
-  int c = 1;
-  while (c < n) c <<= 1;
-  return std::min(c, kMaxItems);
+
+bool make_plan(const vl_model* m, int32_t n, const int32_t* hs, const int32_t* ws, Plan* p,
+               std::string* why, bool one_part = false, bool bucketed = false) {
+  return vl::make_plan(plan_model(m), n, hs, ws, p, why, one_part, bucketed);
+}
+
+bool make_text_plan(const vl_model* m, int32_t n, const int32_t* lens, Plan* p,
+                    std::string* why) {
+  return vl::make_text_plan(plan_model(m), n, lens, p, why);
 }
 
 // Whether the model's encode calls plan for capacity buckets: graph replay
@@ -261,180 +224,6 @@ int cap_images(int n) {
 bool bucket_mode(const vl_model* m) {
   return m->use_graphs && !m->text && (m->prec == VL_BF16 || m->prec == VL_FP8W_BF16A) &&
          m->cfg.pool == VL_POOL_CLS && !m->fused_ln;
-}
-
-// The common tail of planning: part boundaries, attention work items, the
-// descriptor blob and the workspace regions.  imgs[] hold absolute token
-// starts on entry.
-bool finish_plan(const vl_model* m, std::vector<ImgDesc>& imgs, int64_t T, Plan* p,
-                 bool one_part = false, bool bucketed = false) {
-  const int n = (int)imgs.size();
-  p->T = (int)T;
-  p->bucketed = bucketed;
-  // Part boundaries: one part, or two holding about half the tokens each.
-  std::vector<int> cut = {0};
-  if (!one_part && m->split && m->prec != VL_FP32 && n >= 2 && T >= kSplitMinTokens) {
-    int n1 = 1;
-    while (n1 < n - 1 && imgs[n1].tok_start < T / 2) ++n1;
-    cut.push_back(n1);
-  }
-  cut.push_back(n);
-  // Descriptor region: per part, its image descriptors then its attention
-  // items (16-byte aligned).
-  auto a16 = [](size_t x) { return (x + 15) / 16 * 16; };
-  p->parts.clear();
-  std::vector<std::vector<AttnItem>> items(cut.size() - 1);
-  std::vector<std::vector<int32_t>> res(cut.size() - 1);
-  const bool res_ok = m->attn_resident && m->prec != VL_FP32 && m->hd == 64 && !m->text;
-  size_t doff = 0;
-  for (size_t k = 0; k + 1 < cut.size(); ++k) {
-    Part q;
-    q.i0 = cut[k];
-    q.n = cut[k + 1] - cut[k];
-    const int t0 = imgs[q.i0].tok_start;
-    for (int i = q.i0; i < cut[k + 1]; ++i) {
-      imgs[i].tok_start -= t0;
-      q.T += imgs[i].ntok;
-      q.max_ntok = std::max<int>(q.max_ntok, imgs[i].ntok);
-      const int nt = imgs[i].ntok;
-      if (res_ok && nt > kResMinTokens && nt <= 64 * kResMaxTiles) {
-        res[k].push_back(i - q.i0);
-        q.res_tiles = std::max(q.res_tiles, (nt + 63) / 64);
-      } else {
-        for (int q0 = 0; q0 < nt; q0 += kAttnQ) items[k].push_back(AttnItem{i - q.i0, q0});
-      }
-    }
-    q.n_items = (int)items[k].size();
-    q.n_res = (int)res[k].size();
-    q.T_cap = q.T; q.n_cap = q.n; q.items_cap = q.n_items; q.res_cap = q.n_res;
-    q.ntok_cap = q.max_ntok; q.res_class = q.res_tiles;
-    if (bucketed) {
-      // Every batch of the bucket fits: a part's streamed items number at
-      // most sum ceil(ntok / 128) <= T / 128 + n, its resident images at
-      // most n, each of at most kResMaxTiles key tiles, its images at most
-      // kMaxTokens tokens.  Both attention kernels are launched (their live
-      // counts may be 0).
-      q.T_cap = cap_tokens(q.T);
-      q.n_cap = cap_images(q.n);
-      q.items_cap = (q.T_cap + kAttnQ - 1) / kAttnQ + q.n_cap;
-      q.res_cap = res_ok ? q.n_cap : 0;
-      q.ntok_cap = kMaxTokens;
-      q.res_class = kResMaxTiles;
-      q.bucketed = true;
-      q.off_bc = doff;
-      doff = a16(doff + sizeof(BatchCounts));
-    }
-    q.off_imgs = doff;
-    doff = a16(doff + sizeof(ImgDesc) * q.n_cap);
-    q.off_items = doff;
-    doff = a16(doff + sizeof(AttnItem) * q.items_cap);
-    q.off_res = doff;
-    doff = a16(doff + sizeof(int32_t) * q.res_cap);
-    p->parts.push_back(q);
-  }
-  p->desc_bytes = doff;
-  p->desc.assign(doff, 0);
-  for (size_t k = 0; k < p->parts.size(); ++k) {
-    const Part& q = p->parts[k];
-    std::memcpy(p->desc.data() + q.off_imgs, imgs.data() + q.i0, sizeof(ImgDesc) * q.n);
-    std::memcpy(p->desc.data() + q.off_items, items[k].data(), sizeof(AttnItem) * q.n_items);
-    std::memcpy(p->desc.data() + q.off_res, res[k].data(), sizeof(int32_t) * q.n_res);
-    if (bucketed) {
-      BatchCounts bc{q.T, q.n, q.n_items, q.n_res, nullptr, nullptr};   // pointers: bind_batch
-      std::memcpy(p->desc.data() + q.off_bc, &bc, sizeof bc);
-    }
-  }
-  // Workspace: the descriptor region, then each part's activation regions.
-  const size_t es = m->prec == VL_FP32 ? 4 : 2;
-  const size_t qh_cols = std::max<size_t>({(size_t)3 * m->D, (size_t)m->F, (size_t)m->Kpad});
-  size_t off = align_up(p->desc_bytes);
-  for (Part& q : p->parts) {
-    const size_t Tc = q.T_cap, nc = q.n_cap;
-    q.off_tok = off;
-    off += align_up(sizeof(int2) * Tc);
-    q.off_X = off;
-    off += align_up(4ull * Tc * m->D);
-    q.off_Y = off;
-    off += align_up(es * Tc * m->D);
-    q.off_QH = off;
-    off += align_up(es * Tc * qh_cols);
-    q.off_E = off;
-    off += align_up(4ull * nc * m->Pd);
-    if (!m->text && m->cfg.pool == VL_POOL_MAP) {
-      q.off_map = off;
-      off += align_up(4ull * nc * (3 * (size_t)m->D + m->F));
-    }
-    if (m->prec == VL_BF16 || m->prec == VL_FP8W_BF16A) {
-      q.off_U = off;
-      off += align_up(2ull * Tc * m->D);
-      q.off_PS = off;
-      off += align_up(4ull * Tc * (m->D / 32) * 2);
-      q.off_RS = off;
-      off += align_up(8ull * Tc);
-    }
-  }
-  p->total = off;
-  return true;
-}
-
-bool make_plan(const vl_model* m, int32_t n, const int32_t* hs, const int32_t* ws, Plan* p,
-               std::string* why, bool one_part = false, bool bucketed = false) {
-  if (m->text) { *why = "this model encodes texts (vl_encode_texts)"; return false; }
-  if (n <= 0) { *why = "n_images must be > 0"; return false; }
-  if (n > kMaxItems) { *why = "n_images must be <= 65535 (split larger batches)"; return false; }
-  if (!hs || !ws) { *why = "heights/widths are NULL"; return false; }
-  p->n = n;
-  p->hw.resize(2 * (size_t)n);
-  std::vector<ImgDesc> imgs(n);
-  int64_t pix = 0, T = 0;
-  for (int i = 0; i < n; ++i) {
-    const int H = hs[i], W = ws[i];
-    if (H < m->P || W < m->P) { *why = "image " + std::to_string(i) + " smaller than one patch"; return false; }
-    const int gh = H / m->P, gw = W / m->P;
-    const int64_t ntok = 1 + (int64_t)gh * gw;
-    if (ntok > kMaxTokens) { *why = "image " + std::to_string(i) + " has more than 1024 patches"; return false; }
-    ImgDesc& d = imgs[i];
-    d.pix_off = pix;
-    d.H = H; d.W = W; d.gh = gh; d.gw = gw;
-    d.tok_start = (int32_t)T;   // absolute for now
-    d.ntok = (int32_t)ntok;
-    pix += (int64_t)m->cfg.channels * H * W;
-    T += ntok;
-    p->hw[2 * i] = H;
-    p->hw[2 * i + 1] = W;
-  }
-  if (T > (1LL << 24)) { *why = "batch exceeds 2^24 tokens"; return false; }
-  return finish_plan(m, imgs, T, p, one_part, bucketed);
-}
-
-// Text batches: one descriptor per sequence (tokens tok_start .. +ntok-1 of
-// the packed id stream); graph keys use (length, 0) per sequence.
-bool make_text_plan(const vl_model* m, int32_t n, const int32_t* lens, Plan* p,
-                    std::string* why) {
-  if (!m->text) { *why = "this model encodes images (vl_encode_images)"; return false; }
-  if (n <= 0) { *why = "n_texts must be > 0"; return false; }
-  if (n > kMaxItems) { *why = "n_texts must be <= 65535 (split larger batches)"; return false; }
-  if (!lens) { *why = "lengths is NULL"; return false; }
-  p->n = n;
-  p->hw.assign(2 * (size_t)n, 0);
-  std::vector<ImgDesc> seqs(n);
-  int64_t T = 0;
-  for (int i = 0; i < n; ++i) {
-    if (lens[i] < 1 || lens[i] > m->ctx) {
-      *why = "text " + std::to_string(i) + " has length " + std::to_string(lens[i]) +
-             ", not in 1.." + std::to_string(m->ctx);
-      return false;
-    }
-    ImgDesc& d = seqs[i];
-    d.pix_off = T;   // offset of the sequence's ids in the packed id stream
-    d.H = d.W = d.gh = d.gw = 0;
-    d.tok_start = (int32_t)T;
-    d.ntok = lens[i];
-    T += lens[i];
-    p->hw[2 * i] = lens[i];
-  }
-  if (T > (1LL << 24)) { *why = "batch exceeds 2^24 tokens"; return false; }
-  return finish_plan(m, seqs, T, p);
 }
 
 // Async copy of `bytes` host bytes to dst through the next pinned buffer of
@@ -461,17 +250,6 @@ vl_status stage_copy(std::vector<Staging>& ring, size_t& pos, const void* src, s
   VL_HIP(hipEventRecord(st.ev, s));
   st.pending = true;
   return VL_OK;
-}
-
-// A bucketed plan's per-call pointers: the pixel buffer and each part's
-// first output row, in the parts' BatchCounts records.
-void bind_batch(Plan& p, const void* pix, float* emb, int Pd) {
-  if (!p.bucketed) return;
-  for (const Part& q : p.parts) {
-    BatchCounts* bc = reinterpret_cast<BatchCounts*>(p.desc.data() + q.off_bc);
-    bc->pix = static_cast<const float*>(pix);
-    bc->emb = emb + (size_t)q.i0 * Pd;
-  }
 }
 
 // Upload the plan's descriptors with an async copy from pinned memory.
