@@ -67,8 +67,8 @@ __device__ __forceinline__ float gelu_erf(float x) {
 // arithmetic: Phi(x) - 1/2 ~= t * P(t^2), t = x clamped to [-4.5, 4.5], P an
 // even-power polynomial of degree 8 in t^2 (coefficients from
 // fit_gelu_poly.py; |error| of Phi <= 2.5e-5 including the clamp, i.e. a
-// relative GELU error far below the BF16 rounding of the output).  The FP32
-// path keeps erff.
+// relative GELU error far below the BF16 rounding of the output), evaluated
+// as x * (1/2 + t P(t^2)).  The FP32 path keeps erff.
 __device__ __forceinline__ float gelu_poly(float x) {
   const float t = __builtin_amdgcn_fmed3f(x, -4.5f, 4.5f);
   const float u = t * t;
@@ -81,7 +81,7 @@ __device__ __forceinline__ float gelu_poly(float x) {
   p = fmaf(p, u, 9.729534388e-03f);
   p = fmaf(p, u, -6.624048948e-02f);
   p = fmaf(p, u, 3.988665044e-01f);
-  return fmaf(x, t * p, 0.5f * x);
+  return x * fmaf(t, p, 0.5f);
 }
 
 // ------------- MXFP8 blocks (OCP Microscaling Formats (MX) Specification v1.0)
