@@ -303,6 +303,7 @@ def rgbd_leg(torch, vl, steps: int, n_env: int = 256, w_seed: int = 1006, i_seed
     pix = torch.from_numpy(np.concatenate([im.reshape(-1) for im in imgs])).cuda()
     sizes = [(128, 128)] * n_env
     enc = vl.Encoder(c, w, "bf16", graphs=True, split=split)
+    vl.vl_model_set_option(enc.handle, vl.VL_OPT_GRAPH_BUCKETS, 0)   # one fixed batch
     del w
     out = torch.empty((n_env, c.proj_dim), dtype=torch.float32, device="cuda")
     for _ in range(2):
@@ -470,6 +471,9 @@ def main(argv=None) -> int:
     ap.add_argument("--precision", default=None,
                     help="fp32 | bf16 | fp8w | mxfp8 (default: workload's)")
     ap.add_argument("--no-graphs", action="store_true")
+    ap.add_argument("--bucket-graphs", action="store_true",
+                    help="replay the timed batch from its capacity bucket's graph (the serving "
+                         "mode) instead of a graph keyed on the exact batch")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in tile heuristic")
     ap.add_argument("--gemm-tiles", default="",
                     help="fixed tile configurations instead of autotuning, e.g. "
@@ -579,6 +583,8 @@ def main(argv=None) -> int:
                        fused_ln=args.fused_ln)
         if args.no_attn_resident:
             vl.vl_model_set_option(e.handle, vl.VL_OPT_ATTN_RESIDENT, 0)
+        if not args.bucket_graphs:   # a fixed batch: graphs keyed on it exactly
+            vl.vl_model_set_option(e.handle, vl.VL_OPT_GRAPH_BUCKETS, 0)
         t = None
         if prec != "fp32" and named:
             e.set_tuning(named)
@@ -662,7 +668,8 @@ def main(argv=None) -> int:
         "data": "synthetic (seeded U[0,1] pixels, N(0,0.02^2) weights, unit random texts)",
         "config": {"workload": args.workload, "model": wl.model, "batch": n,
                    "resolutions": sorted(set(h for h, _ in sizes)), "precision": prec,
-                   "head": wl.head, "n_texts": wl.n_texts, "graphs": not args.no_graphs,
+                   "head": wl.head, "n_texts": wl.n_texts, "graphs": (False if args.no_graphs else
+                                                "capacity bucket" if args.bucket_graphs else "exact"),
                    "two_part_split": split,
                    "fused_layernorm": prec in ("bf16", "fp8w") and args.fused_ln,
                    "gemm_tiles": tuned, "gemm_tiles_one_part": ttuned},

@@ -280,9 +280,15 @@ vl_status vl_encode_texts(vl_model* m, const int32_t* ids_dev, const int32_t* le
  *                   serves every query of the image from them; other images
  *                   stream key / value tiles per block of 128 queries.  Both
  *                   forms give the same bits.  Changing it drops cached
- *                   graphs.                                                 */
+ *                   graphs.
+ *   VL_OPT_GRAPH_BUCKETS : on by default.  0 = key every graph on the exact
+ *                   call, also for the models that would plan capacity
+ *                   buckets (a fixed-shape workload then launches grids of
+ *                   exactly its size).  Changing it drops cached graphs and
+ *                   changes what vl_encode_workspace_bytes returns.         */
 typedef enum vl_option { VL_OPT_GRAPHS = 0, VL_OPT_TIMING = 1, VL_OPT_SPLIT = 2,
-                         VL_OPT_FUSED_LN = 3, VL_OPT_ATTN_RESIDENT = 4 } vl_option;
+                         VL_OPT_FUSED_LN = 3, VL_OPT_ATTN_RESIDENT = 4,
+                         VL_OPT_GRAPH_BUCKETS = 5 } vl_option;
 vl_status vl_model_set_option(vl_model* m, vl_option opt, int64_t value);
 
 /* Operations of the encoder, as reported by vl_model_op_times:

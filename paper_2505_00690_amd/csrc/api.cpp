@@ -128,6 +128,9 @@ struct vl_model {
   // K/V-resident attention for images of 129 .. 640 tokens (BF16 attention,
   // head width 64, not causal; VL_OPT_ATTN_RESIDENT, on by default).
   bool attn_resident = true;
+  // Graph replay per capacity bucket where the model supports it
+  // (VL_OPT_GRAPH_BUCKETS, on by default).
+  bool graph_buckets = true;
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int32_t tuning[VL_N_GEMM_OPS][VL_N_M_BUCKETS];
@@ -222,8 +225,9 @@ bool make_text_plan(const vl_model* m, int32_t n, const int32_t* lens, Plan* p,
 // device (BF16 or e4m3-weight image models with class-token pooling and
 // standalone LayerNorms).
 bool bucket_mode(const vl_model* m) {
-  return m->use_graphs && !m->text && (m->prec == VL_BF16 || m->prec == VL_FP8W_BF16A) &&
-         m->cfg.pool == VL_POOL_CLS && !m->fused_ln;
+  return m->use_graphs && m->graph_buckets && !m->text &&
+         (m->prec == VL_BF16 || m->prec == VL_FP8W_BF16A) && m->cfg.pool == VL_POOL_CLS &&
+         !m->fused_ln;
 }
 
 // Async copy of `bytes` host bytes to dst through the next pinned buffer of
@@ -946,6 +950,10 @@ vl_status vl_model_set_option(vl_model* m, vl_option opt, int64_t value) {
     case VL_OPT_ATTN_RESIDENT:
       destroy_graphs(m);
       m->attn_resident = value != 0;
+      return VL_OK;
+    case VL_OPT_GRAPH_BUCKETS:
+      destroy_graphs(m);
+      m->graph_buckets = value != 0;
       return VL_OK;
   }
   return fail(VL_ERR_INVALID_ARG, "unknown option");

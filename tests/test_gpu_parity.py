@@ -158,10 +158,15 @@ def test_batch_invariance_bitwise(V):
             assert np.array_equal(alone[0], full[i]), (prec, i)
 
 
-def test_graph_replay_matches_eager(V):
+@pytest.mark.parametrize("buckets", [1, 0])
+def test_graph_replay_matches_eager(V, buckets):
+    """Replays of a captured graph, keyed on the capacity bucket (default) or
+    on the exact batch (VL_OPT_GRAPH_BUCKETS = 0), equal the eager call."""
     imgs = synth.make_images([(64, 64)] * 8, 2000)
     eager = run(encoder(V, "tiny", 1000, "bf16"), imgs)
-    genc = encoder(V, "tiny", 1000, "bf16", graphs=True)
+    w = torch.from_numpy(blob("tiny", 1000)).cuda()
+    genc = V.Encoder(synth.MODELS["tiny"], w, "bf16", graphs=True)
+    V.vl_model_set_option(genc.handle, V.VL_OPT_GRAPH_BUCKETS, buckets)
     pix = torch.from_numpy(pack(imgs)).cuda()
     out = torch.empty((8, 128), dtype=torch.float32, device="cuda")
     for _ in range(3):
@@ -169,6 +174,8 @@ def test_graph_replay_matches_eager(V):
         genc.encode(pix, sizes_of(imgs), out=out)
         torch.cuda.synchronize()
         assert np.array_equal(out.cpu().numpy(), eager)
+    assert V.vl_model_graph_stats(genc.handle)["captures"] == 1
+    genc.close()
 
 
 def _graph_counts(V, enc):
