@@ -1859,8 +1859,15 @@ vl_status run_train_forward(vl_model* m, const TrainPlan& tp, const float* pix, 
   void* QH = ws + p.off_QH;
   const int T = p.T, D = m->D, F = m->F;
   const float eps = m->cfg.ln_eps;
+  // The residual stream is written straight into the kept per-block
+  // buffers: block l reads its input from xin_l, the output projection
+  // writes h_l = xin_l + ..., FC2 writes xin_{l+1} = h_l + ... (X after the
+  // last block), so nothing is copied.
+  auto xin_of = [&](int l) {
+    return l < m->L ? reinterpret_cast<float*>(ws + tp.layers[l].xin) : X;
+  };
   EpiArgs pe;
-  pe.bias = m->patch_b; pe.out = X; pe.ldo = D; pe.tok_info = tok; pe.imgs = d_imgs;
+  pe.bias = m->patch_b; pe.out = xin_of(0); pe.ldo = D; pe.tok_info = tok; pe.imgs = d_imgs;
   pe.cls = m->cls; pe.pos = m->pos; pe.base_grid = m->g0;
   VL_HIP(im2col(pix, d_imgs, p.n, p.max_ntok, m->cfg.channels, m->P, m->Kpad, QH, !f32, tok, s));
   if (f32)
@@ -1877,12 +1884,13 @@ vl_status run_train_forward(vl_model* m, const TrainPlan& tp, const float* pix, 
     void* o = ws + sv.o;
     void* y2 = ws + sv.y2;
     float* z1 = reinterpret_cast<float*>(ws + sv.z1);
-    VL_HIP(copy_f32(X, reinterpret_cast<float*>(ws + sv.xin), (size_t)T * D, s));
-    VL_HIP(layernorm_rows(X, ly.ln1_g, ly.ln1_b, eps, y1, !f32, T, D, s));
+    float* xin = xin_of(l);
+    float* hb = reinterpret_cast<float*>(ws + sv.h);
+    VL_HIP(layernorm_rows(xin, ly.ln1_g, ly.ln1_b, eps, y1, !f32, T, D, s));
     EpiArgs e1; e1.bias = ly.qkv_b; e1.out = qkv; e1.ldo = 3 * D;
-    EpiArgs e2; e2.bias = ly.o_b; e2.out = X; e2.ldo = D;
+    EpiArgs e2; e2.bias = ly.o_b; e2.out = hb; e2.resid_in = xin; e2.ldo = D;
     EpiArgs e3; e3.bias = ly.fc1_b; e3.out = z1; e3.ldo = F;
-    EpiArgs e4; e4.bias = ly.fc2_b; e4.out = X; e4.ldo = D;
+    EpiArgs e4; e4.bias = ly.fc2_b; e4.out = xin_of(l + 1); e4.resid_in = hb; e4.ldo = D;
     if (f32) {
       VL_HIP(gemm_f32(static_cast<const float*>(y1), D, static_cast<const float*>(ly.qkv_w), D, T,
                       3 * D, D, OP_QKV, e1, s));
@@ -1901,8 +1909,7 @@ vl_status run_train_forward(vl_model* m, const TrainPlan& tp, const float* pix, 
       VL_HIP(gemm_bf16(static_cast<const bf16_t*>(o), D, ly.o_w, D, false, T, D, D, OP_OPROJ,
                        gemm_cfg_for(m, 2, T), e2, s));
     }
-    VL_HIP(copy_f32(X, reinterpret_cast<float*>(ws + sv.h), (size_t)T * D, s));
-    VL_HIP(layernorm_rows(X, ly.ln2_g, ly.ln2_b, eps, y2, !f32, T, D, s));
+    VL_HIP(layernorm_rows(hb, ly.ln2_g, ly.ln2_b, eps, y2, !f32, T, D, s));
     if (f32) {
       VL_HIP(gemm_f32(static_cast<const float*>(y2), D, static_cast<const float*>(ly.fc1_w), D, T,
                       F, D, OP_FC1_PRE, e3, s));

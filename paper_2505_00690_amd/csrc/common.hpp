@@ -69,7 +69,8 @@ __device__ __forceinline__ float gelu_erf(float x) {
 // fit_gelu_poly.py; |error| of Phi <= 2.5e-5 including the clamp, i.e. a
 // relative GELU error far below the BF16 rounding of the output), evaluated
 // as x * (1/2 + t P(t^2)).  The FP32 path keeps erff.
-__device__ __forceinline__ float gelu_poly(float x) {
+// Phi(x) = 1/2 + t P(t^2) as above (the GELU backward uses it too).
+__device__ __forceinline__ float phi_poly(float x) {
   const float t = __builtin_amdgcn_fmed3f(x, -4.5f, 4.5f);
   const float u = t * t;
   float p = 3.806312210e-11f;
@@ -81,8 +82,9 @@ __device__ __forceinline__ float gelu_poly(float x) {
   p = fmaf(p, u, 9.729534388e-03f);
   p = fmaf(p, u, -6.624048948e-02f);
   p = fmaf(p, u, 3.988665044e-01f);
-  return x * fmaf(t, p, 0.5f);
+  return fmaf(t, p, 0.5f);
 }
+__device__ __forceinline__ float gelu_poly(float x) { return x * phi_poly(x); }
 
 // ------------- MXFP8 blocks (OCP Microscaling Formats (MX) Specification v1.0)
 // 32 consecutive values along K share one E8M0 scale 2^X (byte X + 127) and

@@ -107,7 +107,8 @@ __device__ __forceinline__ void epi_store4(const EpiArgs& e, int m, int n, float
   }
   if (EPI == EPI_BIAS_RESID) {
     float4* X = reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n);
-    float4 x = *X;
+    float4 x = e.resid_in ? *reinterpret_cast<const float4*>(e.resid_in + (size_t)m * e.ldo + n)
+                          : *X;
     x.x += v[0]; x.y += v[1]; x.z += v[2]; x.w += v[3];
     *X = x;
     return;
@@ -579,8 +580,8 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
         for (int p = 0; p < NB; ++p) {
           const int m = mb + (p0 + p) * RPP;
           if (m < M && n_ok)
-            x[p] = *reinterpret_cast<const float4*>(static_cast<const float*>(e.out) +
-                                                    (size_t)m * e.ldo + n);
+            x[p] = *reinterpret_cast<const float4*>(
+                (e.resid_in ? e.resid_in : static_cast<const float*>(e.out)) + (size_t)m * e.ldo + n);
         }
       }
       // LayerNorm-folded consumer: the batch's row statistics, loaded

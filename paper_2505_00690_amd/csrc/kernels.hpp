@@ -60,6 +60,10 @@ struct EpiArgs {
   // Capacity launches (BF16 GEMMs): the grid covers M rows, the live row
   // count is *m_dev (<= M); tiles past it return at once.
   const int32_t* m_dev = nullptr;
+  // Residual epilogues (OP_OPROJ, OP_FC2; BF16 and FP32 GEMMs): with
+  // resid_in the residual is read from resid_in [M, ldo] and the sum written
+  // to out, instead of updating out in place.
+  const float* resid_in = nullptr;
 };
 
 // Tile configurations of the BF16 GEMM.  Every configuration accumulates K

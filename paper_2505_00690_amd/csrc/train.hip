@@ -261,30 +261,52 @@ hipError_t gelu_forward(const float* z, void* g, bool g_bf16, size_t n, hipStrea
 }
 
 // Backward: dz = dg (Phi(z) + z phi(z)), and the activation itself again
-// (g, as the forward formed it) for the weight gradient of FC2.
+// (g, as the forward formed it) for the weight gradient of FC2.  Two
+// elements per thread.  BF16 models take Phi from the forward's polynomial
+// (so g has the forward's bits) and phi = exp(-z^2/2) / sqrt(2 pi) from the
+// hardware base-2 exponential; FP32 models the erf form.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gelu_bwd(const float* __restrict__ dg,
                                                   const float* __restrict__ z, T* __restrict__ dz,
-                                                  T* __restrict__ g, size_t n) {
+                                                  T* __restrict__ g, size_t n2) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const float v = z[i];
-  const float phi = 0.3989422804014327f * expf(-0.5f * v * v);
-  const float cdf = 0.5f * (1.0f + erff(v * 0.70710678118654752f));
-  stf(dz, i, dg[i] * (cdf + v * phi));
+  if (i >= n2) return;
   constexpr bool BF = sizeof(T) == 2;
-  stf(g, i, BF ? gelu_poly(v) : gelu_erf(v));
+  const float2 v = reinterpret_cast<const float2*>(z)[i];
+  const float2 d = reinterpret_cast<const float2*>(dg)[i];
+  float c[2], ph[2];
+  const float vv[2] = {v.x, v.y};
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    if (BF) {
+      c[j] = phi_poly(vv[j]);
+      // exp(-z^2/2) = 2^(-z^2 log2(e) / 2)
+      ph[j] = 0.3989422804014327f * __builtin_amdgcn_exp2f(-0.72134752044448170f * vv[j] * vv[j]);
+    } else {
+      c[j] = 0.5f * (1.0f + erff(vv[j] * 0.70710678118654752f));
+      ph[j] = 0.3989422804014327f * expf(-0.5f * vv[j] * vv[j]);
+    }
+  }
+  const float dz0 = d.x * (c[0] + v.x * ph[0]), dz1 = d.y * (c[1] + v.y * ph[1]);
+  if (BF) {
+    reinterpret_cast<uint32_t*>(dz)[i] = pack_bf16x2(dz0, dz1);
+    reinterpret_cast<uint32_t*>(g)[i] = pack_bf16x2(v.x * c[0], v.y * c[1]);
+  } else {
+    reinterpret_cast<float2*>(dz)[i] = make_float2(dz0, dz1);
+    reinterpret_cast<float2*>(g)[i] = make_float2(gelu_erf(v.x), gelu_erf(v.y));
+  }
 }
 
 hipError_t gelu_backward(const float* dg, const float* z, void* dz, void* g, bool bf16, size_t n,
                          hipStream_t s) {
-  dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  const size_t n2 = n / 2;  // n is even (the MLP width is a multiple of 128)
+  dim3 grid((unsigned)((n2 + 255) / 256)), block(256);
   if (bf16)
     hipLaunchKernelGGL(k_gelu_bwd<bf16_t>, grid, block, 0, s, dg, z, static_cast<bf16_t*>(dz),
-                       static_cast<bf16_t*>(g), n);
+                       static_cast<bf16_t*>(g), n2);
   else
     hipLaunchKernelGGL(k_gelu_bwd<float>, grid, block, 0, s, dg, z, static_cast<float*>(dz),
-                       static_cast<float*>(g), n);
+                       static_cast<float*>(g), n2);
   return hipGetLastError();
 }
 
