@@ -54,9 +54,63 @@ __global__ __launch_bounds__(256) void k_transpose(const TI* __restrict__ in, in
   }
 }
 
+// BF16 output, 64 x 64 tiles: each thread moves 8 consecutive elements (16
+// bytes of BF16 out, 16 or 32 bytes in) per access; the tile waits in LDS as
+// BF16 rows padded by 8 elements.  Used when cols % 8 == 0, ld_in % 8 == 0,
+// ld_out % 8 == 0 and both pointers are 16-byte aligned.
+template <typename TI>
+__global__ __launch_bounds__(256) void k_transpose64(const TI* __restrict__ in, int rows, int cols,
+                                                     int ld_in, bf16_t* __restrict__ out,
+                                                     int ld_out) {
+  __shared__ __attribute__((aligned(16))) uint16_t t[64][72];
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+    const int r = (tid >> 3) + 32 * pass, cc = (tid & 7) * 8;
+    const int gr = r0 + r, gc = c0 + cc;
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (gr < rows && gc < cols) {   // cols % 8 == 0: the 8 columns are all in range
+      if constexpr (sizeof(TI) == 2) {
+        v = *reinterpret_cast<const u32x4*>(in + (size_t)gr * ld_in + gc);
+      } else {
+        const float4 a = *reinterpret_cast<const float4*>(in + (size_t)gr * ld_in + gc);
+        const float4 b = *reinterpret_cast<const float4*>(in + (size_t)gr * ld_in + gc + 4);
+        v[0] = pack_bf16x2(a.x, a.y); v[1] = pack_bf16x2(a.z, a.w);
+        v[2] = pack_bf16x2(b.x, b.y); v[3] = pack_bf16x2(b.z, b.w);
+      }
+    }
+    *reinterpret_cast<u32x4*>(&t[r][cc]) = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+    const int c = (tid >> 3) + 32 * pass, rr = (tid & 7) * 8;
+    const int gc = c0 + c, gr = r0 + rr;
+    if (gc >= cols || gr >= ld_out) continue;   // ld_out % 8 == 0: all 8 rows in range
+    u32x4 v;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      v[j] = (uint32_t)t[rr + 2 * j][c] | ((uint32_t)t[rr + 2 * j + 1][c] << 16);
+    *reinterpret_cast<u32x4*>(out + (size_t)gc * ld_out + gr) = v;
+  }
+}
+
 hipError_t transpose_rows(const void* in, bool in_bf16, int rows, int cols, int ld_in, void* out,
                           bool out_bf16, int ld_out, hipStream_t s) {
   if (cols <= 0 || ld_out <= 0) return hipSuccess;
+  const bool al16 = (reinterpret_cast<uintptr_t>(in) % 16 == 0) &&
+                    (reinterpret_cast<uintptr_t>(out) % 16 == 0);
+  if (out_bf16 && al16 && cols % 8 == 0 && ld_in % 8 == 0 && ld_out % 8 == 0) {
+    dim3 grid((cols + 63) / 64, (ld_out + 63) / 64), block(256);
+    if (in_bf16)
+      hipLaunchKernelGGL(k_transpose64<bf16_t>, grid, block, 0, s, static_cast<const bf16_t*>(in),
+                         rows, cols, ld_in, static_cast<bf16_t*>(out), ld_out);
+    else
+      hipLaunchKernelGGL(k_transpose64<float>, grid, block, 0, s, static_cast<const float*>(in),
+                         rows, cols, ld_in, static_cast<bf16_t*>(out), ld_out);
+    return hipGetLastError();
+  }
   dim3 grid((cols + 31) / 32, (ld_out + 31) / 32), block(256);
   if (in_bf16 && out_bf16)
     hipLaunchKernelGGL((k_transpose<bf16_t, bf16_t>), grid, block, 0, s,
