@@ -1716,7 +1716,7 @@ namespace {
 
 // Workspace of a training forward + backward: the one-part encode plan, then
 // per block the activations the backward reads, then the backward's scratch.
-struct TrainLayer { size_t xin, y1, qkv, o, h, y2, z1; };
+struct TrainLayer { size_t xin, y1, qkv, o, h, y2, z1, lse; };
 struct TrainPlan {
   Plan p;
   size_t off_items64 = 0;   // 64-token attention blocks, in the descriptor region
@@ -1785,6 +1785,7 @@ bool make_train_plan(const vl_model* m, int32_t n, const int32_t* hs, const int3
   for (TrainLayer& l : tp->layers) {
     l.xin = take(4 * T * D); l.y1 = take(es * T * D); l.qkv = take(es * 3 * T * D);
     l.o = take(es * T * D); l.h = take(4 * T * D); l.y2 = take(es * T * D); l.z1 = take(4 * T * F);
+    l.lse = take(4 * T * m->heads);   // the forward attention's log-sum-exp (BF16)
   }
   const size_t wide = std::max<size_t>({3 * D, F, (size_t)m->Kpad});
   tp->dX = take(4 * T * D);
@@ -1901,11 +1902,12 @@ vl_status run_train_forward(vl_model* m, const TrainPlan& tp, const float* pix, 
     } else {
       VL_HIP(gemm_bf16(static_cast<const bf16_t*>(y1), D, ly.qkv_w, D, false, T, 3 * D, D, OP_QKV,
                        gemm_cfg_for(m, 1, T), e1, s));
+      float* lse = reinterpret_cast<float*>(ws + sv.lse);
       VL_HIP(attention_bf16(static_cast<const bf16_t*>(qkv), static_cast<bf16_t*>(o), d_imgs,
-                            d_items, p.n_items, m->heads, m->hd, false, s));
+                            d_items, p.n_items, m->heads, m->hd, false, s, nullptr, lse));
       VL_HIP(attention_bf16_resident(static_cast<const bf16_t*>(qkv), o, nullptr, false, T,
                                      d_imgs, reinterpret_cast<const int*>(ws + p.off_res),
-                                     p.n_res, p.res_tiles, m->heads, m->hd, s));
+                                     p.n_res, p.res_tiles, m->heads, m->hd, s, nullptr, lse));
       VL_HIP(gemm_bf16(static_cast<const bf16_t*>(o), D, ly.o_w, D, false, T, D, D, OP_OPROJ,
                        gemm_cfg_for(m, 2, T), e2, s));
     }
@@ -2051,9 +2053,11 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
     if ((st = wgrad_gemm(m, tp, ws, gT, actT, D, D, G(go.o_w), s)) != VL_OK) return st;
     VL_HIP(colsum(dX, false, T, D, D, nullptr, part, G(go.o_b), s));
     // ---- attention
+    // (BF16: the log-sum-exp the forward kept; FP32: recomputed)
     VL_HIP(attention_backward(ws + sv.qkv, ws + sv.o, bf, dY, d_imgs, d_items64, tp.n_items64,
-                              m->heads, m->hd, dZ, reinterpret_cast<float*>(ws + tp.lse),
-                              reinterpret_cast<float*>(ws + tp.dsum), s));
+                              m->heads, m->hd, dZ,
+                              reinterpret_cast<float*>(ws + (bf ? sv.lse : tp.lse)),
+                              reinterpret_cast<float*>(ws + tp.dsum), s, bf));
     // ---- QKV: [q|k|v] = y1 Wqkv^T + bqkv
     VL_HIP(transpose_rows(ly.qkv_w, bf, 3 * D, D, D, Wt, bf, 3 * D, s));         // [D, 3D]
     if ((st = gemm_into_f32(m, dZ, 3 * D, Wt, 3 * D, T, D, 3 * D, dY, D, s)) != VL_OK) return st;

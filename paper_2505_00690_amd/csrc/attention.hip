@@ -75,7 +75,8 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
                                                    const ImgDesc* __restrict__ imgs,
                                                    const AttnItem* __restrict__ items,
                                                    int heads, int causal,
-                                                   const BatchCounts* __restrict__ bc) {
+                                                   const BatchCounts* __restrict__ bc,
+                                                   float* __restrict__ lse_out) {
   using T = KvTile<HD, false>;
   using TV = KvTile<HD, true>;
   constexpr int RPI = 1024 / T::ROWB;          // tile rows per 1 KB load instruction
@@ -288,6 +289,7 @@ __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qk
   if (!wave_active || q >= N) return;
   const float lt = l_run + __shfl_xor(l_run, 32, 64);
   const float inv = 1.f / lt;
+  if (lse_out && g == 0) lse_out[(size_t)(dsc.tok_start + q) * heads + h] = m_run + log2f(lt);
   if constexpr (MX) {
     const int row = dsc.tok_start + q;
     uint8_t* op = static_cast<uint8_t*>(out) + (size_t)row * D + h * HD;
@@ -342,7 +344,7 @@ template <int NT, bool MX>
 __global__ __launch_bounds__(RES_W * 64) void k_attn_bf16_res(
     const bf16_t* __restrict__ qkv, void* __restrict__ out, uint8_t* __restrict__ out_scale,
     int T_rows, const ImgDesc* __restrict__ imgs, const int* __restrict__ res_imgs, int heads,
-    const BatchCounts* __restrict__ bc) {
+    const BatchCounts* __restrict__ bc, float* __restrict__ lse_out) {
   constexpr int HD = 64;
   using T = KvTile<HD, false>;
   using TV = KvTile<HD, true>;
@@ -485,10 +487,11 @@ __global__ __launch_bounds__(RES_W * 64) void k_attn_bf16_res(
         o[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vf[jj][a], pf, o[a], 0, 0, 0);
     }
   };
-  auto store = [&](const f32x16* o, float l_run, int q) {
+  auto store = [&](const f32x16* o, float m_run, float l_run, int q) {
     const float lt = l_run + __shfl_xor(l_run, 32, 64);
     if (q >= N) return;
     const float inv = 1.f / lt;
+    if (lse_out && g == 0) lse_out[(size_t)(dsc.tok_start + q) * heads + h] = m_run + log2f(lt);
     if constexpr (MX) {
       const int row = dsc.tok_start + q;
       uint8_t* op = static_cast<uint8_t*>(out) + (size_t)row * D + h * HD;
@@ -554,7 +557,7 @@ __global__ __launch_bounds__(RES_W * 64) void k_attn_bf16_res(
       if (kt + 2 < KT) issue(kt + 2);
       if (active) tile(kt, qf, o, m_run, l_run, q);
     }
-    if (active) store(o, l_run, q);
+    if (active) store(o, m_run, l_run, q);
   }
   // Later passes: every tile resident; chunks RES_W .. of 32 queries.
   for (int c0 = 32 * RES_W; c0 < N; c0 += 32 * RES_W) {
@@ -570,7 +573,7 @@ __global__ __launch_bounds__(RES_W * 64) void k_attn_bf16_res(
 #pragma unroll
       for (int r = 0; r < 16; ++r) o[a][r] = 0.f;
     for (int kt = 0; kt < KT; ++kt) tile(kt, qf, o, m_run, l_run, q);
-    store(o, l_run, q);
+    store(o, m_run, l_run, q);
   }
 }
 
@@ -581,20 +584,20 @@ constexpr int RES_MIN_TOKENS = ATT_Q + 1, RES_MAX_TILES = 10;
 template <bool MX>
 static hipError_t launch_res(const bf16_t* qkv, void* out, uint8_t* out_scale, int T,
                              const ImgDesc* imgs, const int* res_imgs, int n_res, int max_tiles,
-                             int heads, hipStream_t s, const BatchCounts* bc) {
+                             int heads, hipStream_t s, const BatchCounts* bc, float* lse_out) {
   dim3 grid(n_res * heads), block(RES_W * 64);
   if (max_tiles <= 4)
     hipLaunchKernelGGL((k_attn_bf16_res<4, MX>), grid, block, 0, s, qkv, out, out_scale, T, imgs,
-                       res_imgs, heads, bc);
+                       res_imgs, heads, bc, lse_out);
   else if (max_tiles <= 6)
     hipLaunchKernelGGL((k_attn_bf16_res<6, MX>), grid, block, 0, s, qkv, out, out_scale, T, imgs,
-                       res_imgs, heads, bc);
+                       res_imgs, heads, bc, lse_out);
   else if (max_tiles <= 8)
     hipLaunchKernelGGL((k_attn_bf16_res<8, MX>), grid, block, 0, s, qkv, out, out_scale, T, imgs,
-                       res_imgs, heads, bc);
+                       res_imgs, heads, bc, lse_out);
   else if (max_tiles <= RES_MAX_TILES)
     hipLaunchKernelGGL((k_attn_bf16_res<RES_MAX_TILES, MX>), grid, block, 0, s, qkv, out,
-                       out_scale, T, imgs, res_imgs, heads, bc);
+                       out_scale, T, imgs, res_imgs, heads, bc, lse_out);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -603,13 +606,13 @@ static hipError_t launch_res(const bf16_t* qkv, void* out, uint8_t* out_scale, i
 hipError_t attention_bf16_resident(const bf16_t* qkv, void* out, uint8_t* out_scale, bool mx,
                                    int T, const ImgDesc* imgs, const int* res_imgs, int n_res,
                                    int max_tiles, int heads, int head_dim, hipStream_t s,
-                                   const BatchCounts* bc) {
+                                   const BatchCounts* bc, float* lse_out) {
   if (n_res <= 0) return hipSuccess;
   if (head_dim != 64) return hipErrorInvalidValue;
   return mx ? launch_res<true>(qkv, out, out_scale, T, imgs, res_imgs, n_res, max_tiles, heads, s,
-                               bc)
+                               bc, nullptr)
             : launch_res<false>(qkv, out, out_scale, T, imgs, res_imgs, n_res, max_tiles, heads,
-                                s, bc);
+                                s, bc, lse_out);
 }
 
 // ----------------------------------------------------------------- FP32
@@ -765,15 +768,15 @@ hipError_t map_attention(const void* kv, bool kv_bf16, const float* q, const Img
 
 hipError_t attention_bf16(const bf16_t* qkv, bf16_t* o, const ImgDesc* imgs,
                           const AttnItem* items, int n_items, int heads, int head_dim,
-                          bool causal, hipStream_t s, const BatchCounts* bc) {
+                          bool causal, hipStream_t s, const BatchCounts* bc, float* lse_out) {
   if (n_items <= 0) return hipSuccess;
   dim3 grid(n_items * heads), block(256);
   if (head_dim == 64)
     hipLaunchKernelGGL((k_attn_bf16<64, false>), grid, block, 0, s, qkv, o, nullptr, 0, imgs,
-                       items, heads, (int)causal, bc);
+                       items, heads, (int)causal, bc, lse_out);
   else if (head_dim == 32)
     hipLaunchKernelGGL((k_attn_bf16<32, false>), grid, block, 0, s, qkv, o, nullptr, 0, imgs,
-                       items, heads, (int)causal, bc);
+                       items, heads, (int)causal, bc, lse_out);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -786,10 +789,10 @@ hipError_t attention_bf16_mx(const bf16_t* qkv, uint8_t* codes, uint8_t* scales,
   dim3 grid(n_items * heads), block(256);
   if (head_dim == 64)
     hipLaunchKernelGGL((k_attn_bf16<64, true>), grid, block, 0, s, qkv, codes, scales, T, imgs,
-                       items, heads, (int)causal, nullptr);
+                       items, heads, (int)causal, nullptr, nullptr);
   else if (head_dim == 32)
     hipLaunchKernelGGL((k_attn_bf16<32, true>), grid, block, 0, s, qkv, codes, scales, T, imgs,
-                       items, heads, (int)causal, nullptr);
+                       items, heads, (int)causal, nullptr, nullptr);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -152,10 +152,13 @@ hipError_t im2col(const float* pix, const ImgDesc* imgs, int n_imgs, int max_nto
 
 // Multi-head self-attention over a packed QKV buffer [T, 3D] -> O [T, D],
 // within each descriptor's token range; causal: token i attends to 0..i.
-// With bc: items [0, bc->n_items) of a grid sized for n_items.
+// With bc: items [0, bc->n_items) of a grid sized for n_items.  With
+// lse_out [T, heads]: each query's log-sum-exp of its scaled scores in log2
+// units (max + log2 sum 2^(s - max)), which the training backward reuses.
 hipError_t attention_bf16(const bf16_t* qkv, bf16_t* o, const ImgDesc* imgs,
                           const AttnItem* items, int n_items, int heads, int head_dim,
-                          bool causal, hipStream_t s, const BatchCounts* bc = nullptr);
+                          bool causal, hipStream_t s, const BatchCounts* bc = nullptr,
+                          float* lse_out = nullptr);
 // The same with an MXFP8 output: codes [T, D] + scales [D/128][T][4].
 hipError_t attention_bf16_mx(const bf16_t* qkv, uint8_t* codes, uint8_t* scales, int T,
                              const ImgDesc* imgs, const AttnItem* items, int n_items,
@@ -168,7 +171,7 @@ hipError_t attention_bf16_mx(const bf16_t* qkv, uint8_t* codes, uint8_t* scales,
 hipError_t attention_bf16_resident(const bf16_t* qkv, void* out, uint8_t* out_scale, bool mx,
                                    int T, const ImgDesc* imgs, const int* res_imgs, int n_res,
                                    int max_tiles, int heads, int head_dim, hipStream_t s,
-                                   const BatchCounts* bc = nullptr);
+                                   const BatchCounts* bc = nullptr, float* lse_out = nullptr);
 hipError_t attention_f32(const float* qkv, float* o, const ImgDesc* imgs,
                          const AttnItem* items, int n_items, int heads, int head_dim,
                          bool causal, hipStream_t s);
@@ -240,11 +243,13 @@ hipError_t gelu_forward(const float* z, void* g, bool g_bf16, size_t n, hipStrea
 hipError_t gelu_backward(const float* dg, const float* z, void* dz, void* g, bool bf16, size_t n,
                          hipStream_t s);
 // dQKV [T, 3D] of the attention of every image: items64 are (image, first
-// token) blocks of 64 tokens; lse and dsum [T, heads] are scratch.
+// token) blocks of 64 tokens; lse and dsum [T, heads] are scratch, except
+// that with lse_given (BF16) lse already holds the forward's log-sum-exp
+// (attention_bf16's lse_out) and is only read.
 hipError_t attention_backward(const void* qkv, const void* o, bool bf16, const float* dO,
                               const ImgDesc* imgs, const AttnItem* items64, int n_items,
                               int heads, int head_dim, void* dqkv, float* lse, float* dsum,
-                              hipStream_t s);
+                              hipStream_t s, bool lse_given = false);
 // Pooling head: de, z [n, *] scratch, the class rows of dX, and the
 // gradients of the projection and the final LayerNorm (pg, pb [n, D] and
 // part [ceil(n / kColRows), D] scratch).

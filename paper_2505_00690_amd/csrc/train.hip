@@ -649,14 +649,16 @@ __device__ __forceinline__ void fill_tile(char* tile, const T* src, size_t ld, i
   }
 }
 
-template <int HD>
+// LSE_IN: lse2_io already holds each query's log-sum-exp (from the forward),
+// so pass 1 is skipped and nothing is written there.
+template <int HD, bool LSE_IN>
 __global__ __launch_bounds__(128) void k_attn_bwd_dq_mfma(const bf16_t* __restrict__ qkv,
                                                           const bf16_t* __restrict__ o,
                                                           const float* __restrict__ dO,
                                                           const ImgDesc* __restrict__ imgs,
                                                           const AttnItem* __restrict__ items,
                                                           int heads, bf16_t* __restrict__ dqkv,
-                                                          float* __restrict__ lse2_out,
+                                                          float* __restrict__ lse2_io,
                                                           float* __restrict__ dsum_out) {
   using TT = TrTile<HD>;
   constexpr int NC = HD / 16, NA = HD / 32;
@@ -693,6 +695,10 @@ __global__ __launch_bounds__(128) void k_attn_bwd_dq_mfma(const bf16_t* __restri
                                             8 * g);
   };
   // pass 1: log-sum-exp of each query's scaled scores (log2 units)
+  float lse2;
+  if constexpr (LSE_IN) {
+    lse2 = lse2_io[qrow * heads + h];
+  } else {
   float m = -INFINITY, l = 0.f;
   for (int k0 = 0; k0 < N; k0 += 64) {
     f32x16 s[2];
@@ -724,7 +730,8 @@ __global__ __launch_bounds__(128) void k_attn_bwd_dq_mfma(const bf16_t* __restri
     l = l * exp2f(m - mn) + ts;
     m = mn;
   }
-  const float lse2 = m + log2f(l + __shfl_xor(l, 32, 64));
+  lse2 = m + log2f(l + __shfl_xor(l, 32, 64));
+  }
   // pass 2: dS^T and dQ^T
   f32x16 dq[NA];
 #pragma unroll
@@ -782,7 +789,7 @@ __global__ __launch_bounds__(128) void k_attn_bwd_dq_mfma(const bf16_t* __restri
       *reinterpret_cast<u32x2*>(out + a * 32 + 8 * rq + 4 * g) = pk;
     }
   if (g == 0) {
-    lse2_out[row * heads + h] = lse2;
+    if (!LSE_IN) lse2_io[row * heads + h] = lse2;
     dsum_out[row * heads + h] = dsv;
   }
 }
@@ -892,11 +899,17 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void k
 template <int HD>
 static void launch_attn_bwd_mfma(const void* qkv, const void* o, const float* dO,
                                  const ImgDesc* imgs, const AttnItem* items, int n_items,
-                                 int heads, void* dqkv, float* lse, float* dsum, hipStream_t s) {
+                                 int heads, void* dqkv, float* lse, float* dsum, hipStream_t s,
+                                 bool lse_given) {
   dim3 grid(n_items, heads), block(128);
-  hipLaunchKernelGGL(k_attn_bwd_dq_mfma<HD>, grid, block, 0, s, static_cast<const bf16_t*>(qkv),
-                     static_cast<const bf16_t*>(o), dO, imgs, items, heads,
-                     static_cast<bf16_t*>(dqkv), lse, dsum);
+  if (lse_given)
+    hipLaunchKernelGGL((k_attn_bwd_dq_mfma<HD, true>), grid, block, 0, s,
+                       static_cast<const bf16_t*>(qkv), static_cast<const bf16_t*>(o), dO, imgs,
+                       items, heads, static_cast<bf16_t*>(dqkv), lse, dsum);
+  else
+    hipLaunchKernelGGL((k_attn_bwd_dq_mfma<HD, false>), grid, block, 0, s,
+                       static_cast<const bf16_t*>(qkv), static_cast<const bf16_t*>(o), dO, imgs,
+                       items, heads, static_cast<bf16_t*>(dqkv), lse, dsum);
   hipLaunchKernelGGL(k_attn_bwd_dkv_mfma<HD>, grid, block, 0, s, static_cast<const bf16_t*>(qkv),
                      dO, imgs, items, heads, lse, dsum, static_cast<bf16_t*>(dqkv));
 }
@@ -916,13 +929,18 @@ static void launch_attn_bwd(const void* qkv, const void* o, const float* dO, con
 hipError_t attention_backward(const void* qkv, const void* o, bool bf16, const float* dO,
                               const ImgDesc* imgs, const AttnItem* items64, int n_items,
                               int heads, int head_dim, void* dqkv, float* lse, float* dsum,
-                              hipStream_t s) {
+                              hipStream_t s, bool lse_given) {
   if (n_items <= 0) return hipSuccess;
+  if (lse_given && !bf16) return hipErrorInvalidValue;
   if (head_dim == 64) {
-    if (bf16) launch_attn_bwd_mfma<64>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s);
+    if (bf16)
+      launch_attn_bwd_mfma<64>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s,
+                               lse_given);
     else launch_attn_bwd<float, 64>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s);
   } else if (head_dim == 32) {
-    if (bf16) launch_attn_bwd_mfma<32>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s);
+    if (bf16)
+      launch_attn_bwd_mfma<32>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s,
+                               lse_given);
     else launch_attn_bwd<float, 32>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s);
   } else {
     return hipErrorInvalidValue;
