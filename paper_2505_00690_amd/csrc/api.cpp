@@ -1919,9 +1919,9 @@ vl_status run_train_forward(vl_model* m, const TrainPlan& tp, const float* pix, 
       VL_HIP(gemm_f32(static_cast<const float*>(QH), F, static_cast<const float*>(ly.fc2_w), F, T,
                       D, F, OP_FC2, e4, s));
     } else {
+      e3.out2 = QH;   // GELU(z1) in BF16 from the same epilogue
       VL_HIP(gemm_bf16(static_cast<const bf16_t*>(y2), D, ly.fc1_w, D, false, T, F, D, OP_FC1_PRE,
                        gemm_cfg_for(m, 3, T), e3, s));
-      VL_HIP(gelu_forward(z1, QH, true, (size_t)T * F, s));
       VL_HIP(gemm_bf16(static_cast<const bf16_t*>(QH), F, ly.fc2_w, F, false, T, D, F, OP_FC2,
                        gemm_cfg_for(m, 4, T), e4, s));
     }
@@ -2029,9 +2029,16 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
     // ---- FC2: x_out = h + GELU(z1) W2^T + b2
     if ((st = prep_dx()) != VL_OK) return st;
     VL_HIP(transpose_rows(ly.fc2_w, bf, D, F, F, Wt, bf, D, s));                 // W2^T [F, D]
-    if ((st = gemm_into_f32(m, dXb, D, Wt, D, T, F, D, dGf, F, s)) != VL_OK) return st;
-    VL_HIP(gelu_backward(dGf, reinterpret_cast<const float*>(ws + sv.z1), dZ, QH, bf,
-                         (size_t)T * F, s));                                     // dz1, g
+    if (bf) {   // dz1 = (dX W2) GELU'(z1) and g = GELU(z1) from the GEMM's epilogue
+      EpiArgs eg;
+      eg.out = dZ; eg.out2 = QH; eg.aux = reinterpret_cast<const float*>(ws + sv.z1); eg.ldo = F;
+      VL_HIP(gemm_bf16(static_cast<const bf16_t*>(dXb), D, Wt, D, false, T, F, D, OP_DGELU, -1,
+                       eg, s));
+    } else {
+      if ((st = gemm_into_f32(m, dXb, D, Wt, D, T, F, D, dGf, F, s)) != VL_OK) return st;
+      VL_HIP(gelu_backward(dGf, reinterpret_cast<const float*>(ws + sv.z1), dZ, QH, bf,
+                           (size_t)T * F, s));                                   // dz1, g
+    }
     VL_HIP(transpose_rows(QH, bf, T, F, F, actT, bf, Tp, s));                    // g^T
     if ((st = wgrad_gemm(m, tp, ws, gT, actT, D, F, G(go.fc2_w), s)) != VL_OK) return st;
     VL_HIP(colsum(dX, false, T, D, D, nullptr, part, G(go.fc2_b), s));

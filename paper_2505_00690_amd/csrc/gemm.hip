@@ -84,9 +84,10 @@ hipError_t gemm_bf16(const bf16_t* A, int lda, const void* B, int ldb, bool b_fp
   if (b_fp8 && op == OP_PATCH) return hipErrorInvalidValue;
   if (cfg < 0 || cfg >= N_BF16_CFGS) cfg = gemm_cfg_heuristic(M, N, K, b_fp8);
   // The register-staged kernel has no producer side of the LayerNorm
-  // folding and reads no device row count; its direct-to-LDS counterpart
-  // gives the same bits.
-  if (cfg == CFG_REG_128x128_W2x2 && (e.u_out || e.m_dev)) cfg = CFG_DL_128x128_W2x2;
+  // folding, reads no device row count and has no GELU-backward form; its
+  // direct-to-LDS counterpart gives the same bits.
+  if (cfg == CFG_REG_128x128_W2x2 && (e.u_out || e.m_dev || op == OP_DGELU))
+    cfg = CFG_DL_128x128_W2x2;
   switch (cfg) {
     case 0: return gemm_launch_cfg0(A, lda, B, ldb, b_fp8, M, N, K, op, e, s);
     case 1: return gemm_launch_cfg1(A, lda, B, ldb, b_fp8, M, N, K, op, e, s);

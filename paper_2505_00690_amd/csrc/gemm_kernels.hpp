@@ -20,7 +20,8 @@
 namespace vl {
 
 // ---------------------------------------------------------------- epilogue
-enum EpiKind { EPI_BIAS, EPI_BIAS_GELU, EPI_BIAS_RESID, EPI_PATCH, EPI_SCALE_BIAS, EPI_BIAS_F32 };
+enum EpiKind { EPI_BIAS, EPI_BIAS_GELU, EPI_BIAS_RESID, EPI_PATCH, EPI_SCALE_BIAS, EPI_BIAS_F32,
+               EPI_DGELU };
 template <int OP>
 struct OpEpi {
   static constexpr int kind = OP == OP_PATCH ? EPI_PATCH
@@ -28,6 +29,7 @@ struct OpEpi {
                               : OP == OP_FC1 ? EPI_BIAS_GELU
                               : OP == OP_LOGITS ? EPI_SCALE_BIAS
                               : OP == OP_FC1_PRE ? EPI_BIAS_F32
+                              : OP == OP_DGELU ? EPI_DGELU
                                                 : EPI_BIAS_RESID;
 };
 
@@ -38,10 +40,48 @@ __device__ __forceinline__ float ln_fold1(float v, float ws, float c1, float c2,
   return __builtin_fmaf(rstd, __builtin_fmaf(v, ws, -(mu * c1)), c2);
 }
 
+// GELU backward of four columns (OP_DGELU): dz = dg (Phi(z) + z phi(z)) and
+// g = GELU(z), Phi from the forward's polynomial (so g has the forward's
+// bits), phi = exp(-z^2 / 2) / sqrt(2 pi); both stored as BF16.
+__device__ __forceinline__ void dgelu_store4(const EpiArgs& e, int m, int n, float4 dg,
+                                             float4 z) {
+  const float zz[4] = {z.x, z.y, z.z, z.w}, dd[4] = {dg.x, dg.y, dg.z, dg.w};
+  float dz[4], gg[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float c = phi_poly(zz[j]);
+    const float ph =
+        0.3989422804014327f * __builtin_amdgcn_exp2f(-0.72134752044448170f * zz[j] * zz[j]);
+    dz[j] = dd[j] * (c + zz[j] * ph);
+    gg[j] = zz[j] * c;
+  }
+  const size_t o = (size_t)m * e.ldo + n;
+  u32x2 pk;
+  pk.x = pack_bf16x2(dz[0], dz[1]);
+  pk.y = pack_bf16x2(dz[2], dz[3]);
+  *reinterpret_cast<u32x2*>(static_cast<bf16_t*>(e.out) + o) = pk;
+  pk.x = pack_bf16x2(gg[0], gg[1]);
+  pk.y = pack_bf16x2(gg[2], gg[3]);
+  *reinterpret_cast<u32x2*>(static_cast<bf16_t*>(e.out2) + o) = pk;
+}
+
+// BF16 GELU of an FP32 pre-activation into out2 (OP_FC1_PRE with out2).
+__device__ __forceinline__ void gelu_out2_store4(const EpiArgs& e, int m, int n, float4 y) {
+  u32x2 pk;
+  pk.x = pack_bf16x2(gelu_poly(y.x), gelu_poly(y.y));
+  pk.y = pack_bf16x2(gelu_poly(y.z), gelu_poly(y.w));
+  *reinterpret_cast<u32x2*>(static_cast<bf16_t*>(e.out2) + (size_t)m * e.ldo + n) = pk;
+}
+
 template <int EPI, bool OUT_BF16>
 __device__ __forceinline__ void epi_store4(const EpiArgs& e, int m, int n, float v0, float v1,
                                            float v2, float v3) {
   float v[4] = {v0, v1, v2, v3};
+  if (EPI == EPI_DGELU) {
+    dgelu_store4(e, m, n, make_float4(v[0], v[1], v[2], v[3]),
+                 *reinterpret_cast<const float4*>(e.aux + (size_t)m * e.ldo + n));
+    return;
+  }
   if (EPI == EPI_SCALE_BIAS) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) v[j] = e.alpha * v[j] + e.beta;
@@ -114,8 +154,9 @@ __device__ __forceinline__ void epi_store4(const EpiArgs& e, int m, int n, float
     return;
   }
   if (EPI == EPI_BIAS_F32) {
-    *reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n) =
-        make_float4(v[0], v[1], v[2], v[3]);
+    const float4 y = make_float4(v[0], v[1], v[2], v[3]);
+    *reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n) = y;
+    if (e.out2) gelu_out2_store4(e, m, n, y);
     return;
   }
   if (EPI == EPI_BIAS_GELU) {
@@ -545,7 +586,7 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
   const bool fold_in = (EPI == EPI_BIAS || EPI == EPI_BIAS_GELU) && e.row_stats != nullptr;
   const bool fold_out = EPI == EPI_BIAS_RESID && e.u_out != nullptr;
   float4 c14 = make_float4(0.f, 0.f, 0.f, 0.f), g4 = c14;
-  if (EPI != EPI_PATCH && EPI != EPI_SCALE_BIAS && n_ok) {
+  if (EPI != EPI_PATCH && EPI != EPI_SCALE_BIAS && EPI != EPI_DGELU && n_ok) {
     if (fold_in) {
       c14 = *reinterpret_cast<const float4*>(e.c1 + n);
       bias4 = *reinterpret_cast<const float4*>(e.c2 + n);
@@ -575,13 +616,15 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
         const int row = (p0 + p) * RPP + rr;
         v[p] = *reinterpret_cast<const float4*>(stage + row * WN + ((rc ^ sw(row)) << 2));
       }
-      if (EPI == EPI_BIAS_RESID) {
+      if (EPI == EPI_BIAS_RESID || EPI == EPI_DGELU) {   // the residual, or z
 #pragma unroll
         for (int p = 0; p < NB; ++p) {
           const int m = mb + (p0 + p) * RPP;
           if (m < M && n_ok)
             x[p] = *reinterpret_cast<const float4*>(
-                (e.resid_in ? e.resid_in : static_cast<const float*>(e.out)) + (size_t)m * e.ldo + n);
+                (EPI == EPI_DGELU ? e.aux
+                                  : e.resid_in ? e.resid_in : static_cast<const float*>(e.out)) +
+                (size_t)m * e.ldo + n);
         }
       }
       // LayerNorm-folded consumer: the batch's row statistics, loaded
@@ -608,6 +651,10 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
           *reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n) =
               make_float4(e.alpha * v[p].x + e.beta, e.alpha * v[p].y + e.beta,
                           e.alpha * v[p].z + e.beta, e.alpha * v[p].w + e.beta);
+          continue;
+        }
+        if (EPI == EPI_DGELU) {
+          dgelu_store4(e, m, n, v[p], x[p]);
           continue;
         }
         float4 y;
@@ -652,6 +699,7 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
         }
         if (EPI == EPI_BIAS_F32) {
           *reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n) = y;
+          if (e.out2) gelu_out2_store4(e, m, n, y);
           continue;
         }
         if (EPI == EPI_BIAS_GELU) {
@@ -688,6 +736,7 @@ static hipError_t launch_bf16_dl(const bf16_t* A, int lda, const void* B, int ld
     VL_GEMM_CASE(OP_FC2)
     VL_GEMM_CASE(OP_LOGITS)
     VL_GEMM_CASE(OP_FC1_PRE)
+    VL_GEMM_CASE(OP_DGELU)
     default: return hipErrorInvalidValue;
   }
 #undef VL_GEMM_CASE

@@ -19,9 +19,13 @@ namespace vl {
 //   OP_FC2    : resid[m,n] += acc * ws[n] + bias[n]      (FP32)
 //   OP_LOGITS : out = alpha * acc + beta                 (FP32)
 //   OP_FC1_PRE: out = acc * ws[n] + bias[n]              (FP32 out; the FC1
-//               pre-activation the training forward keeps for the backward)
+//               pre-activation the training forward keeps for the backward;
+//               with out2 also GELU of it in BF16 [M, ldo], as OP_FC1 forms it)
+//   OP_DGELU  : the FC2 input gradient through the GELU (BF16 GEMMs): with
+//               z = aux[m,n] (the kept FC1 pre-activation, FP32),
+//               out = acc * GELU'(z) and out2 = GELU(z), both BF16 [M, ldo]
 enum GemmOp { OP_PATCH = 0, OP_QKV = 1, OP_OPROJ = 2, OP_FC1 = 3, OP_FC2 = 4, OP_LOGITS = 5,
-              OP_FC1_PRE = 6 };
+              OP_FC1_PRE = 6, OP_DGELU = 7 };
 
 struct EpiArgs {
   const float* bias = nullptr;    // [N]
@@ -60,6 +64,9 @@ struct EpiArgs {
   // Capacity launches (BF16 GEMMs): the grid covers M rows, the live row
   // count is *m_dev (<= M); tiles past it return at once.
   const int32_t* m_dev = nullptr;
+  // Second output and auxiliary input (OP_FC1_PRE, OP_DGELU).
+  void* out2 = nullptr;
+  const float* aux = nullptr;
   // Residual epilogues (OP_OPROJ, OP_FC2; BF16 and FP32 GEMMs): with
   // resid_in the residual is read from resid_in [M, ldo] and the sum written
   // to out, instead of updating out in place.
