@@ -2060,11 +2060,14 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
     if ((st = wgrad_gemm(m, tp, ws, gT, actT, D, D, G(go.o_w), s)) != VL_OK) return st;
     VL_HIP(colsum(dX, false, T, D, D, nullptr, part, G(go.o_b), s));
     // ---- attention
-    // (BF16: the log-sum-exp the forward kept; FP32: recomputed)
+    // (BF16: the log-sum-exp the forward kept, and dO also in BF16, in the
+    // dX operand buffer, free until the next block's; FP32: recomputed)
+    if (bf) VL_HIP(convert_bf16(dY, static_cast<bf16_t*>(dXb), (size_t)T * D, s));
     VL_HIP(attention_backward(ws + sv.qkv, ws + sv.o, bf, dY, d_imgs, d_items64, tp.n_items64,
                               m->heads, m->hd, dZ,
                               reinterpret_cast<float*>(ws + (bf ? sv.lse : tp.lse)),
-                              reinterpret_cast<float*>(ws + tp.dsum), s, bf));
+                              reinterpret_cast<float*>(ws + tp.dsum), s, bf,
+                              bf ? static_cast<const bf16_t*>(dXb) : nullptr));
     // ---- QKV: [q|k|v] = y1 Wqkv^T + bqkv
     VL_HIP(transpose_rows(ly.qkv_w, bf, 3 * D, D, D, Wt, bf, 3 * D, s));         // [D, 3D]
     if ((st = gemm_into_f32(m, dZ, 3 * D, Wt, 3 * D, T, D, 3 * D, dY, D, s)) != VL_OK) return st;

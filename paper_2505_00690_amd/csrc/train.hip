@@ -794,9 +794,12 @@ __global__ __launch_bounds__(128) void k_attn_bwd_dq_mfma(const bf16_t* __restri
   }
 }
 
+// dO in BF16 (dO_b [T, DM]); the query and dO tiles of the next 64 queries
+// stream into the second of two LDS stages by direct-to-LDS loads while the
+// current ones are used, and their log-sum-exp / D values wait in registers.
 template <int HD>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void k_attn_bwd_dkv_mfma(const bf16_t* __restrict__ qkv,
-                                                           const float* __restrict__ dO,
+                                                           const bf16_t* __restrict__ dO_b,
                                                            const ImgDesc* __restrict__ imgs,
                                                            const AttnItem* __restrict__ items,
                                                            int heads,
@@ -805,16 +808,20 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                            bf16_t* __restrict__ dqkv) {
   using TT = TrTile<HD>;
   constexpr int NC = HD / 16, NA = HD / 32;
-  __shared__ __attribute__((aligned(16))) char sQ[TT::BYTES];
-  __shared__ __attribute__((aligned(16))) char sdO[TT::BYTES];
-  __shared__ float sL[64], sD[64];
+  constexpr int RPI = 1024 / TT::ROWB;   // tile rows per 1 KB direct-to-LDS load
+  constexpr int NI = 64 / RPI;           // such loads per tile (two waves share them)
+  static_assert(NI % 2 == 0, "tile / waves");
+  __shared__ __attribute__((aligned(1024))) char sQ[2][TT::BYTES];
+  __shared__ __attribute__((aligned(1024))) char sdO[2][TT::BYTES];
+  __shared__ float sL[2][64], sD[2][64];
   const AttnItem it = items[blockIdx.x];   // it.q0: first key of the block
   const int h = blockIdx.y;
   const ImgDesc dsc = imgs[it.img];
   const int N = dsc.ntok, DM = heads * HD, ld3 = 3 * DM;
   const bf16_t* base = qkv + (size_t)dsc.tok_start * ld3 + h * HD;
-  const float* dbase = dO + (size_t)dsc.tok_start * DM + h * HD;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l32 = lane & 31, g = lane >> 5;
+  const bf16_t* dbase = dO_b + (size_t)dsc.tok_start * DM + h * HD;
+  const int lane = threadIdx.x & 63, l32 = lane & 31, g = lane >> 5;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: LDS bases
   const int k = it.q0 + 32 * wave + l32;
   const bool kok = k < N;
   const int kc = min(k, N - 1);
@@ -830,18 +837,51 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void k
   for (int a = 0; a < NA; ++a)
 #pragma unroll
     for (int r = 0; r < 16; ++r) dv[a][r] = dk[a][r] = 0.f;
-  const uint32_t ldsQ = lds_offset(sQ), ldsO = lds_offset(sdO);
-  for (int q0 = 0; q0 < N; q0 += 64) {
-    const int nq = min(64, N - q0);
-    __syncthreads();
-    fill_tile<HD>(sQ, base + (size_t)q0 * ld3, ld3, nq);
-    fill_tile<HD>(sdO, dbase + (size_t)q0 * DM, DM, nq);
-    if (threadIdx.x < 64) {
-      const size_t row = (size_t)dsc.tok_start + q0 + threadIdx.x;
-      sL[threadIdx.x] = (int)threadIdx.x < nq ? lse2[row * heads + h] : 0.f;
-      sD[threadIdx.x] = (int)threadIdx.x < nq ? dsum[row * heads + h] : 0.f;
+  // Rows past the image read as zero (buffer bounds).  Load i of wave w
+  // fills rows RPI (NI/2 w + i) .. +RPI-1; lane l takes row l / NCH of them
+  // and physical chunk l % NCH, i.e. logical chunk (l % NCH) ^ f(row).
+  const i32x4 rq = buffer_rsrc(base, (uint64_t)N * ld3 * 2);
+  const i32x4 rd = buffer_rsrc(dbase, (uint64_t)N * DM * 2);
+  const uint32_t ldsQ0 = lds_offset(&sQ[0][0]), ldsO0 = lds_offset(&sdO[0][0]);
+  auto issue = [&](int st, int q0) {
+#pragma unroll
+    for (int i = 0; i < NI / 2; ++i) {
+      const int grp = (NI / 2) * wave + i;
+      const int row = grp * RPI + lane / TT::NCH;
+      const int chunk = (lane % TT::NCH) ^ TT::f(row);
+      const uint32_t lo = st * TT::BYTES + grp * 1024;
+      dma16(rq, ldsQ0 + lo, (q0 + row) * ld3 * 2 + chunk * 16, 0);
+      dma16(rd, ldsO0 + lo, (q0 + row) * DM * 2 + chunk * 16, 0);
     }
-    __syncthreads();
+  };
+  float l_next = 0.f, d_next = 0.f;
+  auto load_ld = [&](int q0) {
+    if (threadIdx.x < 64) {
+      const int qi = q0 + (int)threadIdx.x;
+      const size_t row = (size_t)dsc.tok_start + min(qi, N - 1);
+      l_next = qi < N ? lse2[row * heads + h] : 0.f;
+      d_next = qi < N ? dsum[row * heads + h] : 0.f;
+    }
+  };
+  issue(0, 0);
+  load_ld(0);
+  for (int q0 = 0, cur = 0; q0 < N; q0 += 64, cur ^= 1) {
+    const int nq = min(64, N - q0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's loads of tile q0
+    if (threadIdx.x < 64) {
+      sL[cur][threadIdx.x] = l_next;
+      sD[cur][threadIdx.x] = d_next;
+    }
+    __syncthreads();   // tile q0 complete; every wave is done with the other stage
+    if (q0 + 64 < N) {
+      issue(cur ^ 1, q0 + 64);
+      load_ld(q0 + 64);
+    }
+    const char* tQ = sQ[cur];
+    const char* tO = sdO[cur];
+    const uint32_t ldsQ = ldsQ0 + cur * TT::BYTES, ldsO = ldsO0 + cur * TT::BYTES;
+    const float* cL = sL[cur];
+    const float* cD = sD[cur];
     // The 64 queries as two halves of 32 (fewer live registers): for half qb,
     // s[r] = S[query q0 + qi][key k], qi = 32qb + 8(r/4) + 4g + r%4, then its
     // two 16-query chunks jj = 2qb, 2qb + 1 of dV^T += dO^T P, dK^T += Q^T dS.
@@ -852,17 +892,17 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void k
       const int row = 32 * qb + l32;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const bf16x8 qa = *reinterpret_cast<const bf16x8*>(sQ + TT::off(row, 2 * c + g));
+        const bf16x8 qa = *reinterpret_cast<const bf16x8*>(tQ + TT::off(row, 2 * c + g));
         s = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa, kf[c], s, 0, 0, 0);
-        const bf16x8 da = *reinterpret_cast<const bf16x8*>(sdO + TT::off(row, 2 * c + g));
+        const bf16x8 da = *reinterpret_cast<const bf16x8*>(tO + TT::off(row, 2 * c + g));
         dp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(da, vf[c], dp, 0, 0, 0);
       }
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int qi = 32 * qb + 8 * (r >> 2) + 4 * g + (r & 3);
-        const float p = (qi < nq && kok) ? exp2f(fmaf(s[r], sl2, -sL[qi])) : 0.f;
+        const float p = (qi < nq && kok) ? exp2f(fmaf(s[r], sl2, -cL[qi])) : 0.f;
         s[r] = p;
-        dp[r] = p * (dp[r] - sD[qi]);
+        dp[r] = p * (dp[r] - cD[qi]);
       }
 #pragma unroll
       for (int hh = 0; hh < 2; ++hh) {
@@ -900,7 +940,7 @@ template <int HD>
 static void launch_attn_bwd_mfma(const void* qkv, const void* o, const float* dO,
                                  const ImgDesc* imgs, const AttnItem* items, int n_items,
                                  int heads, void* dqkv, float* lse, float* dsum, hipStream_t s,
-                                 bool lse_given) {
+                                 bool lse_given, const bf16_t* dO_bf16) {
   dim3 grid(n_items, heads), block(128);
   if (lse_given)
     hipLaunchKernelGGL((k_attn_bwd_dq_mfma<HD, true>), grid, block, 0, s,
@@ -911,7 +951,7 @@ static void launch_attn_bwd_mfma(const void* qkv, const void* o, const float* dO
                        static_cast<const bf16_t*>(qkv), static_cast<const bf16_t*>(o), dO, imgs,
                        items, heads, static_cast<bf16_t*>(dqkv), lse, dsum);
   hipLaunchKernelGGL(k_attn_bwd_dkv_mfma<HD>, grid, block, 0, s, static_cast<const bf16_t*>(qkv),
-                     dO, imgs, items, heads, lse, dsum, static_cast<bf16_t*>(dqkv));
+                     dO_bf16, imgs, items, heads, lse, dsum, static_cast<bf16_t*>(dqkv));
 }
 
 template <typename T, int HD>
@@ -929,18 +969,19 @@ static void launch_attn_bwd(const void* qkv, const void* o, const float* dO, con
 hipError_t attention_backward(const void* qkv, const void* o, bool bf16, const float* dO,
                               const ImgDesc* imgs, const AttnItem* items64, int n_items,
                               int heads, int head_dim, void* dqkv, float* lse, float* dsum,
-                              hipStream_t s, bool lse_given) {
+                              hipStream_t s, bool lse_given, const bf16_t* dO_bf16) {
   if (n_items <= 0) return hipSuccess;
-  if (lse_given && !bf16) return hipErrorInvalidValue;
+  if ((lse_given || dO_bf16) && !bf16) return hipErrorInvalidValue;
+  if (bf16 && !dO_bf16) return hipErrorInvalidValue;
   if (head_dim == 64) {
     if (bf16)
       launch_attn_bwd_mfma<64>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s,
-                               lse_given);
+                               lse_given, dO_bf16);
     else launch_attn_bwd<float, 64>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s);
   } else if (head_dim == 32) {
     if (bf16)
       launch_attn_bwd_mfma<32>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s,
-                               lse_given);
+                               lse_given, dO_bf16);
     else launch_attn_bwd<float, 32>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s);
   } else {
     return hipErrorInvalidValue;
