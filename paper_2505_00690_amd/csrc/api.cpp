@@ -2015,10 +2015,19 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
                        reinterpret_cast<float*>(ws + tp.zp), dX,
                        reinterpret_cast<float*>(ws + tp.ppg), reinterpret_cast<float*>(ws + tp.ppb),
                        part, G(bo.proj), G(bo.lnf_g), G(bo.lnf_b), s));
-  // dX in the GEMM operand type (BF16 copy, or dX itself) and transposed.
+  // dX in the GEMM operand type (BF16 copy, or dX itself) and transposed
+  // (BF16: with the column-sum partials of dX for the bias gradient).
   auto prep_dx = [&]() -> vl_status {
     if (bf) VL_HIP(convert_bf16(dX, static_cast<bf16_t*>(dXb), (size_t)T * D, s));
-    VL_HIP(transpose_rows(dX, false, T, D, D, gT, bf, Tp, s));
+    VL_HIP(transpose_rows(dX, false, T, D, D, gT, bf, Tp, s, bf ? part : nullptr));
+    return VL_OK;
+  };
+  // Bias gradient = column sums of the layer's output gradient: from the
+  // partials its transpose left (BF16), or a pass of its own.
+  const int nbc = (T + kColRows - 1) / kColRows;
+  auto bias_grad = [&](const void* g, bool g_bf16, int C, float* out) -> vl_status {
+    if (bf) VL_HIP(colsum_final(part, nbc, C, out, s));
+    else VL_HIP(colsum(g, g_bf16, T, C, C, nullptr, part, out, s));
     return VL_OK;
   };
   for (int l = m->L - 1; l >= 0; --l) {
@@ -2041,14 +2050,14 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
     }
     VL_HIP(transpose_rows(QH, bf, T, F, F, actT, bf, Tp, s));                    // g^T
     if ((st = wgrad_gemm(m, tp, ws, gT, actT, D, F, G(go.fc2_w), s)) != VL_OK) return st;
-    VL_HIP(colsum(dX, false, T, D, D, nullptr, part, G(go.fc2_b), s));
+    if ((st = bias_grad(dX, false, D, G(go.fc2_b))) != VL_OK) return st;
     // ---- FC1: z1 = y2 W1^T + b1
     VL_HIP(transpose_rows(ly.fc1_w, bf, F, D, D, Wt, bf, F, s));                 // W1^T [D, F]
     if ((st = gemm_into_f32(m, dZ, F, Wt, F, T, D, F, dY, D, s)) != VL_OK) return st;
-    VL_HIP(transpose_rows(dZ, bf, T, F, F, gT, bf, Tp, s));
+    VL_HIP(transpose_rows(dZ, bf, T, F, F, gT, bf, Tp, s, bf ? part : nullptr));
     VL_HIP(transpose_rows(ws + sv.y2, bf, T, D, D, actT, bf, Tp, s));
     if ((st = wgrad_gemm(m, tp, ws, gT, actT, F, D, G(go.fc1_w), s)) != VL_OK) return st;
-    VL_HIP(colsum(dZ, bf, T, F, F, nullptr, part, G(go.fc1_b), s));
+    if ((st = bias_grad(dZ, bf, F, G(go.fc1_b))) != VL_OK) return st;
     // ---- LN2 (dX += LN2'(h) dY)
     VL_HIP(layernorm_backward(reinterpret_cast<const float*>(ws + sv.h), ly.ln2_g, dY, eps, dX, T,
                               D, pg, pb, G(go.ln2_g), G(go.ln2_b), s));
@@ -2058,7 +2067,7 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
     if ((st = gemm_into_f32(m, dXb, D, Wt, D, T, D, D, dY, D, s)) != VL_OK) return st;   // dO
     VL_HIP(transpose_rows(ws + sv.o, bf, T, D, D, actT, bf, Tp, s));
     if ((st = wgrad_gemm(m, tp, ws, gT, actT, D, D, G(go.o_w), s)) != VL_OK) return st;
-    VL_HIP(colsum(dX, false, T, D, D, nullptr, part, G(go.o_b), s));
+    if ((st = bias_grad(dX, false, D, G(go.o_b))) != VL_OK) return st;
     // ---- attention
     // (BF16: the log-sum-exp the forward kept, and dO also in BF16, in the
     // dX operand buffer, free until the next block's; FP32: recomputed)
@@ -2071,10 +2080,10 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
     // ---- QKV: [q|k|v] = y1 Wqkv^T + bqkv
     VL_HIP(transpose_rows(ly.qkv_w, bf, 3 * D, D, D, Wt, bf, 3 * D, s));         // [D, 3D]
     if ((st = gemm_into_f32(m, dZ, 3 * D, Wt, 3 * D, T, D, 3 * D, dY, D, s)) != VL_OK) return st;
-    VL_HIP(transpose_rows(dZ, bf, T, 3 * D, 3 * D, gT, bf, Tp, s));
+    VL_HIP(transpose_rows(dZ, bf, T, 3 * D, 3 * D, gT, bf, Tp, s, bf ? part : nullptr));
     VL_HIP(transpose_rows(ws + sv.y1, bf, T, D, D, actT, bf, Tp, s));
     if ((st = wgrad_gemm(m, tp, ws, gT, actT, 3 * D, D, G(go.qkv_w), s)) != VL_OK) return st;
-    VL_HIP(colsum(dZ, bf, T, 3 * D, 3 * D, nullptr, part, G(go.qkv_b), s));
+    if ((st = bias_grad(dZ, bf, 3 * D, G(go.qkv_b))) != VL_OK) return st;
     // ---- LN1 (dX += LN1'(x) dY)
     VL_HIP(layernorm_backward(reinterpret_cast<const float*>(ws + sv.xin), ly.ln1_g, dY, eps, dX,
                               T, D, pg, pb, G(go.ln1_g), G(go.ln1_b), s));

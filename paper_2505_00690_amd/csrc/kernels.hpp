@@ -232,8 +232,13 @@ struct ChanNorm { float mean[4], std[4]; };  // per-plane pixel normalisation
 
 // out[c][r] = in[r][c] (rows < rows), zero for rows <= r < ld_out; element
 // types BF16 or FP32 (BF16 -> FP32 is not offered).
+// With colsum_part (BF16 output, cols % 8 == 0): also the row-block partials
+// of colsum for the same input, [ceil(rows / kColRows), cols]; finish with
+// colsum_final.
 hipError_t transpose_rows(const void* in, bool in_bf16, int rows, int cols, int ld_in, void* out,
-                          bool out_bf16, int ld_out, hipStream_t s);
+                          bool out_bf16, int ld_out, hipStream_t s,
+                          float* colsum_part = nullptr);
+hipError_t colsum_final(const float* part, int nb, int C, float* out, hipStream_t s);
 // out[c] = sum over rows of in[r][c] (class-token rows skipped when tok is
 // given), via part [ceil(R / kColRows), C] in a fixed order.  C % 4 == 0,
 // ld % 4 == 0.

@@ -58,11 +58,17 @@ __global__ __launch_bounds__(256) void k_transpose(const TI* __restrict__ in, in
 // bytes of BF16 out, 16 or 32 bytes in) per access; the tile waits in LDS as
 // BF16 rows padded by 8 elements.  Used when cols % 8 == 0, ld_in % 8 == 0,
 // ld_out % 8 == 0 and both pointers are 16-byte aligned.
+// With part (the row-block partials of colsum, kColRows = 64 rows per
+// block): part[blockIdx.y][c] = the sum of the input column c over the
+// tile's rows in ascending order, from the values as given (FP32 input before
+// its BF16 rounding), as k_colsum_part forms it.
 template <typename TI>
 __global__ __launch_bounds__(256) void k_transpose64(const TI* __restrict__ in, int rows, int cols,
                                                      int ld_in, bf16_t* __restrict__ out,
-                                                     int ld_out) {
+                                                     int ld_out, float* __restrict__ part) {
+  static_assert(kColRows == 64, "one partial per 64-row tile");
   __shared__ __attribute__((aligned(16))) uint16_t t[64][72];
+  __shared__ float tf[sizeof(TI) == 4 ? 64 : 1][65];   // FP32 input as given, for the sums
   const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
   const int tid = threadIdx.x;
 #pragma unroll
@@ -78,11 +84,24 @@ __global__ __launch_bounds__(256) void k_transpose64(const TI* __restrict__ in, 
         const float4 b = *reinterpret_cast<const float4*>(in + (size_t)gr * ld_in + gc + 4);
         v[0] = pack_bf16x2(a.x, a.y); v[1] = pack_bf16x2(a.z, a.w);
         v[2] = pack_bf16x2(b.x, b.y); v[3] = pack_bf16x2(b.z, b.w);
+        if (part) {
+          const float f[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+          for (int j = 0; j < 8; ++j) tf[r][cc + j] = f[j];
+        }
       }
     }
     *reinterpret_cast<u32x4*>(&t[r][cc]) = v;
   }
   __syncthreads();
+  if (part && tid < 64 && c0 + tid < cols) {   // rows past the matrix are not added
+    const int nr = min(64, rows - r0);
+    float acc = 0.f;
+    for (int r = 0; r < nr; ++r)
+      acc += sizeof(TI) == 4 ? tf[sizeof(TI) == 4 ? r : 0][tid]
+                             : bf16_bits_to_f32(t[r][tid]);
+    part[(size_t)blockIdx.y * cols + c0 + tid] = acc;
+  }
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
     const int c = (tid >> 3) + 32 * pass, rr = (tid & 7) * 8;
@@ -97,20 +116,23 @@ __global__ __launch_bounds__(256) void k_transpose64(const TI* __restrict__ in, 
 }
 
 hipError_t transpose_rows(const void* in, bool in_bf16, int rows, int cols, int ld_in, void* out,
-                          bool out_bf16, int ld_out, hipStream_t s) {
+                          bool out_bf16, int ld_out, hipStream_t s, float* colsum_part) {
   if (cols <= 0 || ld_out <= 0) return hipSuccess;
   const bool al16 = (reinterpret_cast<uintptr_t>(in) % 16 == 0) &&
                     (reinterpret_cast<uintptr_t>(out) % 16 == 0);
   if (out_bf16 && al16 && cols % 8 == 0 && ld_in % 8 == 0 && ld_out % 8 == 0) {
+    // the partials need every row block of the input to be a row of blocks
+    if (colsum_part && (ld_out + 63) / 64 < (rows + 63) / 64) return hipErrorInvalidValue;
     dim3 grid((cols + 63) / 64, (ld_out + 63) / 64), block(256);
     if (in_bf16)
       hipLaunchKernelGGL(k_transpose64<bf16_t>, grid, block, 0, s, static_cast<const bf16_t*>(in),
-                         rows, cols, ld_in, static_cast<bf16_t*>(out), ld_out);
+                         rows, cols, ld_in, static_cast<bf16_t*>(out), ld_out, colsum_part);
     else
       hipLaunchKernelGGL(k_transpose64<float>, grid, block, 0, s, static_cast<const float*>(in),
-                         rows, cols, ld_in, static_cast<bf16_t*>(out), ld_out);
+                         rows, cols, ld_in, static_cast<bf16_t*>(out), ld_out, colsum_part);
     return hipGetLastError();
   }
+  if (colsum_part) return hipErrorInvalidValue;
   dim3 grid((cols + 31) / 32, (ld_out + 31) / 32), block(256);
   if (in_bf16 && out_bf16)
     hipLaunchKernelGGL((k_transpose<bf16_t, bf16_t>), grid, block, 0, s,
