@@ -179,28 +179,29 @@ __global__ __launch_bounds__(256) void k_colsum_part(const T* __restrict__ in, i
   *reinterpret_cast<float4*>(part + (size_t)blockIdx.y * C + c) = s;
 }
 
-// Final pass: 16 columns per workgroup, 16 phases per column; phase k sums
-// the partials b = k, k + 16, ... in ascending order, then the 16 phase sums
-// are added in phase order.
+// Final pass: 4 columns per workgroup, 64 phases per column (many small
+// workgroups: the partials are few, so the pass is latency-bound); phase k
+// sums the partials b = k, k + 64, ... in ascending order, then the 64 phase
+// sums are added in phase order.
 __global__ __launch_bounds__(256) void k_colsum_final(const float* __restrict__ part, int nb,
                                                       int C, float* __restrict__ out) {
-  __shared__ float red[16][17];
-  const int cl = threadIdx.x & 15, ph = threadIdx.x >> 4;
-  const int c = blockIdx.x * 16 + cl;
+  __shared__ float red[64][5];
+  const int cl = threadIdx.x & 3, ph = threadIdx.x >> 2;
+  const int c = blockIdx.x * 4 + cl;
   float s = 0.f;
   if (c < C)
-    for (int b = ph; b < nb; b += 16) s += part[(size_t)b * C + c];
+    for (int b = ph; b < nb; b += 64) s += part[(size_t)b * C + c];
   red[ph][cl] = s;
   __syncthreads();
   if (ph == 0 && c < C) {
     float t = 0.f;
-    for (int k = 0; k < 16; ++k) t += red[k][cl];
+    for (int k = 0; k < 64; ++k) t += red[k][cl];
     out[c] = t;
   }
 }
 
 hipError_t colsum_final(const float* part, int nb, int C, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_colsum_final, dim3((C + 15) / 16), dim3(256), 0, s, part, nb, C, out);
+  hipLaunchKernelGGL(k_colsum_final, dim3((C + 3) / 4), dim3(256), 0, s, part, nb, C, out);
   return hipGetLastError();
 }
 
