@@ -2018,11 +2018,12 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
                        reinterpret_cast<float*>(ws + tp.zp), dX,
                        reinterpret_cast<float*>(ws + tp.ppg), reinterpret_cast<float*>(ws + tp.ppb),
                        part, G(bo.proj), G(bo.lnf_g), G(bo.lnf_b), s));
-  // dX in the GEMM operand type (BF16 copy, or dX itself) and transposed
-  // (BF16: with the column-sum partials of dX for the bias gradient).
+  // dX in the GEMM operand type (BF16 copy, or dX itself) and transposed; in
+  // BF16 models one pass forms the transpose, the copy and the column-sum
+  // partials of dX for the bias gradient.
   auto prep_dx = [&]() -> vl_status {
-    if (bf) VL_HIP(convert_bf16(dX, static_cast<bf16_t*>(dXb), (size_t)T * D, s));
-    VL_HIP(transpose_rows(dX, false, T, D, D, gT, bf, Tp, s, bf ? part : nullptr));
+    VL_HIP(transpose_rows(dX, false, T, D, D, gT, bf, Tp, s, bf ? part : nullptr,
+                          bf ? static_cast<bf16_t*>(dXb) : nullptr));
     return VL_OK;
   };
   // Bias gradient = column sums of the layer's output gradient: from the

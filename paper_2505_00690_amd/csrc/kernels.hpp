@@ -234,10 +234,11 @@ struct ChanNorm { float mean[4], std[4]; };  // per-plane pixel normalisation
 // types BF16 or FP32 (BF16 -> FP32 is not offered).
 // With colsum_part (BF16 output, cols % 8 == 0): also the row-block partials
 // of colsum for the same input, [ceil(rows / kColRows), cols]; finish with
-// colsum_final.
+// colsum_final.  With copy_bf16 (FP32 input, BF16 output): also the input
+// rounded to BF16 in its own layout [rows, ld_in].
 hipError_t transpose_rows(const void* in, bool in_bf16, int rows, int cols, int ld_in, void* out,
                           bool out_bf16, int ld_out, hipStream_t s,
-                          float* colsum_part = nullptr);
+                          float* colsum_part = nullptr, bf16_t* copy_bf16 = nullptr);
 hipError_t colsum_final(const float* part, int nb, int C, float* out, hipStream_t s);
 // out[c] = sum over rows of in[r][c] (class-token rows skipped when tok is
 // given), via part [ceil(R / kColRows), C] in a fixed order.  C % 4 == 0,

@@ -62,10 +62,13 @@ __global__ __launch_bounds__(256) void k_transpose(const TI* __restrict__ in, in
 // block): part[blockIdx.y][c] = the sum of the input column c over the
 // tile's rows in ascending order, from the values as given (FP32 input before
 // its BF16 rounding), as k_colsum_part forms it.
+// With copy (FP32 input): also the input rounded to BF16 in its own layout
+// ([rows, ld_in]), from the same loads.
 template <typename TI>
 __global__ __launch_bounds__(256) void k_transpose64(const TI* __restrict__ in, int rows, int cols,
                                                      int ld_in, bf16_t* __restrict__ out,
-                                                     int ld_out, float* __restrict__ part) {
+                                                     int ld_out, float* __restrict__ part,
+                                                     bf16_t* __restrict__ copy) {
   static_assert(kColRows == 64, "one partial per 64-row tile");
   __shared__ __attribute__((aligned(16))) uint16_t t[64][72];
   __shared__ float tf[sizeof(TI) == 4 ? 64 : 1][65];   // FP32 input as given, for the sums
@@ -84,6 +87,7 @@ __global__ __launch_bounds__(256) void k_transpose64(const TI* __restrict__ in, 
         const float4 b = *reinterpret_cast<const float4*>(in + (size_t)gr * ld_in + gc + 4);
         v[0] = pack_bf16x2(a.x, a.y); v[1] = pack_bf16x2(a.z, a.w);
         v[2] = pack_bf16x2(b.x, b.y); v[3] = pack_bf16x2(b.z, b.w);
+        if (copy) *reinterpret_cast<u32x4*>(copy + (size_t)gr * ld_in + gc) = v;
         if (part) {
           const float f[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
@@ -116,23 +120,29 @@ __global__ __launch_bounds__(256) void k_transpose64(const TI* __restrict__ in, 
 }
 
 hipError_t transpose_rows(const void* in, bool in_bf16, int rows, int cols, int ld_in, void* out,
-                          bool out_bf16, int ld_out, hipStream_t s, float* colsum_part) {
+                          bool out_bf16, int ld_out, hipStream_t s, float* colsum_part,
+                          bf16_t* copy_bf16) {
   if (cols <= 0 || ld_out <= 0) return hipSuccess;
   const bool al16 = (reinterpret_cast<uintptr_t>(in) % 16 == 0) &&
                     (reinterpret_cast<uintptr_t>(out) % 16 == 0);
   if (out_bf16 && al16 && cols % 8 == 0 && ld_in % 8 == 0 && ld_out % 8 == 0) {
     // the partials need every row block of the input to be a row of blocks
     if (colsum_part && (ld_out + 63) / 64 < (rows + 63) / 64) return hipErrorInvalidValue;
+    if (copy_bf16 && (in_bf16 || (ld_out + 63) / 64 < (rows + 63) / 64 ||
+                      reinterpret_cast<uintptr_t>(copy_bf16) % 16))
+      return hipErrorInvalidValue;
     dim3 grid((cols + 63) / 64, (ld_out + 63) / 64), block(256);
     if (in_bf16)
       hipLaunchKernelGGL(k_transpose64<bf16_t>, grid, block, 0, s, static_cast<const bf16_t*>(in),
-                         rows, cols, ld_in, static_cast<bf16_t*>(out), ld_out, colsum_part);
+                         rows, cols, ld_in, static_cast<bf16_t*>(out), ld_out, colsum_part,
+                         nullptr);
     else
       hipLaunchKernelGGL(k_transpose64<float>, grid, block, 0, s, static_cast<const float*>(in),
-                         rows, cols, ld_in, static_cast<bf16_t*>(out), ld_out, colsum_part);
+                         rows, cols, ld_in, static_cast<bf16_t*>(out), ld_out, colsum_part,
+                         copy_bf16);
     return hipGetLastError();
   }
-  if (colsum_part) return hipErrorInvalidValue;
+  if (colsum_part || copy_bf16) return hipErrorInvalidValue;
   dim3 grid((cols + 31) / 32, (ld_out + 31) / 32), block(256);
   if (in_bf16 && out_bf16)
     hipLaunchKernelGGL((k_transpose<bf16_t, bf16_t>), grid, block, 0, s,
