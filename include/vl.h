@@ -285,10 +285,16 @@ vl_status vl_encode_texts(vl_model* m, const int32_t* ids_dev, const int32_t* le
  *                   call, also for the models that would plan capacity
  *                   buckets (a fixed-shape workload then launches grids of
  *                   exactly its size).  Changing it drops cached graphs and
- *                   changes what vl_encode_workspace_bytes returns.         */
+ *                   changes what vl_encode_workspace_bytes returns.
+ *   VL_OPT_KMAJOR_WGRAD : on by default (VL_BF16 training with width and MLP
+ *                   width multiples of 256).  The weight gradients of the
+ *                   encoder blocks read the token-major output gradients
+ *                   and activations directly; 0 = transpose both into
+ *                   scratch first.  Same operands and splits: results
+ *                   differ only in FP32 summation order.                   */
 typedef enum vl_option { VL_OPT_GRAPHS = 0, VL_OPT_TIMING = 1, VL_OPT_SPLIT = 2,
                          VL_OPT_FUSED_LN = 3, VL_OPT_ATTN_RESIDENT = 4,
-                         VL_OPT_GRAPH_BUCKETS = 5 } vl_option;
+                         VL_OPT_GRAPH_BUCKETS = 5, VL_OPT_KMAJOR_WGRAD = 6 } vl_option;
 vl_status vl_model_set_option(vl_model* m, vl_option opt, int64_t value);
 
 /* Operations of the encoder, as reported by vl_model_op_times:

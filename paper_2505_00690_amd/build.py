@@ -19,7 +19,8 @@ ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libvl.so")
 OBJDIR = os.path.join(PKG, "_build")
 
-SOURCES = ["api.cpp", "plan.cpp", "gemm.hip", "attention.hip", "elementwise.hip", "contrastive.hip", "train.hip"] + [
+SOURCES = ["api.cpp", "plan.cpp", "gemm.hip", "attention.hip", "elementwise.hip", "contrastive.hip", "train.hip",
+           "gemm_kmajor.hip"] + [
     f"gemm_cfg{i}.hip" for i in range(9)] + [f"gemm_mx_cfg{i}.hip" for i in range(9, 13)]
 
 ARCH = "gfx950"

@@ -131,6 +131,7 @@ struct vl_model {
   // Graph replay per capacity bucket where the model supports it
   // (VL_OPT_GRAPH_BUCKETS, on by default).
   bool graph_buckets = true;
+  bool kmajor_wgrad = true;   // BF16 weight gradients from token-major operands
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int32_t tuning[VL_N_GEMM_OPS][VL_N_M_BUCKETS];
@@ -954,6 +955,9 @@ vl_status vl_model_set_option(vl_model* m, vl_option opt, int64_t value) {
     case VL_OPT_GRAPH_BUCKETS:
       destroy_graphs(m);
       m->graph_buckets = value != 0;
+      return VL_OK;
+    case VL_OPT_KMAJOR_WGRAD:
+      m->kmajor_wgrad = value != 0;
       return VL_OK;
   }
   return fail(VL_ERR_INVALID_ARG, "unknown option");
@@ -1981,6 +1985,27 @@ vl_status wgrad_gemm(const vl_model* m, const TrainPlan& tp, char* ws, const voi
   return VL_OK;
 }
 
+// The same weight gradient from token-major BF16 operands: out [M, N] =
+// A^T B with A [T, lda] (columns 0..M-1) and B [T, ldb] (columns 0..N-1),
+// the token rows T..Tp-1 read as zero; same splits, same partial sums.
+vl_status wgrad_gemm_km(const TrainPlan& tp, char* ws, const void* A, int lda, const void* B,
+                        int ldb, int M, int N, float* out, hipStream_t s) {
+  const int Tp = tp.Tp, T = tp.p.T;
+  auto sp = wgrad_splits(M, N, Tp);
+  EpiArgs e;
+  e.alpha = 1.f; e.beta = 0.f;
+  e.ldo = N;
+  const bool split = sp.first > 1 && (size_t)sp.first * M * N * 4 <= tp.wsplit_bytes;
+  float* part = reinterpret_cast<float*>(ws + tp.wsplit);
+  e.out = split ? part : out;
+  e.kc = split ? sp.second : Tp;
+  e.zstride = (size_t)M * N;
+  VL_HIP(gemm_bf16_kmajor(static_cast<const bf16_t*>(A), lda, static_cast<const bf16_t*>(B), ldb,
+                          M, N, Tp, T, e, s));
+  if (split) VL_HIP(sum_splits(part, sp.first, (size_t)M * N, out, s));
+  return VL_OK;
+}
+
 // The backward pass, block by block in reverse.  dX is the gradient of the
 // residual stream; every linear layer's input gradient is a GEMM against the
 // transposed weight and its weight gradient a GEMM over the tokens (K = T,
@@ -2018,11 +2043,17 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
                        reinterpret_cast<float*>(ws + tp.zp), dX,
                        reinterpret_cast<float*>(ws + tp.ppg), reinterpret_cast<float*>(ws + tp.ppb),
                        part, G(bo.proj), G(bo.lnf_g), G(bo.lnf_b), s));
+  // BF16 models whose widths are multiples of 256 form the weight gradients
+  // from the token-major operands (no transposed copies); the passes over
+  // the output gradients still run for their column-sum partials (and dX's
+  // BF16 copy) but write no transposed matrix.
+  const bool km = bf && m->kmajor_wgrad && D % 256 == 0 && F % 256 == 0;
+  void* gTo = km ? nullptr : gT;
   // dX in the GEMM operand type (BF16 copy, or dX itself) and transposed; in
   // BF16 models one pass forms the transpose, the copy and the column-sum
   // partials of dX for the bias gradient.
   auto prep_dx = [&]() -> vl_status {
-    VL_HIP(transpose_rows(dX, false, T, D, D, gT, bf, Tp, s, bf ? part : nullptr,
+    VL_HIP(transpose_rows(dX, false, T, D, D, gTo, bf, Tp, s, bf ? part : nullptr,
                           bf ? static_cast<bf16_t*>(dXb) : nullptr));
     return VL_OK;
   };
@@ -2052,15 +2083,25 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
       VL_HIP(gelu_backward(dGf, reinterpret_cast<const float*>(ws + sv.z1), dZ, QH, bf,
                            (size_t)T * F, s));                                   // dz1, g
     }
-    VL_HIP(transpose_rows(QH, bf, T, F, F, actT, bf, Tp, s));                    // g^T
-    if ((st = wgrad_gemm(m, tp, ws, gT, actT, D, F, G(go.fc2_w), s)) != VL_OK) return st;
+    if (km) {
+      st = wgrad_gemm_km(tp, ws, dXb, D, QH, F, D, F, G(go.fc2_w), s);
+    } else {
+      VL_HIP(transpose_rows(QH, bf, T, F, F, actT, bf, Tp, s));                  // g^T
+      st = wgrad_gemm(m, tp, ws, gT, actT, D, F, G(go.fc2_w), s);
+    }
+    if (st != VL_OK) return st;
     if ((st = bias_grad(dX, false, D, G(go.fc2_b))) != VL_OK) return st;
     // ---- FC1: z1 = y2 W1^T + b1
     VL_HIP(transpose_rows(ly.fc1_w, bf, F, D, D, Wt, bf, F, s));                 // W1^T [D, F]
     if ((st = gemm_into_f32(m, dZ, F, Wt, F, T, D, F, dY, D, s)) != VL_OK) return st;
-    VL_HIP(transpose_rows(dZ, bf, T, F, F, gT, bf, Tp, s, bf ? part : nullptr));
-    VL_HIP(transpose_rows(ws + sv.y2, bf, T, D, D, actT, bf, Tp, s));
-    if ((st = wgrad_gemm(m, tp, ws, gT, actT, F, D, G(go.fc1_w), s)) != VL_OK) return st;
+    VL_HIP(transpose_rows(dZ, bf, T, F, F, gTo, bf, Tp, s, bf ? part : nullptr));
+    if (km) {
+      st = wgrad_gemm_km(tp, ws, dZ, F, ws + sv.y2, D, F, D, G(go.fc1_w), s);
+    } else {
+      VL_HIP(transpose_rows(ws + sv.y2, bf, T, D, D, actT, bf, Tp, s));
+      st = wgrad_gemm(m, tp, ws, gT, actT, F, D, G(go.fc1_w), s);
+    }
+    if (st != VL_OK) return st;
     if ((st = bias_grad(dZ, bf, F, G(go.fc1_b))) != VL_OK) return st;
     // ---- LN2 (dX += LN2'(h) dY)
     VL_HIP(layernorm_backward(reinterpret_cast<const float*>(ws + sv.h), ly.ln2_g, dY, eps, dX, T,
@@ -2069,8 +2110,13 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
     if ((st = prep_dx()) != VL_OK) return st;
     VL_HIP(transpose_rows(ly.o_w, bf, D, D, D, Wt, bf, D, s));
     if ((st = gemm_into_f32(m, dXb, D, Wt, D, T, D, D, dY, D, s)) != VL_OK) return st;   // dO
-    VL_HIP(transpose_rows(ws + sv.o, bf, T, D, D, actT, bf, Tp, s));
-    if ((st = wgrad_gemm(m, tp, ws, gT, actT, D, D, G(go.o_w), s)) != VL_OK) return st;
+    if (km) {
+      st = wgrad_gemm_km(tp, ws, dXb, D, ws + sv.o, D, D, D, G(go.o_w), s);
+    } else {
+      VL_HIP(transpose_rows(ws + sv.o, bf, T, D, D, actT, bf, Tp, s));
+      st = wgrad_gemm(m, tp, ws, gT, actT, D, D, G(go.o_w), s);
+    }
+    if (st != VL_OK) return st;
     if ((st = bias_grad(dX, false, D, G(go.o_b))) != VL_OK) return st;
     // ---- attention
     // (BF16: the log-sum-exp the forward kept, and dO also in BF16, in the
@@ -2084,9 +2130,14 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
     // ---- QKV: [q|k|v] = y1 Wqkv^T + bqkv
     VL_HIP(transpose_rows(ly.qkv_w, bf, 3 * D, D, D, Wt, bf, 3 * D, s));         // [D, 3D]
     if ((st = gemm_into_f32(m, dZ, 3 * D, Wt, 3 * D, T, D, 3 * D, dY, D, s)) != VL_OK) return st;
-    VL_HIP(transpose_rows(dZ, bf, T, 3 * D, 3 * D, gT, bf, Tp, s, bf ? part : nullptr));
-    VL_HIP(transpose_rows(ws + sv.y1, bf, T, D, D, actT, bf, Tp, s));
-    if ((st = wgrad_gemm(m, tp, ws, gT, actT, 3 * D, D, G(go.qkv_w), s)) != VL_OK) return st;
+    VL_HIP(transpose_rows(dZ, bf, T, 3 * D, 3 * D, gTo, bf, Tp, s, bf ? part : nullptr));
+    if (km) {
+      st = wgrad_gemm_km(tp, ws, dZ, 3 * D, ws + sv.y1, D, 3 * D, D, G(go.qkv_w), s);
+    } else {
+      VL_HIP(transpose_rows(ws + sv.y1, bf, T, D, D, actT, bf, Tp, s));
+      st = wgrad_gemm(m, tp, ws, gT, actT, 3 * D, D, G(go.qkv_w), s);
+    }
+    if (st != VL_OK) return st;
     if ((st = bias_grad(dZ, bf, 3 * D, G(go.qkv_b))) != VL_OK) return st;
     // ---- LN1 (dX += LN1'(x) dY)
     VL_HIP(layernorm_backward(reinterpret_cast<const float*>(ws + sv.xin), ly.ln1_g, dY, eps, dX,

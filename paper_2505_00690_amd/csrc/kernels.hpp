@@ -108,6 +108,15 @@ int gemm_mx_cfg_heuristic(int M, int N, int K);
 hipError_t gemm_bf16(const bf16_t* A, int lda, const void* B, int ldb, bool b_fp8,
                      int M, int N, int K, int op, int cfg, const EpiArgs& e, hipStream_t s);
 
+// C = alpha A^T B + beta with K-major BF16 operands A [K, lda] and B [K, ldb]
+// (a weight gradient summed over token rows, with neither operand
+// transposed first): FP32 output at e.out [M, e.ldo]; split z over K rows
+// [z e.kc, (z + 1) e.kc) writes its partial product at e.out + z e.zstride.
+// Rows at or past k_valid read as zero.  M % 256 == N % 256 == 0,
+// K % 64 == e.kc % 64 == 0, lda >= M, ldb >= N, both multiples of 8.
+hipError_t gemm_bf16_kmajor(const bf16_t* A, int lda, const bf16_t* B, int ldb, int M, int N,
+                            int K, int k_valid, const EpiArgs& e, hipStream_t s);
+
 // C[M,N] = A[M,K] . B[N,K]^T with both operands MXFP8: e4m3 codes [rows, K]
 // and E8M0 scales [K/128][rows][4] (layout in common.hpp), FP32
 // accumulation.  OP_QKV writes BF16; OP_FC1 writes MXFP8 codes to e.out and
@@ -235,7 +244,8 @@ struct ChanNorm { float mean[4], std[4]; };  // per-plane pixel normalisation
 // With colsum_part (BF16 output, cols % 8 == 0): also the row-block partials
 // of colsum for the same input, [ceil(rows / kColRows), cols]; finish with
 // colsum_final.  With copy_bf16 (FP32 input, BF16 output): also the input
-// rounded to BF16 in its own layout [rows, ld_in].
+// rounded to BF16 in its own layout [rows, ld_in].  out may be NULL (BF16
+// output type) when colsum_part or copy_bf16 is given: those alone.
 hipError_t transpose_rows(const void* in, bool in_bf16, int rows, int cols, int ld_in, void* out,
                           bool out_bf16, int ld_out, hipStream_t s,
                           float* colsum_part = nullptr, bf16_t* copy_bf16 = nullptr);

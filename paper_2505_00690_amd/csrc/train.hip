@@ -106,6 +106,7 @@ __global__ __launch_bounds__(256) void k_transpose64(const TI* __restrict__ in, 
                              : bf16_bits_to_f32(t[r][tid]);
     part[(size_t)blockIdx.y * cols + c0 + tid] = acc;
   }
+  if (out == nullptr) return;   // partials (and the copy) only
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
     const int c = (tid >> 3) + 32 * pass, rr = (tid & 7) * 8;
@@ -123,6 +124,8 @@ hipError_t transpose_rows(const void* in, bool in_bf16, int rows, int cols, int 
                           bool out_bf16, int ld_out, hipStream_t s, float* colsum_part,
                           bf16_t* copy_bf16) {
   if (cols <= 0 || ld_out <= 0) return hipSuccess;
+  // (no output: a pass for the column-sum partials or the copy alone)
+  if (!out && (!out_bf16 || (!colsum_part && !copy_bf16))) return hipErrorInvalidValue;
   const bool al16 = (reinterpret_cast<uintptr_t>(in) % 16 == 0) &&
                     (reinterpret_cast<uintptr_t>(out) % 16 == 0);
   if (out_bf16 && al16 && cols % 8 == 0 && ld_in % 8 == 0 && ld_out % 8 == 0) {
@@ -142,7 +145,7 @@ hipError_t transpose_rows(const void* in, bool in_bf16, int rows, int cols, int 
                          copy_bf16);
     return hipGetLastError();
   }
-  if (colsum_part || copy_bf16) return hipErrorInvalidValue;
+  if (colsum_part || copy_bf16 || !out) return hipErrorInvalidValue;
   dim3 grid((cols + 31) / 32, (ld_out + 31) / 32), block(256);
   if (in_bf16 && out_bf16)
     hipLaunchKernelGGL((k_transpose<bf16_t, bf16_t>), grid, block, 0, s,

@@ -16,7 +16,8 @@ import torch
 
 __all__ = [
     "VlError", "VlConfig", "lib", "library_path", "VL_FP32", "VL_BF16", "VL_FP8W_BF16A",
-    "VL_HEAD_SOFTMAX", "VL_HEAD_SIGMOID", "VL_OPT_GRAPHS", "VL_OPT_TIMING", "VL_OPT_SPLIT", "VL_OPT_GRAPH_BUCKETS",
+    "VL_HEAD_SOFTMAX", "VL_HEAD_SIGMOID", "VL_OPT_GRAPHS", "VL_OPT_TIMING", "VL_OPT_SPLIT",
+    "VL_OPT_GRAPH_BUCKETS", "VL_OPT_KMAJOR_WGRAD",
     "VL_N_OPS", "OP_NAMES", "vl_model_op_times", "PRECISIONS", "HEADS",
     "vl_abi_version", "vl_weights_count", "vl_model_create", "vl_model_destroy",
     "vl_model_set_option", "vl_encode_workspace_bytes", "vl_encode_images", "vl_score",
@@ -36,6 +37,7 @@ VL_FP32, VL_BF16, VL_FP8W_BF16A, VL_MXFP8 = 0, 1, 2, 3
 VL_HEAD_SOFTMAX, VL_HEAD_SIGMOID = 0, 1
 VL_OPT_GRAPHS, VL_OPT_TIMING, VL_OPT_SPLIT, VL_OPT_FUSED_LN, VL_OPT_ATTN_RESIDENT = 0, 1, 2, 3, 4
 VL_OPT_GRAPH_BUCKETS = 5
+VL_OPT_KMAJOR_WGRAD = 6
 VL_N_OPS = 8
 OP_NAMES = ("patch_embed", "layernorm", "qkv_gemm", "attention", "oproj_gemm", "fc1_gemm",
             "fc2_gemm", "pool_proj_l2")

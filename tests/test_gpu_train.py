@@ -164,3 +164,42 @@ def test_backward_needs_matching_train_call(V):
     with pytest.raises(V.VlError) as ei:
         mx.forward(pix, sizes)
     mx.close()
+
+
+def test_backward_kmajor_weight_gradients_match_transposed(V):
+    """The weight gradients formed from the token-major operands equal those
+    of the transposed-copy path (same BF16 operands, same K splits) up to
+    FP32 summation order inside the matrix instructions; every other
+    gradient is bitwise equal.  One ViT-L/14-shaped block (widths 1024,
+    3072, 4096: the K-major path's multiples of 256), two 336-px images:
+    1154 token rows, a ragged last 64-row K tile in the last split."""
+    p = synth.make_params(L14_1, 67, std=0.02)
+    blob = torch.from_numpy(synth.params_to_blob(L14_1, p)).cuda()
+    sizes = [(336, 336)] * 2
+    pix = torch.from_numpy(pack(synth.make_images(sizes, 68))).cuda()
+    de = torch.from_numpy(synth.make_texts(2, L14_1.proj_dim, 69)).cuda() * 0.1
+    tr = V.Trainer(L14_1, blob, "bf16")
+    got = {}
+    for km in (1, 0):
+        _say(f"train l14_1block bf16 kmajor={km}")
+        V.vl_model_set_option(tr.handle, V.VL_OPT_KMAJOR_WGRAD, km)
+        tr.forward(pix, sizes)
+        got[km] = tr.backward(pix, sizes, de).clone().cpu().numpy()
+    tr.close()
+    block_w = {"qkv_w", "o_w", "fc1_w", "fc2_w"}
+    for name, a, b in _per_tensor_pair(L14_1, got[1], got[0]):
+        if name.split(".")[-1] in block_w:
+            scale = np.abs(b).max()
+            assert scale > 0, name
+            err = np.abs(a - b).max() / scale
+            assert err <= 1e-5, (name, err)
+        else:
+            assert np.array_equal(a, b), name
+
+
+def _per_tensor_pair(cfg, a, b):
+    o = 0
+    for name, shape in synth.weight_layout(cfg):
+        n = int(np.prod(shape))
+        yield name, a[o:o + n], b[o:o + n]
+        o += n
