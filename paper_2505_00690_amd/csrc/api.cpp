@@ -1723,8 +1723,10 @@ namespace {
 struct TrainLayer { size_t xin, y1, qkv, o, h, y2, z1, lse; };
 struct TrainPlan {
   Plan p;
-  size_t off_items64 = 0;   // 64-token attention blocks, in the descriptor region
+  size_t off_items64 = 0;   // 64-token attention blocks (dK / dV), in the descriptor region
   int n_items64 = 0;
+  size_t off_items128 = 0;  // 128-token attention blocks (dQ), after them
+  int n_items128 = 0;
   int Tp = 0;               // T rounded up to 64 (K of the weight-gradient GEMMs)
   std::vector<TrainLayer> layers;
   size_t dX, dXb, gT, actT, dGf, dZ, dY, Wt, lse, dsum, part, pg, pb, de, zp, ppg, ppb, dwf;
@@ -1763,14 +1765,18 @@ bool make_train_plan(const vl_model* m, int32_t n, const int32_t* hs, const int3
   Plan& p = tp->p;
   // (2^20 tokens: the transposes' grid spans T / 32 rows of workgroups)
   if (p.T > (1 << 20)) { *why = "training batch exceeds 2^20 tokens"; return false; }
-  // 64-token blocks of every image for the attention backward
-  std::vector<AttnItem> it;
+  // 64- and 128-token blocks of every image for the attention backward
+  std::vector<AttnItem> it, it2;
   const ImgDesc* imgs = reinterpret_cast<const ImgDesc*>(p.desc.data() + p.parts[0].off_imgs);
-  for (int i = 0; i < n; ++i)
+  for (int i = 0; i < n; ++i) {
     for (int t0 = 0; t0 < imgs[i].ntok; t0 += 64) it.push_back(AttnItem{i, t0});
+    for (int t0 = 0; t0 < imgs[i].ntok; t0 += 128) it2.push_back(AttnItem{i, t0});
+  }
   tp->n_items64 = (int)it.size();
   tp->off_items64 = (p.desc_bytes + 15) / 16 * 16;
-  const size_t new_desc = tp->off_items64 + sizeof(AttnItem) * it.size();
+  tp->n_items128 = (int)it2.size();
+  tp->off_items128 = tp->off_items64 + sizeof(AttnItem) * it.size();
+  const size_t new_desc = tp->off_items128 + sizeof(AttnItem) * it2.size();
   if (align_up(new_desc) > align_up(p.desc_bytes)) {
     // the activation regions start after the descriptor region: move them
     const size_t shift = align_up(new_desc) - align_up(p.desc_bytes);
@@ -1781,6 +1787,7 @@ bool make_train_plan(const vl_model* m, int32_t n, const int32_t* hs, const int3
   }
   p.desc.resize(new_desc, 0);
   std::memcpy(p.desc.data() + tp->off_items64, it.data(), sizeof(AttnItem) * it.size());
+  std::memcpy(p.desc.data() + tp->off_items128, it2.data(), sizeof(AttnItem) * it2.size());
   p.desc_bytes = new_desc;
 
   const size_t T = p.T, D = m->D, F = m->F, es = m->prec == VL_FP32 ? 4 : 2;
@@ -2018,6 +2025,7 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
   const bool f32 = m->prec == VL_FP32, bf = !f32;
   const ImgDesc* d_imgs = reinterpret_cast<const ImgDesc*>(ws + p.off_imgs);
   const AttnItem* d_items64 = reinterpret_cast<const AttnItem*>(ws + tp.off_items64);
+  const AttnItem* d_items128 = reinterpret_cast<const AttnItem*>(ws + tp.off_items128);
   int2* tok = reinterpret_cast<int2*>(ws + p.off_tok);
   const float* X = reinterpret_cast<const float*>(ws + p.off_X);
   void* QH = ws + p.off_QH;
@@ -2123,6 +2131,7 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
     // dX operand buffer, free until the next block's; FP32: recomputed)
     if (bf) VL_HIP(convert_bf16(dY, static_cast<bf16_t*>(dXb), (size_t)T * D, s));
     VL_HIP(attention_backward(ws + sv.qkv, ws + sv.o, bf, dY, d_imgs, d_items64, tp.n_items64,
+                              d_items128, tp.n_items128,
                               m->heads, m->hd, dZ,
                               reinterpret_cast<float*>(ws + (bf ? sv.lse : tp.lse)),
                               reinterpret_cast<float*>(ws + tp.dsum), s, bf,

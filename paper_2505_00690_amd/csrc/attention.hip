@@ -58,15 +58,10 @@ typedef short s16x4 __attribute__((ext_vector_type(4)));
 // MX = false: O is BF16 [T, D].  MX = true: O is MXFP8 for the output
 // projection, codes [T, D] (out) and scales [D/128][T][4] (out_scale); a
 // 32-column block of a head lies in one lane pair (lane, lane ^ 32).
-// Work items are dealt XCD by XCD: workgroup ids go round-robin to the 8
-// XCDs, so each XCD is given a contiguous range of (head, query block)
-// items, in which the query blocks of one (image, head) are consecutive and
-// share that image's key and value rows in the XCD's L2.
-__device__ __forceinline__ int xcd_linear(int bid, int total) {
-  const int xcd = bid & 7, local = bid >> 3;
-  const int q = total >> 3, r = total & 7;
-  return xcd * q + min(xcd, r) + local;
-}
+// Work items are dealt XCD by XCD (xcd_linear): each XCD is given a
+// contiguous range of (head, query block) items, in which the query blocks
+// of one (image, head) are consecutive and share that image's key and value
+// rows in the XCD's L2.
 
 template <int HD, bool MX>
 __global__ __launch_bounds__(256) void k_attn_bf16(const bf16_t* __restrict__ qkv,

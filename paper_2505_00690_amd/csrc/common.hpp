@@ -155,6 +155,14 @@ __device__ __forceinline__ void dma16(i32x4 rsrc, uint32_t lds, int voffset, int
                : "memory", "m0");
 }
 
+// The same with 4 bytes per lane: lane i's dword lands at LDS byte lds + 4 i.
+__device__ __forceinline__ void dma4(i32x4 rsrc, uint32_t lds, int voffset, int soffset) {
+  asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dword %1, %2, %3 offen lds"
+               :
+               : "s"(lds), "v"(voffset), "s"(rsrc), "s"(soffset)
+               : "memory", "m0");
+}
+
 // Workgroup barrier without the compiler's memory fence (which would also
 // wait for every outstanding global load): LDS reads of this wave are
 // drained first, global-to-LDS loads are waited for explicitly by callers.
@@ -199,6 +207,15 @@ __device__ __forceinline__ float block_reduce(float v, float* red, Op op) {
 __device__ __forceinline__ bool xcd_live(int bid, int total) {
   const int xcd = bid & 7, local = bid >> 3;
   return local < (total >> 3) + (xcd < (total & 7) ? 1 : 0);
+}
+
+// The position of workgroup bid in an order that gives each XCD a contiguous
+// range of `total` items: XCD x takes items x * (total / 8) + min(x, total %
+// 8) onwards, in the order its workgroups arrive.
+__device__ __forceinline__ int xcd_linear(int bid, int total) {
+  const int xcd = bid & 7, local = bid >> 3;
+  const int q = total >> 3, r = total & 7;
+  return xcd * q + min(xcd, r) + local;
 }
 
 }  // namespace vl

@@ -266,15 +266,16 @@ hipError_t gelu_forward(const float* z, void* g, bool g_bf16, size_t n, hipStrea
 hipError_t gelu_backward(const float* dg, const float* z, void* dz, void* g, bool bf16, size_t n,
                          hipStream_t s);
 // dQKV [T, 3D] of the attention of every image: items64 are (image, first
-// token) blocks of 64 tokens; lse and dsum [T, heads] are scratch, except
+// token) blocks of 64 tokens (dK / dV), items128 blocks of 128 tokens (dQ,
+// BF16 only); lse and dsum [T, heads] are scratch, except
 // that with lse_given (BF16) lse already holds the forward's log-sum-exp
 // (attention_bf16's lse_out) and is only read.  BF16 models also pass dO
 // rounded to BF16 (dO_bf16 [T, D]), from which the dK/dV pass loads its tiles.
 hipError_t attention_backward(const void* qkv, const void* o, bool bf16, const float* dO,
                               const ImgDesc* imgs, const AttnItem* items64, int n_items,
-                              int heads, int head_dim, void* dqkv, float* lse, float* dsum,
-                              hipStream_t s, bool lse_given = false,
-                              const bf16_t* dO_bf16 = nullptr);
+                              const AttnItem* items128, int n_items128, int heads, int head_dim,
+                              void* dqkv, float* lse, float* dsum, hipStream_t s,
+                              bool lse_given = false, const bf16_t* dO_bf16 = nullptr);
 // Pooling head: de, z [n, *] scratch, the class rows of dX, and the
 // gradients of the projection and the final LayerNorm (pg, pb [n, D] and
 // part [ceil(n / kColRows), D] scratch).

@@ -13,6 +13,8 @@
 // here are the transposes that feed them, the deterministic column sums of
 // the bias and LayerNorm gradients (per-block partial sums added in a fixed
 // order), the attention backward and the head / embedding pieces.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace vl {
@@ -607,13 +609,9 @@ __global__ __launch_bounds__(256) void k_attn_bwd_dkv(const T* __restrict__ qkv,
 // gfx950 LDS transpose read gives exactly that from a row-major tile (the
 // forward attention kernel's value-operand read).
 //
-// dq kernel: a workgroup of two waves owns 64 queries of one (image, head),
-// a lane one query (B operands Q, dO of its row in registers).  Pass 1:
-// S^T = K Q^T per 64-key tile, the row maximum and sum of exponentials
-// (log-sum-exp, in log2 units of the scaled scores).  Pass 2: S^T and
-// dP^T = V dO^T again, dS^T = P^T (dP^T - D), dQ^T += K^T dS^T with K^T read
-// transposed from the key tile in LDS.  It also writes the log-sum-exp and
-// D = rowsum(dO O).  dkv kernel: two waves own 64 keys (lane: one key, K and
+// dq kernel (below): four waves own 128 queries, key / value tiles stream
+// through LDS; dS^T = P^T (dP^T - D) and dQ^T += K^T dS^T with K^T read
+// transposed from the key tile.  dkv kernel: two waves own 64 keys (lane: one key, K and
 // V rows in registers); per 64-query tile (Q and dO in LDS) S = Q K^T, dP =
 // dO V^T, P, dS, then dV^T += dO^T P and dK^T += Q^T dS with dO^T and Q^T
 // read transposed.  FP32 accumulation; P and dS rounded to BF16 as MFMA
@@ -629,20 +627,25 @@ struct TrTile {   // row-major 64 x HD BF16 tile; chunk c of row r at c ^ f(r)
 
 typedef short s16x4b __attribute__((ext_vector_type(4)));
 
-// Transposed operand from a TrTile at LDS byte address `tile`: lane (column
-// 32a + l32, g) receives rows 16jj + 4g + 0..3 and 16jj + 8 + 4g + 0..3.
+// This lane's offset, within a TrTile, of its transposed-operand reads for
+// 32-column block a and 16-row chunk 0 (chunk jj adds 16 jj rows: the
+// permutation depends on the row modulo 8 only).
 template <int HD>
-__device__ __forceinline__ bf16x8 tr_frag(uint32_t tile, int a, int jj, int lane) {
+__device__ __forceinline__ uint32_t tr_lane_off(int a, int lane) {
   using TT = TrTile<HD>;
   const int grp = lane >> 4, li = lane & 15;
-  const int tg = grp >> 1, dh = grp & 1;
-  const int col = 32 * a + 16 * dh + 4 * (li & 3);
-  const uint32_t vb = tile + TT::off(4 * tg + (li >> 2), col >> 3) + (col & 7) * 2 +
-                      16 * jj * TT::ROWB;
+  const int col = 32 * a + 16 * (grp & 1) + 4 * (li & 3);
+  return TT::off(4 * (grp >> 1) + (li >> 2), col >> 3) + (col & 7) * 2;
+}
+
+// Transposed operand at LDS byte address `addr` (a lane's tr_lane_off plus
+// the tile and 16-row chunk): rows +0..3 and +8..11 of the lane's column.
+template <int HD>
+__device__ __forceinline__ bf16x8 tr_read(uint32_t addr) {
   typedef __attribute__((address_space(3))) s16x4b lds_s16x4;
-  const s16x4b v0 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(uintptr_t)vb);
-  const s16x4b v1 =
-      __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(uintptr_t)(vb + 8 * TT::ROWB));
+  const s16x4b v0 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(uintptr_t)addr);
+  const s16x4b v1 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+      (lds_s16x4*)(uintptr_t)(addr + 8 * TrTile<HD>::ROWB));
   u32x4 vk;
   vk[0] = __builtin_bit_cast(u32x2, v0).x; vk[1] = __builtin_bit_cast(u32x2, v0).y;
   vk[2] = __builtin_bit_cast(u32x2, v1).x; vk[3] = __builtin_bit_cast(u32x2, v1).y;
@@ -663,32 +666,34 @@ __device__ __forceinline__ bf16x8 f32x8_to_bf16(float4 a, float4 b) {
   return __builtin_bit_cast(bf16x8, pk);
 }
 
-// Cooperative fill of a TrTile (128 threads) from rows r0.. of a BF16 or
-// FP32 (converted) matrix with row stride ld; rows >= nrows are zero.
-template <int HD, typename T>
-__device__ __forceinline__ void fill_tile(char* tile, const T* src, size_t ld, int nrows) {
-  using TT = TrTile<HD>;
-  for (int i = threadIdx.x; i < 64 * TT::NCH; i += 128) {
-    const int r = i / TT::NCH, c = i - r * TT::NCH;
-    bf16x8 v;
-    if (r < nrows) {
-      if constexpr (sizeof(T) == 2) {
-        v = *reinterpret_cast<const bf16x8*>(src + (size_t)r * ld + 8 * c);
-      } else {
-        const float4* p = reinterpret_cast<const float4*>(src + (size_t)r * ld + 8 * c);
-        v = f32x8_to_bf16(p[0], p[1]);
-      }
-    } else {
-      v = __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u});
-    }
-    *reinterpret_cast<bf16x8*>(tile + TT::off(r, c)) = v;
-  }
-}
+// Value tile of the dQ kernel (read by rows only): chunk c of row r at
+// c ^ f(r), f chosen so 16 consecutive rows read at one logical chunk hit
+// distinct banks.
+template <int HD>
+struct RowTile {
+  static constexpr int NCH = HD / 8;
+  static constexpr int ROWB = HD * 2;
+  static constexpr int BYTES = 64 * ROWB;
+  __device__ static int f(int r) { return NCH == 8 ? ((r ^ (r >> 3)) & 7) : ((r >> 2) & 3); }
+  __device__ static int off(int r, int chunk) { return r * ROWB + ((chunk ^ f(r)) << 4); }
+};
 
-// LSE_IN: lse2_io already holds each query's log-sum-exp (from the forward),
-// so pass 1 is skipped and nothing is written there.
+constexpr int BWD_Q = 128;   // queries per dQ workgroup (four waves of 32)
+constexpr int BWD_ST = 3;    // key / value tile ring stages of the dQ kernel
+
+// dQ kernel: four waves own 128 queries of one (image, head), a lane one
+// query (B operands Q and dO of its row in registers).  Key and value tiles
+// of 64 tokens stream through a three-stage LDS ring by direct-to-LDS loads
+// issued two tiles ahead (rows past the image read as zero).  Per tile:
+// S^T = K Q^T, dP^T = V dO^T, P = exp2(S log2(e) / sqrt(d) - lse),
+// dS^T = P^T (dP^T - D), dQ^T += K^T dS^T with K^T read transposed from the
+// key tile.  Work items are dealt XCD by XCD (the query blocks of one
+// (image, head) share its keys and values in one L2).  LSE_IN: lse2_io holds
+// each query's log-sum-exp (log2 units, from the forward) and is only read;
+// otherwise a first pass over the keys forms and writes it.  Also writes D =
+// rowsum(dO O) per query.
 template <int HD, bool LSE_IN>
-__global__ __launch_bounds__(128) void k_attn_bwd_dq_mfma(const bf16_t* __restrict__ qkv,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_attn_bwd_dq_mfma(const bf16_t* __restrict__ qkv,
                                                           const bf16_t* __restrict__ o,
                                                           const float* __restrict__ dO,
                                                           const ImgDesc* __restrict__ imgs,
@@ -696,16 +701,26 @@ __global__ __launch_bounds__(128) void k_attn_bwd_dq_mfma(const bf16_t* __restri
                                                           int heads, bf16_t* __restrict__ dqkv,
                                                           float* __restrict__ lse2_io,
                                                           float* __restrict__ dsum_out) {
-  using TT = TrTile<HD>;
+  using TK = TrTile<HD>;
+  using TV = RowTile<HD>;
   constexpr int NC = HD / 16, NA = HD / 32;
-  __shared__ __attribute__((aligned(16))) char sK[TT::BYTES];
-  const AttnItem it = items[blockIdx.x];
-  const int h = blockIdx.y;
+  constexpr int RPI = 1024 / TK::ROWB;     // tile rows per 1 KB direct-to-LDS load
+  constexpr int LPW = 64 / RPI / 4;        // key (and value) loads per wave and tile
+  static_assert(LPW >= 1 && LPW * RPI * 4 == 64, "tile / waves");
+  __shared__ __attribute__((aligned(1024))) char sK[BWD_ST][TK::BYTES];
+  __shared__ __attribute__((aligned(1024))) char sV[BWD_ST][TV::BYTES];
+  const int total = gridDim.x, n_items = total / heads;
+  const int wi = xcd_linear(blockIdx.x, total);
+  const AttnItem it = items[wi % n_items];
+  const int h = wi / n_items;
   const ImgDesc dsc = imgs[it.img];
   const int N = dsc.ntok, DM = heads * HD, ld3 = 3 * DM;
   const bf16_t* base = qkv + (size_t)dsc.tok_start * ld3 + h * HD;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l32 = lane & 31, g = lane >> 5;
-  const int q = it.q0 + 32 * wave + l32;
+  const int tid = threadIdx.x, lane = tid & 63, l32 = lane & 31, g = lane >> 5;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: LDS bases
+  const int qw = it.q0 + 32 * wave;
+  const bool wave_active = qw < N;
+  const int q = qw + l32;
   const bool qok = q < N;
   const int qc = min(q, N - 1);
   const size_t qrow = (size_t)dsc.tok_start + qc;
@@ -726,90 +741,141 @@ __global__ __launch_bounds__(128) void k_attn_bwd_dq_mfma(const bf16_t* __restri
   }
   dsv += __shfl_xor(dsv, 32, 64);
   const float sl2 = 1.4426950408889634f / sqrtf((float)HD);
-  auto key_frag = [&](int row, int c) {   // K row fragment from global (row clamped)
-    return *reinterpret_cast<const bf16x8*>(base + DM + (size_t)min(row, N - 1) * ld3 + 16 * c +
-                                            8 * g);
-  };
-  // pass 1: log-sum-exp of each query's scaled scores (log2 units)
+  // pass 1 (no log-sum-exp given): each query's log-sum-exp of its scaled
+  // scores (log2 units), key fragments straight from global memory
   float lse2;
   if constexpr (LSE_IN) {
     lse2 = lse2_io[qrow * heads + h];
   } else {
-  float m = -INFINITY, l = 0.f;
-  for (int k0 = 0; k0 < N; k0 += 64) {
-    f32x16 s[2];
+    float m = -INFINITY, l = 0.f;
+    for (int k0 = 0; k0 < N; k0 += 64) {
+      f32x16 s[2];
 #pragma unroll
-    for (int kb = 0; kb < 2; ++kb) {
+      for (int kb = 0; kb < 2; ++kb) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) s[kb][r] = 0.f;
+        for (int r = 0; r < 16; ++r) s[kb][r] = 0.f;
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        s[kb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(key_frag(k0 + 32 * kb + l32, c), qf[c],
-                                                        s[kb], 0, 0, 0);
-    }
-    float mt = -INFINITY;
-#pragma unroll
-    for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int key = k0 + 32 * kb + 8 * (r >> 2) + 4 * g + (r & 3);
-        s[kb][r] = key < N ? s[kb][r] * sl2 : -INFINITY;
-        mt = fmaxf(mt, s[kb][r]);
+        for (int c = 0; c < NC; ++c) {
+          const bf16x8 kf = *reinterpret_cast<const bf16x8*>(
+              base + DM + (size_t)min(k0 + 32 * kb + l32, N - 1) * ld3 + 16 * c + 8 * g);
+          s[kb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kf, qf[c], s[kb], 0, 0, 0);
+        }
       }
-    mt = fmaxf(mt, __shfl_xor(mt, 32, 64));
-    const float mn = fmaxf(m, mt);
-    float ts = 0.f;
+      float mt = -INFINITY;
 #pragma unroll
-    for (int kb = 0; kb < 2; ++kb)
+      for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) ts += exp2f(s[kb][r] - mn);
-    l = l * exp2f(m - mn) + ts;
-    m = mn;
+        for (int r = 0; r < 16; ++r) {
+          const int key = k0 + 32 * kb + 8 * (r >> 2) + 4 * g + (r & 3);
+          s[kb][r] = key < N ? s[kb][r] * sl2 : -INFINITY;
+          mt = fmaxf(mt, s[kb][r]);
+        }
+      mt = fmaxf(mt, __shfl_xor(mt, 32, 64));
+      const float mn = fmaxf(m, mt);
+      float ts = 0.f;
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) ts += exp2f(s[kb][r] - mn);
+      l = l * exp2f(m - mn) + ts;
+      m = mn;
+    }
+    lse2 = m + log2f(l + __shfl_xor(l, 32, 64));
   }
-  lse2 = m + log2f(l + __shfl_xor(l, 32, 64));
+  // Wait for the operands above with a wait the compiler sees, so its
+  // wait-count pass does not hold the ring's loads back for them later.
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+
+  // Direct-to-LDS loads: instruction i of this wave fills tile rows
+  // R = (wave LPW + i) RPI ..; lane l takes row R + l / NCH and physical
+  // chunk l % NCH, i.e. logical chunk (l % NCH) ^ f(row).
+  const i32x4 rk = buffer_rsrc(base + DM, (uint64_t)N * ld3 * 2);
+  const i32x4 rv = buffer_rsrc(base + 2 * DM, (uint64_t)N * ld3 * 2);
+  int goffK[LPW], goffV[LPW];
+#pragma unroll
+  for (int i = 0; i < LPW; ++i) {
+    const int row = (wave * LPW + i) * RPI + lane / TK::NCH;
+    goffK[i] = row * ld3 * 2 + (((lane % TK::NCH) ^ TK::f(row)) << 4);
+    goffV[i] = row * ld3 * 2 + (((lane % TV::NCH) ^ TV::f(row)) << 4);
   }
-  // pass 2: dS^T and dQ^T
+  const uint32_t ldsK = lds_offset(&sK[0][0]), ldsV = lds_offset(&sV[0][0]);
+  auto issue = [&](int kt, int st) {
+    const int kb = kt * 64 * ld3 * 2;
+#pragma unroll
+    for (int i = 0; i < LPW; ++i) {
+      const uint32_t lo = st * TK::BYTES + (wave * LPW + i) * 1024;
+      dma16(rk, ldsK + lo, goffK[i] + kb, 0);
+      dma16(rv, ldsV + lo, goffV[i] + kb, 0);
+    }
+  };
+  // Row-operand offsets: lane reads row 32kb + l32, logical chunk 2c + g.
+  int koff[2][NC], voff[2][NC];
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      koff[kb][c] = TK::off(32 * kb + l32, 2 * c + g);
+      voff[kb][c] = TV::off(32 * kb + l32, 2 * c + g);
+    }
+
+  uint32_t trK[NA];   // K^T reads: per-lane base, plus stage and chunk immediates
+#pragma unroll
+  for (int a = 0; a < NA; ++a) trK[a] = ldsK + tr_lane_off<HD>(a, lane);
   f32x16 dq[NA];
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
     for (int r = 0; r < 16; ++r) dq[a][r] = 0.f;
-  const uint32_t ldsK = lds_offset(sK);
-  for (int k0 = 0; k0 < N; k0 += 64) {
-    __syncthreads();   // the previous tile's readers are done
-    fill_tile<HD>(sK, base + DM + (size_t)k0 * ld3, ld3, N - k0);
-    __syncthreads();
-    f32x16 s[2], dp[2];
+  const int KT = (N + 63) / 64;
+  auto tile = [&](auto stage, int kt) {
+    constexpr int st = decltype(stage)::value;
+    // Tile kt must have landed; tile kt+1's loads may stay in flight.
+    if (kt + 1 < KT) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * LPW) : "memory");
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    lds_barrier();
+    // Stage (st+2)%3 held tile kt-1, whose readers all passed the barrier.
+    if (kt + 2 < KT) issue(kt + 2, (st + 2) % BWD_ST);
+    if (!wave_active) return;
+    const char* tK = sK[st];
+    const char* tV = sV[st];
+    const int k0 = kt * 64;
+    // The 64 keys as two halves of 32 (fewer live registers): half kb gives
+    // the 16-key chunks jj = 2kb, 2kb + 1 of dQ^T += K^T dS^T.
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
+      f32x16 s, dp;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) s[kb][r] = dp[kb][r] = 0.f;
-      const int row = 32 * kb + l32;
+      for (int r = 0; r < 16; ++r) s[r] = dp[r] = 0.f;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const bf16x8 kf = *reinterpret_cast<const bf16x8*>(sK + TT::off(row, 2 * c + g));
-        s[kb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kf, qf[c], s[kb], 0, 0, 0);
-        const bf16x8 vf = *reinterpret_cast<const bf16x8*>(
-            base + 2 * DM + (size_t)min(k0 + row, N - 1) * ld3 + 16 * c + 8 * g);
-        dp[kb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vf, df[c], dp[kb], 0, 0, 0);
+        const bf16x8 kf = *reinterpret_cast<const bf16x8*>(tK + koff[kb][c]);
+        s = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kf, qf[c], s, 0, 0, 0);
+        const bf16x8 vf = *reinterpret_cast<const bf16x8*>(tV + voff[kb][c]);
+        dp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vf, df[c], dp, 0, 0, 0);
       }
-    }
-#pragma unroll
-    for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int key = k0 + 32 * kb + 8 * (r >> 2) + 4 * g + (r & 3);
-        const float p = key < N ? exp2f(fmaf(s[kb][r], sl2, -lse2)) : 0.f;
-        s[kb][r] = p * (dp[kb][r] - dsv);
+        const float p = key < N ? exp2f(fmaf(s[r], sl2, -lse2)) : 0.f;
+        s[r] = p * (dp[r] - dsv);
       }
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      const bf16x8 dsf = pack8(s[jj >> 1], jj & 1);
+      for (int hh = 0; hh < 2; ++hh) {
+        const bf16x8 dsf = pack8(s, hh);
 #pragma unroll
-      for (int a = 0; a < NA; ++a)
-        dq[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(tr_frag<HD>(ldsK, a, jj, lane), dsf,
-                                                        dq[a], 0, 0, 0);
+        for (int a = 0; a < NA; ++a)
+          dq[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              tr_read<HD>(trK[a] + st * TK::BYTES + 16 * (2 * kb + hh) * TK::ROWB), dsf, dq[a],
+              0, 0, 0);
+      }
     }
+  };
+  issue(0, 0);
+  if (KT > 1) issue(1, 1);
+  for (int kt = 0; kt < KT; kt += BWD_ST) {
+    tile(std::integral_constant<int, 0>(), kt);
+    if (kt + 1 < KT) tile(std::integral_constant<int, 1>(), kt + 1);
+    if (kt + 2 < KT) tile(std::integral_constant<int, 2>(), kt + 2);
   }
   if (!qok) return;
   const float scale = 1.0f / sqrtf((float)HD);
@@ -830,35 +896,41 @@ __global__ __launch_bounds__(128) void k_attn_bwd_dq_mfma(const bf16_t* __restri
   }
 }
 
-// dO in BF16 (dO_b [T, DM]); the query and dO tiles of the next 64 queries
-// stream into the second of two LDS stages by direct-to-LDS loads while the
-// current ones are used, and their log-sum-exp / D values wait in registers.
+// dK/dV kernel: four waves own 128 keys of one (image, head), a lane one key
+// (K and V rows of its key in registers, the A-side operands of S and dP).
+// dO in BF16 (dO_b [T, DM]).  Query and dO tiles of 64 tokens, with their
+// log-sum-exp and D values, stream through a three-stage LDS ring by
+// direct-to-LDS loads issued two tiles ahead (rows past the image read as
+// zero).  Work items are dealt XCD by XCD.
+// (Head width 64 keeps ~180 registers live: two waves per SIMD; 32: three.)
 template <int HD>
-__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void k_attn_bwd_dkv_mfma(const bf16_t* __restrict__ qkv,
-                                                           const bf16_t* __restrict__ dO_b,
-                                                           const ImgDesc* __restrict__ imgs,
-                                                           const AttnItem* __restrict__ items,
-                                                           int heads,
-                                                           const float* __restrict__ lse2,
-                                                           const float* __restrict__ dsum,
-                                                           bf16_t* __restrict__ dqkv) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HD == 64 ? 2 : 3))) void
+k_attn_bwd_dkv_mfma(const bf16_t* __restrict__ qkv, const bf16_t* __restrict__ dO_b,
+                    const ImgDesc* __restrict__ imgs, const AttnItem* __restrict__ items,
+                    int heads, const float* __restrict__ lse2, const float* __restrict__ dsum,
+                    bf16_t* __restrict__ dqkv) {
   using TT = TrTile<HD>;
   constexpr int NC = HD / 16, NA = HD / 32;
   constexpr int RPI = 1024 / TT::ROWB;   // tile rows per 1 KB direct-to-LDS load
-  constexpr int NI = 64 / RPI;           // such loads per tile (two waves share them)
-  static_assert(NI % 2 == 0, "tile / waves");
-  __shared__ __attribute__((aligned(1024))) char sQ[2][TT::BYTES];
-  __shared__ __attribute__((aligned(1024))) char sdO[2][TT::BYTES];
-  __shared__ float sL[2][64], sD[2][64];
-  const AttnItem it = items[blockIdx.x];   // it.q0: first key of the block
-  const int h = blockIdx.y;
+  constexpr int LPW = 64 / RPI / 4;      // query (and dO) loads per wave and tile
+  static_assert(LPW >= 1 && LPW * RPI * 4 == 64, "tile / waves");
+  __shared__ __attribute__((aligned(1024))) char sQ[BWD_ST][TT::BYTES];
+  __shared__ __attribute__((aligned(1024))) char sdO[BWD_ST][TT::BYTES];
+  __shared__ __attribute__((aligned(256))) float sL[BWD_ST][64];
+  __shared__ __attribute__((aligned(256))) float sD[BWD_ST][64];
+  const int total = gridDim.x, n_items = total / heads;
+  const int wi = xcd_linear(blockIdx.x, total);
+  const AttnItem it = items[wi % n_items];   // it.q0: first key of the block
+  const int h = wi / n_items;
   const ImgDesc dsc = imgs[it.img];
   const int N = dsc.ntok, DM = heads * HD, ld3 = 3 * DM;
   const bf16_t* base = qkv + (size_t)dsc.tok_start * ld3 + h * HD;
   const bf16_t* dbase = dO_b + (size_t)dsc.tok_start * DM + h * HD;
-  const int lane = threadIdx.x & 63, l32 = lane & 31, g = lane >> 5;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: LDS bases
-  const int k = it.q0 + 32 * wave + l32;
+  const int tid = threadIdx.x, lane = tid & 63, l32 = lane & 31, g = lane >> 5;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: LDS bases
+  const int kw = it.q0 + 32 * wave;
+  const bool wave_active = kw < N;
+  const int k = kw + l32;
   const bool kok = k < N;
   const int kc = min(k, N - 1);
   bf16x8 kf[NC], vf[NC];
@@ -867,93 +939,119 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void k
     kf[c] = *reinterpret_cast<const bf16x8*>(base + DM + (size_t)kc * ld3 + 16 * c + 8 * g);
     vf[c] = *reinterpret_cast<const bf16x8*>(base + 2 * DM + (size_t)kc * ld3 + 16 * c + 8 * g);
   }
+  // Wait for K and V with a wait the compiler sees, so its wait-count pass
+  // does not hold the ring's loads back for them later.
+  __builtin_amdgcn_s_waitcnt(0x0F70);
   const float sl2 = 1.4426950408889634f / sqrtf((float)HD);
   f32x16 dv[NA], dk[NA];
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
     for (int r = 0; r < 16; ++r) dv[a][r] = dk[a][r] = 0.f;
-  // Rows past the image read as zero (buffer bounds).  Load i of wave w
-  // fills rows RPI (NI/2 w + i) .. +RPI-1; lane l takes row l / NCH of them
-  // and physical chunk l % NCH, i.e. logical chunk (l % NCH) ^ f(row).
+  // Load i of wave w fills rows RPI (LPW w + i) .. +RPI-1; lane l takes row
+  // l / NCH of them and physical chunk l % NCH, i.e. logical chunk
+  // (l % NCH) ^ f(row).  Wave 0 also loads the tile's 64 log-sum-exp and D
+  // values (one per lane, stride `heads`).
   const i32x4 rq = buffer_rsrc(base, (uint64_t)N * ld3 * 2);
   const i32x4 rd = buffer_rsrc(dbase, (uint64_t)N * DM * 2);
-  const uint32_t ldsQ0 = lds_offset(&sQ[0][0]), ldsO0 = lds_offset(&sdO[0][0]);
-  auto issue = [&](int st, int q0) {
+  const size_t lbase = (size_t)dsc.tok_start * heads + h;
+  const i32x4 rl = buffer_rsrc(lse2 + lbase, (uint64_t)N * heads * 4);
+  const i32x4 rs = buffer_rsrc(dsum + lbase, (uint64_t)N * heads * 4);
+  int goffQ[LPW], goffD[LPW];
 #pragma unroll
-    for (int i = 0; i < NI / 2; ++i) {
-      const int grp = (NI / 2) * wave + i;
-      const int row = grp * RPI + lane / TT::NCH;
-      const int chunk = (lane % TT::NCH) ^ TT::f(row);
-      const uint32_t lo = st * TT::BYTES + grp * 1024;
-      dma16(rq, ldsQ0 + lo, (q0 + row) * ld3 * 2 + chunk * 16, 0);
-      dma16(rd, ldsO0 + lo, (q0 + row) * DM * 2 + chunk * 16, 0);
+  for (int i = 0; i < LPW; ++i) {
+    const int row = (wave * LPW + i) * RPI + lane / TT::NCH;
+    const int chunk = (lane % TT::NCH) ^ TT::f(row);
+    goffQ[i] = row * ld3 * 2 + chunk * 16;
+    goffD[i] = row * DM * 2 + chunk * 16;
+  }
+  const uint32_t ldsQ0 = lds_offset(&sQ[0][0]), ldsO0 = lds_offset(&sdO[0][0]);
+  const uint32_t ldsL0 = lds_offset(&sL[0][0]), ldsD0 = lds_offset(&sD[0][0]);
+  // Per-lane read offsets within a tile: rows (query half qb adds 32 rows,
+  // which keep the permutation) and transposed reads (plus immediates).
+  int roff[NC];
+  uint32_t trb[NA];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) roff[c] = TT::off(l32, 2 * c + g);
+#pragma unroll
+  for (int a = 0; a < NA; ++a) trb[a] = tr_lane_off<HD>(a, lane);
+  auto issue = [&](int qt, int st) {
+    const int q0 = qt * 64;
+#pragma unroll
+    for (int i = 0; i < LPW; ++i) {
+      const uint32_t lo = st * TT::BYTES + (wave * LPW + i) * 1024;
+      dma16(rq, ldsQ0 + lo, goffQ[i] + q0 * ld3 * 2, 0);
+      dma16(rd, ldsO0 + lo, goffD[i] + q0 * DM * 2, 0);
+    }
+    if (wave == 0) {
+      dma4(rl, ldsL0 + st * 256, (q0 + lane) * heads * 4, 0);
+      dma4(rs, ldsD0 + st * 256, (q0 + lane) * heads * 4, 0);
     }
   };
-  float l_next = 0.f, d_next = 0.f;
-  auto load_ld = [&](int q0) {
-    if (threadIdx.x < 64) {
-      const int qi = q0 + (int)threadIdx.x;
-      const size_t row = (size_t)dsc.tok_start + min(qi, N - 1);
-      l_next = qi < N ? lse2[row * heads + h] : 0.f;
-      d_next = qi < N ? dsum[row * heads + h] : 0.f;
+  const int QT = (N + 63) / 64;
+  auto tile = [&](auto stage, int qt) {
+    constexpr int st = decltype(stage)::value;
+    // Tile qt must have landed; tile qt+1's loads may stay in flight.
+    if (qt + 1 < QT) {
+      if (wave == 0) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * LPW + 2) : "memory");
+      else asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * LPW) : "memory");
+    } else {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
-  };
-  issue(0, 0);
-  load_ld(0);
-  for (int q0 = 0, cur = 0; q0 < N; q0 += 64, cur ^= 1) {
-    const int nq = min(64, N - q0);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's loads of tile q0
-    if (threadIdx.x < 64) {
-      sL[cur][threadIdx.x] = l_next;
-      sD[cur][threadIdx.x] = d_next;
-    }
-    __syncthreads();   // tile q0 complete; every wave is done with the other stage
-    if (q0 + 64 < N) {
-      issue(cur ^ 1, q0 + 64);
-      load_ld(q0 + 64);
-    }
-    const char* tQ = sQ[cur];
-    const char* tO = sdO[cur];
-    const uint32_t ldsQ = ldsQ0 + cur * TT::BYTES, ldsO = ldsO0 + cur * TT::BYTES;
-    const float* cL = sL[cur];
-    const float* cD = sD[cur];
+    lds_barrier();
+    // Stage (st+2)%3 held tile qt-1, whose readers all passed the barrier.
+    if (qt + 2 < QT) issue(qt + 2, (st + 2) % BWD_ST);
+    if (!wave_active) return;
+    const int nq = min(64, N - qt * 64);
+    const char* tQ = sQ[st];
+    const char* tO = sdO[st];
+    const float* cL = sL[st];
+    const float* cD = sD[st];
     // The 64 queries as two halves of 32 (fewer live registers): for half qb,
     // s[r] = S[query q0 + qi][key k], qi = 32qb + 8(r/4) + 4g + r%4, then its
     // two 16-query chunks jj = 2qb, 2qb + 1 of dV^T += dO^T P, dK^T += Q^T dS.
-    for (int qb = 0; qb < 2; ++qb) {
-      f32x16 s, dp;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) s[r] = dp[r] = 0.f;
-      const int row = 32 * qb + l32;
+    for (int qb = 0; qb < 2; ++qb) {
+      f32x16 sc, dp;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) sc[r] = dp[r] = 0.f;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const bf16x8 qa = *reinterpret_cast<const bf16x8*>(tQ + TT::off(row, 2 * c + g));
-        s = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa, kf[c], s, 0, 0, 0);
-        const bf16x8 da = *reinterpret_cast<const bf16x8*>(tO + TT::off(row, 2 * c + g));
+        const int ro = roff[c] + 32 * qb * TT::ROWB;
+        const bf16x8 qa = *reinterpret_cast<const bf16x8*>(tQ + ro);
+        sc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa, kf[c], sc, 0, 0, 0);
+        const bf16x8 da = *reinterpret_cast<const bf16x8*>(tO + ro);
         dp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(da, vf[c], dp, 0, 0, 0);
       }
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int qi = 32 * qb + 8 * (r >> 2) + 4 * g + (r & 3);
-        const float p = (qi < nq && kok) ? exp2f(fmaf(s[r], sl2, -cL[qi])) : 0.f;
-        s[r] = p;
+        const float p = (qi < nq && kok) ? exp2f(fmaf(sc[r], sl2, -cL[qi])) : 0.f;
+        sc[r] = p;
         dp[r] = p * (dp[r] - cD[qi]);
       }
 #pragma unroll
       for (int hh = 0; hh < 2; ++hh) {
         const int jj = 2 * qb + hh;
-        const bf16x8 pf = pack8(s, hh);
+        const bf16x8 pf = pack8(sc, hh);
         const bf16x8 dsf = pack8(dp, hh);
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
-          dv[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(tr_frag<HD>(ldsO, a, jj, lane), pf,
-                                                          dv[a], 0, 0, 0);
-          dk[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(tr_frag<HD>(ldsQ, a, jj, lane), dsf,
-                                                          dk[a], 0, 0, 0);
+          const uint32_t o = trb[a] + st * TT::BYTES + 16 * jj * TT::ROWB;
+          dv[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(tr_read<HD>(ldsO0 + o), pf, dv[a], 0,
+                                                          0, 0);
+          dk[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(tr_read<HD>(ldsQ0 + o), dsf, dk[a], 0,
+                                                          0, 0);
         }
       }
     }
+  };
+  issue(0, 0);
+  if (QT > 1) issue(1, 1);
+  for (int qt = 0; qt < QT; qt += BWD_ST) {
+    tile(std::integral_constant<int, 0>(), qt);
+    if (qt + 1 < QT) tile(std::integral_constant<int, 1>(), qt + 1);
+    if (qt + 2 < QT) tile(std::integral_constant<int, 2>(), qt + 2);
   }
   if (!kok) return;
   const float scale = 1.0f / sqrtf((float)HD);
@@ -961,33 +1059,34 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
-    for (int rq = 0; rq < 4; ++rq) {
+    for (int rq4 = 0; rq4 < 4; ++rq4) {
       u32x2 pk;
-      pk.x = pack_bf16x2(dk[a][4 * rq + 0] * scale, dk[a][4 * rq + 1] * scale);
-      pk.y = pack_bf16x2(dk[a][4 * rq + 2] * scale, dk[a][4 * rq + 3] * scale);
-      *reinterpret_cast<u32x2*>(out + DM + a * 32 + 8 * rq + 4 * g) = pk;
-      pk.x = pack_bf16x2(dv[a][4 * rq + 0], dv[a][4 * rq + 1]);
-      pk.y = pack_bf16x2(dv[a][4 * rq + 2], dv[a][4 * rq + 3]);
-      *reinterpret_cast<u32x2*>(out + 2 * DM + a * 32 + 8 * rq + 4 * g) = pk;
+      pk.x = pack_bf16x2(dk[a][4 * rq4 + 0] * scale, dk[a][4 * rq4 + 1] * scale);
+      pk.y = pack_bf16x2(dk[a][4 * rq4 + 2] * scale, dk[a][4 * rq4 + 3] * scale);
+      *reinterpret_cast<u32x2*>(out + DM + a * 32 + 8 * rq4 + 4 * g) = pk;
+      pk.x = pack_bf16x2(dv[a][4 * rq4 + 0], dv[a][4 * rq4 + 1]);
+      pk.y = pack_bf16x2(dv[a][4 * rq4 + 2], dv[a][4 * rq4 + 3]);
+      *reinterpret_cast<u32x2*>(out + 2 * DM + a * 32 + 8 * rq4 + 4 * g) = pk;
     }
 }
 
 template <int HD>
 static void launch_attn_bwd_mfma(const void* qkv, const void* o, const float* dO,
-                                 const ImgDesc* imgs, const AttnItem* items, int n_items,
-                                 int heads, void* dqkv, float* lse, float* dsum, hipStream_t s,
-                                 bool lse_given, const bf16_t* dO_bf16) {
-  dim3 grid(n_items, heads), block(128);
+                                 const ImgDesc* imgs, const AttnItem* items64, int n_items64,
+                                 const AttnItem* items128, int n_items128, int heads, void* dqkv,
+                                 float* lse, float* dsum, hipStream_t s, bool lse_given,
+                                 const bf16_t* dO_bf16) {
+  dim3 gq(n_items128 * heads), bq(256);
   if (lse_given)
-    hipLaunchKernelGGL((k_attn_bwd_dq_mfma<HD, true>), grid, block, 0, s,
+    hipLaunchKernelGGL((k_attn_bwd_dq_mfma<HD, true>), gq, bq, 0, s,
                        static_cast<const bf16_t*>(qkv), static_cast<const bf16_t*>(o), dO, imgs,
-                       items, heads, static_cast<bf16_t*>(dqkv), lse, dsum);
+                       items128, heads, static_cast<bf16_t*>(dqkv), lse, dsum);
   else
-    hipLaunchKernelGGL((k_attn_bwd_dq_mfma<HD, false>), grid, block, 0, s,
+    hipLaunchKernelGGL((k_attn_bwd_dq_mfma<HD, false>), gq, bq, 0, s,
                        static_cast<const bf16_t*>(qkv), static_cast<const bf16_t*>(o), dO, imgs,
-                       items, heads, static_cast<bf16_t*>(dqkv), lse, dsum);
-  hipLaunchKernelGGL(k_attn_bwd_dkv_mfma<HD>, grid, block, 0, s, static_cast<const bf16_t*>(qkv),
-                     dO_bf16, imgs, items, heads, lse, dsum, static_cast<bf16_t*>(dqkv));
+                       items128, heads, static_cast<bf16_t*>(dqkv), lse, dsum);
+  hipLaunchKernelGGL(k_attn_bwd_dkv_mfma<HD>, gq, bq, 0, s, static_cast<const bf16_t*>(qkv),
+                     dO_bf16, imgs, items128, heads, lse, dsum, static_cast<bf16_t*>(dqkv));
 }
 
 template <typename T, int HD>
@@ -1004,20 +1103,21 @@ static void launch_attn_bwd(const void* qkv, const void* o, const float* dO, con
 
 hipError_t attention_backward(const void* qkv, const void* o, bool bf16, const float* dO,
                               const ImgDesc* imgs, const AttnItem* items64, int n_items,
-                              int heads, int head_dim, void* dqkv, float* lse, float* dsum,
-                              hipStream_t s, bool lse_given, const bf16_t* dO_bf16) {
+                              const AttnItem* items128, int n_items128, int heads, int head_dim,
+                              void* dqkv, float* lse, float* dsum, hipStream_t s, bool lse_given,
+                              const bf16_t* dO_bf16) {
   if (n_items <= 0) return hipSuccess;
   if ((lse_given || dO_bf16) && !bf16) return hipErrorInvalidValue;
-  if (bf16 && !dO_bf16) return hipErrorInvalidValue;
+  if (bf16 && (!dO_bf16 || !items128 || n_items128 <= 0)) return hipErrorInvalidValue;
   if (head_dim == 64) {
     if (bf16)
-      launch_attn_bwd_mfma<64>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s,
-                               lse_given, dO_bf16);
+      launch_attn_bwd_mfma<64>(qkv, o, dO, imgs, items64, n_items, items128, n_items128, heads,
+                               dqkv, lse, dsum, s, lse_given, dO_bf16);
     else launch_attn_bwd<float, 64>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s);
   } else if (head_dim == 32) {
     if (bf16)
-      launch_attn_bwd_mfma<32>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s,
-                               lse_given, dO_bf16);
+      launch_attn_bwd_mfma<32>(qkv, o, dO, imgs, items64, n_items, items128, n_items128, heads,
+                               dqkv, lse, dsum, s, lse_given, dO_bf16);
     else launch_attn_bwd<float, 32>(qkv, o, dO, imgs, items64, n_items, heads, dqkv, lse, dsum, s);
   } else {
     return hipErrorInvalidValue;
