@@ -471,6 +471,35 @@ vl_status vl_attention(const void* qkv_dev, vl_precision prec, const int32_t* le
                        void* out_dev, void* workspace_dev, size_t workspace_bytes,
                        void* stream);
 
+/* Backward of vl_attention without a mask (causal = 0; the image tower's
+ * attention), per head h of each sequence (Vaswani et al. 2017, Sec. 3.2.1
+ * Eq. 1, differentiated): with S = Q K^T / sqrt(d), P = softmax(S) by rows
+ * and O = P V,  dV = P^T dO,  dP = dO V^T,  dS = P * (dP - rowsum(dO * O)),
+ *  dQ = dS K / sqrt(d),  dK = dS^T Q / sqrt(d).
+ *  qkv_dev   : as for vl_attention ([T, 3 * heads * head_dim], BF16 or FP32).
+ *  out_dev   : the forward's output O [T, heads * head_dim] (vl_attention's
+ *              out_dev for the same qkv), element type as qkv.
+ *  d_out_dev : dL/dO [T, heads * head_dim] FP32.
+ *  lengths, n_seqs, heads, head_dim : as for vl_attention.
+ *  d_qkv_dev : written, [T, 3 * heads * head_dim] = [dQ | dK | dV] in the
+ *              layout of qkv, element type as qkv.
+ *  workspace_dev : >= vl_attention_backward_workspace_bytes(n_seqs, lengths,
+ *              heads, head_dim) bytes, 256-byte aligned (descriptors, the
+ *              per-query log-sum-exp and rowsum(dO * O), dO in BF16).
+ * All device pointers 16-byte aligned.  The BF16 kernels recompute P from
+ * BF16 Q and K with FP32 softmax statistics, round dO, P and dS to BF16 as
+ * matrix operands and accumulate in FP32; FP32 runs FMA kernels throughout.
+ * Asynchronous on `stream`; the descriptors are copied from a pinned host
+ * buffer the library owns.  The workspace query returns 0 for invalid
+ * arguments.                                                               */
+size_t vl_attention_backward_workspace_bytes(int32_t n_seqs, const int32_t* lengths,
+                                             int32_t heads, int32_t head_dim);
+vl_status vl_attention_backward(const void* qkv_dev, const void* out_dev,
+                                const float* d_out_dev, vl_precision prec,
+                                const int32_t* lengths, int32_t n_seqs, int32_t heads,
+                                int32_t head_dim, void* d_qkv_dev, void* workspace_dev,
+                                size_t workspace_bytes, void* stream);
+
 /* Contrastive loss of n matched (image, text) pairs, e.g. the embeddings of
  * a training batch, and its gradient.  Logits l_ij = scale <e_i, t_j> + bias;
  *  VL_HEAD_SOFTMAX (CLIP, Radford et al. 2021, Sec. 2.3): L = the mean of

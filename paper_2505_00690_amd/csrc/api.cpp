@@ -1484,6 +1484,58 @@ bool attention_plan(int32_t n, const int32_t* lens, bool resident, AttnPlan* ap,
   return true;
 }
 
+// The attention backward's descriptor region: sequences, then 64- and
+// 128-token blocks (16-byte aligned); then, each 256-byte aligned, the
+// log-sum-exp and D = rowsum(dO O) scratch [T, heads] FP32 and dO in BF16
+// [T, heads * head_dim].
+struct AttnBwdPlan {
+  std::vector<char> desc;
+  size_t off_items64 = 0, off_items128 = 0, off_lse = 0, off_dsum = 0, off_dob = 0, total = 0;
+  int n_items64 = 0, n_items128 = 0;
+  int64_t T = 0;
+};
+
+bool attention_bwd_plan(int32_t n, const int32_t* lens, int heads, int head_dim,
+                        AttnBwdPlan* bp, std::string* why) {
+  if (n <= 0 || n > kMaxItems) { *why = "n_seqs must be 1..65535"; return false; }
+  if (!lens) { *why = "lengths is NULL"; return false; }
+  std::vector<ImgDesc> seqs(n);
+  std::vector<AttnItem> it64, it128;
+  int64_t t = 0;
+  for (int i = 0; i < n; ++i) {
+    if (lens[i] < 1 || lens[i] > kMaxAttnLen) {
+      *why = "sequence " + std::to_string(i) + " has length " + std::to_string(lens[i]) +
+             ", not in 1..4096";
+      return false;
+    }
+    ImgDesc& d = seqs[i];
+    d.pix_off = 0;
+    d.H = d.W = d.gh = d.gw = 0;
+    d.tok_start = (int32_t)t;
+    d.ntok = lens[i];
+    for (int q0 = 0; q0 < lens[i]; q0 += 64) it64.push_back(AttnItem{i, q0});
+    for (int q0 = 0; q0 < lens[i]; q0 += 128) it128.push_back(AttnItem{i, q0});
+    t += lens[i];
+  }
+  if (t > (1LL << 24)) { *why = "more than 2^24 tokens"; return false; }
+  auto a16 = [](size_t x) { return (x + 15) / 16 * 16; };
+  bp->off_items64 = a16(sizeof(ImgDesc) * n);
+  bp->off_items128 = a16(bp->off_items64 + sizeof(AttnItem) * it64.size());
+  bp->desc.assign(bp->off_items128 + sizeof(AttnItem) * it128.size(), 0);
+  std::memcpy(bp->desc.data(), seqs.data(), sizeof(ImgDesc) * n);
+  std::memcpy(bp->desc.data() + bp->off_items64, it64.data(), sizeof(AttnItem) * it64.size());
+  std::memcpy(bp->desc.data() + bp->off_items128, it128.data(),
+              sizeof(AttnItem) * it128.size());
+  bp->n_items64 = (int)it64.size();
+  bp->n_items128 = (int)it128.size();
+  bp->T = t;
+  bp->off_lse = align_up(bp->desc.size());
+  bp->off_dsum = bp->off_lse + align_up(4 * (size_t)t * heads);
+  bp->off_dob = bp->off_dsum + align_up(4 * (size_t)t * heads);
+  bp->total = bp->off_dob + align_up(2 * (size_t)t * heads * head_dim);
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1537,6 +1589,57 @@ vl_status vl_attention(const void* qkv, vl_precision prec, const int32_t* length
     VL_HIP(attention_f32(static_cast<const float*>(qkv), static_cast<float*>(out), d_seqs,
                          d_items, ap.n_items, heads, head_dim, causal != 0, s));
   }
+  return VL_OK;
+}
+
+size_t vl_attention_backward_workspace_bytes(int32_t n_seqs, const int32_t* lengths,
+                                             int32_t heads, int32_t head_dim) {
+  if (heads < 1 || heads > 64 || (head_dim != 32 && head_dim != 64)) return 0;
+  AttnBwdPlan bp;
+  std::string why;
+  if (!attention_bwd_plan(n_seqs, lengths, heads, head_dim, &bp, &why)) return 0;
+  return bp.total;
+}
+
+vl_status vl_attention_backward(const void* qkv, const void* out, const float* d_out,
+                                vl_precision prec, const int32_t* lengths, int32_t n_seqs,
+                                int32_t heads, int32_t head_dim, void* d_qkv, void* ws,
+                                size_t ws_bytes, void* stream) {
+  if (!qkv || !out || !d_out || !d_qkv || !ws)
+    return fail(VL_ERR_INVALID_ARG, "qkv, out, d_out, d_qkv or workspace is NULL");
+  if (prec != VL_FP32 && prec != VL_BF16)
+    return fail(VL_ERR_INVALID_ARG, "precision must be VL_FP32 or VL_BF16");
+  if (heads < 1 || heads > 64) return fail(VL_ERR_INVALID_ARG, "heads must be 1..64");
+  if (head_dim != 32 && head_dim != 64) return fail(VL_ERR_UNSUPPORTED, "head_dim must be 32 or 64");
+  auto al = [](const void* p, uintptr_t k) { return reinterpret_cast<uintptr_t>(p) % k == 0; };
+  if (!al(qkv, 16) || !al(out, 16) || !al(d_out, 16) || !al(d_qkv, 16) || !al(ws, kAlign))
+    return fail(VL_ERR_INVALID_ARG,
+                "qkv, out, d_out and d_qkv must be 16-byte, the workspace 256-byte aligned");
+  AttnBwdPlan bp;
+  std::string why;
+  if (!attention_bwd_plan(n_seqs, lengths, heads, head_dim, &bp, &why))
+    return fail(VL_ERR_INVALID_ARG, why);
+  if (ws_bytes < bp.total) return fail(VL_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  {
+    static std::mutex mu;
+    static std::vector<Staging> ring(8);
+    static size_t pos = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    vl_status st = stage_copy(ring, pos, bp.desc.data(), bp.desc.size(), w, s);
+    if (st != VL_OK) return st;
+  }
+  const bool bf = prec == VL_BF16;
+  bf16_t* dob = reinterpret_cast<bf16_t*>(w + bp.off_dob);
+  if (bf) VL_HIP(convert_bf16(d_out, dob, (size_t)bp.T * heads * head_dim, s));
+  VL_HIP(attention_backward(qkv, out, bf, d_out, reinterpret_cast<const ImgDesc*>(w),
+                            reinterpret_cast<const AttnItem*>(w + bp.off_items64), bp.n_items64,
+                            reinterpret_cast<const AttnItem*>(w + bp.off_items128),
+                            bp.n_items128, heads, head_dim, d_qkv,
+                            reinterpret_cast<float*>(w + bp.off_lse),
+                            reinterpret_cast<float*>(w + bp.off_dsum), s, false,
+                            bf ? dob : nullptr));
   return VL_OK;
 }
 

@@ -31,6 +31,7 @@ __all__ = [
     "vl_model_load_tuning", "vl_contrastive_loss_noalloc", "VL_NOALLOC_SCRATCH_BYTES",
     "vl_train_workspace_bytes", "vl_encode_images_train", "vl_encode_images_backward", "Trainer",
     "vl_bf16_round", "vl_fp8_quantize_rows", "vl_model_graph_stats",
+    "vl_attention_backward_workspace_bytes", "vl_attention_backward",
 ]
 
 VL_FP32, VL_BF16, VL_FP8W_BF16A, VL_MXFP8 = 0, 1, 2, 3
@@ -57,6 +58,7 @@ EXPORTED_SYMBOLS = (
     "vl_model_set_tuning", "vl_model_autotune", "vl_model_save_tuning", "vl_model_load_tuning",
     "vl_contrastive_loss_noalloc", "vl_train_workspace_bytes", "vl_encode_images_train",
     "vl_encode_images_backward", "vl_bf16_round", "vl_fp8_quantize_rows", "vl_model_graph_stats",
+    "vl_attention_backward_workspace_bytes", "vl_attention_backward",
 )
 VL_NOALLOC_SCRATCH_BYTES = 64 << 20
 VL_N_GEMM_OPS, VL_N_M_BUCKETS = 5, 25
@@ -195,6 +197,11 @@ def lib() -> ctypes.CDLL:
     L.vl_attention.restype = ctypes.c_int
     L.vl_attention.argtypes = [_vp, ctypes.c_int, _pi32, _i32, _i32, _i32, _i32, _vp, _vp, _sz,
                                _vp]
+    L.vl_attention_backward_workspace_bytes.restype = _sz
+    L.vl_attention_backward_workspace_bytes.argtypes = [_i32, _pi32, _i32, _i32]
+    L.vl_attention_backward.restype = ctypes.c_int
+    L.vl_attention_backward.argtypes = [_vp, _vp, _vp, ctypes.c_int, _pi32, _i32, _i32, _i32,
+                                        _vp, _vp, _sz, _vp]
     L.vl_mx_gemm.restype = ctypes.c_int
     L.vl_mx_gemm.argtypes = [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _i32, _vp]
     L.vl_score.restype = ctypes.c_int
@@ -496,6 +503,45 @@ def vl_attention(qkv: torch.Tensor, lengths: Sequence[int], heads: int, head_dim
                               int(heads), int(head_dim), 1 if causal else 0, _ptr(out, None, "out"),
                               _ptr(workspace, None, "workspace"),
                               workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def vl_attention_backward_workspace_bytes(lengths: Sequence[int], heads: int,
+                                          head_dim: int) -> int:
+    return int(lib().vl_attention_backward_workspace_bytes(len(lengths), _i32_array(lengths),
+                                                           int(heads), int(head_dim)))
+
+
+def vl_attention_backward(qkv: torch.Tensor, out: torch.Tensor, d_out: torch.Tensor,
+                          lengths: Sequence[int], heads: int, head_dim: int,
+                          d_qkv: torch.Tensor, workspace: Optional[torch.Tensor] = None,
+                          stream=None) -> None:
+    """Backward of unmasked vl_attention: qkv [T, 3D] and its output out [T, D]
+    (BF16 or FP32), d_out [T, D] FP32 -> d_qkv [T, 3D] of qkv's dtype."""
+    T = sum(int(x) for x in lengths)
+    D = int(heads) * int(head_dim)
+    if qkv.dtype not in (torch.bfloat16, torch.float32):
+        raise ValueError("qkv must be bfloat16 or float32")
+    if tuple(qkv.shape) != (T, 3 * D):
+        raise ValueError(f"qkv must be [{T}, {3 * D}], got {tuple(qkv.shape)}")
+    if tuple(out.shape) != (T, D) or out.dtype != qkv.dtype:
+        raise ValueError(f"out must be [{T}, {D}] {qkv.dtype}")
+    if tuple(d_out.shape) != (T, D) or d_out.dtype != torch.float32:
+        raise ValueError(f"d_out must be [{T}, {D}] float32")
+    if tuple(d_qkv.shape) != (T, 3 * D) or d_qkv.dtype != qkv.dtype:
+        raise ValueError(f"d_qkv must be [{T}, {3 * D}] {qkv.dtype}")
+    prec = VL_BF16 if qkv.dtype == torch.bfloat16 else VL_FP32
+    nb = vl_attention_backward_workspace_bytes(lengths, heads, head_dim)
+    if nb == 0:
+        raise VlError(1, "invalid sequence lengths, heads or head_dim")
+    if workspace is None:
+        workspace = torch.empty(nb, dtype=torch.uint8, device=qkv.device)
+    elif workspace.numel() * workspace.element_size() < nb:
+        raise ValueError("workspace too small")
+    _check(lib().vl_attention_backward(
+        _ptr(qkv, None, "qkv"), _ptr(out, None, "out"), _ptr(d_out, torch.float32, "d_out"), prec,
+        _i32_array(lengths), len(lengths), int(heads), int(head_dim), _ptr(d_qkv, None, "d_qkv"),
+        _ptr(workspace, None, "workspace"), workspace.numel() * workspace.element_size(),
+        _stream(stream)))
 
 
 def vl_mx_quantize(src: torch.Tensor, codes_out: torch.Tensor, scales_out: torch.Tensor,

@@ -154,6 +154,35 @@ def test_attention_entry_point_validates_on_host(V):
     assert f(p, 1, (ctypes.c_int32 * 2)(65, 0), 2, 4, 64, 0, p, p, nb, None) == 1
 
 
+def test_attention_backward_entry_point_validates_on_host(V):
+    """vl_attention_backward's documented constraints, each checked on its
+    own, and its workspace size from its parts."""
+    lib = V.lib()
+    p = ctypes.c_void_p(256)
+    L = (ctypes.c_int32 * 2)(65, 577)
+    T, heads, d = 642, 4, 64
+    nb = lib.vl_attention_backward_workspace_bytes(2, L, heads, d)
+    up = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    # descriptors (2 x 32 B, (2 + 10) 64-token and (1 + 5) 128-token blocks
+    # of 8 B), log-sum-exp and D [T, heads] FP32, dO in BF16 [T, heads d]
+    want = up(64 + 12 * 8 + 6 * 8) + 2 * up(4 * T * heads) + up(2 * T * heads * d)
+    assert nb == want, (nb, want)
+    assert lib.vl_attention_backward_workspace_bytes(0, L, heads, d) == 0
+    assert lib.vl_attention_backward_workspace_bytes(2, L, 0, d) == 0
+    assert lib.vl_attention_backward_workspace_bytes(2, L, heads, 48) == 0
+    assert lib.vl_attention_backward_workspace_bytes(1, (ctypes.c_int32 * 1)(4097), heads, d) == 0
+    f = lambda *a: lib.vl_attention_backward(*a)  # noqa: E731
+    assert f(p, p, p, 1, L, 2, 0, 64, p, p, nb, None) == 1       # heads
+    assert f(p, p, p, 1, L, 2, 65, 64, p, p, nb, None) == 1      # heads <= 64
+    assert f(p, p, p, 1, L, 2, 4, 48, p, p, nb, None) == 2       # head_dim 32 / 64
+    assert f(p, p, p, 2, L, 2, 4, 64, p, p, nb, None) == 1       # precision
+    assert f(p, None, p, 1, L, 2, 4, 64, p, p, nb, None) == 1    # O
+    assert f(p, p, ctypes.c_void_p(260), 1, L, 2, 4, 64, p, p, nb, None) == 1   # dO alignment
+    assert f(p, p, p, 1, L, 2, 4, 64, p, ctypes.c_void_p(384), nb, None) == 1   # ws alignment
+    assert f(p, p, p, 1, L, 2, 4, 64, p, p, nb - 1, None) == 3   # workspace too small
+    assert f(p, p, p, 1, (ctypes.c_int32 * 2)(65, 0), 2, 4, 64, p, p, nb, None) == 1
+
+
 def test_tuning_file_entry_points_validate_on_host(V, tmp_path):
     lib = V.lib()
     assert lib.vl_model_save_tuning(None, str(tmp_path / "t.json").encode()) == 1
