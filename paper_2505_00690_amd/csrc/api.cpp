@@ -1823,7 +1823,10 @@ namespace {
 
 // Workspace of a training forward + backward: the one-part encode plan, then
 // per block the activations the backward reads, then the backward's scratch.
-struct TrainLayer { size_t xin, y1, qkv, o, h, y2, z1, lse; };
+// Kept per block: input x, LN1 output, QKV, attention output, post-attention
+// residual h, LN2 output, FC1 pre-activation z1 (FP32), the forward
+// attention's log-sum-exp and (BF16 models) GELU(z1) as FC2 read it.
+struct TrainLayer { size_t xin, y1, qkv, o, h, y2, z1, lse, g = 0; };
 struct TrainPlan {
   Plan p;
   size_t off_items64 = 0;   // 64-token attention blocks (dK / dV), in the descriptor region
@@ -1903,6 +1906,7 @@ bool make_train_plan(const vl_model* m, int32_t n, const int32_t* hs, const int3
     l.xin = take(4 * T * D); l.y1 = take(es * T * D); l.qkv = take(es * 3 * T * D);
     l.o = take(es * T * D); l.h = take(4 * T * D); l.y2 = take(es * T * D); l.z1 = take(4 * T * F);
     l.lse = take(4 * T * m->heads);   // the forward attention's log-sum-exp (BF16)
+    if (es == 2) l.g = take(2 * T * F);
   }
   const size_t wide = std::max<size_t>({3 * D, F, (size_t)m->Kpad});
   tp->dX = take(4 * T * D);
@@ -2036,11 +2040,12 @@ vl_status run_train_forward(vl_model* m, const TrainPlan& tp, const float* pix, 
       VL_HIP(gemm_f32(static_cast<const float*>(QH), F, static_cast<const float*>(ly.fc2_w), F, T,
                       D, F, OP_FC2, e4, s));
     } else {
-      e3.out2 = QH;   // GELU(z1) in BF16 from the same epilogue
+      // GELU(z1) in BF16 from the same epilogue, kept for the backward
+      bf16_t* g = reinterpret_cast<bf16_t*>(ws + sv.g);
+      e3.out2 = g;
       VL_HIP(gemm_bf16(static_cast<const bf16_t*>(y2), D, ly.fc1_w, D, false, T, F, D, OP_FC1_PRE,
                        gemm_cfg_for(m, 3, T), e3, s));
-      VL_HIP(gemm_bf16(static_cast<const bf16_t*>(QH), F, ly.fc2_w, F, false, T, D, F, OP_FC2,
-                       gemm_cfg_for(m, 4, T), e4, s));
+      VL_HIP(gemm_bf16(g, F, ly.fc2_w, F, false, T, D, F, OP_FC2, gemm_cfg_for(m, 4, T), e4, s));
     }
   }
   VL_HIP(pool_project(X, d_imgs, p.n, m->lnf_g, m->lnf_b, eps, m->proj, D, m->Pd, false,
@@ -2184,9 +2189,11 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
     // ---- FC2: x_out = h + GELU(z1) W2^T + b2
     if ((st = prep_dx()) != VL_OK) return st;
     VL_HIP(transpose_rows(ly.fc2_w, bf, D, F, F, Wt, bf, D, s));                 // W2^T [F, D]
-    if (bf) {   // dz1 = (dX W2) GELU'(z1) and g = GELU(z1) from the GEMM's epilogue
+    // g = GELU(z1): kept by the forward (BF16), formed again here (FP32)
+    void* g = bf ? static_cast<void*>(ws + sv.g) : QH;
+    if (bf) {   // dz1 = (dX W2) GELU'(z1) from the GEMM's epilogue
       EpiArgs eg;
-      eg.out = dZ; eg.out2 = QH; eg.aux = reinterpret_cast<const float*>(ws + sv.z1); eg.ldo = F;
+      eg.out = dZ; eg.aux = reinterpret_cast<const float*>(ws + sv.z1); eg.ldo = F;
       VL_HIP(gemm_bf16(static_cast<const bf16_t*>(dXb), D, Wt, D, false, T, F, D, OP_DGELU, -1,
                        eg, s));
     } else {
@@ -2195,9 +2202,9 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
                            (size_t)T * F, s));                                   // dz1, g
     }
     if (km) {
-      st = wgrad_gemm_km(tp, ws, dXb, D, QH, F, D, F, G(go.fc2_w), s);
+      st = wgrad_gemm_km(tp, ws, dXb, D, g, F, D, F, G(go.fc2_w), s);
     } else {
-      VL_HIP(transpose_rows(QH, bf, T, F, F, actT, bf, Tp, s));                  // g^T
+      VL_HIP(transpose_rows(g, bf, T, F, F, actT, bf, Tp, s));                   // g^T
       st = wgrad_gemm(m, tp, ws, gT, actT, D, F, G(go.fc2_w), s);
     }
     if (st != VL_OK) return st;

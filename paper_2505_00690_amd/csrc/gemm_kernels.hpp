@@ -40,9 +40,9 @@ __device__ __forceinline__ float ln_fold1(float v, float ws, float c1, float c2,
   return __builtin_fmaf(rstd, __builtin_fmaf(v, ws, -(mu * c1)), c2);
 }
 
-// GELU backward of four columns (OP_DGELU): dz = dg (Phi(z) + z phi(z)) and
-// g = GELU(z), Phi from the forward's polynomial (so g has the forward's
-// bits), phi = exp(-z^2 / 2) / sqrt(2 pi); both stored as BF16.
+// GELU backward of four columns (OP_DGELU): dz = dg (Phi(z) + z phi(z)) and,
+// with out2, g = GELU(z), Phi from the forward's polynomial (so g has the
+// forward's bits), phi = exp(-z^2 / 2) / sqrt(2 pi); both stored as BF16.
 __device__ __forceinline__ void dgelu_store4(const EpiArgs& e, int m, int n, float4 dg,
                                              float4 z) {
   const float zz[4] = {z.x, z.y, z.z, z.w}, dd[4] = {dg.x, dg.y, dg.z, dg.w};
@@ -60,9 +60,11 @@ __device__ __forceinline__ void dgelu_store4(const EpiArgs& e, int m, int n, flo
   pk.x = pack_bf16x2(dz[0], dz[1]);
   pk.y = pack_bf16x2(dz[2], dz[3]);
   *reinterpret_cast<u32x2*>(static_cast<bf16_t*>(e.out) + o) = pk;
-  pk.x = pack_bf16x2(gg[0], gg[1]);
-  pk.y = pack_bf16x2(gg[2], gg[3]);
-  *reinterpret_cast<u32x2*>(static_cast<bf16_t*>(e.out2) + o) = pk;
+  if (e.out2) {
+    pk.x = pack_bf16x2(gg[0], gg[1]);
+    pk.y = pack_bf16x2(gg[2], gg[3]);
+    *reinterpret_cast<u32x2*>(static_cast<bf16_t*>(e.out2) + o) = pk;
+  }
 }
 
 // BF16 GELU of an FP32 pre-activation into out2 (OP_FC1_PRE with out2).

@@ -23,7 +23,8 @@ namespace vl {
 //               with out2 also GELU of it in BF16 [M, ldo], as OP_FC1 forms it)
 //   OP_DGELU  : the FC2 input gradient through the GELU (BF16 GEMMs): with
 //               z = aux[m,n] (the kept FC1 pre-activation, FP32),
-//               out = acc * GELU'(z) and out2 = GELU(z), both BF16 [M, ldo]
+//               out = acc * GELU'(z) and, with out2, out2 = GELU(z), both
+//               BF16 [M, ldo]
 enum GemmOp { OP_PATCH = 0, OP_QKV = 1, OP_OPROJ = 2, OP_FC1 = 3, OP_FC2 = 4, OP_LOGITS = 5,
               OP_FC1_PRE = 6, OP_DGELU = 7 };
 
