@@ -254,7 +254,10 @@ def top1_agreement(top_a: np.ndarray, top_ref: np.ndarray, emb_a: np.ndarray,
     return {"images": int(len(agree)), "raw": float(agree.mean()),
             "certified_images": int(cert.sum()),
             "certified_agree": float(agree[cert].mean()) if cert.any() else None,
-            "vs": "fp32 GPU path"}
+            "vs": "fp32 GPU path",
+            "note": "random unit texts: most top-1/top-2 logit gaps lie below the change the "
+                    "BF16 embedding error can make, so raw agreement measures ties; only "
+                    "certified images are decided by the model"}
 
 
 def text_leg(torch, vl, n_texts: int, steps: int, seed: int = 3002, split: bool = True):
