@@ -267,8 +267,8 @@ hipError_t gelu_forward(const float* z, void* g, bool g_bf16, size_t n, hipStrea
 hipError_t gelu_backward(const float* dg, const float* z, void* dz, void* g, bool bf16, size_t n,
                          hipStream_t s);
 // dQKV [T, 3D] of the attention of every image: items64 are (image, first
-// token) blocks of 64 tokens (dK / dV), items128 blocks of 128 tokens (dQ,
-// BF16 only); lse and dsum [T, heads] are scratch, except
+// token) blocks of 64 tokens (FP32 kernels), items128 blocks of 128 tokens
+// (BF16 kernels); lse and dsum [T, heads] are scratch, except
 // that with lse_given (BF16) lse already holds the forward's log-sum-exp
 // (attention_bf16's lse_out) and is only read.  BF16 models also pass dO
 // rounded to BF16 (dO_bf16 [T, D]), from which the dK/dV pass loads its tiles.

@@ -611,11 +611,11 @@ __global__ __launch_bounds__(256) void k_attn_bwd_dkv(const T* __restrict__ qkv,
 //
 // dq kernel (below): four waves own 128 queries, key / value tiles stream
 // through LDS; dS^T = P^T (dP^T - D) and dQ^T += K^T dS^T with K^T read
-// transposed from the key tile.  dkv kernel: two waves own 64 keys (lane: one key, K and
-// V rows in registers); per 64-query tile (Q and dO in LDS) S = Q K^T, dP =
-// dO V^T, P, dS, then dV^T += dO^T P and dK^T += Q^T dS with dO^T and Q^T
-// read transposed.  FP32 accumulation; P and dS rounded to BF16 as MFMA
-// operands; dO rounded to BF16 where it is an MFMA operand.
+// transposed from the key tile.  dkv kernel: four waves own 128 keys (lane:
+// one key, K and V rows in registers); per 64-query tile (Q and dO in LDS)
+// S = Q K^T, dP = dO V^T, P, dS, then dV^T += dO^T P and dK^T += Q^T dS with
+// dO^T and Q^T read transposed.  FP32 accumulation; P and dS rounded to BF16
+// as MFMA operands; dO rounded to BF16 where it is an MFMA operand.
 template <int HD>
 struct TrTile {   // row-major 64 x HD BF16 tile; chunk c of row r at c ^ f(r)
   static constexpr int NCH = HD / 8;
