@@ -134,6 +134,9 @@ struct vl_model {
   bool kmajor_wgrad = true;   // BF16 weight gradients from token-major operands
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // Training backward: ordering between the caller's stream and the side
+  // stream that runs the weight-gradient GEMMs (see run_backward).
+  hipEvent_t tev[10] = {};
   int32_t tuning[VL_N_GEMM_OPS][VL_N_M_BUCKETS];
   // The last vl_encode_images_train call (workspace, pixels, shapes): the
   // backward pass must be given the same, since it reads what that forward
@@ -925,6 +928,8 @@ void vl_model_destroy(vl_model* m) {
   if (m->side) (void)hipStreamDestroy(m->side);
   if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
   if (m->ev_join) (void)hipEventDestroy(m->ev_join);
+  for (hipEvent_t e : m->tev)
+    if (e) (void)hipEventDestroy(e);
   if (m->wmem) (void)hipFree(m->wmem);
   delete m;
 }
@@ -1836,6 +1841,7 @@ struct TrainPlan {
   int Tp = 0;               // T rounded up to 64 (K of the weight-gradient GEMMs)
   std::vector<TrainLayer> layers;
   size_t dX, dXb, gT, actT, dGf, dZ, dY, Wt, lse, dsum, part, pg, pb, de, zp, ppg, ppb, dwf;
+  size_t dOb = 0;   // dO of the attention in BF16 (BF16 models)
   size_t wsplit = 0, wsplit_bytes = 0;   // split-K partial products of the weight gradients
   size_t total = 0;
 };
@@ -1911,6 +1917,7 @@ bool make_train_plan(const vl_model* m, int32_t n, const int32_t* hs, const int3
   const size_t wide = std::max<size_t>({3 * D, F, (size_t)m->Kpad});
   tp->dX = take(4 * T * D);
   tp->dXb = es == 2 ? take(es * T * D) : tp->dX;
+  if (es == 2) tp->dOb = take(es * T * D);
   tp->gT = take(es * std::max<size_t>(3 * D, F) * Tp);
   tp->actT = take(es * std::max<size_t>({D, F, (size_t)m->Kpad}) * Tp);
   tp->dGf = take(4 * T * F);
@@ -2121,14 +2128,24 @@ vl_status wgrad_gemm_km(const TrainPlan& tp, char* ws, const void* A, int lda, c
   return VL_OK;
 }
 
+// Events of the overlapped backward (indices into vl_model::tev): recorded on
+// the caller's stream when an operand of a weight gradient is ready, and on
+// the side stream when a weight gradient has read its operands.
+enum TrainEvent { kEvDxFc2, kEvDzFc1, kEvDxO, kEvDzQkv, kEvWFc2, kEvWFc1, kEvWO, kEvWQkv,
+                  kEvFork, kEvJoin };
+
 // The backward pass, block by block in reverse.  dX is the gradient of the
 // residual stream; every linear layer's input gradient is a GEMM against the
 // transposed weight and its weight gradient a GEMM over the tokens (K = T,
 // zero-padded to a multiple of 64) of transposed operands; in the BF16 model
 // the GEMM operands (dX, dGELU, dQKV and the kept activations) are BF16 and
-// the accumulation FP32.
-vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const float* demb,
-                       float* grads, char* ws, hipStream_t s) {
+// the accumulation FP32.  With a side stream (K-major weight gradients), the
+// four weight-gradient GEMMs of each block run there, overlapped with the
+// input-gradient chain on s; s waits before it overwrites an operand they
+// read (dX's BF16 copy, dZ), and the split-K partial buffer is used on the
+// side stream only.
+vl_status run_backward_body(vl_model* m, const TrainPlan& tp, const float* pix, const float* demb,
+                            float* grads, char* ws, hipStream_t s, hipStream_t side) {
   const Part& p = tp.p.parts[0];
   const bool f32 = m->prec == VL_FP32, bf = !f32;
   const ImgDesc* d_imgs = reinterpret_cast<const ImgDesc*>(ws + p.off_imgs);
@@ -2165,6 +2182,17 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
   // BF16 copy) but write no transposed matrix.
   const bool km = bf && m->kmajor_wgrad && D % 256 == 0 && F % 256 == 0;
   void* gTo = km ? nullptr : gT;
+  const bool ovl = km && side != nullptr;
+  hipStream_t sw = ovl ? side : s;   // the weight gradients' stream
+  auto rec = [&](int i, hipStream_t st) -> vl_status {
+    if (ovl) VL_HIP(hipEventRecord(m->tev[i], st));
+    return VL_OK;
+  };
+  auto wait = [&](hipStream_t st, int i) -> vl_status {
+    if (ovl) VL_HIP(hipStreamWaitEvent(st, m->tev[i], 0));
+    return VL_OK;
+  };
+  void* dOb = bf ? static_cast<void*>(ws + tp.dOb) : nullptr;
   // dX in the GEMM operand type (BF16 copy, or dX itself) and transposed; in
   // BF16 models one pass forms the transpose, the copy and the column-sum
   // partials of dX for the bias gradient.
@@ -2187,8 +2215,12 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
     const BlobOffsets::L& go = bo.layers[l];
     vl_status st;
     // ---- FC2: x_out = h + GELU(z1) W2^T + b2
+    const bool later = l < m->L - 1;   // the previous block's weight gradients may still read
+    if (later && (st = wait(s, kEvWO)) != VL_OK) return st;        // ... dX's copy
     if ((st = prep_dx()) != VL_OK) return st;
+    if ((st = rec(kEvDxFc2, s)) != VL_OK) return st;
     VL_HIP(transpose_rows(ly.fc2_w, bf, D, F, F, Wt, bf, D, s));                 // W2^T [F, D]
+    if (later && (st = wait(s, kEvWQkv)) != VL_OK) return st;      // ... and dZ
     // g = GELU(z1): kept by the forward (BF16), formed again here (FP32)
     void* g = bf ? static_cast<void*>(ws + sv.g) : QH;
     if (bf) {   // dz1 = (dX W2) GELU'(z1) from the GEMM's epilogue
@@ -2201,8 +2233,11 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
       VL_HIP(gelu_backward(dGf, reinterpret_cast<const float*>(ws + sv.z1), dZ, QH, bf,
                            (size_t)T * F, s));                                   // dz1, g
     }
+    if ((st = rec(kEvDzFc1, s)) != VL_OK) return st;   // dZ of FC1 ready
     if (km) {
-      st = wgrad_gemm_km(tp, ws, dXb, D, g, F, D, F, G(go.fc2_w), s);
+      if ((st = wait(sw, kEvDxFc2)) != VL_OK) return st;
+      st = wgrad_gemm_km(tp, ws, dXb, D, g, F, D, F, G(go.fc2_w), sw);
+      if (st == VL_OK) st = rec(kEvWFc2, sw);
     } else {
       VL_HIP(transpose_rows(g, bf, T, F, F, actT, bf, Tp, s));                   // g^T
       st = wgrad_gemm(m, tp, ws, gT, actT, D, F, G(go.fc2_w), s);
@@ -2214,7 +2249,9 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
     if ((st = gemm_into_f32(m, dZ, F, Wt, F, T, D, F, dY, D, s)) != VL_OK) return st;
     VL_HIP(transpose_rows(dZ, bf, T, F, F, gTo, bf, Tp, s, bf ? part : nullptr));
     if (km) {
-      st = wgrad_gemm_km(tp, ws, dZ, F, ws + sv.y2, D, F, D, G(go.fc1_w), s);
+      if ((st = wait(sw, kEvDzFc1)) != VL_OK) return st;
+      st = wgrad_gemm_km(tp, ws, dZ, F, ws + sv.y2, D, F, D, G(go.fc1_w), sw);
+      if (st == VL_OK) st = rec(kEvWFc1, sw);
     } else {
       VL_HIP(transpose_rows(ws + sv.y2, bf, T, D, D, actT, bf, Tp, s));
       st = wgrad_gemm(m, tp, ws, gT, actT, F, D, G(go.fc1_w), s);
@@ -2225,11 +2262,15 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
     VL_HIP(layernorm_backward(reinterpret_cast<const float*>(ws + sv.h), ly.ln2_g, dY, eps, dX, T,
                               D, pg, pb, G(go.ln2_g), G(go.ln2_b), s));
     // ---- output projection: h = x + O Wo^T + bo
+    if ((st = wait(s, kEvWFc2)) != VL_OK) return st;   // FC2's weight gradient read dX's copy
     if ((st = prep_dx()) != VL_OK) return st;
+    if ((st = rec(kEvDxO, s)) != VL_OK) return st;
     VL_HIP(transpose_rows(ly.o_w, bf, D, D, D, Wt, bf, D, s));
     if ((st = gemm_into_f32(m, dXb, D, Wt, D, T, D, D, dY, D, s)) != VL_OK) return st;   // dO
     if (km) {
-      st = wgrad_gemm_km(tp, ws, dXb, D, ws + sv.o, D, D, D, G(go.o_w), s);
+      if ((st = wait(sw, kEvDxO)) != VL_OK) return st;
+      st = wgrad_gemm_km(tp, ws, dXb, D, ws + sv.o, D, D, D, G(go.o_w), sw);
+      if (st == VL_OK) st = rec(kEvWO, sw);
     } else {
       VL_HIP(transpose_rows(ws + sv.o, bf, T, D, D, actT, bf, Tp, s));
       st = wgrad_gemm(m, tp, ws, gT, actT, D, D, G(go.o_w), s);
@@ -2237,21 +2278,25 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
     if (st != VL_OK) return st;
     if ((st = bias_grad(dX, false, D, G(go.o_b))) != VL_OK) return st;
     // ---- attention
-    // (BF16: the log-sum-exp the forward kept, and dO also in BF16, in the
-    // dX operand buffer, free until the next block's; FP32: recomputed)
-    if (bf) VL_HIP(convert_bf16(dY, static_cast<bf16_t*>(dXb), (size_t)T * D, s));
+    // (BF16: the log-sum-exp the forward kept, and dO also in BF16; FP32:
+    // recomputed)
+    if (bf) VL_HIP(convert_bf16(dY, static_cast<bf16_t*>(dOb), (size_t)T * D, s));
+    if ((st = wait(s, kEvWFc1)) != VL_OK) return st;   // FC1's weight gradient read dZ
     VL_HIP(attention_backward(ws + sv.qkv, ws + sv.o, bf, dY, d_imgs, d_items64, tp.n_items64,
                               d_items128, tp.n_items128,
                               m->heads, m->hd, dZ,
                               reinterpret_cast<float*>(ws + (bf ? sv.lse : tp.lse)),
                               reinterpret_cast<float*>(ws + tp.dsum), s, bf,
-                              bf ? static_cast<const bf16_t*>(dXb) : nullptr));
+                              bf ? static_cast<const bf16_t*>(dOb) : nullptr));
+    if ((st = rec(kEvDzQkv, s)) != VL_OK) return st;
     // ---- QKV: [q|k|v] = y1 Wqkv^T + bqkv
     VL_HIP(transpose_rows(ly.qkv_w, bf, 3 * D, D, D, Wt, bf, 3 * D, s));         // [D, 3D]
     if ((st = gemm_into_f32(m, dZ, 3 * D, Wt, 3 * D, T, D, 3 * D, dY, D, s)) != VL_OK) return st;
     VL_HIP(transpose_rows(dZ, bf, T, 3 * D, 3 * D, gTo, bf, Tp, s, bf ? part : nullptr));
     if (km) {
-      st = wgrad_gemm_km(tp, ws, dZ, 3 * D, ws + sv.y1, D, 3 * D, D, G(go.qkv_w), s);
+      if ((st = wait(sw, kEvDzQkv)) != VL_OK) return st;
+      st = wgrad_gemm_km(tp, ws, dZ, 3 * D, ws + sv.y1, D, 3 * D, D, G(go.qkv_w), sw);
+      if (st == VL_OK) st = rec(kEvWQkv, sw);
     } else {
       VL_HIP(transpose_rows(ws + sv.y1, bf, T, D, D, actT, bf, Tp, s));
       st = wgrad_gemm(m, tp, ws, gT, actT, 3 * D, D, G(go.qkv_w), s);
@@ -2263,6 +2308,12 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
                               T, D, pg, pb, G(go.ln1_g), G(go.ln1_b), s));
   }
   // ---- token embedding: patches (gathered again), class token, positions
+  // (after every weight gradient of the side stream: the split-K partials)
+  if (ovl) {
+    vl_status sj = rec(kEvJoin, side);
+    if (sj == VL_OK) sj = wait(s, kEvJoin);
+    if (sj != VL_OK) return sj;
+  }
   VL_HIP(im2col(pix, d_imgs, p.n, p.max_ntok, m->cfg.channels, m->P, m->Kpad, QH, bf, tok, s));
   VL_HIP(transpose_rows(dX, false, T, D, D, gT, bf, Tp, s));
   VL_HIP(transpose_rows(QH, bf, T, m->Kpad, m->Kpad, actT, bf, Tp, s));
@@ -2280,6 +2331,27 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
   VL_HIP(embed_backward(dX, d_imgs, p.n, D, 1 + m->g0 * m->g0, dwf, m->Kpad, G(bo.patch_b), cn,
                         m->Kpe, m->P * m->P, G(bo.pos), G(bo.cls), G(bo.patch_w), s));
   return VL_OK;
+}
+
+// The backward on the caller's stream s; with K-major weight gradients the
+// model's side stream takes them (forked after everything before this call
+// on s, joined back into s before returning, also after an error).
+vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const float* demb,
+                       float* grads, char* ws, hipStream_t s) {
+  const bool km = m->prec == VL_BF16 && m->kmajor_wgrad && m->D % 256 == 0 && m->F % 256 == 0;
+  hipStream_t side = nullptr;
+  if (km) {
+    if (!m->side) VL_HIP(hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking));
+    for (hipEvent_t& e : m->tev)
+      if (!e) VL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    VL_HIP(hipEventRecord(m->tev[kEvFork], s));
+    VL_HIP(hipStreamWaitEvent(m->side, m->tev[kEvFork], 0));
+    side = m->side;
+  }
+  const vl_status st = run_backward_body(m, tp, pix, demb, grads, ws, s, side);
+  if (side && hipEventRecord(m->tev[kEvJoin], side) == hipSuccess)
+    (void)hipStreamWaitEvent(s, m->tev[kEvJoin], 0);
+  return st;
 }
 
 vl_status check_train_args(vl_model* m, const float* pix, const void* a, const void* ws,
