@@ -342,7 +342,7 @@ def train_leg(torch, vl, steps: int, model: str = "l14", res: int = 336, batch: 
     imgs = synth.make_images(sizes, i_seed, channels=c.channels)
     pix = torch.from_numpy(np.concatenate([im.reshape(-1) for im in imgs])).cuda()
     texts = torch.from_numpy(synth.make_texts(batch, c.proj_dim, t_seed)).cuda()
-    tr = vl.Trainer(c, w, "bf16")
+    tr = vl.Trainer(c, w, "bf16", split=True)   # the forward as two overlapped halves
     del w
     emb = torch.empty((batch, c.proj_dim), dtype=torch.float32, device="cuda")
     grads = torch.empty(vl.vl_weights_count(c), dtype=torch.float32, device="cuda")

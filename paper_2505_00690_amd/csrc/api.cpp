@@ -1842,6 +1842,17 @@ struct TrainPlan {
   std::vector<TrainLayer> layers;
   size_t dX, dXb, gT, actT, dGf, dZ, dY, Wt, lse, dsum, part, pg, pb, de, zp, ppg, ppb, dwf;
   size_t dOb = 0;   // dO of the attention in BF16 (BF16 models)
+  // The training forward as two halves of consecutive images on two streams
+  // (VL_OPT_SPLIT, BF16): each half's descriptors (token starts relative to
+  // the half) in the descriptor region, its rows / images at t0 / i0 of the
+  // whole-batch buffers.  Empty: one pass over the batch.
+  struct Half {
+    int i0 = 0, n = 0, t0 = 0, T = 0, max_ntok = 0, n_items = 0, n_res = 0, res_tiles = 0;
+    size_t off_imgs = 0, off_items = 0, off_res = 0;
+  };
+  std::vector<Half> halves;
+  size_t off_split = 0;
+  size_t zscr = 0;  // pooled rows [n, D] (final LayerNorm scratch of the forward)
   size_t wsplit = 0, wsplit_bytes = 0;   // split-K partial products of the weight gradients
   size_t total = 0;
 };
@@ -1888,7 +1899,27 @@ bool make_train_plan(const vl_model* m, int32_t n, const int32_t* hs, const int3
   tp->off_items64 = (p.desc_bytes + 15) / 16 * 16;
   tp->n_items128 = (int)it2.size();
   tp->off_items128 = tp->off_items64 + sizeof(AttnItem) * it.size();
-  const size_t new_desc = tp->off_items128 + sizeof(AttnItem) * it2.size();
+  size_t new_desc = tp->off_items128 + sizeof(AttnItem) * it2.size();
+  // Two halves for the forward: the split planner's parts, their descriptor
+  // blob appended here.
+  Plan sp;
+  std::string why2;
+  tp->halves.clear();
+  if (m->prec == VL_BF16 && make_plan(m, n, hs, ws, &sp, &why2) && sp.parts.size() == 2) {
+    const size_t base = (new_desc + 15) / 16 * 16;
+    int t0 = 0;
+    for (const Part& q : sp.parts) {
+      TrainPlan::Half h;
+      h.i0 = q.i0; h.n = q.n; h.t0 = t0; h.T = q.T; h.max_ntok = q.max_ntok;
+      h.n_items = q.n_items; h.n_res = q.n_res; h.res_tiles = q.res_tiles;
+      h.off_imgs = base + q.off_imgs; h.off_items = base + q.off_items;
+      h.off_res = base + q.off_res;
+      tp->halves.push_back(h);
+      t0 += q.T;
+    }
+    tp->off_split = base;
+    new_desc = base + sp.desc_bytes;
+  }
   if (align_up(new_desc) > align_up(p.desc_bytes)) {
     // the activation regions start after the descriptor region: move them
     const size_t shift = align_up(new_desc) - align_up(p.desc_bytes);
@@ -1900,6 +1931,7 @@ bool make_train_plan(const vl_model* m, int32_t n, const int32_t* hs, const int3
   p.desc.resize(new_desc, 0);
   std::memcpy(p.desc.data() + tp->off_items64, it.data(), sizeof(AttnItem) * it.size());
   std::memcpy(p.desc.data() + tp->off_items128, it2.data(), sizeof(AttnItem) * it2.size());
+  if (!tp->halves.empty()) std::memcpy(p.desc.data() + tp->off_split, sp.desc.data(), sp.desc_bytes);
   p.desc_bytes = new_desc;
 
   const size_t T = p.T, D = m->D, F = m->F, es = m->prec == VL_FP32 ? 4 : 2;
@@ -1918,6 +1950,7 @@ bool make_train_plan(const vl_model* m, int32_t n, const int32_t* hs, const int3
   tp->dX = take(4 * T * D);
   tp->dXb = es == 2 ? take(es * T * D) : tp->dX;
   if (es == 2) tp->dOb = take(es * T * D);
+  tp->zscr = take(4 * (size_t)n * D);
   tp->gT = take(es * std::max<size_t>(3 * D, F) * Tp);
   tp->actT = take(es * std::max<size_t>({D, F, (size_t)m->Kpad}) * Tp);
   tp->dGf = take(4 * T * F);
@@ -1976,29 +2009,37 @@ vl_status gemm_into_f32(const vl_model* m, const void* A, int lda, const void* B
 // after attention and FC1 pre-activation.  Every kernel and its arithmetic is
 // the inference forward's, so the embeddings agree with vl_encode_images
 // bitwise.
-vl_status run_train_forward(vl_model* m, const TrainPlan& tp, const float* pix, float* emb,
-                            char* ws, hipStream_t s) {
-  const Plan& pl = tp.p;
-  const Part& p = pl.parts[0];
+// A run of consecutive images of a training batch: its rows t0 .. t0+T-1
+// and images i0 .. i0+n-1 of the whole-batch buffers, with descriptors
+// whose token starts are relative to t0.
+struct FwdRange {
+  int i0 = 0, n = 0, t0 = 0, T = 0, max_ntok = 0, n_items = 0, n_res = 0, res_tiles = 0;
+  const ImgDesc* imgs = nullptr;
+  const AttnItem* items = nullptr;
+  const int* res = nullptr;
+};
+
+vl_status train_forward_range(vl_model* m, const TrainPlan& tp, const float* pix, float* emb,
+                              char* ws, const FwdRange& r, hipStream_t s) {
+  const Part& p = tp.p.parts[0];
   const bool f32 = m->prec == VL_FP32;
-  const ImgDesc* d_imgs = reinterpret_cast<const ImgDesc*>(ws + p.off_imgs);
-  const AttnItem* d_items = reinterpret_cast<const AttnItem*>(ws + p.off_items);
-  int2* tok = reinterpret_cast<int2*>(ws + p.off_tok);
-  float* X = reinterpret_cast<float*>(ws + p.off_X);
-  void* QH = ws + p.off_QH;
-  const int T = p.T, D = m->D, F = m->F;
+  const size_t es = f32 ? 4 : 2;
+  const int T = r.T, D = m->D, F = m->F, t0 = r.t0;
   const float eps = m->cfg.ln_eps;
+  int2* tok = reinterpret_cast<int2*>(ws + p.off_tok) + t0;
+  float* X = reinterpret_cast<float*>(ws + p.off_X) + (size_t)t0 * D;
+  void* QH = ws + p.off_QH + es * (size_t)t0 * m->Kpad;   // this range's patch rows
   // The residual stream is written straight into the kept per-block
   // buffers: block l reads its input from xin_l, the output projection
   // writes h_l = xin_l + ..., FC2 writes xin_{l+1} = h_l + ... (X after the
   // last block), so nothing is copied.
   auto xin_of = [&](int l) {
-    return l < m->L ? reinterpret_cast<float*>(ws + tp.layers[l].xin) : X;
+    return l < m->L ? reinterpret_cast<float*>(ws + tp.layers[l].xin) + (size_t)t0 * D : X;
   };
   EpiArgs pe;
-  pe.bias = m->patch_b; pe.out = xin_of(0); pe.ldo = D; pe.tok_info = tok; pe.imgs = d_imgs;
+  pe.bias = m->patch_b; pe.out = xin_of(0); pe.ldo = D; pe.tok_info = tok; pe.imgs = r.imgs;
   pe.cls = m->cls; pe.pos = m->pos; pe.base_grid = m->g0;
-  VL_HIP(im2col(pix, d_imgs, p.n, p.max_ntok, m->cfg.channels, m->P, m->Kpad, QH, !f32, tok, s));
+  VL_HIP(im2col(pix, r.imgs, r.n, r.max_ntok, m->cfg.channels, m->P, m->Kpad, QH, !f32, tok, s));
   if (f32)
     VL_HIP(gemm_f32(static_cast<const float*>(QH), m->Kpad, static_cast<const float*>(m->patch_w),
                     m->Kpad, T, D, m->Kpad, OP_PATCH, pe, s));
@@ -2008,13 +2049,13 @@ vl_status run_train_forward(vl_model* m, const TrainPlan& tp, const float* pix, 
   for (int l = 0; l < m->L; ++l) {
     const Layer& ly = m->layers[l];
     const TrainLayer& sv = tp.layers[l];
-    void* y1 = ws + sv.y1;
-    void* qkv = ws + sv.qkv;
-    void* o = ws + sv.o;
-    void* y2 = ws + sv.y2;
-    float* z1 = reinterpret_cast<float*>(ws + sv.z1);
+    void* y1 = ws + sv.y1 + es * (size_t)t0 * D;
+    void* qkv = ws + sv.qkv + es * (size_t)t0 * 3 * D;
+    void* o = ws + sv.o + es * (size_t)t0 * D;
+    void* y2 = ws + sv.y2 + es * (size_t)t0 * D;
+    float* z1 = reinterpret_cast<float*>(ws + sv.z1) + (size_t)t0 * F;
     float* xin = xin_of(l);
-    float* hb = reinterpret_cast<float*>(ws + sv.h);
+    float* hb = reinterpret_cast<float*>(ws + sv.h) + (size_t)t0 * D;
     VL_HIP(layernorm_rows(xin, ly.ln1_g, ly.ln1_b, eps, y1, !f32, T, D, s));
     EpiArgs e1; e1.bias = ly.qkv_b; e1.out = qkv; e1.ldo = 3 * D;
     EpiArgs e2; e2.bias = ly.o_b; e2.out = hb; e2.resid_in = xin; e2.ldo = D;
@@ -2023,19 +2064,19 @@ vl_status run_train_forward(vl_model* m, const TrainPlan& tp, const float* pix, 
     if (f32) {
       VL_HIP(gemm_f32(static_cast<const float*>(y1), D, static_cast<const float*>(ly.qkv_w), D, T,
                       3 * D, D, OP_QKV, e1, s));
-      VL_HIP(attention_f32(static_cast<const float*>(qkv), static_cast<float*>(o), d_imgs, d_items,
-                           p.n_items, m->heads, m->hd, false, s));
+      VL_HIP(attention_f32(static_cast<const float*>(qkv), static_cast<float*>(o), r.imgs, r.items,
+                           r.n_items, m->heads, m->hd, false, s));
       VL_HIP(gemm_f32(static_cast<const float*>(o), D, static_cast<const float*>(ly.o_w), D, T, D,
                       D, OP_OPROJ, e2, s));
     } else {
       VL_HIP(gemm_bf16(static_cast<const bf16_t*>(y1), D, ly.qkv_w, D, false, T, 3 * D, D, OP_QKV,
                        gemm_cfg_for(m, 1, T), e1, s));
-      float* lse = reinterpret_cast<float*>(ws + sv.lse);
-      VL_HIP(attention_bf16(static_cast<const bf16_t*>(qkv), static_cast<bf16_t*>(o), d_imgs,
-                            d_items, p.n_items, m->heads, m->hd, false, s, nullptr, lse));
-      VL_HIP(attention_bf16_resident(static_cast<const bf16_t*>(qkv), o, nullptr, false, T,
-                                     d_imgs, reinterpret_cast<const int*>(ws + p.off_res),
-                                     p.n_res, p.res_tiles, m->heads, m->hd, s, nullptr, lse));
+      float* lse = reinterpret_cast<float*>(ws + sv.lse) + (size_t)t0 * m->heads;
+      VL_HIP(attention_bf16(static_cast<const bf16_t*>(qkv), static_cast<bf16_t*>(o), r.imgs,
+                            r.items, r.n_items, m->heads, m->hd, false, s, nullptr, lse));
+      VL_HIP(attention_bf16_resident(static_cast<const bf16_t*>(qkv), o, nullptr, false, T, r.imgs,
+                                     r.res, r.n_res, r.res_tiles, m->heads, m->hd, s, nullptr,
+                                     lse));
       VL_HIP(gemm_bf16(static_cast<const bf16_t*>(o), D, ly.o_w, D, false, T, D, D, OP_OPROJ,
                        gemm_cfg_for(m, 2, T), e2, s));
     }
@@ -2048,16 +2089,56 @@ vl_status run_train_forward(vl_model* m, const TrainPlan& tp, const float* pix, 
                       D, F, OP_FC2, e4, s));
     } else {
       // GELU(z1) in BF16 from the same epilogue, kept for the backward
-      bf16_t* g = reinterpret_cast<bf16_t*>(ws + sv.g);
+      bf16_t* g = reinterpret_cast<bf16_t*>(ws + sv.g) + (size_t)t0 * F;
       e3.out2 = g;
       VL_HIP(gemm_bf16(static_cast<const bf16_t*>(y2), D, ly.fc1_w, D, false, T, F, D, OP_FC1_PRE,
                        gemm_cfg_for(m, 3, T), e3, s));
       VL_HIP(gemm_bf16(g, F, ly.fc2_w, F, false, T, D, F, OP_FC2, gemm_cfg_for(m, 4, T), e4, s));
     }
   }
-  VL_HIP(pool_project(X, d_imgs, p.n, m->lnf_g, m->lnf_b, eps, m->proj, D, m->Pd, false,
-                      static_cast<float*>(QH), reinterpret_cast<float*>(ws + p.off_E), emb, s));
+  VL_HIP(pool_project(X, r.imgs, r.n, m->lnf_g, m->lnf_b, eps, m->proj, D, m->Pd, false,
+                      reinterpret_cast<float*>(ws + tp.zscr) + (size_t)r.i0 * D,
+                      reinterpret_cast<float*>(ws + p.off_E) + (size_t)r.i0 * m->Pd,
+                      emb + (size_t)r.i0 * m->Pd, s));
   return VL_OK;
+}
+
+// The training forward: one pass over the batch, or its two halves on the
+// caller's stream and the model's side stream (forked after everything
+// before this call on s, joined back into s, also after an error).  Every
+// kernel works per token row or per image in a fixed order, so the halves
+// compute the same bits as one pass.
+vl_status run_train_forward(vl_model* m, const TrainPlan& tp, const float* pix, float* emb,
+                            char* ws, hipStream_t s) {
+  const Part& p = tp.p.parts[0];
+  if (tp.halves.size() != 2) {
+    FwdRange r;
+    r.n = p.n; r.T = p.T; r.max_ntok = p.max_ntok; r.n_items = p.n_items; r.n_res = p.n_res;
+    r.res_tiles = p.res_tiles;
+    r.imgs = reinterpret_cast<const ImgDesc*>(ws + p.off_imgs);
+    r.items = reinterpret_cast<const AttnItem*>(ws + p.off_items);
+    r.res = reinterpret_cast<const int*>(ws + p.off_res);
+    return train_forward_range(m, tp, pix, emb, ws, r, s);
+  }
+  if (!m->side) VL_HIP(hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking));
+  if (!m->ev_fork) VL_HIP(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
+  if (!m->ev_join) VL_HIP(hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming));
+  VL_HIP(hipEventRecord(m->ev_fork, s));
+  VL_HIP(hipStreamWaitEvent(m->side, m->ev_fork, 0));
+  vl_status st = VL_OK;
+  for (int k = 0; k < 2 && st == VL_OK; ++k) {
+    const TrainPlan::Half& h = tp.halves[k];
+    FwdRange r;
+    r.i0 = h.i0; r.n = h.n; r.t0 = h.t0; r.T = h.T; r.max_ntok = h.max_ntok;
+    r.n_items = h.n_items; r.n_res = h.n_res; r.res_tiles = h.res_tiles;
+    r.imgs = reinterpret_cast<const ImgDesc*>(ws + h.off_imgs);
+    r.items = reinterpret_cast<const AttnItem*>(ws + h.off_items);
+    r.res = reinterpret_cast<const int*>(ws + h.off_res);
+    st = train_forward_range(m, tp, pix, emb, ws, r, k == 0 ? s : m->side);
+  }
+  if (hipEventRecord(m->ev_join, m->side) == hipSuccess)
+    (void)hipStreamWaitEvent(s, m->ev_join, 0);
+  return st;
 }
 
 // Offsets (floats) of every tensor in the FP32 weight blob, hence in the

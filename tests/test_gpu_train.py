@@ -197,6 +197,29 @@ def test_backward_kmajor_weight_gradients_match_transposed(V):
             assert np.array_equal(a, b), name
 
 
+def test_training_forward_in_two_halves_is_bitwise_one_pass(V):
+    """VL_OPT_SPLIT: the training forward runs the batch as two halves of
+    consecutive images on two streams.  Eight 336-px images of a ViT-L/14
+    block (4616 tokens, enough to split): embeddings and every gradient of
+    the following backward equal the one-pass run bit for bit."""
+    p = synth.make_params(L14_1, 70, std=0.02)
+    blob = torch.from_numpy(synth.params_to_blob(L14_1, p)).cuda()
+    sizes = [(336, 336)] * 8
+    pix = torch.from_numpy(pack(synth.make_images(sizes, 71))).cuda()
+    de = torch.from_numpy(synth.make_texts(8, L14_1.proj_dim, 72)).cuda() * 0.1
+    out = {}
+    for split in (False, True):
+        _say(f"train l14_1block bf16 n=8 split={split}")
+        tr = V.Trainer(L14_1, blob, "bf16", split=split)
+        emb = tr.forward(pix, sizes).clone()
+        grads = tr.backward(pix, sizes, de).clone()
+        torch.cuda.synchronize()
+        out[split] = (emb.cpu(), grads.cpu())
+        tr.close()
+    assert torch.equal(out[True][0], out[False][0])
+    assert torch.equal(out[True][1], out[False][1])
+
+
 def _per_tensor_pair(cfg, a, b):
     o = 0
     for name, shape in synth.weight_layout(cfg):
