@@ -254,8 +254,9 @@ vl_status vl_encode_texts(vl_model* m, const int32_t* ids_dev, const int32_t* le
  *                   call's stream, so the parts overlap.  Outputs are
  *                   bitwise identical to a one-part run.  0 = one part on
  *                   the call's stream.  Changing it drops cached graphs.
- *                   (On MI355X at ViT-L/14@336, batch 32, it measured
- *                   between -2 % and +3 % against one part.)
+ *                   The training forward (vl_encode_images_train, VL_BF16)
+ *                   splits the same way.  (On MI355X at ViT-L/14@336, batch
+ *                   32, two parts run 6-7 % faster than one.)
  *   VL_OPT_FUSED_LN : off by default (VL_BF16 and VL_FP8W_BF16A; no effect
  *                   on other precisions).  Both LayerNorms of a block are
  *                   folded into the GEMMs around them: the residual
