@@ -1992,9 +1992,11 @@ std::string train_key(const TrainPlan& tp, const void* pix, const void* ws, size
 // FP32 product C[M, N] = A[M, K] . B[N, K]^T in the model's arithmetic (FP32
 // FMA, or BF16 operands with FP32 accumulation on the MFMA kernel).
 vl_status gemm_into_f32(const vl_model* m, const void* A, int lda, const void* B, int ldb, int M,
-                        int N, int K, float* out, int ldo, hipStream_t s) {
+                        int N, int K, float* out, int ldo, hipStream_t s,
+                        bf16_t* copy_bf16 = nullptr) {
   EpiArgs e;
   e.out = out; e.ldo = ldo; e.alpha = 1.f; e.beta = 0.f;
+  e.out2 = m->prec == VL_FP32 ? nullptr : copy_bf16;   // BF16 copy of out (BF16 models)
   if (m->prec == VL_FP32)
     VL_HIP(gemm_f32(static_cast<const float*>(A), lda, static_cast<const float*>(B), ldb, M, N, K,
                     OP_LOGITS, e, s));
@@ -2004,11 +2006,12 @@ vl_status gemm_into_f32(const vl_model* m, const void* A, int lda, const void* B
   return VL_OK;
 }
 
-// The training forward: the encoder's kernel sequence on one part, keeping
-// each block's input, LayerNorm outputs, Q/K/V, attention output, residual
-// after attention and FC1 pre-activation.  Every kernel and its arithmetic is
-// the inference forward's, so the embeddings agree with vl_encode_images
-// bitwise.
+// The training forward: the encoder's kernel sequence, keeping each block's
+// input, LayerNorm outputs, Q/K/V, attention output, residual after
+// attention, FC1 pre-activation and (BF16) GELU output.  Every kernel and its
+// arithmetic is the inference forward's, so the embeddings agree with
+// vl_encode_images bitwise.
+//
 // A run of consecutive images of a training batch: its rows t0 .. t0+T-1
 // and images i0 .. i0+n-1 of the whole-batch buffers, with descriptors
 // whose token starts are relative to t0.
@@ -2347,7 +2350,10 @@ vl_status run_backward_body(vl_model* m, const TrainPlan& tp, const float* pix, 
     if ((st = prep_dx()) != VL_OK) return st;
     if ((st = rec(kEvDxO, s)) != VL_OK) return st;
     VL_HIP(transpose_rows(ly.o_w, bf, D, D, D, Wt, bf, D, s));
-    if ((st = gemm_into_f32(m, dXb, D, Wt, D, T, D, D, dY, D, s)) != VL_OK) return st;   // dO
+    // dO in FP32, and (BF16) its BF16 copy for the attention backward
+    if ((st = gemm_into_f32(m, dXb, D, Wt, D, T, D, D, dY, D, s,
+                            bf ? static_cast<bf16_t*>(dOb) : nullptr)) != VL_OK)
+      return st;
     if (km) {
       if ((st = wait(sw, kEvDxO)) != VL_OK) return st;
       st = wgrad_gemm_km(tp, ws, dXb, D, ws + sv.o, D, D, D, G(go.o_w), sw);
@@ -2361,7 +2367,6 @@ vl_status run_backward_body(vl_model* m, const TrainPlan& tp, const float* pix, 
     // ---- attention
     // (BF16: the log-sum-exp the forward kept, and dO also in BF16; FP32:
     // recomputed)
-    if (bf) VL_HIP(convert_bf16(dY, static_cast<bf16_t*>(dOb), (size_t)T * D, s));
     if ((st = wait(s, kEvWFc1)) != VL_OK) return st;   // FC1's weight gradient read dZ
     VL_HIP(attention_backward(ws + sv.qkv, ws + sv.o, bf, dY, d_imgs, d_items64, tp.n_items64,
                               d_items128, tp.n_items128,

@@ -89,6 +89,12 @@ __device__ __forceinline__ void epi_store4(const EpiArgs& e, int m, int n, float
     for (int j = 0; j < 4; ++j) v[j] = e.alpha * v[j] + e.beta;
     *reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n) =
         make_float4(v[0], v[1], v[2], v[3]);
+    if (e.out2) {   // BF16 copy
+      u32x2 pk;
+      pk.x = pack_bf16x2(v[0], v[1]);
+      pk.y = pack_bf16x2(v[2], v[3]);
+      *reinterpret_cast<u32x2*>(static_cast<bf16_t*>(e.out2) + (size_t)m * e.ldo + n) = pk;
+    }
     return;
   }
   float4 ws = make_float4(1.f, 1.f, 1.f, 1.f);
@@ -650,9 +656,15 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
           continue;
         }
         if (EPI == EPI_SCALE_BIAS) {
-          *reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n) =
-              make_float4(e.alpha * v[p].x + e.beta, e.alpha * v[p].y + e.beta,
-                          e.alpha * v[p].z + e.beta, e.alpha * v[p].w + e.beta);
+          const float4 y = make_float4(e.alpha * v[p].x + e.beta, e.alpha * v[p].y + e.beta,
+                                       e.alpha * v[p].z + e.beta, e.alpha * v[p].w + e.beta);
+          *reinterpret_cast<float4*>(static_cast<float*>(e.out) + (size_t)m * e.ldo + n) = y;
+          if (e.out2) {   // BF16 copy
+            u32x2 pk;
+            pk.x = pack_bf16x2(y.x, y.y);
+            pk.y = pack_bf16x2(y.z, y.w);
+            *reinterpret_cast<u32x2*>(static_cast<bf16_t*>(e.out2) + (size_t)m * e.ldo + n) = pk;
+          }
           continue;
         }
         if (EPI == EPI_DGELU) {

@@ -17,7 +17,8 @@ namespace vl {
 //   OP_OPROJ  : resid[m,n] += acc * ws[n] + bias[n]      (FP32)
 //   OP_FC1    : out = GELU(acc * ws[n] + bias[n])        (BF16 / FP32 out)
 //   OP_FC2    : resid[m,n] += acc * ws[n] + bias[n]      (FP32)
-//   OP_LOGITS : out = alpha * acc + beta                 (FP32)
+//   OP_LOGITS : out = alpha * acc + beta                 (FP32; BF16 GEMMs
+//               without split-K: with out2 also its BF16 copy [M, ldo])
 //   OP_FC1_PRE: out = acc * ws[n] + bias[n]              (FP32 out; the FC1
 //               pre-activation the training forward keeps for the backward;
 //               with out2 also GELU of it in BF16 [M, ldo], as OP_FC1 forms it)
