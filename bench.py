@@ -620,6 +620,19 @@ def main(argv=None) -> int:
     ms = ev0.elapsed_time(ev1) / args.steps
     value = n / (ms / 1e3)
     print(f"# {prec}: {ms:.3f} ms/step, {value:.1f} images/s", file=sys.stderr, flush=True)
+    # The spread of single steps, after the timed region: each of `args.steps`
+    # more steps between its own pair of events on the call's stream.
+    pev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for a, b in pev:
+        a.record(stream)
+        step(enc)
+        b.record(stream)
+    torch.cuda.synchronize()
+    from paper_2505_00690_amd.serve import percentile
+    per_step = [a.elapsed_time(b) for a, b in pev]
+    step_spread = {"steps": len(per_step), "p10_ms": percentile(per_step, 10),
+                   "p50_ms": percentile(per_step, 50), "p90_ms": percentile(per_step, 90)}
 
     # Per-operation device time: events around every launch, on its stream.
     # It is taken on the one-part schedule: with two parts the kernels of one
@@ -679,6 +692,7 @@ def main(argv=None) -> int:
         "encoder_tflops": total_flops / (ms / 1e3) / 1e12,
         "mfu_bf16": total_flops / (ms / 1e3) / BF16_PEAK,
         "op_ms_per_step": breakdown,
+        "step_ms_spread": step_spread,
         "roofline": roofline,
     }
     if fp8_note:
