@@ -7,8 +7,10 @@ leg do.  It shares no code with the HIP path.
 What is computed: the gradient of a contrastive loss (CLIP, Radford et al.
 2021, Sec. 2.3; SigLIP, Zhai et al. 2023, Eq. 1) of a batch of images
 against given text embeddings, with respect to every parameter of the image
-tower of vit64 (class-token pooling) -- the backward pass of the forward in
-vit64, written out by the chain rule of each of its definitions:
+tower of vit64 (class-token pooling, or the attention-pooling head: a learned
+query attending over every final-LayerNormed token, Lee et al. 2019, Sec.
+3.2) -- the backward pass of the forward in vit64, written out by the chain
+rule of each of its definitions:
 
   * L2 normalisation e_hat = e / |e|:  de = (de_hat - e_hat <e_hat, de_hat>) / |e|.
   * Linear y = x W^T + b:  dx = dy W,  dW = dy^T x,  db = sum over rows of dy.
@@ -20,7 +22,9 @@ vit64, written out by the chain rule of each of its definitions:
     GELU'(z) = Phi(z) + z phi(z), phi the standard normal density.
   * Attention (Vaswani et al. 2017, Sec. 3.2.1 Eq. 1) O = P V with
     P = softmax(S), S = Q K^T / sqrt(d):  dV = P^T dO,  dP = dO V^T,
-    dS = P * (dP - rowsum(dP * P)),  dQ = dS K / sqrt(d),  dK = dS^T Q / sqrt(d).
+    dS = P * (dP - rowsum(dP * P)),  dQ = dS K / sqrt(d),  dK = dS^T Q / sqrt(d)
+    (the attention-pooling head: one query row per head, q = probe W_q^T + b_q,
+    so dprobe = dq W_q, dW_q = dq probe^T).
   * Patch embedding and position table (ViT, Dosovitskiy et al. 2021,
     Sec. 3.1 Eq. 1, Sec. 3.2): the patch weights' gradient is the
     row-sum of outer products of token gradients with the normalised patch
@@ -96,12 +100,79 @@ def _add(acc: Dict, g: Dict) -> None:
             acc[k] += v
 
 
+def map_forward(xl: np.ndarray, params: Dict, heads: int, eps: float) -> Dict:
+    """The attention-pooling head of vit64.map_head on final-LayerNormed
+    tokens xl [N, D], keeping every intermediate the backward needs; 'out'
+    is the head's output."""
+    xl = np.asarray(xl, F64)
+    dm = xl.shape[1]
+    d = dm // heads
+    probe = np.asarray(params["map_probe"], F64)
+    q = probe @ np.asarray(params["map_q_w"], F64).T + np.asarray(params["map_q_b"], F64)
+    kv = xl @ np.asarray(params["map_kv_w"], F64).T + np.asarray(params["map_kv_b"], F64)
+    o = np.zeros(dm)
+    for h in range(heads):
+        sl = slice(h * d, (h + 1) * d)
+        o[sl] = V.attention_head(q[None, sl], kv[:, :dm][:, sl], kv[:, dm:][:, sl])[0]
+    y = o @ np.asarray(params["map_o_w"], F64).T + np.asarray(params["map_o_b"], F64)
+    zl = V.layernorm(y, params["map_ln_g"], params["map_ln_b"], eps)
+    hpre = zl @ np.asarray(params["map_fc1_w"], F64).T + np.asarray(params["map_fc1_b"], F64)
+    hg = V.gelu(hpre)
+    out = y + hg @ np.asarray(params["map_fc2_w"], F64).T + np.asarray(params["map_fc2_b"], F64)
+    return {"xl": xl, "q": q, "kv": kv, "o": o, "y": y, "zl": zl, "hpre": hpre, "hg": hg,
+            "out": out}
+
+
+def map_backward(dout: np.ndarray, s: Dict, params: Dict, heads: int, eps: float,
+                 g: Dict) -> np.ndarray:
+    """Backward of the attention-pooling head from d(out) [D]: adds the
+    head's parameter gradients to g and returns d(xl) [N, D]."""
+    dout = np.asarray(dout, F64)
+    dm = dout.shape[0]
+    d = dm // heads
+    # out = y + GELU(zl W1^T + b1) W2^T + b2,  zl = LN(y)
+    g["map_fc2_w"] += np.outer(dout, s["hg"])
+    g["map_fc2_b"] += dout
+    dh = (dout @ np.asarray(params["map_fc2_w"], F64)) * gelu_grad(s["hpre"])
+    g["map_fc1_w"] += np.outer(dh, s["zl"])
+    g["map_fc1_b"] += dh
+    dzl = dh @ np.asarray(params["map_fc1_w"], F64)
+    dyl, dg, db = layernorm_backward(s["y"][None], params["map_ln_g"], dzl[None], eps)
+    g["map_ln_g"] += dg
+    g["map_ln_b"] += db
+    dy = dout + dyl[0]
+    # y = o W_o^T + b_o
+    g["map_o_w"] += np.outer(dy, s["o"])
+    g["map_o_b"] += dy
+    do = dy @ np.asarray(params["map_o_w"], F64)
+    # one query per head over the N keys and values
+    kv = s["kv"]
+    dq = np.zeros(dm)
+    dkv = np.zeros_like(kv)
+    for h in range(heads):
+        sl = slice(h * d, (h + 1) * d)
+        dqh, dkh, dvh = attention_head_backward(s["q"][None, sl], kv[:, :dm][:, sl],
+                                                kv[:, dm:][:, sl], do[None, sl])
+        dq[sl] = dqh[0]
+        dkv[:, :dm][:, sl] = dkh
+        dkv[:, dm:][:, sl] = dvh
+    # q = probe W_q^T + b_q;  kv = xl W_kv^T + b_kv
+    g["map_q_w"] += np.outer(dq, np.asarray(params["map_probe"], F64))
+    g["map_q_b"] += dq
+    g["map_probe"] += dq @ np.asarray(params["map_q_w"], F64)
+    g["map_kv_w"] += dkv.T @ s["xl"]
+    g["map_kv_b"] += dkv.sum(axis=0)
+    return dkv @ np.asarray(params["map_kv_w"], F64)
+
+
 def encode_image_backward(img: np.ndarray, params: Dict, cfg,
                           d_emb: np.ndarray) -> Dict:
     """Gradient of <d_emb, e_hat(img)> with respect to every parameter (same
-    structure as params), for the class-token-pooled image tower."""
-    if getattr(cfg, "pool", "cls") != "cls":
-        raise ValueError("the training backward covers class-token pooling")
+    structure as params), for the image tower with class-token or
+    attention-pooling head."""
+    pool = getattr(cfg, "pool", "cls")
+    if pool not in ("cls", "map"):
+        raise ValueError(f"unknown pooling {pool!r}")
     eps = cfg.ln_eps
     g = _zeros_like_params(params)
     # ---- forward, keeping what the backward needs
@@ -125,7 +196,12 @@ def encode_image_backward(img: np.ndarray, params: Dict, cfg,
         gz = V.gelu(z1)
         saved.append((x, y1, qkv, o, hres, y2, z1, gz))
         x = hres + gz @ np.asarray(lp["fc2_w"], F64).T + np.asarray(lp["fc2_b"], F64)
-    z = V.layernorm(x[0], params["lnf_g"], params["lnf_b"], eps)
+    if pool == "map":
+        mp = map_forward(V.layernorm(x, params["lnf_g"], params["lnf_b"], eps), params,
+                         cfg.heads, eps)
+        z = mp["out"]
+    else:
+        z = V.layernorm(x[0], params["lnf_g"], params["lnf_b"], eps)
     e = np.asarray(params["proj_w"], F64) @ z
     ne = max(np.linalg.norm(e), 1e-12)
     eh = e / ne
@@ -134,11 +210,15 @@ def encode_image_backward(img: np.ndarray, params: Dict, cfg,
     de = (dh_ - eh * (eh @ dh_)) / ne
     g["proj_w"] += np.outer(de, z)
     dz = np.asarray(params["proj_w"], F64).T @ de
-    dx0, dgf, dbf = layernorm_backward(x[0][None], params["lnf_g"], dz[None], eps)
+    if pool == "map":
+        dxl = map_backward(dz, mp, params, cfg.heads, eps, g)
+        dx, dgf, dbf = layernorm_backward(x, params["lnf_g"], dxl, eps)
+    else:
+        dx0, dgf, dbf = layernorm_backward(x[0][None], params["lnf_g"], dz[None], eps)
+        dx = np.zeros_like(x)
+        dx[0] = dx0[0]
     g["lnf_g"] += dgf
     g["lnf_b"] += dbf
-    dx = np.zeros_like(x)
-    dx[0] = dx0[0]
     for lp, gl, (xin, y1, qkv, o, hres, y2, z1, gz) in zip(
             reversed(params["layers"]), reversed(g["layers"]), reversed(saved)):
         dm = xin.shape[1]

@@ -58,16 +58,36 @@ def _torch_encode(c, tp, img):
         t = t + F.linear(torch.cat(heads, dim=1), g("o_w"), g("o_b"))
         y = F.layer_norm(t, (D,), g("ln2_g"), g("ln2_b"), c.ln_eps)
         t = t + F.linear(F.gelu(F.linear(y, g("fc1_w"), g("fc1_b"))), g("fc2_w"), g("fc2_b"))
-    z = F.layer_norm(t[0], (D,), tp["lnf_g"], tp["lnf_b"], c.ln_eps)
+    if getattr(c, "pool", "cls") == "map":
+        # attention pooling through torch's own multi-head attention, the
+        # learned probe as the one query (in-projection [W_q; W_kv])
+        xl = F.layer_norm(t, (D,), tp["lnf_g"], tp["lnf_b"], c.ln_eps)
+        y, _ = F.multi_head_attention_forward(
+            tp["map_probe"][None, None], xl[:, None], xl[:, None], D, c.heads,
+            torch.cat([tp["map_q_w"], tp["map_kv_w"]]), torch.cat([tp["map_q_b"], tp["map_kv_b"]]),
+            None, None, False, 0.0, tp["map_o_w"], tp["map_o_b"], training=False,
+            need_weights=False)
+        y = y[0, 0]
+        zl = F.layer_norm(y, (D,), tp["map_ln_g"], tp["map_ln_b"], c.ln_eps)
+        z = y + F.linear(F.gelu(F.linear(zl, tp["map_fc1_w"], tp["map_fc1_b"])),
+                         tp["map_fc2_w"], tp["map_fc2_b"])
+    else:
+        z = F.layer_norm(t[0], (D,), tp["lnf_g"], tp["lnf_b"], c.ln_eps)
     return F.normalize(tp["proj_w"] @ z, dim=0)
 
 
+@pytest.mark.parametrize("pool", ["cls", "map"])
 @pytest.mark.parametrize("sizes", [[(64, 64), (64, 64)], [(48, 80), (96, 64)]])
-def test_backward_matches_torch_autograd(sizes):
+def test_backward_matches_torch_autograd(sizes, pool):
     """Every parameter gradient of sum_i <d_emb_i, e_hat_i> against float64
     autograd, at the base resolution and at two resampled grids (adjoint of
-    the bilinear position resampling)."""
-    c, p = _small()
+    the bilinear position resampling), with class-token pooling and with the
+    attention-pooling head (autograd through torch's multi-head attention)."""
+    if pool == "cls":
+        c, p = _small()
+    else:
+        c = synth.ModelConfig("tiny_train_map", 16, 64, 2, 4, 256, 32, 4, pool="map")
+        p = synth.make_params(c, 48, std=0.2)
     imgs = synth.make_images(sizes, 43)
     d_emb = _rng(44).standard_normal((len(imgs), c.proj_dim))
     layout = synth.weight_layout(c)
@@ -128,6 +148,50 @@ def test_backward_central_differences():
             fm = f(pp)
             fd = (fp - fm) / (2 * h)
             assert abs(fd - gt[idx]) <= 1e-6 * max(1.0, abs(fd)), (name, idx, fd, gt[idx])
+
+
+def test_map_backward_central_differences():
+    """Entries of every attention-pooling head tensor (and the final
+    LayerNorm over all tokens it reads) against central differences of the
+    oracle's own MAP forward (vit64.map_head)."""
+    c = synth.ModelConfig("tiny_train_map", 16, 64, 1, 4, 256, 32, 4, pool="map")
+    p = synth.make_params(c, 49, std=0.2)
+    imgs = synth.make_images([(64, 64), (48, 64)], 50)
+    d_emb = _rng(51).standard_normal((2, c.proj_dim))
+    g = TR.encode_backward(imgs, p, c, d_emb)
+    rng = _rng(52)
+
+    def f(pp):
+        return float((O.encode(imgs, pp, c) * d_emb).sum())
+
+    h = 1e-6
+    for name in ("map_probe", "map_q_w", "map_q_b", "map_kv_w", "map_kv_b", "map_o_w",
+                 "map_o_b", "map_ln_g", "map_ln_b", "map_fc1_w", "map_fc1_b", "map_fc2_w",
+                 "map_fc2_b", "lnf_g", "lnf_b"):
+        for _ in range(2):
+            idx = tuple(int(rng.integers(0, s)) for s in np.shape(p[name]))
+            pp = {k: v for k, v in p.items() if k != "layers"}
+            pp["layers"] = p["layers"]
+            a = np.array(p[name], np.float64)
+            a[idx] += h
+            pp[name] = a
+            fp = f(pp)
+            a = a.copy()
+            a[idx] -= 2 * h
+            pp[name] = a
+            fm = f(pp)
+            fd = (fp - fm) / (2 * h)
+            assert abs(fd - g[name][idx]) <= 1e-6 * max(1.0, abs(fd)), (name, idx, fd, g[name][idx])
+
+
+def test_map_forward_is_the_inference_head():
+    """The backward's MAP forward computes vit64.map_head (pinned against
+    torch's multi-head attention) exactly."""
+    c = synth.MODELS["tiny_map"]
+    p = synth.make_params(c, 53)
+    x = _rng(54).standard_normal((29, c.width))
+    got = TR.map_forward(x, p, c.heads, c.ln_eps)["out"]
+    assert np.max(np.abs(got - O.map_head(x, p, c.heads, c.ln_eps))) <= 1e-12
 
 
 def test_layernorm_backward_invariants():
