@@ -407,13 +407,15 @@ vl_status vl_encode_images(vl_model* m, const float* pixels_dev,
  *                               summed over the batch.
  * The backward is the chain rule of each forward step (LayerNorm, GELU,
  * attention, linear layers, patch embedding with the folded pixel
- * normalisation, class token and position table, final LayerNorm,
- * projection, L2 normalisation).  VL_FP32 models compute in FP32; VL_BF16
+ * normalisation, class token and position table, final LayerNorm, the
+ * attention-pooling head with its learned query (VL_POOL_MAP), projection,
+ * L2 normalisation).  VL_FP32 models compute in FP32; VL_BF16
  * models multiply BF16 operands (the kept activations, dL/dx of the
  * residual stream, dGELU and dQKV rounded to BF16) with FP32 accumulation;
  * LayerNorm, softmax and L2 statistics stay FP32.
- * Supported: VL_FP32 and VL_BF16 image models with VL_POOL_CLS (else
- * VL_ERR_UNSUPPORTED), every image at the base patch grid (floor(H/P) ==
+ * Supported: VL_FP32 and VL_BF16 image models, class-token or attention
+ * pooling (the latter at head width <= 64; else VL_ERR_UNSUPPORTED), every
+ * image at the base patch grid (floor(H/P) ==
  * floor(W/P) == base_grid), at most 2^20 tokens.  The backward returns
  * VL_ERR_INVALID_ARG unless the model's last vl_encode_images_train call had
  * the same pixels pointer, shapes and workspace; the caller must not reuse

@@ -99,6 +99,7 @@ struct vl_model {
   const float *map_q = nullptr, *map_kv_b = nullptr, *map_o_w = nullptr, *map_o_b = nullptr;
   const float *map_ln_g = nullptr, *map_ln_b = nullptr, *map_fc1_w = nullptr, *map_fc1_b = nullptr;
   const float *map_fc2_w = nullptr, *map_fc2_b = nullptr;
+  const float *map_probe = nullptr, *map_q_w = nullptr;   // for the training backward
   const void* map_kv_w = nullptr;
   std::vector<Layer> layers;
   bool use_graphs = false;
@@ -706,9 +707,10 @@ static vl_status build_weights(vl_model* m, const float* wdev, hipStream_t s, vl
   const size_t d_lnf_g = alloc(4 * D);
   const size_t d_lnf_b = alloc(4 * D);
   const size_t d_proj = alloc(4 * (size_t)m->Pd * D);
-  struct DstMap { size_t q, kv_w, kv_b, o_w, o_b, ln_g, ln_b, fc1_w, fc1_b, fc2_w, fc2_b; } dm{};
+  struct DstMap { size_t q, kv_w, kv_b, o_w, o_b, ln_g, ln_b, fc1_w, fc1_b, fc2_w, fc2_b, probe, q_w; } dm{};
   if (map) {
-    dm.q = alloc(4 * D); dm.kv_w = alloc(pes * 2 * D * D); dm.kv_b = alloc(4 * 2 * D);
+    dm.q = alloc(4 * D); dm.probe = alloc(4 * D); dm.q_w = alloc(4 * D * D);
+    dm.kv_w = alloc(pes * 2 * D * D); dm.kv_b = alloc(4 * 2 * D);
     dm.o_w = alloc(4 * D * D); dm.o_b = alloc(4 * D); dm.ln_g = alloc(4 * D); dm.ln_b = alloc(4 * D);
     dm.fc1_w = alloc(4 * F * D); dm.fc1_b = alloc(4 * F); dm.fc2_w = alloc(4 * D * F);
     dm.fc2_b = alloc(4 * D);
@@ -798,6 +800,8 @@ static vl_status build_weights(vl_model* m, const float* wdev, hipStream_t s, vl
     eq.out = f(dm.q);
     eq.ldo = (int)D;
     chk(gemm_f32(sm.probe, (int)D, sm.q_w, (int)D, 1, (int)D, (int)D, OP_QKV, eq, s), "map query");
+    chk(copy_f32(sm.probe, f(dm.probe), D, s), "copy");
+    chk(copy_f32(sm.q_w, f(dm.q_w), D * D, s), "copy");
     if (prec == VL_FP32)
       chk(copy_f32(sm.kv_w, f(dm.kv_w), 2 * D * D, s), "copy");
     else
@@ -815,6 +819,7 @@ static vl_status build_weights(vl_model* m, const float* wdev, hipStream_t s, vl
     m->map_o_w = f(dm.o_w); m->map_o_b = f(dm.o_b); m->map_ln_g = f(dm.ln_g); m->map_ln_b = f(dm.ln_b);
     m->map_fc1_w = f(dm.fc1_w); m->map_fc1_b = f(dm.fc1_b); m->map_fc2_w = f(dm.fc2_w);
     m->map_fc2_b = f(dm.fc2_b);
+    m->map_probe = f(dm.probe); m->map_q_w = f(dm.q_w);
   }
   if (m->text) {
     m->tok_emb = f(d_tok);
@@ -1852,6 +1857,13 @@ struct TrainPlan {
   };
   std::vector<Half> halves;
   size_t off_split = 0;
+  // The attention-pooling head: kept forward values (LN_f of every token,
+  // its K/V projection, the head's rows) and backward scratch.
+  struct Map {
+    bool on = false;
+    size_t yf = 0, kv = 0, dkv = 0, mo = 0, my = 0, mzl = 0, mz = 0, mh = 0;
+    size_t dy = 0, dzl = 0, dO = 0, dq = 0, dhg = 0, hpre = 0, dh = 0, gtmp = 0, wt = 0;
+  } map;
   size_t zscr = 0;  // pooled rows [n, D] (final LayerNorm scratch of the forward)
   size_t wsplit = 0, wsplit_bytes = 0;   // split-K partial products of the weight gradients
   size_t total = 0;
@@ -1877,7 +1889,8 @@ bool make_train_plan(const vl_model* m, int32_t n, const int32_t* hs, const int3
     *why = "training runs in VL_FP32 or VL_BF16";
     return false;
   }
-  if (m->cfg.pool != VL_POOL_CLS) { *why = "training covers class-token pooling"; return false; }
+  const bool map = m->cfg.pool == VL_POOL_MAP;
+  if (map && m->hd > 64) { *why = "training the pooling head needs head width <= 64"; return false; }
   if (!make_plan(m, n, hs, ws, &tp->p, why, /*one_part=*/true)) return false;
   for (int i = 0; i < n; ++i)
     if (hs[i] / m->P != m->g0 || ws[i] / m->P != m->g0) {
@@ -1905,7 +1918,8 @@ bool make_train_plan(const vl_model* m, int32_t n, const int32_t* hs, const int3
   Plan sp;
   std::string why2;
   tp->halves.clear();
-  if (m->prec == VL_BF16 && make_plan(m, n, hs, ws, &sp, &why2) && sp.parts.size() == 2) {
+  if (m->prec == VL_BF16 && !map && make_plan(m, n, hs, ws, &sp, &why2) &&
+      sp.parts.size() == 2) {
     const size_t base = (new_desc + 15) / 16 * 16;
     int t0 = 0;
     for (const Part& q : sp.parts) {
@@ -1951,6 +1965,17 @@ bool make_train_plan(const vl_model* m, int32_t n, const int32_t* hs, const int3
   tp->dXb = es == 2 ? take(es * T * D) : tp->dX;
   if (es == 2) tp->dOb = take(es * T * D);
   tp->zscr = take(4 * (size_t)n * D);
+  if (map) {
+    TrainPlan::Map& mp = tp->map;
+    mp.on = true;
+    mp.yf = take(es * T * D); mp.kv = take(es * T * 2 * D); mp.dkv = take(es * T * 2 * D);
+    mp.mo = take(4 * n * D); mp.my = take(4 * n * D); mp.mzl = take(4 * n * D);
+    mp.mz = take(4 * n * D); mp.mh = take(4 * n * F);
+    mp.dy = take(4 * n * D); mp.dzl = take(4 * n * D); mp.dO = take(4 * n * D);
+    mp.dq = take(4 * n * D); mp.dhg = take(4 * n * F); mp.hpre = take(4 * n * F);
+    mp.dh = take(4 * n * F); mp.gtmp = take(4 * n * F);
+    mp.wt = take(4 * std::max(F * D, D * D));
+  }
   tp->gT = take(es * std::max<size_t>(3 * D, F) * Tp);
   tp->actT = take(es * std::max<size_t>({D, F, (size_t)m->Kpad}) * Tp);
   tp->dGf = take(4 * T * F);
@@ -2099,6 +2124,39 @@ vl_status train_forward_range(vl_model* m, const TrainPlan& tp, const float* pix
       VL_HIP(gemm_bf16(g, F, ly.fc2_w, F, false, T, D, F, OP_FC2, gemm_cfg_for(m, 4, T), e4, s));
     }
   }
+  if (tp.map.on) {
+    // Attention-pooling head, as vl_encode_images runs it, keeping LN_f of
+    // every token, their K / V, and the head's attention output o, its
+    // output projection y, LN(y), the MLP activation and the head output.
+    const TrainPlan::Map& mp = tp.map;
+    auto fp = [&](size_t off) { return reinterpret_cast<float*>(ws + off); };
+    void* yf = ws + mp.yf;
+    void* kv = ws + mp.kv;
+    float* e = reinterpret_cast<float*>(ws + p.off_E);
+    VL_HIP(layernorm_rows(X, m->lnf_g, m->lnf_b, eps, yf, !f32, T, D, s));
+    EpiArgs ekv;
+    ekv.bias = m->map_kv_b; ekv.out = kv; ekv.ldo = 2 * D;
+    if (f32)
+      VL_HIP(gemm_f32(static_cast<const float*>(yf), D, static_cast<const float*>(m->map_kv_w), D,
+                      T, 2 * D, D, OP_QKV, ekv, s));
+    else
+      VL_HIP(gemm_bf16(static_cast<const bf16_t*>(yf), D, m->map_kv_w, D, false, T, 2 * D, D,
+                       OP_QKV, -1, ekv, s));
+    VL_HIP(map_attention(kv, !f32, m->map_q, r.imgs, r.n, m->heads, m->hd, fp(mp.mo), s));
+    EpiArgs e1; e1.bias = m->map_o_b; e1.out = fp(mp.my); e1.ldo = D;
+    VL_HIP(gemm_f32_rows(fp(mp.mo), D, m->map_o_w, D, r.n, D, D, OP_QKV, e1, s));
+    VL_HIP(layernorm_rows(fp(mp.my), m->map_ln_g, m->map_ln_b, eps, fp(mp.mzl), false, r.n, D,
+                          s));
+    EpiArgs e2; e2.bias = m->map_fc1_b; e2.out = fp(mp.mh); e2.ldo = F;
+    VL_HIP(gemm_f32_rows(fp(mp.mzl), D, m->map_fc1_w, D, r.n, F, D, OP_FC1, e2, s));
+    VL_HIP(copy_f32(fp(mp.my), fp(mp.mz), (size_t)r.n * D, s));
+    EpiArgs e3; e3.bias = m->map_fc2_b; e3.out = fp(mp.mz); e3.ldo = D;
+    VL_HIP(gemm_f32_rows(fp(mp.mh), F, m->map_fc2_w, F, r.n, D, F, OP_FC2, e3, s));
+    EpiArgs e4; e4.out = e; e4.ldo = m->Pd;
+    VL_HIP(gemm_f32_rows(fp(mp.mz), D, m->proj, D, r.n, m->Pd, D, OP_LOGITS, e4, s));
+    VL_HIP(l2_normalise_rows(e, emb, r.n, m->Pd, s));
+    return VL_OK;
+  }
   VL_HIP(pool_project(X, r.imgs, r.n, m->lnf_g, m->lnf_b, eps, m->proj, D, m->Pd, false,
                       reinterpret_cast<float*>(ws + tp.zscr) + (size_t)r.i0 * D,
                       reinterpret_cast<float*>(ws + p.off_E) + (size_t)r.i0 * m->Pd,
@@ -2148,6 +2206,8 @@ vl_status run_train_forward(vl_model* m, const TrainPlan& tp, const float* pix, 
 // gradient blob (the same layout).
 struct BlobOffsets {
   size_t patch_w, patch_b, cls, pos, lnf_g, lnf_b, proj;
+  struct M { size_t probe, q_w, q_b, kv_w, kv_b, o_w, o_b, ln_g, ln_b, fc1_w, fc1_b, fc2_w, fc2_b; };
+  M map{};   // attention-pooling head (pool = MAP)
   struct L { size_t ln1_g, ln1_b, qkv_w, qkv_b, o_w, o_b, ln2_g, ln2_b, fc1_w, fc1_b, fc2_w, fc2_b; };
   std::vector<L> layers;
 };
@@ -2166,6 +2226,12 @@ BlobOffsets blob_offsets(const vl_model* m) {
     l.fc1_w = take(F * D); l.fc1_b = take(F); l.fc2_w = take(D * F); l.fc2_b = take(D);
   }
   b.lnf_g = take(D); b.lnf_b = take(D);
+  if (!m->text && m->cfg.pool == VL_POOL_MAP) {
+    BlobOffsets::M& q = b.map;
+    q.probe = take(D); q.q_w = take(D * D); q.q_b = take(D); q.kv_w = take(2 * D * D);
+    q.kv_b = take(2 * D); q.o_w = take(D * D); q.o_b = take(D); q.ln_g = take(D); q.ln_b = take(D);
+    q.fc1_w = take(F * D); q.fc1_b = take(F); q.fc2_w = take(D * F); q.fc2_b = take(D);
+  }
   b.proj = take((size_t)m->Pd * D);
   return b;
 }
@@ -2212,6 +2278,89 @@ vl_status wgrad_gemm_km(const TrainPlan& tp, char* ws, const void* A, int lda, c
   return VL_OK;
 }
 
+// Backward of the attention-pooling head and of the final LayerNorm over
+// every token (the chain rule of the head's forward, as the oracle writes
+// it): L2 and projection, the head's MLP residual and LayerNorm, its output
+// projection, the one-query attention, the query (probe) and K / V
+// projections, then LN_f; leaves dL/dX of every token in dX.  The head's
+// small products (rows of n images) run on the FP32 row GEMM against
+// transposed weights, the K / V projection's on the block GEMMs.
+vl_status map_head_backward(vl_model* m, const TrainPlan& tp, char* ws, const float* demb,
+                            float* grads, const BlobOffsets& bo, hipStream_t s) {
+  const Part& p = tp.p.parts[0];
+  const TrainPlan::Map& mp = tp.map;
+  const bool f32 = m->prec == VL_FP32, bf = !f32;
+  const int T = p.T, n = p.n, D = m->D, F = m->F, Pd = m->Pd, Tp = tp.Tp;
+  const float eps = m->cfg.ln_eps;
+  const ImgDesc* d_imgs = reinterpret_cast<const ImgDesc*>(ws + p.off_imgs);
+  auto fp = [&](size_t off) { return reinterpret_cast<float*>(ws + off); };
+  auto G = [&](size_t off) { return grads + off; };
+  float* part = fp(tp.part);
+  float* pg = fp(tp.pg);
+  float* pb = fp(tp.pb);
+  float* wt = fp(mp.wt);
+  float* dz = fp(tp.zp);   // dL/d(head output) [n, D]
+  const BlobOffsets::M& g = bo.map;
+  auto rows = [&](const float* A, int lda, const float* B, int ldb, int M, int N, int K,
+                  float* out) -> vl_status {
+    EpiArgs e;
+    e.out = out; e.ldo = N; e.alpha = 1.f; e.beta = 0.f;
+    VL_HIP(gemm_f32_rows(A, lda, B, ldb, M, N, K, OP_LOGITS, e, s));
+    return VL_OK;
+  };
+  vl_status st;
+  // e = W_p z, e_hat = e / |e|
+  VL_HIP(l2proj_backward(fp(p.off_E), demb, m->proj, n, D, Pd, fp(tp.de), dz, s));
+  VL_HIP(outer_sum(fp(tp.de), fp(mp.mz), n, Pd, D, G(bo.proj), s));
+  // z = y + GELU(LN(y) W1^T + b1) W2^T + b2
+  VL_HIP(copy_f32(dz, fp(mp.dy), (size_t)n * D, s));
+  VL_HIP(outer_sum(dz, fp(mp.mh), n, D, F, G(g.fc2_w), s));
+  VL_HIP(colsum(dz, false, n, D, D, nullptr, part, G(g.fc2_b), s));
+  VL_HIP(transpose_rows(m->map_fc2_w, false, D, F, F, wt, false, D, s));          // W2^T [F, D]
+  if ((st = rows(dz, D, wt, D, n, F, D, fp(mp.dhg))) != VL_OK) return st;
+  {
+    EpiArgs e;
+    e.bias = m->map_fc1_b; e.out = fp(mp.hpre); e.ldo = F;                      // pre-activation
+    VL_HIP(gemm_f32_rows(fp(mp.mzl), D, m->map_fc1_w, D, n, F, D, OP_QKV, e, s));
+  }
+  VL_HIP(gelu_backward(fp(mp.dhg), fp(mp.hpre), fp(mp.dh), fp(mp.gtmp), false, (size_t)n * F, s));
+  VL_HIP(outer_sum(fp(mp.dh), fp(mp.mzl), n, F, D, G(g.fc1_w), s));
+  VL_HIP(colsum(fp(mp.dh), false, n, F, F, nullptr, part, G(g.fc1_b), s));
+  VL_HIP(transpose_rows(m->map_fc1_w, false, F, D, D, wt, false, F, s));          // W1^T [D, F]
+  if ((st = rows(fp(mp.dh), F, wt, F, n, D, F, fp(mp.dzl))) != VL_OK) return st;
+  VL_HIP(layernorm_backward(fp(mp.my), m->map_ln_g, fp(mp.dzl), eps, fp(mp.dy), n, D, pg, pb,
+                            G(g.ln_g), G(g.ln_b), s));
+  // y = o W_o^T + b_o
+  VL_HIP(outer_sum(fp(mp.dy), fp(mp.mo), n, D, D, G(g.o_w), s));
+  VL_HIP(colsum(fp(mp.dy), false, n, D, D, nullptr, part, G(g.o_b), s));
+  VL_HIP(transpose_rows(m->map_o_w, false, D, D, D, wt, false, D, s));            // W_o^T
+  if ((st = rows(fp(mp.dy), D, wt, D, n, D, D, fp(mp.dO))) != VL_OK) return st;
+  // one query per head over each image's K / V
+  VL_HIP(map_attention_backward(ws + mp.kv, bf, m->map_q, fp(mp.mo), fp(mp.dO), d_imgs, n,
+                                p.max_ntok, m->heads, m->hd, ws + mp.dkv, fp(mp.dq), s));
+  // q = probe W_q^T + b_q, shared by every image: dq summed over images
+  VL_HIP(colsum(fp(mp.dq), false, n, D, D, nullptr, part, G(g.q_b), s));
+  VL_HIP(outer_sum(G(g.q_b), m->map_probe, 1, D, D, G(g.q_w), s));
+  VL_HIP(transpose_rows(m->map_q_w, false, D, D, D, wt, false, D, s));            // W_q^T
+  if ((st = rows(G(g.q_b), D, wt, D, 1, D, D, G(g.probe))) != VL_OK) return st;
+  // [K | V] = LN_f(x) W_kv^T + b_kv over every token
+  void* gT = ws + tp.gT;
+  void* actT = ws + tp.actT;
+  VL_HIP(colsum(ws + mp.dkv, bf, T, 2 * D, 2 * D, nullptr, part, G(g.kv_b), s));
+  VL_HIP(transpose_rows(ws + mp.dkv, bf, T, 2 * D, 2 * D, gT, bf, Tp, s));
+  VL_HIP(transpose_rows(ws + mp.yf, bf, T, D, D, actT, bf, Tp, s));
+  if ((st = wgrad_gemm(m, tp, ws, gT, actT, 2 * D, D, G(g.kv_w), s)) != VL_OK) return st;
+  VL_HIP(transpose_rows(m->map_kv_w, bf, 2 * D, D, D, ws + tp.Wt, bf, 2 * D, s));  // W_kv^T
+  float* dY = fp(tp.dY);
+  if ((st = gemm_into_f32(m, ws + mp.dkv, 2 * D, ws + tp.Wt, 2 * D, T, D, 2 * D, dY, D, s)) !=
+      VL_OK)
+    return st;
+  // LN_f on every token: dX (zero) += LN_f'(X) dY
+  VL_HIP(layernorm_backward(reinterpret_cast<const float*>(ws + p.off_X), m->lnf_g, dY, eps,
+                            fp(tp.dX), T, D, pg, pb, G(bo.lnf_g), G(bo.lnf_b), s));
+  return VL_OK;
+}
+
 // Events of the overlapped backward (indices into vl_model::tev): recorded on
 // the caller's stream when an operand of a weight gradient is ready, and on
 // the side stream when a weight gradient has read its operands.
@@ -2255,11 +2404,17 @@ vl_status run_backward_body(vl_model* m, const TrainPlan& tp, const float* pix, 
   auto G = [&](size_t off) { return grads + off; };
 
   VL_HIP(fill_zero(dX, (size_t)T * D, s));
-  VL_HIP(pool_backward(X, d_imgs, p.n, reinterpret_cast<const float*>(ws + p.off_E), demb, m->proj,
-                       m->lnf_g, m->lnf_b, eps, D, m->Pd, reinterpret_cast<float*>(ws + tp.de),
-                       reinterpret_cast<float*>(ws + tp.zp), dX,
-                       reinterpret_cast<float*>(ws + tp.ppg), reinterpret_cast<float*>(ws + tp.ppb),
-                       part, G(bo.proj), G(bo.lnf_g), G(bo.lnf_b), s));
+  if (tp.map.on) {
+    const vl_status sm = map_head_backward(m, tp, ws, demb, grads, bo, s);
+    if (sm != VL_OK) return sm;
+  } else {
+    VL_HIP(pool_backward(X, d_imgs, p.n, reinterpret_cast<const float*>(ws + p.off_E), demb,
+                         m->proj, m->lnf_g, m->lnf_b, eps, D, m->Pd,
+                         reinterpret_cast<float*>(ws + tp.de), reinterpret_cast<float*>(ws + tp.zp),
+                         dX, reinterpret_cast<float*>(ws + tp.ppg),
+                         reinterpret_cast<float*>(ws + tp.ppb), part, G(bo.proj), G(bo.lnf_g),
+                         G(bo.lnf_b), s));
+  }
   // BF16 models whose widths are multiples of 256 form the weight gradients
   // from the token-major operands (no transposed copies); the passes over
   // the output gradients still run for their column-sum partials (and dX's
@@ -2451,7 +2606,7 @@ vl_status check_train_args(vl_model* m, const float* pix, const void* a, const v
   std::string why;
   if (!make_train_plan(m, n, hs, wsz, tp, &why)) {
     const bool unsup = m->text || (m->prec != VL_FP32 && m->prec != VL_BF16) ||
-                       m->cfg.pool != VL_POOL_CLS;
+                       (m->cfg.pool == VL_POOL_MAP && m->hd > 64);
     return fail(unsup ? VL_ERR_UNSUPPORTED : VL_ERR_INVALID_ARG, why);
   }
   if (ws_bytes < tp->total)

@@ -291,6 +291,18 @@ hipError_t pool_backward(const float* X, const ImgDesc* imgs, int n, const float
 hipError_t embed_backward(const float* dX, const ImgDesc* imgs, int n, int D, int rows_pos,
                           const float* dwf, int kpad, const float* db, ChanNorm cn, int kpe,
                           int pp, float* d_pos, float* d_cls, float* d_patch_w, hipStream_t s);
+// out [P, D] = sum over rows i (ascending) of a[i] (x) b[i], a [n, P], b [n, D].
+hipError_t outer_sum(const float* a, const float* b, int n, int P, int D, float* out,
+                     hipStream_t s);
+// Attention-pooling head backward pieces: the L2 normalisation and
+// projection of the pooled rows (de [n, P], dz = W_p^T de [n, D]; P <= 1024),
+// and the one-query attention per (image, head) (dkv [T, 2D] = [dK | dV] in
+// kv's element type, dq [n, D]; head_dim <= 64, images of <= 4096 tokens).
+hipError_t l2proj_backward(const float* e, const float* demb, const float* proj, int n, int D,
+                           int P, float* de, float* dz, hipStream_t s);
+hipError_t map_attention_backward(const void* kv, bool kv_bf16, const float* q, const float* o,
+                                  const float* dO, const ImgDesc* imgs, int n, int max_ntok,
+                                  int heads, int hd, void* dkv, float* dq, hipStream_t s);
 hipError_t fill_zero(float* p, size_t n, hipStream_t s);
 // out[i] = sum over z = 0 .. splits-1 (ascending) of part[z * n + i].
 hipError_t sum_splits(const float* part, int splits, size_t n, float* out, hipStream_t s);

@@ -1228,6 +1228,151 @@ hipError_t pool_backward(const float* X, const ImgDesc* imgs, int n, const float
   return colsum(pb, false, n, D, D, nullptr, part, d_lnf_b, s);
 }
 
+hipError_t outer_sum(const float* a, const float* b, int n, int P, int D, float* out,
+                     hipStream_t s) {
+  if (n <= 0 || P <= 0 || D <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_outer_sum, dim3((D + 255) / 256, P), dim3(256), 0, s, a, b, n, P, D, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------- attention-pooling head backward
+// L2 normalisation and projection of the pooled rows: per image, from e
+// [n, P] (before normalisation) and dL/d(e_hat) demb: de = (demb - e_hat
+// <e_hat, demb>) / |e| and dz = W_p^T de [n, D] (W_p [P, D]).  P <= 1024.
+__global__ __launch_bounds__(256) void k_l2proj_bwd(const float* __restrict__ e,
+                                                    const float* __restrict__ demb,
+                                                    const float* __restrict__ proj, int D, int P,
+                                                    float* __restrict__ de_out,
+                                                    float* __restrict__ dz) {
+  __shared__ float red[4];
+  __shared__ float sde[1024];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const float* er = e + (size_t)i * P;
+  const float* dr = demb + (size_t)i * P;
+  auto sum = [](float a, float b) { return a + b; };
+  float n2 = 0.f, dot = 0.f;
+  for (int p = tid; p < P; p += 256) {
+    n2 += er[p] * er[p];
+    dot += er[p] * dr[p];
+  }
+  n2 = block_reduce(n2, red, sum);
+  dot = block_reduce(dot, red, sum);
+  const float inv = 1.f / fmaxf(sqrtf(n2), 1e-12f);
+  const float ehd = dot * inv;   // <e_hat, d e_hat>
+  for (int p = tid; p < P; p += 256) {
+    const float v = (dr[p] - er[p] * inv * ehd) * inv;
+    sde[p] = v;
+    de_out[(size_t)i * P + p] = v;
+  }
+  __syncthreads();
+  for (int c = tid; c < D; c += 256) {
+    float acc = 0.f;
+    for (int p = 0; p < P; ++p) acc += proj[(size_t)p * D + c] * sde[p];
+    dz[(size_t)i * D + c] = acc;
+  }
+}
+
+hipError_t l2proj_backward(const float* e, const float* demb, const float* proj, int n, int D,
+                           int P, float* de, float* dz, hipStream_t s) {
+  if (n <= 0 || P > 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_l2proj_bwd, dim3(n), dim3(256), 0, s, e, demb, proj, D, P, de, dz);
+  return hipGetLastError();
+}
+
+// One query per head over an image's tokens (the pooling head): with p =
+// softmax(q_h k_t / sqrt(d)) over the image's tokens t, D = dO_h . o_h,
+// dV_t = p_t dO_h, dS_t = p_t (dO_h . v_t - D), dK_t = dS_t q_h / sqrt(d),
+// dq_h = sum_t dS_t k_t / sqrt(d).  One workgroup per (image, head); scores
+// and dS in LDS (images of up to 4096 tokens), FP32 throughout; dK / dV
+// written in kv's element type into dkv [T, 2D] = [dK | dV].
+template <typename T>
+__global__ __launch_bounds__(256) void k_map_attn_bwd(const T* __restrict__ kv,
+                                                      const float* __restrict__ q,
+                                                      const float* __restrict__ o,
+                                                      const float* __restrict__ dO,
+                                                      const ImgDesc* __restrict__ imgs, int heads,
+                                                      int hd, T* __restrict__ dkv,
+                                                      float* __restrict__ dq) {
+  constexpr int kMaxN = 4096;
+  __shared__ float sq[64], sdo[64], red[4];
+  __shared__ float sp[kMaxN], sds[kMaxN];
+  const int i = blockIdx.x, h = blockIdx.y, tid = threadIdx.x;
+  const ImgDesc dsc = imgs[i];
+  const int N = dsc.ntok, D = heads * hd, ld = 2 * D;
+  const T* base = kv + (size_t)dsc.tok_start * ld + h * hd;
+  T* obase = dkv + (size_t)dsc.tok_start * ld + h * hd;
+  const float scale = 1.f / sqrtf((float)hd);
+  if (tid < hd) {
+    sq[tid] = q[h * hd + tid];
+    sdo[tid] = dO[(size_t)i * D + h * hd + tid];
+  }
+  __syncthreads();
+  auto sum = [](float a, float b) { return a + b; };
+  auto mx = [](float a, float b) { return fmaxf(a, b); };
+  float dd = tid < hd ? sdo[tid] * o[(size_t)i * D + h * hd + tid] : 0.f;
+  const float Dsum = block_reduce(dd, red, sum);
+  auto ld_f = [](const T* p) {
+    if constexpr (sizeof(T) == 2) return bf16_bits_to_f32(*reinterpret_cast<const uint16_t*>(p));
+    else return static_cast<float>(*p);
+  };
+  auto st_f = [](T* p, float v) {
+    if constexpr (sizeof(T) == 2) *reinterpret_cast<uint16_t*>(p) = (uint16_t)f32_to_bf16_bits(v);
+    else *p = v;
+  };
+  float m = -INFINITY;
+  for (int t = tid; t < N; t += 256) {
+    const T* kr = base + (size_t)t * ld;
+    float acc = 0.f;
+    for (int j = 0; j < hd; ++j) acc += sq[j] * ld_f(kr + j);
+    const float sc = acc * scale;
+    sp[t] = sc;
+    m = fmaxf(m, sc);
+  }
+  m = block_reduce(m, red, mx);
+  float l = 0.f;
+  for (int t = tid; t < N; t += 256) {
+    const float e = expf(sp[t] - m);
+    sp[t] = e;
+    l += e;
+  }
+  l = block_reduce(l, red, sum);
+  const float il = 1.f / l;
+  for (int t = tid; t < N; t += 256) {
+    const float p = sp[t] * il;
+    const T* vr = base + D + (size_t)t * ld;
+    float dp = 0.f;
+    for (int j = 0; j < hd; ++j) dp += sdo[j] * ld_f(vr + j);
+    const float ds = p * (dp - Dsum);
+    sds[t] = ds;
+    T* kr = obase + (size_t)t * ld;
+    for (int j = 0; j < hd; ++j) {
+      st_f(kr + j, ds * sq[j] * scale);
+      st_f(kr + D + j, p * sdo[j]);
+    }
+  }
+  __syncthreads();
+  for (int j = tid; j < hd; j += 256) {
+    float acc = 0.f;
+    for (int t = 0; t < N; ++t) acc += sds[t] * ld_f(base + (size_t)t * ld + j);
+    dq[(size_t)i * D + h * hd + j] = acc * scale;
+  }
+}
+
+hipError_t map_attention_backward(const void* kv, bool kv_bf16, const float* q, const float* o,
+                                  const float* dO, const ImgDesc* imgs, int n, int max_ntok,
+                                  int heads, int hd, void* dkv, float* dq, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (hd > 64 || max_ntok > 4096) return hipErrorInvalidValue;
+  dim3 grid(n, heads), block(256);
+  if (kv_bf16)
+    hipLaunchKernelGGL(k_map_attn_bwd<bf16_t>, grid, block, 0, s, static_cast<const bf16_t*>(kv),
+                       q, o, dO, imgs, heads, hd, static_cast<bf16_t*>(dkv), dq);
+  else
+    hipLaunchKernelGGL(k_map_attn_bwd<float>, grid, block, 0, s, static_cast<const float*>(kv), q,
+                       o, dO, imgs, heads, hd, static_cast<float*>(dkv), dq);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------- token embedding backward
 // Position table rows (images at the base grid, so token j of every image
 // uses row j): dpos[j] = sum over images of dX[tok_start + j]; row 0 is also

@@ -41,6 +41,9 @@ SMALL = synth.ModelConfig("train_small", patch=8, width=128, layers=2, heads=4, 
                           proj_dim=64, base_grid=8)
 SMALL_HD64 = synth.ModelConfig("train_small64", patch=8, width=128, layers=1, heads=2, mlp=256,
                                proj_dim=64, base_grid=8)
+# the attention-pooling (MAP) head over every token instead of the class token
+SMALL_MAP = synth.ModelConfig("train_small_map", patch=8, width=128, layers=2, heads=4, mlp=512,
+                              proj_dim=64, base_grid=8, pool="map")
 # one ViT-L/14-shaped block at 336 px: 577 tokens, width 1024, 16 heads
 L14_1 = synth.ModelConfig("l14_1block", patch=14, width=1024, layers=1, heads=16, mlp=4096,
                           proj_dim=768, base_grid=24)
@@ -93,6 +96,35 @@ def _check_bf16(cfg, got, ref):
         worst = min(worst, cos)
         assert cos >= 0.999, (name, cos)
     _say(f"  bf16 worst per-tensor cosine {worst:.6f}")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_train_forward_with_pooling_head_equals_inference_bitwise(V, precision):
+    """With the attention-pooling head the training forward keeps the head's
+    values too and still gives vl_encode_images' embeddings bit for bit."""
+    p = synth.make_params(SMALL_MAP, 66, std=0.1)
+    blob = torch.from_numpy(synth.params_to_blob(SMALL_MAP, p)).cuda()
+    sizes = [(64, 64)] * 5
+    pix = torch.from_numpy(pack(synth.make_images(sizes, 67))).cuda()
+    tr = V.Trainer(SMALL_MAP, blob, precision)
+    a = tr.forward(pix, sizes).clone()
+    b = tr.encode(pix, sizes).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    tr.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_backward_with_pooling_head(V, precision):
+    """Every weight gradient of a tower with the attention-pooling head
+    (learned query over every final-LayerNormed token): the head's tensors,
+    the final LayerNorm over all tokens, and the blocks below it."""
+    got, ref, emb, emb_ref = _run(V, SMALL_MAP, 68, [(64, 64)] * 5, precision, 0.1)
+    if precision == "fp32":
+        assert np.abs(emb - emb_ref).max() <= 1e-4
+        _check_fp32(SMALL_MAP, got, ref)
+    else:
+        _check_bf16(SMALL_MAP, got, ref)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
