@@ -44,6 +44,9 @@ SMALL_HD64 = synth.ModelConfig("train_small64", patch=8, width=128, layers=1, he
 # the attention-pooling (MAP) head over every token instead of the class token
 SMALL_MAP = synth.ModelConfig("train_small_map", patch=8, width=128, layers=2, heads=4, mlp=512,
                               proj_dim=64, base_grid=8, pool="map")
+# one ViT-B/16-shaped block with the pooling head at 224 px: 197 tokens
+B16_MAP_1 = synth.ModelConfig("b16_map_1block", patch=16, width=768, layers=1, heads=12,
+                              mlp=3072, proj_dim=768, base_grid=14, pool="map")
 # one ViT-L/14-shaped block at 336 px: 577 tokens, width 1024, 16 heads
 L14_1 = synth.ModelConfig("l14_1block", patch=14, width=1024, layers=1, heads=16, mlp=4096,
                           proj_dim=768, base_grid=24)
@@ -125,6 +128,17 @@ def test_backward_with_pooling_head(V, precision):
         _check_fp32(SMALL_MAP, got, ref)
     else:
         _check_bf16(SMALL_MAP, got, ref)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_backward_with_pooling_head_b16_block(V, precision):
+    """The pooling head at ViT-B/16 width (768, 12 heads of 64, MLP 3072),
+    three 224-px images, N(0, 0.02^2) weights."""
+    got, ref, _, _ = _run(V, B16_MAP_1, 73, [(224, 224)] * 3, precision, 0.02)
+    if precision == "fp32":
+        _check_fp32(B16_MAP_1, got, ref)
+    else:
+        _check_bf16(B16_MAP_1, got, ref)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
