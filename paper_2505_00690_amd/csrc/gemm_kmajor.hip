@@ -42,6 +42,8 @@ __device__ __forceinline__ bf16x8 km_frag(uint32_t a) {
   return __builtin_bit_cast(bf16x8, vk);
 }
 
+}  // namespace
+
 // C = alpha A^T B + beta over K rows [z kc, z kc + kc) of split z = grid y,
 // written FP32 at out + z zstride ([M, ldo]).  A [K, lda], B [K, ldb] BF16,
 // rows >= k_valid read as zero.  8 waves, 2 x 4 of 128 x 64 outputs.
@@ -170,8 +172,6 @@ k_gemm_bf16_kmajor(const bf16_t* __restrict__ A, int lda, const bf16_t* __restri
         out[(size_t)m * e.ldo + n] = e.alpha * acc[b][a][r] + e.beta;
       }
 }
-
-}  // namespace
 
 hipError_t gemm_bf16_kmajor(const bf16_t* A, int lda, const bf16_t* B, int ldb, int M, int N,
                             int K, int k_valid, const EpiArgs& e, hipStream_t s) {
