@@ -330,6 +330,32 @@ def test_full_size_every_image(V, name):
         assert cos.min() >= COS_TOL
 
 
+def test_l14_336_in_the_benchmark_launch_configuration(V):
+    """The headline batch (32 ViT-L/14 images at 336 px, BF16) encoded the
+    way bench.py times it -- two overlapped parts, HIP graphs keyed on the
+    exact batch, the second call a graph replay -- against every image's FP64
+    oracle embedding, and bitwise against the plain one-part eager call."""
+    g = GOLDENS["l14_336_bf16"]
+    sizes = [tuple(x) for x in g["sizes"]]
+    imgs = synth.make_images(sizes, g["images_seed"])
+    ref = np.load(os.path.join(GOLDEN_DIR, g["file"]))
+    plain = run(encoder(V, "l14", g["weights_seed"], "bf16"), imgs)
+    w = torch.from_numpy(blob("l14", g["weights_seed"])).cuda()
+    enc = V.Encoder(synth.MODELS["l14"], w, "bf16", graphs=True, split=True)
+    del w
+    V.vl_model_set_option(enc.handle, V.VL_OPT_GRAPH_BUCKETS, 0)
+    _say("l14_336 bf16: two parts, exact graphs, capture then replay")
+    first = run(enc, imgs)
+    second = run(enc, imgs)
+    stats = enc.graph_stats()
+    enc.close()
+    assert stats["replays"] >= 1, stats
+    assert np.array_equal(first, plain) and np.array_equal(second, plain)
+    cos = cosine(second, ref)
+    _say(f"  min cos {cos.min():.6f}")
+    assert cos.min() >= COS_TOL
+
+
 def test_bf16_top1_agreement_1024_images(V):
     """BF16 top-1 against the FP32 GPU path (itself within 1e-4 of the
     oracle) over 1024 ViT-B/16 224 px images and 1000 texts, softmax head,
