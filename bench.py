@@ -178,6 +178,34 @@ def summarize_traffic(fetch_dir: str, write_dir: str, copy_mib: int = 256) -> st
     return "\n".join(out)
 
 
+def summarize_counters(*dirs: str) -> str:
+    """Per kernel of one or more rocprofv3 --pmc runs: dispatches and the
+    mean per dispatch of every counter collected, with the derived ratios
+    the counters give (MFMA busy share of SIMD cycles, share of wave cycles
+    spent waiting on any dependency, BF16 MFMA FLOPs issued)."""
+    vals, disp = {}, {}
+    for d in dirs:
+        for r in _csv(d, "counter_collection.csv"):
+            n = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            if not n.startswith("vl::"):
+                continue
+            vals.setdefault(n, {}).setdefault(r["Counter_Name"], []).append(
+                float(r["Counter_Value"]))
+            disp.setdefault(n, set()).add((d, r["Dispatch_Id"]))
+    out = ["| kernel | dispatches | MFMA busy % | waiting % of wave cycles | "
+           "BF16 MFMA GFLOP per dispatch |", "|---|---|---|---|---|"]
+    for n in sorted(vals, key=lambda k: -sum(vals[k].get("SQ_WAVE_CYCLES", [0]))):
+        c = {k: sum(v) / len(v) for k, v in vals[n].items()}
+        util = c.get("MfmaUtil")
+        wait = (100.0 * c["SQ_WAIT_INST_ANY"] / c["SQ_WAVE_CYCLES"]
+                if c.get("SQ_WAVE_CYCLES") else None)
+        fl = c.get("SQ_INSTS_VALU_MFMA_MOPS_BF16")
+        f = lambda x, fmt: "-" if x is None else format(x, fmt)  # noqa: E731
+        out.append(f"| `{n}` | {len(disp[n]) // max(1, len(dirs))} | {f(util, '.1f')} | "
+                   f"{f(wait, '.1f')} | {f(None if fl is None else fl * 512 / 1e9, '.2f')} |")
+    return "\n".join(out)
+
+
 def cpu_baseline(wl: synth.Workload, blob: np.ndarray, images, texts, n_sample: int,
                  precision: str = None, one_thread: bool = True):
     """The FP64 oracle as it stands, on the host cores, over a bounded
@@ -497,6 +525,8 @@ def main(argv=None) -> int:
     ap.add_argument("--summarize-kernels", metavar="DIR", default=None,
                     help="print the kernel-time tables of a rocprofv3 --kernel-trace --stats "
                          "output directory and exit")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR", default=None,
+                    help="print per-kernel SQ counter ratios of rocprofv3 --pmc runs")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     default=None, help="print the GEMM traffic records of two rocprofv3 "
                     "--pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
@@ -521,6 +551,9 @@ def main(argv=None) -> int:
     args = ap.parse_args(argv)
     if args.summarize_kernels:
         print(summarize_kernels(args.summarize_kernels))
+        return 0
+    if args.summarize_counters:
+        print(summarize_counters(*args.summarize_counters))
         return 0
     if args.summarize_traffic:
         print(summarize_traffic(*args.summarize_traffic, args.copy_calibration_mib or 256))
