@@ -414,6 +414,8 @@ def train_leg(torch, vl, steps: int, model: str = "l14", res: int = 336, batch: 
     return {"value": batch / (ms / 1e3), "unit": "images/s", "ms_per_step": ms,
             "model": c.name, "resolution": res, "batch": batch, "precision": "bf16",
             "loss": "sigmoid (scale 10, bias -10), matched random texts",
+            "schedule": "forward as two overlapped halves; weight gradients on a second "
+                        "stream beside the input-gradient chain",
             "ms_forward": ph[0], "ms_loss": ph[1], "ms_backward": ph[2],
             "tflops_3x_forward": flops / (ms / 1e3) / 1e12,
             "grads_finite": bool(np.isfinite(g).all()), "steps": steps,
