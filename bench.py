@@ -562,8 +562,9 @@ def main(argv=None) -> int:
         return 0
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(images are independent; see DESIGN.md for how the path would shard).",
+        print("bench.py measures one GPU only: there is no multi-GPU path (images are "
+              "independent, so each GPU would encode its share of a batch with its own "
+              "weight replica).",
               file=sys.stderr)
         return 2
 

@@ -38,7 +38,7 @@ follows:
     block's largest magnitude) minus the element format's largest exponent,
     elements rounded after division by the scale, saturating).
 
-Readings of unspecified points (each also listed in the design doc): pixels are
+Readings of unspecified points: pixels are
 normalised with mean 1/2 and std 1/sqrt(12) per channel; patch vectors are
 channel-major (c, a, b) like a conv weight [D, 3, P, P]; tokens are row-major
 over the patch grid with the class token first; the grid is floor(H/P) x
