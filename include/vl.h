@@ -421,7 +421,11 @@ vl_status vl_encode_images(vl_model* m, const float* pixels_dev,
  * the same pixels pointer, shapes and workspace; the caller must not reuse
  * that workspace in between.  Workspace: vl_train_workspace_bytes(...) bytes,
  * 256-byte aligned (about 2 x (10 D + 2 F) bytes per token per block in BF16,
- * twice that in FP32).  Asynchronous on `stream`.                          */
+ * twice that in FP32).  Asynchronous on `stream`.  The first backward call
+ * on a VL_BF16 model also allocates (device memory owned by the model, freed
+ * by vl_model_destroy) and fills the transposed weights of every block,
+ * 2 x L x (4 D^2 + 2 D F) bytes, which later calls reuse; if that
+ * allocation fails the call returns VL_ERR_DEVICE.                         */
 size_t vl_train_workspace_bytes(const vl_model* m, int32_t n_images, const int32_t* heights,
                                 const int32_t* widths);
 vl_status vl_encode_images_train(vl_model* m, const float* pixels_dev, const int32_t* heights,

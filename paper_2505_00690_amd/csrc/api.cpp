@@ -138,6 +138,12 @@ struct vl_model {
   // Training backward: ordering between the caller's stream and the side
   // stream that runs the weight-gradient GEMMs (see run_backward).
   hipEvent_t tev[10] = {};
+  // BF16 training backward: every block's transposed weights (W_qkv^T
+  // [D, 3D], W_o^T [D, D], W_1^T [D, F], W_2^T [F, D]), formed by the first
+  // backward call and kept, since a model's weights never change after
+  // creation; wT_ev marks the end of that fill.
+  char* wT = nullptr;
+  hipEvent_t wT_ev = nullptr;
   int32_t tuning[VL_N_GEMM_OPS][VL_N_M_BUCKETS];
   // The last vl_encode_images_train call (workspace, pixels, shapes): the
   // backward pass must be given the same, since it reads what that forward
@@ -936,6 +942,8 @@ void vl_model_destroy(vl_model* m) {
   for (hipEvent_t e : m->tev)
     if (e) (void)hipEventDestroy(e);
   if (m->wmem) (void)hipFree(m->wmem);
+  if (m->wT) (void)hipFree(m->wT);
+  if (m->wT_ev) (void)hipEventDestroy(m->wT_ev);
   delete m;
 }
 
@@ -1870,14 +1878,17 @@ struct TrainPlan {
 };
 
 // Splits of a weight-gradient GEMM [M, N] over K = Tp (BF16 models): as many
-// as keep the 256 x 256 tiles of all splits within one round of 256 CUs
-// (measured on MI355X at ViT-L/14@336, batch 32: fewer, longer splits beat
-// two rounds, 71.7 against 75.0 ms per training step, since every split adds
-// an FP32 partial product to write and sum), each split a multiple of 64
-// columns.  Returns (splits, columns per split).
+// as keep the 256 x 256 tiles of all splits within half a round of 256 CUs,
+// each split a multiple of 64 columns.  Every split adds an FP32 partial
+// product to write and sum, and the weight gradients run on a second stream
+// beside the input-gradient chain, which takes the other CUs.  Measured on
+// MI355X at ViT-L/14@336, batch 32 (one box, training step): half a round
+// 55.7 ms, a full round 56.5 ms, a quarter round 68 ms; two splits for every
+// product 55.3 against 54.9 ms for half a round.  Returns (splits, columns
+// per split).
 std::pair<int, int> wgrad_splits(int M, int N, int Tp) {
   const int tiles = ((M + 255) / 256) * ((N + 255) / 256);
-  int want = std::max(1, std::min(256 / tiles, Tp / 64));
+  int want = std::max(1, std::min(128 / tiles, Tp / 64));
   const int kc = ((Tp + want - 1) / want + 63) / 64 * 64;
   return {(Tp + kc - 1) / kc, kc};
 }
@@ -2367,6 +2378,21 @@ vl_status map_head_backward(vl_model* m, const TrainPlan& tp, char* ws, const fl
 enum TrainEvent { kEvDxFc2, kEvDzFc1, kEvDxO, kEvDzQkv, kEvWFc2, kEvWFc1, kEvWO, kEvWQkv,
                   kEvFork, kEvJoin };
 
+// Byte offsets of one block's transposed weights in vl_model::wT.
+struct WtOffsets {
+  size_t qkv, o, fc1, fc2, per_layer;
+};
+WtOffsets wt_offsets(const vl_model* m) {
+  const size_t D = m->D, F = m->F, es = sizeof(bf16_t);
+  WtOffsets w;
+  w.qkv = 0;
+  w.o = w.qkv + es * 3 * D * D;
+  w.fc1 = w.o + es * D * D;
+  w.fc2 = w.fc1 + es * D * F;
+  w.per_layer = w.fc2 + es * F * D;
+  return w;
+}
+
 // The backward pass, block by block in reverse.  dX is the gradient of the
 // residual stream; every linear layer's input gradient is a GEMM against the
 // transposed weight and its weight gradient a GEMM over the tokens (K = T,
@@ -2396,7 +2422,8 @@ vl_status run_backward_body(vl_model* m, const TrainPlan& tp, const float* pix, 
   float* dGf = reinterpret_cast<float*>(ws + tp.dGf);
   void* dZ = ws + tp.dZ;
   float* dY = reinterpret_cast<float*>(ws + tp.dY);
-  void* Wt = ws + tp.Wt;
+  void* Wt = ws + tp.Wt;   // transposed weights of the FP32 path
+  const WtOffsets wo = wt_offsets(m);
   float* part = reinterpret_cast<float*>(ws + tp.part);
   float* pg = reinterpret_cast<float*>(ws + tp.pg);
   float* pb = reinterpret_cast<float*>(ws + tp.pb);
@@ -2452,20 +2479,24 @@ vl_status run_backward_body(vl_model* m, const TrainPlan& tp, const float* pix, 
     const Layer& ly = m->layers[l];
     const TrainLayer& sv = tp.layers[l];
     const BlobOffsets::L& go = bo.layers[l];
+    // this block's transposed weights: kept by the model (BF16), or formed
+    // here into scratch (FP32)
+    const char* wl = bf ? m->wT + wo.per_layer * l : nullptr;
     vl_status st;
     // ---- FC2: x_out = h + GELU(z1) W2^T + b2
     const bool later = l < m->L - 1;   // the previous block's weight gradients may still read
     if (later && (st = wait(s, kEvWO)) != VL_OK) return st;        // ... dX's copy
     if ((st = prep_dx()) != VL_OK) return st;
     if ((st = rec(kEvDxFc2, s)) != VL_OK) return st;
-    VL_HIP(transpose_rows(ly.fc2_w, bf, D, F, F, Wt, bf, D, s));                 // W2^T [F, D]
+    const void* W2t = bf ? static_cast<const void*>(wl + wo.fc2) : Wt;            // W2^T [F, D]
+    if (!bf) VL_HIP(transpose_rows(ly.fc2_w, bf, D, F, F, Wt, bf, D, s));
     if (later && (st = wait(s, kEvWQkv)) != VL_OK) return st;      // ... and dZ
     // g = GELU(z1): kept by the forward (BF16), formed again here (FP32)
     void* g = bf ? static_cast<void*>(ws + sv.g) : QH;
     if (bf) {   // dz1 = (dX W2) GELU'(z1) from the GEMM's epilogue
       EpiArgs eg;
       eg.out = dZ; eg.aux = reinterpret_cast<const float*>(ws + sv.z1); eg.ldo = F;
-      VL_HIP(gemm_bf16(static_cast<const bf16_t*>(dXb), D, Wt, D, false, T, F, D, OP_DGELU, -1,
+      VL_HIP(gemm_bf16(static_cast<const bf16_t*>(dXb), D, W2t, D, false, T, F, D, OP_DGELU, -1,
                        eg, s));
     } else {
       if ((st = gemm_into_f32(m, dXb, D, Wt, D, T, F, D, dGf, F, s)) != VL_OK) return st;
@@ -2484,8 +2515,9 @@ vl_status run_backward_body(vl_model* m, const TrainPlan& tp, const float* pix, 
     if (st != VL_OK) return st;
     if ((st = bias_grad(dX, false, D, G(go.fc2_b))) != VL_OK) return st;
     // ---- FC1: z1 = y2 W1^T + b1
-    VL_HIP(transpose_rows(ly.fc1_w, bf, F, D, D, Wt, bf, F, s));                 // W1^T [D, F]
-    if ((st = gemm_into_f32(m, dZ, F, Wt, F, T, D, F, dY, D, s)) != VL_OK) return st;
+    const void* W1t = bf ? static_cast<const void*>(wl + wo.fc1) : Wt;            // W1^T [D, F]
+    if (!bf) VL_HIP(transpose_rows(ly.fc1_w, bf, F, D, D, Wt, bf, F, s));
+    if ((st = gemm_into_f32(m, dZ, F, W1t, F, T, D, F, dY, D, s)) != VL_OK) return st;
     VL_HIP(transpose_rows(dZ, bf, T, F, F, gTo, bf, Tp, s, bf ? part : nullptr));
     if (km) {
       if ((st = wait(sw, kEvDzFc1)) != VL_OK) return st;
@@ -2504,9 +2536,10 @@ vl_status run_backward_body(vl_model* m, const TrainPlan& tp, const float* pix, 
     if ((st = wait(s, kEvWFc2)) != VL_OK) return st;   // FC2's weight gradient read dX's copy
     if ((st = prep_dx()) != VL_OK) return st;
     if ((st = rec(kEvDxO, s)) != VL_OK) return st;
-    VL_HIP(transpose_rows(ly.o_w, bf, D, D, D, Wt, bf, D, s));
+    const void* Wot = bf ? static_cast<const void*>(wl + wo.o) : Wt;              // W_o^T
+    if (!bf) VL_HIP(transpose_rows(ly.o_w, bf, D, D, D, Wt, bf, D, s));
     // dO in FP32, and (BF16) its BF16 copy for the attention backward
-    if ((st = gemm_into_f32(m, dXb, D, Wt, D, T, D, D, dY, D, s,
+    if ((st = gemm_into_f32(m, dXb, D, Wot, D, T, D, D, dY, D, s,
                             bf ? static_cast<bf16_t*>(dOb) : nullptr)) != VL_OK)
       return st;
     if (km) {
@@ -2531,8 +2564,9 @@ vl_status run_backward_body(vl_model* m, const TrainPlan& tp, const float* pix, 
                               bf ? static_cast<const bf16_t*>(dOb) : nullptr));
     if ((st = rec(kEvDzQkv, s)) != VL_OK) return st;
     // ---- QKV: [q|k|v] = y1 Wqkv^T + bqkv
-    VL_HIP(transpose_rows(ly.qkv_w, bf, 3 * D, D, D, Wt, bf, 3 * D, s));         // [D, 3D]
-    if ((st = gemm_into_f32(m, dZ, 3 * D, Wt, 3 * D, T, D, 3 * D, dY, D, s)) != VL_OK) return st;
+    const void* Wqt = bf ? static_cast<const void*>(wl + wo.qkv) : Wt;            // [D, 3D]
+    if (!bf) VL_HIP(transpose_rows(ly.qkv_w, bf, 3 * D, D, D, Wt, bf, 3 * D, s));
+    if ((st = gemm_into_f32(m, dZ, 3 * D, Wqt, 3 * D, T, D, 3 * D, dY, D, s)) != VL_OK) return st;
     VL_HIP(transpose_rows(dZ, bf, T, 3 * D, 3 * D, gTo, bf, Tp, s, bf ? part : nullptr));
     if (km) {
       if ((st = wait(sw, kEvDzQkv)) != VL_OK) return st;
@@ -2574,6 +2608,44 @@ vl_status run_backward_body(vl_model* m, const TrainPlan& tp, const float* pix, 
   return VL_OK;
 }
 
+// BF16 models: make sure the transposed block weights exist (allocated and
+// formed on s by the first call; later calls make s wait for that fill).
+vl_status ensure_transposed_weights(vl_model* m, hipStream_t s) {
+  if (m->wT) {
+    VL_HIP(hipStreamWaitEvent(s, m->wT_ev, 0));
+    return VL_OK;
+  }
+  const WtOffsets o = wt_offsets(m);
+  const int D = m->D, F = m->F;
+  char* p = nullptr;
+  hipError_t e = hipMalloc(&p, o.per_layer * m->L);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();   // leave no stale error for the next launch check
+    return hip_fail(e, "hipMalloc(transposed weights)");
+  }
+  hipEvent_t ev = nullptr;
+  e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  for (int l = 0; l < m->L && e == hipSuccess; ++l) {
+    const Layer& ly = m->layers[l];
+    char* q = p + o.per_layer * l;
+    e = transpose_rows(ly.qkv_w, true, 3 * D, D, D, q + o.qkv, true, 3 * D, s);
+    if (e == hipSuccess) e = transpose_rows(ly.o_w, true, D, D, D, q + o.o, true, D, s);
+    if (e == hipSuccess) e = transpose_rows(ly.fc1_w, true, F, D, D, q + o.fc1, true, F, s);
+    if (e == hipSuccess) e = transpose_rows(ly.fc2_w, true, D, F, F, q + o.fc2, true, D, s);
+  }
+  if (e == hipSuccess) e = hipEventRecord(ev, s);
+  if (e != hipSuccess) {
+    // nothing enqueued after a failed launch reads p; wait for the rest
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(p);
+    if (ev) (void)hipEventDestroy(ev);
+    return hip_fail(e, "transposed weights");
+  }
+  m->wT = p;
+  m->wT_ev = ev;
+  return VL_OK;
+}
+
 // The backward on the caller's stream s; with K-major weight gradients the
 // model's side stream takes them (forked after everything before this call
 // on s, joined back into s before returning, also after an error).
@@ -2581,6 +2653,10 @@ vl_status run_backward(vl_model* m, const TrainPlan& tp, const float* pix, const
                        float* grads, char* ws, hipStream_t s) {
   const bool km = m->prec == VL_BF16 && m->kmajor_wgrad && m->D % 256 == 0 && m->F % 256 == 0;
   hipStream_t side = nullptr;
+  if (m->prec == VL_BF16) {
+    const vl_status sw = ensure_transposed_weights(m, s);
+    if (sw != VL_OK) return sw;
+  }
   if (km) {
     if (!m->side) VL_HIP(hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking));
     for (hipEvent_t& e : m->tev)

@@ -1422,10 +1422,37 @@ __global__ __launch_bounds__(256) void k_sum_splits(const float* __restrict__ pa
   out[i] = s;
 }
 
+// Four consecutive elements per lane (16-byte loads and stores); the sum of
+// each element runs over the splits in the same ascending order as above.
+__global__ __launch_bounds__(256) void k_sum_splits4(const float4* __restrict__ part, int splits,
+                                                     size_t n4, float4* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n4) return;
+  float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 4
+  for (int z = 0; z < splits; ++z) {
+    const float4 v = part[(size_t)z * n4 + i];
+    s.x += v.x;
+    s.y += v.y;
+    s.z += v.z;
+    s.w += v.w;
+  }
+  out[i] = s;
+}
+
 hipError_t sum_splits(const float* part, int splits, size_t n, float* out, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
-                     splits, n, out);
+  const bool vec = n % 4 == 0 && reinterpret_cast<uintptr_t>(part) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(out) % 16 == 0;
+  if (vec) {
+    const size_t n4 = n / 4;
+    hipLaunchKernelGGL(k_sum_splits4, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<const float4*>(part), splits, n4,
+                       reinterpret_cast<float4*>(out));
+  } else {
+    hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
+                       splits, n, out);
+  }
   return hipGetLastError();
 }
 

@@ -243,6 +243,40 @@ def test_backward_kmajor_weight_gradients_match_transposed(V):
             assert np.array_equal(a, b), name
 
 
+def test_backward_repeats_bitwise_with_kept_transposed_weights(V):
+    """A BF16 model forms its blocks' transposed weights on the first
+    backward call and reuses them: the second and third calls on one model
+    (the third on another stream) and a first call on a fresh model give
+    the same gradients bit for bit."""
+    p = synth.make_params(SMALL, 73, std=0.1)
+    blob = torch.from_numpy(synth.params_to_blob(SMALL, p)).cuda()
+    sizes = [(64, 64)] * 3
+    pix = torch.from_numpy(pack(synth.make_images(sizes, 74))).cuda()
+    de = torch.from_numpy(synth.make_texts(3, SMALL.proj_dim, 75)).cuda()
+    tr = V.Trainer(SMALL, blob, "bf16")
+    runs = []
+    for k in range(2):
+        _say(f"train {SMALL.name} bf16 repeat {k}")
+        tr.forward(pix, sizes)
+        runs.append(tr.backward(pix, sizes, de).clone())
+    _say(f"train {SMALL.name} bf16 repeat 2, another stream")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        tr.forward(pix, sizes)
+        runs.append(tr.backward(pix, sizes, de).clone())
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    tr.close()
+    fresh = V.Trainer(SMALL, blob, "bf16")
+    fresh.forward(pix, sizes)
+    runs.append(fresh.backward(pix, sizes, de).clone())
+    torch.cuda.synchronize()
+    fresh.close()
+    for r in runs[1:]:
+        assert torch.equal(r, runs[0])
+
+
 def test_training_forward_in_two_halves_is_bitwise_one_pass(V):
     """VL_OPT_SPLIT: the training forward runs the batch as two halves of
     consecutive images on two streams.  Eight 336-px images of a ViT-L/14
