@@ -47,6 +47,10 @@ SMALL_MAP = synth.ModelConfig("train_small_map", patch=8, width=128, layers=2, h
 # one ViT-B/16-shaped block with the pooling head at 224 px: 197 tokens
 B16_MAP_1 = synth.ModelConfig("b16_map_1block", patch=16, width=768, layers=1, heads=12,
                               mlp=3072, proj_dim=768, base_grid=14, pool="map")
+# three blocks at widths that are multiples of 256 (the K-major weight-
+# gradient path, whose LayerNorm backward also writes dX's BF16 copy)
+MID3 = synth.ModelConfig("train_mid3", patch=8, width=256, layers=3, heads=4, mlp=1024,
+                         proj_dim=64, base_grid=8)
 # one ViT-L/14-shaped block at 336 px: 577 tokens, width 1024, 16 heads
 L14_1 = synth.ModelConfig("l14_1block", patch=14, width=1024, layers=1, heads=16, mlp=4096,
                           proj_dim=768, base_grid=24)
@@ -179,6 +183,14 @@ def test_backward_bf16_small(V, cfg, std):
     _check_bf16(cfg, got, ref)
 
 
+def test_backward_bf16_three_blocks_kmajor(V):
+    """Three blocks of width 256 / MLP 1024 (the K-major weight-gradient path,
+    its GEMMs on the side stream beside the next block's input-gradient
+    chain), five 65-token images: every gradient against the oracle."""
+    got, ref, _, _ = _run(V, MID3, 76, [(64, 64)] * 5, "bf16", 0.1)
+    _check_bf16(MID3, got, ref)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_backward_l14_one_block(V, precision):
     """One ViT-L/14-shaped block at 336 px (577 tokens, ten 64-token
@@ -218,29 +230,31 @@ def test_backward_kmajor_weight_gradients_match_transposed(V):
     FP32 summation order inside the matrix instructions; every other
     gradient is bitwise equal.  One ViT-L/14-shaped block (widths 1024,
     3072, 4096: the K-major path's multiples of 256), two 336-px images:
-    1154 token rows, a ragged last 64-row K tile in the last split."""
-    p = synth.make_params(L14_1, 67, std=0.02)
-    blob = torch.from_numpy(synth.params_to_blob(L14_1, p)).cuda()
-    sizes = [(336, 336)] * 2
-    pix = torch.from_numpy(pack(synth.make_images(sizes, 68))).cuda()
-    de = torch.from_numpy(synth.make_texts(2, L14_1.proj_dim, 69)).cuda() * 0.1
-    tr = V.Trainer(L14_1, blob, "bf16")
-    got = {}
-    for km in (1, 0):
-        _say(f"train l14_1block bf16 kmajor={km}")
-        V.vl_model_set_option(tr.handle, V.VL_OPT_KMAJOR_WGRAD, km)
-        tr.forward(pix, sizes)
-        got[km] = tr.backward(pix, sizes, de).clone().cpu().numpy()
-    tr.close()
-    block_w = {"qkv_w", "o_w", "fc1_w", "fc2_w"}
-    for name, a, b in _per_tensor_pair(L14_1, got[1], got[0]):
-        if name.split(".")[-1] in block_w:
-            scale = np.abs(b).max()
-            assert scale > 0, name
-            err = np.abs(a - b).max() / scale
-            assert err <= 1e-5, (name, err)
-        else:
-            assert np.array_equal(a, b), name
+    1154 token rows, a ragged last 64-row K tile in the last split; and
+    three blocks of width 256, whose weight gradients on the side stream
+    overlap the next block's input-gradient chain."""
+    for cfg, seed, sizes in ((L14_1, 67, [(336, 336)] * 2), (MID3, 77, [(64, 64)] * 5)):
+        p = synth.make_params(cfg, seed, std=0.02 if cfg is L14_1 else 0.1)
+        blob = torch.from_numpy(synth.params_to_blob(cfg, p)).cuda()
+        pix = torch.from_numpy(pack(synth.make_images(sizes, seed + 1))).cuda()
+        de = torch.from_numpy(synth.make_texts(len(sizes), cfg.proj_dim, seed + 2)).cuda() * 0.1
+        tr = V.Trainer(cfg, blob, "bf16")
+        got = {}
+        for km in (1, 0):
+            _say(f"train {cfg.name} bf16 kmajor={km}")
+            V.vl_model_set_option(tr.handle, V.VL_OPT_KMAJOR_WGRAD, km)
+            tr.forward(pix, sizes)
+            got[km] = tr.backward(pix, sizes, de).clone().cpu().numpy()
+        tr.close()
+        block_w = {"qkv_w", "o_w", "fc1_w", "fc2_w"}
+        for name, a, b in _per_tensor_pair(cfg, got[1], got[0]):
+            if name.split(".")[-1] in block_w:
+                scale = np.abs(b).max()
+                assert scale > 0, name
+                err = np.abs(a - b).max() / scale
+                assert err <= 1e-5, (name, err)
+            else:
+                assert np.array_equal(a, b), name
 
 
 def test_backward_repeats_bitwise_with_kept_transposed_weights(V):
