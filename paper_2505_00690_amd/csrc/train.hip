@@ -856,7 +856,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int key = k0 + 32 * kb + 8 * (r >> 2) + 4 * g + (r & 3);
-        const float p = key < N ? exp2f(fmaf(s[r], sl2, -lse2)) : 0.f;
+        // (a key past the image has a zero row, score 0; its p could
+        // overflow for a very negative log-sum-exp, so it is selected away)
+        const float p = key < N ? __builtin_amdgcn_exp2f(fmaf(s[r], sl2, -lse2)) : 0.f;
         s[r] = p * (dp[r] - dsv);
       }
 #pragma unroll
@@ -1002,7 +1004,6 @@ k_attn_bwd_dkv_mfma(const bf16_t* __restrict__ qkv, const bf16_t* __restrict__ d
     // Stage (st+2)%3 held tile qt-1, whose readers all passed the barrier.
     if (qt + 2 < QT) issue(qt + 2, (st + 2) % BWD_ST);
     if (!wave_active) return;
-    const int nq = min(64, N - qt * 64);
     const char* tQ = sQ[st];
     const char* tO = sdO[st];
     const float* cL = sL[st];
@@ -1023,10 +1024,14 @@ k_attn_bwd_dkv_mfma(const bf16_t* __restrict__ qkv, const bf16_t* __restrict__ d
         const bf16x8 da = *reinterpret_cast<const bf16x8*>(tO + ro);
         dp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(da, vf[c], dp, 0, 0, 0);
       }
+      // No masks: query rows past the image read as zero (Q, dO, the
+      // log-sum-exp and D), so their p is 1 and their dS 0, and both meet
+      // zero dO and Q rows; a lane past the last key holds key N-1's rows
+      // (p <= 1) and its dK / dV are not stored.
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int qi = 32 * qb + 8 * (r >> 2) + 4 * g + (r & 3);
-        const float p = (qi < nq && kok) ? exp2f(fmaf(sc[r], sl2, -cL[qi])) : 0.f;
+        const float p = __builtin_amdgcn_exp2f(fmaf(sc[r], sl2, -cL[qi]));
         sc[r] = p;
         dp[r] = p * (dp[r] - cD[qi]);
       }
