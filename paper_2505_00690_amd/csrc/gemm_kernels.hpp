@@ -604,6 +604,24 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
     if (fold_out) g4 = *reinterpret_cast<const float4*>(e.u_gamma + n);
     if (e.wscale) ws4 = *reinterpret_cast<const float4*>(e.wscale + n);
   }
+  // The residual (or z) rows of a slab: with one batch of loads per slab,
+  // slab b+1's are issued before slab b's stores, so waiting for them does
+  // not also wait for those stores to complete (the vector memory counter
+  // counts loads and stores in issue order).
+  constexpr bool XLOAD = EPI == EPI_BIAS_RESID || EPI == EPI_DGELU;
+  constexpr bool XNEXT = XLOAD && NB == NP;
+  const float* xsrc = EPI == EPI_DGELU ? e.aux
+                      : e.resid_in     ? e.resid_in
+                                       : static_cast<const float*>(e.out);
+  float4 xn[NB];
+  auto load_x = [&](int b, float4 (&dst)[NB]) {
+#pragma unroll
+    for (int p = 0; p < NB; ++p) {
+      const int m = m0 + wm * WM + b * 32 + rr + p * RPP;
+      if (m < M && n_ok) dst[p] = *reinterpret_cast<const float4*>(xsrc + (size_t)m * e.ldo + n);
+    }
+  };
+  if (XNEXT) load_x(0, xn);
 #pragma unroll
   for (int b = 0; b < TM; ++b) {
 #pragma unroll
@@ -624,15 +642,15 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_b
         const int row = (p0 + p) * RPP + rr;
         v[p] = *reinterpret_cast<const float4*>(stage + row * WN + ((rc ^ sw(row)) << 2));
       }
-      if (EPI == EPI_BIAS_RESID || EPI == EPI_DGELU) {   // the residual, or z
+      if (XNEXT) {   // this slab's rows, then the next slab's
+#pragma unroll
+        for (int p = 0; p < NB; ++p) x[p] = xn[p];
+        if (b + 1 < TM) load_x(b + 1, xn);
+      } else if (XLOAD) {   // the residual, or z
 #pragma unroll
         for (int p = 0; p < NB; ++p) {
           const int m = mb + (p0 + p) * RPP;
-          if (m < M && n_ok)
-            x[p] = *reinterpret_cast<const float4*>(
-                (EPI == EPI_DGELU ? e.aux
-                                  : e.resid_in ? e.resid_in : static_cast<const float*>(e.out)) +
-                (size_t)m * e.ldo + n);
+          if (m < M && n_ok) x[p] = *reinterpret_cast<const float4*>(xsrc + (size_t)m * e.ldo + n);
         }
       }
       // LayerNorm-folded consumer: the batch's row statistics, loaded
