@@ -233,6 +233,21 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_m
   const bool n_ok = n < N;
   float4 bias4 = make_float4(0.f, 0.f, 0.f, 0.f);
   if (n_ok) bias4 = *reinterpret_cast<const float4*>(e.bias + n);
+  // Residual rows: slab b+1's are loaded before slab b's stores, so waiting
+  // for them does not wait for those stores too (loads and stores share the
+  // vector memory counter, in issue order).
+  constexpr bool XNEXT = EPI == EPI_BIAS_RESID && NB == NP;
+  float4 xn[NB];
+  auto load_x = [&](int b, float4 (&dst)[NB]) {
+#pragma unroll
+    for (int p = 0; p < NB; ++p) {
+      const int m = m0 + wm * WM + b * 32 + rr + p * RPP;
+      if (m < M && n_ok)
+        dst[p] = *reinterpret_cast<const float4*>(static_cast<const float*>(e.out) +
+                                                  (size_t)m * e.ldo + n);
+    }
+  };
+  if (XNEXT) load_x(0, xn);
 #pragma unroll
   for (int b = 0; b < TM; ++b) {
 #pragma unroll
@@ -253,7 +268,11 @@ __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4, WGM * WGN / 4))) void k_gemm_m
         const int row = (p0 + p) * RPP + rr;
         v[p] = *reinterpret_cast<const float4*>(stage + row * WN + ((rc ^ swe(row)) << 2));
       }
-      if (EPI == EPI_BIAS_RESID) {
+      if (XNEXT) {
+#pragma unroll
+        for (int p = 0; p < NB; ++p) x[p] = xn[p];
+        if (b + 1 < TM) load_x(b + 1, xn);
+      } else if (EPI == EPI_BIAS_RESID) {
 #pragma unroll
         for (int p = 0; p < NB; ++p) {
           const int m = mb + (p0 + p) * RPP;
