@@ -108,14 +108,19 @@ def _csv(dirpath: str, suffix: str):
 
 
 def _gemm_config(name: str):
-    """(op, tile configuration name) of a BF16 block-GEMM kernel name."""
+    """(op, tile configuration name, kernel source) of a BF16 or MXFP8
+    block-GEMM kernel name."""
     import re
     m = re.search(r"k_gemm_bf16_dl<(\d+), (\d+), (\d+), (\d+), false, (\d), \d, (\d)>", name)
-    if not m or m.group(5) not in _OPS:
-        return None
-    bm, bn, wm, wn, op, st = m.groups()
-    pre = "DL3" if st == "3" else "DL"
-    return _OPS[op], f"{pre}_{bm}x{bn}_W{wm}x{wn}"
+    if m and m.group(5) in _OPS:
+        bm, bn, wm, wn, op, st = m.groups()
+        pre = "DL3" if st == "3" else "DL"
+        return _OPS[op], f"{pre}_{bm}x{bn}_W{wm}x{wn}", "gemm_kernels.hpp"
+    m = re.search(r"k_gemm_mx<(\d+), (\d+), (\d+), (\d+), (\d), \d>", name)
+    if m and m.group(5) in _OPS:
+        bm, bn, wm, wn, op = m.groups()
+        return _OPS[op], f"MX_{bm}x{bn}_W{wm}x{wn}", "gemm_mx.hpp"
+    return None
 
 
 def summarize_kernels(dirpath: str) -> str:
@@ -130,7 +135,7 @@ def summarize_kernels(dirpath: str) -> str:
     groups = {}
     for r in trace:
         n = r["Kernel_Name"].split("(")[0].replace("void ", "")
-        if not any(k in n for k in ("k_gemm_bf16_dl", "k_attn_bf16", "k_layernorm")):
+        if not any(k in n for k in ("k_gemm_bf16_dl", "k_gemm_mx", "k_attn_bf16", "k_layernorm")):
             continue
         wg = int(r["Grid_Size_X"]) // max(1, int(r["Workgroup_Size_X"]))
         d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
@@ -161,14 +166,14 @@ def summarize_traffic(fetch_dir: str, write_dir: str, copy_mib: int = 256) -> st
     write, _, wcal = per_kernel(write_dir, "WRITE_SIZE")
     kib = copy_mib * 1024
     ff, wf = kib / fcal, kib / wcal
-    src = "gemm_kernels.hpp"
-    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2505_00690_amd", "csrc", src),
-                              "rb").read()).hexdigest()
     out = []
     for k in sorted(fetch):
         oc = _gemm_config(k)
         if oc is None or k not in write:
             continue
+        src = oc[2]
+        sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2505_00690_amd", "csrc", src),
+                                  "rb").read()).hexdigest()
         rec = {"op": oc[0], "fetch_kib": round(fetch[k], 1), "write_kib": round(write[k], 1),
                "fetch_factor": round(ff, 4), "write_factor": round(wf, 4),
                "copy_fetch_kib": round(fcal, 1), "copy_write_kib": round(wcal, 1),
