@@ -197,9 +197,14 @@ __global__ __launch_bounds__(256) void k_colsum_part(const T* __restrict__ in, i
 // Final pass: 4 columns per workgroup, 64 phases per column (many small
 // workgroups: the partials are few, so the pass is latency-bound); phase k
 // sums the partials b = k, k + 64, ... in ascending order, then the 64 phase
-// sums are added in phase order.
-__global__ __launch_bounds__(256) void k_colsum_final(const float* __restrict__ part, int nb,
-                                                      int C, float* __restrict__ out) {
+// sums are added in phase order.  blockIdx.y = 1 takes a second partial array
+// of the same shape (part2 -> out2) in the same launch.
+__global__ __launch_bounds__(256) void k_colsum_final(const float* __restrict__ part0, int nb,
+                                                      int C, float* __restrict__ out0,
+                                                      const float* __restrict__ part2,
+                                                      float* __restrict__ out2) {
+  const float* part = blockIdx.y ? part2 : part0;
+  float* out = blockIdx.y ? out2 : out0;
   __shared__ float red[64][5];
   const int cl = threadIdx.x & 3, ph = threadIdx.x >> 2;
   const int c = blockIdx.x * 4 + cl;
@@ -216,7 +221,16 @@ __global__ __launch_bounds__(256) void k_colsum_final(const float* __restrict__ 
 }
 
 hipError_t colsum_final(const float* part, int nb, int C, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_colsum_final, dim3((C + 3) / 4), dim3(256), 0, s, part, nb, C, out);
+  hipLaunchKernelGGL(k_colsum_final, dim3((C + 3) / 4), dim3(256), 0, s, part, nb, C, out,
+                     nullptr, nullptr);
+  return hipGetLastError();
+}
+
+// Two column sums of [nb, C] partial arrays in one launch.
+static hipError_t colsum_final2(const float* part, const float* part2, int nb, int C,
+                                float* out, float* out2, hipStream_t s) {
+  hipLaunchKernelGGL(k_colsum_final, dim3((C + 3) / 4, 2), dim3(256), 0, s, part, nb, C, out,
+                     part2, out2);
   return hipGetLastError();
 }
 
@@ -324,8 +338,7 @@ hipError_t layernorm_backward(const float* x, const float* g, const float* dy, f
 #undef VL_LNB
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if ((e = colsum_final(pg, nb, D, dgamma, s)) != hipSuccess) return e;
-  return colsum_final(pb, nb, D, dbeta, s);
+  return colsum_final2(pg, pb, nb, D, dgamma, dbeta, s);
 }
 
 // ------------------------------------------------------------------- GELU
