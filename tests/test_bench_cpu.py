@@ -116,3 +116,22 @@ def test_traffic_summary_from_counter_csvs(tmp_path):
     assert r["op"] == "fc1_gemm" and r["config"] == "DL_256x256_W4x2"
     assert r["fetch_kib"] == 200.0 and r["write_kib"] == 50.0 and r["dispatches"] == 2
     assert r["fetch_factor"] == 2.0 and r["write_factor"] == 1.0
+
+
+def test_gemm_kernel_names_map_to_op_configuration_and_source():
+    """The summarisers' kernel-name parser: BF16 tile kernels (two- and
+    three-stage), MXFP8 tile kernels (their own source file), and names that
+    are not block GEMMs."""
+    import bench
+    assert bench._gemm_config("void vl::k_gemm_bf16_dl<160, 256, 1, 8, false, 4, 2, 3>(x)") == (
+        "fc2_gemm", "DL3_160x256_W1x8", "gemm_kernels.hpp")
+    assert bench._gemm_config("void vl::k_gemm_bf16_dl<256, 256, 2, 4, false, 1, 2, 2>(x)") == (
+        "qkv_gemm", "DL_256x256_W2x4", "gemm_kernels.hpp")
+    assert bench._gemm_config("void vl::k_gemm_mx<192, 256, 2, 4, 3, 2>(x)") == (
+        "fc1_gemm", "MX_192x256_W2x4", "gemm_mx.hpp")
+    assert bench._gemm_config("void vl::k_gemm_mx<160, 256, 1, 8, 2, 2>(x)") == (
+        "oproj_gemm", "MX_160x256_W1x8", "gemm_mx.hpp")
+    # e4m3-weight variants, the weight-gradient ops and other kernels are not block GEMMs
+    assert bench._gemm_config("void vl::k_gemm_bf16_dl<256, 256, 2, 4, true, 3, 2, 2>(x)") is None
+    assert bench._gemm_config("void vl::k_gemm_bf16_dl<256, 256, 2, 4, false, 7, 2, 2>(x)") is None
+    assert bench._gemm_config("void vl::k_layernorm<16, true>(float const*)") is None
